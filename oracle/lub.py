@@ -1,0 +1,78 @@
+"""Near-field lubrication resistance, dense (oracle).
+
+The paper adds a pairwise near-field resistance R_nf = R_2B - R_2B^inf
+(Section 2.1) but never states its functions.  The model used here acts on
+the *translational disturbance* velocity of bead pairs on different bodies
+(Algorithm 1, step 1 restricts lubrication to inter-body pairs):
+
+    R_pair = 6 pi eta a [ X(eps) n n + Y(eps) (I - n n) ],
+    eps    = max(r/a - 2, eps_min),   n = (x_i - x_k) / r,
+    X(eps) = 1/(4 eps) + (9/40) ln(1/eps) + (3/112) eps ln(1/eps) - 1/4,
+    Y(eps) = (1/6) ln(1/eps),
+
+the leading squeeze and shear terms of two equal spheres, shifted so that
+both vanish at the cutoff r = 3a (eps = 1).  The force on bead i is
+-sum_k R_pair (v_i - v_k).  Rotational rows are zero.  The sparse
+preconditioner copy (Section 2.2.2: pairs with r < 2.1a) uses the same
+functions with the smaller cutoff.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def X_squeeze(eps):
+    eps = np.asarray(eps, dtype=float)
+    lg = np.log(1.0 / eps)
+    return 1.0 / (4.0 * eps) + 0.225 * lg + (3.0 / 112.0) * eps * lg - 0.25
+
+
+def Y_shear(eps):
+    return np.log(1.0 / np.asarray(eps, dtype=float)) / 6.0
+
+
+def pairs(x, body, L, r_cut):
+    """Inter-body bead pairs (i < k) with minimum-image distance < r_cut.
+
+    Returns (i, k, d) with d = x_i - x_k (minimum image).  Requires r_cut < L/2.
+    """
+    if r_cut <= 0:
+        return np.zeros(0, int), np.zeros(0, int), np.zeros((0, 3))
+    if r_cut >= L / 2:
+        raise ValueError("lubrication cutoff must be below half the box side")
+    n = len(x)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.round(d / L)
+    r = np.linalg.norm(d, axis=-1)
+    iu = np.triu_indices(n, 1)
+    sel = (r[iu] < r_cut) & (body[iu[0]] != body[iu[1]])
+    i, k = iu[0][sel], iu[1][sel]
+    return i, k, d[i, k]
+
+
+def pair_blocks(d, a, eta, eps_min=1e-3):
+    """3x3 pair resistance blocks for separations d (m, 3)."""
+    r = np.linalg.norm(d, axis=1)
+    n = d / r[:, None]
+    eps = np.maximum(r / a - 2.0, eps_min)
+    z = 6.0 * math.pi * eta * a
+    X, Y = X_squeeze(eps), Y_shear(eps)
+    nn = n[:, :, None] * n[:, None, :]
+    return z * (X[:, None, None] * nn + Y[:, None, None] * (np.eye(3) - nn))
+
+
+def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3):
+    """Dense 6N x 6N R_nf (translational rows/columns only)."""
+    n = len(x)
+    R = np.zeros((n, 6, n, 6))
+    i, k, d = pairs(x, body, L, r_cut)
+    if len(i):
+        B = pair_blocks(d, a, eta, eps_min)
+        for m in range(len(i)):
+            R[i[m], :3, i[m], :3] += B[m]
+            R[k[m], :3, k[m], :3] += B[m]
+            R[i[m], :3, k[m], :3] -= B[m]
+            R[k[m], :3, i[m], :3] -= B[m]
+    return R.reshape(6 * n, 6 * n)
