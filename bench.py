@@ -1,0 +1,142 @@
+"""Benchmark: rigid-aggregate Stokesian dynamics time steps on one MI355X.
+
+A step is one pass of the whole hot path over the suspension: neighbour lists,
+lubrication and preconditioner set-up, the right-hand side, the GMRES saddle
+solve (PSE mobility, lubrication, rigid constraints, block-triangular
+preconditioner) and the explicit Euler update.  The default workload is 256
+random-sticking clusters of 8 beads (2048 beads, phi = 0.10) in simple shear
+with lubrication, a 64^3 spectral grid and tolerance 1e-6, in FP64.
+
+Prints one JSON line (rank 0).  --gpus above 1 is not supported: this build
+runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bead-solves/s at 1e-5 saddle residual vs plain FP64; p50/p99 solve latency"
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_bytes(name, info, prec_bytes, n_lub):
+    """Minimal HBM traffic of one launch of a kernel class (bytes)."""
+    N3 = info.grid ** 3
+    nb = info.n_bead
+    grid = 3 * 2 * N3 * prec_bytes          # three complex component grids
+    bead_io = nb * (32 + 48)                 # position + 6 doubles per bead
+    if name == "real_sum":
+        return 4 * info.nnz_real + nb * (32 + 48 + 48)
+    if name in ("fft_pass", "green_scale"):
+        return 2 * grid
+    if name in ("spread", "interp"):
+        return grid + bead_io
+    if name == "lub":
+        return 44 * n_lub + nb * 48
+    return None
+
+
+def cpu_baseline(precision_note):
+    """Time the CPU oracle on a bounded sample of the same generator (one solve)."""
+    import fsdgen
+    from oracle import saddle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    s = fsdgen.sheared_clusters(n_agg=96, n_b=8, phi=0.10, name="clusters-96x8")
+    t0 = time.perf_counter()
+    U, F, res, A = saddle.solve_suspension(s)
+    dt = time.perf_counter() - t0
+    return {"value": s.n_bead / dt, "unit": "bead-solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"1 dense FP64 solve of 96x8 clusters ({s.n_bead} beads, phi 0.10, shear + lubrication, "
+                      f"same generator) in {dt:.1f} s; {precision_note}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              f"(systems shard by LPT assignment, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fsdgen
+    import paper_2607_25161_amd as F
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    s = fsdgen.config(1)
+    prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
+    sysm = F.System.from_suspension(s, stream=stream.cuda_stream, precision=prec)
+    for _ in range(args.warmup):
+        sysm.step(s.dt, 1)
+    info = sysm.info()
+
+    torch.cuda.synchronize()
+    sysm.set_timing(True)
+    lat, its, res = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        si = sysm.step(s.dt, 1)
+        lat.append(time.perf_counter() - a)
+        its.append(si.iterations)
+        res.append(si.rel_residual_fp64)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = sysm.timers()
+    sysm.set_timing(False)
+
+    counted = sum(1 for r in res if r <= 1e-5)
+    value = s.n_bead * counted / elapsed
+    prec_bytes = 4 if prec == F.FSD_MIXED else 8
+    best = max(((k, v) for k, v in timers.items() if v[1] > 0), key=lambda kv: kv[1][0])
+    name, (tot_ms, launches) = best
+    avg_s = tot_ms / launches / 1e3
+    alg = algorithmic_bytes(name, info, prec_bytes, info.n_lub_pairs)
+    roofline = None
+    if alg is not None:
+        ach = alg / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": name, "achieved": round(ach, 2), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                    "bytes_per_launch": int(alg), "avg_launch_us": round(avg_s * 1e6, 2)}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "bead-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead,
+                   "n_agg": s.n_agg, "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid,
+                   "support": info.support, "xi": info.xi, "r_cut": round(info.r_cut, 3), "tol": s.gmres_tol,
+                   "precision": args.precision, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "gmres_iterations_mean": round(float(np.mean(its)), 2),
+        "max_rel_residual": float(max(res)),
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in timers.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline("bead-solves/s of the oracle as it stands")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * fsd.h -- fast Stokesian dynamics of rigid bead aggregates on one MI355X GPU.
+ *
+ * The library solves, per time step, the aggregate saddle-point system of
+ * Section 2.3.3 (Eq. `spm_agg`) at force-torque level:
+ *
+ *   [ M      Sigma^T ] [ F ]   [ (E r_i + u_B, w_B)_i                       ]
+ *   [ Sigma  -R_agg  ] [ V ] = [ -(F_P + Sigma F_B,nf + Sigma R_nf e)_j     ]
+ *
+ * with M the periodic force-torque RPY mobility of the beads (positively split
+ * Ewald: real-space pair sum + Gaussian spreading / 3D FFT / Green's scaling /
+ * interpolation), R_nf the near-field lubrication between beads of different
+ * bodies, Sigma the geometric constraint of Eq. `sigma`, R_agg = Sigma R_nf
+ * Sigma^T, and V = U - U_inf the aggregate velocity relative to the imposed
+ * flow.  GMRES (Algorithm 1, step 4) with the block-triangular preconditioner
+ * of Section 2.3.3 (per-aggregate LU of the block-diagonal Schur
+ * approximation, Algorithm 1 step 1) solves it; Eqs. `EM1`-`EM3` advance the
+ * bodies (Algorithm 1, step 5).
+ *
+ * Conventions
+ *  - Units are any consistent set; lengths, viscosity and forces as given.
+ *  - Every function returns an fsd_status: 0 on success, negative on error.
+ *    No function aborts or throws.  fsd_last_error() describes the last error
+ *    of a system.
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied; outputs are written to caller buffers.  Pointers documented as
+ *    "device" must be device memory of the system's GPU; they are used on the
+ *    system's HIP stream.
+ *  - The primary periodic box is [-L/2, L/2)^3.  Aggregate centroids are kept
+ *    wrapped into it; U_inf at a centroid X is grad_u . X.
+ *  - Vectors of bead (force, torque) or (velocity, angular velocity) are 6
+ *    doubles per bead, force/velocity first.  Aggregate vectors likewise, 6
+ *    per aggregate.  Quaternions are (w, x, y, z).
+ *  - One fsd_system must not be used from two threads at once; distinct
+ *    systems may run concurrently on distinct streams.
+ */
+#ifndef FSD_H
+#define FSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsd_system fsd_system;
+
+typedef enum {
+  FSD_OK = 0,
+  FSD_EINVAL = -1,    /* invalid argument; outputs untouched                       */
+  FSD_ENOMEM = -2,    /* device allocation failed                                  */
+  FSD_ENOCONV = -3,   /* GMRES hit gmres_maxit; outputs hold the last iterate      */
+  FSD_EDEVICE = -4,   /* a HIP call failed                                         */
+  FSD_ESTATE = -5,    /* call out of order (e.g. solve before init_aggregates)     */
+  FSD_EOVERLAP = -6,  /* two beads of different bodies overlap by more than a/2    */
+  FSD_EBUSY = -7      /* resource exhausted (batch slots or memory budget)         */
+} fsd_status;
+
+typedef enum { FSD_FP64 = 0, FSD_MIXED = 1 } fsd_precision;
+
+/* Solver and physics parameters.  fsd_default_params() fills every field. */
+typedef struct {
+  double eta;            /* fluid viscosity                                            */
+  double radius;         /* bead radius a                                              */
+  double kT;             /* thermal energy (0: deterministic)                          */
+  double xi;             /* Ewald splitting parameter; <= 0 selects 0.5 / a            */
+  double ewald_tol;      /* truncation tolerance x_err of the cutoff rules (Sec. 3.2)  */
+  int grid;              /* spectral grid points per side; 0: from the k_c rule        */
+  int support;           /* Gaussian support P (points per side); 0: from ewald_tol    */
+  double r_lub;          /* lubrication cutoff (3a); 0 disables lubrication            */
+  double r_precond;      /* cutoff of the preconditioner's sparse lubrication (2.1a)   */
+  double lub_eps_min;    /* smallest gap/a used in the lubrication functions (1e-3)   */
+  double gmres_tol;      /* relative residual ||b - A x|| / ||b||                      */
+  int gmres_restart;     /* Krylov dimension m of GMRES(m)                             */
+  int gmres_maxit;       /* total inner iterations allowed per solve                   */
+  int precision;         /* fsd_precision                                              */
+  double inner_tol;      /* FSD_MIXED: relative tolerance of each FP32 inner solve     */
+  uint64_t seed;         /* key of the counter-based noise generator                   */
+} fsd_params;
+
+typedef struct {
+  int status;                 /* fsd_status of the solve                              */
+  int iterations;             /* GMRES iterations (inner iterations summed in MIXED)  */
+  int restarts;               /* GMRES restarts                                       */
+  int refinements;            /* FP64 outer corrections (MIXED), 1 in FP64            */
+  double rel_residual_fp64;   /* ||b - A x|| / ||b|| recomputed with the FP64 matvec  */
+} fsd_solve_info;
+
+/* Geometry and split actually used (after the parameter rules). */
+typedef struct {
+  double L, xi, r_cut, h, eta_tilde, self_t, self_r;
+  int grid, support, n_bead, n_agg;
+  long long nnz_real, n_lub_pairs;
+} fsd_info;
+
+void fsd_default_params(fsd_params* p);
+
+/* Create a system on the current HIP device.  hip_stream: a hipStream_t to run
+ * on (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a private
+ * stream.  The system owns all of its device memory. */
+fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out);
+
+/* Periodic cube of side L (Section 2.3.1 works in a periodic box). */
+fsd_status fsd_init_box(fsd_system* s, double L);
+
+/* Aggregates (Section 2.3.1): n_agg bodies; bead range of body j is
+ * [bead_offsets[j], bead_offsets[j+1]); x_body (3 per bead) are body-frame
+ * bead centres, re-centred by the callee to zero mean per body (the centroid is
+ * the centre of mass); com (3 per body) is wrapped into the primary box; quat
+ * (4 per body, (w,x,y,z)) is normalised by the callee.  Empty bodies and
+ * zero-norm quaternions give FSD_EINVAL.  Allocates the system's device
+ * memory (the only allocation besides neighbour-list growth). */
+fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* bead_offsets,
+                               const double* x_body, const double* com, const double* quat);
+
+/* Applied force and torque per aggregate, 6 per body (F_P of Eq. `spm_agg`). */
+fsd_status fsd_set_forces(fsd_system* s, const double* ft_agg);
+
+/* Bead-level conservative forces, 3 per bead, projected as Sigma F_P
+ * (Section 2.3.2; Algorithm 1, step 2).  Replaces the aggregate forces. */
+fsd_status fsd_set_bead_forces(fsd_system* s, const double* f_bead);
+
+/* Imposed linear flow u_inf(x) = grad_u . x, grad_u row-major with
+ * grad_u[3*a+b] = d u_a / d x_b, traceless.  E_inf = sym(grad_u),
+ * W_inf = curl(u)/2 (Eq. `gc`). */
+fsd_status fsd_set_shear(fsd_system* s, const double grad_u[9]);
+
+/* One saddle solve at the current configuration.  U_agg (6 per body, host) gets
+ * U = V + U_inf; lambda_bead (6 per bead, host, may be NULL) gets the bead
+ * force moments F.  info may be NULL.  FSD_ENOCONV leaves the last iterate. */
+fsd_status fsd_solve(fsd_system* s, double* U_agg, double* lambda_bead, fsd_solve_info* info);
+
+/* As fsd_solve with device output buffers, stream-ordered on the system stream. */
+fsd_status fsd_solve_dev(fsd_system* s, double* d_U_agg, double* d_lambda, fsd_solve_info* info);
+
+/* n_steps x (solve, explicit Euler update of Eqs. `EM1`-`EM3`).  last gets the
+ * info of the final solve. */
+fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last);
+
+/* Current state: com (3 per body), quat (4 per body), x_bead (3 per bead,
+ * lab frame, unwrapped X_j + R(q_j) x_body; may be NULL). */
+fsd_status fsd_get_state(const fsd_system* s, double* com, double* quat, double* x_bead);
+
+fsd_status fsd_get_info(const fsd_system* s, fsd_info* info);
+
+/* Device bytes a system of this size needs (for admission decisions). */
+size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, double L);
+
+const char* fsd_last_error(const fsd_system* s);
+void fsd_destroy(fsd_system* s);
+
+/* ---- operator access (host buffers), for verification and profiling ---------------- */
+
+/* u = M lambda (6 per bead each).  parts: 1 real-space sum only, 2 wave-space
+ * (spread/FFT/scale/IFFT/interpolate) only, 3 both.  precision: fsd_precision
+ * (MIXED evaluates in FP32).  Section 2.2 far-field mobility. */
+fsd_status fsd_apply_mobility(fsd_system* s, const double* lambda, double* u, int parts, int precision);
+
+/* y = A x for the saddle matrix of Eq. `spm_agg`; x, y of length 6 (Nb + N),
+ * beads first.  precision as above. */
+fsd_status fsd_apply_saddle(fsd_system* s, const double* x, double* y, int precision);
+
+/* z = P^-1 r, the block-triangular preconditioner (Section 2.3.3). */
+fsd_status fsd_apply_precond(fsd_system* s, const double* r, double* z);
+
+/* Right-hand side b of Eq. `spm_agg` (length 6 (Nb + N)). */
+fsd_status fsd_get_rhs(fsd_system* s, double* b);
+
+/* Real-space pair functions used by the sum at distances r (n values):
+ * out[5*k + {0..4}] = (tt_I, tt_rr, rr_I, rr_rr, rt) as in M_real = tt_I I + tt_rr r^r^ ... */
+fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out);
+
+/* In-place 3D complex FFT of an n^3 grid (interleaved re/im doubles, x fastest),
+ * forward (sign -1) or inverse (sign +1, unnormalised), with the library's
+ * transform.  Host buffer; for verification of the FFT stages. */
+fsd_status fsd_fft3d(int n, int sign, double* data);
+
+/* ---- kernel timing on the system stream (HIP events around each launch) ------------- */
+
+typedef enum {
+  FSD_TIMER_REAL = 0,    /* real-space pair sum                                     */
+  FSD_TIMER_SPREAD = 1,  /* Gaussian spreading to the grid                          */
+  FSD_TIMER_FFT = 2,     /* one 1D-transform pass of a 3D FFT (6 per wave apply)     */
+  FSD_TIMER_GREEN = 3,   /* Green's-function scaling of the spectra                 */
+  FSD_TIMER_INTERP = 4,  /* interpolation back to the beads                         */
+  FSD_TIMER_RIGID = 5,   /* Sigma^T V and Sigma reductions                          */
+  FSD_TIMER_LUB = 6,     /* lubrication block product                               */
+  FSD_TIMER_PRECOND = 7, /* preconditioner apply (2 launches)                        */
+  FSD_TIMER_KRYLOV = 8,  /* one CGS2 orthogonalisation (5+ launches)                 */
+  FSD_TIMER_COUNT = 9
+} fsd_timer;
+
+/* Enable (1) or disable (0) event timing and reset the accumulators. */
+fsd_status fsd_set_timing(fsd_system* s, int enable);
+
+/* Accumulated milliseconds and launch counts per fsd_timer class since the last
+ * fsd_set_timing; both arrays hold FSD_TIMER_COUNT entries.  Synchronises. */
+fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSD_H */

@@ -21,4 +21,4 @@ Everything here is plain, dense and FP64:
 Paper sections cited are those of "Fast Stokesian Dynamics for Rigid
 Aggregates" (Mangal et al.).
 """
-from . import rpy, lub, rigid, saddle, integrate  # noqa: F401
+from . import rpy, lub, rigid, saddle, integrate, pse  # noqa: F401

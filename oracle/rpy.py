@@ -315,23 +315,43 @@ def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2
     M = M.transpose(0, 2, 1, 3).reshape(6 * n, 6 * n)
 
     # ---- wave space (half space of k; k and -k combined) --------------------
-    V = L ** 3
-    kc = 2 * r_cut_factor * xi
+    kv, k2 = wave_vectors(L, 2 * r_cut_factor * xi)
+    u = k2 / (4 * xi * xi)
+    hb = (1 + u + 2 * u * u) * np.exp(-u)
+    Mt, Mr, Mrt = wave_sum(x, L, kv, (1 - a * a * k2 / 3) * hb / k2, 0.25 * hb, hb / np.sqrt(k2),
+                           eta, k_chunk)
+    return add_wave(M, Mt, Mr, Mrt)
+
+
+
+def wave_vectors(L, kc):
+    """Half space of k = 2 pi n / L, 0 < |k| < kc (one of each +-k pair)."""
     m = int(math.ceil(kc * L / (2 * math.pi)))
     g = np.arange(-m, m + 1)
     ks = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
-    # keep one of each (k, -k) pair: lexicographically positive integer triples
     pos = (ks[:, 0] > 0) | ((ks[:, 0] == 0) & ((ks[:, 1] > 0) | ((ks[:, 1] == 0) & (ks[:, 2] > 0))))
     kv = (2 * math.pi / L) * ks[pos].astype(float)
     k2 = np.einsum("ij,ij->i", kv, kv)
     keep = k2 < kc * kc
-    kv, k2 = kv[keep], k2[keep]
-    u = k2 / (4 * xi * xi)
-    hb = (1 + u + 2 * u * u) * np.exp(-u)
-    w_tt = 2.0 / (eta * V) * (1 - a * a * k2 / 3) * hb / k2
-    w_rr = 2.0 / (eta * V) * 0.25 * hb
-    w_rt = 1.0 / (eta * V) * hb / np.sqrt(k2)           # times -sin and [k^]x
-    kn = np.sqrt(k2)
+    return kv[keep], k2[keep]
+
+
+def wave_sum(x, L, kv, m_tt, m_rr, m_rt, eta=1.0, k_chunk=2048):
+    """Dense wave-space blocks for multipliers given per k (half space):
+
+        tt: m_tt (I - kk) cos(k.r),  rr: m_rr (I - kk) cos(k.r),
+        rt: (i/2) m_rt [k^]x e^{ik.r} summed with its -k partner,
+
+    each times 2 / (eta V) (the -k partner of tt/rr), i.e. the full lattice sum.
+    Returns (Mt, Mr, Mrt) as 3N x 3N arrays; Mrt maps force to angular velocity.
+    """
+    x = np.asarray(x, dtype=float)
+    n = len(x)
+    V = L ** 3
+    w_tt = 2.0 / (eta * V) * m_tt
+    w_rr = 2.0 / (eta * V) * m_rr
+    w_rt = 1.0 / (eta * V) * m_rt
+    kn = np.linalg.norm(kv, axis=1)
     khat = kv / kn[:, None]
     # two unit vectors orthogonal to k, (e1, e2, k^) right-handed
     ref = np.where(np.abs(khat[:, 2:3]) < 0.9, [[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])
@@ -340,25 +360,30 @@ def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2
     e2 = np.cross(khat, e1)
     Mt = np.zeros((3 * n, 3 * n))
     Mr = np.zeros((3 * n, 3 * n))
-    Mrt = np.zeros((3 * n, 3 * n))      # angular velocity of i from force on j
+    Mrt = np.zeros((3 * n, 3 * n))
     for s in range(0, len(kv), k_chunk):
         sl = slice(s, s + k_chunk)
         ph = x @ kv[sl].T                           # (n, K)
         cs, sn = np.cos(ph), np.sin(ph)
         E1, E2 = e1[sl], e2[sl]
-        # columns: (c e1, c e2, s e1, s e2) per k; rows (bead, component)
+
         def cols(a_, E):
             return (a_[:, None, :] * E.T[None, :, :]).reshape(3 * n, -1)
         C1, C2, S1, S2 = cols(cs, E1), cols(cs, E2), cols(sn, E1), cols(sn, E2)
         Z = np.concatenate([C1, C2, S1, S2], axis=1)
         Mt += (Z * np.tile(w_tt[sl], 4)) @ Z.T
         Mr += (Z * np.tile(w_rr[sl], 4)) @ Z.T
-        # rt: -w sin(k.(xi - xj)) (e2 e1^T - e1 e2^T),
+        # rt pair sum: -w sin(k.(xi - xj)) (e2 e1^T - e1 e2^T),
         # sin(k.(xi-xj)) = s_i c_j - c_i s_j
         wr = np.tile(w_rt[sl], 4)
         Zl = np.concatenate([S2, -S1, -C2, C1], axis=1)
-        Zr = np.concatenate([C1, C2, S1, S2], axis=1)
-        Mrt -= (Zl * wr) @ Zr.T
+        Mrt -= (Zl * wr) @ Z.T
+    return Mt, Mr, Mrt
+
+
+def add_wave(M, Mt, Mr, Mrt):
+    """Add 3N x 3N wave blocks into a 6N x 6N mobility (tr = rt transposed)."""
+    n = M.shape[0] // 6
     M6 = M.reshape(n, 6, n, 6)
     M6[:, :3, :, :3] += Mt.reshape(n, 3, n, 3)
     M6[:, 3:, :, 3:] += Mr.reshape(n, 3, n, 3)

@@ -1,0 +1,280 @@
+"""ctypes binding of include/fsd.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libfsd.so")
+
+if not os.path.exists(library_path):
+    raise ImportError(f"{library_path} is missing: build it with `python -m paper_2607_25161_amd.build`")
+
+lib = C.CDLL(library_path)
+
+FSD_FP64, FSD_MIXED = 0, 1
+_STATUS = {0: "FSD_OK", -1: "FSD_EINVAL", -2: "FSD_ENOMEM", -3: "FSD_ENOCONV", -4: "FSD_EDEVICE",
+           -5: "FSD_ESTATE", -6: "FSD_EOVERLAP", -7: "FSD_EBUSY"}
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("eta", C.c_double), ("radius", C.c_double), ("kT", C.c_double), ("xi", C.c_double),
+        ("ewald_tol", C.c_double), ("grid", C.c_int), ("support", C.c_int), ("r_lub", C.c_double),
+        ("r_precond", C.c_double), ("lub_eps_min", C.c_double), ("gmres_tol", C.c_double),
+        ("gmres_restart", C.c_int), ("gmres_maxit", C.c_int), ("precision", C.c_int),
+        ("inner_tol", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("restarts", C.c_int),
+                ("refinements", C.c_int), ("rel_residual_fp64", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("L", C.c_double), ("xi", C.c_double), ("r_cut", C.c_double), ("h", C.c_double),
+                ("eta_tilde", C.c_double), ("self_t", C.c_double), ("self_r", C.c_double),
+                ("grid", C.c_int), ("support", C.c_int), ("n_bead", C.c_int), ("n_agg", C.c_int),
+                ("nnz_real", C.c_longlong), ("n_lub_pairs", C.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_SYS = C.c_void_p
+
+
+def _sig(name, res, *args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("fsd_default_params", None, C.POINTER(Params))
+_sig("fsd_create", C.c_int, C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p))
+_sig("fsd_init_box", C.c_int, _SYS, C.c_double)
+_sig("fsd_init_aggregates", C.c_int, _SYS, C.c_int32, _I32, _D, _D, _D)
+_sig("fsd_set_forces", C.c_int, _SYS, _D)
+_sig("fsd_set_bead_forces", C.c_int, _SYS, _D)
+_sig("fsd_set_shear", C.c_int, _SYS, _D)
+_sig("fsd_solve", C.c_int, _SYS, _D, _D, C.POINTER(SolveInfo))
+_sig("fsd_solve_dev", C.c_int, _SYS, C.c_void_p, C.c_void_p, C.POINTER(SolveInfo))
+_sig("fsd_step", C.c_int, _SYS, C.c_double, C.c_int, C.POINTER(SolveInfo))
+_sig("fsd_get_state", C.c_int, _SYS, _D, _D, _D)
+_sig("fsd_get_info", C.c_int, _SYS, C.POINTER(Info))
+_sig("fsd_estimate_bytes", C.c_size_t, C.POINTER(Params), C.c_int32, C.c_int32, C.c_double)
+_sig("fsd_last_error", C.c_char_p, _SYS)
+_sig("fsd_destroy", None, _SYS)
+_sig("fsd_apply_mobility", C.c_int, _SYS, _D, _D, C.c_int, C.c_int)
+_sig("fsd_apply_saddle", C.c_int, _SYS, _D, _D, C.c_int)
+_sig("fsd_apply_precond", C.c_int, _SYS, _D, _D)
+_sig("fsd_get_rhs", C.c_int, _SYS, _D)
+_sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
+_sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
+_sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
+_sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong))
+
+TIMER_NAMES = ("real_sum", "spread", "fft_pass", "green_scale", "interp", "rigid", "lub", "precond", "cgs2")
+
+
+class FsdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib.fsd_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def estimate_bytes(params: Params, n_bead: int, n_agg: int, L: float) -> int:
+    return int(lib.fsd_estimate_bytes(C.byref(params), n_bead, n_agg, L))
+
+
+def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
+    """Library 3D FFT of a complex n^3 array (index order [z, y, x]); unnormalised."""
+    a = np.ascontiguousarray(data, dtype=np.complex128)
+    n = a.shape[0]
+    buf = a.view(np.float64).copy()
+    rc = lib.fsd_fft3d(n, sign, _dptr(buf))
+    if rc:
+        raise FsdError(rc, "fsd_fft3d")
+    return buf.view(np.complex128).reshape(a.shape)
+
+
+class System:
+    """One periodic suspension resident on the GPU (wraps fsd_system)."""
+
+    def __init__(self, params: Params | None = None, stream=None, **kw):
+        self.params = params if params is not None else default_params(**kw)
+        h = C.c_void_p()
+        st = C.c_void_p(int(stream)) if stream else None
+        self._check(lib.fsd_create(C.byref(self.params), st, C.byref(h)), "fsd_create", raw=True)
+        self._h = h
+        self.n_agg = self.n_bead = 0
+
+    # -- plumbing ---------------------------------------------------------------------
+    def _check(self, rc, what, raw=False):
+        if rc:
+            msg = what if raw else f"{what}: {lib.fsd_last_error(self._h).decode()}"
+            raise FsdError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.fsd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- setup ------------------------------------------------------------------------
+    def init_box(self, L):
+        self._check(lib.fsd_init_box(self._h, float(L)), "fsd_init_box")
+
+    def init_aggregates(self, offsets, x_body, com, quat):
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        na = len(off) - 1
+        nb = int(off[-1])
+        xb, X, q = _f64(x_body, 3 * nb), _f64(com, 3 * na), _f64(quat, 4 * na)
+        self._check(lib.fsd_init_aggregates(self._h, na, off.ctypes.data_as(_I32), _dptr(xb), _dptr(X), _dptr(q)),
+                    "fsd_init_aggregates")
+        self.n_agg, self.n_bead = na, nb
+
+    def set_forces(self, ft):
+        a = _f64(ft, 6 * self.n_agg)
+        self._check(lib.fsd_set_forces(self._h, _dptr(a)), "fsd_set_forces")
+
+    def set_bead_forces(self, f):
+        a = _f64(f, 3 * self.n_bead)
+        self._check(lib.fsd_set_bead_forces(self._h, _dptr(a)), "fsd_set_bead_forces")
+
+    def set_shear(self, grad_u):
+        a = _f64(grad_u, 9)
+        self._check(lib.fsd_set_shear(self._h, _dptr(a)), "fsd_set_shear")
+
+    # -- solve ------------------------------------------------------------------------
+    def solve(self, want_lambda=False, check=True):
+        U = np.zeros((self.n_agg, 6))
+        lam = np.zeros((self.n_bead, 6)) if want_lambda else None
+        info = SolveInfo()
+        rc = lib.fsd_solve(self._h, _dptr(U), _dptr(lam) if lam is not None else None, C.byref(info))
+        if check:
+            self._check(rc, "fsd_solve")
+        return U, lam, info
+
+    def solve_dev(self, U_ptr: int, lam_ptr: int | None = None, check=True):
+        info = SolveInfo()
+        rc = lib.fsd_solve_dev(self._h, C.c_void_p(U_ptr), C.c_void_p(lam_ptr) if lam_ptr else None, C.byref(info))
+        if check:
+            self._check(rc, "fsd_solve_dev")
+        return info
+
+    def step(self, dt, n_steps=1):
+        info = SolveInfo()
+        self._check(lib.fsd_step(self._h, float(dt), int(n_steps), C.byref(info)), "fsd_step")
+        return info
+
+    def state(self, beads=False):
+        X = np.zeros((self.n_agg, 3))
+        q = np.zeros((self.n_agg, 4))
+        xb = np.zeros((self.n_bead, 3)) if beads else None
+        self._check(lib.fsd_get_state(self._h, _dptr(X), _dptr(q), _dptr(xb) if beads else None), "fsd_get_state")
+        return (X, q, xb) if beads else (X, q)
+
+    def info(self) -> Info:
+        inf = Info()
+        self._check(lib.fsd_get_info(self._h, C.byref(inf)), "fsd_get_info")
+        return inf
+
+    # -- operators --------------------------------------------------------------------
+    def apply_mobility(self, lam, parts=3, precision=FSD_FP64):
+        a = _f64(lam, 6 * self.n_bead)
+        out = np.zeros(6 * self.n_bead)
+        self._check(lib.fsd_apply_mobility(self._h, _dptr(a), _dptr(out), parts, precision), "fsd_apply_mobility")
+        return out
+
+    def apply_saddle(self, x, precision=FSD_FP64):
+        n = 6 * (self.n_bead + self.n_agg)
+        a = _f64(x, n)
+        out = np.zeros(n)
+        self._check(lib.fsd_apply_saddle(self._h, _dptr(a), _dptr(out), precision), "fsd_apply_saddle")
+        return out
+
+    def apply_precond(self, r):
+        n = 6 * (self.n_bead + self.n_agg)
+        a = _f64(r, n)
+        out = np.zeros(n)
+        self._check(lib.fsd_apply_precond(self._h, _dptr(a), _dptr(out)), "fsd_apply_precond")
+        return out
+
+    def rhs(self):
+        out = np.zeros(6 * (self.n_bead + self.n_agg))
+        self._check(lib.fsd_get_rhs(self._h, _dptr(out)), "fsd_get_rhs")
+        return out
+
+    def real_functions(self, r):
+        r = _f64(r)
+        out = np.zeros((len(r), 5))
+        self._check(lib.fsd_real_functions(self._h, len(r), _dptr(r), _dptr(out)), "fsd_real_functions")
+        return out
+
+    # -- timing -----------------------------------------------------------------------
+    def set_timing(self, enable=True):
+        self._check(lib.fsd_set_timing(self._h, 1 if enable else 0), "fsd_set_timing")
+
+    def timers(self):
+        """{class: (total_ms, launches)} since the last set_timing."""
+        ms = np.zeros(len(TIMER_NAMES))
+        cnt = (C.c_longlong * len(TIMER_NAMES))()
+        self._check(lib.fsd_get_timers(self._h, _dptr(ms), cnt), "fsd_get_timers")
+        return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(TIMER_NAMES)}
+
+    # -- convenience ------------------------------------------------------------------
+    @classmethod
+    def from_suspension(cls, s, stream=None, **overrides):
+        """Build from any object with the workload attributes (L, a, eta, offsets, ...)."""
+        kw = dict(eta=s.eta, radius=s.a, xi=s.xi, ewald_tol=s.ewald_tol, grid=s.grid, r_lub=s.r_lub,
+                  r_precond=s.r_precond, gmres_tol=s.gmres_tol, kT=getattr(s, "kT", 0.0))
+        kw.update(overrides)
+        sysm = cls(default_params(**kw), stream=stream)
+        sysm.init_box(s.L)
+        sysm.init_aggregates(s.offsets, s.x_body, s.com, s.quat)
+        sysm.set_forces(s.force)
+        sysm.set_shear(s.grad_u)
+        return sysm

@@ -1,0 +1,112 @@
+// Internal interfaces between the host orchestration (host.cpp) and the HIP
+// kernels (k_*.hip).  Each .hip file defines its kernels and exports plain C++
+// launch wrappers declared here; host.cpp never launches a kernel directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fsd {
+
+constexpr int kMaxStages = 12;
+
+// Mixed-radix plan of one 1D FFT length: n = prod(radix[0..nstage)).
+struct FftPlan {
+  int n;
+  int nstage;
+  int radix[kMaxStages];
+};
+
+// Constants of the wave-space (spectral Ewald) part of the mobility.
+struct WaveParams {
+  int n;            // grid points per side
+  int support;      // Gaussian support P (points per side)
+  double L, h;      // box side, grid spacing
+  double alpha;     // spreading weight exp(-alpha |x - x_m|^2)
+  double xi, eta_t; // splitting parameter and Gaussian split fraction eta~
+  double a, eta;    // bead radius and viscosity
+  double scale;     // h^6 / V * (normalisation of the two Gaussians)^2
+};
+
+// Constants of the real-space part.
+struct RealParams {
+  double L, a, eta;
+  double r_cut;
+  double inv_ht;    // 1 / table spacing
+  int ntab;         // table nodes covering [0, r_cut] (plus 3 guard nodes)
+  double self_t, self_r;
+};
+
+// ---- geometry (k_geometry.hip) ----------------------------------------------------------
+void launch_bead_positions(int nb, int na, const int* body, const double* xbody, const double* com,
+                           const double* quat, double L, double* r4, double* pos4, hipStream_t st);
+void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat,
+                      hipStream_t st);
+
+// Neighbour lists in CSR form.  Column entries pack the bead index (22 bits)
+// and the periodic image shift (3 x 3 bits, offset by 3).
+struct NeighborWork;
+NeighborWork* neighbor_work_create(int nb);
+void neighbor_work_destroy(NeighborWork* w);
+// Returns hipSuccess or an error; on capacity overflow sets *needed > cap and
+// leaves the list unfilled (the caller grows and calls again).
+hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
+                           double cutoff, bool exclude_same_body, int* rowptr, uint32_t* col,
+                           long long cap, long long* needed, hipStream_t st);
+
+void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col,
+                      double a, double eta, double eps_min, double r_pre, double* coef,
+                      double* rdiag, int* overlap_flag, hipStream_t st);
+void launch_precond_factor(int na, const int* offsets, const double* r4, const double* rdiag,
+                           double drag_t, double drag_r, double* lu, int* piv, int* singular,
+                           hipStream_t st);
+
+// ---- mobility (k_mobility.hip) ------------------------------------------------------------
+template <typename R>
+void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr,
+                     const uint32_t* col, const R* table, const RealParams& rp, double* out,
+                     bool accumulate, int lanes_per_row, hipStream_t st);
+template <typename R>
+void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
+                   hipStream_t st);
+// pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
+template <typename R>
+void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
+                  int sign, hipStream_t st, int pass = -1);
+template <typename R>
+void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st);
+template <typename R>
+void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
+                   hipStream_t st);
+
+// ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
+void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1,
+                           double* wt, hipStream_t st);
+void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,
+                      const double* wt, double* f, hipStream_t st);
+void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam,
+                       const double* flub, double* y2, hipStream_t st);
+void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4,
+                          const double* lu, const int* piv, double drag_t, double drag_r,
+                          const double* r, double* z, double* tmp_agg, hipStream_t st);
+void launch_rhs(int nb, int na, const int* offsets, const int* body, const double* r4,
+                const double* E, const double* force, const double* fnf, double* b1, double* e3,
+                hipStream_t st);
+void launch_rhs_agg(int na, const int* offsets, const double* r4, const double* force,
+                    const double* flub_e, double* b2, hipStream_t st);
+void launch_add_ambient(int na, const double* V, const double* com, const double* G,
+                        const double* W, double* U, hipStream_t st);
+
+// dots: partial[q * nblk + b] then out[q]; deterministic two-stage reduction
+int dot_blocks(size_t n);
+void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w,
+                      double* partial, double* out, hipStream_t st);
+void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h,
+                       double sgn, double* w, hipStream_t st);
+void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst,
+                       hipStream_t st);
+void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st);
+
+}  // namespace fsd

@@ -1,0 +1,1228 @@
+// Host side of libfsd: parameter rules, the real-space function table, the
+// saddle operator, the preconditioned GMRES solve, time stepping and the C ABI
+// declared in include/fsd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fsd.h"
+#include "fsd_impl.hpp"
+
+using namespace fsd;
+
+namespace {
+
+struct HipError : std::runtime_error {
+  explicit HipError(const std::string& m) : std::runtime_error(m) {}
+};
+struct ApiError : std::runtime_error {
+  fsd_status code;
+  ApiError(fsd_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(x) hip_check((x), #x)
+
+template <typename T>
+T* dalloc(std::vector<void*>& owned, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sizeof(T) * count);
+  if (e != hipSuccess) throw ApiError(FSD_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+// ---- spherical Bessel functions, stable near 0 ------------------------------------------
+// j0(x), j1(x)/x, j1(x), j2(x): power series for x < 1, trigonometric forms above.
+void sph_bessel(double x, double& j0, double& j1x, double& j1, double& j2) {
+  if (x < 1.0) {
+    const double y = -0.5 * x * x;
+    // j_n(x) = x^n sum_k y^k / (k! (2n+2k+1)!!)
+    double t0 = 1.0, t1 = 1.0 / 3.0, t2 = 1.0 / 15.0;
+    double s0 = t0, s1 = t1, s2 = t2;
+    for (int k = 1; k < 12; ++k) {
+      t0 *= y / (k * (2.0 * k + 1.0));
+      t1 *= y / (k * (2.0 * k + 3.0));
+      t2 *= y / (k * (2.0 * k + 5.0));
+      s0 += t0;
+      s1 += t1;
+      s2 += t2;
+    }
+    j0 = s0;
+    j1x = s1;
+    j1 = x * s1;
+    j2 = x * x * s2;
+  } else {
+    const double s = std::sin(x), c = std::cos(x);
+    j0 = s / x;
+    j1 = s / (x * x) - c / x;
+    j1x = j1 / x;
+    j2 = (3.0 / (x * x) - 1.0) * s / x - 3.0 * c / (x * x);
+  }
+}
+
+void sinc_jv_host(double x, double& s, double& j) {
+  double j0, j1x, j1, j2;
+  sph_bessel(x, j0, j1x, j1, j2);
+  s = j0;
+  j = 3.0 * j1x;  // jv(x) = 3 j1(x) / x
+}
+
+// ---- real-space smooth part ----------------------------------------------------------------
+// S(r): inverse transform of the Hasimoto-damped FT-RPY multipliers
+//   tt: sinc^2(ka) H(k) (I - kk)/k^2,  rr: jv^2(ka) H(k) (I - kk)/4,  rt: (i/2) sinc jv H [k]x / k^2,
+//   H(k) = (1 + k^2/(4 xi^2)) exp(-k^2/(4 xi^2)).
+// Angular integration leaves radial integrals of j0 - j1/x (I part), j2 (rr part) and
+// k j1 (rt part).  The integrands are even, entire in k and Gaussian-decaying, so the
+// trapezoid rule on a step below 2 pi / (band of the integrand) is spectrally accurate.
+struct SmoothPart {
+  std::vector<double> k, wtt, wrr, wrt;  // nodes and multiplier-times-weight
+  double eta;
+  SmoothPart(double a, double eta_, double xi, double rmax) : eta(eta_) {
+    const double kmax = 2.0 * xi * std::sqrt(46.0);
+    const double band = rmax + 2.0 * a + 7.0 / xi;
+    const double hk = 2.0 * M_PI / band / 2.0;
+    const int nk = int(std::ceil(kmax / hk)) + 1;
+    for (int m = 0; m < nk; ++m) {
+      const double kk = m * hk;
+      const double q = kk * kk / (4.0 * xi * xi);
+      const double H = (1.0 + q) * std::exp(-q);
+      double s, j;
+      sinc_jv_host(kk * a, s, j);
+      const double w = (m == 0 ? 0.5 : 1.0) * hk;
+      k.push_back(kk);
+      wtt.push_back(w * s * s * H);
+      wrr.push_back(w * 0.25 * kk * kk * j * j * H);
+      wrt.push_back(w * kk * s * j * H);
+    }
+  }
+  // out: (tI, tR, rI, rR, c) of S at distance r (r may be negative or zero)
+  void eval(double r, double* out) const {
+    double tI = 0, tR = 0, rI = 0, rR = 0, c = 0;
+    const double ar = std::fabs(r);
+    for (size_t m = 0; m < k.size(); ++m) {
+      double j0, j1x, j1, j2;
+      sph_bessel(k[m] * ar, j0, j1x, j1, j2);
+      const double fI = j0 - j1x;
+      tI += wtt[m] * fI;
+      tR += wtt[m] * j2;
+      rI += wrr[m] * fI;
+      rR += wrr[m] * j2;
+      c += wrt[m] * j1;
+    }
+    const double p = 1.0 / (2.0 * M_PI * M_PI * eta);
+    out[0] = p * tI;
+    out[1] = p * tR;
+    out[2] = p * rI;
+    out[3] = p * rR;
+    out[4] = -(r < 0 ? -1.0 : 1.0) * c / (4.0 * M_PI * M_PI * eta);
+  }
+};
+
+void rpy_free(double r, double a, double eta, double* o) {
+  const double c8 = 1.0 / (8.0 * M_PI * eta);
+  const double mt = 1.0 / (6.0 * M_PI * eta * a), mr = 1.0 / (8.0 * M_PI * eta * a * a * a);
+  if (r >= 2.0 * a) {
+    const double ir = 1.0 / r, ir2 = ir * ir;
+    o[0] = c8 * ir * (1.0 + 2.0 / 3.0 * a * a * ir2);
+    o[1] = c8 * ir * (1.0 - 2.0 * a * a * ir2);
+    o[2] = -0.5 * c8 * ir * ir2;
+    o[3] = 1.5 * c8 * ir * ir2;
+    o[4] = -c8 * ir2;
+  } else {
+    const double s = r / a;
+    o[0] = mt * (1.0 - 9.0 / 32.0 * s);
+    o[1] = mt * 3.0 / 32.0 * s;
+    o[2] = mr * (1.0 - 27.0 / 32.0 * s + 5.0 / 64.0 * s * s * s);
+    o[3] = mr * (9.0 / 32.0 * s - 3.0 / 64.0 * s * s * s);
+    o[4] = -0.5 * c8 / (a * a) * s * (1.0 - 3.0 / 8.0 * s);
+  }
+}
+
+// ---- FFT plan ---------------------------------------------------------------------------------
+bool make_plan(int n, FftPlan& p) {
+  p.n = n;
+  p.nstage = 0;
+  int m = n;
+  while (m % 4 == 0 && p.nstage < kMaxStages) {
+    p.radix[p.nstage++] = 4;
+    m /= 4;
+  }
+  while (m % 2 == 0 && p.nstage < kMaxStages) {
+    p.radix[p.nstage++] = 2;
+    m /= 2;
+  }
+  while (m % 3 == 0 && p.nstage < kMaxStages) {
+    p.radix[p.nstage++] = 3;
+    m /= 3;
+  }
+  return m == 1 && n >= 2;
+}
+
+int next_smooth(int n) {
+  for (int m = std::max(n, 4);; ++m) {
+    int k = m;
+    while (k % 2 == 0) k /= 2;
+    while (k % 3 == 0) k /= 3;
+    if (k == 1) return m;
+  }
+}
+
+}  // namespace
+
+// ==========================================================================================
+// system
+// ==========================================================================================
+
+struct fsd_system {
+  fsd_params p{};
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::string err;
+
+  double L = 0;
+  int nb = 0, na = 0;
+  bool have_box = false, have_agg = false, prepared = false;
+  double G[9] = {0}, E[9] = {0}, W[3] = {0};
+
+  RealParams rp{};
+  WaveParams wp{};
+  FftPlan plan{};
+  int lpr = 4;
+  double drag_t = 0, drag_r = 0;
+  size_t n = 0;
+  int m = 30;
+
+  std::vector<int> h_offsets;
+  std::vector<void*> owned;
+  int *d_offsets = nullptr, *d_body = nullptr;
+  double *d_xbody = nullptr, *d_com = nullptr, *d_quat = nullptr, *d_r4 = nullptr, *d_pos4 = nullptr;
+  double *d_force = nullptr, *d_G = nullptr, *d_E = nullptr, *d_W = nullptr;
+  double* d_tab64 = nullptr;
+  float* d_tab32 = nullptr;
+  int* d_nrow = nullptr;
+  uint32_t* d_ncol = nullptr;
+  long long ncap = 0, nnz = 0;
+  int* d_lrow = nullptr;
+  uint32_t* d_lcol = nullptr;
+  double* d_lcoef = nullptr;
+  long long lcap = 0, nlub = 0, lcoef_cap = 0;
+  double *d_rdiag = nullptr, *d_lu = nullptr;
+  int *d_piv = nullptr, *d_flags = nullptr;
+  void* d_grid = nullptr;
+  double* d_tw64 = nullptr;
+  float* d_tw32 = nullptr;
+  double *d_b = nullptr, *d_x = nullptr, *d_basis = nullptr, *d_z = nullptr, *d_w = nullptr, *d_t = nullptr;
+  double *d_r = nullptr, *d_wt = nullptr, *d_fl = nullptr, *d_h = nullptr, *d_part = nullptr, *d_U = nullptr;
+  double* h_small = nullptr;  // pinned
+  NeighborWork* nw = nullptr;
+  std::vector<double> h_tab;  // host copy of the smooth-part table (5 per node, 8 stride)
+
+  // per-kernel-class event timing (fsd_set_timing)
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  std::vector<Pending> pending;
+  double t_ms[FSD_TIMER_COUNT] = {0};
+  long long t_n[FSD_TIMER_COUNT] = {0};
+
+  ~fsd_system() { release(); }
+  void release() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
+    if (nw) neighbor_work_destroy(nw);
+    nw = nullptr;
+    for (void* q : owned) (void)hipFree(q);
+    owned.clear();
+    if (h_small) (void)hipHostFree(h_small);
+    h_small = nullptr;
+  }
+};
+
+namespace {
+
+fsd_status fail(fsd_system* s, fsd_status c, const std::string& m) {
+  if (s) s->err = m;
+  return c;
+}
+
+template <typename F>
+fsd_status guarded(fsd_system* s, F&& f) {
+  try {
+    return f();
+  } catch (const ApiError& e) {
+    return fail(s, e.code, e.what());
+  } catch (const HipError& e) {
+    return fail(s, FSD_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(s, FSD_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(s, FSD_EDEVICE, e.what());
+  }
+}
+
+// ---- event timing -------------------------------------------------------------------------
+void harvest_timers(fsd_system* s) {
+  if (s->pending.empty()) return;
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (auto& p : s->pending) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    s->t_ms[p.cls] += ms;
+    s->t_n[p.cls] += 1;
+  }
+  s->pending.clear();
+  s->ev_next = 0;
+}
+
+hipEvent_t next_event(fsd_system* s) {
+  if (s->ev_next == s->ev_pool.size()) {
+    if (s->ev_pool.size() < 4096) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      s->ev_pool.push_back(e);
+    } else {
+      harvest_timers(s);
+    }
+  }
+  return s->ev_pool[s->ev_next++];
+}
+
+// Records events around one kernel launch on the system stream when timing is on.
+struct Timed {
+  fsd_system* s;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(fsd_system* s_, int c) : s(s_), cls(c) {
+    if (s->timing) {
+      a = next_event(s);
+      HIPCHK(hipEventRecord(a, s->st));
+    }
+  }
+  ~Timed() noexcept(false) {
+    if (a) {
+      hipEvent_t b = next_event(s);
+      HIPCHK(hipEventRecord(b, s->st));
+      s->pending.push_back({cls, a, b});
+    }
+  }
+};
+
+// ---- parameter rules (Section 3.2: R_c = sqrt(-ln x_err)/xi, k_c = 2 sqrt(-ln x_err) xi + 1) --
+void choose_parameters(fsd_system* s) {
+  const fsd_params& p = s->p;
+  const double a = p.radius, L = s->L;
+  const double xi = p.xi > 0 ? p.xi : 0.5 / a;
+  const double tol = p.ewald_tol;
+  const double lnt = std::sqrt(-std::log(tol));
+  const double rc = lnt / xi;
+  const double kc = 2.0 * lnt * xi + 1.0 / a;
+  int N = p.grid > 0 ? p.grid : next_smooth(int(std::ceil(kc * L / M_PI)));
+  if (!make_plan(N, s->plan))
+    throw ApiError(FSD_EINVAL, "grid size must be a product of powers of 2 and 3");
+  int P = p.support > 0 ? p.support : int(std::ceil(2.0 / M_PI * std::log(1.0 / tol))) + 2;
+  P = std::max(4, std::min(P, 21));
+  if (P > N) throw ApiError(FSD_EINVAL, "Gaussian support exceeds the grid");
+  const double h = L / N;
+  const double mshape = 0.976 * std::sqrt(M_PI * P);
+  const double eta_t = std::pow(P * h * xi / mshape, 2.0);
+  if (eta_t >= 1.0) throw ApiError(FSD_EINVAL, "grid too coarse for the splitting parameter and support");
+  if (p.r_lub > 0 && p.r_lub >= 0.5 * L) throw ApiError(FSD_EINVAL, "lubrication cutoff must be below L/2");
+  WaveParams& w = s->wp;
+  w.n = N;
+  w.support = P;
+  w.L = L;
+  w.h = h;
+  w.xi = xi;
+  w.eta_t = eta_t;
+  w.alpha = 2.0 * xi * xi / eta_t;
+  w.a = a;
+  w.eta = p.eta;
+  const double gnorm = std::pow(2.0 * xi * xi / (M_PI * eta_t), 1.5);
+  w.scale = std::pow(h, 6) / (L * L * L) * gnorm * gnorm;
+  RealParams& r = s->rp;
+  r.L = L;
+  r.a = a;
+  r.eta = p.eta;
+  // Real-space cutoff: the rule sqrt(-ln tol)/xi is the floor; the polynomial
+  // prefactors of the split leave the pair functions above tol there, so the
+  // cutoff grows until every function is below tol times the self-mobility.
+  const double mt = 1.0 / (6.0 * M_PI * p.eta * a), mr = 1.0 / (8.0 * M_PI * p.eta * a * a * a);
+  double rcut = rc;
+  {
+    SmoothPart probe(a, p.eta, xi, 3.0 * rc);
+    const double scale[5] = {mt, mt, mr, mr, mt};
+    for (int it = 0; it < 400; ++it, rcut *= 1.005) {
+      double f[5], sm[5];
+      rpy_free(rcut, a, p.eta, f);
+      probe.eval(rcut, sm);
+      double worst = 0;
+      for (int k = 0; k < 5; ++k) worst = std::max(worst, std::fabs(f[k] - sm[k]) / scale[k]);
+      if (worst <= tol) break;
+    }
+  }
+  if (rcut >= 3.0 * L) throw ApiError(FSD_EINVAL, "real-space cutoff exceeds three box lengths; raise xi");
+  r.r_cut = rcut;
+  const int ntab = 4096;
+  const double ht = rcut / ntab;
+  r.inv_ht = 1.0 / ht;
+  r.ntab = ntab;
+  SmoothPart sp(a, p.eta, xi, rcut + 4 * ht);
+  s->h_tab.assign(size_t(ntab + 4) * 8, 0.0);
+  for (int t = 0; t < ntab + 4; ++t) sp.eval((t - 1) * ht, &s->h_tab[8 * size_t(t)]);
+  double s0[5];
+  sp.eval(0.0, s0);
+  r.self_t = mt - s0[0];
+  r.self_r = mr - s0[2];
+  s->drag_t = 6.0 * M_PI * p.eta * a;
+  s->drag_r = 8.0 * M_PI * p.eta * a * a * a;
+}
+
+void upload_tables(fsd_system* s) {
+  const size_t nt = s->h_tab.size();
+  s->d_tab64 = dalloc<double>(s->owned, nt);
+  s->d_tab32 = dalloc<float>(s->owned, nt);
+  std::vector<float> f(nt);
+  for (size_t i = 0; i < nt; ++i) f[i] = float(s->h_tab[i]);
+  HIPCHK(hipMemcpy(s->d_tab64, s->h_tab.data(), nt * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->d_tab32, f.data(), nt * sizeof(float), hipMemcpyHostToDevice));
+  const int N = s->wp.n;
+  std::vector<double> tw(2 * N);
+  std::vector<float> twf(2 * N);
+  for (int t = 0; t < N; ++t) {
+    // e^{-2 pi i t / N}
+    tw[2 * t] = std::cos(2.0 * M_PI * t / N);
+    tw[2 * t + 1] = -std::sin(2.0 * M_PI * t / N);
+    twf[2 * t] = float(tw[2 * t]);
+    twf[2 * t + 1] = float(tw[2 * t + 1]);
+  }
+  s->d_tw64 = dalloc<double>(s->owned, 2 * N);
+  s->d_tw32 = dalloc<float>(s->owned, 2 * N);
+  HIPCHK(hipMemcpy(s->d_tw64, tw.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(s->d_tw32, twf.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+}
+
+void build_list(fsd_system* s, double cutoff, bool exclude, int* rowptr, uint32_t*& col, long long& cap,
+                long long& count) {
+  long long needed = 0;
+  HIPCHK(build_neighbors(s->nw, s->nb, s->d_pos4, s->d_body, s->L, cutoff, exclude, rowptr, col, cap, &needed,
+                         s->st));
+  if (needed > cap) {
+    // grow (the only allocation after setup) and rebuild
+    auto it = std::find(s->owned.begin(), s->owned.end(), (void*)col);
+    if (it != s->owned.end()) {
+      (void)hipFree(*it);
+      s->owned.erase(it);
+    }
+    cap = needed + needed / 4 + 64;
+    col = dalloc<uint32_t>(s->owned, size_t(cap));
+    HIPCHK(build_neighbors(s->nw, s->nb, s->d_pos4, s->d_body, s->L, cutoff, exclude, rowptr, col, cap, &needed,
+                           s->st));
+  }
+  count = needed;
+}
+
+// Algorithm 1 step 1 plus the geometry it needs: bead positions, neighbour lists,
+// lubrication coefficients, per-aggregate LU of the Schur approximation.
+void prepare(fsd_system* s) {
+  if (s->prepared) return;
+  launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->d_r4, s->d_pos4, s->st);
+  build_list(s, s->rp.r_cut, false, s->d_nrow, s->d_ncol, s->ncap, s->nnz);
+  HIPCHK(hipMemsetAsync(s->d_flags, 0, 2 * sizeof(int), s->st));
+  if (s->p.r_lub > 0) {
+    build_list(s, s->p.r_lub, true, s->d_lrow, s->d_lcol, s->lcap, s->nlub);
+    if (s->lcoef_cap < s->lcap) {
+      auto it = std::find(s->owned.begin(), s->owned.end(), (void*)s->d_lcoef);
+      if (it != s->owned.end()) {
+        (void)hipFree(*it);
+        s->owned.erase(it);
+      }
+      s->d_lcoef = dalloc<double>(s->owned, size_t(5 * s->lcap));
+      s->lcoef_cap = s->lcap;
+    }
+    launch_lub_setup(s->nb, s->d_pos4, s->L, s->d_lrow, s->d_lcol, s->p.radius, s->p.eta, s->p.lub_eps_min,
+                     s->p.r_precond, s->d_lcoef, s->d_rdiag, s->d_flags, s->st);
+  } else {
+    HIPCHK(hipMemsetAsync(s->d_rdiag, 0, sizeof(double) * 6 * s->nb, s->st));
+    s->nlub = 0;
+  }
+  launch_precond_factor(s->na, s->d_offsets, s->d_r4, s->d_rdiag, s->drag_t, s->drag_r, s->d_lu, s->d_piv,
+                        s->d_flags + 1, s->st);
+  int flags[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(flags, s->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  if (flags[0]) throw ApiError(FSD_EOVERLAP, "beads of different bodies overlap by more than a/2");
+  if (flags[1]) throw ApiError(FSD_EDEVICE, "singular aggregate block in the preconditioner");
+  const double avg = s->nb ? double(s->nnz) / s->nb : 0.0;
+  int l = 1;
+  while (l < 64 && l * 6 < avg) l *= 2;
+  s->lpr = l;
+  s->prepared = true;
+}
+
+}  // namespace
+
+// ==========================================================================================
+// operators
+// ==========================================================================================
+
+namespace {
+
+template <typename R>
+const R* table_of(fsd_system* s);
+template <>
+const double* table_of<double>(fsd_system* s) {
+  return s->d_tab64;
+}
+template <>
+const float* table_of<float>(fsd_system* s) {
+  return s->d_tab32;
+}
+template <typename R>
+const R* twiddle_of(fsd_system* s);
+template <>
+const double* twiddle_of<double>(fsd_system* s) {
+  return s->d_tw64;
+}
+template <>
+const float* twiddle_of<float>(fsd_system* s) {
+  return s->d_tw32;
+}
+
+// out = M lam (parts: 1 real space, 2 wave space)
+template <typename R>
+void apply_mobility(fsd_system* s, const double* lam, double* out, int parts) {
+  if (parts & 1) {
+    Timed t(s, FSD_TIMER_REAL);
+    launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr,
+                       s->st);
+  } else {
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(double) * 6 * s->nb, s->st));
+  }
+  if (parts & 2) {
+    const int N = s->wp.n;
+    const size_t cs = 2 * size_t(N) * N * N;  // R elements per complex component grid
+    R* grid = static_cast<R*>(s->d_grid);
+    HIPCHK(hipMemsetAsync(grid, 0, sizeof(R) * 3 * cs, s->st));
+    {
+      Timed t(s, FSD_TIMER_SPREAD);
+      launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st);
+    }
+    for (int ps = 0; ps < 3; ++ps) {
+      Timed t(s, FSD_TIMER_FFT);
+      launch_fft3d<R>(grid, 3, cs, s->plan, twiddle_of<R>(s), -1, s->st, ps);
+    }
+    {
+      Timed t(s, FSD_TIMER_GREEN);
+      launch_green_scale<R>(grid, cs, s->wp, s->st);
+    }
+    for (int ps = 0; ps < 3; ++ps) {
+      Timed t(s, FSD_TIMER_FFT);
+      launch_fft3d<R>(grid, 3, cs, s->plan, twiddle_of<R>(s), +1, s->st, ps);
+    }
+    {
+      Timed t(s, FSD_TIMER_INTERP);
+      launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st);
+    }
+  }
+}
+
+// y = A x for the saddle matrix [[M, Sigma^T], [Sigma, -Sigma R_nf Sigma^T]]
+template <typename R>
+void apply_saddle(fsd_system* s, const double* x, double* y) {
+  const size_t nb6 = 6 * size_t(s->nb);
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  apply_mobility<R>(s, x, y, 3);
+  {
+    Timed t(s, FSD_TIMER_RIGID);
+    launch_rigid_velocity(s->nb, s->d_body, s->d_r4, x + nb6, y, lub ? s->d_wt : nullptr, s->st);
+  }
+  if (lub) {
+    Timed t(s, FSD_TIMER_LUB);
+    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
+  }
+  {
+    Timed t(s, FSD_TIMER_RIGID);
+    launch_agg_reduce(s->na, s->d_offsets, s->d_r4, x, lub ? s->d_fl : nullptr, y + nb6, s->st);
+  }
+}
+
+void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32) {
+  if (fp32)
+    apply_saddle<float>(s, x, y);
+  else
+    apply_saddle<double>(s, x, y);
+}
+
+void apply_precond(fsd_system* s, const double* r, double* z) {
+  Timed t(s, FSD_TIMER_PRECOND);
+  // M~^-1 = diag(6 pi eta a, 8 pi eta a^3): the bead drag (inverse self-mobility)
+  launch_precond_apply(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, r,
+                       z, nullptr, s->st);
+}
+
+void assemble_rhs(fsd_system* s) {
+  const size_t nb6 = 6 * size_t(s->nb);
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  launch_rhs(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_E, s->d_force, nullptr, s->d_b, s->d_wt, s->st);
+  if (lub) launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
+  launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_force, lub ? s->d_fl : nullptr, s->d_b + nb6, s->st);
+}
+
+// ||v||^2 and similar small reductions land in s->h_small after a sync
+double norm2(fsd_system* s, const double* v) {
+  launch_multi_dot(s->n, 1, v, s->n, v, s->d_part, s->d_h, s->st);
+  HIPCHK(hipMemcpyAsync(s->h_small, s->d_h, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return std::sqrt(s->h_small[0]);
+}
+
+struct GmresOut {
+  int its = 0, restarts = 0;
+  double rel = 0;
+  bool converged = false;
+};
+
+// Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
+// twice (CGS2).  x is the initial guess on entry and the iterate on exit.
+// The stopping test uses the recomputed residual ||b - A x|| / ||b||.
+GmresOut gmres(fsd_system* s, const double* b, double* x, double tol, bool fp32, int maxit) {
+  GmresOut o;
+  const size_t n = s->n;
+  const int m = s->m;
+  double* V = s->d_basis;
+  const double bn = norm2(s, b);
+  if (bn == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, s->st));
+    o.converged = true;
+    return o;
+  }
+  std::vector<double> H(size_t(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  double* hs = s->h_small;  // pinned: [0, m+1) first pass, [m+1, 2m+2) second pass, 2m+2 norm
+  while (true) {
+    apply_saddle_p(s, x, s->d_t, fp32);
+    launch_sub(n, b, s->d_t, s->d_r, s->st);
+    const double beta = norm2(s, s->d_r);
+    o.rel = beta / bn;
+    if (o.rel <= tol) {
+      o.converged = true;
+      return o;
+    }
+    if (o.its >= maxit) return o;
+    launch_axpby(n, 1.0 / beta, s->d_r, 0.0, V, s->st);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k_used = 0;
+    for (int k = 0; k < m; ++k) {
+      apply_precond(s, V + size_t(k) * n, s->d_z);
+      apply_saddle_p(s, s->d_z, s->d_w, fp32);
+      {  // CGS2
+        Timed t(s, FSD_TIMER_KRYLOV);
+        launch_multi_dot(n, k + 1, V, n, s->d_w, s->d_part, s->d_h, s->st);
+        launch_multi_axpy(n, k + 1, V, n, s->d_h, -1.0, s->d_w, s->st);
+        launch_multi_dot(n, k + 1, V, n, s->d_w, s->d_part, s->d_h + (m + 1), s->st);
+        launch_multi_axpy(n, k + 1, V, n, s->d_h + (m + 1), -1.0, s->d_w, s->st);
+        launch_multi_dot(n, 1, s->d_w, n, s->d_w, s->d_part, s->d_h + 2 * (m + 1), s->st);
+      }
+      HIPCHK(hipMemcpyAsync(hs, s->d_h, sizeof(double) * (2 * (m + 1) + 1), hipMemcpyDeviceToHost, s->st));
+      HIPCHK(hipStreamSynchronize(s->st));
+      for (int j = 0; j <= k; ++j) H[size_t(j) * m + k] = hs[j] + hs[m + 1 + j];
+      const double hn = std::sqrt(std::max(hs[2 * (m + 1)], 0.0));
+      H[size_t(k + 1) * m + k] = hn;
+      if (hn > 0) launch_axpby(n, 1.0 / hn, s->d_w, 0.0, V + size_t(k + 1) * n, s->st);
+      for (int j = 0; j < k; ++j) {
+        const double t = cs[j] * H[size_t(j) * m + k] + sn[j] * H[size_t(j + 1) * m + k];
+        H[size_t(j + 1) * m + k] = -sn[j] * H[size_t(j) * m + k] + cs[j] * H[size_t(j + 1) * m + k];
+        H[size_t(j) * m + k] = t;
+      }
+      const double den = std::hypot(H[size_t(k) * m + k], H[size_t(k + 1) * m + k]);
+      cs[k] = H[size_t(k) * m + k] / den;
+      sn[k] = H[size_t(k + 1) * m + k] / den;
+      H[size_t(k) * m + k] = den;
+      H[size_t(k + 1) * m + k] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++o.its;
+      k_used = k + 1;
+      if (std::fabs(g[k + 1]) / bn <= tol || o.its >= maxit || hn == 0.0) break;
+    }
+    for (int i = k_used - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int j = i + 1; j < k_used; ++j) t -= H[size_t(i) * m + j] * y[j];
+      y[i] = t / H[size_t(i) * m + i];
+    }
+    for (int i = 0; i < k_used; ++i) hs[i] = y[i];
+    HIPCHK(hipMemcpyAsync(s->d_h, hs, sizeof(double) * k_used, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemsetAsync(s->d_t, 0, sizeof(double) * n, s->st));
+    launch_multi_axpy(n, k_used, V, n, s->d_h, 1.0, s->d_t, s->st);
+    apply_precond(s, s->d_t, s->d_z);
+    launch_axpby(n, 1.0, s->d_z, 1.0, x, s->st);
+    ++o.restarts;
+  }
+}
+
+fsd_status solve_current(fsd_system* s, fsd_solve_info* info) {
+  prepare(s);
+  assemble_rhs(s);
+  const size_t n = s->n;
+  HIPCHK(hipMemsetAsync(s->d_x, 0, sizeof(double) * n, s->st));
+  fsd_solve_info inf{};
+  bool ok = false;
+  if (s->p.precision == FSD_MIXED) {
+    // FP64 outer residual, FP32-matvec GMRES corrections
+    const double bn = norm2(s, s->d_b);
+    int outer = 0;
+    double rel = 1.0;
+    for (; outer < 50; ++outer) {
+      apply_saddle<double>(s, s->d_x, s->d_t);
+      launch_sub(n, s->d_b, s->d_t, s->d_r, s->st);
+      rel = bn > 0 ? norm2(s, s->d_r) / bn : 0.0;
+      if (rel <= s->p.gmres_tol || inf.iterations >= s->p.gmres_maxit) break;
+      // correction A d = r with FP32 matvecs; two spare vectors follow the Krylov basis
+      double* corr = s->d_basis + size_t(s->m + 1) * n;  // spare vector after the basis
+      double* rhs = s->d_basis + size_t(s->m + 2) * n;
+      HIPCHK(hipMemcpyAsync(rhs, s->d_r, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
+      HIPCHK(hipMemsetAsync(corr, 0, sizeof(double) * n, s->st));
+      GmresOut go = gmres(s, rhs, corr, s->p.inner_tol, true, s->p.gmres_maxit - inf.iterations);
+      inf.iterations += go.its;
+      inf.restarts += go.restarts;
+      launch_axpby(n, 1.0, corr, 1.0, s->d_x, s->st);
+    }
+    inf.refinements = outer;
+    inf.rel_residual_fp64 = rel;
+    ok = rel <= s->p.gmres_tol;
+  } else {
+    GmresOut go = gmres(s, s->d_b, s->d_x, s->p.gmres_tol, false, s->p.gmres_maxit);
+    inf.iterations = go.its;
+    inf.restarts = go.restarts;
+    inf.refinements = 1;
+    inf.rel_residual_fp64 = go.rel;
+    ok = go.converged;
+  }
+  const size_t nb6 = 6 * size_t(s->nb);
+  launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
+  inf.status = ok ? FSD_OK : FSD_ENOCONV;
+  if (info) *info = inf;
+  if (!ok) s->err = "GMRES did not reach the tolerance within gmres_maxit iterations";
+  return ok ? FSD_OK : FSD_ENOCONV;
+}
+
+fsd_status check_ready(fsd_system* s) {
+  if (!s) return FSD_EINVAL;
+  if (!s->have_box || !s->have_agg) return fail(s, FSD_ESTATE, "call fsd_init_box and fsd_init_aggregates first");
+  return FSD_OK;
+}
+
+}  // namespace
+
+// ==========================================================================================
+// C ABI
+// ==========================================================================================
+
+extern "C" {
+
+void fsd_default_params(fsd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->eta = 1.0;
+  p->radius = 1.0;
+  p->kT = 0.0;
+  p->xi = 0.0;
+  p->ewald_tol = 1e-6;
+  p->grid = 0;
+  p->support = 0;
+  p->r_lub = 3.0;
+  p->r_precond = 2.1;
+  p->lub_eps_min = 1e-3;
+  p->gmres_tol = 1e-6;
+  p->gmres_restart = 30;
+  p->gmres_maxit = 1000;
+  p->precision = FSD_FP64;
+  p->inner_tol = 1e-3;
+  p->seed = 2607251610ull;
+}
+
+fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out) {
+  if (!p || !out) return FSD_EINVAL;
+  if (!(p->eta > 0) || !(p->radius > 0) || !(p->ewald_tol > 0 && p->ewald_tol < 1) || !(p->gmres_tol > 0) ||
+      p->gmres_restart < 1 || p->gmres_restart > 200 || p->gmres_maxit < 1 || p->grid < 0 || p->support < 0 ||
+      p->support > 21 || p->r_lub < 0 || (p->precision != FSD_FP64 && p->precision != FSD_MIXED) ||
+      !(p->inner_tol > 0 && p->inner_tol < 1) || p->kT < 0)
+    return FSD_EINVAL;
+  fsd_system* s = new (std::nothrow) fsd_system;
+  if (!s) return FSD_ENOMEM;
+  s->p = *p;
+  s->m = p->gmres_restart;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return FSD_EDEVICE;
+  }
+  if (hip_stream) {
+    s->st = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreate(&s->st) != hipSuccess) {
+      delete s;
+      return FSD_EDEVICE;
+    }
+    s->own_stream = true;
+  }
+  *out = s;
+  return FSD_OK;
+}
+
+fsd_status fsd_init_box(fsd_system* s, double L) {
+  if (!s) return FSD_EINVAL;
+  if (!(L > 4.0 * s->p.radius)) return fail(s, FSD_EINVAL, "box side must exceed 4a");
+  if (s->have_agg) return fail(s, FSD_ESTATE, "the box is fixed once aggregates are set");
+  s->L = L;
+  s->have_box = true;
+  return FSD_OK;
+}
+
+fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off, const double* x_body,
+                               const double* com, const double* quat) {
+  if (!s) return FSD_EINVAL;
+  if (!s->have_box) return fail(s, FSD_ESTATE, "call fsd_init_box first");
+  if (s->have_agg) return fail(s, FSD_ESTATE, "aggregates already set");
+  if (n_agg < 1 || !off || !x_body || !com || !quat) return fail(s, FSD_EINVAL, "null or empty input");
+  if (off[0] != 0) return fail(s, FSD_EINVAL, "bead_offsets[0] must be 0");
+  for (int j = 0; j < n_agg; ++j)
+    if (off[j + 1] <= off[j]) return fail(s, FSD_EINVAL, "every aggregate needs at least one bead");
+  const int nb = off[n_agg];
+  if (nb >= (1 << 22)) return fail(s, FSD_EINVAL, "at most 4194303 beads");
+  const double L = s->L;
+  std::vector<double> xb(x_body, x_body + 3 * size_t(nb)), X(3 * size_t(n_agg)), q(4 * size_t(n_agg));
+  for (int i = 0; i < 3 * nb; ++i)
+    if (!std::isfinite(xb[i])) return fail(s, FSD_EINVAL, "non-finite body coordinates");
+  for (int j = 0; j < n_agg; ++j) {
+    double c[3] = {0, 0, 0};
+    const int n = off[j + 1] - off[j];
+    for (int i = off[j]; i < off[j + 1]; ++i)
+      for (int d = 0; d < 3; ++d) c[d] += xb[3 * i + d] / n;
+    for (int i = off[j]; i < off[j + 1]; ++i)
+      for (int d = 0; d < 3; ++d) xb[3 * i + d] -= c[d];
+    double nq = 0;
+    for (int d = 0; d < 4; ++d) nq += quat[4 * j + d] * quat[4 * j + d];
+    nq = std::sqrt(nq);
+    if (!(nq > 0) || !std::isfinite(nq)) return fail(s, FSD_EINVAL, "zero or non-finite quaternion");
+    for (int d = 0; d < 4; ++d) q[4 * j + d] = quat[4 * j + d] / nq;
+    // the body-frame centroid shift moves the centroid in the lab frame by R(q) c
+    const double w = q[4 * j], x = q[4 * j + 1], y = q[4 * j + 2], z = q[4 * j + 3];
+    const double Rc[3] = {(1 - 2 * (y * y + z * z)) * c[0] + 2 * (x * y - w * z) * c[1] + 2 * (x * z + w * y) * c[2],
+                          2 * (x * y + w * z) * c[0] + (1 - 2 * (x * x + z * z)) * c[1] + 2 * (y * z - w * x) * c[2],
+                          2 * (x * z - w * y) * c[0] + 2 * (y * z + w * x) * c[1] + (1 - 2 * (x * x + y * y)) * c[2]};
+    for (int d = 0; d < 3; ++d) {
+      if (!std::isfinite(com[3 * j + d])) return fail(s, FSD_EINVAL, "non-finite centroid");
+      double v = com[3 * j + d] + Rc[d];
+      v -= L * std::floor((v + 0.5 * L) / L);
+      if (v >= 0.5 * L) v -= L;
+      X[3 * j + d] = v;
+    }
+  }
+  return guarded(s, [&]() -> fsd_status {
+    s->nb = nb;
+    s->na = n_agg;
+    s->n = 6 * size_t(nb + n_agg);
+    choose_parameters(s);
+    std::vector<int> body(nb);
+    for (int j = 0; j < n_agg; ++j)
+      for (int i = off[j]; i < off[j + 1]; ++i) body[i] = j;
+    s->h_offsets.assign(off, off + n_agg + 1);
+    auto& o = s->owned;
+    s->d_offsets = dalloc<int>(o, n_agg + 1);
+    s->d_body = dalloc<int>(o, nb);
+    s->d_xbody = dalloc<double>(o, 3 * size_t(nb));
+    s->d_com = dalloc<double>(o, 3 * size_t(n_agg));
+    s->d_quat = dalloc<double>(o, 4 * size_t(n_agg));
+    s->d_r4 = dalloc<double>(o, 4 * size_t(nb));
+    s->d_pos4 = dalloc<double>(o, 4 * size_t(nb));
+    s->d_force = dalloc<double>(o, 6 * size_t(n_agg));
+    s->d_G = dalloc<double>(o, 9);
+    s->d_E = dalloc<double>(o, 9);
+    s->d_W = dalloc<double>(o, 3);
+    s->d_nrow = dalloc<int>(o, nb + 1);
+    s->d_lrow = dalloc<int>(o, nb + 1);
+    s->d_rdiag = dalloc<double>(o, 6 * size_t(nb));
+    s->d_lu = dalloc<double>(o, 36 * size_t(n_agg));
+    s->d_piv = dalloc<int>(o, 6 * size_t(n_agg));
+    s->d_flags = dalloc<int>(o, 2);
+    const size_t N = s->wp.n;
+    s->d_grid = dalloc<double>(o, 3 * 2 * N * N * N);
+    const size_t n = s->n;
+    s->d_b = dalloc<double>(o, n);
+    s->d_x = dalloc<double>(o, n);
+    s->d_basis = dalloc<double>(o, size_t(s->m + 3) * n);
+    s->d_z = dalloc<double>(o, n);
+    s->d_w = dalloc<double>(o, n);
+    s->d_t = dalloc<double>(o, n);
+    s->d_r = dalloc<double>(o, n);
+    s->d_wt = dalloc<double>(o, 3 * size_t(nb));
+    s->d_fl = dalloc<double>(o, 3 * size_t(nb));
+    s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 8);
+    s->d_part = dalloc<double>(o, size_t(s->m + 2) * 1024);
+    s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
+    HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
+    s->nw = neighbor_work_create(nb);
+    if (!s->nw) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
+    upload_tables(s);
+    HIPCHK(hipMemcpy(s->d_offsets, off, sizeof(int) * (n_agg + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_body, body.data(), sizeof(int) * nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_xbody, xb.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_com, X.data(), sizeof(double) * 3 * n_agg, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_quat, q.data(), sizeof(double) * 4 * n_agg, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(s->d_force, 0, sizeof(double) * 6 * n_agg));
+    HIPCHK(hipMemcpy(s->d_G, s->G, sizeof(double) * 9, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_E, s->E, sizeof(double) * 9, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->d_W, s->W, sizeof(double) * 3, hipMemcpyHostToDevice));
+    // initial neighbour capacity from the expected pair count
+    const double dens = nb / (L * L * L);
+    const double rc = s->rp.r_cut;
+    s->ncap = (long long)(nb * (4.19 * rc * rc * rc * dens * 1.3 + 64));
+    s->d_ncol = dalloc<uint32_t>(o, size_t(s->ncap));
+    if (s->p.r_lub > 0) {
+      const double rl = s->p.r_lub;
+      s->lcap = (long long)(nb * (4.19 * rl * rl * rl * dens * 2.0 + 16));
+      s->d_lcol = dalloc<uint32_t>(o, size_t(s->lcap));
+      s->d_lcoef = dalloc<double>(o, 5 * size_t(s->lcap));
+      s->lcoef_cap = s->lcap;
+    }
+    s->have_agg = true;
+    s->prepared = false;
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_set_forces(fsd_system* s, const double* ft) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!ft) return fail(s, FSD_EINVAL, "null forces");
+  for (int i = 0; i < 6 * s->na; ++i)
+    if (!std::isfinite(ft[i])) return fail(s, FSD_EINVAL, "non-finite force");
+  return guarded(s, [&]() -> fsd_status {
+    HIPCHK(hipMemcpyAsync(s->d_force, ft, sizeof(double) * 6 * s->na, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_set_bead_forces(fsd_system* s, const double* fb) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!fb) return fail(s, FSD_EINVAL, "null forces");
+  for (int i = 0; i < 3 * s->nb; ++i)
+    if (!std::isfinite(fb[i])) return fail(s, FSD_EINVAL, "non-finite force");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    // Sigma F_P: forces summed, torques r x f, with r the current body vectors
+    std::vector<double> r4(4 * size_t(s->nb)), ft(6 * size_t(s->na), 0.0);
+    HIPCHK(hipMemcpyAsync(r4.data(), s->d_r4, sizeof(double) * 4 * s->nb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (int j = 0; j < s->na; ++j)
+      for (int i = s->h_offsets[j]; i < s->h_offsets[j + 1]; ++i) {
+        const double* f = fb + 3 * i;
+        const double* r = &r4[4 * size_t(i)];
+        ft[6 * j] += f[0];
+        ft[6 * j + 1] += f[1];
+        ft[6 * j + 2] += f[2];
+        ft[6 * j + 3] += r[1] * f[2] - r[2] * f[1];
+        ft[6 * j + 4] += r[2] * f[0] - r[0] * f[2];
+        ft[6 * j + 5] += r[0] * f[1] - r[1] * f[0];
+      }
+    HIPCHK(hipMemcpyAsync(s->d_force, ft.data(), sizeof(double) * 6 * s->na, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_set_shear(fsd_system* s, const double g[9]) {
+  if (!s || !g) return FSD_EINVAL;
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(g[i])) return fail(s, FSD_EINVAL, "non-finite velocity gradient");
+  if (std::fabs(g[0] + g[4] + g[8]) > 1e-12 * (1 + std::fabs(g[0]) + std::fabs(g[4]) + std::fabs(g[8])))
+    return fail(s, FSD_EINVAL, "velocity gradient must be traceless");
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      s->G[3 * a + b] = g[3 * a + b];
+      s->E[3 * a + b] = 0.5 * (g[3 * a + b] + g[3 * b + a]);
+    }
+  s->W[0] = 0.5 * (g[7] - g[5]);
+  s->W[1] = 0.5 * (g[2] - g[6]);
+  s->W[2] = 0.5 * (g[3] - g[1]);
+  if (!s->have_agg) return FSD_OK;
+  return guarded(s, [&]() -> fsd_status {
+    HIPCHK(hipMemcpyAsync(s->d_G, s->G, sizeof(double) * 9, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d_E, s->E, sizeof(double) * 9, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->d_W, s->W, sizeof(double) * 3, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_solve_dev(fsd_system* s, double* dU, double* dlam, fsd_solve_info* info) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!dU) return fail(s, FSD_EINVAL, "null output");
+  return guarded(s, [&]() -> fsd_status {
+    fsd_status r = solve_current(s, info);
+    HIPCHK(hipMemcpyAsync(dU, s->d_U, sizeof(double) * 6 * s->na, hipMemcpyDeviceToDevice, s->st));
+    if (dlam) HIPCHK(hipMemcpyAsync(dlam, s->d_x, sizeof(double) * 6 * s->nb, hipMemcpyDeviceToDevice, s->st));
+    return r;
+  });
+}
+
+fsd_status fsd_solve(fsd_system* s, double* U, double* lam, fsd_solve_info* info) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!U) return fail(s, FSD_EINVAL, "null output");
+  return guarded(s, [&]() -> fsd_status {
+    fsd_status r = solve_current(s, info);
+    HIPCHK(hipMemcpyAsync(U, s->d_U, sizeof(double) * 6 * s->na, hipMemcpyDeviceToHost, s->st));
+    if (lam) HIPCHK(hipMemcpyAsync(lam, s->d_x, sizeof(double) * 6 * s->nb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return r;
+  });
+}
+
+fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!(dt > 0) || n_steps < 0) return fail(s, FSD_EINVAL, "dt must be positive and n_steps >= 0");
+  return guarded(s, [&]() -> fsd_status {
+    fsd_status r = FSD_OK;
+    for (int k = 0; k < n_steps; ++k) {
+      r = solve_current(s, last);
+      if (r != FSD_OK) return r;
+      launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+      s->prepared = false;
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    return r;
+  });
+}
+
+fsd_status fsd_get_state(const fsd_system* cs, double* com, double* quat, double* x_bead) {
+  fsd_system* s = const_cast<fsd_system*>(cs);
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  return guarded(s, [&]() -> fsd_status {
+    if (com) HIPCHK(hipMemcpyAsync(com, s->d_com, sizeof(double) * 3 * s->na, hipMemcpyDeviceToHost, s->st));
+    if (quat) HIPCHK(hipMemcpyAsync(quat, s->d_quat, sizeof(double) * 4 * s->na, hipMemcpyDeviceToHost, s->st));
+    if (x_bead) {
+      launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->d_r4, s->d_pos4,
+                            s->st);
+      std::vector<double> r4(4 * size_t(s->nb)), X(3 * size_t(s->na));
+      HIPCHK(hipMemcpyAsync(r4.data(), s->d_r4, sizeof(double) * 4 * s->nb, hipMemcpyDeviceToHost, s->st));
+      HIPCHK(hipMemcpyAsync(X.data(), s->d_com, sizeof(double) * 3 * s->na, hipMemcpyDeviceToHost, s->st));
+      HIPCHK(hipStreamSynchronize(s->st));
+      for (int j = 0; j < s->na; ++j)
+        for (int i = s->h_offsets[j]; i < s->h_offsets[j + 1]; ++i)
+          for (int d = 0; d < 3; ++d) x_bead[3 * i + d] = X[3 * j + d] + r4[4 * size_t(i) + d];
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_get_info(const fsd_system* cs, fsd_info* info) {
+  fsd_system* s = const_cast<fsd_system*>(cs);
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!info) return FSD_EINVAL;
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    info->L = s->L;
+    info->xi = s->wp.xi;
+    info->r_cut = s->rp.r_cut;
+    info->h = s->wp.h;
+    info->eta_tilde = s->wp.eta_t;
+    info->self_t = s->rp.self_t;
+    info->self_r = s->rp.self_r;
+    info->grid = s->wp.n;
+    info->support = s->wp.support;
+    info->n_bead = s->nb;
+    info->n_agg = s->na;
+    info->nnz_real = s->nnz;
+    info->n_lub_pairs = s->nlub;
+    return FSD_OK;
+  });
+}
+
+size_t fsd_estimate_bytes(const fsd_params* p, int32_t nb, int32_t na, double L) {
+  if (!p || nb <= 0 || na <= 0 || !(L > 0)) return 0;
+  const double a = p->radius;
+  const double xi = p->xi > 0 ? p->xi : 0.5 / a;
+  const double lnt = std::sqrt(-std::log(p->ewald_tol));
+  const double rc = lnt / xi;
+  int N = p->grid > 0 ? p->grid : next_smooth(int(std::ceil((2.0 * lnt * xi + 1.0 / a) * L / M_PI)));
+  const double dens = nb / (L * L * L);
+  const double nnz = nb * (4.19 * rc * rc * rc * dens * 1.3 + 64);
+  const double rl = p->r_lub;
+  const double nl = rl > 0 ? nb * (4.19 * rl * rl * rl * dens * 2.0 + 16) : 0;
+  const double n = 6.0 * (nb + na);
+  const int m = p->gmres_restart;
+  double bytes = 48.0 * double(N) * N * N + 4.0 * nnz + 44.0 * nl + 8.0 * n * (m + 9) + 200.0 * nb + 400.0 * na +
+                 8.0 * (m + 2) * 1024 + 8.0 * 8 * 4100 + (1 << 20);
+  return size_t(bytes);
+}
+
+const char* fsd_last_error(const fsd_system* s) { return s ? s->err.c_str() : "null system"; }
+
+void fsd_destroy(fsd_system* s) {
+  if (!s) return;
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
+  delete s;
+}
+
+fsd_status fsd_apply_mobility(fsd_system* s, const double* lam, double* u, int parts, int precision) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!lam || !u || parts < 1 || parts > 3) return fail(s, FSD_EINVAL, "bad arguments");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    const size_t nb6 = 6 * size_t(s->nb);
+    HIPCHK(hipMemcpyAsync(s->d_z, lam, sizeof(double) * nb6, hipMemcpyHostToDevice, s->st));
+    if (precision == FSD_MIXED)
+      apply_mobility<float>(s, s->d_z, s->d_w, parts);
+    else
+      apply_mobility<double>(s, s->d_z, s->d_w, parts);
+    HIPCHK(hipMemcpyAsync(u, s->d_w, sizeof(double) * nb6, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_apply_saddle(fsd_system* s, const double* x, double* y, int precision) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!x || !y) return fail(s, FSD_EINVAL, "bad arguments");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    HIPCHK(hipMemcpyAsync(s->d_z, x, sizeof(double) * s->n, hipMemcpyHostToDevice, s->st));
+    apply_saddle_p(s, s->d_z, s->d_w, precision == FSD_MIXED);
+    HIPCHK(hipMemcpyAsync(y, s->d_w, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_apply_precond(fsd_system* s, const double* r, double* z) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!r || !z) return fail(s, FSD_EINVAL, "bad arguments");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    HIPCHK(hipMemcpyAsync(s->d_r, r, sizeof(double) * s->n, hipMemcpyHostToDevice, s->st));
+    apply_precond(s, s->d_r, s->d_z);
+    HIPCHK(hipMemcpyAsync(z, s->d_z, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_get_rhs(fsd_system* s, double* b) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!b) return fail(s, FSD_EINVAL, "bad arguments");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    assemble_rhs(s);
+    HIPCHK(hipMemcpyAsync(b, s->d_b, sizeof(double) * s->n, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (n < 0 || (n > 0 && (!r || !out))) return fail(s, FSD_EINVAL, "bad arguments");
+  // the same interpolation as the real-space kernel, evaluated on the host table
+  for (int q = 0; q < n; ++q) {
+    if (!(r[q] > 0) || r[q] >= s->rp.r_cut) return fail(s, FSD_EINVAL, "r outside (0, r_cut)");
+    double o[5];
+    rpy_free(r[q], s->p.radius, s->p.eta, o);
+    const double t = r[q] * s->rp.inv_ht;
+    const int it = int(t);
+    const double f = t - it;
+    const double w[4] = {-f * (f - 1) * (f - 2) / 6.0, (f + 1) * (f - 1) * (f - 2) / 2.0,
+                         -(f + 1) * f * (f - 2) / 2.0, (f + 1) * f * (f - 1) / 6.0};
+    for (int k = 0; k < 5; ++k) {
+      double sv = 0;
+      for (int m = 0; m < 4; ++m) sv += w[m] * s->h_tab[8 * size_t(it + m) + k];
+      out[5 * q + k] = o[k] - sv;
+    }
+  }
+  return FSD_OK;
+}
+
+fsd_status fsd_set_timing(fsd_system* s, int enable) {
+  if (!s) return FSD_EINVAL;
+  return guarded(s, [&]() -> fsd_status {
+    harvest_timers(s);
+    for (int k = 0; k < FSD_TIMER_COUNT; ++k) {
+      s->t_ms[k] = 0;
+      s->t_n[k] = 0;
+    }
+    s->timing = enable != 0;
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches) {
+  if (!s || !total_ms || !launches) return FSD_EINVAL;
+  return guarded(s, [&]() -> fsd_status {
+    harvest_timers(s);
+    for (int k = 0; k < FSD_TIMER_COUNT; ++k) {
+      total_ms[k] = s->t_ms[k];
+      launches[k] = s->t_n[k];
+    }
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_fft3d(int n, int sign, double* data) {
+  if (!data || (sign != 1 && sign != -1)) return FSD_EINVAL;
+  FftPlan plan;
+  if (!make_plan(n, plan) || n > 512) return FSD_EINVAL;
+  std::vector<void*> owned;
+  fsd_status rc = FSD_OK;
+  try {
+    const size_t count = 2 * size_t(n) * n * n;
+    double* d = dalloc<double>(owned, count);
+    double* tw = dalloc<double>(owned, 2 * size_t(n));
+    std::vector<double> h(2 * n);
+    for (int t = 0; t < n; ++t) {
+      h[2 * t] = std::cos(2.0 * M_PI * t / n);
+      h[2 * t + 1] = -std::sin(2.0 * M_PI * t / n);
+    }
+    HIPCHK(hipMemcpy(tw, h.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d, data, sizeof(double) * count, hipMemcpyHostToDevice));
+    launch_fft3d<double>(d, 1, count, plan, tw, sign, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(data, d, sizeof(double) * count, hipMemcpyDeviceToHost));
+  } catch (const ApiError& e) {
+    rc = e.code;
+  } catch (const std::exception&) {
+    rc = FSD_EDEVICE;
+  }
+  for (void* q : owned) (void)hipFree(q);
+  return rc;
+}
+
+}  // extern "C"

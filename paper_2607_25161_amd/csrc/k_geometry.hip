@@ -1,0 +1,401 @@
+// Geometry kernels: rigid-body kinematics, neighbour lists, lubrication pair
+// coefficients and the per-aggregate factorisation of the preconditioner.
+#include <hipcub/hipcub.hpp>
+
+#include "fsd_impl.hpp"
+
+namespace fsd {
+
+namespace {
+constexpr int kThreads = 256;
+inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t); }
+
+__device__ inline void quat_rotate(const double* q, const double* v, double* out) {
+  // rotation matrix of the unit quaternion (w, x, y, z) applied to v
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  out[0] = (1 - 2 * (y * y + z * z)) * v[0] + 2 * (x * y - w * z) * v[1] + 2 * (x * z + w * y) * v[2];
+  out[1] = 2 * (x * y + w * z) * v[0] + (1 - 2 * (x * x + z * z)) * v[1] + 2 * (y * z - w * x) * v[2];
+  out[2] = 2 * (x * z - w * y) * v[0] + 2 * (y * z + w * x) * v[1] + (1 - 2 * (x * x + y * y)) * v[2];
+}
+
+__device__ inline double wrap01(double p, double L) {
+  double q = p - L * floor(p / L);
+  return (q >= L) ? q - L : q;
+}
+}  // namespace
+
+// Eq. `EM3`: x_i = X_j + R(q_j) x_body,i.  r4 holds the body vector R x_body,
+// pos4 the bead centre wrapped into [0, L)^3.
+__global__ void k_bead_positions(int nb, const int* __restrict__ body, const double* __restrict__ xbody,
+                                 const double* __restrict__ com, const double* __restrict__ quat, double L,
+                                 double4* __restrict__ r4, double4* __restrict__ pos4) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int j = body[i];
+  double r[3];
+  quat_rotate(quat + 4 * j, xbody + 3 * i, r);
+  r4[i] = make_double4(r[0], r[1], r[2], 0.0);
+  pos4[i] = make_double4(wrap01(com[3 * j] + r[0], L), wrap01(com[3 * j + 1] + r[1], L),
+                         wrap01(com[3 * j + 2] + r[2], L), 0.0);
+}
+
+void launch_bead_positions(int nb, int na, const int* body, const double* xbody, const double* com,
+                           const double* quat, double L, double* r4, double* pos4, hipStream_t st) {
+  (void)na;
+  k_bead_positions<<<nblocks(nb), kThreads, 0, st>>>(nb, body, xbody, com, quat, L, (double4*)r4,
+                                                     (double4*)pos4);
+}
+
+// Eqs. `EM1` and `EM2`: X += U dt; q += (dt/2) (0, W) (x) q, normalised; X wrapped
+// into [-L/2, L/2)^3.
+__global__ void k_integrate(int na, const double* __restrict__ U, double dt, double L, double* __restrict__ com,
+                            double* __restrict__ quat) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  for (int c = 0; c < 3; ++c) {
+    double x = com[3 * j + c] + U[6 * j + c] * dt;
+    x -= L * floor((x + 0.5 * L) / L);
+    if (x >= 0.5 * L) x -= L;
+    com[3 * j + c] = x;
+  }
+  const double ox = U[6 * j + 3], oy = U[6 * j + 4], oz = U[6 * j + 5];
+  double w = quat[4 * j], x = quat[4 * j + 1], y = quat[4 * j + 2], z = quat[4 * j + 3];
+  // (0, o) (x) (w, v) = (-o.v, w o + o x v)
+  const double h = 0.5 * dt;
+  const double dw = -(ox * x + oy * y + oz * z);
+  const double dx = w * ox + (oy * z - oz * y);
+  const double dy = w * oy + (oz * x - ox * z);
+  const double dz = w * oz + (ox * y - oy * x);
+  w += h * dw;
+  x += h * dx;
+  y += h * dy;
+  z += h * dz;
+  const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  quat[4 * j] = w * inv;
+  quat[4 * j + 1] = x * inv;
+  quat[4 * j + 2] = y * inv;
+  quat[4 * j + 3] = z * inv;
+}
+
+void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat, hipStream_t st) {
+  k_integrate<<<nblocks(na), kThreads, 0, st>>>(na, U, dt, L, com, quat);
+}
+
+// ------------------------------------------------------------------------------------------
+// neighbour lists
+// ------------------------------------------------------------------------------------------
+
+__device__ inline uint32_t pack_entry(int j, int sx, int sy, int sz) {
+  return uint32_t(j) | (uint32_t(sx + 3) << 22) | (uint32_t(sy + 3) << 25) | (uint32_t(sz + 3) << 28);
+}
+
+struct NeighborWork {
+  int nb = 0;
+  int ncell_cap = 0;
+  int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *vals_out = nullptr;
+  int *cell_start = nullptr, *cell_end = nullptr, *counts = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  int* total = nullptr;  // pinned host, row count of the last build
+};
+
+NeighborWork* neighbor_work_create(int nb) {
+  auto* w = new NeighborWork;
+  w->nb = nb;
+  bool ok = hipMalloc(&w->keys_in, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&w->keys_out, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&w->vals_in, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&w->vals_out, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&w->counts, sizeof(int) * (nb + 1)) == hipSuccess &&
+            hipHostMalloc(&w->total, sizeof(int)) == hipSuccess;
+  size_t b1 = 0, b2 = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, b1, w->keys_in, w->keys_out, w->vals_in, w->vals_out, nb);
+  hipcub::DeviceScan::ExclusiveSum(nullptr, b2, w->counts, w->counts, nb + 1);
+  w->temp_bytes = b1 > b2 ? b1 : b2;
+  ok = ok && hipMalloc(&w->temp, w->temp_bytes) == hipSuccess;
+  if (!ok) {
+    neighbor_work_destroy(w);
+    return nullptr;
+  }
+  return w;
+}
+
+void neighbor_work_destroy(NeighborWork* w) {
+  if (!w) return;
+  (void)hipFree(w->keys_in);
+  (void)hipFree(w->keys_out);
+  (void)hipFree(w->vals_in);
+  (void)hipFree(w->vals_out);
+  (void)hipFree(w->counts);
+  (void)hipFree(w->cell_start);
+  (void)hipFree(w->cell_end);
+  (void)hipFree(w->temp);
+  if (w->total) (void)hipHostFree(w->total);
+  delete w;
+}
+
+__global__ void k_cell_keys(int nb, const double4* __restrict__ pos, double cs, int nc, int* keys, int* vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 p = pos[i];
+  int cx = min(nc - 1, int(p.x / cs)), cy = min(nc - 1, int(p.y / cs)), cz = min(nc - 1, int(p.z / cs));
+  keys[i] = (cz * nc + cy) * nc + cx;
+  vals[i] = i;
+}
+
+__global__ void k_cell_bounds(int nb, const int* __restrict__ keys, int* start, int* end) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  const int c = keys[k];
+  if (k == 0 || keys[k - 1] != c) start[c] = k;
+  if (k == nb - 1 || keys[k + 1] != c) end[c] = k + 1;
+}
+
+// One thread per bead scans the 27 surrounding cells (nc >= 3, so each cell is
+// visited once and the minimum image is unique).
+template <bool FILL>
+__global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int* __restrict__ body, double L,
+                             double cs, int nc, double rc2, int exclude_same_body, const int* __restrict__ start,
+                             const int* __restrict__ end, const int* __restrict__ sorted, int* counts,
+                             const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 p = pos[i];
+  const int bi = body[i];
+  const int cx = min(nc - 1, int(p.x / cs)), cy = min(nc - 1, int(p.y / cs)), cz = min(nc - 1, int(p.z / cs));
+  int cnt = 0;
+  const int base = FILL ? rowptr[i] : 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int z = (cz + dz + nc) % nc;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = (cy + dy + nc) % nc;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = (cx + dx + nc) % nc;
+        const int c = (z * nc + y) * nc + x;
+        for (int k = start[c]; k < end[c]; ++k) {
+          const int j = sorted[k];
+          if (j == i || (exclude_same_body && body[j] == bi)) continue;
+          const double4 q = pos[j];
+          double ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
+          const double sx = -rint(ddx / L), sy = -rint(ddy / L), sz = -rint(ddz / L);
+          ddx += sx * L;
+          ddy += sy * L;
+          ddz += sz * L;
+          if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
+            if (FILL) col[base + cnt] = pack_entry(j, int(sx), int(sy), int(sz));
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (!FILL) counts[i] = cnt;
+}
+
+// Small boxes (fewer than 3 cells per side): all pairs and all images within
+// the cutoff, including images of a bead itself.
+template <bool FILL>
+__global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int* __restrict__ body, double L,
+                              double rc2, int nmax, int exclude_same_body, int* counts,
+                              const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 p = pos[i];
+  const int bi = body[i];
+  int cnt = 0;
+  const int base = FILL ? rowptr[i] : 0;
+  for (int j = 0; j < nb; ++j) {
+    if (exclude_same_body && body[j] == bi) continue;
+    const double4 q = pos[j];
+    for (int sz = -nmax; sz <= nmax; ++sz)
+      for (int sy = -nmax; sy <= nmax; ++sy)
+        for (int sx = -nmax; sx <= nmax; ++sx) {
+          if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
+          const double ddx = p.x - q.x + sx * L, ddy = p.y - q.y + sy * L, ddz = p.z - q.z + sz * L;
+          if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
+            if (FILL) col[base + cnt] = pack_entry(j, sx, sy, sz);
+            ++cnt;
+          }
+        }
+  }
+  if (!FILL) counts[i] = cnt;
+}
+
+hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
+                           bool exclude_same_body, int* rowptr, uint32_t* col, long long cap, long long* needed,
+                           hipStream_t st) {
+  const double4* pos = (const double4*)pos4v;
+  const double rc2 = cutoff * cutoff;
+  int nc = int(L / cutoff);
+  if (nc > 1024) nc = 1024;
+  hipError_t e;
+  if (nc >= 3) {
+    const double cs = L / nc;
+    const int ncell = nc * nc * nc;
+    if (ncell > w->ncell_cap) {
+      (void)hipFree(w->cell_start);
+      (void)hipFree(w->cell_end);
+      if ((e = hipMalloc(&w->cell_start, sizeof(int) * ncell)) != hipSuccess) return e;
+      if ((e = hipMalloc(&w->cell_end, sizeof(int) * ncell)) != hipSuccess) return e;
+      w->ncell_cap = ncell;
+    }
+    k_cell_keys<<<nblocks(nb), kThreads, 0, st>>>(nb, pos, cs, nc, w->keys_in, w->vals_in);
+    int bits = 1;
+    while ((1 << bits) < ncell) ++bits;
+    size_t tb = w->temp_bytes;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(w->temp, tb, w->keys_in, w->keys_out, w->vals_in, w->vals_out, nb, 0,
+                                                 bits, st)) != hipSuccess)
+      return e;
+    if ((e = hipMemsetAsync(w->cell_start, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(w->cell_end, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
+    k_cell_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, w->keys_out, w->cell_start, w->cell_end);
+    k_cell_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, cs, nc, rc2, exclude_same_body,
+                                                           w->cell_start, w->cell_end, w->vals_out, w->counts,
+                                                           nullptr, nullptr);
+  } else {
+    const int nmax = int(cutoff / L) + 1;
+    k_brute_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, rc2, nmax, exclude_same_body,
+                                                            w->counts, nullptr, nullptr);
+  }
+  if ((e = hipMemsetAsync(w->counts + nb, 0, sizeof(int), st)) != hipSuccess) return e;
+  size_t tb = w->temp_bytes;
+  if ((e = hipcub::DeviceScan::ExclusiveSum(w->temp, tb, w->counts, rowptr, nb + 1, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(w->total, rowptr + nb, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  const long long total = *w->total;
+  *needed = total;
+  if (total > cap) return hipSuccess;
+  if (nc >= 3) {
+    const double cs = L / nc;
+    k_cell_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, cs, nc, rc2, exclude_same_body,
+                                                          w->cell_start, w->cell_end, w->vals_out, nullptr, rowptr,
+                                                          col);
+  } else {
+    const int nmax = int(cutoff / L) + 1;
+    k_brute_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, rc2, nmax, exclude_same_body, nullptr,
+                                                           rowptr, col);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// lubrication pairs: the stated model (squeeze X and shear Y of two equal spheres,
+// shifted to vanish at r = 3a) acting on translational disturbance velocities
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, const int* __restrict__ rowptr,
+                            const uint32_t* __restrict__ col, double a, double eta, double eps_min, double r_pre,
+                            double* __restrict__ coef, double* __restrict__ rdiag, int* overlap_flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 p = pos[i];
+  const double z = 6.0 * M_PI * eta * a;
+  double d6[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const uint32_t c = col[e];
+    const int j = int(c & 0x3FFFFFu);
+    const double4 q = pos[j];
+    const double dx = p.x - q.x + (int((c >> 22) & 7u) - 3) * L;
+    const double dy = p.y - q.y + (int((c >> 25) & 7u) - 3) * L;
+    const double dz = p.z - q.z + (int((c >> 28) & 7u) - 3) * L;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r < 1.5 * a) atomicOr(overlap_flag, 1);
+    const double nx = dx / r, ny = dy / r, nz = dz / r;
+    const double eps = fmax(r / a - 2.0, eps_min);
+    const double lg = log(1.0 / eps);
+    const double X = z * (0.25 / eps + 0.225 * lg + (3.0 / 112.0) * eps * lg - 0.25);
+    const double Y = z * (lg / 6.0);
+    coef[5 * e] = X;
+    coef[5 * e + 1] = Y;
+    coef[5 * e + 2] = nx;
+    coef[5 * e + 3] = ny;
+    coef[5 * e + 4] = nz;
+    if (r < r_pre) {
+      const double dXY = X - Y;
+      d6[0] += Y + dXY * nx * nx;
+      d6[1] += Y + dXY * ny * ny;
+      d6[2] += Y + dXY * nz * nz;
+      d6[3] += dXY * nx * ny;
+      d6[4] += dXY * nx * nz;
+      d6[5] += dXY * ny * nz;
+    }
+  }
+  for (int k = 0; k < 6; ++k) rdiag[6 * i + k] = d6[k];
+}
+
+void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col, double a,
+                      double eta, double eps_min, double r_pre, double* coef, double* rdiag, int* overlap_flag,
+                      hipStream_t st) {
+  k_lub_setup<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, L, rowptr, col, a, eta, eps_min, r_pre,
+                                                 coef, rdiag, overlap_flag);
+}
+
+// ------------------------------------------------------------------------------------------
+// preconditioner factor (Algorithm 1, step 1): A_j = sum_i Sigma_ji (M~^-1 + R~_ii) Sigma_ji^T,
+// LU with partial pivoting in FP64, one thread per aggregate
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_precond_factor(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
+                                 const double* __restrict__ rdiag, double drag_t, double drag_r, double* __restrict__ lu,
+                                 int* __restrict__ piv, int* singular) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  double A[6][6];
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) A[a][b] = 0.0;
+  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
+    const double4 rv = r4[i];
+    const double* d = rdiag + 6 * i;
+    double D[3][3] = {{drag_t + d[0], d[3], d[4]}, {d[3], drag_t + d[1], d[5]}, {d[4], d[5], drag_t + d[2]}};
+    const double X[3][3] = {{0, -rv.z, rv.y}, {rv.z, 0, -rv.x}, {-rv.y, rv.x, 0}};
+    double XD[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) XD[a][b] = X[a][0] * D[0][b] + X[a][1] * D[1][b] + X[a][2] * D[2][b];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        A[a][b] += D[a][b];
+        A[3 + a][b] += XD[a][b];
+        A[b][3 + a] += XD[a][b];
+        // X D X^T
+        A[3 + a][3 + b] += XD[a][0] * X[b][0] + XD[a][1] * X[b][1] + XD[a][2] * X[b][2];
+      }
+    for (int a = 0; a < 3; ++a) A[3 + a][3 + a] += drag_r;
+  }
+  int bad = 0;
+  for (int k = 0; k < 6; ++k) {
+    int p = k;
+    double best = fabs(A[k][k]);
+    for (int i = k + 1; i < 6; ++i)
+      if (fabs(A[i][k]) > best) {
+        best = fabs(A[i][k]);
+        p = i;
+      }
+    piv[6 * j + k] = p;
+    if (p != k)
+      for (int c = 0; c < 6; ++c) {
+        const double t = A[k][c];
+        A[k][c] = A[p][c];
+        A[p][c] = t;
+      }
+    if (A[k][k] == 0.0) {
+      bad = 1;
+      continue;
+    }
+    const double inv = 1.0 / A[k][k];
+    for (int i = k + 1; i < 6; ++i) {
+      A[i][k] *= inv;
+      for (int c = k + 1; c < 6; ++c) A[i][c] -= A[i][k] * A[k][c];
+    }
+  }
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) lu[36 * j + 6 * a + b] = A[a][b];
+  if (bad) atomicOr(singular, 1);
+}
+
+void launch_precond_factor(int na, const int* offsets, const double* r4, const double* rdiag, double drag_t,
+                           double drag_r, double* lu, int* piv, int* singular, hipStream_t st) {
+  k_precond_factor<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, rdiag, drag_t, drag_r, lu, piv,
+                                                      singular);
+}
+
+}  // namespace fsd

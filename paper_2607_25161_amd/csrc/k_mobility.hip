@@ -1,0 +1,566 @@
+// Far-field mobility M = M_real + M_wave of the positively split Ewald sum.
+//
+// Wave space (spectral Ewald, Gaussian spreading): bead (force, torque) are
+// spread to three complex grids Z_c = F_c + i T_c (c = x, y, z), transformed,
+// multiplied by the Hasimoto-damped FT-RPY Green's function, transformed back
+// and interpolated to the beads, where the grid holds u_c + i w_c.
+//
+// Real space: per neighbour pair within the cutoff, the free-space RPY block
+// minus the smooth inverse transform of the damped multiplier, read from a
+// table by cubic interpolation.
+#include "fsd_impl.hpp"
+
+namespace fsd {
+
+namespace {
+constexpr int kThreads = 256;
+constexpr int kMaxP = 21;  // 3 * P weights computed by one 64-lane wavefront
+inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t); }
+
+template <typename R>
+struct C2;
+template <>
+struct C2<double> {
+  using T = double2;
+};
+template <>
+struct C2<float> {
+  using T = float2;
+};
+
+template <typename R>
+__device__ inline R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// real-space pair sum: one group of LPR lanes per bead row
+// ------------------------------------------------------------------------------------------
+
+template <typename R, int LPR>
+__global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restrict__ pos,
+                                                  const double* __restrict__ lam, const int* __restrict__ rowptr,
+                                                  const uint32_t* __restrict__ col, const R* __restrict__ tab,
+                                                  RealParams rp, double* __restrict__ out, int accumulate) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gt / LPR;
+  const int lane = gt % LPR;
+  if (row >= nb) return;  // LPR divides the wavefront, so whole groups leave together
+  const double4 pi = pos[row];
+  const R a = R(rp.a);
+  const R c8 = R(1.0 / (8.0 * M_PI * rp.eta));
+  const R mt = R(1.0 / (6.0 * M_PI * rp.eta * rp.a));
+  const R mr = R(1.0 / (8.0 * M_PI * rp.eta * rp.a * rp.a * rp.a));
+  const R inv_ht = R(rp.inv_ht);
+  R u0 = 0, u1 = 0, u2 = 0, w0 = 0, w1 = 0, w2 = 0;
+  const int e1 = rowptr[row + 1];
+  for (int e = rowptr[row] + lane; e < e1; e += LPR) {
+    const uint32_t c = col[e];
+    const int j = int(c & 0x3FFFFFu);
+    const double4 pj = pos[j];
+    const R dx = R(pi.x - pj.x + (int((c >> 22) & 7u) - 3) * rp.L);
+    const R dy = R(pi.y - pj.y + (int((c >> 25) & 7u) - 3) * rp.L);
+    const R dz = R(pi.z - pj.z + (int((c >> 28) & 7u) - 3) * rp.L);
+    const R r = sqrt(dx * dx + dy * dy + dz * dz);
+    const R ir = R(1) / r;
+    const R ex = dx * ir, ey = dy * ir, ez = dz * ir;
+    // free-space force-torque RPY (non-overlapping and overlapping branches)
+    R tI, tR, rI, rR, cc;
+    if (r >= R(2) * a) {
+      const R ir2 = ir * ir, a2 = a * a;
+      tI = c8 * ir * (R(1) + R(2.0 / 3.0) * a2 * ir2);
+      tR = c8 * ir * (R(1) - R(2) * a2 * ir2);
+      rI = R(-0.5) * c8 * ir * ir2;
+      rR = R(1.5) * c8 * ir * ir2;
+      cc = -c8 * ir2;
+    } else {
+      const R s = r / a;
+      tI = mt * (R(1) - R(9.0 / 32.0) * s);
+      tR = mt * R(3.0 / 32.0) * s;
+      rI = mr * (R(1) - R(27.0 / 32.0) * s + R(5.0 / 64.0) * s * s * s);
+      rR = mr * (R(9.0 / 32.0) * s - R(3.0 / 64.0) * s * s * s);
+      cc = -R(0.5) * c8 / (a * a) * s * (R(1) - R(3.0 / 8.0) * s);
+    }
+    // minus the smooth part (cubic Lagrange on nodes it-1 .. it+2; table row 0 is r = -h)
+    const R t = r * inv_ht;
+    const int it = int(t);
+    const R f = t - R(it);
+    const R wa = -f * (f - 1) * (f - 2) * R(1.0 / 6.0);
+    const R wb = (f + 1) * (f - 1) * (f - 2) * R(0.5);
+    const R wc = -(f + 1) * f * (f - 2) * R(0.5);
+    const R wd = (f + 1) * f * (f - 1) * R(1.0 / 6.0);
+    const R* T0 = tab + 8 * it;
+    tI -= wa * T0[0] + wb * T0[8] + wc * T0[16] + wd * T0[24];
+    tR -= wa * T0[1] + wb * T0[9] + wc * T0[17] + wd * T0[25];
+    rI -= wa * T0[2] + wb * T0[10] + wc * T0[18] + wd * T0[26];
+    rR -= wa * T0[3] + wb * T0[11] + wc * T0[19] + wd * T0[27];
+    cc -= wa * T0[4] + wb * T0[12] + wc * T0[20] + wd * T0[28];
+    const double* lj = lam + 6 * j;
+    const R fx = R(lj[0]), fy = R(lj[1]), fz = R(lj[2]);
+    const R tx = R(lj[3]), ty = R(lj[4]), tz = R(lj[5]);
+    const R fd = ex * fx + ey * fy + ez * fz;
+    const R td = ex * tx + ey * ty + ez * tz;
+    u0 += tI * fx + tR * fd * ex + cc * (ey * tz - ez * ty);
+    u1 += tI * fy + tR * fd * ey + cc * (ez * tx - ex * tz);
+    u2 += tI * fz + tR * fd * ez + cc * (ex * ty - ey * tx);
+    w0 += rI * tx + rR * td * ex + cc * (ey * fz - ez * fy);
+    w1 += rI * ty + rR * td * ey + cc * (ez * fx - ex * fz);
+    w2 += rI * tz + rR * td * ez + cc * (ex * fy - ey * fx);
+  }
+#pragma unroll
+  for (int o = LPR / 2; o >= 1; o >>= 1) {
+    u0 += __shfl_xor(u0, o, LPR);
+    u1 += __shfl_xor(u1, o, LPR);
+    u2 += __shfl_xor(u2, o, LPR);
+    w0 += __shfl_xor(w0, o, LPR);
+    w1 += __shfl_xor(w1, o, LPR);
+    w2 += __shfl_xor(w2, o, LPR);
+  }
+  if (lane == 0) {
+    const double* li = lam + 6 * row;
+    double* o = out + 6 * row;
+    const double v[6] = {double(u0) + rp.self_t * li[0], double(u1) + rp.self_t * li[1],
+                         double(u2) + rp.self_t * li[2], double(w0) + rp.self_r * li[3],
+                         double(w1) + rp.self_r * li[4], double(w2) + rp.self_r * li[5]};
+    if (accumulate)
+      for (int k = 0; k < 6; ++k) o[k] += v[k];
+    else
+      for (int k = 0; k < 6; ++k) o[k] = v[k];
+  }
+}
+
+template <typename R>
+void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr, const uint32_t* col,
+                     const R* table, const RealParams& rp, double* out, bool accumulate, int lpr, hipStream_t st) {
+  const long long threads = (long long)nb * lpr;
+  const int acc = accumulate ? 1 : 0;
+  const double4* p = (const double4*)pos4;
+#define FSD_REAL(L_)                                                                                    \
+  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc)
+  switch (lpr) {
+    case 1: FSD_REAL(1); break;
+    case 2: FSD_REAL(2); break;
+    case 4: FSD_REAL(4); break;
+    case 8: FSD_REAL(8); break;
+    case 16: FSD_REAL(16); break;
+    case 32: FSD_REAL(32); break;
+    default: FSD_REAL(64); break;
+  }
+#undef FSD_REAL
+}
+
+// ------------------------------------------------------------------------------------------
+// Gaussian spreading and interpolation: one wavefront per bead
+// ------------------------------------------------------------------------------------------
+
+namespace {
+// 1D weights exp(-alpha (x_m - p)^2) for the P support points of each axis.
+template <typename R>
+__device__ inline void axis_weights(const double4& p, const WaveParams& wp, int lane, R* w, int* st) {
+  const int P = wp.support;
+  if (lane < 3 * P) {
+    const int d = lane / P, k = lane % P;
+    const double pd = d == 0 ? p.x : (d == 1 ? p.y : p.z);
+    const double u = pd / wp.h;
+    const int s = int(ceil(u - 0.5 * P));
+    const double xm = (s + k) * wp.h - pd;
+    w[d * kMaxP + k] = R(exp(-wp.alpha * xm * xm));
+    if (k == 0) st[d] = s;
+  }
+}
+
+__device__ inline int wrapi(int m, int n) {
+  m %= n;
+  return m < 0 ? m + n : m;
+}
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_spread(int nb, const double4* __restrict__ pos,
+                                                const double* __restrict__ lam, WaveParams wp, R* __restrict__ grid,
+                                                size_t cs) {
+  __shared__ R wts[4][3 * kMaxP];
+  __shared__ int sta[4][3];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  const bool live = i < nb;
+  const double4 p = live ? pos[i] : make_double4(0, 0, 0, 0);
+  if (live) axis_weights<R>(p, wp, lane, wts[wv], sta[wv]);
+  __syncthreads();
+  if (!live) return;
+  const int P = wp.support, N = wp.n;
+  const double* li = lam + 6 * i;
+  const R f0 = R(li[0]), f1 = R(li[1]), f2 = R(li[2]);
+  const R t0 = R(li[3]), t1 = R(li[4]), t2 = R(li[5]);
+  const int sx = sta[wv][0], sy = sta[wv][1], sz = sta[wv][2];
+  const R* wx = wts[wv];
+  const R* wy = wts[wv] + kMaxP;
+  const R* wz = wts[wv] + 2 * kMaxP;
+  const int P3 = P * P * P;
+  for (int idx = lane; idx < P3; idx += 64) {
+    const int kx = idx % P, ky = (idx / P) % P, kz = idx / (P * P);
+    const R w = wx[kx] * wy[ky] * wz[kz];
+    const size_t m = (size_t(wrapi(sz + kz, N)) * N + wrapi(sy + ky, N)) * N + wrapi(sx + kx, N);
+    R* g = grid + 2 * m;
+    atomicAdd(g, w * f0);
+    atomicAdd(g + 1, w * t0);
+    atomicAdd(g + cs, w * f1);
+    atomicAdd(g + cs + 1, w * t1);
+    atomicAdd(g + 2 * cs, w * f2);
+    atomicAdd(g + 2 * cs + 1, w * t2);
+  }
+}
+
+template <typename R>
+void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid, hipStream_t st) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  k_spread<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, lam, wp, grid, cs);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restrict__ pos,
+                                                const R* __restrict__ grid, size_t cs, WaveParams wp,
+                                                double* __restrict__ out) {
+  __shared__ R wts[4][3 * kMaxP];
+  __shared__ int sta[4][3];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  const bool live = i < nb;
+  const double4 p = live ? pos[i] : make_double4(0, 0, 0, 0);
+  if (live) axis_weights<R>(p, wp, lane, wts[wv], sta[wv]);
+  __syncthreads();
+  if (!live) return;
+  const int P = wp.support, N = wp.n;
+  const int sx = sta[wv][0], sy = sta[wv][1], sz = sta[wv][2];
+  const R* wx = wts[wv];
+  const R* wy = wts[wv] + kMaxP;
+  const R* wz = wts[wv] + 2 * kMaxP;
+  R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  const int P3 = P * P * P;
+  for (int idx = lane; idx < P3; idx += 64) {
+    const int kx = idx % P, ky = (idx / P) % P, kz = idx / (P * P);
+    const R w = wx[kx] * wy[ky] * wz[kz];
+    const size_t m = (size_t(wrapi(sz + kz, N)) * N + wrapi(sy + ky, N)) * N + wrapi(sx + kx, N);
+    const R* g = grid + 2 * m;
+    a0 += w * g[0];
+    a3 += w * g[1];
+    a1 += w * g[cs];
+    a4 += w * g[cs + 1];
+    a2 += w * g[2 * cs];
+    a5 += w * g[2 * cs + 1];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  a3 = wave_sum(a3);
+  a4 = wave_sum(a4);
+  a5 = wave_sum(a5);
+  if (lane == 0) {
+    double* o = out + 6 * i;
+    o[0] += double(a0);
+    o[1] += double(a1);
+    o[2] += double(a2);
+    o[3] += double(a3);
+    o[4] += double(a4);
+    o[5] += double(a5);
+  }
+}
+
+template <typename R>
+void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// 3D FFT: three passes of batched 1D transforms, each line staged in LDS and
+// transformed by mixed-radix (4, 2, 3) Stockham stages.
+// ------------------------------------------------------------------------------------------
+
+namespace {
+template <typename T>
+__device__ inline T cmul(T a, T b) {
+  T r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename T>
+__device__ inline T cadd(T a, T b) {
+  T r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename T>
+__device__ inline T csub(T a, T b) {
+  T r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+// multiply by -i*sign... rot(v, s) = s * i * v
+template <typename T>
+__device__ inline T rot(T v, int s) {
+  T r;
+  r.x = -s * v.y;
+  r.y = s * v.x;
+  return r;
+}
+}  // namespace
+
+template <typename R, int DIR>
+__global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t cs, FftPlan plan,
+                                                  const R* __restrict__ twiddle, int sign, int B) {
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + B * N;
+  T* tw = buf1 + B * N;
+  T* base = reinterpret_cast<T*>(data + blockIdx.y * cs);
+  const int line0 = blockIdx.x * B;
+  const T* twg = reinterpret_cast<const T*>(twiddle);
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    T w = twg[t];
+    if (sign > 0) w.y = -w.y;
+    tw[t] = w;
+  }
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    int l, e;
+    if (DIR == 0) {
+      l = t / N;
+      e = t % N;
+    } else {
+      l = t % B;
+      e = t / B;
+    }
+    const size_t gl = size_t(line0 + l);
+    size_t off;
+    if (DIR == 0)
+      off = gl * N + e;
+    else if (DIR == 1)
+      off = ((gl / N) * N + e) * N + (gl % N);
+    else
+      off = (size_t(e) * N + (gl / N)) * N + (gl % N);
+    buf0[l * N + e] = base[off];
+  }
+  __syncthreads();
+  T* in = buf0;
+  T* out = buf1;
+  int Ns = 1;
+  const int s = sign > 0 ? 1 : -1;
+  for (int stg = 0; stg < plan.nstage; ++stg) {
+    const int Rd = plan.radix[stg];
+    const int nbf = N / Rd;
+    const int tstride = N / (Ns * Rd);
+    for (int t = threadIdx.x; t < B * nbf; t += blockDim.x) {
+      const int l = t / nbf, b = t % nbf;
+      const T* li = in + l * N;
+      T* lo = out + l * N;
+      const int k = b % Ns;
+      const int od = (b / Ns) * Ns * Rd + k;
+      if (Rd == 4) {
+        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf], v3 = li[b + 3 * nbf];
+        if (Ns > 1) {
+          v1 = cmul(v1, tw[k * tstride]);
+          v2 = cmul(v2, tw[2 * k * tstride]);
+          v3 = cmul(v3, tw[3 * k * tstride]);
+        }
+        const T s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = rot(csub(v1, v3), s);
+        lo[od] = cadd(s02, s13);
+        lo[od + Ns] = cadd(d02, d13);
+        lo[od + 2 * Ns] = csub(s02, s13);
+        lo[od + 3 * Ns] = csub(d02, d13);
+      } else if (Rd == 2) {
+        T v0 = li[b], v1 = li[b + nbf];
+        if (Ns > 1) v1 = cmul(v1, tw[k * tstride]);
+        lo[od] = cadd(v0, v1);
+        lo[od + Ns] = csub(v0, v1);
+      } else {  // radix 3
+        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf];
+        if (Ns > 1) {
+          v1 = cmul(v1, tw[k * tstride]);
+          v2 = cmul(v2, tw[2 * k * tstride]);
+        }
+        const R c3 = R(-0.5), s3 = R(0.86602540378443864676);
+        const T sm = cadd(v1, v2), df = csub(v1, v2);
+        T m1;
+        m1.x = v0.x + c3 * sm.x;
+        m1.y = v0.y + c3 * sm.y;
+        const T jd = rot(df, s);  // s i (v1 - v2)
+        T y1, y2;
+        y1.x = m1.x + s3 * jd.x;
+        y1.y = m1.y + s3 * jd.y;
+        y2.x = m1.x - s3 * jd.x;
+        y2.y = m1.y - s3 * jd.y;
+        lo[od] = cadd(v0, sm);
+        lo[od + Ns] = y1;
+        lo[od + 2 * Ns] = y2;
+      }
+    }
+    __syncthreads();
+    T* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= Rd;
+  }
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    int l, e;
+    if (DIR == 0) {
+      l = t / N;
+      e = t % N;
+    } else {
+      l = t % B;
+      e = t / B;
+    }
+    const size_t gl = size_t(line0 + l);
+    size_t off;
+    if (DIR == 0)
+      off = gl * N + e;
+    else if (DIR == 1)
+      off = ((gl / N) * N + e) * N + (gl % N);
+    else
+      off = (size_t(e) * N + (gl / N)) * N + (gl % N);
+    base[off] = in[l * N + e];
+  }
+}
+
+namespace {
+int lines_per_block(int N) {
+  int B = 1;
+  while (B * 2 * N <= 1024 && (N % (B * 2)) == 0) B *= 2;
+  return B;
+}
+}  // namespace
+
+template <typename R>
+void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle, int sign,
+                  hipStream_t st, int pass) {
+  using T = typename C2<R>::T;
+  const int N = plan.n;
+  const int B = lines_per_block(N);
+  const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
+  dim3 g(N * N / B, ncomp);
+  if (pass < 0 || pass == 0) k_fft_pass<R, 0><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
+  if (pass < 0 || pass == 1) k_fft_pass<R, 1><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
+  if (pass < 0 || pass == 2) k_fft_pass<R, 2><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
+}
+
+// ------------------------------------------------------------------------------------------
+// Green's-function scaling of the packed spectra (one thread per +-k pair)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+__device__ inline void sinc_jv(double x, double& s, double& j) {
+  if (x < 0.5) {
+    const double x2 = x * x;
+    s = 1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0 * (1.0 - x2 / 110.0))));
+    j = 1.0 - x2 / 10.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0 * (1.0 - x2 / 88.0 * (1.0 - x2 / 130.0))));
+  } else {
+    double sn, cn;
+    sincos(x, &sn, &cn);
+    s = sn / x;
+    j = 3.0 * (sn - x * cn) / (x * x * x);
+  }
+}
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_green(R* __restrict__ grid, size_t cs, WaveParams wp) {
+  using T = typename C2<R>::T;
+  const int N = wp.n;
+  const size_t N3 = size_t(N) * N * N;
+  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= N3) return;
+  const int ix = int(idx % N), iy = int((idx / N) % N), iz = int(idx / (size_t(N) * N));
+  const int jx = (N - ix) % N, jy = (N - iy) % N, jz = (N - iz) % N;
+  const size_t midx = (size_t(jz) * N + jy) * N + jx;
+  if (midx < idx) return;  // the partner thread handles this pair
+  T* Z[3] = {reinterpret_cast<T*>(grid), reinterpret_cast<T*>(grid + cs), reinterpret_cast<T*>(grid + 2 * cs)};
+  const bool nyq = (N % 2 == 0) && (ix == N / 2 || iy == N / 2 || iz == N / 2);
+  if (nyq || idx == midx) {
+    T zero;
+    zero.x = 0;
+    zero.y = 0;
+    for (int c = 0; c < 3; ++c) {
+      Z[c][idx] = zero;
+      Z[c][midx] = zero;
+    }
+    return;
+  }
+  const double tp = 2.0 * M_PI / wp.L;
+  const double k[3] = {tp * (ix < N / 2 ? ix : ix - N), tp * (iy < N / 2 ? iy : iy - N),
+                       tp * (iz < N / 2 ? iz : iz - N)};
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  const double kn = sqrt(k2);
+  const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
+  double sk, jk;
+  sinc_jv(kn * wp.a, sk, jk);
+  const double q = k2 / (4.0 * wp.xi * wp.xi);
+  const double Bk = wp.scale * (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / (wp.eta * k2);
+  // unpack F(k), T(k) from Z(k) = F + i T and Z(-k) = conj(F(k)) + i conj(T(k))
+  double Fr[3], Fi[3], Tr[3], Ti[3];
+  for (int c = 0; c < 3; ++c) {
+    const T zk = Z[c][idx], zm = Z[c][midx];
+    const double ar = zk.x, ai = zk.y, br = zm.x, bi = -zm.y;  // b = conj(Z(-k))
+    Fr[c] = 0.5 * (ar + br);
+    Fi[c] = 0.5 * (ai + bi);
+    Tr[c] = 0.5 * (ai - bi);
+    Ti[c] = -0.5 * (ar - br);
+  }
+  // g = sinc F + (i/2) jv (k x T), projected transverse to k
+  double gr[3], gi[3];
+  const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
+  const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
+  for (int c = 0; c < 3; ++c) {
+    gr[c] = sk * Fr[c] - 0.5 * jk * cxi[c];
+    gi[c] = sk * Fi[c] + 0.5 * jk * cxr[c];
+  }
+  const double pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
+  const double pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
+  double ur[3], ui[3];
+  for (int c = 0; c < 3; ++c) {
+    ur[c] = Bk * (gr[c] - pr * kh[c]);
+    ui[c] = Bk * (gi[c] - pim * kh[c]);
+  }
+  // bead velocity U = sinc u, angular velocity W = (i/2) jv (k x u)
+  const double kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
+  const double kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
+  for (int c = 0; c < 3; ++c) {
+    const double Ur = sk * ur[c], Ui = sk * ui[c];
+    const double Wr = -0.5 * jk * kui[c], Wi = 0.5 * jk * kur[c];
+    T yk, ym;
+    yk.x = R(Ur - Wi);
+    yk.y = R(Ui + Wr);
+    ym.x = R(Ur + Wi);
+    ym.y = R(-Ui + Wr);
+    Z[c][idx] = yk;
+    Z[c][midx] = ym;
+  }
+}
+
+template <typename R>
+void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st) {
+  const size_t N3 = size_t(wp.n) * wp.n * wp.n;
+  k_green<R><<<nblocks((long long)N3), kThreads, 0, st>>>(grid, comp_stride, wp);
+}
+
+// explicit instantiations
+template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
+                                      const RealParams&, double*, bool, int, hipStream_t);
+template void launch_real_sum<float>(int, const double*, const double*, const int*, const uint32_t*, const float*,
+                                     const RealParams&, double*, bool, int, hipStream_t);
+template void launch_spread<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t);
+template void launch_spread<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t);
+template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t);
+template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t);
+template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int);
+template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int);
+template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t);
+template void launch_green_scale<float>(float*, size_t, const WaveParams&, hipStream_t);
+
+}  // namespace fsd

@@ -1,0 +1,365 @@
+// Kernels of the saddle operator outside the mobility, the preconditioner and
+// the FP64 Krylov vector operations.
+#include "fsd_impl.hpp"
+
+namespace fsd {
+
+namespace {
+constexpr int kThreads = 256;
+inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t); }
+}  // namespace
+
+// Sigma^T V: rigid velocity of bead i of body j, (U_j + W_j x r_i, W_j), added to
+// y1; its translational part also goes to wt (input of the lubrication product).
+__global__ void k_rigid_velocity(int nb, const int* __restrict__ body, const double4* __restrict__ r4,
+                                 const double* __restrict__ V, double* __restrict__ y1, double* __restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int j = body[i];
+  const double* v = V + 6 * j;
+  const double4 r = r4[i];
+  const double ux = v[0] + (v[4] * r.z - v[5] * r.y);
+  const double uy = v[1] + (v[5] * r.x - v[3] * r.z);
+  const double uz = v[2] + (v[3] * r.y - v[4] * r.x);
+  double* y = y1 + 6 * i;
+  y[0] += ux;
+  y[1] += uy;
+  y[2] += uz;
+  y[3] += v[3];
+  y[4] += v[4];
+  y[5] += v[5];
+  if (wt) {
+    wt[3 * i] = ux;
+    wt[3 * i + 1] = uy;
+    wt[3 * i + 2] = uz;
+  }
+}
+
+void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1, double* wt,
+                           hipStream_t st) {
+  k_rigid_velocity<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, V, y1, wt);
+}
+
+// f_i = -sum_k R_pair,ik (w_i - w_k), R_pair = X nn + Y (I - nn)
+__global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32_t* __restrict__ col,
+                            const double* __restrict__ coef, const double* __restrict__ wt, double* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double wx = wt[3 * i], wy = wt[3 * i + 1], wz = wt[3 * i + 2];
+  double ax = 0, ay = 0, az = 0;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const int k = int(col[e] & 0x3FFFFFu);
+    const double* c = coef + 5 * e;
+    const double dx = wx - wt[3 * k], dy = wy - wt[3 * k + 1], dz = wz - wt[3 * k + 2];
+    const double nd = c[2] * dx + c[3] * dy + c[4] * dz;
+    const double g = (c[0] - c[1]) * nd;
+    ax += c[1] * dx + g * c[2];
+    ay += c[1] * dy + g * c[3];
+    az += c[1] * dz + g * c[4];
+  }
+  f[3 * i] = -ax;
+  f[3 * i + 1] = -ay;
+  f[3 * i + 2] = -az;
+}
+
+void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef, const double* wt, double* f,
+                      hipStream_t st) {
+  k_lub_apply<<<nblocks(nb), kThreads, 0, st>>>(nb, rowptr, col, coef, wt, f);
+}
+
+// Sigma (lambda + (f_lub, 0)): per body (sum f, sum t + r x f)
+__global__ void k_agg_reduce(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
+                             const double* __restrict__ lam, const double* __restrict__ flub, double* __restrict__ y2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
+    const double* l = lam + 6 * i;
+    double fx = l[0], fy = l[1], fz = l[2];
+    if (flub) {
+      fx += flub[3 * i];
+      fy += flub[3 * i + 1];
+      fz += flub[3 * i + 2];
+    }
+    const double4 r = r4[i];
+    F[0] += fx;
+    F[1] += fy;
+    F[2] += fz;
+    T[0] += l[3] + (r.y * fz - r.z * fy);
+    T[1] += l[4] + (r.z * fx - r.x * fz);
+    T[2] += l[5] + (r.x * fy - r.y * fx);
+  }
+  double* y = y2 + 6 * j;
+  y[0] = F[0];
+  y[1] = F[1];
+  y[2] = F[2];
+  y[3] = T[0];
+  y[4] = T[1];
+  y[5] = T[2];
+}
+
+void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam, const double* flub,
+                       double* y2, hipStream_t st) {
+  k_agg_reduce<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, lam, flub, y2);
+}
+
+// ------------------------------------------------------------------------------------------
+// preconditioner apply (Section 2.3.3):
+//   y2 = r2 - Sigma M~^-1 r1,  z2 = -A_j^-1 y2,  z1 = M~^-1 (r1 - Sigma^T z2)
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_precond_agg(int nb, int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
+                              const double* __restrict__ lu, const int* __restrict__ piv, double drag_t, double drag_r,
+                              const double* __restrict__ r, double* __restrict__ z) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  double y[6];
+  const double* r2 = r + 6 * size_t(nb) + 6 * j;
+  for (int c = 0; c < 6; ++c) y[c] = r2[c];
+  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
+    const double* l = r + 6 * size_t(i);
+    const double fx = drag_t * l[0], fy = drag_t * l[1], fz = drag_t * l[2];
+    const double4 rv = r4[i];
+    y[0] -= fx;
+    y[1] -= fy;
+    y[2] -= fz;
+    y[3] -= drag_r * l[3] + (rv.y * fz - rv.z * fy);
+    y[4] -= drag_r * l[4] + (rv.z * fx - rv.x * fz);
+    y[5] -= drag_r * l[5] + (rv.x * fy - rv.y * fx);
+  }
+  // solve A x = y with the stored LU (P A = L U)
+  const double* A = lu + 36 * j;
+  const int* p = piv + 6 * j;
+  for (int k = 0; k < 6; ++k) {
+    const int q = p[k];
+    if (q != k) {
+      const double t = y[k];
+      y[k] = y[q];
+      y[q] = t;
+    }
+  }
+  for (int a = 1; a < 6; ++a)
+    for (int b = 0; b < a; ++b) y[a] -= A[6 * a + b] * y[b];
+  for (int a = 5; a >= 0; --a) {
+    for (int b = a + 1; b < 6; ++b) y[a] -= A[6 * a + b] * y[b];
+    y[a] /= A[6 * a + a];
+  }
+  double* z2 = z + 6 * size_t(nb) + 6 * j;
+  for (int c = 0; c < 6; ++c) z2[c] = -y[c];
+}
+
+__global__ void k_precond_bead(int nb, const int* __restrict__ body, const double4* __restrict__ r4, double drag_t,
+                               double drag_r, const double* __restrict__ r, double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double* v = z + 6 * size_t(nb) + 6 * body[i];
+  const double4 rv = r4[i];
+  const double* l = r + 6 * size_t(i);
+  double* o = z + 6 * size_t(i);
+  o[0] = drag_t * (l[0] - (v[0] + (v[4] * rv.z - v[5] * rv.y)));
+  o[1] = drag_t * (l[1] - (v[1] + (v[5] * rv.x - v[3] * rv.z)));
+  o[2] = drag_t * (l[2] - (v[2] + (v[3] * rv.y - v[4] * rv.x)));
+  o[3] = drag_r * (l[3] - v[3]);
+  o[4] = drag_r * (l[4] - v[4]);
+  o[5] = drag_r * (l[5] - v[5]);
+}
+
+void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4, const double* lu,
+                          const int* piv, double drag_t, double drag_r, const double* r, double* z, double* tmp_agg,
+                          hipStream_t st) {
+  (void)tmp_agg;
+  k_precond_agg<<<nblocks(na, 128), 128, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z);
+  k_precond_bead<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, drag_t, drag_r, r, z);
+}
+
+// ------------------------------------------------------------------------------------------
+// right-hand side of Eq. `spm_agg`
+// ------------------------------------------------------------------------------------------
+
+// b1_i = (E r_i, 0) [+ (u_B, w_B)_i]; e3_i = E r_i (ambient flow relative to the body)
+__global__ void k_rhs_bead(int nb, const double4* __restrict__ r4, const double* __restrict__ E,
+                           const double* __restrict__ ub, double* __restrict__ b1, double* __restrict__ e3) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 r = r4[i];
+  double e[3];
+  for (int a = 0; a < 3; ++a) e[a] = E[3 * a] * r.x + E[3 * a + 1] * r.y + E[3 * a + 2] * r.z;
+  double* b = b1 + 6 * i;
+  for (int a = 0; a < 3; ++a) {
+    b[a] = e[a] + (ub ? ub[6 * i + a] : 0.0);
+    b[3 + a] = ub ? ub[6 * i + 3 + a] : 0.0;
+    e3[3 * i + a] = e[a];
+  }
+}
+
+void launch_rhs(int nb, int na, const int* offsets, const int* body, const double* r4, const double* E,
+                const double* force, const double* fnf, double* b1, double* e3, hipStream_t st) {
+  (void)na;
+  (void)offsets;
+  (void)body;
+  (void)force;
+  k_rhs_bead<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)r4, E, fnf, b1, e3);
+}
+
+// b2_j = -F_j + Sigma (f_e, 0) with f_e = -R_nf e (so Sigma R_nf e = -Sigma f_e)
+__global__ void k_rhs_agg(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
+                          const double* __restrict__ force, const double* __restrict__ fe, double* __restrict__ b2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+  if (fe) {
+    for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
+      const double fx = fe[3 * i], fy = fe[3 * i + 1], fz = fe[3 * i + 2];
+      const double4 r = r4[i];
+      F[0] += fx;
+      F[1] += fy;
+      F[2] += fz;
+      T[0] += r.y * fz - r.z * fy;
+      T[1] += r.z * fx - r.x * fz;
+      T[2] += r.x * fy - r.y * fx;
+    }
+  }
+  double* b = b2 + 6 * j;
+  for (int a = 0; a < 3; ++a) {
+    b[a] = -force[6 * j + a] + F[a];
+    b[3 + a] = -force[6 * j + 3 + a] + T[a];
+  }
+}
+
+void launch_rhs_agg(int na, const int* offsets, const double* r4, const double* force, const double* flub_e,
+                    double* b2, hipStream_t st) {
+  k_rhs_agg<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, force, flub_e, b2);
+}
+
+// U_j = V_j + (G X_j, W_inf)
+__global__ void k_add_ambient(int na, const double* __restrict__ V, const double* __restrict__ com,
+                              const double* __restrict__ G, const double* __restrict__ W, double* __restrict__ U) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  const double* X = com + 3 * j;
+  for (int a = 0; a < 3; ++a) {
+    U[6 * j + a] = V[6 * j + a] + G[3 * a] * X[0] + G[3 * a + 1] * X[1] + G[3 * a + 2] * X[2];
+    U[6 * j + 3 + a] = V[6 * j + 3 + a] + W[a];
+  }
+}
+
+void launch_add_ambient(int na, const double* V, const double* com, const double* G, const double* W, double* U,
+                        hipStream_t st) {
+  k_add_ambient<<<nblocks(na, 128), 128, 0, st>>>(na, V, com, G, W, U);
+}
+
+// ------------------------------------------------------------------------------------------
+// Krylov vectors (FP64)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+constexpr int kDotThreads = 256;
+constexpr int kDotChunk = 8;  // basis vectors reduced per pass
+
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kDotThreads / 64; ++k) s += sh[k];
+  return s;
+}
+}  // namespace
+
+int dot_blocks(size_t n) {
+  long long b = (long long)((n + kDotThreads * 4 - 1) / (kDotThreads * 4));
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+__global__ __launch_bounds__(kDotThreads) void k_multi_dot(size_t n, int q0, int nq, const double* __restrict__ V,
+                                                           size_t ldv, const double* __restrict__ w,
+                                                           double* __restrict__ partial) {
+  __shared__ double sh[kDotThreads / 64];
+  double acc[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) acc[c] = 0;
+  const int cnt = min(kDotChunk, nq - q0);
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (c < cnt) acc[c] += V[size_t(q0 + c) * ldv + i] * wi;
+  }
+  for (int c = 0; c < cnt; ++c) {
+    const double s = block_sum(acc[c], sh);
+    if (threadIdx.x == 0) partial[size_t(q0 + c) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kDotThreads) void k_dot_final(int nblk, const double* __restrict__ partial,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kDotThreads / 64];
+  const int q = blockIdx.x;
+  double v = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[size_t(q) * nblk + b];
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) out[q] = s;
+}
+
+void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
+                      hipStream_t st) {
+  const int nb = dot_blocks(n);
+  for (int q0 = 0; q0 < nq; q0 += kDotChunk)
+    k_multi_dot<<<nb, kDotThreads, 0, st>>>(n, q0, nq, V, ldv, w, partial);
+  k_dot_final<<<nq, kDotThreads, 0, st>>>(nb, partial, out);
+}
+
+// w += sgn * sum_q h[q] V_q
+__global__ void k_multi_axpy(size_t n, int nq, const double* __restrict__ V, size_t ldv, const double* __restrict__ h,
+                             double sgn, double* __restrict__ w) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0;
+  for (int q = 0; q < nq; ++q) s += h[q] * V[size_t(q) * ldv + i];
+  w[i] += sgn * s;
+}
+
+void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h, double sgn, double* w,
+                       hipStream_t st) {
+  k_multi_axpy<<<nblocks((long long)n), kThreads, 0, st>>>(n, nq, V, ldv, h, sgn, w);
+}
+
+// dst = src / s_dev[0]
+__global__ void k_scale_copy(size_t n, const double* __restrict__ src, const double* __restrict__ s,
+                             double* __restrict__ dst) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[i] / s[0];
+}
+
+void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst, hipStream_t st) {
+  k_scale_copy<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, s_dev, dst);
+}
+
+__global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = a * x[i] + b * y[i];
+}
+
+void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+  k_axpby<<<nblocks((long long)n), kThreads, 0, st>>>(n, a, x, b, y);
+}
+
+__global__ void k_sub(size_t n, const double* __restrict__ b, const double* __restrict__ ax, double* __restrict__ r) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  r[i] = b[i] - ax[i];
+}
+
+void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st) {
+  k_sub<<<nblocks((long long)n), kThreads, 0, st>>>(n, b, ax, r);
+}
+
+}  // namespace fsd

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/fsd.h declares, and its pure-host entry points behave."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def F():
+    lib = os.path.join(ROOT, "paper_2607_25161_amd", "libfsd.so")
+    if not os.path.exists(lib):
+        from paper_2607_25161_amd.build import build
+        build(verbose=False)
+    import paper_2607_25161_amd as F
+    return F
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(fsd_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_every_declared_symbol_is_exported(F):
+    names = _declared()
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(F.lib, n), n
+
+
+def test_default_params(F):
+    p = F.default_params()
+    assert p.eta == 1.0 and p.radius == 1.0 and p.r_lub == 3.0 and p.r_precond == 2.1
+    assert p.gmres_restart == 30 and p.precision == F.FSD_FP64 and p.lub_eps_min == 1e-3
+
+
+def test_estimate_bytes_grows_with_size(F):
+    p = F.default_params(ewald_tol=1e-5, xi=0.348, grid=128)
+    small = F.estimate_bytes(p, 2048, 256, 44.1)
+    big = F.estimate_bytes(p, 81920, 4096, 119.7)
+    assert 0 < small < big
+    assert F.estimate_bytes(p, 0, 1, 10.0) == 0
+
+
+def test_binding_structs_match_header_layout(F):
+    import ctypes
+    # fsd_params: 5 doubles, 2 ints, 4 doubles, 3 ints, double, uint64 (C alignment)
+    assert ctypes.sizeof(F.Params) == 5 * 8 + 2 * 4 + 4 * 8 + 3 * 4 + 4 + 8 + 8
+    assert ctypes.sizeof(F.SolveInfo) == 4 * 4 + 8

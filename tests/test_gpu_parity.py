@@ -1,0 +1,312 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: wherever the GPU evaluates the Ewald sum it carries the spectral
+truncation error of its parameters (ewald_tol), so operator checks run at
+ewald_tol = 1e-10 and compare at 1e-8 relative to the largest entry; pieces
+with no truncation (preconditioner, right-hand side, lubrication) compare at
+1e-12.  Full solves compare aggregate velocities to 1e-5 (translational and
+rotational parts separately), the bar of the method's stated accuracy.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import fsdgen
+from oracle import integrate, lub, pse, rigid, rpy, saddle
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def F(gpu):
+    import paper_2607_25161_amd as F
+    return F
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def _vel_errors(U, Uo):
+    return _rel(U[:, :3], Uo[:, :3]), _rel(U[:, 3:], Uo[:, 3:])
+
+
+def _cluster_system(seed=11, sizes=(3, 5, 1, 4, 7, 2, 6), L=14.0, shear=True, lub_on=True):
+    rng = fsdgen.rng_from(seed)
+    shapes = [fsdgen.sticking_cluster(rng, nb) for nb in sizes]
+    com, quat = fsdgen.place_clusters(rng, shapes, L, gap=0.05)
+    offs = np.r_[0, np.cumsum([len(s) for s in shapes])].astype(np.int32)
+    return dict(L=L, a=1.0, eta=1.0, offsets=offs, x_body=np.concatenate(shapes), com=com, quat=quat,
+                force=rng.normal(size=(len(sizes), 6)),
+                grad_u=fsdgen.simple_shear(1.0) if shear else np.zeros((3, 3)),
+                r_lub=3.0 if lub_on else 0.0)
+
+
+def _make(F, kw, **p):
+    par = dict(xi=0.6, ewald_tol=1e-10, r_lub=kw["r_lub"], r_precond=2.1 if kw["r_lub"] else 0.0,
+               gmres_tol=1e-11, gmres_restart=40, gmres_maxit=3000)
+    par.update(p)
+    s = F.System(F.default_params(**par))
+    s.init_box(kw["L"])
+    s.init_aggregates(kw["offsets"], kw["x_body"], kw["com"], kw["quat"])
+    s.set_forces(kw["force"])
+    s.set_shear(kw["grad_u"])
+    return s
+
+
+# ---------------------------------------------------------------------------------------
+# FFT stages
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 12, 24, 32, 48, 64, 72])
+def test_fft3d_matches_numpy(F, n):
+    rng = np.random.default_rng(n)
+    a = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
+    fw = F.fft3d(a, -1)
+    assert np.abs(fw - np.fft.fftn(a)).max() < 1e-12 * np.abs(fw).max()
+    bw = F.fft3d(a, +1)
+    ref = np.fft.ifftn(a) * n ** 3
+    assert np.abs(bw - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------------------
+# mobility halves
+# ---------------------------------------------------------------------------------------
+
+def _single_beads(n, L, seed):
+    rng = np.random.default_rng(seed)
+    x = []
+    while len(x) < n:
+        p = (rng.random(3) - 0.5) * L
+        if all(np.linalg.norm((p - q) - L * np.round((p - q) / L)) > 2.1 for q in x):
+            x.append(p)
+    x = np.array(x)
+    return dict(L=L, a=1.0, eta=1.0, offsets=np.arange(n + 1, dtype=np.int32), x_body=np.zeros((n, 3)), com=x,
+                quat=np.tile([1.0, 0, 0, 0], (n, 1)), force=rng.normal(size=(n, 6)), grad_u=np.zeros((3, 3)),
+                r_lub=0.0)
+
+
+def test_real_functions_match_oracle_quadrature(F):
+    kw = _single_beads(3, 12.0, 1)
+    s = _make(F, kw, xi=0.7)
+    r = np.array([0.4, 1.3, 2.0, 2.05, 3.3, 5.1, 0.98 * s.info().r_cut])
+    g = s.real_functions(r)
+    o = pse.real_functions(r, 1.0, 1.0, 0.7)
+    scale = np.array([rpy.mu_t(1, 1), rpy.mu_t(1, 1), rpy.mu_r(1, 1), rpy.mu_r(1, 1), rpy.mu_t(1, 1)])
+    assert np.abs((g - o) / scale).max() < 1e-10
+    st, sr = pse.self_terms(1.0, 1.0, 0.7)
+    inf = s.info()
+    assert abs(inf.self_t - st) < 1e-12 and abs(inf.self_r - sr) < 1e-12
+
+
+@pytest.mark.parametrize("xi,L,n", [(0.6, 11.0, 9), (0.9, 7.5, 5)])
+def test_mobility_real_and_wave_parts(F, xi, L, n):
+    kw = _single_beads(n, L, 2 + n)
+    s = _make(F, kw, xi=xi)
+    inf = s.info()
+    lam = np.random.default_rng(3).normal(size=6 * n)
+    x = kw["com"]
+    Mr = pse.real_mobility(x, L, 1.0, 1.0, xi, inf.r_cut)
+    Mw = pse.wave_mobility(x, L, 1.0, 1.0, xi)
+    ur = s.apply_mobility(lam, parts=1)
+    uw = s.apply_mobility(lam, parts=2)
+    ut = s.apply_mobility(lam, parts=3)
+    ref_r, ref_w = Mr @ lam, Mw @ lam
+    sc = np.abs(ref_r + ref_w).max()
+    # the real part is truncated at r_cut, where it is ~ ewald_tol of its scale
+    assert np.abs(ur - ref_r).max() < 1e-8 * sc
+    assert np.abs(uw - ref_w).max() < 1e-8 * sc
+    Mb = rpy.periodic_mobility(x, L, 1.0, 1.0)
+    assert np.abs(ut - Mb @ lam).max() < 1e-8 * sc
+
+
+def test_mobility_fp32_within_single_precision(F):
+    kw = _single_beads(12, 13.0, 5)
+    s = _make(F, kw, xi=0.6, ewald_tol=1e-6)
+    lam = np.random.default_rng(4).normal(size=72)
+    u64 = s.apply_mobility(lam, precision=F.FSD_FP64)
+    u32 = s.apply_mobility(lam, precision=F.FSD_MIXED)
+    assert _rel(u32, u64) < 2e-6
+
+
+def test_mobility_many_tiles_ragged(F):
+    # 101 beads: several spreading blocks with a ragged last block, odd grid multiple of 3
+    kw = _single_beads(101, 26.0, 6)
+    s = _make(F, kw, xi=0.5, ewald_tol=1e-8, grid=48)
+    lam = np.random.default_rng(5).normal(size=6 * 101)
+    M = rpy.periodic_mobility(kw["com"], 26.0, 1.0, 1.0)
+    u = s.apply_mobility(lam)
+    assert _rel(u, M @ lam) < 1e-7
+
+
+# ---------------------------------------------------------------------------------------
+# saddle operator, preconditioner, right-hand side
+# ---------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cluster_case(F):
+    kw = _cluster_system()
+    s = _make(F, kw)
+    A = saddle.assemble(**kw)
+    return kw, s, A
+
+
+def test_rhs_matches_oracle(cluster_case):
+    kw, s, A = cluster_case
+    b = s.rhs()
+    ref = saddle.rhs(A)
+    assert np.abs(b - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_saddle_operator_matches_oracle(cluster_case):
+    kw, s, A = cluster_case
+    K = saddle.saddle_matrix(A)
+    x = np.random.default_rng(7).normal(size=K.shape[0])
+    y = s.apply_saddle(x)
+    ref = K @ x
+    assert np.abs(y - ref).max() < 1e-8 * np.abs(ref).max()
+    # lubrication / constraint rows carry no Ewald truncation
+    nb6 = A.M.shape[0]
+    assert np.abs(y[nb6:] - ref[nb6:]).max() < 1e-10 * np.abs(ref[nb6:]).max()
+
+
+def test_preconditioner_matches_oracle(cluster_case):
+    kw, s, A = cluster_case
+    P = saddle.preconditioner(A, kw["offsets"], 1.0, 1.0, kw["L"], r_pre=2.1)
+    r = np.random.default_rng(8).normal(size=P.shape[0])
+    z = s.apply_precond(r)
+    ref = P @ r
+    assert np.abs(z - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_small_solve_matches_oracle(cluster_case):
+    kw, s, A = cluster_case
+    U, lam, info = s.solve(want_lambda=True)
+    F_o, V_o = saddle.solve_schur(A)
+    Uo = V_o.reshape(-1, 6) + A.Uinf
+    et, er = _vel_errors(U, Uo)
+    assert et < 1e-8 and er < 1e-8, (et, er)
+    assert info.rel_residual_fp64 < 1e-11
+    assert _rel(lam.reshape(-1), F_o) < 1e-7
+
+
+def test_small_solve_mixed_precision(F, cluster_case):
+    kw, s, A = cluster_case
+    sm = _make(F, kw, precision=F.FSD_MIXED, gmres_tol=1e-9, inner_tol=1e-3)
+    U, _, info = sm.solve()
+    F_o, V_o = saddle.solve_schur(A)
+    Uo = V_o.reshape(-1, 6) + A.Uinf
+    et, er = _vel_errors(U, Uo)
+    assert et < 1e-7 and er < 1e-7, (et, er)
+    assert info.rel_residual_fp64 <= 1e-9
+    assert info.refinements >= 1
+
+
+def test_single_bead_aggregates_give_mobility_product(F):
+    kw = _single_beads(10, 12.0, 9)
+    s = _make(F, kw)
+    U, _, _ = s.solve()
+    M = rpy.periodic_mobility(kw["com"], 12.0, 1.0, 1.0)
+    ref = (M @ kw["force"].reshape(-1)).reshape(-1, 6)
+    et, er = _vel_errors(U, ref)
+    assert et < 1e-8 and er < 1e-8
+
+
+def test_bead_forces_project_like_sigma(F):
+    kw = _cluster_system(seed=12, shear=False)
+    s = _make(F, kw)
+    rng = np.random.default_rng(13)
+    fb = rng.normal(size=(int(kw["offsets"][-1]), 3))
+    s.set_bead_forces(fb)
+    U, _, _ = s.solve()
+    A = saddle.assemble(**kw)
+    lam = np.zeros((len(fb), 6))
+    lam[:, :3] = fb
+    ft = (A.Sig @ lam.reshape(-1)).reshape(-1, 6)
+    Uo, *_ = saddle.solve(**{**kw, "force": ft})
+    assert max(_vel_errors(U, Uo)) < 1e-8
+
+
+# ---------------------------------------------------------------------------------------
+# full-size workloads against stored oracle values
+# ---------------------------------------------------------------------------------------
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_golden.py)")
+    return np.load(path, allow_pickle=False)
+
+
+def test_doublets16_matches_oracle(F):
+    from tests.golden.make_golden import digest
+    g = _golden("doublets16_oracle.npz")
+    s0 = fsdgen.config(0)
+    assert str(g["digest"]) == digest(s0)
+    s = F.System.from_suspension(s0)
+    U, _, info = s.solve()
+    et, er = _vel_errors(U, g["U"][0])
+    assert et < 1e-5 and er < 1e-5, (et, er)
+    assert info.rel_residual_fp64 <= s0.gmres_tol
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_clusters256x8_ten_steps_match_oracle(F, precision):
+    from tests.golden.make_golden import digest
+    g = _golden("clusters256x8_oracle.npz")
+    s1 = fsdgen.config(1)
+    assert str(g["digest"]) == digest(s1)
+    s = F.System.from_suspension(s1, precision=precision, gmres_tol=1e-6)
+    worst = 0.0
+    for step in range(len(g["U"])):
+        U, _, info = s.solve()
+        et, er = _vel_errors(U, g["U"][step])
+        worst = max(worst, et, er)
+        assert et < 1e-5 and er < 1e-5, (step, et, er)
+        assert info.rel_residual_fp64 <= 1e-6
+        # advance with the same Euler rule the oracle used (re-solves, then integrates)
+        s.step(s1.dt, 1)
+    print("worst relative velocity error over 10 steps:", worst)
+
+
+# ---------------------------------------------------------------------------------------
+# error paths
+# ---------------------------------------------------------------------------------------
+
+def test_error_paths(F):
+    kw = _cluster_system(seed=14)
+    s = F.System(F.default_params())
+    with pytest.raises(F.FsdError) as e:
+        s.solve()
+    assert e.value.code == -5
+    s.init_box(kw["L"])
+    with pytest.raises(F.FsdError) as e:
+        s.init_aggregates([0, 0], np.zeros((0, 3)), np.zeros(3), [1, 0, 0, 0])
+    assert e.value.code == -1
+    with pytest.raises(F.FsdError) as e:
+        s.init_aggregates([0, 1], np.zeros((1, 3)), np.zeros(3), [0, 0, 0, 0])
+    assert e.value.code == -1
+    s.init_aggregates(kw["offsets"], kw["x_body"], kw["com"], kw["quat"])
+    with pytest.raises(F.FsdError) as e:
+        s.set_shear(np.eye(3))
+    assert e.value.code == -1
+    f = kw["force"].copy()
+    f[0, 0] = np.nan
+    with pytest.raises(F.FsdError) as e:
+        s.set_forces(f)
+    assert e.value.code == -1
+    # maxit = 1 must report non-convergence with the residual
+    s2 = _make(F, kw, gmres_maxit=1)
+    U, _, info = s2.solve(check=False)
+    assert info.status == -3 and info.rel_residual_fp64 > 0
+    # overlapping bodies
+    kw3 = _single_beads(2, 10.0, 15)
+    kw3["com"] = np.array([[0.0, 0, 0], [1.2, 0, 0]])
+    kw3["r_lub"] = 3.0
+    s3 = _make(F, kw3)
+    with pytest.raises(F.FsdError) as e:
+        s3.solve()
+    assert e.value.code == -6
