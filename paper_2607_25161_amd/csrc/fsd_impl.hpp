@@ -76,6 +76,14 @@ void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, c
                   int sign, hipStream_t st, int pass = -1);
 template <typename R>
 void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st);
+// Gaussian spreading as a gather over beads binned by grid block (no atomics).
+struct SpreadPlan;
+SpreadPlan* spread_plan_create(int nb, int n_grid, int support);  // nullptr if n_grid % 4 != 0
+void spread_plan_destroy(SpreadPlan* sp);
+hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WaveParams& wp, hipStream_t st);
+template <typename R>
+void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid,
+                          hipStream_t st);
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
                    hipStream_t st);

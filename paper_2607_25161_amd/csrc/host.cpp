@@ -227,6 +227,7 @@ struct fsd_system {
   double *d_r = nullptr, *d_wt = nullptr, *d_fl = nullptr, *d_h = nullptr, *d_part = nullptr, *d_U = nullptr;
   double* h_small = nullptr;  // pinned
   NeighborWork* nw = nullptr;
+  SpreadPlan* spread = nullptr;  // gather spreading (nullptr: atomic scatter)
   std::vector<double> h_tab;  // host copy of the smooth-part table (5 per node, 8 stride)
 
   // per-kernel-class event timing (fsd_set_timing)
@@ -247,6 +248,8 @@ struct fsd_system {
     ev_pool.clear();
     if (nw) neighbor_work_destroy(nw);
     nw = nullptr;
+    if (spread) spread_plan_destroy(spread);
+    spread = nullptr;
     for (void* q : owned) (void)hipFree(q);
     owned.clear();
     if (h_small) (void)hipHostFree(h_small);
@@ -463,6 +466,7 @@ void prepare(fsd_system* s) {
   }
   launch_precond_factor(s->na, s->d_offsets, s->d_r4, s->d_rdiag, s->drag_t, s->drag_r, s->d_lu, s->d_piv,
                         s->d_flags + 1, s->st);
+  if (s->spread) HIPCHK(spread_plan_update(s->spread, s->d_pos4, s->wp, s->st));
   int flags[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(flags, s->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
@@ -518,8 +522,11 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts) {
     const int N = s->wp.n;
     const size_t cs = 2 * size_t(N) * N * N;  // R elements per complex component grid
     R* grid = static_cast<R*>(s->d_grid);
-    HIPCHK(hipMemsetAsync(grid, 0, sizeof(R) * 3 * cs, s->st));
-    {
+    if (s->spread) {
+      Timed t(s, FSD_TIMER_SPREAD);
+      launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st);
+    } else {
+      HIPCHK(hipMemsetAsync(grid, 0, sizeof(R) * 3 * cs, s->st));
       Timed t(s, FSD_TIMER_SPREAD);
       launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st);
     }
@@ -879,6 +886,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
     s->nw = neighbor_work_create(nb);
     if (!s->nw) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
+    s->spread = spread_plan_create(nb, s->wp.n, s->wp.support);  // nullptr: grid not a multiple of 4
     upload_tables(s);
     HIPCHK(hipMemcpy(s->d_offsets, off, sizeof(int) * (n_agg + 1), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(s->d_body, body.data(), sizeof(int) * nb, hipMemcpyHostToDevice));

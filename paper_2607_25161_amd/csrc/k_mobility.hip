@@ -8,6 +8,10 @@
 // Real space: per neighbour pair within the cutoff, the free-space RPY block
 // minus the smooth inverse transform of the damped multiplier, read from a
 // table by cubic interpolation.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+
 #include "fsd_impl.hpp"
 
 namespace fsd {
@@ -273,6 +277,268 @@ template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
   k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// Gaussian spreading as a gather: beads are binned by the grid block that holds
+// the first point of their support (sorted once per configuration); a workgroup
+// owns one BS^3 block of grid points and sums the contributions of every bead
+// whose support reaches it.  No atomics, deterministic, each grid value written
+// once.
+// ------------------------------------------------------------------------------------------
+
+struct SpreadPlan {
+  int nb = 0, BS = 0, nbin = 0, K = 0, P = 0;
+  int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *perm = nullptr;
+  int *bin_start = nullptr, *bin_end = nullptr;
+  int4* starts = nullptr;   // (sx, sy, sz, bin) per bead, sorted order
+  double* weights = nullptr;  // 3P weights per bead, sorted order
+  float* weights32 = nullptr;  // the same in FP32
+  double* wtmp = nullptr;
+  int4* stmp = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  size_t rbytes = 0;
+};
+
+namespace {
+int pick_block(int N) {
+  if (N % 8 == 0) return 8;
+  if (N % 4 == 0) return 4;
+  return 0;
+}
+}  // namespace
+
+SpreadPlan* spread_plan_create(int nb, int N, int P) {
+  const int BS = pick_block(N);
+  if (BS == 0) return nullptr;
+  auto* sp = new SpreadPlan;
+  sp->nb = nb;
+  sp->BS = BS;
+  sp->nbin = N / BS;
+  sp->P = P;
+  sp->K = std::min(1 + (P - 1 + BS - 1) / BS, sp->nbin);
+  const int nbins = sp->nbin * sp->nbin * sp->nbin;
+  bool ok = hipMalloc(&sp->keys_in, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&sp->keys_out, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&sp->vals_in, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&sp->perm, sizeof(int) * nb) == hipSuccess &&
+            hipMalloc(&sp->bin_start, sizeof(int) * nbins) == hipSuccess &&
+            hipMalloc(&sp->bin_end, sizeof(int) * nbins) == hipSuccess &&
+            hipMalloc(&sp->starts, sizeof(int4) * nb) == hipSuccess &&
+            hipMalloc(&sp->stmp, sizeof(int4) * nb) == hipSuccess &&
+            hipMalloc(&sp->weights, sizeof(double) * 3 * P * size_t(nb)) == hipSuccess &&
+            hipMalloc(&sp->weights32, sizeof(float) * 3 * P * size_t(nb)) == hipSuccess &&
+            hipMalloc(&sp->wtmp, sizeof(double) * 3 * P * size_t(nb)) == hipSuccess;
+  size_t b = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, b, sp->keys_in, sp->keys_out, sp->vals_in, sp->perm, nb);
+  sp->temp_bytes = b;
+  ok = ok && hipMalloc(&sp->temp, b) == hipSuccess;
+  if (!ok) {
+    spread_plan_destroy(sp);
+    return nullptr;
+  }
+  return sp;
+}
+
+void spread_plan_destroy(SpreadPlan* sp) {
+  if (!sp) return;
+  (void)hipFree(sp->keys_in);
+  (void)hipFree(sp->keys_out);
+  (void)hipFree(sp->vals_in);
+  (void)hipFree(sp->perm);
+  (void)hipFree(sp->bin_start);
+  (void)hipFree(sp->bin_end);
+  (void)hipFree(sp->starts);
+  (void)hipFree(sp->stmp);
+  (void)hipFree(sp->weights);
+  (void)hipFree(sp->weights32);
+  (void)hipFree(sp->wtmp);
+  (void)hipFree(sp->temp);
+  delete sp;
+}
+
+__global__ void k_bead_prep(int nb, const double4* __restrict__ pos, WaveParams wp, int BS, int nbin,
+                            double* __restrict__ w, int4* __restrict__ st, int* __restrict__ keys, int* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int P = wp.support, N = wp.n;
+  const double4 p = pos[i];
+  int sm[3];
+  for (int d = 0; d < 3; ++d) {
+    const double pd = d == 0 ? p.x : (d == 1 ? p.y : p.z);
+    const int s = int(ceil(pd / wp.h - 0.5 * P));
+    for (int k = 0; k < P; ++k) {
+      const double xm = (s + k) * wp.h - pd;
+      w[size_t(i) * 3 * P + d * P + k] = exp(-wp.alpha * xm * xm);
+    }
+    sm[d] = ((s % N) + N) % N;
+  }
+  const int bin = ((sm[2] / BS) * nbin + sm[1] / BS) * nbin + sm[0] / BS;
+  st[i] = make_int4(sm[0], sm[1], sm[2], bin);
+  keys[i] = bin;
+  vals[i] = i;
+}
+
+__global__ void k_bead_permute(int nb, int P3, const int* __restrict__ perm, const double* __restrict__ w_in,
+                               const int4* __restrict__ s_in, double* __restrict__ w_out, float* __restrict__ w32,
+                               int4* __restrict__ s_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  const int i = perm[k];
+  for (int q = 0; q < P3; ++q) {
+    const double v = w_in[size_t(i) * P3 + q];
+    w_out[size_t(k) * P3 + q] = v;
+    w32[size_t(k) * P3 + q] = float(v);
+  }
+  s_out[k] = s_in[i];
+}
+
+__global__ void k_bin_bounds(int nb, const int* __restrict__ keys, int* start, int* end) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  const int c = keys[k];
+  if (k == 0 || keys[k - 1] != c) start[c] = k;
+  if (k == nb - 1 || keys[k + 1] != c) end[c] = k + 1;
+}
+
+hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WaveParams& wp, hipStream_t st) {
+  const int nb = sp->nb;
+  double* w = sp->wtmp;
+  k_bead_prep<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, wp, sp->BS, sp->nbin, w, sp->stmp,
+                                                   sp->keys_in, sp->vals_in);
+  int bits = 1;
+  const int nbins = sp->nbin * sp->nbin * sp->nbin;
+  while ((1 << bits) < nbins) ++bits;
+  size_t tb = sp->temp_bytes;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(sp->temp, tb, sp->keys_in, sp->keys_out, sp->vals_in, sp->perm,
+                                                    nb, 0, bits, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipMemsetAsync(sp->bin_start, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(sp->bin_end, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
+  k_bin_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, sp->keys_out, sp->bin_start, sp->bin_end);
+  k_bead_permute<<<nblocks(nb), kThreads, 0, st>>>(nb, 3 * sp->P, sp->perm, w, sp->stmp, sp->weights,
+                                                   sp->weights32, sp->starts);
+  return hipGetLastError();
+}
+
+namespace {
+constexpr int kChunk = 64;
+}
+
+template <typename R, int BS>
+__global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restrict__ bin_start,
+                                                               const int* __restrict__ bin_end,
+                                                               const int* __restrict__ perm,
+                                                               const int4* __restrict__ starts,
+                                                               const R* __restrict__ weights,
+                                                               const double* __restrict__ lam, WaveParams wp,
+                                                               int nbin, int K, R* __restrict__ grid, size_t cs) {
+  __shared__ int4 sh_s[kChunk];
+  __shared__ R sh_w[kChunk * 3 * kMaxP];
+  __shared__ R sh_l[kChunk * 6];
+  const int P = wp.support, N = wp.n, P3 = 3 * P;
+  const int bx = blockIdx.x % nbin, by = (blockIdx.x / nbin) % nbin, bz = blockIdx.x / (nbin * nbin);
+  const int t = threadIdx.x;
+  const int mx = bx * BS + t % BS, my = by * BS + (t / BS) % BS, mz = bz * BS + t / (BS * BS);
+  R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  for (int kz = 0; kz < K; ++kz) {
+    const int cz = (bz - kz + nbin) % nbin;
+    for (int ky = 0; ky < K; ++ky) {
+      const int cy = (by - ky + nbin) % nbin;
+      // bins bx-K+1 .. bx along x are consecutive in the sorted order unless they wrap
+      const int x0 = bx - K + 1;
+      for (int part = 0; part < 2; ++part) {
+        int lo, hi;  // inclusive bin range along x
+        if (x0 >= 0) {
+          if (part == 1) break;
+          lo = x0;
+          hi = bx;
+        } else if (part == 0) {
+          lo = 0;
+          hi = bx;
+        } else {
+          lo = x0 + nbin;
+          hi = nbin - 1;
+        }
+        const int row = (cz * nbin + cy) * nbin;
+        // first non-empty start / last end over the range
+        int b0 = 0, b1 = 0;
+        bool any = false;
+        for (int c = lo; c <= hi; ++c) {
+          const int e0 = bin_start[row + c], e1 = bin_end[row + c];
+          if (e1 > e0) {
+            if (!any) b0 = e0;
+            b1 = e1;
+            any = true;
+          }
+        }
+        if (!any) continue;
+        for (int c0 = b0; c0 < b1; c0 += kChunk) {
+          const int n = min(kChunk, b1 - c0);
+          __syncthreads();
+          for (int q = t; q < n * P3; q += BS * BS * BS) sh_w[q] = weights[size_t(c0) * P3 + q];
+          for (int q = t; q < n; q += BS * BS * BS) {
+            sh_s[q] = starts[c0 + q];
+            const double* l = lam + 6 * size_t(perm[c0 + q]);
+            for (int c = 0; c < 6; ++c) sh_l[6 * q + c] = R(l[c]);
+          }
+          __syncthreads();
+          for (int q = 0; q < n; ++q) {
+            const int4 s = sh_s[q];
+            int ix = mx - s.x, iy = my - s.y, iz = mz - s.z;
+            ix += ix < 0 ? N : 0;
+            iy += iy < 0 ? N : 0;
+            iz += iz < 0 ? N : 0;
+            if (ix < P && iy < P && iz < P) {
+              const R* wq = sh_w + q * P3;
+              const R w = wq[ix] * wq[P + iy] * wq[2 * P + iz];
+              const R* l = sh_l + 6 * q;
+              a0 += w * l[0];
+              a1 += w * l[1];
+              a2 += w * l[2];
+              a3 += w * l[3];
+              a4 += w * l[4];
+              a5 += w * l[5];
+            }
+          }
+        }
+      }
+    }
+  }
+  const size_t m = (size_t(mz) * N + my) * N + mx;
+  R* g = grid + 2 * m;
+  g[0] = a0;
+  g[1] = a3;
+  g[cs] = a1;
+  g[cs + 1] = a4;
+  g[2 * cs] = a2;
+  g[2 * cs + 1] = a5;
+}
+
+namespace {
+template <typename R>
+const R* plan_weights(const SpreadPlan* sp);
+template <>
+const double* plan_weights<double>(const SpreadPlan* sp) {
+  return sp->weights;
+}
+template <>
+const float* plan_weights<float>(const SpreadPlan* sp) {
+  return sp->weights32;
+}
+}  // namespace
+
+template <typename R>
+void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid, hipStream_t st) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  const int nblk = sp->nbin * sp->nbin * sp->nbin;
+  if (sp->BS == 8)
+    k_spread_gather<R, 8><<<nblk, 512, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
+                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs);
+  else
+    k_spread_gather<R, 4><<<nblk, 64, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
+                                                plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -550,6 +816,8 @@ void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipSt
 }
 
 // explicit instantiations
+template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t);
+template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t);
 template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
                                       const RealParams&, double*, bool, int, hipStream_t);
 template void launch_real_sum<float>(int, const double*, const double*, const int*, const uint32_t*, const float*,

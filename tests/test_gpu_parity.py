@@ -142,6 +142,15 @@ def test_mobility_many_tiles_ragged(F):
     assert _rel(u, M @ lam) < 1e-7
 
 
+def test_mobility_scatter_fallback_grid(F):
+    # a grid that is not a multiple of 4 takes the atomic scatter spreading path
+    kw = _single_beads(40, 20.0, 7)
+    s = _make(F, kw, xi=0.5, ewald_tol=1e-8, grid=54)
+    lam = np.random.default_rng(6).normal(size=6 * 40)
+    M = rpy.periodic_mobility(kw["com"], 20.0, 1.0, 1.0)
+    assert _rel(s.apply_mobility(lam), M @ lam) < 1e-7
+
+
 # ---------------------------------------------------------------------------------------
 # saddle operator, preconditioner, right-hand side
 # ---------------------------------------------------------------------------------------
