@@ -89,8 +89,8 @@ def main():
         sysm.step(s.dt, 1)
     info = sysm.info()
 
+    # timed region: graph-replayed GMRES, no instrumentation
     torch.cuda.synchronize()
-    sysm.set_timing(True)
     lat, its, res = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -101,8 +101,16 @@ def main():
         res.append(si.rel_residual_fp64)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    # kernel durations: the same steps again with HIP events around every launch on the
+    # library's stream (this runtime cannot time kernels inside captured graphs, so
+    # this pass launches eagerly; the kernels are the same)
+    sysm.set_timing(True)
+    for _ in range(args.steps):
+        sysm.step(s.dt, 1)
     timers = sysm.timers()
     sysm.set_timing(False)
+    torch.cuda.synchronize()
 
     counted = sum(1 for r in res if r <= 1e-5)
     value = s.n_bead * counted / elapsed
@@ -131,6 +139,7 @@ def main():
         "gmres_iterations_mean": round(float(np.mean(its)), 2),
         "max_rel_residual": float(max(res)),
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in timers.items()},
+        "kernel_timing": "HIP events around each launch on the library stream, eager pass of the same step count",
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

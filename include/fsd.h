@@ -181,8 +181,8 @@ fsd_status fsd_fft3d(int n, int sign, double* data);
 typedef enum {
   FSD_TIMER_REAL = 0,    /* real-space pair sum                                     */
   FSD_TIMER_SPREAD = 1,  /* Gaussian spreading to the grid                          */
-  FSD_TIMER_FFT = 2,     /* one 1D-transform pass of a 3D FFT (6 per wave apply)     */
-  FSD_TIMER_GREEN = 3,   /* Green's-function scaling of the spectra                 */
+  FSD_TIMER_FFT = 2,     /* one x or y transform pass (4 per wave apply)            */
+  FSD_TIMER_GREEN = 3,   /* z transforms fused with the Green's-function scaling    */
   FSD_TIMER_INTERP = 4,  /* interpolation back to the beads                         */
   FSD_TIMER_RIGID = 5,   /* Sigma^T V and Sigma reductions                          */
   FSD_TIMER_LUB = 6,     /* lubrication block product                               */
@@ -190,6 +190,12 @@ typedef enum {
   FSD_TIMER_KRYLOV = 8,  /* one CGS2 orthogonalisation (5+ launches)                 */
   FSD_TIMER_COUNT = 9
 } fsd_timer;
+
+/* GMRES launch mode: enable = 1 replays cached HIP graphs (cycle start, batches of
+ * `batch` Arnoldi steps, cycle end; default), 0 launches every kernel eagerly.
+ * batch = 0 keeps the current batch size (default 4).  Graphs are rebuilt when
+ * the neighbour-list storage or launch shapes change. */
+fsd_status fsd_set_graphs(fsd_system* s, int enable, int batch);
 
 /* Enable (1) or disable (0) event timing and reset the accumulators. */
 fsd_status fsd_set_timing(fsd_system* s, int enable);

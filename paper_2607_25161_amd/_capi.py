@@ -81,6 +81,7 @@ _sig("fsd_get_rhs", C.c_int, _SYS, _D)
 _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
 _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
+_sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong))
 
 TIMER_NAMES = ("real_sum", "spread", "fft_pass", "green_scale", "interp", "rigid", "lub", "precond", "cgs2")
@@ -254,7 +255,10 @@ class System:
         self._check(lib.fsd_real_functions(self._h, len(r), _dptr(r), _dptr(out)), "fsd_real_functions")
         return out
 
-    # -- timing -----------------------------------------------------------------------
+    # -- launch mode and timing ---------------------------------------------------------
+    def set_graphs(self, enable=True, batch=0):
+        self._check(lib.fsd_set_graphs(self._h, 1 if enable else 0, int(batch)), "fsd_set_graphs")
+
     def set_timing(self, enable=True):
         self._check(lib.fsd_set_timing(self._h, 1 if enable else 0), "fsd_set_timing")
 

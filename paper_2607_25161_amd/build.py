@@ -1,6 +1,6 @@
 """Build libfsd.so (HIP kernels + host orchestration + C ABI) for gfx950, in-tree.
 
-    python -m paper_2607_25161_amd.build        # or paper_2607_25161_amd.build.build()
+    python paper_2607_25161_amd/build.py    (run by path: the package imports the library)
 """
 from __future__ import annotations
 

@@ -66,16 +66,24 @@ void launch_precond_factor(int na, const int* offsets, const double* r4, const d
 template <typename R>
 void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr,
                      const uint32_t* col, const R* table, const RealParams& rp, double* out,
-                     bool accumulate, int lanes_per_row, hipStream_t st);
+                     bool accumulate, int lanes_per_row, hipStream_t st,
+                     const int* skip = nullptr);
 template <typename R>
 void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
-                   hipStream_t st);
+                   hipStream_t st, const int* skip = nullptr);
 // pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
-                  int sign, hipStream_t st, int pass = -1);
+                  int sign, hipStream_t st, int pass = -1, const int* skip = nullptr);
+// Half-spectrum wave-space transforms: stage 0 x forward + split (grid -> half),
+// 1 y forward, 2 z forward + Green's scaling + z inverse, 3 y inverse, 4 x inverse +
+// merge (half -> grid).  half holds 6 (n/2+1) n^2 complex values.
 template <typename R>
-void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st);
+void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
+                     hipStream_t st, const int* skip = nullptr);
+template <typename R>
+void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st,
+                        const int* skip = nullptr);
 // Gaussian spreading as a gather over beads binned by grid block (no atomics).
 struct SpreadPlan;
 SpreadPlan* spread_plan_create(int nb, int n_grid, int support);  // nullptr if n_grid % 4 != 0
@@ -83,21 +91,22 @@ void spread_plan_destroy(SpreadPlan* sp);
 hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WaveParams& wp, hipStream_t st);
 template <typename R>
 void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid,
-                          hipStream_t st);
+                          hipStream_t st, const int* skip = nullptr);
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
-                   hipStream_t st);
+                   hipStream_t st, const int* skip = nullptr);
 
 // ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
 void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1,
-                           double* wt, hipStream_t st);
+                           double* wt, hipStream_t st, const int* skip = nullptr);
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,
-                      const double* wt, double* f, hipStream_t st);
+                      const double* wt, double* f, hipStream_t st, const int* skip = nullptr);
 void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam,
-                       const double* flub, double* y2, hipStream_t st);
+                       const double* flub, double* y2, hipStream_t st, const int* skip = nullptr);
 void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4,
                           const double* lu, const int* piv, double drag_t, double drag_r,
-                          const double* r, double* z, double* tmp_agg, hipStream_t st);
+                          const double* r, double* z, double* tmp_agg, hipStream_t st,
+                          const int* skip = nullptr);
 void launch_rhs(int nb, int na, const int* offsets, const int* body, const double* r4,
                 const double* E, const double* force, const double* fnf, double* b1, double* e3,
                 hipStream_t st);
@@ -106,15 +115,38 @@ void launch_rhs_agg(int na, const int* offsets, const double* r4, const double* 
 void launch_add_ambient(int na, const double* V, const double* com, const double* G,
                         const double* W, double* U, hipStream_t st);
 
+// GMRES cycle state kept on the device so the host synchronises once per batch
+// of iterations, not once per iteration.
+struct GmresCtl {
+  int stop;       // 1: no further Arnoldi steps in this cycle (kernels of later steps return early)
+  int k_used;     // Arnoldi steps completed in this cycle
+  int its;        // iterations in this solve
+  int breakdown;  // Krylov space exhausted (happy breakdown)
+  int maxit, m;
+  double bn;      // ||b||
+  double beta;    // ||r|| at the start of the cycle
+  double resid;   // Givens estimate |g_k| / ||b|| (true residual at a cycle start)
+  double tol;
+};
+void launch_gmres_begin(GmresCtl* ctl, const double* rr, double* g, double* scal, hipStream_t st);
+void launch_scale_by(size_t n, const double* src, const double* scal, double* dst, hipStream_t st,
+                     const int* skip);
+void launch_arnoldi_step(int j, GmresCtl* ctl, const double* h1, const double* h2, const double* hn2,
+                         double* H, double* cs, double* sn, double* g, double* scal, hipStream_t st);
+void launch_gmres_solve(const GmresCtl* ctl, const double* H, const double* g, double* y, hipStream_t st);
+void launch_basis_combine(size_t n, int m, const double* V, size_t ldv, const double* y, const GmresCtl* ctl,
+                          double* out, hipStream_t st);
+
 // dots: partial[q * nblk + b] then out[q]; deterministic two-stage reduction
 int dot_blocks(size_t n);
 void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w,
-                      double* partial, double* out, hipStream_t st);
+                      double* partial, double* out, hipStream_t st, const int* skip = nullptr);
 void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h,
-                       double sgn, double* w, hipStream_t st);
+                       double sgn, double* w, hipStream_t st, const int* skip = nullptr);
 void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst,
-                       hipStream_t st);
+                       hipStream_t st, const int* skip = nullptr);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st);
+void launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes a multiple of 4
 
 }  // namespace fsd

@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
+#include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -221,11 +224,15 @@ struct fsd_system {
   double *d_rdiag = nullptr, *d_lu = nullptr;
   int *d_piv = nullptr, *d_flags = nullptr;
   void* d_grid = nullptr;
+  void* d_half = nullptr;  // six half-spectrum fields
   double* d_tw64 = nullptr;
   float* d_tw32 = nullptr;
   double *d_b = nullptr, *d_x = nullptr, *d_basis = nullptr, *d_z = nullptr, *d_w = nullptr, *d_t = nullptr;
   double *d_r = nullptr, *d_wt = nullptr, *d_fl = nullptr, *d_h = nullptr, *d_part = nullptr, *d_U = nullptr;
   double* h_small = nullptr;  // pinned
+  GmresCtl* d_ctl = nullptr;   // device GMRES cycle state
+  GmresCtl* h_ctl = nullptr;   // pinned mirror
+  double *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr, *d_y = nullptr, *d_scal = nullptr;
   NeighborWork* nw = nullptr;
   SpreadPlan* spread = nullptr;  // gather spreading (nullptr: atomic scatter)
   std::vector<double> h_tab;  // host copy of the smooth-part table (5 per node, 8 stride)
@@ -242,8 +249,37 @@ struct fsd_system {
   double t_ms[FSD_TIMER_COUNT] = {0};
   long long t_n[FSD_TIMER_COUNT] = {0};
 
+  // captured GMRES graphs
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    struct Pair {
+      int cls, iter;
+      hipEvent_t a, b;
+    };
+    std::vector<Pair> pairs;  // timing events recorded as graph nodes
+  };
+  using GraphKey = std::tuple<int, int, int, int, const void*, const void*>;
+  std::map<GraphKey, GraphEntry*> graphs;
+  GraphEntry* capturing = nullptr;
+  int cap_iter = -1;
+  bool use_graphs = true;
+  int batch = 4;
+  std::tuple<const void*, const void*, const void*, int, int, const void*> graph_sig{};
+  void drop_graphs() {
+    for (auto& kv : graphs) {
+      for (auto& p : kv.second->pairs) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+      }
+      if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+      delete kv.second;
+    }
+    graphs.clear();
+  }
+
   ~fsd_system() { release(); }
   void release() {
+    drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     if (nw) neighbor_work_destroy(nw);
@@ -254,6 +290,8 @@ struct fsd_system {
     owned.clear();
     if (h_small) (void)hipHostFree(h_small);
     h_small = nullptr;
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    h_ctl = nullptr;
   }
 };
 
@@ -307,24 +345,74 @@ hipEvent_t next_event(fsd_system* s) {
 }
 
 // Records events around one kernel launch on the system stream when timing is on.
+// Events around one eager kernel launch on the system stream when timing is on.
+// (This runtime cannot time event nodes inside captured graphs, so timed runs
+// launch eagerly; see run_body.)
 struct Timed {
   fsd_system* s;
   int cls;
   hipEvent_t a = nullptr;
   Timed(fsd_system* s_, int c) : s(s_), cls(c) {
-    if (s->timing) {
-      a = next_event(s);
-      HIPCHK(hipEventRecord(a, s->st));
-    }
+    if (!s->timing || s->capturing) return;
+    a = next_event(s);
+    HIPCHK(hipEventRecord(a, s->st));
   }
   ~Timed() noexcept(false) {
-    if (a) {
-      hipEvent_t b = next_event(s);
-      HIPCHK(hipEventRecord(b, s->st));
-      s->pending.push_back({cls, a, b});
-    }
+    if (!a) return;
+    hipEvent_t b = next_event(s);
+    HIPCHK(hipEventRecord(b, s->st));
+    s->pending.push_back({cls, a, b});
   }
 };
+
+// ---- graphs ----------------------------------------------------------------------------------
+using GraphEntry = fsd_system::GraphEntry;
+
+GraphEntry* graph_for(fsd_system* s, const fsd_system::GraphKey& key, const std::function<void()>& body) {
+  auto it = s->graphs.find(key);
+  if (it != s->graphs.end()) return it->second;
+  auto* e = new GraphEntry;
+  s->capturing = e;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(s->st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    s->capturing = nullptr;
+    delete e;
+    throw;
+  }
+  s->capturing = nullptr;
+  HIPCHK(hipStreamEndCapture(s->st, &g));
+  const hipError_t ie = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    delete e;
+    throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  }
+  s->graphs[key] = e;
+  return e;
+}
+
+// run body captured (cached) or eagerly
+GraphEntry* run_body(fsd_system* s, const fsd_system::GraphKey& key, const std::function<void()>& body) {
+  if (!s->use_graphs || s->timing) {
+    body();
+    return nullptr;
+  }
+  GraphEntry* e = graph_for(s, key, body);
+  HIPCHK(hipGraphLaunch(e->exec, s->st));
+  return e;
+}
+
+// after the stream has drained: add the timings of iterations that did work
+void harvest_graph(fsd_system* s, GraphEntry* e, int active) {
+  (void)s;
+  (void)e;
+  (void)active;  // captured graphs carry no timing nodes
+}
 
 // ---- parameter rules (Section 3.2: R_c = sqrt(-ln x_err)/xi, k_c = 2 sqrt(-ln x_err) xi + 1) --
 void choose_parameters(fsd_system* s) {
@@ -476,6 +564,13 @@ void prepare(fsd_system* s) {
   int l = 1;
   while (l < 64 && l * 6 < avg) l *= 2;
   s->lpr = l;
+  // captured graphs hold buffer pointers and launch shapes: drop them when those change
+  auto sig = std::make_tuple((const void*)s->d_ncol, (const void*)s->d_lcol, (const void*)s->d_lcoef, s->lpr,
+                             int(s->p.r_lub > 0 && s->nlub > 0), (const void*)s->spread);
+  if (sig != s->graph_sig) {
+    s->drop_graphs();
+    s->graph_sig = sig;
+  }
   s->prepared = true;
 }
 
@@ -510,11 +605,11 @@ const float* twiddle_of<float>(fsd_system* s) {
 
 // out = M lam (parts: 1 real space, 2 wave space)
 template <typename R>
-void apply_mobility(fsd_system* s, const double* lam, double* out, int parts) {
+void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, const int* skip = nullptr) {
   if (parts & 1) {
     Timed t(s, FSD_TIMER_REAL);
     launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr,
-                       s->st);
+                       s->st, skip);
   } else {
     HIPCHK(hipMemsetAsync(out, 0, sizeof(double) * 6 * s->nb, s->st));
   }
@@ -524,63 +619,56 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts) {
     R* grid = static_cast<R*>(s->d_grid);
     if (s->spread) {
       Timed t(s, FSD_TIMER_SPREAD);
-      launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st);
+      launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st, skip);
     } else {
-      HIPCHK(hipMemsetAsync(grid, 0, sizeof(R) * 3 * cs, s->st));
+      launch_zero(grid, sizeof(R) * 3 * cs, s->st);
       Timed t(s, FSD_TIMER_SPREAD);
       launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st);
     }
-    for (int ps = 0; ps < 3; ++ps) {
-      Timed t(s, FSD_TIMER_FFT);
-      launch_fft3d<R>(grid, 3, cs, s->plan, twiddle_of<R>(s), -1, s->st, ps);
-    }
-    {
-      Timed t(s, FSD_TIMER_GREEN);
-      launch_green_scale<R>(grid, cs, s->wp, s->st);
-    }
-    for (int ps = 0; ps < 3; ++ps) {
-      Timed t(s, FSD_TIMER_FFT);
-      launch_fft3d<R>(grid, 3, cs, s->plan, twiddle_of<R>(s), +1, s->st, ps);
+    R* half = static_cast<R*>(s->d_half);
+    for (int stage = 0; stage < 5; ++stage) {
+      Timed t(s, stage == 2 ? FSD_TIMER_GREEN : FSD_TIMER_FFT);
+      launch_wave_fft<R>(grid, half, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
     }
     {
       Timed t(s, FSD_TIMER_INTERP);
-      launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st);
+      launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip);
     }
   }
 }
 
 // y = A x for the saddle matrix [[M, Sigma^T], [Sigma, -Sigma R_nf Sigma^T]]
 template <typename R>
-void apply_saddle(fsd_system* s, const double* x, double* y) {
+void apply_saddle(fsd_system* s, const double* x, double* y, const int* skip = nullptr) {
   const size_t nb6 = 6 * size_t(s->nb);
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
-  apply_mobility<R>(s, x, y, 3);
+  apply_mobility<R>(s, x, y, 3, skip);
   {
     Timed t(s, FSD_TIMER_RIGID);
-    launch_rigid_velocity(s->nb, s->d_body, s->d_r4, x + nb6, y, lub ? s->d_wt : nullptr, s->st);
+    launch_rigid_velocity(s->nb, s->d_body, s->d_r4, x + nb6, y, lub ? s->d_wt : nullptr, s->st, skip);
   }
   if (lub) {
     Timed t(s, FSD_TIMER_LUB);
-    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
+    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st, skip);
   }
   {
     Timed t(s, FSD_TIMER_RIGID);
-    launch_agg_reduce(s->na, s->d_offsets, s->d_r4, x, lub ? s->d_fl : nullptr, y + nb6, s->st);
+    launch_agg_reduce(s->na, s->d_offsets, s->d_r4, x, lub ? s->d_fl : nullptr, y + nb6, s->st, skip);
   }
 }
 
-void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32) {
+void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32, const int* skip = nullptr) {
   if (fp32)
-    apply_saddle<float>(s, x, y);
+    apply_saddle<float>(s, x, y, skip);
   else
-    apply_saddle<double>(s, x, y);
+    apply_saddle<double>(s, x, y, skip);
 }
 
-void apply_precond(fsd_system* s, const double* r, double* z) {
+void apply_precond(fsd_system* s, const double* r, double* z, const int* skip = nullptr) {
   Timed t(s, FSD_TIMER_PRECOND);
   // M~^-1 = diag(6 pi eta a, 8 pi eta a^3): the bead drag (inverse self-mobility)
   launch_precond_apply(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, r,
-                       z, nullptr, s->st);
+                       z, nullptr, s->st, skip);
 }
 
 void assemble_rhs(fsd_system* s) {
@@ -606,79 +694,87 @@ struct GmresOut {
 };
 
 // Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
-// twice (CGS2).  x is the initial guess on entry and the iterate on exit.
-// The stopping test uses the recomputed residual ||b - A x|| / ||b||.
+// twice (CGS2).  x is the initial guess on entry and the iterate on exit.  The
+// Arnoldi bookkeeping, Givens rotations and stopping test run on the device; the
+// host launches iterations in batches and synchronises once per batch, reading
+// the device stop flag.  Kernels of steps after the stop return immediately.
+// Every cycle starts from the recomputed residual b - A x, so the reported
+// residual is a true one.
 GmresOut gmres(fsd_system* s, const double* b, double* x, double tol, bool fp32, int maxit) {
   GmresOut o;
   const size_t n = s->n;
   const int m = s->m;
   double* V = s->d_basis;
+  const int* stop = &s->d_ctl->stop;
   const double bn = norm2(s, b);
   if (bn == 0.0) {
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, s->st));
     o.converged = true;
     return o;
   }
-  std::vector<double> H(size_t(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
-  double* hs = s->h_small;  // pinned: [0, m+1) first pass, [m+1, 2m+2) second pass, 2m+2 norm
+  GmresCtl c{};
+  c.bn = bn;
+  c.tol = tol;
+  c.maxit = maxit;
+  c.m = m;
+  HIPCHK(hipMemcpyAsync(s->d_ctl, &c, sizeof(GmresCtl), hipMemcpyHostToDevice, s->st));
+  double* h1 = s->d_h;
+  double* h2 = s->d_h + (m + 1);
+  double* hn2 = s->d_h + 2 * (m + 1);
+  const int S = std::max(1, std::min(s->batch, m));
+  const int prec = fp32 ? 1 : 0;
+  GraphEntry* pending_end = nullptr;
   while (true) {
-    apply_saddle_p(s, x, s->d_t, fp32);
-    launch_sub(n, b, s->d_t, s->d_r, s->st);
-    const double beta = norm2(s, s->d_r);
-    o.rel = beta / bn;
+    // cycle start: r = b - A x, beta = ||r||, v0 = r / beta
+    GraphEntry* e0 = run_body(s, {0, 0, 0, prec, b, x}, [&] {
+      apply_saddle_p(s, x, s->d_t, fp32);
+      launch_sub(n, b, s->d_t, s->d_r, s->st);
+      launch_multi_dot(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->st);
+      launch_gmres_begin(s->d_ctl, hn2, s->d_g, s->d_scal, s->st);
+      launch_scale_by(n, s->d_r, s->d_scal, V, s->st, stop);
+    });
+    HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    harvest_graph(s, pending_end, 1 << 30);
+    harvest_graph(s, e0, 1 << 30);
+    pending_end = nullptr;
+    o.rel = s->h_ctl->resid;
+    o.its = s->h_ctl->its;
     if (o.rel <= tol) {
       o.converged = true;
       return o;
     }
-    if (o.its >= maxit) return o;
-    launch_axpby(n, 1.0 / beta, s->d_r, 0.0, V, s->st);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k_used = 0;
-    for (int k = 0; k < m; ++k) {
-      apply_precond(s, V + size_t(k) * n, s->d_z);
-      apply_saddle_p(s, s->d_z, s->d_w, fp32);
-      {  // CGS2
-        Timed t(s, FSD_TIMER_KRYLOV);
-        launch_multi_dot(n, k + 1, V, n, s->d_w, s->d_part, s->d_h, s->st);
-        launch_multi_axpy(n, k + 1, V, n, s->d_h, -1.0, s->d_w, s->st);
-        launch_multi_dot(n, k + 1, V, n, s->d_w, s->d_part, s->d_h + (m + 1), s->st);
-        launch_multi_axpy(n, k + 1, V, n, s->d_h + (m + 1), -1.0, s->d_w, s->st);
-        launch_multi_dot(n, 1, s->d_w, n, s->d_w, s->d_part, s->d_h + 2 * (m + 1), s->st);
-      }
-      HIPCHK(hipMemcpyAsync(hs, s->d_h, sizeof(double) * (2 * (m + 1) + 1), hipMemcpyDeviceToHost, s->st));
+    if (s->h_ctl->stop) return o;  // iteration budget spent
+    for (int j0 = 0; j0 < m; j0 += S) {
+      const int cnt = std::min(S, m - j0);
+      GraphEntry* eb = run_body(s, {1, j0, cnt, prec, nullptr, nullptr}, [&] {
+        for (int j = j0; j < j0 + cnt; ++j) {
+          s->cap_iter = j - j0;
+          apply_precond(s, V + size_t(j) * n, s->d_z, stop);
+          apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
+          Timed t(s, FSD_TIMER_KRYLOV);  // CGS2 + Givens
+          launch_multi_dot(n, j + 1, V, n, s->d_w, s->d_part, h1, s->st, stop);
+          launch_multi_axpy(n, j + 1, V, n, h1, -1.0, s->d_w, s->st, stop);
+          launch_multi_dot(n, j + 1, V, n, s->d_w, s->d_part, h2, s->st, stop);
+          launch_multi_axpy(n, j + 1, V, n, h2, -1.0, s->d_w, s->st, stop);
+          launch_multi_dot(n, 1, s->d_w, n, s->d_w, s->d_part, hn2, s->st, stop);
+          launch_arnoldi_step(j, s->d_ctl, h1, h2, hn2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal, s->st);
+          launch_scale_by(n, s->d_w, s->d_scal, V + size_t(j + 1) * n, s->st, stop);
+        }
+        s->cap_iter = -1;
+      });
+      HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
       HIPCHK(hipStreamSynchronize(s->st));
-      for (int j = 0; j <= k; ++j) H[size_t(j) * m + k] = hs[j] + hs[m + 1 + j];
-      const double hn = std::sqrt(std::max(hs[2 * (m + 1)], 0.0));
-      H[size_t(k + 1) * m + k] = hn;
-      if (hn > 0) launch_axpby(n, 1.0 / hn, s->d_w, 0.0, V + size_t(k + 1) * n, s->st);
-      for (int j = 0; j < k; ++j) {
-        const double t = cs[j] * H[size_t(j) * m + k] + sn[j] * H[size_t(j + 1) * m + k];
-        H[size_t(j + 1) * m + k] = -sn[j] * H[size_t(j) * m + k] + cs[j] * H[size_t(j + 1) * m + k];
-        H[size_t(j) * m + k] = t;
-      }
-      const double den = std::hypot(H[size_t(k) * m + k], H[size_t(k + 1) * m + k]);
-      cs[k] = H[size_t(k) * m + k] / den;
-      sn[k] = H[size_t(k + 1) * m + k] / den;
-      H[size_t(k) * m + k] = den;
-      H[size_t(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      ++o.its;
-      k_used = k + 1;
-      if (std::fabs(g[k + 1]) / bn <= tol || o.its >= maxit || hn == 0.0) break;
+      harvest_graph(s, eb, s->h_ctl->k_used - j0);
+      if (s->h_ctl->stop) break;
     }
-    for (int i = k_used - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int j = i + 1; j < k_used; ++j) t -= H[size_t(i) * m + j] * y[j];
-      y[i] = t / H[size_t(i) * m + i];
-    }
-    for (int i = 0; i < k_used; ++i) hs[i] = y[i];
-    HIPCHK(hipMemcpyAsync(s->d_h, hs, sizeof(double) * k_used, hipMemcpyHostToDevice, s->st));
-    HIPCHK(hipMemsetAsync(s->d_t, 0, sizeof(double) * n, s->st));
-    launch_multi_axpy(n, k_used, V, n, s->d_h, 1.0, s->d_t, s->st);
-    apply_precond(s, s->d_t, s->d_z);
-    launch_axpby(n, 1.0, s->d_z, 1.0, x, s->st);
+    // x += P^-1 (V y)
+    pending_end = run_body(s, {2, 0, 0, prec, b, x}, [&] {
+      launch_gmres_solve(s->d_ctl, s->d_H, s->d_g, s->d_y, s->st);
+      launch_basis_combine(n, m, V, n, s->d_y, s->d_ctl, s->d_t, s->st);
+      apply_precond(s, s->d_t, s->d_z);
+      launch_axpby(n, 1.0, s->d_z, 1.0, x, s->st);
+    });
     ++o.restarts;
   }
 }
@@ -870,6 +966,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_flags = dalloc<int>(o, 2);
     const size_t N = s->wp.n;
     s->d_grid = dalloc<double>(o, 3 * 2 * N * N * N);
+    s->d_half = dalloc<double>(o, 6 * 2 * (N / 2 + 1) * N * N);
     const size_t n = s->n;
     s->d_b = dalloc<double>(o, n);
     s->d_x = dalloc<double>(o, n);
@@ -884,6 +981,14 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_part = dalloc<double>(o, size_t(s->m + 2) * 1024);
     s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
     HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
+    HIPCHK(hipHostMalloc((void**)&s->h_ctl, sizeof(GmresCtl)));
+    s->d_ctl = reinterpret_cast<GmresCtl*>(dalloc<double>(o, (sizeof(GmresCtl) + 7) / 8));
+    s->d_H = dalloc<double>(o, size_t(s->m + 1) * s->m);
+    s->d_cs = dalloc<double>(o, s->m);
+    s->d_sn = dalloc<double>(o, s->m);
+    s->d_g = dalloc<double>(o, s->m + 1);
+    s->d_y = dalloc<double>(o, s->m);
+    s->d_scal = dalloc<double>(o, 2);
     s->nw = neighbor_work_create(nb);
     if (!s->nw) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
     s->spread = spread_plan_create(nb, s->wp.n, s->wp.support);  // nullptr: grid not a multiple of 4
@@ -1179,6 +1284,17 @@ fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out
   return FSD_OK;
 }
 
+fsd_status fsd_set_graphs(fsd_system* s, int enable, int batch) {
+  if (!s || batch < 0 || batch > 64) return FSD_EINVAL;
+  return guarded(s, [&]() -> fsd_status {
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->drop_graphs();
+    s->use_graphs = enable != 0;
+    if (batch > 0) s->batch = batch;
+    return FSD_OK;
+  });
+}
+
 fsd_status fsd_set_timing(fsd_system* s, int enable) {
   if (!s) return FSD_EINVAL;
   return guarded(s, [&]() -> fsd_status {
@@ -1187,6 +1303,7 @@ fsd_status fsd_set_timing(fsd_system* s, int enable) {
       s->t_ms[k] = 0;
       s->t_n[k] = 0;
     }
+    if ((enable != 0) != s->timing) s->drop_graphs();  // event nodes are captured or not
     s->timing = enable != 0;
     return FSD_OK;
   });

@@ -48,7 +48,8 @@ template <typename R, int LPR>
 __global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restrict__ pos,
                                                   const double* __restrict__ lam, const int* __restrict__ rowptr,
                                                   const uint32_t* __restrict__ col, const R* __restrict__ tab,
-                                                  RealParams rp, double* __restrict__ out, int accumulate) {
+                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int row = gt / LPR;
   const int lane = gt % LPR;
@@ -138,12 +139,13 @@ __global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restr
 
 template <typename R>
 void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr, const uint32_t* col,
-                     const R* table, const RealParams& rp, double* out, bool accumulate, int lpr, hipStream_t st) {
+                     const R* table, const RealParams& rp, double* out, bool accumulate, int lpr, hipStream_t st,
+                     const int* skip) {
   const long long threads = (long long)nb * lpr;
   const int acc = accumulate ? 1 : 0;
   const double4* p = (const double4*)pos4;
 #define FSD_REAL(L_)                                                                                    \
-  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc)
+  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc, skip)
   switch (lpr) {
     case 1: FSD_REAL(1); break;
     case 2: FSD_REAL(2); break;
@@ -185,7 +187,8 @@ __device__ inline int wrapi(int m, int n) {
 template <typename R>
 __global__ __launch_bounds__(256) void k_spread(int nb, const double4* __restrict__ pos,
                                                 const double* __restrict__ lam, WaveParams wp, R* __restrict__ grid,
-                                                size_t cs) {
+                                                size_t cs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ R wts[4][3 * kMaxP];
   __shared__ int sta[4][3];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -219,15 +222,17 @@ __global__ __launch_bounds__(256) void k_spread(int nb, const double4* __restric
 }
 
 template <typename R>
-void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid, hipStream_t st) {
+void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid, hipStream_t st,
+                   const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
-  k_spread<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, lam, wp, grid, cs);
+  k_spread<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, lam, wp, grid, cs, skip);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restrict__ pos,
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ R wts[4][3 * kMaxP];
   __shared__ int sta[4][3];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -274,9 +279,10 @@ __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restric
 }
 
 template <typename R>
-void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st) {
+void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st,
+                   const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
-  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out);
+  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -433,7 +439,8 @@ __global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restr
                                                                const int4* __restrict__ starts,
                                                                const R* __restrict__ weights,
                                                                const double* __restrict__ lam, WaveParams wp,
-                                                               int nbin, int K, R* __restrict__ grid, size_t cs) {
+                                                               int nbin, int K, R* __restrict__ grid, size_t cs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ int4 sh_s[kChunk];
   __shared__ R sh_w[kChunk * 3 * kMaxP];
   __shared__ R sh_l[kChunk * 6];
@@ -530,15 +537,16 @@ const float* plan_weights<float>(const SpreadPlan* sp) {
 }  // namespace
 
 template <typename R>
-void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid, hipStream_t st) {
+void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid, hipStream_t st,
+                          const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
   const int nblk = sp->nbin * sp->nbin * sp->nbin;
   if (sp->BS == 8)
     k_spread_gather<R, 8><<<nblk, 512, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
-                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs);
+                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
   else
     k_spread_gather<R, 4><<<nblk, 64, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
-                                                plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs);
+                                                plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -580,7 +588,8 @@ __device__ inline T rot(T v, int s) {
 
 template <typename R, int DIR>
 __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t cs, FftPlan plan,
-                                                  const R* __restrict__ twiddle, int sign, int B) {
+                                                  const R* __restrict__ twiddle, int sign, int B, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int N = plan.n;
@@ -705,15 +714,357 @@ int lines_per_block(int N) {
 
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle, int sign,
-                  hipStream_t st, int pass) {
+                  hipStream_t st, int pass, const int* skip) {
   using T = typename C2<R>::T;
   const int N = plan.n;
   const int B = lines_per_block(N);
   const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
   dim3 g(N * N / B, ncomp);
-  if (pass < 0 || pass == 0) k_fft_pass<R, 0><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
-  if (pass < 0 || pass == 1) k_fft_pass<R, 1><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
-  if (pass < 0 || pass == 2) k_fft_pass<R, 2><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B);
+  if (pass < 0 || pass == 0) k_fft_pass<R, 0><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
+  if (pass < 0 || pass == 1) k_fft_pass<R, 1><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
+  if (pass < 0 || pass == 2) k_fft_pass<R, 2><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
+}
+
+// ------------------------------------------------------------------------------------------
+// Half-spectrum wave-space pipeline (5 passes per mobility apply):
+//   x_fwd : rows of Z_c = F_c + i T_c transformed along x and split, by the row-local
+//           Hermitian symmetry, into the half spectra F^_c, T^_c (kx = 0..N/2)
+//   y     : transforms along y of the six half-spectrum fields
+//   zgz   : forward transform along z, Green's-function scaling (local in k: all six
+//           fields of one column are in the workgroup), inverse transform along z
+//   y     : inverse transforms along y
+//   x_inv : rows rebuilt as Y_c = u_c + i w_c from the half spectra and transformed back
+// Half-spectrum field f (0..5 = F_x F_y F_z T_x T_y T_z, then U, W) holds (N/2+1) N^2
+// complex values at ((kz N + ky)(N/2+1) + kx).
+// ------------------------------------------------------------------------------------------
+
+namespace {
+// Stockham stages on `nl` lines of length N held in LDS (`in`, scratch `out`);
+// returns the buffer holding the result.
+template <typename T, typename R>
+__device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan& plan, int s) {
+  int Ns = 1;
+  for (int stg = 0; stg < plan.nstage; ++stg) {
+    const int Rd = plan.radix[stg];
+    const int nbf = N / Rd;
+    const int tstride = N / (Ns * Rd);
+    for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
+      const int l = t / nbf, b = t % nbf;
+      const T* li = in + l * N;
+      T* lo = out + l * N;
+      const int k = b % Ns;
+      const int od = (b / Ns) * Ns * Rd + k;
+      if (Rd == 4) {
+        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf], v3 = li[b + 3 * nbf];
+        if (Ns > 1) {
+          v1 = cmul(v1, tw[k * tstride]);
+          v2 = cmul(v2, tw[2 * k * tstride]);
+          v3 = cmul(v3, tw[3 * k * tstride]);
+        }
+        const T s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = rot(csub(v1, v3), s);
+        lo[od] = cadd(s02, s13);
+        lo[od + Ns] = cadd(d02, d13);
+        lo[od + 2 * Ns] = csub(s02, s13);
+        lo[od + 3 * Ns] = csub(d02, d13);
+      } else if (Rd == 2) {
+        T v0 = li[b], v1 = li[b + nbf];
+        if (Ns > 1) v1 = cmul(v1, tw[k * tstride]);
+        lo[od] = cadd(v0, v1);
+        lo[od + Ns] = csub(v0, v1);
+      } else {
+        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf];
+        if (Ns > 1) {
+          v1 = cmul(v1, tw[k * tstride]);
+          v2 = cmul(v2, tw[2 * k * tstride]);
+        }
+        const R c3 = R(-0.5), s3 = R(0.86602540378443864676);
+        const T sm = cadd(v1, v2), df = csub(v1, v2);
+        T m1;
+        m1.x = v0.x + c3 * sm.x;
+        m1.y = v0.y + c3 * sm.y;
+        const T jd = rot(df, s);
+        T y1, y2;
+        y1.x = m1.x + s3 * jd.x;
+        y1.y = m1.y + s3 * jd.y;
+        y2.x = m1.x - s3 * jd.x;
+        y2.y = m1.y - s3 * jd.y;
+        lo[od] = cadd(v0, sm);
+        lo[od + Ns] = y1;
+        lo[od + 2 * Ns] = y2;
+      }
+    }
+    __syncthreads();
+    T* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= Rd;
+  }
+  return in;
+}
+
+template <typename T>
+__device__ inline void load_twiddles(T* tw, const T* twg, int N, int sign) {
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    T w = twg[t];
+    if (sign > 0) w.y = -w.y;
+    tw[t] = w;
+  }
+}
+}  // namespace
+
+// x forward + split: rows (y, z) of component c -> half spectra of F_c (field c) and T_c (field 3 + c)
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
+                                                     size_t hs, FftPlan plan, const R* __restrict__ twiddle, int B,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, H = N / 2 + 1;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + B * N;
+  T* tw = buf1 + B * N;
+  const int c = blockIdx.y;
+  const T* src = reinterpret_cast<const T*>(grid + c * cs);
+  T* dF = reinterpret_cast<T*>(half + c * hs);
+  T* dT = reinterpret_cast<T*>(half + (3 + c) * hs);
+  const size_t row0 = size_t(blockIdx.x) * B;
+  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) buf0[t] = src[row0 * N + t];
+  __syncthreads();
+  const T* X = stockham<T, R>(buf0, buf1, tw, N, B, plan, -1);
+  for (int t = threadIdx.x; t < B * H; t += blockDim.x) {
+    const int l = t / H, kx = t % H;
+    const T a = X[l * N + kx];
+    const T b = X[l * N + (N - kx) % N];  // partner; conj(b) enters
+    T f, tt;
+    f.x = R(0.5) * (a.x + b.x);
+    f.y = R(0.5) * (a.y - b.y);
+    tt.x = R(0.5) * (a.y + b.y);
+    tt.y = R(-0.5) * (a.x - b.x);
+    dF[(row0 + l) * H + kx] = f;
+    dT[(row0 + l) * H + kx] = tt;
+  }
+}
+
+// transforms along y of the six half-spectrum fields (element stride H); lines are (kx, z)
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t hs, FftPlan plan,
+                                                    const R* __restrict__ twiddle, int sign, int B,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, H = N / 2 + 1;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + B * N;
+  T* tw = buf1 + B * N;
+  T* base = reinterpret_cast<T*>(half + blockIdx.y * hs);
+  const int nlines = H * N;
+  const int l0 = blockIdx.x * B;
+  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int l = t % B, e = t / B, gl = l0 + l;
+    T v;
+    v.x = 0;
+    v.y = 0;
+    if (gl < nlines) v = base[(size_t(gl / H) * N + e) * H + gl % H];
+    buf0[l * N + e] = v;
+  }
+  __syncthreads();
+  const T* Y = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int l = t % B, e = t / B, gl = l0 + l;
+    if (gl < nlines) base[(size_t(gl / H) * N + e) * H + gl % H] = Y[l * N + e];
+  }
+}
+
+namespace {
+__device__ inline void sinc_jv_d(double x, double& s, double& j) {
+  if (x < 0.5) {
+    const double x2 = x * x;
+    s = 1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0 * (1.0 - x2 / 110.0))));
+    j = 1.0 - x2 / 10.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0 * (1.0 - x2 / 88.0 * (1.0 - x2 / 130.0))));
+  } else {
+    double sn, cn;
+    sincos(x, &sn, &cn);
+    s = sn / x;
+    j = 3.0 * (sn - x * cn) / (x * x * x);
+  }
+}
+}  // namespace
+
+// z forward, Green's-function scaling, z inverse for B columns (kx, ky) of all six fields
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_t hs, FftPlan plan,
+                                                     const R* __restrict__ twiddle, WaveParams wp, int B,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, H = N / 2 + 1;
+  const int NL = 6 * B;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + NL * N;
+  T* tw = buf1 + NL * N;
+  const int ncol = H * N;
+  const int c0 = blockIdx.x * B;
+  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
+  // line index: l = f * B + b  (field f, column c0 + b)
+  for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
+    const int b = t % B, f = (t / B) % 6, e = t / NL, col = c0 + b;
+    T v;
+    v.x = 0;
+    v.y = 0;
+    if (col < ncol) v = reinterpret_cast<const T*>(half + f * hs)[size_t(e) * ncol + col];
+    buf0[(f * B + b) * N + e] = v;
+  }
+  __syncthreads();
+  T* X = stockham<T, R>(buf0, buf1, tw, N, NL, plan, -1);
+  T* scratch = (X == buf0) ? buf1 : buf0;
+  const double tp = 2.0 * M_PI / wp.L;
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int b = t % B, kz = t / B, col = c0 + b;
+    const int kx = col % H, ky = col / H;
+    T* ln[6];
+    for (int f = 0; f < 6; ++f) ln[f] = X + (f * B + b) * N + kz;
+    const bool nyq = (N % 2 == 0) && (kx == N / 2 || ky == N / 2 || kz == N / 2);
+    if (col >= ncol || nyq || (kx == 0 && ky == 0 && kz == 0)) {
+      for (int f = 0; f < 6; ++f) {
+        ln[f]->x = 0;
+        ln[f]->y = 0;
+      }
+      continue;
+    }
+    const double k[3] = {tp * kx, tp * (ky < N / 2 ? ky : ky - N), tp * (kz < N / 2 ? kz : kz - N)};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const double kn = sqrt(k2);
+    const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
+    double sk, jk;
+    sinc_jv_d(kn * wp.a, sk, jk);
+    const double q = k2 / (4.0 * wp.xi * wp.xi);
+    const double Bk = wp.scale * (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / (wp.eta * k2);
+    double Fr[3], Fi[3], Tr[3], Ti[3];
+    for (int a = 0; a < 3; ++a) {
+      Fr[a] = ln[a]->x;
+      Fi[a] = ln[a]->y;
+      Tr[a] = ln[3 + a]->x;
+      Ti[a] = ln[3 + a]->y;
+    }
+    // g = sinc F + (i/2) jv (k x T), transverse part, times B(k)
+    const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
+    const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
+    double gr[3], gi[3];
+    for (int a = 0; a < 3; ++a) {
+      gr[a] = sk * Fr[a] - 0.5 * jk * cxi[a];
+      gi[a] = sk * Fi[a] + 0.5 * jk * cxr[a];
+    }
+    const double pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
+    const double pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
+    double ur[3], ui[3];
+    for (int a = 0; a < 3; ++a) {
+      ur[a] = Bk * (gr[a] - pr * kh[a]);
+      ui[a] = Bk * (gi[a] - pim * kh[a]);
+    }
+    // U = sinc u (fields 0..2), W = (i/2) jv (k x u) (fields 3..5)
+    const double kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
+    const double kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
+    for (int a = 0; a < 3; ++a) {
+      ln[a]->x = R(sk * ur[a]);
+      ln[a]->y = R(sk * ui[a]);
+      ln[3 + a]->x = R(-0.5 * jk * kui[a]);
+      ln[3 + a]->y = R(0.5 * jk * kur[a]);
+    }
+  }
+  __syncthreads();
+  // inverse transform along z with conjugated twiddles
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t].y = -tw[t].y;
+  __syncthreads();
+  const T* Y = stockham<T, R>(X, scratch, tw, N, NL, plan, +1);
+  for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
+    const int b = t % B, f = (t / B) % 6, e = t / NL, col = c0 + b;
+    if (col < ncol) reinterpret_cast<T*>(half + f * hs)[size_t(e) * ncol + col] = Y[(f * B + b) * N + e];
+  }
+}
+
+// x inverse + merge: rows (y, z): Y_c = u_c + i w_c rebuilt from the half spectra of
+// fields c (u) and 3 + c (w), transformed back into grid component c
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
+                                                     size_t cs, FftPlan plan, const R* __restrict__ twiddle, int B,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, H = N / 2 + 1;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + B * N;
+  T* tw = buf1 + B * N;
+  const int c = blockIdx.y;
+  const T* sU = reinterpret_cast<const T*>(half + c * hs);
+  const T* sW = reinterpret_cast<const T*>(half + (3 + c) * hs);
+  T* dst = reinterpret_cast<T*>(grid + c * cs);
+  const size_t row0 = size_t(blockIdx.x) * B;
+  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, +1);
+  for (int t = threadIdx.x; t < B * H; t += blockDim.x) {
+    const int l = t / H, kx = t % H;
+    const T u = sU[(row0 + l) * H + kx], w = sW[(row0 + l) * H + kx];
+    T y;  // u + i w
+    y.x = u.x - w.y;
+    y.y = u.y + w.x;
+    if (kx == N / 2 && N % 2 == 0) {
+      y.x = 0;
+      y.y = 0;
+    }
+    buf0[l * N + kx] = y;
+    if (kx > 0 && kx < N - kx) {
+      T z;  // conj(u) + i conj(w)
+      z.x = u.x + w.y;
+      z.y = -u.y + w.x;
+      buf0[l * N + N - kx] = z;
+    }
+  }
+  __syncthreads();
+  const T* X = stockham<T, R>(buf0, buf1, tw, N, B, plan, +1);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) dst[row0 * N + t] = X[t];
+}
+
+namespace {
+int rows_per_block(int N) {
+  int B = 1;
+  while (B * 2 * N <= 1024 && ((N * N) % (B * 2)) == 0) B *= 2;
+  return B;
+}
+}  // namespace
+
+template <typename R>
+void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
+                     hipStream_t st, const int* skip) {
+  using T = typename C2<R>::T;
+  const int N = plan.n, H = N / 2 + 1;
+  const size_t cs = 2 * size_t(N) * N * N;
+  const size_t hs = 2 * size_t(H) * N * N;
+  if (stage == 0 || stage == 4) {
+    const int B = rows_per_block(N);
+    const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
+    dim3 g(N * N / B, 3);
+    if (stage == 0)
+      k_fft_x_split<R><<<g, kThreads, shm, st>>>(grid, cs, half, hs, plan, twiddle, B, skip);
+    else
+      k_fft_x_merge<R><<<g, kThreads, shm, st>>>(half, hs, grid, cs, plan, twiddle, B, skip);
+  } else if (stage == 1 || stage == 3) {
+    int B = 1;
+    while (B * 2 * N <= 1024) B *= 2;
+    const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
+    dim3 g((H * N + B - 1) / B, 6);
+    k_fft_y_half<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, stage == 1 ? -1 : +1, B, skip);
+  } else {
+    int B = 1;
+    while (B * 2 * 6 * N <= 1536) B *= 2;
+    const size_t shm = sizeof(T) * (2 * size_t(6 * B) * N + N);
+    dim3 g((H * N + B - 1) / B);
+    k_fft_z_green<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, wp, B, skip);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -736,7 +1087,8 @@ __device__ inline void sinc_jv(double x, double& s, double& j) {
 }  // namespace
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_green(R* __restrict__ grid, size_t cs, WaveParams wp) {
+__global__ __launch_bounds__(256) void k_green(R* __restrict__ grid, size_t cs, WaveParams wp, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   using T = typename C2<R>::T;
   const int N = wp.n;
   const size_t N3 = size_t(N) * N * N;
@@ -810,25 +1162,29 @@ __global__ __launch_bounds__(256) void k_green(R* __restrict__ grid, size_t cs, 
 }
 
 template <typename R>
-void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st) {
+void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st, const int* skip) {
   const size_t N3 = size_t(wp.n) * wp.n * wp.n;
-  k_green<R><<<nblocks((long long)N3), kThreads, 0, st>>>(grid, comp_stride, wp);
+  k_green<R><<<nblocks((long long)N3), kThreads, 0, st>>>(grid, comp_stride, wp, skip);
 }
 
 // explicit instantiations
-template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t);
-template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t);
+template void launch_wave_fft<double>(double*, double*, const FftPlan&, const double*, const WaveParams&, int,
+                                      hipStream_t, const int*);
+template void launch_wave_fft<float>(float*, float*, const FftPlan&, const float*, const WaveParams&, int,
+                                     hipStream_t, const int*);
+template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t, const int*);
+template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t, const int*);
 template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
-                                      const RealParams&, double*, bool, int, hipStream_t);
+                                      const RealParams&, double*, bool, int, hipStream_t, const int*);
 template void launch_real_sum<float>(int, const double*, const double*, const int*, const uint32_t*, const float*,
-                                     const RealParams&, double*, bool, int, hipStream_t);
-template void launch_spread<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t);
-template void launch_spread<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t);
-template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t);
-template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t);
-template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int);
-template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int);
-template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t);
-template void launch_green_scale<float>(float*, size_t, const WaveParams&, hipStream_t);
+                                     const RealParams&, double*, bool, int, hipStream_t, const int*);
+template void launch_spread<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*);
+template void launch_spread<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t, const int*);
+template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*);
+template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t, const int*);
+template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
+template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
+template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t, const int*);
+template void launch_green_scale<float>(float*, size_t, const WaveParams&, hipStream_t, const int*);
 
 }  // namespace fsd

@@ -12,7 +12,8 @@ inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t);
 // Sigma^T V: rigid velocity of bead i of body j, (U_j + W_j x r_i, W_j), added to
 // y1; its translational part also goes to wt (input of the lubrication product).
 __global__ void k_rigid_velocity(int nb, const int* __restrict__ body, const double4* __restrict__ r4,
-                                 const double* __restrict__ V, double* __restrict__ y1, double* __restrict__ wt) {
+                                 const double* __restrict__ V, double* __restrict__ y1, double* __restrict__ wt, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const int j = body[i];
@@ -36,13 +37,14 @@ __global__ void k_rigid_velocity(int nb, const int* __restrict__ body, const dou
 }
 
 void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1, double* wt,
-                           hipStream_t st) {
-  k_rigid_velocity<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, V, y1, wt);
+                           hipStream_t st, const int* skip) {
+  k_rigid_velocity<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, V, y1, wt, skip);
 }
 
 // f_i = -sum_k R_pair,ik (w_i - w_k), R_pair = X nn + Y (I - nn)
 __global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32_t* __restrict__ col,
-                            const double* __restrict__ coef, const double* __restrict__ wt, double* __restrict__ f) {
+                            const double* __restrict__ coef, const double* __restrict__ wt, double* __restrict__ f, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const double wx = wt[3 * i], wy = wt[3 * i + 1], wz = wt[3 * i + 2];
@@ -63,13 +65,14 @@ __global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32
 }
 
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef, const double* wt, double* f,
-                      hipStream_t st) {
-  k_lub_apply<<<nblocks(nb), kThreads, 0, st>>>(nb, rowptr, col, coef, wt, f);
+                      hipStream_t st, const int* skip) {
+  k_lub_apply<<<nblocks(nb), kThreads, 0, st>>>(nb, rowptr, col, coef, wt, f, skip);
 }
 
 // Sigma (lambda + (f_lub, 0)): per body (sum f, sum t + r x f)
 __global__ void k_agg_reduce(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
-                             const double* __restrict__ lam, const double* __restrict__ flub, double* __restrict__ y2) {
+                             const double* __restrict__ lam, const double* __restrict__ flub, double* __restrict__ y2, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= na) return;
   double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
@@ -99,8 +102,8 @@ __global__ void k_agg_reduce(int na, const int* __restrict__ offsets, const doub
 }
 
 void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam, const double* flub,
-                       double* y2, hipStream_t st) {
-  k_agg_reduce<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, lam, flub, y2);
+                       double* y2, hipStream_t st, const int* skip) {
+  k_agg_reduce<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, lam, flub, y2, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -110,7 +113,8 @@ void launch_agg_reduce(int na, const int* offsets, const double* r4, const doubl
 
 __global__ void k_precond_agg(int nb, int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
                               const double* __restrict__ lu, const int* __restrict__ piv, double drag_t, double drag_r,
-                              const double* __restrict__ r, double* __restrict__ z) {
+                              const double* __restrict__ r, double* __restrict__ z, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= na) return;
   double y[6];
@@ -149,7 +153,8 @@ __global__ void k_precond_agg(int nb, int na, const int* __restrict__ offsets, c
 }
 
 __global__ void k_precond_bead(int nb, const int* __restrict__ body, const double4* __restrict__ r4, double drag_t,
-                               double drag_r, const double* __restrict__ r, double* __restrict__ z) {
+                               double drag_r, const double* __restrict__ r, double* __restrict__ z, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const double* v = z + 6 * size_t(nb) + 6 * body[i];
@@ -166,10 +171,11 @@ __global__ void k_precond_bead(int nb, const int* __restrict__ body, const doubl
 
 void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4, const double* lu,
                           const int* piv, double drag_t, double drag_r, const double* r, double* z, double* tmp_agg,
-                          hipStream_t st) {
+                          hipStream_t st, const int* skip) {
   (void)tmp_agg;
-  k_precond_agg<<<nblocks(na, 128), 128, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z);
-  k_precond_bead<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, drag_t, drag_r, r, z);
+  k_precond_agg<<<nblocks(na, 128), 128, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z,
+                                                   skip);
+  k_precond_bead<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, drag_t, drag_r, r, z, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -279,7 +285,8 @@ int dot_blocks(size_t n) {
 
 __global__ __launch_bounds__(kDotThreads) void k_multi_dot(size_t n, int q0, int nq, const double* __restrict__ V,
                                                            size_t ldv, const double* __restrict__ w,
-                                                           double* __restrict__ partial) {
+                                                           double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double sh[kDotThreads / 64];
   double acc[kDotChunk];
 #pragma unroll
@@ -298,7 +305,8 @@ __global__ __launch_bounds__(kDotThreads) void k_multi_dot(size_t n, int q0, int
 }
 
 __global__ __launch_bounds__(kDotThreads) void k_dot_final(int nblk, const double* __restrict__ partial,
-                                                           double* __restrict__ out) {
+                                                           double* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double sh[kDotThreads / 64];
   const int q = blockIdx.x;
   double v = 0;
@@ -308,16 +316,17 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_final(int nblk, const doubl
 }
 
 void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
-                      hipStream_t st) {
+                      hipStream_t st, const int* skip) {
   const int nb = dot_blocks(n);
   for (int q0 = 0; q0 < nq; q0 += kDotChunk)
-    k_multi_dot<<<nb, kDotThreads, 0, st>>>(n, q0, nq, V, ldv, w, partial);
-  k_dot_final<<<nq, kDotThreads, 0, st>>>(nb, partial, out);
+    k_multi_dot<<<nb, kDotThreads, 0, st>>>(n, q0, nq, V, ldv, w, partial, skip);
+  k_dot_final<<<nq, kDotThreads, 0, st>>>(nb, partial, out, skip);
 }
 
 // w += sgn * sum_q h[q] V_q
 __global__ void k_multi_axpy(size_t n, int nq, const double* __restrict__ V, size_t ldv, const double* __restrict__ h,
-                             double sgn, double* __restrict__ w) {
+                             double sgn, double* __restrict__ w, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0;
@@ -326,20 +335,22 @@ __global__ void k_multi_axpy(size_t n, int nq, const double* __restrict__ V, siz
 }
 
 void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h, double sgn, double* w,
-                       hipStream_t st) {
-  k_multi_axpy<<<nblocks((long long)n), kThreads, 0, st>>>(n, nq, V, ldv, h, sgn, w);
+                       hipStream_t st, const int* skip) {
+  k_multi_axpy<<<nblocks((long long)n), kThreads, 0, st>>>(n, nq, V, ldv, h, sgn, w, skip);
 }
 
 // dst = src / s_dev[0]
 __global__ void k_scale_copy(size_t n, const double* __restrict__ src, const double* __restrict__ s,
-                             double* __restrict__ dst) {
+                             double* __restrict__ dst, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   dst[i] = src[i] / s[0];
 }
 
-void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst, hipStream_t st) {
-  k_scale_copy<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, s_dev, dst);
+void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst, hipStream_t st,
+                       const int* skip) {
+  k_scale_copy<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, s_dev, dst, skip);
 }
 
 __global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -352,6 +363,17 @@ void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipS
   k_axpby<<<nblocks((long long)n), kThreads, 0, st>>>(n, a, x, b, y);
 }
 
+// zero n 32-bit words (used instead of a memset so captured graphs hold kernels only)
+__global__ void k_zero_words(size_t n, uint32_t* __restrict__ p) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  k_zero_words<<<nblocks((long long)n), kThreads, 0, st>>>(n, static_cast<uint32_t*>(p));
+}
+
 __global__ void k_sub(size_t n, const double* __restrict__ b, const double* __restrict__ ax, double* __restrict__ r) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -360,6 +382,114 @@ __global__ void k_sub(size_t n, const double* __restrict__ b, const double* __re
 
 void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st) {
   k_sub<<<nblocks((long long)n), kThreads, 0, st>>>(n, b, ax, r);
+}
+
+// ------------------------------------------------------------------------------------------
+// GMRES cycle control on the device (right-preconditioned GMRES(m), Givens QR of H)
+// ------------------------------------------------------------------------------------------
+
+// start of a cycle: beta = sqrt(rr), g = (beta, 0, ...), scal = 1/beta; stop when the
+// true residual already meets the tolerance or the iteration budget is spent
+__global__ void k_gmres_begin(GmresCtl* ctl, const double* __restrict__ rr, double* __restrict__ g,
+                              double* __restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double beta = sqrt(fmax(rr[0], 0.0));
+  ctl->beta = beta;
+  ctl->resid = ctl->bn > 0 ? beta / ctl->bn : 0.0;
+  ctl->k_used = 0;
+  ctl->breakdown = 0;
+  for (int i = 0; i <= ctl->m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  scal[0] = beta > 0 ? 1.0 / beta : 0.0;
+  ctl->stop = (ctl->resid <= ctl->tol || ctl->its >= ctl->maxit || beta == 0.0) ? 1 : 0;
+}
+
+void launch_gmres_begin(GmresCtl* ctl, const double* rr, double* g, double* scal, hipStream_t st) {
+  k_gmres_begin<<<1, 64, 0, st>>>(ctl, rr, g, scal);
+}
+
+__global__ void k_scale_by(size_t n, const double* __restrict__ src, const double* __restrict__ scal,
+                           double* __restrict__ dst, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[i] * scal[0];
+}
+
+void launch_scale_by(size_t n, const double* src, const double* scal, double* dst, hipStream_t st, const int* skip) {
+  k_scale_by<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, scal, dst, skip);
+}
+
+// Arnoldi step j: H[:, j] = h1 + h2 (classical Gram-Schmidt, twice), H[j+1, j] = ||w||;
+// previous Givens rotations applied, a new one formed, g updated; stop flag raised
+// when |g_{j+1}| / ||b|| <= tol, the cycle is full, the budget is spent, or on breakdown.
+__global__ void k_arnoldi_step(int j, GmresCtl* ctl, const double* __restrict__ h1, const double* __restrict__ h2,
+                               const double* __restrict__ hn2, double* __restrict__ H, double* __restrict__ cs,
+                               double* __restrict__ sn, double* __restrict__ g, double* __restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (ctl->stop) return;
+  const int m = ctl->m;
+  double col[256];
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(fmax(hn2[0], 0.0));
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    const double u = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+    col[i + 1] = u;
+  }
+  const double den = hypot(col[j], hn);
+  const double c = den > 0 ? col[j] / den : 1.0, s = den > 0 ? hn / den : 0.0;
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = den;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = col[i];
+  ctl->k_used = j + 1;
+  ctl->its += 1;
+  ctl->resid = fabs(g[j + 1]) / ctl->bn;
+  if (hn == 0.0) ctl->breakdown = 1;
+  if (ctl->resid <= ctl->tol || j + 1 == m || ctl->its >= ctl->maxit || hn == 0.0) ctl->stop = 1;
+  scal[0] = hn > 0 ? 1.0 / hn : 0.0;
+}
+
+void launch_arnoldi_step(int j, GmresCtl* ctl, const double* h1, const double* h2, const double* hn2, double* H,
+                         double* cs, double* sn, double* g, double* scal, hipStream_t st) {
+  k_arnoldi_step<<<1, 64, 0, st>>>(j, ctl, h1, h2, hn2, H, cs, sn, g, scal);
+}
+
+// y = R^-1 g over the k_used leading rows of the rotated Hessenberg matrix
+__global__ void k_gmres_solve(const GmresCtl* ctl, const double* __restrict__ H, const double* __restrict__ g,
+                              double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k = ctl->k_used, m = ctl->m;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int q = i + 1; q < k; ++q) t -= H[size_t(i) * m + q] * y[q];
+    y[i] = t / H[size_t(i) * m + i];
+  }
+}
+
+void launch_gmres_solve(const GmresCtl* ctl, const double* H, const double* g, double* y, hipStream_t st) {
+  k_gmres_solve<<<1, 64, 0, st>>>(ctl, H, g, y);
+}
+
+// out = sum_{q < k_used} y_q V_q
+__global__ void k_basis_combine(size_t n, const double* __restrict__ V, size_t ldv, const double* __restrict__ y,
+                                const GmresCtl* __restrict__ ctl, double* __restrict__ out) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = ctl->k_used;
+  double s = 0;
+  for (int q = 0; q < k; ++q) s += y[q] * V[size_t(q) * ldv + i];
+  out[i] = s;
+}
+
+void launch_basis_combine(size_t n, int m, const double* V, size_t ldv, const double* y, const GmresCtl* ctl,
+                          double* out, hipStream_t st) {
+  (void)m;
+  k_basis_combine<<<nblocks((long long)n), kThreads, 0, st>>>(n, V, ldv, y, ctl, out);
 }
 
 }  // namespace fsd

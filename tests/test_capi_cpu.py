@@ -12,8 +12,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def F():
     lib = os.path.join(ROOT, "paper_2607_25161_amd", "libfsd.so")
     if not os.path.exists(lib):
-        from paper_2607_25161_amd.build import build
-        build(verbose=False)
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("_fsd_build", os.path.join(ROOT, "paper_2607_25161_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build(verbose=False)
     import paper_2607_25161_amd as F
     return F
 

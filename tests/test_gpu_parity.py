@@ -239,6 +239,25 @@ def test_bead_forces_project_like_sigma(F):
     assert max(_vel_errors(U, Uo)) < 1e-8
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_match_eager(F, precision):
+    # captured GMRES graphs replayed several times, with eager work and synchronisation
+    # between replays; every replay must reproduce the eager solve
+    kw = _cluster_system(seed=21)
+    s = _make(F, kw, precision=precision, gmres_tol=1e-9, ewald_tol=1e-8)
+    s.set_graphs(False)
+    U_e, _, inf_e = s.solve()
+    s.set_graphs(True, 3)
+    x = np.random.default_rng(22).normal(size=6 * (int(kw["offsets"][-1]) + len(kw["offsets"]) - 1))
+    for rep in range(4):
+        U_g, _, inf_g = s.solve()
+        assert np.abs(U_g - U_e).max() <= 1e-12 * np.abs(U_e).max(), rep
+        assert inf_g.iterations == inf_e.iterations
+        s.apply_saddle(x)          # eager work between replays
+        s.set_timing(rep % 2 == 0)  # alternate captured timing nodes on and off
+    s.set_timing(False)
+
+
 # ---------------------------------------------------------------------------------------
 # full-size workloads against stored oracle values
 # ---------------------------------------------------------------------------------------
