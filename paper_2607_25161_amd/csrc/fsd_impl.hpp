@@ -92,9 +92,11 @@ hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WavePara
 template <typename R>
 void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid,
                           hipStream_t st, const int* skip = nullptr);
+// out += interpolated grid velocities; with V != nullptr also += Sigma^T V (rigid velocities)
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
-                   hipStream_t st, const int* skip = nullptr);
+                   hipStream_t st, const int* skip = nullptr, const int* body = nullptr,
+                   const double* r4 = nullptr, const double* V = nullptr);
 
 // ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
 void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1,
@@ -106,6 +108,14 @@ void launch_agg_reduce(int na, const int* offsets, const double* r4, const doubl
 void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4,
                           const double* lu, const int* piv, double drag_t, double drag_r,
                           const double* r, double* z, double* tmp_agg, hipStream_t st,
+                          const int* skip = nullptr);
+// fused: y2 = Sigma (lambda - R_nf Sigma^T V) with lubrication evaluated on the fly
+// (lrow == nullptr: no lubrication)
+void launch_agg_lub(int na, const int* offsets, const int* body, const double* r4, const double* lam,
+                    const double* V, const int* lrow, const uint32_t* lcol, const double* coef, double* y2,
+                    hipStream_t st, const int* skip = nullptr);
+void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
+                          double drag_t, double drag_r, const double* r, double* z, hipStream_t st,
                           const int* skip = nullptr);
 void launch_rhs(int nb, int na, const int* offsets, const int* body, const double* r4,
                 const double* E, const double* force, const double* fnf, double* b1, double* e3,
@@ -141,6 +151,13 @@ void launch_basis_combine(size_t n, int m, const double* V, size_t ldv, const do
 int dot_blocks(size_t n);
 void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w,
                       double* partial, double* out, hipStream_t st, const int* skip = nullptr);
+// one-launch CGS kernels (counters: zeroed device tickets, one per chunk of 8 vectors)
+void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
+                 unsigned* counters, hipStream_t st, const int* skip = nullptr);
+// w -= V h; then mode 0: out[q] = V_q . w (q < nq), mode 1: out[0] = w . w
+void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
+                      double* partial, double* out, unsigned* counters, hipStream_t st,
+                      const int* skip = nullptr);
 void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h,
                        double sgn, double* w, hipStream_t st, const int* skip = nullptr);
 void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst,

@@ -191,6 +191,9 @@ struct fsd_system {
   fsd_params p{};
   hipStream_t st = nullptr;
   bool own_stream = false;
+  hipStream_t st2 = nullptr;           // side stream: the real-space sum overlaps the wave space
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  unsigned* d_counters = nullptr;      // tickets of the one-launch reductions
   int device = 0;
   std::string err;
 
@@ -280,6 +283,11 @@ struct fsd_system {
   ~fsd_system() { release(); }
   void release() {
     drop_graphs();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st2) (void)hipStreamDestroy(st2);
+    ev_fork = ev_join = nullptr;
+    st2 = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     if (nw) neighbor_work_destroy(nw);
@@ -603,15 +611,26 @@ const float* twiddle_of<float>(fsd_system* s) {
   return s->d_tw32;
 }
 
-// out = M lam (parts: 1 real space, 2 wave space)
+// out = M lam (parts: 1 real space, 2 wave space); with Vr != nullptr the rigid
+// velocities Sigma^T Vr are added in the interpolation kernel.  Untimed, the
+// real-space sum runs on the side stream, overlapping spreading and the transforms.
 template <typename R>
-void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, const int* skip = nullptr) {
+void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, const int* skip = nullptr,
+                    const double* Vr = nullptr) {
+  const bool fork = (parts & 1) && (parts & 2) && !s->timing;
   if (parts & 1) {
+    hipStream_t rs = s->st;
+    if (fork) {
+      HIPCHK(hipEventRecord(s->ev_fork, s->st));
+      HIPCHK(hipStreamWaitEvent(s->st2, s->ev_fork, 0));
+      rs = s->st2;
+    }
     Timed t(s, FSD_TIMER_REAL);
-    launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr,
-                       s->st, skip);
+    launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr, rs,
+                       skip);
+    if (fork) HIPCHK(hipEventRecord(s->ev_join, s->st2));
   } else {
-    HIPCHK(hipMemsetAsync(out, 0, sizeof(double) * 6 * s->nb, s->st));
+    launch_zero(out, sizeof(double) * 6 * s->nb, s->st);
   }
   if (parts & 2) {
     const int N = s->wp.n;
@@ -623,38 +642,30 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
     } else {
       launch_zero(grid, sizeof(R) * 3 * cs, s->st);
       Timed t(s, FSD_TIMER_SPREAD);
-      launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st);
+      launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
     }
     R* half = static_cast<R*>(s->d_half);
     for (int stage = 0; stage < 5; ++stage) {
       Timed t(s, stage == 2 ? FSD_TIMER_GREEN : FSD_TIMER_FFT);
       launch_wave_fft<R>(grid, half, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
     }
-    {
-      Timed t(s, FSD_TIMER_INTERP);
-      launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip);
-    }
+    if (fork) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
+    Timed t(s, FSD_TIMER_INTERP);
+    launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr);
   }
 }
 
-// y = A x for the saddle matrix [[M, Sigma^T], [Sigma, -Sigma R_nf Sigma^T]]
+// y = A x for the saddle matrix [[M, Sigma^T], [Sigma, -Sigma R_nf Sigma^T]]:
+// y1 = M lambda + Sigma^T V (rigid part added during interpolation),
+// y2 = Sigma (lambda - R_nf Sigma^T V) (lubrication evaluated inside the reduction)
 template <typename R>
 void apply_saddle(fsd_system* s, const double* x, double* y, const int* skip = nullptr) {
   const size_t nb6 = 6 * size_t(s->nb);
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
-  apply_mobility<R>(s, x, y, 3, skip);
-  {
-    Timed t(s, FSD_TIMER_RIGID);
-    launch_rigid_velocity(s->nb, s->d_body, s->d_r4, x + nb6, y, lub ? s->d_wt : nullptr, s->st, skip);
-  }
-  if (lub) {
-    Timed t(s, FSD_TIMER_LUB);
-    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st, skip);
-  }
-  {
-    Timed t(s, FSD_TIMER_RIGID);
-    launch_agg_reduce(s->na, s->d_offsets, s->d_r4, x, lub ? s->d_fl : nullptr, y + nb6, s->st, skip);
-  }
+  apply_mobility<R>(s, x, y, 3, skip, x + nb6);
+  Timed t(s, FSD_TIMER_RIGID);
+  launch_agg_lub(s->na, s->d_offsets, s->d_body, s->d_r4, x, x + nb6, lub ? s->d_lrow : nullptr, s->d_lcol,
+                 s->d_lcoef, y + nb6, s->st, skip);
 }
 
 void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32, const int* skip = nullptr) {
@@ -667,8 +678,8 @@ void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32, const 
 void apply_precond(fsd_system* s, const double* r, double* z, const int* skip = nullptr) {
   Timed t(s, FSD_TIMER_PRECOND);
   // M~^-1 = diag(6 pi eta a, 8 pi eta a^3): the bead drag (inverse self-mobility)
-  launch_precond_apply(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, r,
-                       z, nullptr, s->st, skip);
+  launch_precond_fused(s->nb, s->na, s->d_offsets, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, r, z, s->st,
+                       skip);
 }
 
 void assemble_rhs(fsd_system* s) {
@@ -681,7 +692,7 @@ void assemble_rhs(fsd_system* s) {
 
 // ||v||^2 and similar small reductions land in s->h_small after a sync
 double norm2(fsd_system* s, const double* v) {
-  launch_multi_dot(s->n, 1, v, s->n, v, s->d_part, s->d_h, s->st);
+  launch_dots(s->n, 1, v, s->n, v, s->d_part, s->d_h, s->d_counters, s->st);
   HIPCHK(hipMemcpyAsync(s->h_small, s->d_h, sizeof(double), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   return std::sqrt(s->h_small[0]);
@@ -729,7 +740,7 @@ GmresOut gmres(fsd_system* s, const double* b, double* x, double tol, bool fp32,
     GraphEntry* e0 = run_body(s, {0, 0, 0, prec, b, x}, [&] {
       apply_saddle_p(s, x, s->d_t, fp32);
       launch_sub(n, b, s->d_t, s->d_r, s->st);
-      launch_multi_dot(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->st);
+      launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->d_counters, s->st);
       launch_gmres_begin(s->d_ctl, hn2, s->d_g, s->d_scal, s->st);
       launch_scale_by(n, s->d_r, s->d_scal, V, s->st, stop);
     });
@@ -753,11 +764,9 @@ GmresOut gmres(fsd_system* s, const double* b, double* x, double tol, bool fp32,
           apply_precond(s, V + size_t(j) * n, s->d_z, stop);
           apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
           Timed t(s, FSD_TIMER_KRYLOV);  // CGS2 + Givens
-          launch_multi_dot(n, j + 1, V, n, s->d_w, s->d_part, h1, s->st, stop);
-          launch_multi_axpy(n, j + 1, V, n, h1, -1.0, s->d_w, s->st, stop);
-          launch_multi_dot(n, j + 1, V, n, s->d_w, s->d_part, h2, s->st, stop);
-          launch_multi_axpy(n, j + 1, V, n, h2, -1.0, s->d_w, s->st, stop);
-          launch_multi_dot(n, 1, s->d_w, n, s->d_w, s->d_part, hn2, s->st, stop);
+          launch_dots(n, j + 1, V, n, s->d_w, s->d_part, h1, s->d_counters, s->st, stop);
+          launch_axpy_dots(n, j + 1, V, n, h1, s->d_w, 0, s->d_part, h2, s->d_counters, s->st, stop);
+          launch_axpy_dots(n, j + 1, V, n, h2, s->d_w, 1, s->d_part, hn2, s->d_counters, s->st, stop);
           launch_arnoldi_step(j, s->d_ctl, h1, h2, hn2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal, s->st);
           launch_scale_by(n, s->d_w, s->d_scal, V + size_t(j + 1) * n, s->st, stop);
         }
@@ -989,6 +998,11 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_g = dalloc<double>(o, s->m + 1);
     s->d_y = dalloc<double>(o, s->m);
     s->d_scal = dalloc<double>(o, 2);
+    s->d_counters = reinterpret_cast<unsigned*>(dalloc<int>(o, 64));
+    HIPCHK(hipMemset(s->d_counters, 0, 64 * sizeof(int)));
+    HIPCHK(hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     s->nw = neighbor_work_create(nb);
     if (!s->nw) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
     s->spread = spread_plan_create(nb, s->wp.n, s->wp.support);  // nullptr: grid not a multiple of 4

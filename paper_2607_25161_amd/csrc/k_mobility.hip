@@ -231,8 +231,11 @@ void launch_spread(int nb, const double* pos4, const double* lam, const WavePara
 template <typename R>
 __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restrict__ pos,
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
-                                                double* __restrict__ out, const int* __restrict__ skip) {
+                                                double* __restrict__ out, const int* __restrict__ skip,
+                                                const int* __restrict__ body, const double4* __restrict__ r4,
+                                                const double* __restrict__ V) {
   if (skip && *skip) return;
+  // one wavefront per bead
   __shared__ R wts[4][3 * kMaxP];
   __shared__ int sta[4][3];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -268,21 +271,28 @@ __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restric
   a4 = wave_sum(a4);
   a5 = wave_sum(a5);
   if (lane == 0) {
-    double* o = out + 6 * i;
-    o[0] += double(a0);
-    o[1] += double(a1);
-    o[2] += double(a2);
-    o[3] += double(a3);
-    o[4] += double(a4);
-    o[5] += double(a5);
+    double* o = out + 6 * size_t(i);
+    double add[6] = {double(a0), double(a1), double(a2), double(a3), double(a4), double(a5)};
+    if (V) {  // Sigma^T V: (U + W x r, W) of the bead's body
+      const double* v = V + 6 * body[i];
+      const double4 r = r4[i];
+      add[0] += v[0] + (v[4] * r.z - v[5] * r.y);
+      add[1] += v[1] + (v[5] * r.x - v[3] * r.z);
+      add[2] += v[2] + (v[3] * r.y - v[4] * r.x);
+      add[3] += v[3];
+      add[4] += v[4];
+      add[5] += v[5];
+    }
+    for (int k = 0; k < 6; ++k) o[k] += add[k];
   }
 }
 
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st,
-                   const int* skip) {
+                   const int* skip, const int* body, const double* r4, const double* V) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
-  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out, skip);
+  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out, skip, body,
+                                                   (const double4*)r4, V);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -439,77 +449,98 @@ __global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restr
                                                                const int4* __restrict__ starts,
                                                                const R* __restrict__ weights,
                                                                const double* __restrict__ lam, WaveParams wp,
-                                                               int nbin, int K, R* __restrict__ grid, size_t cs, const int* __restrict__ skip) {
+                                                               int nbin, int K, R* __restrict__ grid, size_t cs,
+                                                               const int* __restrict__ skip) {
   if (skip && *skip) return;
+  constexpr int NT = BS * BS * BS;
   __shared__ int4 sh_s[kChunk];
   __shared__ R sh_w[kChunk * 3 * kMaxP];
   __shared__ R sh_l[kChunk * 6];
+  __shared__ int rb0[2 * 8 * 8], rlen[2 * 8 * 8], roff[2 * 8 * 8 + 1];
   const int P = wp.support, N = wp.n, P3 = 3 * P;
   const int bx = blockIdx.x % nbin, by = (blockIdx.x / nbin) % nbin, bz = blockIdx.x / (nbin * nbin);
   const int t = threadIdx.x;
   const int mx = bx * BS + t % BS, my = by * BS + (t / BS) % BS, mz = bz * BS + t / (BS * BS);
+  // candidate beads: per (kz, ky) one or two contiguous runs of the sorted bead array
+  // (bins bx-K+1 .. bx along x, split where they wrap); thread r computes run r
+  const int x0 = bx - K + 1;
+  const int nparts = x0 >= 0 ? 1 : 2;
+  const int nruns = K * K * nparts;
+  for (int rr = t; rr < nruns; rr += NT) {
+    const int part = rr % nparts, ky = (rr / nparts) % K, kz = rr / (nparts * K);
+    const int cz = (bz - kz + nbin) % nbin, cy = (by - ky + nbin) % nbin;
+    int lo, hi;
+    if (x0 >= 0) {
+      lo = x0;
+      hi = bx;
+    } else if (part == 0) {
+      lo = 0;
+      hi = bx;
+    } else {
+      lo = x0 + nbin;
+      hi = nbin - 1;
+    }
+    const int row = (cz * nbin + cy) * nbin;
+    int b0 = 0, b1 = 0;
+    bool any = false;
+    for (int c = lo; c <= hi; ++c) {
+      const int e0 = bin_start[row + c], e1 = bin_end[row + c];
+      if (e1 > e0) {
+        if (!any) b0 = e0;
+        b1 = e1;
+        any = true;
+      }
+    }
+    rb0[rr] = b0;
+    rlen[rr] = any ? b1 - b0 : 0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int r = 0; r < nruns; ++r) {
+      roff[r] = acc;
+      acc += rlen[r];
+    }
+    roff[nruns] = acc;
+  }
+  __syncthreads();
+  const int total = roff[nruns];
   R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-  for (int kz = 0; kz < K; ++kz) {
-    const int cz = (bz - kz + nbin) % nbin;
-    for (int ky = 0; ky < K; ++ky) {
-      const int cy = (by - ky + nbin) % nbin;
-      // bins bx-K+1 .. bx along x are consecutive in the sorted order unless they wrap
-      const int x0 = bx - K + 1;
-      for (int part = 0; part < 2; ++part) {
-        int lo, hi;  // inclusive bin range along x
-        if (x0 >= 0) {
-          if (part == 1) break;
-          lo = x0;
-          hi = bx;
-        } else if (part == 0) {
-          lo = 0;
-          hi = bx;
-        } else {
-          lo = x0 + nbin;
-          hi = nbin - 1;
-        }
-        const int row = (cz * nbin + cy) * nbin;
-        // first non-empty start / last end over the range
-        int b0 = 0, b1 = 0;
-        bool any = false;
-        for (int c = lo; c <= hi; ++c) {
-          const int e0 = bin_start[row + c], e1 = bin_end[row + c];
-          if (e1 > e0) {
-            if (!any) b0 = e0;
-            b1 = e1;
-            any = true;
-          }
-        }
-        if (!any) continue;
-        for (int c0 = b0; c0 < b1; c0 += kChunk) {
-          const int n = min(kChunk, b1 - c0);
-          __syncthreads();
-          for (int q = t; q < n * P3; q += BS * BS * BS) sh_w[q] = weights[size_t(c0) * P3 + q];
-          for (int q = t; q < n; q += BS * BS * BS) {
-            sh_s[q] = starts[c0 + q];
-            const double* l = lam + 6 * size_t(perm[c0 + q]);
-            for (int c = 0; c < 6; ++c) sh_l[6 * q + c] = R(l[c]);
-          }
-          __syncthreads();
-          for (int q = 0; q < n; ++q) {
-            const int4 s = sh_s[q];
-            int ix = mx - s.x, iy = my - s.y, iz = mz - s.z;
-            ix += ix < 0 ? N : 0;
-            iy += iy < 0 ? N : 0;
-            iz += iz < 0 ? N : 0;
-            if (ix < P && iy < P && iz < P) {
-              const R* wq = sh_w + q * P3;
-              const R w = wq[ix] * wq[P + iy] * wq[2 * P + iz];
-              const R* l = sh_l + 6 * q;
-              a0 += w * l[0];
-              a1 += w * l[1];
-              a2 += w * l[2];
-              a3 += w * l[3];
-              a4 += w * l[4];
-              a5 += w * l[5];
-            }
-          }
-        }
+  for (int c0 = 0; c0 < total; c0 += kChunk) {
+    const int n = min(kChunk, total - c0);
+    if (c0 > 0) __syncthreads();
+    // stage candidates c0 .. c0+n-1 (run-major order) in LDS
+    for (int q = t; q < n * (P3 + 7); q += NT) {
+      const int cand = q / (P3 + 7), f = q % (P3 + 7);
+      const int gidx = c0 + cand;
+      int r = 0;
+      while (roff[r + 1] <= gidx) ++r;
+      const int k = rb0[r] + (gidx - roff[r]);
+      if (f < P3) {
+        sh_w[cand * P3 + f] = weights[size_t(k) * P3 + f];
+      } else if (f == P3) {
+        sh_s[cand] = starts[k];
+      } else {
+        sh_l[6 * cand + (f - P3 - 1)] = R(lam[6 * size_t(perm[k]) + (f - P3 - 1)]);
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < n; ++q) {
+      const int4 s = sh_s[q];
+      int ix = mx - s.x, iy = my - s.y, iz = mz - s.z;
+      ix += ix < 0 ? N : 0;
+      iy += iy < 0 ? N : 0;
+      iz += iz < 0 ? N : 0;
+      if (ix < P && iy < P && iz < P) {
+        const R* wq = sh_w + q * P3;
+        const R w = wq[ix] * wq[P + iy] * wq[2 * P + iz];
+        const R* l = sh_l + 6 * q;
+        a0 += w * l[0];
+        a1 += w * l[1];
+        a2 += w * l[2];
+        a3 += w * l[3];
+        a4 += w * l[4];
+        a5 += w * l[5];
       }
     }
   }
@@ -1180,8 +1211,10 @@ template void launch_real_sum<float>(int, const double*, const double*, const in
                                      const RealParams&, double*, bool, int, hipStream_t, const int*);
 template void launch_spread<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*);
 template void launch_spread<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t, const int*);
-template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*);
-template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t, const int*);
+template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*,
+                                    const int*, const double*, const double*);
+template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t, const int*,
+                                   const int*, const double*, const double*);
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t, const int*);

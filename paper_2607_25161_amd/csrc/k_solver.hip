@@ -277,7 +277,7 @@ __device__ inline double block_sum(double v, double* sh) {
 }  // namespace
 
 int dot_blocks(size_t n) {
-  long long b = (long long)((n + kDotThreads * 4 - 1) / (kDotThreads * 4));
+  long long b = (long long)((n + kDotThreads - 1) / kDotThreads);
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   return int(b);
@@ -490,6 +490,268 @@ void launch_basis_combine(size_t n, int m, const double* V, size_t ldv, const do
                           double* out, hipStream_t st) {
   (void)m;
   k_basis_combine<<<nblocks((long long)n), kThreads, 0, st>>>(n, V, ldv, y, ctl, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// fused bead/aggregate kernels: one wavefront per aggregate
+// ------------------------------------------------------------------------------------------
+
+namespace {
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+}  // namespace
+
+// y2_j = Sigma_j (lambda + f_lub) with f_lub,i = -sum_k R_ik (u_i - u_k) and u the rigid
+// translational velocities of V (neighbour velocities rebuilt from V and body vectors)
+__global__ __launch_bounds__(256) void k_agg_lub(int na, const int* __restrict__ offsets, const int* __restrict__ body,
+                                                 const double4* __restrict__ r4, const double* __restrict__ lam,
+                                                 const double* __restrict__ V, const int* __restrict__ lrow,
+                                                 const uint32_t* __restrict__ lcol, const double* __restrict__ coef,
+                                                 double* __restrict__ y2, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= na) return;
+  double F0 = 0, F1 = 0, F2 = 0, T0 = 0, T1 = 0, T2 = 0;
+  for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
+    const double* l = lam + 6 * size_t(i);
+    double fx = l[0], fy = l[1], fz = l[2];
+    const double4 r = r4[i];
+    if (lrow) {
+      const double* v = V + 6 * j;
+      const double ux = v[0] + (v[4] * r.z - v[5] * r.y);
+      const double uy = v[1] + (v[5] * r.x - v[3] * r.z);
+      const double uz = v[2] + (v[3] * r.y - v[4] * r.x);
+      for (int e = lrow[i]; e < lrow[i + 1]; ++e) {
+        const int k = int(lcol[e] & 0x3FFFFFu);
+        const double* vk = V + 6 * body[k];
+        const double4 rk = r4[k];
+        const double dx = ux - (vk[0] + (vk[4] * rk.z - vk[5] * rk.y));
+        const double dy = uy - (vk[1] + (vk[5] * rk.x - vk[3] * rk.z));
+        const double dz = uz - (vk[2] + (vk[3] * rk.y - vk[4] * rk.x));
+        const double* c = coef + 5 * size_t(e);
+        const double nd = c[2] * dx + c[3] * dy + c[4] * dz;
+        const double g = (c[0] - c[1]) * nd;
+        fx -= c[1] * dx + g * c[2];
+        fy -= c[1] * dy + g * c[3];
+        fz -= c[1] * dz + g * c[4];
+      }
+    }
+    F0 += fx;
+    F1 += fy;
+    F2 += fz;
+    T0 += l[3] + (r.y * fz - r.z * fy);
+    T1 += l[4] + (r.z * fx - r.x * fz);
+    T2 += l[5] + (r.x * fy - r.y * fx);
+  }
+  F0 = wsum(F0);
+  F1 = wsum(F1);
+  F2 = wsum(F2);
+  T0 = wsum(T0);
+  T1 = wsum(T1);
+  T2 = wsum(T2);
+  if (lane == 0) {
+    double* y = y2 + 6 * size_t(j);
+    y[0] = F0;
+    y[1] = F1;
+    y[2] = F2;
+    y[3] = T0;
+    y[4] = T1;
+    y[5] = T2;
+  }
+}
+
+void launch_agg_lub(int na, const int* offsets, const int* body, const double* r4, const double* lam,
+                    const double* V, const int* lrow, const uint32_t* lcol, const double* coef, double* y2,
+                    hipStream_t st, const int* skip) {
+  k_agg_lub<<<(na + 3) / 4, 256, 0, st>>>(na, offsets, body, (const double4*)r4, lam, V, lrow, lcol, coef, y2, skip);
+}
+
+// preconditioner in one launch: the wavefront of aggregate j reduces y2 = r2 - Sigma M~^-1 r1
+// over its beads, solves z2 = -A_j^-1 y2 in lane 0, and writes z1 = M~^-1 (r1 - Sigma^T z2)
+__global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int* __restrict__ offsets,
+                                                       const double4* __restrict__ r4, const double* __restrict__ lu,
+                                                       const int* __restrict__ piv, double drag_t, double drag_r,
+                                                       const double* __restrict__ r, double* __restrict__ z,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= na) return;
+  double p[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
+    const double* l = r + 6 * size_t(i);
+    const double fx = drag_t * l[0], fy = drag_t * l[1], fz = drag_t * l[2];
+    const double4 rv = r4[i];
+    p[0] += fx;
+    p[1] += fy;
+    p[2] += fz;
+    p[3] += drag_r * l[3] + (rv.y * fz - rv.z * fy);
+    p[4] += drag_r * l[4] + (rv.z * fx - rv.x * fz);
+    p[5] += drag_r * l[5] + (rv.x * fy - rv.y * fx);
+  }
+  double y[6];
+  const double* r2 = r + 6 * size_t(nb) + 6 * j;
+  for (int c = 0; c < 6; ++c) y[c] = r2[c] - wsum(p[c]);
+  // every lane solves the same 6x6 system (uniform work, no broadcast needed)
+  const double* A = lu + 36 * size_t(j);
+  const int* pv = piv + 6 * size_t(j);
+  for (int k = 0; k < 6; ++k) {
+    const int q = pv[k];
+    if (q != k) {
+      const double t = y[k];
+      y[k] = y[q];
+      y[q] = t;
+    }
+  }
+  for (int a = 1; a < 6; ++a)
+    for (int b = 0; b < a; ++b) y[a] -= A[6 * a + b] * y[b];
+  for (int a = 5; a >= 0; --a) {
+    for (int b = a + 1; b < 6; ++b) y[a] -= A[6 * a + b] * y[b];
+    y[a] /= A[6 * a + a];
+  }
+  for (int c = 0; c < 6; ++c) y[c] = -y[c];  // z2
+  if (lane == 0) {
+    double* z2 = z + 6 * size_t(nb) + 6 * j;
+    for (int c = 0; c < 6; ++c) z2[c] = y[c];
+  }
+  for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
+    const double4 rv = r4[i];
+    const double* l = r + 6 * size_t(i);
+    double* o = z + 6 * size_t(i);
+    o[0] = drag_t * (l[0] - (y[0] + (y[4] * rv.z - y[5] * rv.y)));
+    o[1] = drag_t * (l[1] - (y[1] + (y[5] * rv.x - y[3] * rv.z)));
+    o[2] = drag_t * (l[2] - (y[2] + (y[3] * rv.y - y[4] * rv.x)));
+    o[3] = drag_r * (l[3] - y[3]);
+    o[4] = drag_r * (l[4] - y[4]);
+    o[5] = drag_r * (l[5] - y[5]);
+  }
+}
+
+void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
+                          double drag_t, double drag_r, const double* r, double* z, hipStream_t st, const int* skip) {
+  k_precond_fused<<<(na + 3) / 4, 256, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z,
+                                                 skip);
+}
+
+// ------------------------------------------------------------------------------------------
+// fused CGS2 kernels: one launch each, the last block to finish reduces the per-block
+// partial sums in block order (deterministic) and resets its ticket counter
+// ------------------------------------------------------------------------------------------
+
+namespace {
+// block-level sums of `cnt` (<= 8) per-thread values; result valid in thread 0
+__device__ inline void block_sums8(double* acc, int cnt, double* sh /* [8][kDotThreads/64] */) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int c = 0; c < cnt; ++c) {
+    double v = acc[c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (l == 0) sh[c * (kDotThreads / 64) + w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < cnt; ++c) {
+      double t = 0;
+      for (int k = 0; k < kDotThreads / 64; ++k) t += sh[c * (kDotThreads / 64) + k];
+      acc[c] = t;
+    }
+  __syncthreads();
+}
+
+// partial[q * G + block] are complete for q in [q0, q0 + cnt): the last block reduces them
+__device__ inline void finish_dots(int q0, int cnt, const double* __restrict__ partial, double* __restrict__ out,
+                                   unsigned* counter, double* sh) {
+  __shared__ int last;
+  __threadfence();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[kDotChunk];
+  for (int c = 0; c < cnt; ++c) {
+    double v = 0;
+    for (int b = threadIdx.x; b < int(gridDim.x); b += blockDim.x) v += partial[size_t(q0 + c) * gridDim.x + b];
+    acc[c] = v;
+  }
+  block_sums8(acc, cnt, sh);
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < cnt; ++c) out[q0 + c] = acc[c];
+    *counter = 0u;
+  }
+}
+}  // namespace
+
+// h[q] = V_q . w, q < nq (blockIdx.y selects a chunk of 8 basis vectors)
+__global__ __launch_bounds__(kDotThreads) void k_dots(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                      const double* __restrict__ w, double* __restrict__ partial,
+                                                      double* __restrict__ out, unsigned* counters,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[kDotChunk * (kDotThreads / 64)];
+  const int q0 = blockIdx.y * kDotChunk, cnt = min(kDotChunk, nq - q0);
+  double acc[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) acc[c] = 0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (c < cnt) acc[c] += V[size_t(q0 + c) * ldv + i] * wi;
+  }
+  block_sums8(acc, cnt, sh);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < cnt; ++c) partial[size_t(q0 + c) * gridDim.x + blockIdx.x] = acc[c];
+  finish_dots(q0, cnt, partial, out, counters + blockIdx.y, sh);
+}
+
+// w -= sum_q h[q] V_q, then (mode 0) out[q] = V_q . w for q < nq, or (mode 1) out[0] = w . w
+__global__ __launch_bounds__(kDotThreads) void k_axpy_dots(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                           const double* __restrict__ h, double* __restrict__ w,
+                                                           int mode, double* __restrict__ partial,
+                                                           double* __restrict__ out, unsigned* counters,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[kDotChunk * (kDotThreads / 64)];
+  // the update is element-local, so each thread updates the elements it later reduces
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    double s = 0;
+    for (int q = 0; q < nq; ++q) s += h[q] * V[size_t(q) * ldv + i];
+    w[i] -= s;
+  }
+  const int nout = mode == 0 ? nq : 1;
+  for (int q0 = 0; q0 < nout; q0 += kDotChunk) {
+    const int cnt = min(kDotChunk, nout - q0);
+    double acc[kDotChunk];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c) acc[c] = 0;
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+      const double wi = w[i];
+      if (mode == 0) {
+#pragma unroll
+        for (int c = 0; c < kDotChunk; ++c)
+          if (c < cnt) acc[c] += V[size_t(q0 + c) * ldv + i] * wi;
+      } else {
+        acc[0] += wi * wi;
+      }
+    }
+    block_sums8(acc, cnt, sh);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < cnt; ++c) partial[size_t(q0 + c) * gridDim.x + blockIdx.x] = acc[c];
+    finish_dots(q0, cnt, partial, out, counters + q0 / kDotChunk, sh);
+  }
+}
+
+void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
+                 unsigned* counters, hipStream_t st, const int* skip) {
+  dim3 g(dot_blocks(n), (nq + kDotChunk - 1) / kDotChunk);
+  k_dots<<<g, kDotThreads, 0, st>>>(n, nq, V, ldv, w, partial, out, counters, skip);
+}
+
+void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
+                      double* partial, double* out, unsigned* counters, hipStream_t st, const int* skip) {
+  k_axpy_dots<<<dot_blocks(n), kDotThreads, 0, st>>>(n, nq, V, ldv, h, w, mode, partial, out, counters, skip);
 }
 
 }  // namespace fsd
