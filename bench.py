@@ -63,6 +63,120 @@ def cpu_baseline(precision_note):
                       f"same generator) in {dt:.1f} s; {precision_note}"}
 
 
+def bench_batched(args, F, fsdgen, torch):
+    """Uneven systems: one-at-a-time plain FP64 vs the mixed-precision batch."""
+    systems = fsdgen.uneven_systems(n_sys=args.systems)
+    n_tot = sum(s.n_bead for s in systems)
+
+    def run_plain(steps):
+        sys_ = [F.System.from_suspension(s0) for s0 in systems]
+        for s in sys_:          # warm-up: graphs captured, lists sized
+            s.step(s0.dt if False else 1e-3, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok = 0
+        for _ in range(steps):
+            for s in sys_:
+                info = s.step(1e-3, 1)
+                ok += s.n_bead if info.rel_residual_fp64 <= 1e-5 else 0
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        for s in sys_:
+            s.close()
+        return ok / dt_, dt_ / steps
+
+    def run_batch(steps, precision):
+        sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+        b = F.Batch(1 << 40, len(sys_))
+        slots = [b.admit(s) for s in sys_]
+        for _ in range(args.warmup):
+            b.step(1e-3)
+        torch.cuda.synchronize()
+        lat = []
+        ok = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter()
+            b.step(1e-3)
+            lat.append(time.perf_counter() - a)
+            for k, sl in enumerate(slots):
+                inf = b.info(sl)
+                ok += sys_[k].n_bead if (inf.status == 0 and inf.rel_residual_fp64 <= 1e-5) else 0
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        b.close()
+        for s in sys_:
+            s.close()
+        return ok / dt_, dt_ / steps, lat
+
+    plain, plain_step = run_plain(max(1, args.steps // 2))
+    b64, b64_step, _ = run_batch(args.steps, F.FSD_FP64)
+    value, step_s, lat = run_batch(args.steps, F.FSD_MIXED)
+    grids = sorted({int(F.System.from_suspension(systems[k]).info().grid) for k in range(0, len(systems), 8)})
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "bead-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * step_s, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads, "
+                               f"phi 0.02-0.25, xi = 25/L, tol 1e-5", "n_bead_total": n_tot,
+                   "grids_sampled": grids, "precision": "mixed", "parallelism": "single GPU, one stream per system"},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "plain_fp64_one_at_a_time": {"value": round(plain, 1), "ms_per_step": round(1e3 * plain_step, 3)},
+        "batched_fp64": {"value": round(b64, 1), "ms_per_step": round(1e3 * b64_step, 3)},
+        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
+        "speedup_vs_plain": round(value / plain, 2),
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, F, fsdgen, torch):
+    """Request stream (Poisson arrivals) served by the continuous-batching engine."""
+    from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request, poisson_arrivals
+    reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps)
+    prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+
+    def run(rate, seed):
+        be = LibBackend(F, budget, args.slots, dict(precision=prec))
+        eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
+        t_arr = np.zeros(len(reqs)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(reqs), rate)
+        rs = [Request(k, s, args.req_steps, arrival=float(t_arr[k])) for k, s in enumerate(reqs)]
+        rep = eng.run(rs)
+        torch.cuda.synchronize()
+        be.batch.close()
+        return rep
+
+    run(None, 0) if args.warmup else None          # loads code objects, first-touch allocations
+    closed = run(None, 0)                           # every request queued at t = 0: capacity
+    cap = closed["completed"] / closed["span_s"]
+    rate = args.load * cap
+    open_ = run(rate, 1)
+    out = {
+        "metric": METRIC, "value": round(open_["bead_solves_per_s"], 1), "unit": "bead-solves/s", "n_gpus": 1,
+        "steps": args.req_steps, "warmup": args.warmup, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
+                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, tol 1e-5, Poisson "
+                               f"arrivals at {args.load} x capacity",
+                   "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
+                   "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,
+                   "parallelism": "single GPU, continuous batching"},
+        "latency_ms": {"p50": round(1e3 * open_["p50_latency_s"], 1), "p99": round(1e3 * open_["p99_latency_s"], 1)},
+        "capacity_requests_per_s": round(cap, 3), "arrival_rate": round(rate, 3),
+        "closed_loop": {"bead_solves_per_s": round(closed["bead_solves_per_s"], 1),
+                        "p50_ms": round(1e3 * closed["p50_latency_s"], 1),
+                        "p99_ms": round(1e3 * closed["p99_latency_s"], 1)},
+        "failed": open_["failed"] + closed["failed"],
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +184,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["clusters", "batched", "serving"], default="clusters")
+    ap.add_argument("--systems", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--req-steps", type=int, default=20)
+    ap.add_argument("--max-beads", type=int, default=50000)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--load", type=float, default=0.5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
@@ -81,6 +202,10 @@ def main():
     import paper_2607_25161_amd as F
 
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args, F, fsdgen, torch)
+    if args.workload == "serving":
+        return bench_serving(args, F, fsdgen, torch)
     stream = torch.cuda.current_stream()
     s = fsdgen.config(1)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64

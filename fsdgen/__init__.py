@@ -196,6 +196,73 @@ def place_clusters(rng, shapes, L, a=1.0, gap=0.01, max_tries=2000):
     return com, quat
 
 
+def grow_in_box(rng, sizes, L, a=1.0, gap=0.01, k_p=2.0, max_tries=200):
+    """Grow random-sticking clusters directly inside the periodic box.
+
+    For dense suspensions, where rigid clusters cannot be inserted at random,
+    each cluster starts from a free seed position and grows bead by bead with the
+    sticking rule of `sticking_cluster`; a candidate bead must keep 2a from its own
+    cluster (except the bead it touches) and 2a + gap from every other body
+    (minimum image).  Each finished cluster gets a uniform random orientation: its
+    body-frame coordinates are the lab offsets from the centroid rotated back by
+    that orientation.  Returns (shapes, com, quat).
+    """
+    grid = _CellGrid(L, 2.0 * a + gap)
+    placed = np.zeros((sum(sizes), 3))
+    n_placed = 0
+    shapes, coms, quats = [], [], []
+    for nb in sizes:
+        for _restart in range(50):
+            own = []
+            for _ in range(max_tries):
+                X0 = (rng.random(3) - 0.5) * L
+                if _fits(grid, [X0], L, 2.0 * a + gap, placed):
+                    own.append(X0)
+                    break
+            if not own:
+                continue
+            ok = True
+            for m in range(1, nb):
+                cur = np.array(own)
+                done = False
+                for _ in range(max_tries):
+                    if m == 1:
+                        i = 0
+                    else:
+                        dsum = np.linalg.norm(cur[:, None, :] - cur[None, :, :], axis=2).sum(1)
+                        d = dsum / dsum.max()
+                        pr = np.clip(1.0 - (1.0 - d) * k_p, 0.0, None)
+                        pr = pr / pr.sum() if pr.sum() > 0 else np.full(m, 1.0 / m)
+                        i = rng.choice(m, p=pr)
+                    cand = cur[i] + 2.0 * a * _unit_vectors(rng, 1)[0]
+                    dist = np.linalg.norm(cur - cand, axis=1)
+                    dist[i] = np.inf
+                    if np.all(dist >= 2.0 * a * (1.0 - 1e-12)) and _fits(grid, [cand], L, 2.0 * a + gap, placed):
+                        own.append(cand)
+                        done = True
+                        break
+                if not done:
+                    ok = False
+                    break
+            if ok:
+                break
+        else:
+            raise RuntimeError("grow_in_box: could not grow a cluster")
+        pts = np.array(own)
+        c = pts.mean(axis=0)
+        q = uniform_quaternion(rng)
+        body = Rotation.from_quat([q[1], q[2], q[3], q[0]]).inv().apply(pts - c)
+        for p_ in pts:
+            placed[n_placed] = p_
+            grid.add(p_, n_placed)
+            n_placed += 1
+        shapes.append(body)
+        coms.append(c)
+        quats.append(q)
+    com = (np.array(coms) + L / 2) % L - L / 2
+    return shapes, com, np.array(quats)
+
+
 def box_side(n_bead, phi, a=1.0):
     return (n_bead * (4.0 * math.pi / 3.0) * a ** 3 / phi) ** (1.0 / 3.0)
 
@@ -249,6 +316,13 @@ def _assemble(name, shapes, L, rng, a=1.0, gap=0.01, **kw):
     return dict(name=name, L=L, a=a, offsets=offsets, x_body=x_body, com=com, quat=quat)
 
 
+def _dense_assemble(name, sizes, L, rng, a=1.0, gap=0.01, k_p=2.0):
+    shapes, com, quat = grow_in_box(rng, sizes, L, a=a, gap=gap, k_p=k_p)
+    offsets = np.zeros(len(shapes) + 1, dtype=np.int32)
+    offsets[1:] = np.cumsum([len(s) for s in shapes])
+    return dict(name=name, L=L, a=a, offsets=offsets, x_body=np.concatenate(shapes), com=com, quat=quat)
+
+
 def simple_shear(rate=1.0):
     g = np.zeros((3, 3))
     g[0, 1] = rate          # u = rate * y * x_hat
@@ -269,12 +343,21 @@ def sedimenting_doublets(seed=BASE_SEED + 1, n_agg=16, phi=0.05, a=1.0):
 
 
 def sheared_clusters(seed=BASE_SEED + 2, n_agg=256, n_b=8, phi=0.10, a=1.0,
-                     k_p=2.0, xi=0.5, tol=1e-6, grid=64, n_steps=10, name=None):
-    """Random-sticking clusters in simple shear with lubrication (cutoff 3a)."""
+                     k_p=2.0, xi=0.5, tol=1e-6, grid=64, n_steps=10, name=None, dense=False):
+    """Random-sticking clusters in simple shear with lubrication (cutoff 3a).
+
+    dense=False grows each cluster alone and places it by random sequential
+    addition; dense=True grows the clusters inside the box (for volume fractions
+    that rigid insertion cannot reach).
+    """
     rng = rng_from(seed)
-    shapes = [sticking_cluster(rng, n_b, a, k_p) for _ in range(n_agg)]
     L = box_side(n_agg * n_b, phi, a)
-    g = _assemble(name or f"clusters-{n_agg}x{n_b}", shapes, L, rng, a=a)
+    nm = name or f"clusters-{n_agg}x{n_b}"
+    if dense:
+        g = _dense_assemble(nm, [n_b] * n_agg, L, rng, a=a, k_p=k_p)
+    else:
+        shapes = [sticking_cluster(rng, n_b, a, k_p) for _ in range(n_agg)]
+        g = _assemble(nm, shapes, L, rng, a=a)
     return Suspension(eta=1.0, force=np.zeros((n_agg, 6)), grad_u=simple_shear(1.0),
                       xi=xi / a, ewald_tol=tol, gmres_tol=tol, grid=grid,
                       r_lub=3.0 * a, r_precond=2.1 * a, n_steps=n_steps, **g)
@@ -288,10 +371,67 @@ def config(index: int, **overrides) -> Suspension:
         return sheared_clusters(**overrides)
     if index == 2:
         kw = dict(seed=BASE_SEED + 3, n_agg=4096, n_b=20, phi=0.20, xi=0.348, tol=1e-5,
-                  grid=128, n_steps=1, name="clusters-4096x20")
+                  grid=128, n_steps=1, name="clusters-4096x20", dense=True)
         kw.update(overrides)
         return sheared_clusters(**kw)
     raise ValueError(index)
+
+
+def uneven_systems(seed=BASE_SEED + 4, n_sys=64, n_range=(200, 4000), nb_range=(4, 30),
+                   phi_range=(0.02, 0.25), tol=1e-5, a=1.0, k_p=2.0):
+    """Independent periodic systems of uneven size for the batched form.
+
+    Per system s (seed + s): bead count uniform in n_range, beads per aggregate
+    uniform in nb_range (the last aggregate takes the remainder, at least 1 bead),
+    volume fraction uniform in phi_range, splitting parameter 25 / L, simple shear
+    and lubrication as in the sheared-cluster workload.
+    """
+    out = []
+    for k in range(n_sys):
+        rng = rng_from(seed + k)
+        n_tot = int(rng.integers(n_range[0], n_range[1] + 1))
+        n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
+        phi = float(rng.uniform(*phi_range))
+        sizes = _split_sizes(n_tot, n_b)
+        L = box_side(n_tot, phi, a)
+        g = _dense_assemble(f"system-{k}", sizes, L, rng, a=a, k_p=k_p)
+        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
+                              xi=25.0 / L, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
+                              r_precond=2.1 * a, **g))
+    return out
+
+
+def _split_sizes(n_tot, n_b):
+    sizes = [n_b] * (n_tot // n_b)
+    if n_tot % n_b:
+        sizes.append(n_tot % n_b)
+    return sizes
+
+
+def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(4, 30),
+                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0):
+    """A stream of independent simulation requests for the serving form.
+
+    Request r draws from its own Philox stream keyed by (seed, r): bead count
+    log-uniform in n_range, beads per aggregate uniform in nb_range, volume
+    fraction uniform in phi_range; shear and lubrication as in the other
+    workloads; splitting parameter and grid left to the library's policy
+    (xi = 0, grid = 0); each request asks for n_steps time steps.
+    """
+    out = []
+    for r in range(n_req):
+        rng = np.random.Generator(np.random.Philox(key=np.uint64(seed & ((1 << 64) - 1)),
+                                                   counter=np.array([0, 0, 0, r], dtype=np.uint64)))
+        n_tot = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
+        phi = float(rng.uniform(*phi_range))
+        sizes = _split_sizes(n_tot, n_b)
+        L = box_side(n_tot, phi, a)
+        g = _dense_assemble(f"request-{r}", sizes, L, rng, a=a, k_p=k_p)
+        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
+                              xi=0.0, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
+                              r_precond=2.1 * a, kT=kT, n_steps=n_steps, **g))
+    return out
 
 
 def random_force(rng, n_agg, scale=1.0):

@@ -64,7 +64,9 @@ typedef struct {
   double eta;            /* fluid viscosity                                            */
   double radius;         /* bead radius a                                              */
   double kT;             /* thermal energy (0: deterministic)                          */
-  double xi;             /* Ewald splitting parameter; <= 0 selects 0.5 / a            */
+  double xi;             /* Ewald splitting parameter; <= 0: the cheapest of [25/L, 0.5/a]
+                            under the Section 3.2 error rules (cost model of the pair
+                            sum against the grid passes)                              */
   double ewald_tol;      /* truncation tolerance x_err of the cutoff rules (Sec. 3.2)  */
   int grid;              /* spectral grid points per side; 0: from the k_c rule        */
   int support;           /* Gaussian support P (points per side); 0: from ewald_tol    */
@@ -75,7 +77,7 @@ typedef struct {
   int gmres_restart;     /* Krylov dimension m of GMRES(m)                             */
   int gmres_maxit;       /* total inner iterations allowed per solve                   */
   int precision;         /* fsd_precision                                              */
-  double inner_tol;      /* FSD_MIXED: relative tolerance of each FP32 inner solve     */
+  double inner_tol;      /* reserved (FSD_MIXED refines at every GMRES restart)        */
   uint64_t seed;         /* key of the counter-based noise generator                   */
 } fsd_params;
 
@@ -83,7 +85,7 @@ typedef struct {
   int status;                 /* fsd_status of the solve                              */
   int iterations;             /* GMRES iterations (inner iterations summed in MIXED)  */
   int restarts;               /* GMRES restarts                                       */
-  int refinements;            /* FP64 outer corrections (MIXED), 1 in FP64            */
+  int refinements;            /* FP64 residual replacements (MIXED restarts), 1 in FP64 */
   double rel_residual_fp64;   /* ||b - A x|| / ||b|| recomputed with the FP64 matvec  */
 } fsd_solve_info;
 
@@ -175,6 +177,40 @@ fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out
  * forward (sign -1) or inverse (sign +1, unnormalised), with the library's
  * transform.  Host buffer; for verification of the FFT stages. */
 fsd_status fsd_fft3d(int n, int sign, double* data);
+
+/* ---- batches of independent systems (many small suspensions sharing the GPU) -------- */
+
+/* A batch holds up to max_slots systems whose device memory counts against
+ * mem_budget_bytes (fsd_estimate_bytes of each).  Systems stay owned by the caller
+ * and keep their state, neighbour lists and factors resident between steps; give
+ * each its own stream (fsd_create with NULL) so their work overlaps on the GPU. */
+typedef struct fsd_batch fsd_batch;
+
+fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** out);
+
+/* Admit an initialised system into a free slot.  FSD_EBUSY if no slot is free or
+ * the memory budget would be exceeded; slot receives the slot index. */
+fsd_status fsd_batch_admit(fsd_batch* b, fsd_system* s, int* slot);
+
+/* Free a slot (the system itself is not destroyed). */
+fsd_status fsd_batch_retire(fsd_batch* b, int slot);
+
+/* One saddle solve for every admitted system, their GMRES iterations interleaved
+ * on the GPU.  A failing system records its status in its slot info and does not
+ * stop the others; the return value is the first failure (or FSD_OK). */
+fsd_status fsd_batch_solve(fsd_batch* b);
+
+/* As fsd_batch_solve followed by the Euler update (Eqs. `EM1`-`EM3`) of every
+ * system whose solve succeeded. */
+fsd_status fsd_batch_step(fsd_batch* b, double dt);
+
+/* Info of the last solve in a slot. */
+fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* info);
+
+/* Bytes of the admitted systems (sum of their estimates). */
+size_t fsd_batch_used_bytes(const fsd_batch* b);
+
+void fsd_batch_destroy(fsd_batch* b);
 
 /* ---- kernel timing on the system stream (HIP events around each launch) ------------- */
 

@@ -6,6 +6,6 @@ argument marshalling only.  Importing it on a machine where the library has
 not been built raises ImportError; there is no CPU fallback.
 """
 from ._capi import (  # noqa: F401
-    FSD_FP64, FSD_MIXED, FsdError, Info, Params, SolveInfo, System, default_params,
+    Batch, FSD_FP64, FSD_MIXED, FsdError, Info, Params, SolveInfo, System, default_params,
     estimate_bytes, fft3d, lib, library_path, TIMER_NAMES,
 )

@@ -84,6 +84,15 @@ _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong))
 
+_sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
+_sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
+_sig("fsd_batch_retire", C.c_int, C.c_void_p, C.c_int)
+_sig("fsd_batch_solve", C.c_int, C.c_void_p)
+_sig("fsd_batch_step", C.c_int, C.c_void_p, C.c_double)
+_sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
+_sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
+_sig("fsd_batch_destroy", None, C.c_void_p)
+
 TIMER_NAMES = ("real_sum", "spread", "fft_pass", "green_scale", "interp", "rigid", "lub", "precond", "cgs2")
 
 
@@ -282,3 +291,67 @@ class System:
         sysm.set_forces(s.force)
         sysm.set_shear(s.grad_u)
         return sysm
+
+
+class Batch:
+    """Independent systems sharing the GPU (wraps fsd_batch)."""
+
+    def __init__(self, mem_budget_bytes: int, max_slots: int):
+        h = C.c_void_p()
+        rc = lib.fsd_batch_create(int(mem_budget_bytes), int(max_slots), C.byref(h))
+        if rc:
+            raise FsdError(rc, "fsd_batch_create")
+        self._h = h
+        self.systems = {}
+
+    def admit(self, system: "System") -> int:
+        slot = C.c_int()
+        rc = lib.fsd_batch_admit(self._h, system._h, C.byref(slot))
+        if rc:
+            raise FsdError(rc, "fsd_batch_admit")
+        self.systems[slot.value] = system
+        return slot.value
+
+    def try_admit(self, system: "System"):
+        """Slot index, or None when the batch is full or over its memory budget."""
+        slot = C.c_int()
+        rc = lib.fsd_batch_admit(self._h, system._h, C.byref(slot))
+        if rc == -7:
+            return None
+        if rc:
+            raise FsdError(rc, "fsd_batch_admit")
+        self.systems[slot.value] = system
+        return slot.value
+
+    def retire(self, slot: int):
+        rc = lib.fsd_batch_retire(self._h, int(slot))
+        if rc:
+            raise FsdError(rc, "fsd_batch_retire")
+        return self.systems.pop(slot)
+
+    def solve(self):
+        return lib.fsd_batch_solve(self._h)
+
+    def step(self, dt: float):
+        return lib.fsd_batch_step(self._h, float(dt))
+
+    def info(self, slot: int) -> SolveInfo:
+        inf = SolveInfo()
+        rc = lib.fsd_batch_slot_info(self._h, int(slot), C.byref(inf))
+        if rc:
+            raise FsdError(rc, "fsd_batch_slot_info")
+        return inf
+
+    def used_bytes(self) -> int:
+        return int(lib.fsd_batch_used_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.fsd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

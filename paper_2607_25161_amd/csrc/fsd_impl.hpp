@@ -49,11 +49,15 @@ void launch_integrate(int na, const double* U, double dt, double L, double* com,
 struct NeighborWork;
 NeighborWork* neighbor_work_create(int nb);
 void neighbor_work_destroy(NeighborWork* w);
-// Returns hipSuccess or an error; on capacity overflow sets *needed > cap and
-// leaves the list unfilled (the caller grows and calls again).
-hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
-                           double cutoff, bool exclude_same_body, int* rowptr, uint32_t* col,
-                           long long cap, long long* needed, hipStream_t st);
+// Two phases: neighbors_count launches per-row counts and the scan into rowptr
+// and copies the total to pinned memory (read it with neighbors_total once the
+// stream has drained); neighbors_fill then writes the columns.
+hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
+                           double cutoff, bool exclude_same_body, int* rowptr, hipStream_t st);
+long long neighbors_total(const NeighborWork* w);
+hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
+                          double cutoff, bool exclude_same_body, const int* rowptr, uint32_t* col,
+                          hipStream_t st);
 
 void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col,
                       double a, double eta, double eps_min, double r_pre, double* coef,
@@ -139,6 +143,8 @@ struct GmresCtl {
   double tol;
 };
 void launch_gmres_begin(GmresCtl* ctl, const double* rr, double* g, double* scal, hipStream_t st);
+// fresh solve: ctl->bn = sqrt(bb), its = 0, tolerance, budget, restart length
+void launch_gmres_init(GmresCtl* ctl, const double* bb, double tol, int maxit, int m, hipStream_t st);
 void launch_scale_by(size_t n, const double* src, const double* scal, double* dst, hipStream_t st,
                      const int* skip);
 void launch_arnoldi_step(int j, GmresCtl* ctl, const double* h1, const double* h2, const double* hn2,

@@ -172,13 +172,42 @@ bool make_plan(int n, FftPlan& p) {
   return m == 1 && n >= 2;
 }
 
+// smallest 2^a 3^b >= n with a >= 3 (a multiple of 8, for the gather spreading blocks)
 int next_smooth(int n) {
-  for (int m = std::max(n, 4);; ++m) {
+  for (int m = std::max(n, 8);; ++m) {
+    if (m % 8) continue;
     int k = m;
     while (k % 2 == 0) k /= 2;
     while (k % 3 == 0) k /= 3;
     if (k == 1) return m;
   }
+}
+
+// Splitting parameter when the caller leaves it to the library: the Ewald error rule of
+// Section 3.2 fixes R_c and k_c for a given xi, so the cost of one mobility apply is
+// traded between the real-space pair sum (pairs ~ N (4 pi/3) R_c^3 n) and the grid
+// passes (~ N_g^3 points).  The per-pair and per-point weights are the measured costs
+// of the two FP64 paths on gfx950 (about 2 ps per pair term, 60 ps per grid point);
+// candidates run over [25/L, 0.5/a], the two fixed policies of Section 3.2.
+double pick_xi(const fsd_params& p, int nb, double L) {
+  if (p.xi > 0) return p.xi;
+  const double a = p.radius;
+  const double hi = 0.5 / a;
+  const double lo = std::min(hi, 25.0 / L);
+  if (nb <= 0 || !(L > 0) || p.grid > 0) return hi;
+  const double lnt = std::sqrt(-std::log(p.ewald_tol));
+  const double dens = nb / (L * L * L);
+  double best = hi, best_cost = 1e300;
+  for (int k = 0; k <= 48; ++k) {
+    const double xi = lo * std::pow(hi / lo, k / 48.0);
+    const double rc = 1.15 * lnt / xi;  // the grown cutoff sits ~15% above the rule
+    const int N = next_smooth(int(std::ceil((2.0 * lnt * xi + 1.0 / a) * L / M_PI)));
+    if (N > 512) continue;
+    const double pairs = nb * (4.0 * M_PI / 3.0) * rc * rc * rc * dens;
+    const double cost = 2e-12 * pairs + 6e-11 * double(N) * N * N;
+    if (cost < best_cost) best_cost = cost, best = xi;
+  }
+  return best;
 }
 
 }  // namespace
@@ -236,7 +265,24 @@ struct fsd_system {
   GmresCtl* d_ctl = nullptr;   // device GMRES cycle state
   GmresCtl* h_ctl = nullptr;   // pinned mirror
   double *d_H = nullptr, *d_cs = nullptr, *d_sn = nullptr, *d_g = nullptr, *d_y = nullptr, *d_scal = nullptr;
-  NeighborWork* nw = nullptr;
+  NeighborWork* nw = nullptr;   // real-space list workspace
+  NeighborWork* nwl = nullptr;  // lubrication list workspace
+  int* h_flags = nullptr;       // pinned: overlap, singular block (checked at the next sync)
+  double* h_scal = nullptr;     // pinned: small reductions read by the host (outer residual)
+
+  // resumable solve (state machine advanced after each stream synchronisation)
+  struct SolveState {
+    enum Phase { IDLE, PREP, START, BATCH, OUTER, DONE } phase = IDLE;
+    const double* b = nullptr;  // right-hand side of the GMRES in progress
+    double* x = nullptr;        // its iterate
+    bool fp32 = false;
+    double tol = 0;
+    int maxit = 0, j0 = 0;
+    int its = 0, restarts = 0, outer = 0;
+    double rel = 0;
+    bool converged = false;
+    fsd_status status = FSD_OK;
+  } sv;
   SpreadPlan* spread = nullptr;  // gather spreading (nullptr: atomic scatter)
   std::vector<double> h_tab;  // host copy of the smooth-part table (5 per node, 8 stride)
 
@@ -292,6 +338,12 @@ struct fsd_system {
     ev_pool.clear();
     if (nw) neighbor_work_destroy(nw);
     nw = nullptr;
+    if (nwl) neighbor_work_destroy(nwl);
+    nwl = nullptr;
+    if (h_flags) (void)hipHostFree(h_flags);
+    h_flags = nullptr;
+    if (h_scal) (void)hipHostFree(h_scal);
+    h_scal = nullptr;
     if (spread) spread_plan_destroy(spread);
     spread = nullptr;
     for (void* q : owned) (void)hipFree(q);
@@ -426,7 +478,7 @@ void harvest_graph(fsd_system* s, GraphEntry* e, int active) {
 void choose_parameters(fsd_system* s) {
   const fsd_params& p = s->p;
   const double a = p.radius, L = s->L;
-  const double xi = p.xi > 0 ? p.xi : 0.5 / a;
+  const double xi = pick_xi(p, s->nb, L);
   const double tol = p.ewald_tol;
   const double lnt = std::sqrt(-std::log(tol));
   const double rc = lnt / xi;
@@ -516,35 +568,37 @@ void upload_tables(fsd_system* s) {
   HIPCHK(hipMemcpy(s->d_tw32, twf.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
 }
 
-void build_list(fsd_system* s, double cutoff, bool exclude, int* rowptr, uint32_t*& col, long long& cap,
-                long long& count) {
-  long long needed = 0;
-  HIPCHK(build_neighbors(s->nw, s->nb, s->d_pos4, s->d_body, s->L, cutoff, exclude, rowptr, col, cap, &needed,
-                         s->st));
-  if (needed > cap) {
-    // grow (the only allocation after setup) and rebuild
-    auto it = std::find(s->owned.begin(), s->owned.end(), (void*)col);
-    if (it != s->owned.end()) {
-      (void)hipFree(*it);
-      s->owned.erase(it);
-    }
-    cap = needed + needed / 4 + 64;
-    col = dalloc<uint32_t>(s->owned, size_t(cap));
-    HIPCHK(build_neighbors(s->nw, s->nb, s->d_pos4, s->d_body, s->L, cutoff, exclude, rowptr, col, cap, &needed,
-                           s->st));
+// grow a column buffer (the only allocation after set-up)
+void ensure_cols(fsd_system* s, uint32_t*& col, long long& cap, long long need) {
+  if (need <= cap) return;
+  auto it = std::find(s->owned.begin(), s->owned.end(), (void*)col);
+  if (it != s->owned.end()) {
+    (void)hipFree(*it);
+    s->owned.erase(it);
   }
-  count = needed;
+  cap = need + need / 4 + 64;
+  col = dalloc<uint32_t>(s->owned, size_t(cap));
 }
 
-// Algorithm 1 step 1 plus the geometry it needs: bead positions, neighbour lists,
-// lubrication coefficients, per-aggregate LU of the Schur approximation.
-void prepare(fsd_system* s) {
-  if (s->prepared) return;
+// Algorithm 1 step 1 plus the geometry it needs, in two halves around one stream
+// synchronisation: prepare_begin launches bead positions and the neighbour-list counts;
+// prepare_end (after the stream drained) fills the lists, lubrication coefficients,
+// preconditioner factors and the spreading plan.
+void prepare_begin(fsd_system* s) {
   launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->d_r4, s->d_pos4, s->st);
-  build_list(s, s->rp.r_cut, false, s->d_nrow, s->d_ncol, s->ncap, s->nnz);
-  HIPCHK(hipMemsetAsync(s->d_flags, 0, 2 * sizeof(int), s->st));
+  HIPCHK(neighbors_count(s->nw, s->nb, s->d_pos4, s->d_body, s->L, s->rp.r_cut, false, s->d_nrow, s->st));
+  if (s->p.r_lub > 0)
+    HIPCHK(neighbors_count(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->p.r_lub, true, s->d_lrow, s->st));
+}
+
+void prepare_end(fsd_system* s) {
+  s->nnz = neighbors_total(s->nw);
+  ensure_cols(s, s->d_ncol, s->ncap, s->nnz);
+  HIPCHK(neighbors_fill(s->nw, s->nb, s->d_pos4, s->d_body, s->L, s->rp.r_cut, false, s->d_nrow, s->d_ncol, s->st));
+  launch_zero(s->d_flags, 2 * sizeof(int), s->st);
   if (s->p.r_lub > 0) {
-    build_list(s, s->p.r_lub, true, s->d_lrow, s->d_lcol, s->lcap, s->nlub);
+    s->nlub = neighbors_total(s->nwl);
+    ensure_cols(s, s->d_lcol, s->lcap, s->nlub);
     if (s->lcoef_cap < s->lcap) {
       auto it = std::find(s->owned.begin(), s->owned.end(), (void*)s->d_lcoef);
       if (it != s->owned.end()) {
@@ -554,20 +608,17 @@ void prepare(fsd_system* s) {
       s->d_lcoef = dalloc<double>(s->owned, size_t(5 * s->lcap));
       s->lcoef_cap = s->lcap;
     }
+    HIPCHK(neighbors_fill(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->p.r_lub, true, s->d_lrow, s->d_lcol, s->st));
     launch_lub_setup(s->nb, s->d_pos4, s->L, s->d_lrow, s->d_lcol, s->p.radius, s->p.eta, s->p.lub_eps_min,
                      s->p.r_precond, s->d_lcoef, s->d_rdiag, s->d_flags, s->st);
   } else {
-    HIPCHK(hipMemsetAsync(s->d_rdiag, 0, sizeof(double) * 6 * s->nb, s->st));
+    launch_zero(s->d_rdiag, sizeof(double) * 6 * s->nb, s->st);
     s->nlub = 0;
   }
   launch_precond_factor(s->na, s->d_offsets, s->d_r4, s->d_rdiag, s->drag_t, s->drag_r, s->d_lu, s->d_piv,
                         s->d_flags + 1, s->st);
   if (s->spread) HIPCHK(spread_plan_update(s->spread, s->d_pos4, s->wp, s->st));
-  int flags[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(flags, s->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
-  HIPCHK(hipStreamSynchronize(s->st));
-  if (flags[0]) throw ApiError(FSD_EOVERLAP, "beads of different bodies overlap by more than a/2");
-  if (flags[1]) throw ApiError(FSD_EDEVICE, "singular aggregate block in the preconditioner");
+  HIPCHK(hipMemcpyAsync(s->h_flags, s->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s->st));
   const double avg = s->nb ? double(s->nnz) / s->nb : 0.0;
   int l = 1;
   while (l < 64 && l * 6 < avg) l *= 2;
@@ -580,6 +631,22 @@ void prepare(fsd_system* s) {
     s->graph_sig = sig;
   }
   s->prepared = true;
+}
+
+// flags written by prepare_end, read after a later synchronisation
+void check_flags(fsd_system* s) {
+  if (s->h_flags[0]) throw ApiError(FSD_EOVERLAP, "beads of different bodies overlap by more than a/2");
+  if (s->h_flags[1]) throw ApiError(FSD_EDEVICE, "singular aggregate block in the preconditioner");
+}
+
+// synchronous form for the operator-access calls
+void prepare(fsd_system* s) {
+  if (s->prepared) return;
+  prepare_begin(s);
+  HIPCHK(hipStreamSynchronize(s->st));
+  prepare_end(s);
+  HIPCHK(hipStreamSynchronize(s->st));
+  check_flags(s);
 }
 
 }  // namespace
@@ -690,7 +757,7 @@ void assemble_rhs(fsd_system* s) {
   launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_force, lub ? s->d_fl : nullptr, s->d_b + nb6, s->st);
 }
 
-// ||v||^2 and similar small reductions land in s->h_small after a sync
+// ||v|| with a synchronisation (operator-access paths only)
 double norm2(fsd_system* s, const double* v) {
   launch_dots(s->n, 1, v, s->n, v, s->d_part, s->d_h, s->d_counters, s->st);
   HIPCHK(hipMemcpyAsync(s->h_small, s->d_h, sizeof(double), hipMemcpyDeviceToHost, s->st));
@@ -698,140 +765,206 @@ double norm2(fsd_system* s, const double* v) {
   return std::sqrt(s->h_small[0]);
 }
 
-struct GmresOut {
-  int its = 0, restarts = 0;
-  double rel = 0;
-  bool converged = false;
-};
+// ---- GMRES segments (asynchronous; each ends with the control block copied to the host) ----
+// Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied twice
+// (CGS2).  The Arnoldi bookkeeping, Givens rotations and stopping test run on the
+// device; the host replays captured segments: a cycle start (true residual b - A x,
+// beta, v0), batches of Arnoldi steps (kernels after the device stop flag return
+// early), and a cycle end (x += P^-1 V y).  Every cycle starts from the recomputed
+// residual, so the residual reported at convergence is a true one.
 
-// Right-preconditioned restarted GMRES(m) with classical Gram-Schmidt applied
-// twice (CGS2).  x is the initial guess on entry and the iterate on exit.  The
-// Arnoldi bookkeeping, Givens rotations and stopping test run on the device; the
-// host launches iterations in batches and synchronises once per batch, reading
-// the device stop flag.  Kernels of steps after the stop return immediately.
-// Every cycle starts from the recomputed residual b - A x, so the reported
-// residual is a true one.
-GmresOut gmres(fsd_system* s, const double* b, double* x, double tol, bool fp32, int maxit) {
-  GmresOut o;
+void seg_cycle_start(fsd_system* s) {
+  auto& v = s->sv;
   const size_t n = s->n;
   const int m = s->m;
-  double* V = s->d_basis;
+  double* hn2 = s->d_h + 2 * (m + 1);
   const int* stop = &s->d_ctl->stop;
-  const double bn = norm2(s, b);
-  if (bn == 0.0) {
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, s->st));
-    o.converged = true;
-    return o;
-  }
-  GmresCtl c{};
-  c.bn = bn;
-  c.tol = tol;
-  c.maxit = maxit;
-  c.m = m;
-  HIPCHK(hipMemcpyAsync(s->d_ctl, &c, sizeof(GmresCtl), hipMemcpyHostToDevice, s->st));
+  const double* b = v.b;
+  double* x = v.x;
+  const bool fp32 = v.fp32;
+  (void)fp32;
+  run_body(s, {0, 0, 0, 0, b, x}, [&] {
+    // the true residual in FP64 at every cycle start: with FP32 Arnoldi matvecs
+    // (mixed precision) each restart is an iterative-refinement step
+    apply_saddle<double>(s, x, s->d_t);
+    launch_sub(n, b, s->d_t, s->d_r, s->st);
+    launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->d_counters, s->st);
+    launch_gmres_begin(s->d_ctl, hn2, s->d_g, s->d_scal, s->st);
+    launch_scale_by(n, s->d_r, s->d_scal, s->d_basis, s->st, stop);
+  });
+  HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
+}
+
+void seg_batch(fsd_system* s, int j0) {
+  auto& v = s->sv;
+  const size_t n = s->n;
+  const int m = s->m;
+  const int S = std::max(1, std::min(s->batch, m));
+  const int cnt = std::min(S, m - j0);
+  double* V = s->d_basis;
   double* h1 = s->d_h;
   double* h2 = s->d_h + (m + 1);
   double* hn2 = s->d_h + 2 * (m + 1);
-  const int S = std::max(1, std::min(s->batch, m));
-  const int prec = fp32 ? 1 : 0;
-  GraphEntry* pending_end = nullptr;
-  while (true) {
-    // cycle start: r = b - A x, beta = ||r||, v0 = r / beta
-    GraphEntry* e0 = run_body(s, {0, 0, 0, prec, b, x}, [&] {
-      apply_saddle_p(s, x, s->d_t, fp32);
-      launch_sub(n, b, s->d_t, s->d_r, s->st);
-      launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->d_counters, s->st);
-      launch_gmres_begin(s->d_ctl, hn2, s->d_g, s->d_scal, s->st);
-      launch_scale_by(n, s->d_r, s->d_scal, V, s->st, stop);
-    });
-    HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
-    harvest_graph(s, pending_end, 1 << 30);
-    harvest_graph(s, e0, 1 << 30);
-    pending_end = nullptr;
-    o.rel = s->h_ctl->resid;
-    o.its = s->h_ctl->its;
-    if (o.rel <= tol) {
-      o.converged = true;
-      return o;
+  const int* stop = &s->d_ctl->stop;
+  const bool fp32 = v.fp32;
+  run_body(s, {1, j0, cnt, fp32 ? 1 : 0, nullptr, nullptr}, [&] {
+    for (int j = j0; j < j0 + cnt; ++j) {
+      apply_precond(s, V + size_t(j) * n, s->d_z, stop);
+      apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
+      Timed t(s, FSD_TIMER_KRYLOV);  // CGS2 + Givens
+      launch_dots(n, j + 1, V, n, s->d_w, s->d_part, h1, s->d_counters, s->st, stop);
+      launch_axpy_dots(n, j + 1, V, n, h1, s->d_w, 0, s->d_part, h2, s->d_counters, s->st, stop);
+      launch_axpy_dots(n, j + 1, V, n, h2, s->d_w, 1, s->d_part, hn2, s->d_counters, s->st, stop);
+      launch_arnoldi_step(j, s->d_ctl, h1, h2, hn2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal, s->st);
+      launch_scale_by(n, s->d_w, s->d_scal, V + size_t(j + 1) * n, s->st, stop);
     }
-    if (s->h_ctl->stop) return o;  // iteration budget spent
-    for (int j0 = 0; j0 < m; j0 += S) {
-      const int cnt = std::min(S, m - j0);
-      GraphEntry* eb = run_body(s, {1, j0, cnt, prec, nullptr, nullptr}, [&] {
-        for (int j = j0; j < j0 + cnt; ++j) {
-          s->cap_iter = j - j0;
-          apply_precond(s, V + size_t(j) * n, s->d_z, stop);
-          apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
-          Timed t(s, FSD_TIMER_KRYLOV);  // CGS2 + Givens
-          launch_dots(n, j + 1, V, n, s->d_w, s->d_part, h1, s->d_counters, s->st, stop);
-          launch_axpy_dots(n, j + 1, V, n, h1, s->d_w, 0, s->d_part, h2, s->d_counters, s->st, stop);
-          launch_axpy_dots(n, j + 1, V, n, h2, s->d_w, 1, s->d_part, hn2, s->d_counters, s->st, stop);
-          launch_arnoldi_step(j, s->d_ctl, h1, h2, hn2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal, s->st);
-          launch_scale_by(n, s->d_w, s->d_scal, V + size_t(j + 1) * n, s->st, stop);
-        }
-        s->cap_iter = -1;
-      });
-      HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
-      HIPCHK(hipStreamSynchronize(s->st));
-      harvest_graph(s, eb, s->h_ctl->k_used - j0);
-      if (s->h_ctl->stop) break;
+  });
+  HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
+}
+
+void seg_cycle_end(fsd_system* s) {
+  auto& v = s->sv;
+  const size_t n = s->n;
+  const int m = s->m;
+  double* x = v.x;
+  run_body(s, {2, 0, 0, v.fp32 ? 1 : 0, v.b, x}, [&] {
+    launch_gmres_solve(s->d_ctl, s->d_H, s->d_g, s->d_y, s->st);
+    launch_basis_combine(n, m, s->d_basis, n, s->d_y, s->d_ctl, s->d_t, s->st);
+    apply_precond(s, s->d_t, s->d_z);
+    launch_axpby(n, 1.0, s->d_z, 1.0, x, s->st);
+  });
+}
+
+// start a GMRES on (b, x) from x = 0
+void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp32, int maxit) {
+  auto& v = s->sv;
+  v.b = b;
+  v.x = x;
+  v.tol = tol;
+  v.fp32 = fp32;
+  launch_zero(x, sizeof(double) * s->n, s->st);
+  double* bb = s->d_h + 2 * (s->m + 1) + 1;
+  launch_dots(s->n, 1, b, s->n, b, s->d_part, bb, s->d_counters, s->st);
+  launch_gmres_init(s->d_ctl, bb, tol, std::max(1, maxit), s->m, s->st);
+  seg_cycle_start(s);
+  v.phase = fsd_system::SolveState::START;
+}
+
+// FP64 outer residual of the mixed-precision refinement: r = b - A64 x, ||r||^2, ||b||^2
+void seg_outer(fsd_system* s) {
+  const size_t n = s->n;
+  apply_saddle<double>(s, s->d_x, s->d_t);
+  launch_sub(n, s->d_b, s->d_t, s->d_r, s->st);
+  double* sc = s->d_h + 2 * (s->m + 1) + 2;
+  launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, sc, s->d_counters, s->st);
+  launch_dots(n, 1, s->d_b, n, s->d_b, s->d_part, sc + 1, s->d_counters, s->st);
+  HIPCHK(hipMemcpyAsync(s->h_scal, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  s->sv.phase = fsd_system::SolveState::OUTER;
+}
+
+void finish_solve(fsd_system* s, bool ok) {
+  const size_t nb6 = 6 * size_t(s->nb);
+  launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
+  s->sv.converged = ok;
+  s->sv.status = ok ? FSD_OK : FSD_ENOCONV;
+  if (!ok) s->err = "GMRES did not reach the tolerance within gmres_maxit iterations";
+  s->sv.phase = fsd_system::SolveState::DONE;
+}
+
+// the correction of one mixed-precision refinement lives after the Krylov basis
+double* mixed_corr(fsd_system* s) { return s->d_basis + size_t(s->m + 1) * s->n; }
+double* mixed_rhs(fsd_system* s) { return s->d_basis + size_t(s->m + 2) * s->n; }
+
+// begin a solve at the current configuration (asynchronous)
+void solve_begin(fsd_system* s) {
+  auto& v = s->sv;
+  v = fsd_system::SolveState{};
+  if (!s->prepared) {
+    prepare_begin(s);
+    v.phase = fsd_system::SolveState::PREP;
+    return;
+  }
+  v.phase = fsd_system::SolveState::PREP;  // prepared: PREP only assembles the right-hand side
+}
+
+// Advance after the system stream has drained.  Returns false once the solve is done.
+bool solve_advance(fsd_system* s) {
+  auto& v = s->sv;
+  using SS = fsd_system::SolveState;
+  const bool mixed = s->p.precision == FSD_MIXED;
+  switch (v.phase) {
+    case SS::PREP: {
+      if (!s->prepared) prepare_end(s);
+      assemble_rhs(s);
+      gmres_launch(s, s->d_b, s->d_x, s->p.gmres_tol, mixed, s->p.gmres_maxit);
+      return true;
     }
-    // x += P^-1 (V y)
-    pending_end = run_body(s, {2, 0, 0, prec, b, x}, [&] {
-      launch_gmres_solve(s->d_ctl, s->d_H, s->d_g, s->d_y, s->st);
-      launch_basis_combine(n, m, V, n, s->d_y, s->d_ctl, s->d_t, s->st);
-      apply_precond(s, s->d_t, s->d_z);
-      launch_axpby(n, 1.0, s->d_z, 1.0, x, s->st);
-    });
-    ++o.restarts;
+    case SS::START: {
+      check_flags(s);
+      const GmresCtl& c = *s->h_ctl;
+      if (c.resid <= v.tol || c.stop) {
+        v.its += c.its;
+        v.rel = c.resid;
+        finish_solve(s, c.resid <= v.tol);
+        return false;
+      }
+      v.j0 = 0;
+      seg_batch(s, 0);
+      v.phase = SS::BATCH;
+      return true;
+    }
+    case SS::BATCH: {
+      const GmresCtl& c = *s->h_ctl;
+      const int S = std::max(1, std::min(s->batch, s->m));
+      if (c.stop) {
+        seg_cycle_end(s);
+        ++v.restarts;
+        if (mixed) ++v.outer;  // each FP64 residual replacement is one refinement
+        seg_cycle_start(s);
+        v.phase = SS::START;
+      } else {
+        v.j0 += S;
+        seg_batch(s, v.j0);
+      }
+      return true;
+    }
+    case SS::OUTER: {
+      check_flags(s);
+      const double rr = s->h_scal[0], bb = s->h_scal[1];
+      v.rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      if (v.rel <= s->p.gmres_tol || v.its >= s->p.gmres_maxit || v.outer >= 50) {
+        finish_solve(s, v.rel <= s->p.gmres_tol);
+        return false;
+      }
+      ++v.outer;
+      HIPCHK(hipMemcpyAsync(mixed_rhs(s), s->d_r, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
+      gmres_launch(s, mixed_rhs(s), mixed_corr(s), s->p.inner_tol, true, s->p.gmres_maxit - v.its);
+      return true;
+    }
+    default:
+      return false;
   }
 }
 
-fsd_status solve_current(fsd_system* s, fsd_solve_info* info) {
-  prepare(s);
-  assemble_rhs(s);
-  const size_t n = s->n;
-  HIPCHK(hipMemsetAsync(s->d_x, 0, sizeof(double) * n, s->st));
+fsd_solve_info info_of(const fsd_system* s) {
+  const auto& v = s->sv;
   fsd_solve_info inf{};
-  bool ok = false;
-  if (s->p.precision == FSD_MIXED) {
-    // FP64 outer residual, FP32-matvec GMRES corrections
-    const double bn = norm2(s, s->d_b);
-    int outer = 0;
-    double rel = 1.0;
-    for (; outer < 50; ++outer) {
-      apply_saddle<double>(s, s->d_x, s->d_t);
-      launch_sub(n, s->d_b, s->d_t, s->d_r, s->st);
-      rel = bn > 0 ? norm2(s, s->d_r) / bn : 0.0;
-      if (rel <= s->p.gmres_tol || inf.iterations >= s->p.gmres_maxit) break;
-      // correction A d = r with FP32 matvecs; two spare vectors follow the Krylov basis
-      double* corr = s->d_basis + size_t(s->m + 1) * n;  // spare vector after the basis
-      double* rhs = s->d_basis + size_t(s->m + 2) * n;
-      HIPCHK(hipMemcpyAsync(rhs, s->d_r, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
-      HIPCHK(hipMemsetAsync(corr, 0, sizeof(double) * n, s->st));
-      GmresOut go = gmres(s, rhs, corr, s->p.inner_tol, true, s->p.gmres_maxit - inf.iterations);
-      inf.iterations += go.its;
-      inf.restarts += go.restarts;
-      launch_axpby(n, 1.0, corr, 1.0, s->d_x, s->st);
-    }
-    inf.refinements = outer;
-    inf.rel_residual_fp64 = rel;
-    ok = rel <= s->p.gmres_tol;
-  } else {
-    GmresOut go = gmres(s, s->d_b, s->d_x, s->p.gmres_tol, false, s->p.gmres_maxit);
-    inf.iterations = go.its;
-    inf.restarts = go.restarts;
-    inf.refinements = 1;
-    inf.rel_residual_fp64 = go.rel;
-    ok = go.converged;
+  inf.status = v.status;
+  inf.iterations = v.its;
+  inf.restarts = v.restarts;
+  inf.refinements = s->p.precision == FSD_MIXED ? v.outer : 1;
+  inf.rel_residual_fp64 = v.rel;
+  return inf;
+}
+
+fsd_status solve_current(fsd_system* s, fsd_solve_info* info) {
+  solve_begin(s);
+  while (true) {
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (!solve_advance(s)) break;
   }
-  const size_t nb6 = 6 * size_t(s->nb);
-  launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
-  inf.status = ok ? FSD_OK : FSD_ENOCONV;
-  if (info) *info = inf;
-  if (!ok) s->err = "GMRES did not reach the tolerance within gmres_maxit iterations";
-  return ok ? FSD_OK : FSD_ENOCONV;
+  if (info) *info = info_of(s);
+  return s->sv.status;
 }
 
 fsd_status check_ready(fsd_system* s) {
@@ -986,7 +1119,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_r = dalloc<double>(o, n);
     s->d_wt = dalloc<double>(o, 3 * size_t(nb));
     s->d_fl = dalloc<double>(o, 3 * size_t(nb));
-    s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 8);
+    s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 16);
     s->d_part = dalloc<double>(o, size_t(s->m + 2) * 1024);
     s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
     HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
@@ -1004,7 +1137,11 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
     s->nw = neighbor_work_create(nb);
-    if (!s->nw) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
+    s->nwl = neighbor_work_create(nb);
+    if (!s->nw || !s->nwl) throw ApiError(FSD_ENOMEM, "neighbour-list workspace allocation failed");
+    HIPCHK(hipHostMalloc((void**)&s->h_flags, 2 * sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&s->h_scal, 4 * sizeof(double)));
+    s->h_flags[0] = s->h_flags[1] = 0;
     s->spread = spread_plan_create(nb, s->wp.n, s->wp.support);  // nullptr: grid not a multiple of 4
     upload_tables(s);
     HIPCHK(hipMemcpy(s->d_offsets, off, sizeof(int) * (n_agg + 1), hipMemcpyHostToDevice));
@@ -1192,9 +1329,9 @@ fsd_status fsd_get_info(const fsd_system* cs, fsd_info* info) {
 size_t fsd_estimate_bytes(const fsd_params* p, int32_t nb, int32_t na, double L) {
   if (!p || nb <= 0 || na <= 0 || !(L > 0)) return 0;
   const double a = p->radius;
-  const double xi = p->xi > 0 ? p->xi : 0.5 / a;
+  const double xi = pick_xi(*p, nb, L);
   const double lnt = std::sqrt(-std::log(p->ewald_tol));
-  const double rc = lnt / xi;
+  const double rc = 1.15 * lnt / xi;
   int N = p->grid > 0 ? p->grid : next_smooth(int(std::ceil((2.0 * lnt * xi + 1.0 / a) * L / M_PI)));
   const double dens = nb / (L * L * L);
   const double nnz = nb * (4.19 * rc * rc * rc * dens * 1.3 + 64);
@@ -1363,5 +1500,158 @@ fsd_status fsd_fft3d(int n, int sign, double* data) {
   for (void* q : owned) (void)hipFree(q);
   return rc;
 }
+
+}  // extern "C"
+
+// ==========================================================================================
+// batches of independent systems
+// ==========================================================================================
+
+struct fsd_batch {
+  size_t budget = 0, used = 0;
+  std::vector<fsd_system*> slot;
+  std::vector<size_t> bytes;
+  std::vector<fsd_solve_info> last;
+  std::string err;
+};
+
+namespace {
+size_t system_bytes(const fsd_system* s) {
+  return fsd_estimate_bytes(&s->p, s->nb, s->na, s->L);
+}
+
+// One solve (and optionally an Euler step) for every admitted system.  Each system
+// runs on its own stream; the host advances their state machines round-robin, so
+// while it waits on one system the others keep the GPU busy.
+fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
+  std::vector<fsd_system*> act;
+  for (auto* s : b->slot)
+    if (s) act.push_back(s);
+  fsd_status worst = FSD_OK;
+  std::vector<char> done(act.size(), 0);
+  for (size_t k = 0; k < act.size(); ++k) {
+    fsd_system* s = act[k];
+    fsd_status r = guarded(s, [&]() -> fsd_status {
+      solve_begin(s);
+      return FSD_OK;
+    });
+    if (r != FSD_OK) {
+      done[k] = 1;
+      s->sv.status = r;
+      worst = r;
+    }
+  }
+  size_t remaining = 0;
+  for (char d : done) remaining += d ? 0 : 1;
+  // poll: advance whichever system's stream has drained; block only when none has
+  while (remaining > 0) {
+    bool progressed = false;
+    for (size_t k = 0; k < act.size(); ++k) {
+      if (done[k]) continue;
+      fsd_system* s = act[k];
+      const hipError_t q = hipStreamQuery(s->st);
+      if (q == hipErrorNotReady) continue;
+      progressed = true;
+      bool more = false;
+      fsd_status r = guarded(s, [&]() -> fsd_status {
+        HIPCHK(q);
+        more = solve_advance(s);
+        return FSD_OK;
+      });
+      if (r != FSD_OK) {
+        s->sv.status = r;  // a failure retires only this system's solve
+        more = false;
+      }
+      if (!more) {
+        done[k] = 1;
+        --remaining;
+        if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
+        if (integrate && s->sv.status == FSD_OK) {
+          launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+          s->prepared = false;
+        }
+      }
+    }
+    if (!progressed) {
+      for (size_t k = 0; k < act.size(); ++k)
+        if (!done[k]) {
+          (void)hipStreamSynchronize(act[k]->st);
+          break;
+        }
+    }
+  }
+  for (size_t q = 0; q < b->slot.size(); ++q)
+    if (b->slot[q]) {
+      (void)hipStreamSynchronize(b->slot[q]->st);
+      b->last[q] = info_of(b->slot[q]);
+    }
+  return worst;
+}
+}  // namespace
+
+extern "C" {
+
+fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** out) {
+  if (!out || max_slots < 1 || max_slots > 4096) return FSD_EINVAL;
+  auto* b = new (std::nothrow) fsd_batch;
+  if (!b) return FSD_ENOMEM;
+  b->budget = mem_budget_bytes;
+  b->slot.assign(max_slots, nullptr);
+  b->bytes.assign(max_slots, 0);
+  b->last.assign(max_slots, fsd_solve_info{});
+  *out = b;
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_admit(fsd_batch* b, fsd_system* s, int* slot) {
+  if (!b || !s || !slot) return FSD_EINVAL;
+  if (!s->have_agg) return FSD_ESTATE;
+  for (auto* q : b->slot)
+    if (q == s) return FSD_EINVAL;
+  const size_t need = system_bytes(s);
+  if (b->used + need > b->budget) {
+    b->err = "memory budget exhausted";
+    return FSD_EBUSY;
+  }
+  for (size_t q = 0; q < b->slot.size(); ++q)
+    if (!b->slot[q]) {
+      b->slot[q] = s;
+      b->bytes[q] = need;
+      b->used += need;
+      b->last[q] = fsd_solve_info{};
+      *slot = int(q);
+      return FSD_OK;
+    }
+  b->err = "no free slot";
+  return FSD_EBUSY;
+}
+
+fsd_status fsd_batch_retire(fsd_batch* b, int slot) {
+  if (!b || slot < 0 || slot >= int(b->slot.size()) || !b->slot[slot]) return FSD_EINVAL;
+  b->used -= b->bytes[slot];
+  b->slot[slot] = nullptr;
+  b->bytes[slot] = 0;
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_solve(fsd_batch* b) {
+  if (!b) return FSD_EINVAL;
+  return batch_run(b, 0.0, false);
+}
+
+fsd_status fsd_batch_step(fsd_batch* b, double dt) {
+  if (!b || !(dt > 0)) return FSD_EINVAL;
+  return batch_run(b, dt, true);
+}
+
+fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* info) {
+  if (!b || !info || slot < 0 || slot >= int(b->slot.size())) return FSD_EINVAL;
+  *info = b->last[slot];
+  return FSD_OK;
+}
+
+size_t fsd_batch_used_bytes(const fsd_batch* b) { return b ? b->used : 0; }
+
+void fsd_batch_destroy(fsd_batch* b) { delete b; }
 
 }  // extern "C"

@@ -92,6 +92,7 @@ __device__ inline uint32_t pack_entry(int j, int sx, int sy, int sz) {
 struct NeighborWork {
   int nb = 0;
   int ncell_cap = 0;
+  int nc = 0;  // cells per side of the last count phase
   int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *vals_out = nullptr;
   int *cell_start = nullptr, *cell_end = nullptr, *counts = nullptr;
   void* temp = nullptr;
@@ -221,13 +222,15 @@ __global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int
   if (!FILL) counts[i] = cnt;
 }
 
-hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
-                           bool exclude_same_body, int* rowptr, uint32_t* col, long long cap, long long* needed,
-                           hipStream_t st) {
+// Count phase: per-bead pair counts, exclusive scan into rowptr, and an
+// asynchronous copy of the total into pinned memory (valid once the stream drains).
+hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
+                           bool exclude_same_body, int* rowptr, hipStream_t st) {
   const double4* pos = (const double4*)pos4v;
   const double rc2 = cutoff * cutoff;
   int nc = int(L / cutoff);
   if (nc > 1024) nc = 1024;
+  w->nc = nc;
   hipError_t e;
   if (nc >= 3) {
     const double cs = L / nc;
@@ -235,6 +238,8 @@ hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4v, const i
     if (ncell > w->ncell_cap) {
       (void)hipFree(w->cell_start);
       (void)hipFree(w->cell_end);
+      w->cell_start = w->cell_end = nullptr;
+      w->ncell_cap = 0;
       if ((e = hipMalloc(&w->cell_start, sizeof(int) * ncell)) != hipSuccess) return e;
       if ((e = hipMalloc(&w->cell_end, sizeof(int) * ncell)) != hipSuccess) return e;
       w->ncell_cap = ncell;
@@ -261,10 +266,17 @@ hipError_t build_neighbors(NeighborWork* w, int nb, const double* pos4v, const i
   size_t tb = w->temp_bytes;
   if ((e = hipcub::DeviceScan::ExclusiveSum(w->temp, tb, w->counts, rowptr, nb + 1, st)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(w->total, rowptr + nb, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  const long long total = *w->total;
-  *needed = total;
-  if (total > cap) return hipSuccess;
+  return hipGetLastError();
+}
+
+long long neighbors_total(const NeighborWork* w) { return *w->total; }
+
+// Fill phase (after the count phase has drained; col holds at least the total).
+hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
+                          bool exclude_same_body, const int* rowptr, uint32_t* col, hipStream_t st) {
+  const double4* pos = (const double4*)pos4v;
+  const double rc2 = cutoff * cutoff;
+  const int nc = w->nc;
   if (nc >= 3) {
     const double cs = L / nc;
     k_cell_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, cs, nc, rc2, exclude_same_body,

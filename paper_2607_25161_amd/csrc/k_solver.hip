@@ -395,7 +395,7 @@ __global__ void k_gmres_begin(GmresCtl* ctl, const double* __restrict__ rr, doub
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double beta = sqrt(fmax(rr[0], 0.0));
   ctl->beta = beta;
-  ctl->resid = ctl->bn > 0 ? beta / ctl->bn : 0.0;
+  ctl->resid = ctl->bn > 0 ? beta / ctl->bn : 0.0;  // b = 0: x = 0 is exact
   ctl->k_used = 0;
   ctl->breakdown = 0;
   for (int i = 0; i <= ctl->m; ++i) g[i] = 0.0;
@@ -406,6 +406,23 @@ __global__ void k_gmres_begin(GmresCtl* ctl, const double* __restrict__ rr, doub
 
 void launch_gmres_begin(GmresCtl* ctl, const double* rr, double* g, double* scal, hipStream_t st) {
   k_gmres_begin<<<1, 64, 0, st>>>(ctl, rr, g, scal);
+}
+
+__global__ void k_gmres_init(GmresCtl* ctl, const double* __restrict__ bb, double tol, int maxit, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ctl->bn = sqrt(fmax(bb[0], 0.0));
+  ctl->tol = tol;
+  ctl->maxit = maxit;
+  ctl->m = m;
+  ctl->its = 0;
+  ctl->stop = 0;
+  ctl->k_used = 0;
+  ctl->breakdown = 0;
+  ctl->resid = 1.0;
+}
+
+void launch_gmres_init(GmresCtl* ctl, const double* bb, double tol, int maxit, int m, hipStream_t st) {
+  k_gmres_init<<<1, 64, 0, st>>>(ctl, bb, tol, maxit, m);
 }
 
 __global__ void k_scale_by(size_t n, const double* __restrict__ src, const double* __restrict__ scal,

@@ -259,6 +259,65 @@ def test_graph_replays_match_eager(F, precision):
 
 
 # ---------------------------------------------------------------------------------------
+# batches of independent systems
+# ---------------------------------------------------------------------------------------
+
+def _small_uneven(n_sys=6):
+    return fsdgen.uneven_systems(seed=fsdgen.BASE_SEED + 40, n_sys=n_sys, n_range=(40, 400), nb_range=(2, 12),
+                                 phi_range=(0.03, 0.2), tol=1e-8)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_results_equal_alone(F, precision):
+    systems = _small_uneven()
+    alone = []
+    for s0 in systems:
+        s = F.System.from_suspension(s0, precision=precision)
+        U, _, info = s.solve()
+        alone.append(U)
+        s.close()
+    b = F.Batch(1 << 34, 16)
+    live = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+    slots = [b.admit(s) for s in live]
+    assert b.solve() == 0
+    for k, sl in enumerate(slots):
+        info = b.info(sl)
+        assert info.status == 0 and info.rel_residual_fp64 <= 1e-8
+        U, _, _ = live[k].solve()  # same configuration: the batch left the state unchanged
+        assert np.abs(U - alone[k]).max() <= 1e-12 * np.abs(alone[k]).max()
+    # one Euler step in the batch equals one step alone
+    assert b.step(1e-3) == 0
+    for k, s0 in enumerate(systems):
+        s = F.System.from_suspension(s0, precision=precision)
+        s.step(1e-3, 1)
+        X1, q1 = s.state()
+        X2, q2 = live[k].state()
+        assert np.abs(X1 - X2).max() < 1e-12 and np.abs(q1 - q2).max() < 1e-12
+
+
+def test_batch_against_oracle_and_failure_isolation(F):
+    systems = _small_uneven(4)
+    b = F.Batch(1 << 34, 8)
+    live = [F.System.from_suspension(s0) for s0 in systems]
+    bad = F.System.from_suspension(systems[0], gmres_maxit=1)
+    slots = [b.admit(s) for s in live]
+    sbad = b.admit(bad)
+    assert b.solve() == -3  # the first failure is reported
+    assert b.info(sbad).status == -3
+    for k, s0 in enumerate(systems[:2]):
+        assert b.info(slots[k]).status == 0
+        U, _, _ = live[k].solve()
+        Uo, *_ = saddle.solve_suspension(s0)
+        et, er = _vel_errors(U, Uo)
+        assert et < 1e-5 and er < 1e-5, (k, et, er)
+    # admission control by the memory budget
+    tiny = F.Batch(1, 4)
+    assert tiny.try_admit(live[0]) is None
+    b.retire(sbad)
+    assert b.try_admit(bad) is not None
+
+
+# ---------------------------------------------------------------------------------------
 # full-size workloads against stored oracle values
 # ---------------------------------------------------------------------------------------
 
