@@ -28,21 +28,34 @@ METRIC = "bead-solves/s at 1e-5 saddle residual vs plain FP64; p50/p99 solve lat
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_bytes(name, info, prec_bytes, n_lub):
-    """Minimal HBM traffic of one launch of a kernel class (bytes)."""
-    N3 = info.grid ** 3
-    nb = info.n_bead
-    grid = 3 * 2 * N3 * prec_bytes          # three complex component grids
-    bead_io = nb * (32 + 48)                 # position + 6 doubles per bead
-    if name == "real_sum":
-        return 4 * info.nnz_real + nb * (32 + 48 + 48)
-    if name in ("fft_pass", "green_scale"):
-        return 2 * grid
-    if name in ("spread", "interp"):
-        return grid + bead_io
-    if name == "lub":
-        return 44 * n_lub + nb * 48
-    return None
+# kernel behind each timer class (rocprofv3 names), for matching the two measurements
+KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_gather", "fft_x_split": "k_fft_x_split",
+             "fft_y": "k_fft_y_half", "fft_z_green": "k_fft_z_green", "fft_x_merge": "k_fft_x_merge",
+             "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused", "cgs_dot": "k_cgs<0>",
+             "cgs_update": "k_cgs<1>", "cgs_norm_arnoldi": "k_cgs<2>"}
+
+
+def kernel_table(timers, steps):
+    """Per timer class: ms per step, launches, average launch duration and the
+    algorithmic HBM bandwidth (algorithmic bytes of the launches / their time)."""
+    out = {}
+    for k, (ms, n, by) in timers.items():
+        if n == 0:
+            continue
+        out[k] = {"kernel": KERNEL_OF.get(k, k), "ms_per_step": round(ms / steps, 4), "launches": n,
+                  "avg_us": round(1e3 * ms / n, 2), "alg_bytes_per_launch": int(by / n),
+                  "alg_GBps": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+    return out
+
+
+def roofline_of(table, traffic=None):
+    """Dominant kernel (largest total time) against the HBM roofline."""
+    name = max(table, key=lambda k: table[k]["ms_per_step"])
+    r = table[name]
+    ach = r["alg_GBps"]
+    return {"bound": "hbm", "kernel": r["kernel"], "timer": name, "achieved": ach, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": r["alg_bytes_per_launch"], "avg_launch_us": r["avg_us"]}
 
 
 def cpu_baseline(precision_note):
@@ -140,17 +153,19 @@ def bench_serving(args, F, fsdgen, torch):
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
 
-    def run(rate, seed):
+    def run(rate, seed, subset=None, n_steps=args.req_steps):
+        sel = reqs if subset is None else subset
         be = LibBackend(F, budget, args.slots, dict(precision=prec))
         eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
-        t_arr = np.zeros(len(reqs)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(reqs), rate)
-        rs = [Request(k, s, args.req_steps, arrival=float(t_arr[k])) for k, s in enumerate(reqs)]
+        t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
+        rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
         rep = eng.run(rs)
         torch.cuda.synchronize()
         be.batch.close()
         return rep
 
-    run(None, 0) if args.warmup else None          # loads code objects, first-touch allocations
+    if args.warmup:                                 # code objects loaded, first-touch allocations
+        run(None, 0, sorted(reqs, key=lambda s: s.n_bead)[:2], 2)
     closed = run(None, 0)                           # every request queued at t = 0: capacity
     cap = closed["completed"] / closed["span_s"]
     rate = args.load * cap
@@ -177,6 +192,61 @@ def bench_serving(args, F, fsdgen, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_large(args, F, fsdgen, torch):
+    """81,920 beads (4096 clusters of 20, phi 0.20, 128^3): FP64 against mixed precision."""
+    s = fsdgen.config(2)
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for prec_name, prec in (("fp64", F.FSD_FP64), ("mixed", F.FSD_MIXED)):
+        sysm = F.System.from_suspension(s, stream=stream, precision=prec)
+        U0, _, _ = sysm.solve()              # warm-up: lists sized, graphs captured
+        torch.cuda.synchronize()
+        lat, its, rr = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            si = sysm.step(s.dt, 1)
+            lat.append(time.perf_counter() - a)
+            its.append(si.iterations)
+            rr.append(si.rel_residual_fp64)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sysm.set_timing(True)
+        sysm.step(s.dt, 1)
+        table = kernel_table(sysm.timers(), 1)
+        sysm.set_timing(False)
+        info = sysm.info()
+        sysm.close()
+        res[prec_name] = {"value": s.n_bead * sum(1 for r in rr if r <= 1e-5) / el, "ms_per_step": 1e3 * el / args.steps,
+                          "lat": lat, "its": float(np.mean(its)), "max_res": float(max(rr)), "U0": U0,
+                          "table": table, "info": info}
+    m, d = res["mixed"], res["fp64"]
+    du = np.linalg.norm(m["U0"][:, :3] - d["U0"][:, :3]) / np.linalg.norm(d["U0"][:, :3])
+    dw = np.linalg.norm(m["U0"][:, 3:] - d["U0"][:, 3:]) / np.linalg.norm(d["U0"][:, 3:])
+    info = d["info"]
+    out = {
+        "metric": METRIC, "value": round(m["value"], 1), "unit": "bead-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": round(m["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead, "n_agg": s.n_agg,
+                   "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid, "support": info.support,
+                   "xi": info.xi, "r_cut": round(info.r_cut, 3), "nnz_real": int(info.nnz_real), "tol": s.gmres_tol,
+                   "precision": "mixed", "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(m["lat"], 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(m["lat"], 99)), 3)},
+        "gmres_iterations_mean": round(m["its"], 2), "max_rel_residual": m["max_res"],
+        "fp64": {"value": round(d["value"], 1), "ms_per_step": round(d["ms_per_step"], 3),
+                 "gmres_iterations_mean": round(d["its"], 2), "max_rel_residual": d["max_res"],
+                 "kernels": d["table"], "roofline": roofline_of(d["table"])},
+        "speedup_mixed_vs_fp64": round(m["value"] / d["value"], 3),
+        "mixed_vs_fp64_rel_diff": {"U": float(du), "W": float(dw)},
+        "kernels": m["table"],
+        "roofline": roofline_of(m["table"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,7 +254,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["clusters", "batched", "serving"], default="clusters")
+    ap.add_argument("--workload", choices=["clusters", "large", "batched", "serving"], default="clusters")
     ap.add_argument("--systems", type=int, default=64)
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--req-steps", type=int, default=20)
@@ -206,6 +276,8 @@ def main():
         return bench_batched(args, F, fsdgen, torch)
     if args.workload == "serving":
         return bench_serving(args, F, fsdgen, torch)
+    if args.workload == "large":
+        return bench_large(args, F, fsdgen, torch)
     stream = torch.cuda.current_stream()
     s = fsdgen.config(1)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
@@ -239,17 +311,8 @@ def main():
 
     counted = sum(1 for r in res if r <= 1e-5)
     value = s.n_bead * counted / elapsed
-    prec_bytes = 4 if prec == F.FSD_MIXED else 8
-    best = max(((k, v) for k, v in timers.items() if v[1] > 0), key=lambda kv: kv[1][0])
-    name, (tot_ms, launches) = best
-    avg_s = tot_ms / launches / 1e3
-    alg = algorithmic_bytes(name, info, prec_bytes, info.n_lub_pairs)
-    roofline = None
-    if alg is not None:
-        ach = alg / avg_s / 1e9
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(ach, 2), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                    "bytes_per_launch": int(alg), "avg_launch_us": round(avg_s * 1e6, 2)}
+    table = kernel_table(timers, args.steps)
+    roofline = roofline_of(table)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "bead-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
@@ -263,7 +326,7 @@ def main():
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "gmres_iterations_mean": round(float(np.mean(its)), 2),
         "max_rel_residual": float(max(res)),
-        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in timers.items()},
+        "kernels": table,
         "kernel_timing": "HIP events around each launch on the library stream, eager pass of the same step count",
         "roofline": roofline,
     }

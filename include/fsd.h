@@ -149,6 +149,8 @@ fsd_status fsd_get_info(const fsd_system* s, fsd_info* info);
 /* Device bytes a system of this size needs (for admission decisions). */
 size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, double L);
 
+/* Text of the last error of s; with s == NULL, of the calling thread's last failed
+ * call that takes no system (fsd_fft3d).  Owned by the library. */
 const char* fsd_last_error(const fsd_system* s);
 void fsd_destroy(fsd_system* s);
 
@@ -215,16 +217,19 @@ void fsd_batch_destroy(fsd_batch* b);
 /* ---- kernel timing on the system stream (HIP events around each launch) ------------- */
 
 typedef enum {
-  FSD_TIMER_REAL = 0,    /* real-space pair sum                                     */
-  FSD_TIMER_SPREAD = 1,  /* Gaussian spreading to the grid                          */
-  FSD_TIMER_FFT = 2,     /* one x or y transform pass (4 per wave apply)            */
-  FSD_TIMER_GREEN = 3,   /* z transforms fused with the Green's-function scaling    */
-  FSD_TIMER_INTERP = 4,  /* interpolation back to the beads                         */
-  FSD_TIMER_RIGID = 5,   /* Sigma^T V and Sigma reductions                          */
-  FSD_TIMER_LUB = 6,     /* lubrication block product                               */
-  FSD_TIMER_PRECOND = 7, /* preconditioner apply (2 launches)                        */
-  FSD_TIMER_KRYLOV = 8,  /* one CGS2 orthogonalisation (5+ launches)                 */
-  FSD_TIMER_COUNT = 9
+  FSD_TIMER_REAL = 0,        /* real-space pair sum                                       */
+  FSD_TIMER_SPREAD = 1,      /* Gaussian spreading to the grid                            */
+  FSD_TIMER_FFT_X_SPLIT = 2, /* forward x transform into the half spectrum                */
+  FSD_TIMER_FFT_Y = 3,       /* y transform passes over the half spectrum (2 per apply)   */
+  FSD_TIMER_GREEN = 4,       /* z transforms fused with the Green's-function scaling      */
+  FSD_TIMER_FFT_X_MERGE = 5, /* inverse x transform from the half spectrum                */
+  FSD_TIMER_INTERP = 6,      /* interpolation back to the beads, plus Sigma^T V           */
+  FSD_TIMER_RIGID = 7,       /* Sigma reductions with the lubrication product             */
+  FSD_TIMER_PRECOND = 8,     /* preconditioner apply (forms the next basis vector)        */
+  FSD_TIMER_CGS_DOT = 9,     /* first Gram-Schmidt pass, h = V^T w                        */
+  FSD_TIMER_CGS_UPDATE = 10, /* second pass: w -= V h with the new inner products         */
+  FSD_TIMER_CGS_NORM = 11,   /* last update with ||w||^2 and the Arnoldi (Givens) update  */
+  FSD_TIMER_COUNT = 12
 } fsd_timer;
 
 /* GMRES launch mode: enable = 1 replays cached HIP graphs (cycle start, batches of
@@ -236,9 +241,11 @@ fsd_status fsd_set_graphs(fsd_system* s, int enable, int batch);
 /* Enable (1) or disable (0) event timing and reset the accumulators. */
 fsd_status fsd_set_timing(fsd_system* s, int enable);
 
-/* Accumulated milliseconds and launch counts per fsd_timer class since the last
- * fsd_set_timing; both arrays hold FSD_TIMER_COUNT entries.  Synchronises. */
-fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches);
+/* Accumulated milliseconds, launch counts and algorithmic HBM bytes (the minimum
+ * traffic of each launch's inputs and outputs) per fsd_timer class since the last
+ * fsd_set_timing; each array holds FSD_TIMER_COUNT entries, bytes may be NULL.
+ * Synchronises. */
+fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches, double* bytes);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libfsd.so")
 
 if not os.path.exists(library_path):
-    raise ImportError(f"{library_path} is missing: build it with `python -m paper_2607_25161_amd.build`")
+    raise ImportError(f"{library_path} is missing: build it with `python paper_2607_25161_amd/build.py`")
+
+# One HIP runtime per process: PyTorch ships its own libamdhip64.so.7, and the
+# library's dependency of that name must resolve to the copy torch uses (loading
+# the system copy first leaves two runtimes competing for the device).
+import torch  # noqa: E402,F401
 
 lib = C.CDLL(library_path)
 
@@ -82,7 +87,7 @@ _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
 _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
-_sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong))
+_sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
 
 _sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
 _sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
@@ -93,7 +98,8 @@ _sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
 
-TIMER_NAMES = ("real_sum", "spread", "fft_pass", "green_scale", "interp", "rigid", "lub", "precond", "cgs2")
+TIMER_NAMES = ("real_sum", "spread", "fft_x_split", "fft_y", "fft_z_green", "fft_x_merge", "interp", "rigid_lub",
+               "precond", "cgs_dot", "cgs_update", "cgs_norm_arnoldi")
 
 
 class FsdError(RuntimeError):
@@ -134,7 +140,7 @@ def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
     buf = a.view(np.float64).copy()
     rc = lib.fsd_fft3d(n, sign, _dptr(buf))
     if rc:
-        raise FsdError(rc, "fsd_fft3d")
+        raise FsdError(rc, f"fsd_fft3d: {lib.fsd_last_error(None).decode()}")
     return buf.view(np.complex128).reshape(a.shape)
 
 
@@ -272,11 +278,12 @@ class System:
         self._check(lib.fsd_set_timing(self._h, 1 if enable else 0), "fsd_set_timing")
 
     def timers(self):
-        """{class: (total_ms, launches)} since the last set_timing."""
+        """{class: (total_ms, launches, algorithmic_bytes)} since the last set_timing."""
         ms = np.zeros(len(TIMER_NAMES))
+        by = np.zeros(len(TIMER_NAMES))
         cnt = (C.c_longlong * len(TIMER_NAMES))()
-        self._check(lib.fsd_get_timers(self._h, _dptr(ms), cnt), "fsd_get_timers")
-        return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(TIMER_NAMES)}
+        self._check(lib.fsd_get_timers(self._h, _dptr(ms), cnt, _dptr(by)), "fsd_get_timers")
+        return {n: (float(ms[k]), int(cnt[k]), float(by[k])) for k, n in enumerate(TIMER_NAMES)}
 
     # -- convenience ------------------------------------------------------------------
     @classmethod

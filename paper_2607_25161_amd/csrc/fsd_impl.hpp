@@ -103,24 +103,17 @@ void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& 
                    const double* r4 = nullptr, const double* V = nullptr);
 
 // ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
-void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1,
-                           double* wt, hipStream_t st, const int* skip = nullptr);
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,
                       const double* wt, double* f, hipStream_t st, const int* skip = nullptr);
-void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam,
-                       const double* flub, double* y2, hipStream_t st, const int* skip = nullptr);
-void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4,
-                          const double* lu, const int* piv, double drag_t, double drag_r,
-                          const double* r, double* z, double* tmp_agg, hipStream_t st,
-                          const int* skip = nullptr);
 // fused: y2 = Sigma (lambda - R_nf Sigma^T V) with lubrication evaluated on the fly
 // (lrow == nullptr: no lubrication)
 void launch_agg_lub(int na, const int* offsets, const int* body, const double* r4, const double* lam,
                     const double* V, const int* lrow, const uint32_t* lcol, const double* coef, double* y2,
                     hipStream_t st, const int* skip = nullptr);
+// z = P^-1 r; with scal != nullptr, r = scal[0] * src is formed on the fly and stored to vout
 void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
-                          double drag_t, double drag_r, const double* r, double* z, hipStream_t st,
-                          const int* skip = nullptr);
+                          double drag_t, double drag_r, const double* src, const double* scal, double* vout,
+                          double* z, hipStream_t st, const int* skip = nullptr);
 void launch_rhs(int nb, int na, const int* offsets, const int* body, const double* r4,
                 const double* E, const double* force, const double* fnf, double* b1, double* e3,
                 hipStream_t st);
@@ -145,29 +138,35 @@ struct GmresCtl {
 void launch_gmres_begin(GmresCtl* ctl, const double* rr, double* g, double* scal, hipStream_t st);
 // fresh solve: ctl->bn = sqrt(bb), its = 0, tolerance, budget, restart length
 void launch_gmres_init(GmresCtl* ctl, const double* bb, double tol, int maxit, int m, hipStream_t st);
-void launch_scale_by(size_t n, const double* src, const double* scal, double* dst, hipStream_t st,
-                     const int* skip);
-void launch_arnoldi_step(int j, GmresCtl* ctl, const double* h1, const double* h2, const double* hn2,
-                         double* H, double* cs, double* sn, double* g, double* scal, hipStream_t st);
+// Arnoldi step j of the cycle: Hessenberg column from the two Gram-Schmidt passes and the
+// new norm, Givens rotations, residual estimate, stop flag, scal = 1 / H[j+1, j]
+struct ArnoldiArgs {
+  int j;
+  GmresCtl* ctl;
+  const double* h1;
+  const double* h2;
+  double *H, *cs, *sn, *g, *scal;
+};
+void launch_arnoldi_step(const ArnoldiArgs& a, const double* hn2, hipStream_t st);
 void launch_gmres_solve(const GmresCtl* ctl, const double* H, const double* g, double* y, hipStream_t st);
 void launch_basis_combine(size_t n, int m, const double* V, size_t ldv, const double* y, const GmresCtl* ctl,
                           double* out, hipStream_t st);
 
-// dots: partial[q * nblk + b] then out[q]; deterministic two-stage reduction
-int dot_blocks(size_t n);
-void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w,
-                      double* partial, double* out, hipStream_t st, const int* skip = nullptr);
-// one-launch CGS kernels (counters: zeroed device tickets, one per chunk of 8 vectors)
+// one-launch CGS kernels for any restart length (counters: zeroed device tickets, one per chunk of 8 vectors)
 void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
                  unsigned* counters, hipStream_t st, const int* skip = nullptr);
 // w -= V h; then mode 0: out[q] = V_q . w (q < nq), mode 1: out[0] = w . w
 void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
                       double* partial, double* out, unsigned* counters, hipStream_t st,
                       const int* skip = nullptr);
-void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h,
-                       double sgn, double* w, hipStream_t st, const int* skip = nullptr);
-void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst,
-                       hipStream_t st, const int* skip = nullptr);
+// CGS2 passes with the basis held in registers, for nq <= 32 basis vectors (cgs_fits):
+// mode 0 out = V^T w; mode 1 w -= V hin, out = V^T w; mode 2 w -= V hin, out[0] = w.w and the
+// Arnoldi update *arn.  partial needs nq * cgs_blocks(n) doubles; counter is a zeroed ticket.
+bool cgs_fits(int nq);
+int cgs_blocks(size_t n);
+void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
+                double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
+                const ArnoldiArgs* arn);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes a multiple of 4

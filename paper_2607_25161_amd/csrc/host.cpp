@@ -272,7 +272,7 @@ struct fsd_system {
 
   // resumable solve (state machine advanced after each stream synchronisation)
   struct SolveState {
-    enum Phase { IDLE, PREP, START, BATCH, OUTER, DONE } phase = IDLE;
+    enum Phase { IDLE, PREP, START, BATCH, DONE } phase = IDLE;
     const double* b = nullptr;  // right-hand side of the GMRES in progress
     double* x = nullptr;        // its iterate
     bool fp32 = false;
@@ -289,6 +289,7 @@ struct fsd_system {
   // per-kernel-class event timing (fsd_set_timing)
   struct Pending {
     int cls;
+    double bytes;
     hipEvent_t a, b;
   };
   bool timing = false;
@@ -297,6 +298,7 @@ struct fsd_system {
   std::vector<Pending> pending;
   double t_ms[FSD_TIMER_COUNT] = {0};
   long long t_n[FSD_TIMER_COUNT] = {0};
+  double t_bytes[FSD_TIMER_COUNT] = {0};
 
   // captured GMRES graphs
   struct GraphEntry {
@@ -356,6 +358,11 @@ struct fsd_system {
 };
 
 namespace {
+// last error of a call that has no system (fsd_fft3d, batch calls)
+thread_local std::string g_last_error;
+}  // namespace
+
+namespace {
 
 fsd_status fail(fsd_system* s, fsd_status c, const std::string& m) {
   if (s) s->err = m;
@@ -386,6 +393,7 @@ void harvest_timers(fsd_system* s) {
     HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
     s->t_ms[p.cls] += ms;
     s->t_n[p.cls] += 1;
+    s->t_bytes[p.cls] += p.bytes;
   }
   s->pending.clear();
   s->ev_next = 0;
@@ -404,15 +412,16 @@ hipEvent_t next_event(fsd_system* s) {
   return s->ev_pool[s->ev_next++];
 }
 
-// Records events around one kernel launch on the system stream when timing is on.
-// Events around one eager kernel launch on the system stream when timing is on.
+// Events around one eager kernel launch on the system stream when timing is on, with
+// the launch's algorithmic HBM bytes (the minimum traffic of its inputs and outputs).
 // (This runtime cannot time event nodes inside captured graphs, so timed runs
 // launch eagerly; see run_body.)
 struct Timed {
   fsd_system* s;
   int cls;
+  double bytes;
   hipEvent_t a = nullptr;
-  Timed(fsd_system* s_, int c) : s(s_), cls(c) {
+  Timed(fsd_system* s_, int c, double b) : s(s_), cls(c), bytes(b) {
     if (!s->timing || s->capturing) return;
     a = next_event(s);
     HIPCHK(hipEventRecord(a, s->st));
@@ -421,7 +430,7 @@ struct Timed {
     if (!a) return;
     hipEvent_t b = next_event(s);
     HIPCHK(hipEventRecord(b, s->st));
-    s->pending.push_back({cls, a, b});
+    s->pending.push_back({cls, bytes, a, b});
   }
 };
 
@@ -692,7 +701,7 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
       HIPCHK(hipStreamWaitEvent(s->st2, s->ev_fork, 0));
       rs = s->st2;
     }
-    Timed t(s, FSD_TIMER_REAL);
+    Timed t(s, FSD_TIMER_REAL, 4.0 * (s->nb + 1) + 4.0 * s->nnz + 128.0 * s->nb);
     launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr, rs,
                        skip);
     if (fork) HIPCHK(hipEventRecord(s->ev_join, s->st2));
@@ -703,21 +712,26 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
     const int N = s->wp.n;
     const size_t cs = 2 * size_t(N) * N * N;  // R elements per complex component grid
     R* grid = static_cast<R*>(s->d_grid);
+    // algorithmic bytes: six real component grids, six half spectra, bead inputs
+    const double full = 3.0 * cs * sizeof(R), half_sp = 12.0 * (N / 2 + 1) * double(N) * N * sizeof(R);
+    const double beads = 80.0 * s->nb;
     if (s->spread) {
-      Timed t(s, FSD_TIMER_SPREAD);
+      Timed t(s, FSD_TIMER_SPREAD, full + beads);
       launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st, skip);
     } else {
       launch_zero(grid, sizeof(R) * 3 * cs, s->st);
-      Timed t(s, FSD_TIMER_SPREAD);
+      Timed t(s, FSD_TIMER_SPREAD, full + beads);
       launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
     }
     R* half = static_cast<R*>(s->d_half);
     for (int stage = 0; stage < 5; ++stage) {
-      Timed t(s, stage == 2 ? FSD_TIMER_GREEN : FSD_TIMER_FFT);
+      static const int cls_of[5] = {FSD_TIMER_FFT_X_SPLIT, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
+                                    FSD_TIMER_FFT_X_MERGE};
+      Timed t(s, cls_of[stage], (stage == 0 || stage == 4) ? full + half_sp : 2.0 * half_sp);
       launch_wave_fft<R>(grid, half, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
     }
     if (fork) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
-    Timed t(s, FSD_TIMER_INTERP);
+    Timed t(s, FSD_TIMER_INTERP, full + beads + 80.0 * s->nb + (Vr ? 48.0 * s->na : 0.0));
     launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr);
   }
 }
@@ -730,7 +744,7 @@ void apply_saddle(fsd_system* s, const double* x, double* y, const int* skip = n
   const size_t nb6 = 6 * size_t(s->nb);
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
   apply_mobility<R>(s, x, y, 3, skip, x + nb6);
-  Timed t(s, FSD_TIMER_RIGID);
+  Timed t(s, FSD_TIMER_RIGID, 80.0 * s->nb + 96.0 * s->na + (lub ? 4.0 * (s->nb + 1) + 44.0 * s->nlub : 0.0));
   launch_agg_lub(s->na, s->d_offsets, s->d_body, s->d_r4, x, x + nb6, lub ? s->d_lrow : nullptr, s->d_lcol,
                  s->d_lcoef, y + nb6, s->st, skip);
 }
@@ -742,11 +756,14 @@ void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32, const 
     apply_saddle<double>(s, x, y, skip);
 }
 
-void apply_precond(fsd_system* s, const double* r, double* z, const int* skip = nullptr) {
-  Timed t(s, FSD_TIMER_PRECOND);
+// z = P^-1 r.  With scal != nullptr, r = scal[0] * src is formed on the fly and stored to
+// vout (the Krylov basis vector of this step).
+void apply_precond(fsd_system* s, const double* src, double* z, const int* skip = nullptr,
+                   const double* scal = nullptr, double* vout = nullptr) {
+  Timed t(s, FSD_TIMER_PRECOND, 8.0 * s->n * (vout ? 3 : 2) + 32.0 * s->nb + 312.0 * s->na);
   // M~^-1 = diag(6 pi eta a, 8 pi eta a^3): the bead drag (inverse self-mobility)
-  launch_precond_fused(s->nb, s->na, s->d_offsets, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, r, z, s->st,
-                       skip);
+  launch_precond_fused(s->nb, s->na, s->d_offsets, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, src, scal, vout,
+                       z, s->st, skip);
 }
 
 void assemble_rhs(fsd_system* s) {
@@ -790,7 +807,6 @@ void seg_cycle_start(fsd_system* s) {
     launch_sub(n, b, s->d_t, s->d_r, s->st);
     launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, hn2, s->d_counters, s->st);
     launch_gmres_begin(s->d_ctl, hn2, s->d_g, s->d_scal, s->st);
-    launch_scale_by(n, s->d_r, s->d_scal, s->d_basis, s->st, stop);
   });
   HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
 }
@@ -809,14 +825,37 @@ void seg_batch(fsd_system* s, int j0) {
   const bool fp32 = v.fp32;
   run_body(s, {1, j0, cnt, fp32 ? 1 : 0, nullptr, nullptr}, [&] {
     for (int j = j0; j < j0 + cnt; ++j) {
-      apply_precond(s, V + size_t(j) * n, s->d_z, stop);
+      // v_j = w / H[j, j-1] (r / beta for j = 0) is formed inside the preconditioner
+      apply_precond(s, j == 0 ? s->d_r : s->d_w, s->d_z, stop, s->d_scal, V + size_t(j) * n);
       apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
-      Timed t(s, FSD_TIMER_KRYLOV);  // CGS2 + Givens
-      launch_dots(n, j + 1, V, n, s->d_w, s->d_part, h1, s->d_counters, s->st, stop);
-      launch_axpy_dots(n, j + 1, V, n, h1, s->d_w, 0, s->d_part, h2, s->d_counters, s->st, stop);
-      launch_axpy_dots(n, j + 1, V, n, h2, s->d_w, 1, s->d_part, hn2, s->d_counters, s->st, stop);
-      launch_arnoldi_step(j, s->d_ctl, h1, h2, hn2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal, s->st);
-      launch_scale_by(n, s->d_w, s->d_scal, V + size_t(j + 1) * n, s->st, stop);
+      const ArnoldiArgs arn{j, s->d_ctl, h1, h2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal};
+      const int nq = j + 1;
+      if (cgs_fits(nq)) {
+        {
+          Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));
+          launch_cgs(0, n, nq, V, n, nullptr, s->d_w, s->d_part, h1, s->d_counters, s->st, stop, nullptr);
+        }
+        {
+          Timed t(s, FSD_TIMER_CGS_UPDATE, 8.0 * n * (nq + 2));
+          launch_cgs(1, n, nq, V, n, h1, s->d_w, s->d_part, h2, s->d_counters, s->st, stop, nullptr);
+        }
+        Timed t(s, FSD_TIMER_CGS_NORM, 8.0 * n * (nq + 2));
+        launch_cgs(2, n, nq, V, n, h2, s->d_w, s->d_part, hn2, s->d_counters, s->st, stop, &arn);
+      } else {
+        {
+          Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));
+          launch_dots(n, nq, V, n, s->d_w, s->d_part, h1, s->d_counters, s->st, stop);
+        }
+        {
+          Timed t(s, FSD_TIMER_CGS_UPDATE, 8.0 * n * (nq + 2));
+          launch_axpy_dots(n, nq, V, n, h1, s->d_w, 0, s->d_part, h2, s->d_counters, s->st, stop);
+        }
+        {
+          Timed t(s, FSD_TIMER_CGS_NORM, 8.0 * n * (nq + 2));
+          launch_axpy_dots(n, nq, V, n, h2, s->d_w, 1, s->d_part, hn2, s->d_counters, s->st, stop);
+        }
+        launch_arnoldi_step(arn, hn2, s->st);
+      }
     }
   });
   HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
@@ -850,18 +889,6 @@ void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp
   v.phase = fsd_system::SolveState::START;
 }
 
-// FP64 outer residual of the mixed-precision refinement: r = b - A64 x, ||r||^2, ||b||^2
-void seg_outer(fsd_system* s) {
-  const size_t n = s->n;
-  apply_saddle<double>(s, s->d_x, s->d_t);
-  launch_sub(n, s->d_b, s->d_t, s->d_r, s->st);
-  double* sc = s->d_h + 2 * (s->m + 1) + 2;
-  launch_dots(n, 1, s->d_r, n, s->d_r, s->d_part, sc, s->d_counters, s->st);
-  launch_dots(n, 1, s->d_b, n, s->d_b, s->d_part, sc + 1, s->d_counters, s->st);
-  HIPCHK(hipMemcpyAsync(s->h_scal, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
-  s->sv.phase = fsd_system::SolveState::OUTER;
-}
-
 void finish_solve(fsd_system* s, bool ok) {
   const size_t nb6 = 6 * size_t(s->nb);
   launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
@@ -872,8 +899,6 @@ void finish_solve(fsd_system* s, bool ok) {
 }
 
 // the correction of one mixed-precision refinement lives after the Krylov basis
-double* mixed_corr(fsd_system* s) { return s->d_basis + size_t(s->m + 1) * s->n; }
-double* mixed_rhs(fsd_system* s) { return s->d_basis + size_t(s->m + 2) * s->n; }
 
 // begin a solve at the current configuration (asynchronous)
 void solve_begin(fsd_system* s) {
@@ -926,19 +951,6 @@ bool solve_advance(fsd_system* s) {
         v.j0 += S;
         seg_batch(s, v.j0);
       }
-      return true;
-    }
-    case SS::OUTER: {
-      check_flags(s);
-      const double rr = s->h_scal[0], bb = s->h_scal[1];
-      v.rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-      if (v.rel <= s->p.gmres_tol || v.its >= s->p.gmres_maxit || v.outer >= 50) {
-        finish_solve(s, v.rel <= s->p.gmres_tol);
-        return false;
-      }
-      ++v.outer;
-      HIPCHK(hipMemcpyAsync(mixed_rhs(s), s->d_r, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
-      gmres_launch(s, mixed_rhs(s), mixed_corr(s), s->p.inner_tol, true, s->p.gmres_maxit - v.its);
       return true;
     }
     default:
@@ -1112,7 +1124,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     const size_t n = s->n;
     s->d_b = dalloc<double>(o, n);
     s->d_x = dalloc<double>(o, n);
-    s->d_basis = dalloc<double>(o, size_t(s->m + 3) * n);
+    s->d_basis = dalloc<double>(o, size_t(s->m + 1) * n);
     s->d_z = dalloc<double>(o, n);
     s->d_w = dalloc<double>(o, n);
     s->d_t = dalloc<double>(o, n);
@@ -1120,7 +1132,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_wt = dalloc<double>(o, 3 * size_t(nb));
     s->d_fl = dalloc<double>(o, 3 * size_t(nb));
     s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 16);
-    s->d_part = dalloc<double>(o, size_t(s->m + 2) * 1024);
+    s->d_part = dalloc<double>(o, std::max(size_t(s->m + 2) * 1024, size_t(32) * cgs_blocks(n)));
     s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
     HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
     HIPCHK(hipHostMalloc((void**)&s->h_ctl, sizeof(GmresCtl)));
@@ -1344,7 +1356,7 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t nb, int32_t na, double L)
   return size_t(bytes);
 }
 
-const char* fsd_last_error(const fsd_system* s) { return s ? s->err.c_str() : "null system"; }
+const char* fsd_last_error(const fsd_system* s) { return s ? s->err.c_str() : g_last_error.c_str(); }
 
 void fsd_destroy(fsd_system* s) {
   if (!s) return;
@@ -1453,6 +1465,7 @@ fsd_status fsd_set_timing(fsd_system* s, int enable) {
     for (int k = 0; k < FSD_TIMER_COUNT; ++k) {
       s->t_ms[k] = 0;
       s->t_n[k] = 0;
+      s->t_bytes[k] = 0;
     }
     if ((enable != 0) != s->timing) s->drop_graphs();  // event nodes are captured or not
     s->timing = enable != 0;
@@ -1460,13 +1473,14 @@ fsd_status fsd_set_timing(fsd_system* s, int enable) {
   });
 }
 
-fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches) {
+fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches, double* bytes) {
   if (!s || !total_ms || !launches) return FSD_EINVAL;
   return guarded(s, [&]() -> fsd_status {
     harvest_timers(s);
     for (int k = 0; k < FSD_TIMER_COUNT; ++k) {
       total_ms[k] = s->t_ms[k];
       launches[k] = s->t_n[k];
+      if (bytes) bytes[k] = s->t_bytes[k];
     }
     return FSD_OK;
   });
@@ -1494,8 +1508,10 @@ fsd_status fsd_fft3d(int n, int sign, double* data) {
     HIPCHK(hipMemcpy(data, d, sizeof(double) * count, hipMemcpyDeviceToHost));
   } catch (const ApiError& e) {
     rc = e.code;
-  } catch (const std::exception&) {
+    g_last_error = e.what();
+  } catch (const std::exception& e) {
     rc = FSD_EDEVICE;
+    g_last_error = e.what();
   }
   for (void* q : owned) (void)hipFree(q);
   return rc;

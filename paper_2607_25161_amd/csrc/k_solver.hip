@@ -9,38 +9,6 @@ constexpr int kThreads = 256;
 inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t); }
 }  // namespace
 
-// Sigma^T V: rigid velocity of bead i of body j, (U_j + W_j x r_i, W_j), added to
-// y1; its translational part also goes to wt (input of the lubrication product).
-__global__ void k_rigid_velocity(int nb, const int* __restrict__ body, const double4* __restrict__ r4,
-                                 const double* __restrict__ V, double* __restrict__ y1, double* __restrict__ wt, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const int j = body[i];
-  const double* v = V + 6 * j;
-  const double4 r = r4[i];
-  const double ux = v[0] + (v[4] * r.z - v[5] * r.y);
-  const double uy = v[1] + (v[5] * r.x - v[3] * r.z);
-  const double uz = v[2] + (v[3] * r.y - v[4] * r.x);
-  double* y = y1 + 6 * i;
-  y[0] += ux;
-  y[1] += uy;
-  y[2] += uz;
-  y[3] += v[3];
-  y[4] += v[4];
-  y[5] += v[5];
-  if (wt) {
-    wt[3 * i] = ux;
-    wt[3 * i + 1] = uy;
-    wt[3 * i + 2] = uz;
-  }
-}
-
-void launch_rigid_velocity(int nb, const int* body, const double* r4, const double* V, double* y1, double* wt,
-                           hipStream_t st, const int* skip) {
-  k_rigid_velocity<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, V, y1, wt, skip);
-}
-
 // f_i = -sum_k R_pair,ik (w_i - w_k), R_pair = X nn + Y (I - nn)
 __global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32_t* __restrict__ col,
                             const double* __restrict__ coef, const double* __restrict__ wt, double* __restrict__ f, const int* __restrict__ skip) {
@@ -67,115 +35,6 @@ __global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef, const double* wt, double* f,
                       hipStream_t st, const int* skip) {
   k_lub_apply<<<nblocks(nb), kThreads, 0, st>>>(nb, rowptr, col, coef, wt, f, skip);
-}
-
-// Sigma (lambda + (f_lub, 0)): per body (sum f, sum t + r x f)
-__global__ void k_agg_reduce(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
-                             const double* __restrict__ lam, const double* __restrict__ flub, double* __restrict__ y2, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= na) return;
-  double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
-  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
-    const double* l = lam + 6 * i;
-    double fx = l[0], fy = l[1], fz = l[2];
-    if (flub) {
-      fx += flub[3 * i];
-      fy += flub[3 * i + 1];
-      fz += flub[3 * i + 2];
-    }
-    const double4 r = r4[i];
-    F[0] += fx;
-    F[1] += fy;
-    F[2] += fz;
-    T[0] += l[3] + (r.y * fz - r.z * fy);
-    T[1] += l[4] + (r.z * fx - r.x * fz);
-    T[2] += l[5] + (r.x * fy - r.y * fx);
-  }
-  double* y = y2 + 6 * j;
-  y[0] = F[0];
-  y[1] = F[1];
-  y[2] = F[2];
-  y[3] = T[0];
-  y[4] = T[1];
-  y[5] = T[2];
-}
-
-void launch_agg_reduce(int na, const int* offsets, const double* r4, const double* lam, const double* flub,
-                       double* y2, hipStream_t st, const int* skip) {
-  k_agg_reduce<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, lam, flub, y2, skip);
-}
-
-// ------------------------------------------------------------------------------------------
-// preconditioner apply (Section 2.3.3):
-//   y2 = r2 - Sigma M~^-1 r1,  z2 = -A_j^-1 y2,  z1 = M~^-1 (r1 - Sigma^T z2)
-// ------------------------------------------------------------------------------------------
-
-__global__ void k_precond_agg(int nb, int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
-                              const double* __restrict__ lu, const int* __restrict__ piv, double drag_t, double drag_r,
-                              const double* __restrict__ r, double* __restrict__ z, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= na) return;
-  double y[6];
-  const double* r2 = r + 6 * size_t(nb) + 6 * j;
-  for (int c = 0; c < 6; ++c) y[c] = r2[c];
-  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
-    const double* l = r + 6 * size_t(i);
-    const double fx = drag_t * l[0], fy = drag_t * l[1], fz = drag_t * l[2];
-    const double4 rv = r4[i];
-    y[0] -= fx;
-    y[1] -= fy;
-    y[2] -= fz;
-    y[3] -= drag_r * l[3] + (rv.y * fz - rv.z * fy);
-    y[4] -= drag_r * l[4] + (rv.z * fx - rv.x * fz);
-    y[5] -= drag_r * l[5] + (rv.x * fy - rv.y * fx);
-  }
-  // solve A x = y with the stored LU (P A = L U)
-  const double* A = lu + 36 * j;
-  const int* p = piv + 6 * j;
-  for (int k = 0; k < 6; ++k) {
-    const int q = p[k];
-    if (q != k) {
-      const double t = y[k];
-      y[k] = y[q];
-      y[q] = t;
-    }
-  }
-  for (int a = 1; a < 6; ++a)
-    for (int b = 0; b < a; ++b) y[a] -= A[6 * a + b] * y[b];
-  for (int a = 5; a >= 0; --a) {
-    for (int b = a + 1; b < 6; ++b) y[a] -= A[6 * a + b] * y[b];
-    y[a] /= A[6 * a + a];
-  }
-  double* z2 = z + 6 * size_t(nb) + 6 * j;
-  for (int c = 0; c < 6; ++c) z2[c] = -y[c];
-}
-
-__global__ void k_precond_bead(int nb, const int* __restrict__ body, const double4* __restrict__ r4, double drag_t,
-                               double drag_r, const double* __restrict__ r, double* __restrict__ z, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  const double* v = z + 6 * size_t(nb) + 6 * body[i];
-  const double4 rv = r4[i];
-  const double* l = r + 6 * size_t(i);
-  double* o = z + 6 * size_t(i);
-  o[0] = drag_t * (l[0] - (v[0] + (v[4] * rv.z - v[5] * rv.y)));
-  o[1] = drag_t * (l[1] - (v[1] + (v[5] * rv.x - v[3] * rv.z)));
-  o[2] = drag_t * (l[2] - (v[2] + (v[3] * rv.y - v[4] * rv.x)));
-  o[3] = drag_r * (l[3] - v[3]);
-  o[4] = drag_r * (l[4] - v[4]);
-  o[5] = drag_r * (l[5] - v[5]);
-}
-
-void launch_precond_apply(int nb, int na, const int* offsets, const int* body, const double* r4, const double* lu,
-                          const int* piv, double drag_t, double drag_r, const double* r, double* z, double* tmp_agg,
-                          hipStream_t st, const int* skip) {
-  (void)tmp_agg;
-  k_precond_agg<<<nblocks(na, 128), 128, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z,
-                                                   skip);
-  k_precond_bead<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, drag_t, drag_r, r, z, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -262,18 +121,6 @@ namespace {
 constexpr int kDotThreads = 256;
 constexpr int kDotChunk = 8;  // basis vectors reduced per pass
 
-__device__ inline double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0;
-  if (threadIdx.x == 0)
-    for (int k = 0; k < kDotThreads / 64; ++k) s += sh[k];
-  return s;
-}
 }  // namespace
 
 int dot_blocks(size_t n) {
@@ -281,76 +128,6 @@ int dot_blocks(size_t n) {
   if (b > 1024) b = 1024;
   if (b < 1) b = 1;
   return int(b);
-}
-
-__global__ __launch_bounds__(kDotThreads) void k_multi_dot(size_t n, int q0, int nq, const double* __restrict__ V,
-                                                           size_t ldv, const double* __restrict__ w,
-                                                           double* __restrict__ partial, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ double sh[kDotThreads / 64];
-  double acc[kDotChunk];
-#pragma unroll
-  for (int c = 0; c < kDotChunk; ++c) acc[c] = 0;
-  const int cnt = min(kDotChunk, nq - q0);
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
-    const double wi = w[i];
-#pragma unroll
-    for (int c = 0; c < kDotChunk; ++c)
-      if (c < cnt) acc[c] += V[size_t(q0 + c) * ldv + i] * wi;
-  }
-  for (int c = 0; c < cnt; ++c) {
-    const double s = block_sum(acc[c], sh);
-    if (threadIdx.x == 0) partial[size_t(q0 + c) * gridDim.x + blockIdx.x] = s;
-  }
-}
-
-__global__ __launch_bounds__(kDotThreads) void k_dot_final(int nblk, const double* __restrict__ partial,
-                                                           double* __restrict__ out, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ double sh[kDotThreads / 64];
-  const int q = blockIdx.x;
-  double v = 0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[size_t(q) * nblk + b];
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) out[q] = s;
-}
-
-void launch_multi_dot(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
-                      hipStream_t st, const int* skip) {
-  const int nb = dot_blocks(n);
-  for (int q0 = 0; q0 < nq; q0 += kDotChunk)
-    k_multi_dot<<<nb, kDotThreads, 0, st>>>(n, q0, nq, V, ldv, w, partial, skip);
-  k_dot_final<<<nq, kDotThreads, 0, st>>>(nb, partial, out, skip);
-}
-
-// w += sgn * sum_q h[q] V_q
-__global__ void k_multi_axpy(size_t n, int nq, const double* __restrict__ V, size_t ldv, const double* __restrict__ h,
-                             double sgn, double* __restrict__ w, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0;
-  for (int q = 0; q < nq; ++q) s += h[q] * V[size_t(q) * ldv + i];
-  w[i] += sgn * s;
-}
-
-void launch_multi_axpy(size_t n, int nq, const double* V, size_t ldv, const double* h, double sgn, double* w,
-                       hipStream_t st, const int* skip) {
-  k_multi_axpy<<<nblocks((long long)n), kThreads, 0, st>>>(n, nq, V, ldv, h, sgn, w, skip);
-}
-
-// dst = src / s_dev[0]
-__global__ void k_scale_copy(size_t n, const double* __restrict__ src, const double* __restrict__ s,
-                             double* __restrict__ dst, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  dst[i] = src[i] / s[0];
-}
-
-void launch_scale_copy(size_t n, const double* src, const double* s_dev, double* dst, hipStream_t st,
-                       const int* skip) {
-  k_scale_copy<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, s_dev, dst, skip);
 }
 
 __global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -425,55 +202,43 @@ void launch_gmres_init(GmresCtl* ctl, const double* bb, double tol, int maxit, i
   k_gmres_init<<<1, 64, 0, st>>>(ctl, bb, tol, maxit, m);
 }
 
-__global__ void k_scale_by(size_t n, const double* __restrict__ src, const double* __restrict__ scal,
-                           double* __restrict__ dst, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  dst[i] = src[i] * scal[0];
-}
-
-void launch_scale_by(size_t n, const double* src, const double* scal, double* dst, hipStream_t st, const int* skip) {
-  k_scale_by<<<nblocks((long long)n), kThreads, 0, st>>>(n, src, scal, dst, skip);
-}
-
 // Arnoldi step j: H[:, j] = h1 + h2 (classical Gram-Schmidt, twice), H[j+1, j] = ||w||;
 // previous Givens rotations applied, a new one formed, g updated; stop flag raised
 // when |g_{j+1}| / ||b|| <= tol, the cycle is full, the budget is spent, or on breakdown.
-__global__ void k_arnoldi_step(int j, GmresCtl* ctl, const double* __restrict__ h1, const double* __restrict__ h2,
-                               const double* __restrict__ hn2, double* __restrict__ H, double* __restrict__ cs,
-                               double* __restrict__ sn, double* __restrict__ g, double* __restrict__ scal) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void arnoldi_update(const ArnoldiArgs& a, double hn2) {
+  GmresCtl* ctl = a.ctl;
   if (ctl->stop) return;
-  const int m = ctl->m;
-  double col[256];
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double hn = sqrt(fmax(hn2[0], 0.0));
+  const int j = a.j, m = ctl->m;
+  const double hn = sqrt(fmax(hn2, 0.0));
+  // column j of H, rotated by the previous Givens rotations as it streams in
+  double ci = a.h1[0] + a.h2[0];
   for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    const double u = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
-    col[i + 1] = u;
+    const double next = a.h1[i + 1] + a.h2[i + 1];
+    a.H[size_t(i) * m + j] = a.cs[i] * ci + a.sn[i] * next;
+    ci = -a.sn[i] * ci + a.cs[i] * next;
   }
-  const double den = hypot(col[j], hn);
-  const double c = den > 0 ? col[j] / den : 1.0, s = den > 0 ? hn / den : 0.0;
-  cs[j] = c;
-  sn[j] = s;
-  col[j] = den;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
-  for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = col[i];
+  const double den = hypot(ci, hn);
+  const double c = den > 0 ? ci / den : 1.0, s = den > 0 ? hn / den : 0.0;
+  a.cs[j] = c;
+  a.sn[j] = s;
+  a.H[size_t(j) * m + j] = den;
+  a.g[j + 1] = -s * a.g[j];
+  a.g[j] = c * a.g[j];
   ctl->k_used = j + 1;
   ctl->its += 1;
-  ctl->resid = fabs(g[j + 1]) / ctl->bn;
+  ctl->resid = fabs(a.g[j + 1]) / ctl->bn;
   if (hn == 0.0) ctl->breakdown = 1;
   if (ctl->resid <= ctl->tol || j + 1 == m || ctl->its >= ctl->maxit || hn == 0.0) ctl->stop = 1;
-  scal[0] = hn > 0 ? 1.0 / hn : 0.0;
+  a.scal[0] = hn > 0 ? 1.0 / hn : 0.0;
 }
 
-void launch_arnoldi_step(int j, GmresCtl* ctl, const double* h1, const double* h2, const double* hn2, double* H,
-                         double* cs, double* sn, double* g, double* scal, hipStream_t st) {
-  k_arnoldi_step<<<1, 64, 0, st>>>(j, ctl, h1, h2, hn2, H, cs, sn, g, scal);
+__global__ void k_arnoldi_step(ArnoldiArgs a, const double* __restrict__ hn2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  arnoldi_update(a, hn2[0]);
+}
+
+void launch_arnoldi_step(const ArnoldiArgs& a, const double* hn2, hipStream_t st) {
+  k_arnoldi_step<<<1, 64, 0, st>>>(a, hn2);
 }
 
 // y = R^-1 g over the k_used leading rows of the rotated Hessenberg matrix
@@ -586,19 +351,28 @@ void launch_agg_lub(int na, const int* offsets, const int* body, const double* r
   k_agg_lub<<<(na + 3) / 4, 256, 0, st>>>(na, offsets, body, (const double4*)r4, lam, V, lrow, lcol, coef, y2, skip);
 }
 
-// preconditioner in one launch: the wavefront of aggregate j reduces y2 = r2 - Sigma M~^-1 r1
-// over its beads, solves z2 = -A_j^-1 y2 in lane 0, and writes z1 = M~^-1 (r1 - Sigma^T z2)
+// Preconditioner apply of Section 2.3.3 (block-triangular, block-diagonal Schur
+// approximation) in one launch: the wavefront of aggregate j reduces y2 = r2 - Sigma M~^-1 r1
+// over its beads, solves z2 = -A_j^-1 y2 in lane 0, and writes z1 = M~^-1 (r1 - Sigma^T z2).
+// With scal != nullptr the input is r = scal[0] * src, and r is also stored to vout
+// (the next Krylov basis vector is formed here instead of in a separate launch).
 __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int* __restrict__ offsets,
                                                        const double4* __restrict__ r4, const double* __restrict__ lu,
                                                        const int* __restrict__ piv, double drag_t, double drag_r,
-                                                       const double* __restrict__ r, double* __restrict__ z,
+                                                       const double* __restrict__ src, const double* __restrict__ scal,
+                                                       double* __restrict__ vout, double* __restrict__ z,
                                                        const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= na) return;
+  const double sc = scal ? scal[0] : 1.0;
   double p[6] = {0, 0, 0, 0, 0, 0};
   for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
-    const double* l = r + 6 * size_t(i);
+    const double* ls = src + 6 * size_t(i);
+    double l[6];
+    for (int c = 0; c < 6; ++c) l[c] = sc * ls[c];
+    if (scal)
+      for (int c = 0; c < 6; ++c) vout[6 * size_t(i) + c] = l[c];
     const double fx = drag_t * l[0], fy = drag_t * l[1], fz = drag_t * l[2];
     const double4 rv = r4[i];
     p[0] += fx;
@@ -609,8 +383,10 @@ __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int
     p[5] += drag_r * l[5] + (rv.x * fy - rv.y * fx);
   }
   double y[6];
-  const double* r2 = r + 6 * size_t(nb) + 6 * j;
-  for (int c = 0; c < 6; ++c) y[c] = r2[c] - wsum(p[c]);
+  const double* r2 = src + 6 * size_t(nb) + 6 * j;
+  for (int c = 0; c < 6; ++c) y[c] = sc * r2[c] - wsum(p[c]);
+  if (scal && lane == 0)
+    for (int c = 0; c < 6; ++c) vout[6 * size_t(nb) + 6 * j + c] = sc * r2[c];
   // every lane solves the same 6x6 system (uniform work, no broadcast needed)
   const double* A = lu + 36 * size_t(j);
   const int* pv = piv + 6 * size_t(j);
@@ -635,7 +411,9 @@ __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int
   }
   for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
     const double4 rv = r4[i];
-    const double* l = r + 6 * size_t(i);
+    const double* ls = src + 6 * size_t(i);
+    double l[6];
+    for (int c = 0; c < 6; ++c) l[c] = sc * ls[c];
     double* o = z + 6 * size_t(i);
     o[0] = drag_t * (l[0] - (y[0] + (y[4] * rv.z - y[5] * rv.y)));
     o[1] = drag_t * (l[1] - (y[1] + (y[5] * rv.x - y[3] * rv.z)));
@@ -647,9 +425,10 @@ __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int
 }
 
 void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
-                          double drag_t, double drag_r, const double* r, double* z, hipStream_t st, const int* skip) {
-  k_precond_fused<<<(na + 3) / 4, 256, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, r, z,
-                                                 skip);
+                          double drag_t, double drag_r, const double* src, const double* scal, double* vout, double* z,
+                          hipStream_t st, const int* skip) {
+  k_precond_fused<<<(na + 3) / 4, 256, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, src,
+                                                 scal, vout, z, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -769,6 +548,146 @@ void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w,
 void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
                       double* partial, double* out, unsigned* counters, hipStream_t st, const int* skip) {
   k_axpy_dots<<<dot_blocks(n), kDotThreads, 0, st>>>(n, nq, V, ldv, h, w, mode, partial, out, counters, skip);
+}
+
+// ------------------------------------------------------------------------------------------
+// CGS2 passes with the basis in registers (restart length < kCgsMax).  One wavefront per
+// block: each lane holds its element of every basis vector, so the update and the new
+// inner products read the basis once, and the per-block sums need no LDS or barrier.
+// The nq block sums are reduced across the wavefront by recursive halving (31 lane
+// exchanges for 32 values instead of 6 per value).  The last block to finish adds the
+// per-block partials in a fixed order (deterministic) and resets its ticket.
+// ------------------------------------------------------------------------------------------
+
+namespace {
+constexpr int kCgsMax = 32;
+constexpr int kCgsBlocks = 512;
+
+// halving step: lanes with (lane & D) keep the upper half of a[0..2C), the others the
+// lower half; the half given away is added by the partner lane (lane ^ D)
+template <int C, int D>
+__device__ inline void halve(double (&a)[kCgsMax], int lane) {
+  const bool up = (lane & D) != 0;
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const double send = up ? a[j] : a[j + C];
+    const double keep = up ? a[j + C] : a[j];
+    a[j] = keep + __shfl_xor(send, D, 64);
+  }
+}
+
+// total over the 64 lanes of a[q], returned in every lane whose cgs_q(lane) == q
+__device__ inline double wave_transpose_sum(double (&a)[kCgsMax], int lane) {
+  halve<16, 32>(a, lane);
+  halve<8, 16>(a, lane);
+  halve<4, 8>(a, lane);
+  halve<2, 4>(a, lane);
+  halve<1, 2>(a, lane);
+  return a[0] + __shfl_xor(a[0], 1, 64);
+}
+
+__device__ inline int cgs_q(int lane) {
+  return ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+         ((lane >> 1) & 1);
+}
+
+__device__ inline double wave_total(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+}  // namespace
+
+int cgs_blocks(size_t n) {
+  long long b = (long long)((n + 63) / 64);
+  return int(b < 1 ? 1 : (b > kCgsBlocks ? kCgsBlocks : b));
+}
+
+// MODE 0: out[q] = V_q . w                        (first Gram-Schmidt pass)
+// MODE 1: w -= sum_q hin[q] V_q; out[q] = V_q . w (second pass, fused with the first update)
+// MODE 2: w -= sum_q hin[q] V_q; out[0] = w . w, and the last block runs the Arnoldi update
+template <int MODE>
+__global__ __launch_bounds__(64) void k_cgs(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                            const double* __restrict__ hin, double* __restrict__ w,
+                                            double* __restrict__ partial, double* __restrict__ out,
+                                            unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x;
+  double h[kCgsMax], acc[kCgsMax];
+#pragma unroll
+  for (int q = 0; q < kCgsMax; ++q) {
+    h[q] = (MODE >= 1 && q < nq) ? hin[q] : 0.0;
+    acc[q] = 0.0;
+  }
+  for (size_t i = size_t(blockIdx.x) * 64 + lane; i < n; i += size_t(gridDim.x) * 64) {
+    double v[kCgsMax];
+#pragma unroll
+    for (int q = 0; q < kCgsMax; ++q) v[q] = q < nq ? V[size_t(q) * ldv + i] : 0.0;
+    double wi = w[i];
+    if (MODE >= 1) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kCgsMax; ++q) s += h[q] * v[q];
+      wi -= s;
+      w[i] = wi;
+    }
+    if (MODE <= 1) {
+#pragma unroll
+      for (int q = 0; q < kCgsMax; ++q) acc[q] += v[q] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  const int nout = MODE <= 1 ? nq : 1;
+  const int nblk = gridDim.x;
+  if (MODE <= 1) {
+    const double tot = wave_transpose_sum(acc, lane);
+    const int q = cgs_q(lane);
+    if (!(lane & 1) && q < nout) partial[size_t(q) * nblk + blockIdx.x] = tot;
+  } else {
+    const double tot = wave_total(acc[0]);
+    if (lane == 0) partial[blockIdx.x] = tot;
+  }
+  __threadfence();
+  unsigned ticket = 0;
+  if (lane == 0) ticket = atomicAdd(counter, 1u);
+  ticket = __shfl(ticket, 0, 64);
+  if (ticket != unsigned(nblk - 1)) return;
+  __threadfence();
+#pragma unroll
+  for (int q = 0; q < kCgsMax; ++q) acc[q] = 0.0;
+  for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
+    for (int q = 0; q < kCgsMax; ++q)
+      if (q < nout) acc[q] += partial[size_t(q) * nblk + b];
+  }
+  if (MODE <= 1) {
+    const double tot = wave_transpose_sum(acc, lane);
+    const int q = cgs_q(lane);
+    if (!(lane & 1) && q < nout) out[q] = tot;
+  } else {
+    const double tot = wave_total(acc[0]);
+    if (lane == 0) {
+      out[0] = tot;
+      arnoldi_update(arn, tot);
+    }
+  }
+  if (lane == 0) *counter = 0u;
+}
+
+bool cgs_fits(int nq) { return nq >= 1 && nq <= kCgsMax; }
+
+void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
+                double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
+                const ArnoldiArgs* arn) {
+  const ArnoldiArgs a = arn ? *arn : ArnoldiArgs{};
+  const int g = cgs_blocks(n);
+  if (mode == 0)
+    k_cgs<0><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+  else if (mode == 1)
+    k_cgs<1><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+  else
+    k_cgs<2><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
 }
 
 }  // namespace fsd
