@@ -29,10 +29,15 @@ PEAK_HBM_GBS = 8000.0
 
 
 # kernel behind each timer class (rocprofv3 names), for matching the two measurements
-KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_gather", "fft_x_split": "k_fft_x_split",
+KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_cols", "fft_x_split": "k_fft_x_split",
              "fft_y": "k_fft_y_half", "fft_z_green": "k_fft_z_green", "fft_x_merge": "k_fft_x_merge",
              "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused", "cgs_dot": "k_cgs<0>",
              "cgs_update": "k_cgs<1>", "cgs_norm_arnoldi": "k_cgs<2>"}
+
+
+def progress(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_table(timers, steps):
@@ -98,9 +103,10 @@ def bench_batched(args, F, fsdgen, torch):
             s.close()
         return ok / dt_, dt_ / steps
 
-    def run_batch(steps, precision):
+    def run_batch(steps, precision, fused=True):
         sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
         b = F.Batch(1 << 40, len(sys_))
+        b.set_fused(fused)
         slots = [b.admit(s) for s in sys_]
         for _ in range(args.warmup):
             b.step(1e-3)
@@ -122,8 +128,13 @@ def bench_batched(args, F, fsdgen, torch):
             s.close()
         return ok / dt_, dt_ / steps, lat
 
+    progress(f"generated {len(systems)} systems, {n_tot} beads")
     plain, plain_step = run_plain(max(1, args.steps // 2))
+    progress("plain FP64 one-at-a-time done")
+    b64s, b64s_step, _ = run_batch(args.steps, F.FSD_FP64, fused=False)
+    progress("batched FP64, one stream per system, done")
     b64, b64_step, _ = run_batch(args.steps, F.FSD_FP64)
+    progress("batched FP64, multi-system launches, done")
     value, step_s, lat = run_batch(args.steps, F.FSD_MIXED)
     grids = sorted({int(F.System.from_suspension(systems[k]).info().grid) for k in range(0, len(systems), 8)})
     out = {
@@ -133,11 +144,12 @@ def bench_batched(args, F, fsdgen, torch):
         "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads, "
                                f"phi 0.02-0.25, xi = 25/L, tol 1e-5", "n_bead_total": n_tot,
-                   "grids_sampled": grids, "precision": "mixed", "parallelism": "single GPU, one stream per system"},
+                   "grids_sampled": grids, "precision": "mixed", "parallelism": "single GPU, multi-system launches"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "plain_fp64_one_at_a_time": {"value": round(plain, 1), "ms_per_step": round(1e3 * plain_step, 3)},
         "batched_fp64": {"value": round(b64, 1), "ms_per_step": round(1e3 * b64_step, 3)},
+        "batched_fp64_streams": {"value": round(b64s, 1), "ms_per_step": round(1e3 * b64s_step, 3)},
         "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
         "speedup_vs_plain": round(value / plain, 2),
         "roofline": None,
@@ -148,7 +160,7 @@ def bench_batched(args, F, fsdgen, torch):
 def bench_serving(args, F, fsdgen, torch):
     """Request stream (Poisson arrivals) served by the continuous-batching engine."""
     from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request, poisson_arrivals
-    reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps)
+    reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps, kT=args.kT)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
@@ -164,9 +176,11 @@ def bench_serving(args, F, fsdgen, torch):
         be.batch.close()
         return rep
 
+    progress(f"generated {len(reqs)} requests")
     if args.warmup:                                 # code objects loaded, first-touch allocations
         run(None, 0, sorted(reqs, key=lambda s: s.n_bead)[:2], 2)
     closed = run(None, 0)                           # every request queued at t = 0: capacity
+    progress(f"closed loop: {closed}")
     cap = closed["completed"] / closed["span_s"]
     rate = args.load * cap
     open_ = run(rate, 1)
@@ -176,8 +190,8 @@ def bench_serving(args, F, fsdgen, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
-                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, tol 1e-5, Poisson "
-                               f"arrivals at {args.load} x capacity",
+                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear + lubrication + "
+                               f"Brownian kT {args.kT}, tol 1e-5, Poisson arrivals at {args.load} x capacity",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
                    "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,
                    "parallelism": "single GPU, continuous batching"},
@@ -195,12 +209,14 @@ def bench_serving(args, F, fsdgen, torch):
 def bench_large(args, F, fsdgen, torch):
     """81,920 beads (4096 clusters of 20, phi 0.20, 128^3): FP64 against mixed precision."""
     s = fsdgen.config(2)
+    progress(f"generated {s.name}: {s.n_bead} beads")
     stream = torch.cuda.current_stream().cuda_stream
     res = {}
     for prec_name, prec in (("fp64", F.FSD_FP64), ("mixed", F.FSD_MIXED)):
         sysm = F.System.from_suspension(s, stream=stream, precision=prec)
         U0, _, _ = sysm.solve()              # warm-up: lists sized, graphs captured
         torch.cuda.synchronize()
+        progress(f"{prec_name}: warm-up solve done")
         lat, its, rr = [], [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -211,6 +227,7 @@ def bench_large(args, F, fsdgen, torch):
             rr.append(si.rel_residual_fp64)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        progress(f"{prec_name}: {args.steps} timed steps in {el:.2f} s")
         sysm.set_timing(True)
         sysm.step(s.dt, 1)
         table = kernel_table(sysm.timers(), 1)
@@ -261,6 +278,7 @@ def main():
     ap.add_argument("--max-beads", type=int, default=50000)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--load", type=float, default=0.5)
+    ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "

@@ -77,7 +77,8 @@ typedef struct {
   int gmres_restart;     /* Krylov dimension m of GMRES(m)                             */
   int gmres_maxit;       /* total inner iterations allowed per solve                   */
   int precision;         /* fsd_precision                                              */
-  double inner_tol;      /* reserved (FSD_MIXED refines at every GMRES restart)        */
+  double lanczos_tol;    /* relative stopping tolerance of the Lanczos square roots of
+                            the Brownian terms (1e-4); at most 100 Lanczos steps      */
   uint64_t seed;         /* key of the counter-based noise generator                   */
 } fsd_params;
 
@@ -154,6 +155,40 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, do
 const char* fsd_last_error(const fsd_system* s);
 void fsd_destroy(fsd_system* s);
 
+/* ---- Brownian motion (kT > 0) --------------------------------------------------------
+ * Eq. `SP2` and Algorithm 1 step 3: with kT > 0 every solve adds the Brownian slip
+ * velocity u_B = sqrt(2 kT/dt) (M_r^{1/2} psi_r + M_w^{1/2} psi_w) to the bead rows of the
+ * right-hand side and the near-field Brownian force F_B = sqrt(2 kT/dt) R_nf^{1/2} psi_nf,
+ * projected by Sigma, to the aggregate rows (b2 = -(F_P + Sigma F_B + Sigma R_nf e)).
+ * The wave-space part uses the exact square root of the positively split wave-space
+ * operator applied to white noise on the grid; the real-space and near-field parts use
+ * Lanczos square roots (params.lanczos_tol, at most 100 steps).  The noise is drawn from
+ * Philox4x64-10 keyed by (params.seed, stream) with counters (e/4 + 1, purpose, step, 0),
+ * purpose 0 = grid, 1 = real space, 2 = near field; fsd_step advances step by one per
+ * time step and sets dt. */
+
+/* Time step used by the Brownian amplitude, noise step index and noise stream id. */
+fsd_status fsd_set_brownian(fsd_system* s, double dt, uint64_t step, uint64_t stream);
+
+/* Caller-supplied noise for every following solve (NULL: draw that part from the
+ * generator): psi_w 3 N^3 (component-major [c][z][y][x], N = fsd_info.grid),
+ * psi_r 6 per bead, psi_nf 3 per bead.  Host buffers, copied. */
+fsd_status fsd_set_noise(fsd_system* s, const double* psi_w, const double* psi_r, const double* psi_nf);
+
+/* The Brownian terms of the next solve: u_B (6 per bead) and F_B (3 per bead, the
+ * translational near-field force); lanczos_steps (2 ints, may be NULL) gets the
+ * Lanczos steps of the real-space and near-field roots. */
+fsd_status fsd_brownian_terms(fsd_system* s, double* u_B, double* f_B, int* lanczos_steps);
+
+/* Raw Philox4x64-10 output of the device generator: block b (b < n_blocks) enciphers
+ * the counter (counter[0] + b, counter[1], counter[2], counter[3]) under key (k0, k1);
+ * out gets 4 words per block. */
+fsd_status fsd_philox4x64(uint64_t k0, uint64_t k1, const uint64_t counter[4], int n_blocks, uint64_t* out);
+
+/* n standard normals of stream (k0, k1, purpose, step): Box-Muller on pairs of open
+ * (0, 1) uniforms made from the top 53 bits of each word. */
+fsd_status fsd_normals(uint64_t k0, uint64_t k1, uint64_t purpose, uint64_t step, size_t n, double* out);
+
 /* ---- operator access (host buffers), for verification and profiling ---------------- */
 
 /* u = M lambda (6 per bead each).  parts: 1 real-space sum only, 2 wave-space
@@ -197,9 +232,12 @@ fsd_status fsd_batch_admit(fsd_batch* b, fsd_system* s, int* slot);
 /* Free a slot (the system itself is not destroyed). */
 fsd_status fsd_batch_retire(fsd_batch* b, int slot);
 
-/* One saddle solve for every admitted system, their GMRES iterations interleaved
- * on the GPU.  A failing system records its status in its slot info and does not
- * stop the others; the return value is the first failure (or FSD_OK). */
+/* One saddle solve for every admitted system.  In the fused mode (the default, used
+ * when all systems share precision and restart length <= 31 and have grids that are
+ * multiples of 8) the Arnoldi steps of all systems run in lock step, one launch per
+ * kernel over every system; otherwise each system runs on its own stream and the
+ * host interleaves them.  A failing system records its status in its slot info and
+ * does not stop the others; the return value is the first failure (or FSD_OK). */
 fsd_status fsd_batch_solve(fsd_batch* b);
 
 /* As fsd_batch_solve followed by the Euler update (Eqs. `EM1`-`EM3`) of every
@@ -211,6 +249,9 @@ fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* inf
 
 /* Bytes of the admitted systems (sum of their estimates). */
 size_t fsd_batch_used_bytes(const fsd_batch* b);
+
+/* Select multi-system launches (enable != 0, the default) or one stream per system. */
+fsd_status fsd_batch_set_fused(fsd_batch* b, int enable);
 
 void fsd_batch_destroy(fsd_batch* b);
 

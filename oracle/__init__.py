@@ -17,8 +17,10 @@ Everything here is plain, dense and FP64:
 * pse      -- the positively split Ewald decomposition evaluated by quadrature
               and a direct k-sum, for checking the two halves separately.
 * integrate -- explicit Euler update of centroids and quaternions.
+* brownian -- the Brownian right-hand-side terms with exact (eigendecomposition)
+              square roots of the real-space mobility and the lubrication matrix.
 
 Paper sections cited are those of "Fast Stokesian Dynamics for Rigid
 Aggregates" (Mangal et al.).
 """
-from . import rpy, lub, rigid, saddle, integrate, pse  # noqa: F401
+from . import rpy, lub, rigid, saddle, integrate, pse, brownian  # noqa: F401

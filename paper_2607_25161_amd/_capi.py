@@ -30,7 +30,7 @@ class Params(C.Structure):
         ("ewald_tol", C.c_double), ("grid", C.c_int), ("support", C.c_int), ("r_lub", C.c_double),
         ("r_precond", C.c_double), ("lub_eps_min", C.c_double), ("gmres_tol", C.c_double),
         ("gmres_restart", C.c_int), ("gmres_maxit", C.c_int), ("precision", C.c_int),
-        ("inner_tol", C.c_double), ("seed", C.c_uint64),
+        ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
     ]
 
 
@@ -85,6 +85,12 @@ _sig("fsd_apply_precond", C.c_int, _SYS, _D, _D)
 _sig("fsd_get_rhs", C.c_int, _SYS, _D)
 _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
+_U64P = C.POINTER(C.c_uint64)
+_sig("fsd_set_brownian", C.c_int, _SYS, C.c_double, C.c_uint64, C.c_uint64)
+_sig("fsd_set_noise", C.c_int, _SYS, _D, _D, _D)
+_sig("fsd_brownian_terms", C.c_int, _SYS, _D, _D, C.POINTER(C.c_int))
+_sig("fsd_philox4x64", C.c_int, C.c_uint64, C.c_uint64, _U64P, C.c_int, _U64P)
+_sig("fsd_normals", C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_size_t, _D)
 _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
@@ -97,6 +103,7 @@ _sig("fsd_batch_step", C.c_int, C.c_void_p, C.c_double)
 _sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
+_sig("fsd_batch_set_fused", C.c_int, C.c_void_p, C.c_int)
 
 TIMER_NAMES = ("real_sum", "spread", "fft_x_split", "fft_y", "fft_z_green", "fft_x_merge", "interp", "rigid_lub",
                "precond", "cgs_dot", "cgs_update", "cgs_norm_arnoldi")
@@ -131,6 +138,24 @@ def default_params(**kw) -> Params:
 
 def estimate_bytes(params: Params, n_bead: int, n_agg: int, L: float) -> int:
     return int(lib.fsd_estimate_bytes(C.byref(params), n_bead, n_agg, L))
+
+
+def philox4x64(k0: int, k1: int, counter, n_blocks: int) -> np.ndarray:
+    """Raw device Philox4x64-10 words: block b enciphers (counter[0] + b, counter[1:])."""
+    ctr = np.ascontiguousarray(counter, dtype=np.uint64)
+    out = np.zeros(4 * n_blocks, dtype=np.uint64)
+    rc = lib.fsd_philox4x64(k0, k1, ctr.ctypes.data_as(_U64P), n_blocks, out.ctypes.data_as(_U64P))
+    if rc:
+        raise FsdError(rc, f"fsd_philox4x64: {lib.fsd_last_error(None).decode()}")
+    return out
+
+
+def normals(k0: int, k1: int, purpose: int, step: int, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    rc = lib.fsd_normals(k0, k1, purpose, step, n, _dptr(out))
+    if rc:
+        raise FsdError(rc, f"fsd_normals: {lib.fsd_last_error(None).decode()}")
+    return out
 
 
 def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
@@ -271,6 +296,22 @@ class System:
         return out
 
     # -- launch mode and timing ---------------------------------------------------------
+    def set_brownian(self, dt, step=0, stream=0):
+        self._check(lib.fsd_set_brownian(self._h, float(dt), int(step), int(stream)), "fsd_set_brownian")
+
+    def set_noise(self, psi_w=None, psi_r=None, psi_nf=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64).ravel() for a in (psi_w, psi_r, psi_nf)]
+        ptrs = [None if a is None else _dptr(a) for a in arrs]
+        self._check(lib.fsd_set_noise(self._h, *ptrs), "fsd_set_noise")
+
+    def brownian_terms(self):
+        """(u_B (n_bead, 6), F_B (n_bead, 3), lanczos steps (real, near))."""
+        u = np.zeros((self.n_bead, 6))
+        f = np.zeros((self.n_bead, 3))
+        its = (C.c_int * 2)()
+        self._check(lib.fsd_brownian_terms(self._h, _dptr(u), _dptr(f), its), "fsd_brownian_terms")
+        return u, f, (its[0], its[1])
+
     def set_graphs(self, enable=True, batch=0):
         self._check(lib.fsd_set_graphs(self._h, 1 if enable else 0, int(batch)), "fsd_set_graphs")
 
@@ -351,6 +392,12 @@ class Batch:
 
     def used_bytes(self) -> int:
         return int(lib.fsd_batch_used_bytes(self._h))
+
+    def set_fused(self, enable=True):
+        """Multi-system launches (True) or one stream per system (False)."""
+        rc = lib.fsd_batch_set_fused(self._h, 1 if enable else 0)
+        if rc:
+            raise FsdError(rc, "fsd_batch_set_fused")
 
     def close(self):
         if getattr(self, "_h", None):

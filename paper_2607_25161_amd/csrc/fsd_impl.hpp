@@ -27,6 +27,7 @@ struct WaveParams {
   double xi, eta_t; // splitting parameter and Gaussian split fraction eta~
   double a, eta;    // bead radius and viscosity
   double scale;     // h^6 / V * (normalisation of the two Gaussians)^2
+  int brownian;     // 1: the z pass applies the square-root multiplier to grid noise
 };
 
 // Constants of the real-space part.
@@ -168,7 +169,101 @@ void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const d
                 double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
                 const ArnoldiArgs* arn);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
+
+// ---- Brownian terms (k_brownian.hip) ------------------------------------------------------
+// Noise stream: Philox4x64-10 under key (k0, k1); normal e of the stream comes from the
+// counter (e / 4 + 1, purpose, step, 0).
+struct NoiseKey {
+  uint64_t k0, k1, purpose, step;
+};
+void launch_philox_raw(uint64_t k0, uint64_t k1, const uint64_t ctr[4], int nblk, uint64_t* out, hipStream_t st);
+void launch_normals(size_t n, const NoiseKey& nk, double* out, hipStream_t st);
+// real white noise (3 components per grid point) into the real parts of the three
+// complex grids, from the stream or from src (3 N^3 values, component-major)
+void launch_noise_grid(int N, const NoiseKey& nk, const double* src, double* grid, hipStream_t st);
+void launch_scale(size_t n, double a, const double* x, double* y, hipStream_t st);       // y = a x
+void launch_combine(size_t n, int k, const double* V, size_t ldv, const double* c, double* out,
+                    hipStream_t st);                                                       // out = V c
+void launch_take_trans(int nb, const double* v6, double* t3, hipStream_t st);
 void launch_sub(size_t n, const double* b, const double* ax, double* r, hipStream_t st);
 void launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes a multiple of 4
+
+// ---- multi-system launches --------------------------------------------------------------
+// Many independent systems advance their Arnoldi steps in lock step; each kernel of the
+// step is one launch over all of them.  Block b of a launch belongs to the system s with
+// off[s] <= b < off[s+1] (prefix sums of the per-system block counts); the block runs the
+// single-system kernel body with that system's pointers and parameters.  Systems whose
+// GMRES cycle has stopped return at once (their stop flag), as in the single-system path.
+struct BatchDesc {
+  int nb, na;
+  size_t n;
+  const double* pos4;
+  const double* r4;
+  const int* body;
+  const int* offsets;
+  // real-space pair sum
+  const int* nrow;
+  const uint32_t* ncol;
+  const double* tab64;
+  const float* tab32;
+  RealParams rp;
+  // wave space
+  WaveParams wp;
+  FftPlan plan;
+  const double* tw64;
+  const float* tw32;
+  void* grid;
+  void* half;
+  int bx, by, bz;  // FFT rows per block (x passes), lines per block (y), columns per block (z)
+  // gather spreading (8^3 blocks)
+  const int* bin_start;
+  const int* bin_end;
+  const int* perm;
+  const int4* starts;
+  const double* w64;
+  const float* w32;
+  int nbin, K, C;
+  // lubrication and preconditioner
+  const int* lrow;
+  const uint32_t* lcol;
+  const double* lcoef;
+  const double* lu;
+  const int* piv;
+  double drag_t, drag_r;
+  // Krylov state: the step maps z -> w; V = basis
+  double *basis, *z, *w, *r, *scal, *part, *h1, *h2, *hn2, *H, *gcs, *gsn, *g;
+  unsigned* counters;
+  GmresCtl* ctl;
+  int ncgs;  // CGS workgroups (cgs_blocks(n))
+};
+
+enum BatchKind {
+  BK_PRECOND = 0,
+  BK_REAL,
+  BK_SPREAD,
+  BK_FFT_X,  // split and merge share the geometry
+  BK_FFT_Y,
+  BK_FFT_Z,
+  BK_INTERP,
+  BK_AGG,
+  BK_CGS,
+  BK_COUNT
+};
+
+// FFT blocking used by both the single-system and the multi-system launches
+int fft_rows_x(int N);   // rows per workgroup of the x passes
+int fft_lines_y(int N);  // lines per workgroup of the y passes
+int fft_cols_z(int N);   // columns per workgroup of the fused z pass
+// fill the spreading fields of d from a gather plan (d.wp must be set first)
+void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d);
+// per-system block counts of each kind and the dynamic LDS the kinds need (prec: 0 FP64, 1 FP32)
+int batch_blocks(const BatchDesc& d, int kind);
+size_t batch_shm(const BatchDesc& d, int kind, int prec);
+// one multi-system launch; stage: FFT stage 0..4 for the FFT kinds, j: Arnoldi step for
+// the preconditioner and CGS kinds (mode 0..2 in cgs_mode)
+void launch_batch_mobility(int kind, int prec, int stage, const BatchDesc* D, const int* off, int nsys, int total,
+                           size_t shm, hipStream_t st);
+void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, const int* off, int nsys, int total,
+                         hipStream_t st);
 
 }  // namespace fsd

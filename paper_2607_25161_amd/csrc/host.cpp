@@ -283,6 +283,16 @@ struct fsd_system {
     bool converged = false;
     fsd_status status = FSD_OK;
   } sv;
+  // Brownian terms (kT > 0): time step and noise stream of the next solve, optional
+  // caller-supplied noise, the two right-hand-side vectors and the Lanczos workspace
+  double bdt = 1e-3;
+  uint64_t bstep = 0, bstream = 0;
+  int lan_max = 100;
+  int lan_its[2] = {0, 0};
+  bool psi_w_set = false, psi_r_set = false, psi_nf_set = false;
+  double *d_psi_w = nullptr, *d_psi_r = nullptr, *d_psi_nf = nullptr;
+  double *d_ub = nullptr, *d_fb = nullptr, *d_lan = nullptr, *d_lc = nullptr, *d_u6 = nullptr;
+  double *d_lh = nullptr, *d_lpart = nullptr;  // Lanczos reorthogonalisation coefficients and partials
   SpreadPlan* spread = nullptr;  // gather spreading (nullptr: atomic scatter)
   std::vector<double> h_tab;  // host copy of the smooth-part table (5 per node, 8 stride)
 
@@ -515,6 +525,7 @@ void choose_parameters(fsd_system* s) {
   w.eta = p.eta;
   const double gnorm = std::pow(2.0 * xi * xi / (M_PI * eta_t), 1.5);
   w.scale = std::pow(h, 6) / (L * L * L) * gnorm * gnorm;
+  w.brownian = 0;
   RealParams& r = s->rp;
   r.L = L;
   r.a = a;
@@ -766,11 +777,193 @@ void apply_precond(fsd_system* s, const double* src, double* z, const int* skip 
                        z, s->st, skip);
 }
 
+// ---- Brownian terms (Eq. `SP2`, Algorithm 1 step 3) ------------------------------------------
+
+void ensure_brownian(fsd_system* s) {
+  if (s->d_ub) return;
+  auto& o = s->owned;
+  const size_t nb = s->nb;
+  s->d_ub = dalloc<double>(o, 6 * nb);
+  s->d_fb = dalloc<double>(o, 3 * nb);
+  s->d_u6 = dalloc<double>(o, 6 * nb);
+  s->d_psi_r = dalloc<double>(o, 6 * nb);
+  s->d_psi_nf = dalloc<double>(o, 3 * nb);
+  s->d_lan = dalloc<double>(o, size_t(s->lan_max + 1) * 6 * nb);
+  s->d_lc = dalloc<double>(o, s->lan_max + 1);
+  s->d_lh = dalloc<double>(o, 2 * size_t(s->lan_max + 2));
+  s->d_lpart = dalloc<double>(o, size_t(s->lan_max + 2) * 1024);  // launch_dots partials: <= 1024 blocks
+}
+
+double dev_dot(fsd_system* s, size_t n, const double* x, const double* y) {
+  launch_dots(n, 1, x, n, y, s->d_part, s->d_h, s->d_counters, s->st);
+  HIPCHK(hipMemcpyAsync(s->h_small, s->d_h, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return s->h_small[0];
+}
+
+// Eigen-decomposition of a symmetric k x k matrix (row-major, overwritten by its
+// eigenvalues on the diagonal) by cyclic Jacobi rotations; Q receives the eigenvectors.
+void sym_eig(int k, std::vector<double>& A, std::vector<double>& Q) {
+  Q.assign(size_t(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) Q[size_t(i) * k + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0, diag = 0;
+    for (int i = 0; i < k; ++i) {
+      diag += A[size_t(i) * k + i] * A[size_t(i) * k + i];
+      for (int j = i + 1; j < k; ++j) off += A[size_t(i) * k + j] * A[size_t(i) * k + j];
+    }
+    if (off == 0.0 || off <= 1e-32 * diag) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[size_t(p) * k + q];
+        if (apq == 0.0) continue;
+        const double th = (A[size_t(q) * k + q] - A[size_t(p) * k + p]) / (2.0 * apq);
+        const double tn = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(tn * tn + 1.0), sn = tn * c;
+        for (int r = 0; r < k; ++r) {  // A J
+          const double ap = A[size_t(r) * k + p], aq = A[size_t(r) * k + q];
+          A[size_t(r) * k + p] = c * ap - sn * aq;
+          A[size_t(r) * k + q] = sn * ap + c * aq;
+        }
+        for (int r = 0; r < k; ++r) {  // J^T A
+          const double ap = A[size_t(p) * k + r], aq = A[size_t(q) * k + r];
+          A[size_t(p) * k + r] = c * ap - sn * aq;
+          A[size_t(q) * k + r] = sn * ap + c * aq;
+        }
+        for (int r = 0; r < k; ++r) {  // Q J
+          const double qp = Q[size_t(r) * k + p], qq = Q[size_t(r) * k + q];
+          Q[size_t(r) * k + p] = c * qp - sn * qq;
+          Q[size_t(r) * k + q] = sn * qp + c * qq;
+        }
+      }
+  }
+}
+
+// T^{1/2} e1 for the Lanczos tridiagonal T (diagonal al, off-diagonal be); negative
+// eigenvalues from rounding are clamped at zero
+std::vector<double> tridiag_sqrt_e1(const std::vector<double>& al, const std::vector<double>& be) {
+  const int k = int(al.size());
+  std::vector<double> A(size_t(k) * k, 0.0), Q;
+  for (int i = 0; i < k; ++i) {
+    A[size_t(i) * k + i] = al[i];
+    if (i + 1 < k) A[size_t(i) * k + i + 1] = A[size_t(i + 1) * k + i] = be[i];
+  }
+  sym_eig(k, A, Q);
+  std::vector<double> out(k, 0.0);
+  for (int e = 0; e < k; ++e) {
+    const double f = std::sqrt(std::max(A[size_t(e) * k + e], 0.0)) * Q[e];  // sqrt(lambda_e) (Q^T e1)_e
+    for (int i = 0; i < k; ++i) out[i] += Q[size_t(i) * k + e] * f;
+  }
+  return out;
+}
+
+// out = A^{1/2} z for a symmetric positive semi-definite operator by the Lanczos
+// method (Chow and Saad's square-root approximation): out = |z| V_k T_k^{1/2} e1,
+// stopped when the coefficient vector changes by less than tol (relative).
+// Returns the number of Lanczos steps.
+template <typename Apply>
+int lanczos_sqrt(fsd_system* s, size_t n, Apply&& apply, const double* z, double* out, double tol) {
+  const double b0 = std::sqrt(std::max(dev_dot(s, n, z, z), 0.0));
+  if (b0 == 0.0) {
+    launch_zero(out, sizeof(double) * n, s->st);
+    return 0;
+  }
+  double* V = s->d_lan;
+  double* w = s->d_t;
+  launch_scale(n, 1.0 / b0, z, V, s->st);
+  std::vector<double> al, be, prev;
+  int k = 0;
+  for (; k < s->lan_max; ++k) {
+    double* vk = V + size_t(k) * n;
+    apply(vk, w);
+    const double a = dev_dot(s, n, vk, w);
+    launch_axpby(n, -a, vk, 1.0, w, s->st);
+    if (k > 0) launch_axpby(n, -be.back(), V + size_t(k - 1) * n, 1.0, w, s->st);
+    // full reorthogonalisation against the basis (keeps the Lanczos vectors orthogonal
+    // when the operator is ill-conditioned, as the lubrication matrix is); the second
+    // pass returns ||w||^2
+    launch_dots(n, k + 1, V, n, w, s->d_lpart, s->d_lh, s->d_counters, s->st);
+    launch_axpy_dots(n, k + 1, V, n, s->d_lh, w, 1, s->d_lpart, s->d_lh + s->lan_max + 1, s->d_counters, s->st);
+    HIPCHK(hipMemcpyAsync(s->h_small, s->d_lh + s->lan_max + 1, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    const double b = std::sqrt(std::max(s->h_small[0], 0.0));
+    al.push_back(a);
+    std::vector<double> cur = tridiag_sqrt_e1(al, be);
+    double diff = 0, nrm = 0;
+    for (size_t i = 0; i < cur.size(); ++i) {
+      const double d = cur[i] - (i < prev.size() ? prev[i] : 0.0);
+      diff += d * d;
+      nrm += cur[i] * cur[i];
+    }
+    prev.swap(cur);
+    if ((k > 0 && diff <= tol * tol * nrm) || b <= 1e-14 * std::fabs(a) || k + 1 == s->lan_max) {
+      ++k;
+      break;
+    }
+    be.push_back(b);
+    launch_scale(n, 1.0 / b, w, V + size_t(k + 1) * n, s->st);
+  }
+  std::vector<double> c(prev.size());
+  for (size_t i = 0; i < c.size(); ++i) c[i] = b0 * prev[i];
+  HIPCHK(hipMemcpyAsync(s->d_lc, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, s->st));
+  launch_combine(n, int(c.size()), V, n, s->d_lc, out, s->st);
+  HIPCHK(hipStreamSynchronize(s->st));  // c lives on the host stack
+  return k;
+}
+
+// u_B = sqrt(2 kT / dt) (M_w^{1/2} psi_w + M_r^{1/2} psi_r) into d_ub (6 per bead) and
+// F_B = sqrt(2 kT / dt) R_nf^{1/2} psi_nf into d_fb (3 per bead, translational)
+void brownian_terms(fsd_system* s) {
+  ensure_brownian(s);
+  const size_t nb = s->nb;
+  const double amp = std::sqrt(2.0 * s->p.kT / s->bdt);
+  const NoiseKey kw{s->p.seed, s->bstream, 0, s->bstep}, kr{s->p.seed, s->bstream, 1, s->bstep},
+      kn{s->p.seed, s->bstream, 2, s->bstep};
+  // wave space: white noise on the grid through the square-root multiplier, interpolated
+  double* grid = static_cast<double*>(s->d_grid);
+  launch_noise_grid(s->wp.n, kw, s->psi_w_set ? s->d_psi_w : nullptr, grid, s->st);
+  WaveParams wb = s->wp;
+  wb.brownian = 1;
+  for (int stage = 0; stage < 5; ++stage)
+    launch_wave_fft<double>(grid, static_cast<double*>(s->d_half), s->plan, s->d_tw64, wb, stage, s->st);
+  launch_zero(s->d_ub, sizeof(double) * 6 * nb, s->st);
+  launch_interp<double>(s->nb, s->d_pos4, grid, s->wp, s->d_ub, s->st);
+  // real space: Lanczos on the pair sum
+  if (!s->psi_r_set) launch_normals(6 * nb, kr, s->d_psi_r, s->st);
+  s->lan_its[0] = lanczos_sqrt(
+      s, 6 * nb, [&](const double* in, double* out) { apply_mobility<double>(s, in, out, 1); }, s->d_psi_r,
+      s->d_u6, s->p.lanczos_tol);
+  launch_axpby(6 * nb, amp, s->d_u6, amp, s->d_ub, s->st);
+  // near field: Lanczos on R_nf (the lubrication product returns -R_nf w)
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  if (lub) {
+    if (!s->psi_nf_set) launch_normals(3 * nb, kn, s->d_psi_nf, s->st);
+    s->lan_its[1] = lanczos_sqrt(
+        s, 3 * nb,
+        [&](const double* in, double* out) {
+          launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, in, out, s->st);
+          launch_scale(3 * nb, -1.0, out, out, s->st);
+        },
+        s->d_psi_nf, s->d_fb, s->p.lanczos_tol);
+    launch_scale(3 * nb, amp, s->d_fb, s->d_fb, s->st);
+  } else {
+    s->lan_its[1] = 0;
+    launch_zero(s->d_fb, sizeof(double) * 3 * nb, s->st);
+  }
+}
+
 void assemble_rhs(fsd_system* s) {
   const size_t nb6 = 6 * size_t(s->nb);
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
-  launch_rhs(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_E, s->d_force, nullptr, s->d_b, s->d_wt, s->st);
-  if (lub) launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
+  const bool brown = s->p.kT > 0;
+  if (brown) brownian_terms(s);
+  launch_rhs(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_E, s->d_force, brown ? s->d_ub : nullptr, s->d_b,
+             s->d_wt, s->st);
+  if (lub) {
+    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
+    // b2 = -(F_P + Sigma F_B + Sigma R_nf e) = -F_P + Sigma (f_e - F_B), f_e = -R_nf e
+    if (brown) launch_axpby(3 * size_t(s->nb), -1.0, s->d_fb, 1.0, s->d_fl, s->st);
+  }
   launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_force, lub ? s->d_fl : nullptr, s->d_b + nb6, s->st);
 }
 
@@ -1010,7 +1203,7 @@ void fsd_default_params(fsd_params* p) {
   p->gmres_restart = 30;
   p->gmres_maxit = 1000;
   p->precision = FSD_FP64;
-  p->inner_tol = 1e-3;
+  p->lanczos_tol = 1e-4;
   p->seed = 2607251610ull;
 }
 
@@ -1019,7 +1212,7 @@ fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out) {
   if (!(p->eta > 0) || !(p->radius > 0) || !(p->ewald_tol > 0 && p->ewald_tol < 1) || !(p->gmres_tol > 0) ||
       p->gmres_restart < 1 || p->gmres_restart > 200 || p->gmres_maxit < 1 || p->grid < 0 || p->support < 0 ||
       p->support > 21 || p->r_lub < 0 || (p->precision != FSD_FP64 && p->precision != FSD_MIXED) ||
-      !(p->inner_tol > 0 && p->inner_tol < 1) || p->kT < 0)
+      !(p->lanczos_tol > 0 && p->lanczos_tol < 1) || p->kT < 0)
     return FSD_EINVAL;
   fsd_system* s = new (std::nothrow) fsd_system;
   if (!s) return FSD_ENOMEM;
@@ -1280,11 +1473,13 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
   if (!(dt > 0) || n_steps < 0) return fail(s, FSD_EINVAL, "dt must be positive and n_steps >= 0");
   return guarded(s, [&]() -> fsd_status {
     fsd_status r = FSD_OK;
+    s->bdt = dt;
     for (int k = 0; k < n_steps; ++k) {
       r = solve_current(s, last);
       if (r != FSD_OK) return r;
       launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
       s->prepared = false;
+      ++s->bstep;
     }
     HIPCHK(hipStreamSynchronize(s->st));
     return r;
@@ -1353,6 +1548,7 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t nb, int32_t na, double L)
   const int m = p->gmres_restart;
   double bytes = 48.0 * double(N) * N * N + 4.0 * nnz + 44.0 * nl + 8.0 * n * (m + 9) + 200.0 * nb + 400.0 * na +
                  8.0 * (m + 2) * 1024 + 8.0 * 8 * 4100 + (1 << 20);
+  if (p->kT > 0) bytes += 8.0 * nb * (6.0 * 101 + 24) + 8.0 * 102 * 1024;  // Lanczos basis, Brownian vectors
   return size_t(bytes);
 }
 
@@ -1486,6 +1682,92 @@ fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches, 
   });
 }
 
+fsd_status fsd_set_brownian(fsd_system* s, double dt, uint64_t step, uint64_t stream) {
+  if (!s) return FSD_EINVAL;
+  if (!(dt > 0)) return fail(s, FSD_EINVAL, "dt must be positive");
+  s->bdt = dt;
+  s->bstep = step;
+  s->bstream = stream;
+  return FSD_OK;
+}
+
+fsd_status fsd_set_noise(fsd_system* s, const double* psi_w, const double* psi_r, const double* psi_nf) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    ensure_brownian(s);
+    const size_t nb = s->nb, n3 = size_t(s->wp.n) * s->wp.n * s->wp.n;
+    if (psi_w && !s->d_psi_w) s->d_psi_w = dalloc<double>(s->owned, 3 * n3);
+    if (psi_w) HIPCHK(hipMemcpyAsync(s->d_psi_w, psi_w, sizeof(double) * 3 * n3, hipMemcpyHostToDevice, s->st));
+    if (psi_r) HIPCHK(hipMemcpyAsync(s->d_psi_r, psi_r, sizeof(double) * 6 * nb, hipMemcpyHostToDevice, s->st));
+    if (psi_nf) HIPCHK(hipMemcpyAsync(s->d_psi_nf, psi_nf, sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->psi_w_set = psi_w != nullptr;
+    s->psi_r_set = psi_r != nullptr;
+    s->psi_nf_set = psi_nf != nullptr;
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_brownian_terms(fsd_system* s, double* u_B, double* f_B, int* lanczos_steps) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!u_B || !f_B) return fail(s, FSD_EINVAL, "null output");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    brownian_terms(s);
+    HIPCHK(hipMemcpyAsync(u_B, s->d_ub, sizeof(double) * 6 * s->nb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(f_B, s->d_fb, sizeof(double) * 3 * s->nb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (lanczos_steps) {
+      lanczos_steps[0] = s->lan_its[0];
+      lanczos_steps[1] = s->lan_its[1];
+    }
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_philox4x64(uint64_t k0, uint64_t k1, const uint64_t counter[4], int n_blocks, uint64_t* out) {
+  if (!counter || !out || n_blocks < 1) return FSD_EINVAL;
+  std::vector<void*> owned;
+  fsd_status rc = FSD_OK;
+  try {
+    uint64_t* d = reinterpret_cast<uint64_t*>(dalloc<double>(owned, 4 * size_t(n_blocks)));
+    launch_philox_raw(k0, k1, counter, n_blocks, d, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(out, d, sizeof(uint64_t) * 4 * size_t(n_blocks), hipMemcpyDeviceToHost));
+  } catch (const ApiError& e) {
+    rc = e.code;
+    g_last_error = e.what();
+  } catch (const std::exception& e) {
+    rc = FSD_EDEVICE;
+    g_last_error = e.what();
+  }
+  for (void* q : owned) (void)hipFree(q);
+  return rc;
+}
+
+fsd_status fsd_normals(uint64_t k0, uint64_t k1, uint64_t purpose, uint64_t step, size_t n, double* out) {
+  if (!out || n == 0) return FSD_EINVAL;
+  std::vector<void*> owned;
+  fsd_status rc = FSD_OK;
+  try {
+    double* d = dalloc<double>(owned, n);
+    launch_normals(n, NoiseKey{k0, k1, purpose, step}, d, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(out, d, sizeof(double) * n, hipMemcpyDeviceToHost));
+  } catch (const ApiError& e) {
+    rc = e.code;
+    g_last_error = e.what();
+  } catch (const std::exception& e) {
+    rc = FSD_EDEVICE;
+    g_last_error = e.what();
+  }
+  for (void* q : owned) (void)hipFree(q);
+  return rc;
+}
+
 fsd_status fsd_fft3d(int n, int sign, double* data) {
   if (!data || (sign != 1 && sign != -1)) return FSD_EINVAL;
   FftPlan plan;
@@ -1529,6 +1811,25 @@ struct fsd_batch {
   std::vector<size_t> bytes;
   std::vector<fsd_solve_info> last;
   std::string err;
+  // multi-system launches (fused mode): descriptor and block tables on the device,
+  // a stream of their own, and captured Arnoldi segments for the current composition
+  bool fused = true;
+  hipStream_t st = nullptr;
+  BatchDesc* d_desc = nullptr;
+  int* d_off = nullptr;
+  int cap = 0;
+  std::vector<BatchDesc> h_desc;
+  std::vector<int> h_off;  // BK_COUNT x (cap + 1)
+  int nsys = 0, prec = 0;
+  int total[BK_COUNT] = {0};
+  size_t shm[BK_COUNT] = {0};
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (j0, cnt)
+  ~fsd_batch() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (d_desc) (void)hipFree(d_desc);
+    if (d_off) (void)hipFree(d_off);
+    if (st) (void)hipStreamDestroy(st);
+  }
 };
 
 namespace {
@@ -1539,7 +1840,7 @@ size_t system_bytes(const fsd_system* s) {
 // One solve (and optionally an Euler step) for every admitted system.  Each system
 // runs on its own stream; the host advances their state machines round-robin, so
 // while it waits on one system the others keep the GPU busy.
-fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
+fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
   std::vector<fsd_system*> act;
   for (auto* s : b->slot)
     if (s) act.push_back(s);
@@ -1547,6 +1848,7 @@ fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
   std::vector<char> done(act.size(), 0);
   for (size_t k = 0; k < act.size(); ++k) {
     fsd_system* s = act[k];
+    if (integrate) s->bdt = dt;
     fsd_status r = guarded(s, [&]() -> fsd_status {
       solve_begin(s);
       return FSD_OK;
@@ -1585,6 +1887,7 @@ fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
         if (integrate && s->sv.status == FSD_OK) {
           launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
           s->prepared = false;
+          ++s->bstep;
         }
       }
     }
@@ -1605,6 +1908,285 @@ fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
 }
 }  // namespace
 
+namespace {
+BatchDesc make_desc(fsd_system* s, int prec) {
+  BatchDesc d{};
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  const int N = s->wp.n;
+  d.nb = s->nb;
+  d.na = s->na;
+  d.n = s->n;
+  d.pos4 = s->d_pos4;
+  d.r4 = s->d_r4;
+  d.body = s->d_body;
+  d.offsets = s->d_offsets;
+  d.nrow = s->d_nrow;
+  d.ncol = s->d_ncol;
+  d.tab64 = s->d_tab64;
+  d.tab32 = s->d_tab32;
+  d.rp = s->rp;
+  d.wp = s->wp;
+  d.plan = s->plan;
+  d.tw64 = s->d_tw64;
+  d.tw32 = s->d_tw32;
+  d.grid = s->d_grid;
+  d.half = s->d_half;
+  d.bx = fft_rows_x(N);
+  d.by = fft_lines_y(N);
+  d.bz = fft_cols_z(N);
+  spread_plan_desc(s->spread, prec, d);
+  d.lrow = lub ? s->d_lrow : nullptr;
+  d.lcol = s->d_lcol;
+  d.lcoef = s->d_lcoef;
+  d.lu = s->d_lu;
+  d.piv = s->d_piv;
+  d.drag_t = s->drag_t;
+  d.drag_r = s->drag_r;
+  d.basis = s->d_basis;
+  d.z = s->d_z;
+  d.w = s->d_w;
+  d.r = s->d_r;
+  d.scal = s->d_scal;
+  d.part = s->d_part;
+  d.h1 = s->d_h;
+  d.h2 = s->d_h + (s->m + 1);
+  d.hn2 = s->d_h + 2 * (s->m + 1);
+  d.H = s->d_H;
+  d.gcs = s->d_cs;
+  d.gsn = s->d_sn;
+  d.g = s->d_g;
+  d.counters = s->d_counters;
+  d.ctl = s->d_ctl;
+  d.ncgs = cgs_blocks(s->n);
+  return d;
+}
+
+// can these systems share multi-system launches? (same precision and restart length,
+// CGS in registers, gather spreading on 8^3 blocks, no per-launch timing)
+bool fusable(const std::vector<fsd_system*>& act) {
+  if (act.empty()) return false;
+  const int prec = act[0]->p.precision, m = act[0]->m;
+  for (auto* s : act) {
+    if (s->p.precision != prec || s->m != m || !cgs_fits(m + 1) || s->timing) return false;
+    if (!s->spread || s->wp.n % 8) return false;
+  }
+  return true;
+}
+
+// upload descriptors and block tables for the systems in cyc; drops captured segments
+// when anything that a graph bakes in (block counts, pointers) changed
+void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
+  const int ns = int(cyc.size());
+  std::vector<BatchDesc> desc(ns);
+  for (int k = 0; k < ns; ++k) desc[k] = make_desc(cyc[k], prec);
+  std::vector<int> off(size_t(BK_COUNT) * (ns + 1), 0);
+  int total[BK_COUNT];
+  size_t shm[BK_COUNT];
+  for (int kind = 0; kind < BK_COUNT; ++kind) {
+    int acc = 0;
+    size_t mx = 0;
+    for (int k = 0; k < ns; ++k) {
+      off[size_t(kind) * (ns + 1) + k] = acc;
+      acc += batch_blocks(desc[k], kind);
+      mx = std::max(mx, batch_shm(desc[k], kind, prec));
+    }
+    off[size_t(kind) * (ns + 1) + ns] = acc;
+    total[kind] = acc;
+    shm[kind] = mx;
+  }
+  const bool same = ns == b->nsys && prec == b->prec && off == b->h_off &&
+                    std::memcmp(desc.data(), b->h_desc.data(), sizeof(BatchDesc) * ns) == 0;
+  if (same) return;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  if (ns > b->cap) {
+    if (b->d_desc) HIPCHK(hipFree(b->d_desc));
+    if (b->d_off) HIPCHK(hipFree(b->d_off));
+    b->d_desc = nullptr;
+    b->d_off = nullptr;
+    HIPCHK(hipMalloc(&b->d_desc, sizeof(BatchDesc) * ns));
+    HIPCHK(hipMalloc(&b->d_off, sizeof(int) * BK_COUNT * (ns + 1)));
+    b->cap = ns;
+  }
+  HIPCHK(hipMemcpyAsync(b->d_desc, desc.data(), sizeof(BatchDesc) * ns, hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipStreamSynchronize(b->st));
+  b->h_desc.swap(desc);
+  b->h_off.swap(off);
+  b->nsys = ns;
+  b->prec = prec;
+  std::copy(total, total + BK_COUNT, b->total);
+  std::copy(shm, shm + BK_COUNT, b->shm);
+}
+
+// Arnoldi steps j0 .. j0 + cnt - 1 of every system in the tables, one launch per kernel
+void batch_segment_body(fsd_batch* b, int j0, int cnt) {
+  const int ns = b->nsys, prec = b->prec;
+  auto off = [&](int kind) { return b->d_off + size_t(kind) * (ns + 1); };
+  for (int j = j0; j < j0 + cnt; ++j) {
+    launch_batch_solver(BK_PRECOND, j, 0, b->d_desc, off(BK_PRECOND), ns, b->total[BK_PRECOND], b->st);
+    launch_batch_mobility(BK_REAL, prec, 0, b->d_desc, off(BK_REAL), ns, b->total[BK_REAL], 0, b->st);
+    launch_batch_mobility(BK_SPREAD, prec, 0, b->d_desc, off(BK_SPREAD), ns, b->total[BK_SPREAD], b->shm[BK_SPREAD],
+                          b->st);
+    for (int stage = 0; stage < 5; ++stage) {
+      const int kind = (stage == 0 || stage == 4) ? BK_FFT_X : (stage == 2 ? BK_FFT_Z : BK_FFT_Y);
+      launch_batch_mobility(kind, prec, stage, b->d_desc, off(kind), ns, b->total[kind], b->shm[kind], b->st);
+    }
+    launch_batch_mobility(BK_INTERP, prec, 0, b->d_desc, off(BK_INTERP), ns, b->total[BK_INTERP], 0, b->st);
+    launch_batch_solver(BK_AGG, j, 0, b->d_desc, off(BK_AGG), ns, b->total[BK_AGG], b->st);
+    for (int mode = 0; mode < 3; ++mode)
+      launch_batch_solver(BK_CGS, j, mode, b->d_desc, off(BK_CGS), ns, b->total[BK_CGS], b->st);
+  }
+}
+
+void batch_segment(fsd_batch* b, int j0, int cnt, bool graphs) {
+  if (!graphs) {
+    batch_segment_body(b, j0, cnt);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  const auto key = std::make_pair(j0, cnt);
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    batch_segment_body(b, j0, cnt);
+    HIPCHK(hipStreamEndCapture(b->st, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    it = b->graphs.emplace(key, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, b->st));
+}
+
+// Lock-step solve of all admitted systems with multi-system launches.  Preparation,
+// right-hand sides and GMRES cycle starts/ends run per system on the systems' own
+// streams (they overlap); the Arnoldi steps of all systems whose cycle is running are
+// one launch per kernel on the batch stream.  Systems that converge drop out at the
+// next cycle boundary; the others restart together (equal restart length).
+fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, double dt, bool integrate) {
+  using SS = fsd_system::SolveState;
+  const size_t na = act.size();
+  std::vector<char> done(na, 0);
+  fsd_status worst = FSD_OK;
+  auto fail_one = [&](size_t k, fsd_status r) {
+    act[k]->sv.status = r;
+    act[k]->sv.phase = SS::DONE;
+    done[k] = 1;
+    if (worst == FSD_OK) worst = r;
+  };
+  for (size_t k = 0; k < na; ++k) {
+    fsd_system* s = act[k];
+    if (integrate) s->bdt = dt;
+    fsd_status r = guarded(s, [&]() -> fsd_status {
+      solve_begin(s);
+      return FSD_OK;
+    });
+    if (r != FSD_OK) fail_one(k, r);
+  }
+  for (size_t k = 0; k < na; ++k) {  // PREP: lists, right-hand side, first cycle start
+    if (done[k]) continue;
+    fsd_system* s = act[k];
+    fsd_status r = guarded(s, [&]() -> fsd_status {
+      HIPCHK(hipStreamSynchronize(s->st));
+      (void)solve_advance(s);
+      return FSD_OK;
+    });
+    if (r != FSD_OK) fail_one(k, r);
+  }
+  const int S = std::max(1, std::min(act[0]->batch, act[0]->m));
+  const bool graphs = act[0]->use_graphs;
+  const int prec = act[0]->p.precision == FSD_MIXED ? 1 : 0;
+  while (true) {
+    std::vector<fsd_system*> cyc;
+    for (size_t k = 0; k < na; ++k) {  // cycle starts drained: finish or join the cycle
+      if (done[k]) continue;
+      fsd_system* s = act[k];
+      bool more = false;
+      fsd_status r = guarded(s, [&]() -> fsd_status {
+        HIPCHK(hipStreamSynchronize(s->st));
+        check_flags(s);
+        const GmresCtl& c = *s->h_ctl;
+        auto& v = s->sv;
+        if (c.resid <= v.tol || c.stop) {
+          v.its += c.its;
+          v.rel = c.resid;
+          finish_solve(s, c.resid <= v.tol);
+          return FSD_OK;
+        }
+        more = true;
+        return FSD_OK;
+      });
+      if (r != FSD_OK) {
+        fail_one(k, r);
+        continue;
+      }
+      if (more)
+        cyc.push_back(s);
+      else
+        done[k] = 1;
+    }
+    if (cyc.empty()) break;
+    fsd_status r = guarded(cyc[0], [&]() -> fsd_status {
+      set_tables(b, cyc, prec);
+      for (int j0 = 0;; j0 += S) {
+        const int cnt = std::min(S, cyc[0]->m - j0);
+        batch_segment(b, j0, cnt, graphs);
+        for (auto* s : cyc)
+          HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, b->st));
+        HIPCHK(hipStreamSynchronize(b->st));
+        bool all = true;
+        for (auto* s : cyc) all = all && s->h_ctl->stop;
+        if (all || j0 + cnt >= cyc[0]->m) break;
+      }
+      for (auto* s : cyc) {  // cycle end and the next cycle start, per system
+        seg_cycle_end(s);
+        ++s->sv.restarts;
+        if (s->p.precision == FSD_MIXED) ++s->sv.outer;
+        seg_cycle_start(s);
+        s->sv.phase = SS::START;
+      }
+      return FSD_OK;
+    });
+    if (r != FSD_OK) {
+      for (size_t k = 0; k < na; ++k)
+        if (!done[k]) fail_one(k, r);
+      break;
+    }
+  }
+  for (size_t k = 0; k < na; ++k) {
+    fsd_system* s = act[k];
+    if (integrate && s->sv.status == FSD_OK) {
+      fsd_status r = guarded(s, [&]() -> fsd_status {
+        launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+        s->prepared = false;
+        ++s->bstep;
+        return FSD_OK;
+      });
+      if (r != FSD_OK && worst == FSD_OK) worst = r;
+    }
+    if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
+  }
+  for (auto* s : act) (void)hipStreamSynchronize(s->st);
+  return worst;
+}
+
+// one solve (and optionally an Euler step) for every admitted system: multi-system
+// launches when the systems allow them, otherwise one stream per system
+fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
+  std::vector<fsd_system*> act;
+  for (auto* s : b->slot)
+    if (s) act.push_back(s);
+  if (!b->fused || !fusable(act)) return batch_run_streams(b, dt, integrate);
+  const fsd_status r = batch_run_fused(b, act, dt, integrate);
+  for (size_t q = 0; q < b->slot.size(); ++q)
+    if (b->slot[q]) b->last[q] = info_of(b->slot[q]);
+  return r;
+}
+}  // namespace
+
 extern "C" {
 
 fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** out) {
@@ -1612,6 +2194,10 @@ fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** 
   auto* b = new (std::nothrow) fsd_batch;
   if (!b) return FSD_ENOMEM;
   b->budget = mem_budget_bytes;
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return FSD_EDEVICE;
+  }
   b->slot.assign(max_slots, nullptr);
   b->bytes.assign(max_slots, 0);
   b->last.assign(max_slots, fsd_solve_info{});
@@ -1667,6 +2253,12 @@ fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* inf
 }
 
 size_t fsd_batch_used_bytes(const fsd_batch* b) { return b ? b->used : 0; }
+
+fsd_status fsd_batch_set_fused(fsd_batch* b, int enable) {
+  if (!b) return FSD_EINVAL;
+  b->fused = enable != 0;
+  return FSD_OK;
+}
 
 void fsd_batch_destroy(fsd_batch* b) { delete b; }
 

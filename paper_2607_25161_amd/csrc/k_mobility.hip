@@ -45,12 +45,12 @@ __device__ inline R wave_sum(R v) {
 // ------------------------------------------------------------------------------------------
 
 template <typename R, int LPR>
-__global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restrict__ pos,
+__device__ __forceinline__ void real_sum_body(int nb, const double4* __restrict__ pos,
                                                   const double* __restrict__ lam, const int* __restrict__ rowptr,
                                                   const uint32_t* __restrict__ col, const R* __restrict__ tab,
-                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip) {
+                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gt = bx_ * blockDim.x + threadIdx.x;
   const int row = gt / LPR;
   const int lane = gt % LPR;
   if (row >= nb) return;  // LPR divides the wavefront, so whole groups leave together
@@ -135,6 +135,14 @@ __global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restr
     else
       for (int k = 0; k < 6; ++k) o[k] = v[k];
   }
+}
+
+template <typename R, int LPR>
+__global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restrict__ pos,
+                                                  const double* __restrict__ lam, const int* __restrict__ rowptr,
+                                                  const uint32_t* __restrict__ col, const R* __restrict__ tab,
+                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip) {
+  real_sum_body<R, LPR>(nb, pos, lam, rowptr, col, tab, rp, out, accumulate, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename R>
@@ -229,17 +237,17 @@ void launch_spread(int nb, const double* pos4, const double* lam, const WavePara
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restrict__ pos,
+__device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ pos,
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
                                                 double* __restrict__ out, const int* __restrict__ skip,
                                                 const int* __restrict__ body, const double4* __restrict__ r4,
-                                                const double* __restrict__ V) {
+                                                const double* __restrict__ V, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   // one wavefront per bead
   __shared__ R wts[4][3 * kMaxP];
   __shared__ int sta[4][3];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wv;
+  const int i = bx_ * 4 + wv;
   const bool live = i < nb;
   const double4 p = live ? pos[i] : make_double4(0, 0, 0, 0);
   if (live) axis_weights<R>(p, wp, lane, wts[wv], sta[wv]);
@@ -285,6 +293,15 @@ __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restric
     }
     for (int k = 0; k < 6; ++k) o[k] += add[k];
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restrict__ pos,
+                                                const R* __restrict__ grid, size_t cs, WaveParams wp,
+                                                double* __restrict__ out, const int* __restrict__ skip,
+                                                const int* __restrict__ body, const double4* __restrict__ r4,
+                                                const double* __restrict__ V) {
+  interp_body<R>(nb, pos, grid, cs, wp, out, skip, body, r4, V, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename R>
@@ -554,6 +571,176 @@ __global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restr
   g[2 * cs + 1] = a5;
 }
 
+// Column form of the gather for 8^3 blocks: lane (x, y) of a wavefront owns one grid
+// column of the block and ZW consecutive z planes; the 8 / ZW wavefronts of the
+// workgroup take the remaining planes.  A candidate whose support misses the block's
+// x, y or the wavefront's z range is skipped by the whole wavefront (a uniform test);
+// for the others each lane forms the x-y weight once and reuses it over its planes.
+// Candidates are staged in LDS in chunks of C (dynamic shared memory): first the
+// sorted bead index of each candidate, then the weights with independent loads in
+// flight, then start cells and force moments.
+template <typename R, int ZW>
+__device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_start,
+                                                               const int* __restrict__ bin_end,
+                                                               const int* __restrict__ perm,
+                                                               const int4* __restrict__ starts,
+                                                               const R* __restrict__ weights,
+                                                               const double* __restrict__ lam, WaveParams wp,
+                                                               int nbin, int K, int C, R* __restrict__ grid,
+                                                               size_t cs, const int* __restrict__ skip, int bx_, int by_, int gx_) {
+  if (skip && *skip) return;
+  constexpr int BS = 8, NT = 64 * (BS / ZW);
+  const int P = wp.support, N = wp.n, P3 = 3 * P;
+  extern __shared__ unsigned char smem_raw[];
+  R* sh_w = reinterpret_cast<R*>(smem_raw);                 // C * 3P
+  R* sh_l = sh_w + size_t(C) * P3;                           // C * 6
+  int4* sh_s = reinterpret_cast<int4*>(sh_l + size_t(C) * 6); // C
+  int* sh_k = reinterpret_cast<int*>(sh_s + C);              // C
+  __shared__ int rb0[2 * 8 * 8], rlen[2 * 8 * 8], roff[2 * 8 * 8 + 1];
+  const int bx = bx_ % nbin, by = (bx_ / nbin) % nbin, bz = bx_ / (nbin * nbin);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS + wave * ZW;
+  const int mx = x0 + (lane & 7), my = y0 + (lane >> 3);
+  // candidate beads: per (kz, ky) one or two contiguous runs of the sorted bead array
+  // (bins bx-K+1 .. bx along x, split where they wrap); thread r computes run r
+  const int xb0 = bx - K + 1;
+  const int nparts = xb0 >= 0 ? 1 : 2;
+  const int nruns = K * K * nparts;
+  for (int rr = t; rr < nruns; rr += NT) {
+    const int part = rr % nparts, ky = (rr / nparts) % K, kz = rr / (nparts * K);
+    const int cz = (bz - kz + nbin) % nbin, cy = (by - ky + nbin) % nbin;
+    int lo, hi;
+    if (xb0 >= 0) {
+      lo = xb0;
+      hi = bx;
+    } else if (part == 0) {
+      lo = 0;
+      hi = bx;
+    } else {
+      lo = xb0 + nbin;
+      hi = nbin - 1;
+    }
+    const int row = (cz * nbin + cy) * nbin;
+    int b0 = 0, b1 = 0;
+    bool any = false;
+    for (int c = lo; c <= hi; ++c) {
+      const int e0 = bin_start[row + c], e1 = bin_end[row + c];
+      if (e1 > e0) {
+        if (!any) b0 = e0;
+        b1 = e1;
+        any = true;
+      }
+    }
+    rb0[rr] = b0;
+    rlen[rr] = any ? b1 - b0 : 0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int r = 0; r < nruns; ++r) {
+      roff[r] = acc;
+      acc += rlen[r];
+    }
+    roff[nruns] = acc;
+  }
+  __syncthreads();
+  const int total = roff[nruns];
+  R a[ZW][6];
+#pragma unroll
+  for (int zz = 0; zz < ZW; ++zz)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[zz][c] = 0;
+  for (int c0 = 0; c0 < total; c0 += C) {
+    const int n = min(C, total - c0);
+    if (c0 > 0) __syncthreads();
+    for (int c = t; c < n; c += NT) {
+      const int gidx = c0 + c;
+      int r = 0;
+      while (roff[r + 1] <= gidx) ++r;
+      sh_k[c] = rb0[r] + (gidx - roff[r]);
+    }
+    __syncthreads();
+    const int nw = n * P3;
+    for (int q0 = t; q0 < nw; q0 += 4 * NT) {
+      R v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * NT;
+        if (q < nw) {
+          const int cand = q / P3;
+          v[u] = weights[size_t(sh_k[cand]) * P3 + (q - cand * P3)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (q0 + u * NT < nw) sh_w[q0 + u * NT] = v[u];
+    }
+    for (int c = t; c < n; c += NT) {
+      const int k = sh_k[c];
+      sh_s[c] = starts[k];
+      const double* l = lam + 6 * size_t(perm[k]);
+#pragma unroll
+      for (int f = 0; f < 6; ++f) sh_l[6 * c + f] = R(l[f]);
+    }
+    __syncthreads();
+    for (int q = 0; q < n; ++q) {
+      const int4 s = sh_s[q];
+      // offsets of the block (or the wave's planes) from the support start, mod N
+      int ox = x0 - s.x, oy = y0 - s.y, oz = z0 - s.z;
+      ox += ox < 0 ? N : 0;
+      oy += oy < 0 ? N : 0;
+      oz += oz < 0 ? N : 0;
+      if (!((ox < P || ox > N - BS) && (oy < P || oy > N - BS) && (oz < P || oz > N - ZW))) continue;
+      int ix = mx - s.x, iy = my - s.y;
+      ix += ix < 0 ? N : 0;
+      iy += iy < 0 ? N : 0;
+      if (ix < P && iy < P) {
+        const R* wq = sh_w + q * P3;
+        const R wxy = wq[ix] * wq[P + iy];
+        const R* l = sh_l + 6 * q;
+        const R l0 = l[0], l1 = l[1], l2 = l[2], l3 = l[3], l4 = l[4], l5 = l[5];
+#pragma unroll
+        for (int zz = 0; zz < ZW; ++zz) {
+          int iz = z0 + zz - s.z;
+          iz += iz < 0 ? N : 0;
+          if (iz < P) {
+            const R w = wxy * wq[2 * P + iz];
+            a[zz][0] += w * l0;
+            a[zz][1] += w * l1;
+            a[zz][2] += w * l2;
+            a[zz][3] += w * l3;
+            a[zz][4] += w * l4;
+            a[zz][5] += w * l5;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int zz = 0; zz < ZW; ++zz) {
+    const size_t m = (size_t(z0 + zz) * N + my) * N + mx;
+    R* g = grid + 2 * m;
+    g[0] = a[zz][0];
+    g[1] = a[zz][3];
+    g[cs] = a[zz][1];
+    g[cs + 1] = a[zz][4];
+    g[2 * cs] = a[zz][2];
+    g[2 * cs + 1] = a[zz][5];
+  }
+}
+
+template <typename R, int ZW>
+__global__ __launch_bounds__(64 * (8 / ZW)) void k_spread_cols(const int* __restrict__ bin_start,
+                                                               const int* __restrict__ bin_end,
+                                                               const int* __restrict__ perm,
+                                                               const int4* __restrict__ starts,
+                                                               const R* __restrict__ weights,
+                                                               const double* __restrict__ lam, WaveParams wp,
+                                                               int nbin, int K, int C, R* __restrict__ grid,
+                                                               size_t cs, const int* __restrict__ skip) {
+  spread_cols_body<R, ZW>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 namespace {
 template <typename R>
 const R* plan_weights(const SpreadPlan* sp);
@@ -572,9 +759,14 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
                           const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
   const int nblk = sp->nbin * sp->nbin * sp->nbin;
-  if (sp->BS == 8)
-    k_spread_gather<R, 8><<<nblk, 512, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
-                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
+  if (sp->BS == 8) {
+    // candidates per LDS chunk: at most 128, within 64 KB of dynamic shared memory
+    const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
+    const int C = int(std::min<size_t>(128, (size_t(64) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
+    k_spread_cols<R, 2><<<nblk, 256, per * C, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
+                                                    plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, C, grid, cs,
+                                                    skip);
+  }
   else
     k_spread_gather<R, 4><<<nblk, 64, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
@@ -845,9 +1037,9 @@ __device__ inline void load_twiddles(T* tw, const T* twg, int N, int sign) {
 
 // x forward + split: rows (y, z) of component c -> half spectra of F_c (field c) and T_c (field 3 + c)
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
+__device__ __forceinline__ void fft_x_split_body(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
                                                      size_t hs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip) {
+                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -855,11 +1047,11 @@ __global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid,
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + B * N;
   T* tw = buf1 + B * N;
-  const int c = blockIdx.y;
+  const int c = by_;
   const T* src = reinterpret_cast<const T*>(grid + c * cs);
   T* dF = reinterpret_cast<T*>(half + c * hs);
   T* dT = reinterpret_cast<T*>(half + (3 + c) * hs);
-  const size_t row0 = size_t(blockIdx.x) * B;
+  const size_t row0 = size_t(bx_) * B;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) buf0[t] = src[row0 * N + t];
   __syncthreads();
@@ -878,11 +1070,18 @@ __global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid,
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
+                                                     size_t hs, FftPlan plan, const R* __restrict__ twiddle, int B,
+                                                     const int* __restrict__ skip) {
+  fft_x_split_body<R>(grid, cs, half, hs, plan, twiddle, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // transforms along y of the six half-spectrum fields (element stride H); lines are (kx, z)
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t hs, FftPlan plan,
+__device__ __forceinline__ void fft_y_half_body(R* __restrict__ half, size_t hs, FftPlan plan,
                                                     const R* __restrict__ twiddle, int sign, int B,
-                                                    const int* __restrict__ skip) {
+                                                    const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -890,9 +1089,9 @@ __global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + B * N;
   T* tw = buf1 + B * N;
-  T* base = reinterpret_cast<T*>(half + blockIdx.y * hs);
+  T* base = reinterpret_cast<T*>(half + by_ * hs);
   const int nlines = H * N;
-  const int l0 = blockIdx.x * B;
+  const int l0 = bx_ * B;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int l = t % B, e = t / B, gl = l0 + l;
@@ -908,6 +1107,13 @@ __global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t
     const int l = t % B, e = t / B, gl = l0 + l;
     if (gl < nlines) base[(size_t(gl / H) * N + e) * H + gl % H] = Y[l * N + e];
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t hs, FftPlan plan,
+                                                    const R* __restrict__ twiddle, int sign, int B,
+                                                    const int* __restrict__ skip) {
+  fft_y_half_body<R>(half, hs, plan, twiddle, sign, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 namespace {
@@ -927,9 +1133,9 @@ __device__ inline void sinc_jv_d(double x, double& s, double& j) {
 
 // z forward, Green's-function scaling, z inverse for B columns (kx, ky) of all six fields
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_t hs, FftPlan plan,
+__device__ __forceinline__ void fft_z_green_body(R* __restrict__ half, size_t hs, FftPlan plan,
                                                      const R* __restrict__ twiddle, WaveParams wp, int B,
-                                                     const int* __restrict__ skip) {
+                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -939,7 +1145,7 @@ __global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_
   T* buf1 = buf0 + NL * N;
   T* tw = buf1 + NL * N;
   const int ncol = H * N;
-  const int c0 = blockIdx.x * B;
+  const int c0 = bx_ * B;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
   // line index: l = f * B + b  (field f, column c0 + b)
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
@@ -974,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_
     double sk, jk;
     sinc_jv_d(kn * wp.a, sk, jk);
     const double q = k2 / (4.0 * wp.xi * wp.xi);
-    const double Bk = wp.scale * (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / (wp.eta * k2);
+    const double damp = (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / wp.eta;
     double Fr[3], Fi[3], Tr[3], Ti[3];
     for (int a = 0; a < 3; ++a) {
       Fr[a] = ln[a]->x;
@@ -982,13 +1188,26 @@ __global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_
       Tr[a] = ln[3 + a]->x;
       Ti[a] = ln[3 + a]->y;
     }
-    // g = sinc F + (i/2) jv (k x T), transverse part, times B(k)
-    const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
-    const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
-    double gr[3], gi[3];
-    for (int a = 0; a < 3; ++a) {
-      gr[a] = sk * Fr[a] - 0.5 * jk * cxi[a];
-      gi[a] = sk * Fi[a] + 0.5 * jk * cxr[a];
+    double gr[3], gi[3], Bk;
+    if (wp.brownian) {
+      // square root of the wave-space operator applied to grid noise: with M_w =
+      // scale I F^-1 C^H b P C F I^T (F unnormalised, b = damp / k^2), the factor
+      // sqrt(scale / N^3) I F^-1 C^H sqrt(b) P F maps white grid noise to a vector
+      // of covariance M_w
+      Bk = sqrt(wp.scale / (double(N) * N * N) * damp) / kn;
+      for (int a = 0; a < 3; ++a) {
+        gr[a] = Fr[a];
+        gi[a] = Fi[a];
+      }
+    } else {
+      // g = sinc F + (i/2) jv (k x T), transverse part, times B(k)
+      Bk = wp.scale * damp / k2;
+      const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
+      const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
+      for (int a = 0; a < 3; ++a) {
+        gr[a] = sk * Fr[a] - 0.5 * jk * cxi[a];
+        gi[a] = sk * Fi[a] + 0.5 * jk * cxr[a];
+      }
     }
     const double pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
     const double pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
@@ -1018,12 +1237,19 @@ __global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_t hs, FftPlan plan,
+                                                     const R* __restrict__ twiddle, WaveParams wp, int B,
+                                                     const int* __restrict__ skip) {
+  fft_z_green_body<R>(half, hs, plan, twiddle, wp, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // x inverse + merge: rows (y, z): Y_c = u_c + i w_c rebuilt from the half spectra of
 // fields c (u) and 3 + c (w), transformed back into grid component c
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
+__device__ __forceinline__ void fft_x_merge_body(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
                                                      size_t cs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip) {
+                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -1031,11 +1257,11 @@ __global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half,
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + B * N;
   T* tw = buf1 + B * N;
-  const int c = blockIdx.y;
+  const int c = by_;
   const T* sU = reinterpret_cast<const T*>(half + c * hs);
   const T* sW = reinterpret_cast<const T*>(half + (3 + c) * hs);
   T* dst = reinterpret_cast<T*>(grid + c * cs);
-  const size_t row0 = size_t(blockIdx.x) * B;
+  const size_t row0 = size_t(bx_) * B;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, +1);
   for (int t = threadIdx.x; t < B * H; t += blockDim.x) {
     const int l = t / H, kx = t % H;
@@ -1060,13 +1286,30 @@ __global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half,
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) dst[row0 * N + t] = X[t];
 }
 
-namespace {
-int rows_per_block(int N) {
+template <typename R>
+__global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
+                                                     size_t cs, FftPlan plan, const R* __restrict__ twiddle, int B,
+                                                     const int* __restrict__ skip) {
+  fft_x_merge_body<R>(half, hs, grid, cs, plan, twiddle, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+int fft_rows_x(int N) {
   int B = 1;
   while (B * 2 * N <= 1024 && ((N * N) % (B * 2)) == 0) B *= 2;
   return B;
 }
-}  // namespace
+
+int fft_lines_y(int N) {
+  int B = 1;
+  while (B * 2 * N <= 1024) B *= 2;
+  return B;
+}
+
+int fft_cols_z(int N) {
+  int B = 1;
+  while (B * 2 * 6 * N <= 1536) B *= 2;
+  return B;
+}
 
 template <typename R>
 void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
@@ -1076,7 +1319,7 @@ void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, co
   const size_t cs = 2 * size_t(N) * N * N;
   const size_t hs = 2 * size_t(H) * N * N;
   if (stage == 0 || stage == 4) {
-    const int B = rows_per_block(N);
+    const int B = fft_rows_x(N);
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
     dim3 g(N * N / B, 3);
     if (stage == 0)
@@ -1084,14 +1327,12 @@ void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, co
     else
       k_fft_x_merge<R><<<g, kThreads, shm, st>>>(half, hs, grid, cs, plan, twiddle, B, skip);
   } else if (stage == 1 || stage == 3) {
-    int B = 1;
-    while (B * 2 * N <= 1024) B *= 2;
+    const int B = fft_lines_y(N);
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
     dim3 g((H * N + B - 1) / B, 6);
     k_fft_y_half<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, stage == 1 ? -1 : +1, B, skip);
   } else {
-    int B = 1;
-    while (B * 2 * 6 * N <= 1536) B *= 2;
+    const int B = fft_cols_z(N);
     const size_t shm = sizeof(T) * (2 * size_t(6 * B) * N + N);
     dim3 g((H * N + B - 1) / B);
     k_fft_z_green<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, wp, B, skip);
@@ -1199,6 +1440,202 @@ void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipSt
 }
 
 // explicit instantiations
+// ------------------------------------------------------------------------------------------
+// multi-system launches: block -> (system, local block) by the prefix table, then the
+// single-system body with that system's pointers (the Arnoldi step maps z -> w)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+__device__ inline int batch_sys(const int* __restrict__ off, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename R>
+__device__ inline const R* pick(const double* a, const float* b);
+template <>
+__device__ inline const double* pick<double>(const double* a, const float*) {
+  return a;
+}
+template <>
+__device__ inline const float* pick<float>(const double*, const float* b) {
+  return b;
+}
+
+constexpr int kBatchLpr = 16;  // lanes per bead row of the batched real-space sum
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void kb_real(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                              int nsys) {
+  const int s = batch_sys(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  real_sum_body<R, kBatchLpr>(d.nb, (const double4*)d.pos4, d.z, d.nrow, d.ncol, pick<R>(d.tab64, d.tab32), d.rp,
+                              d.w, 0, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void kb_spread(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                                int nsys) {
+  const int s = batch_sys(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const size_t cs = 2 * size_t(d.wp.n) * d.wp.n * d.wp.n;
+  spread_cols_body<R, 2>(d.bin_start, d.bin_end, d.perm, d.starts, pick<R>(d.w64, d.w32), d.z, d.wp, d.nbin, d.K,
+                         d.C, static_cast<R*>(d.grid), cs, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+}
+
+template <typename R, int STAGE>
+__global__ __launch_bounds__(256) void kb_fft(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                             int nsys) {
+  const int s = batch_sys(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const int lb = blockIdx.x - off[s];
+  const int N = d.plan.n, H = N / 2 + 1;
+  const size_t cs = 2 * size_t(N) * N * N, hs = 2 * size_t(H) * N * N;
+  R* grid = static_cast<R*>(d.grid);
+  R* half = static_cast<R*>(d.half);
+  const R* tw = pick<R>(d.tw64, d.tw32);
+  const int* stop = &d.ctl->stop;
+  if (STAGE == 0 || STAGE == 4) {
+    const int gx = N * N / d.bx;
+    if (STAGE == 0)
+      fft_x_split_body<R>(grid, cs, half, hs, d.plan, tw, d.bx, stop, lb % gx, lb / gx, gx);
+    else
+      fft_x_merge_body<R>(half, hs, grid, cs, d.plan, tw, d.bx, stop, lb % gx, lb / gx, gx);
+  } else if (STAGE == 1 || STAGE == 3) {
+    const int gx = (H * N + d.by - 1) / d.by;
+    fft_y_half_body<R>(half, hs, d.plan, tw, STAGE == 1 ? -1 : +1, d.by, stop, lb % gx, lb / gx, gx);
+  } else {
+    fft_z_green_body<R>(half, hs, d.plan, tw, d.wp, d.bz, stop, lb, 0, 0);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void kb_interp(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                                int nsys) {
+  const int s = batch_sys(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const size_t cs = 2 * size_t(d.wp.n) * d.wp.n * d.wp.n;
+  interp_body<R>(d.nb, (const double4*)d.pos4, static_cast<const R*>(d.grid), cs, d.wp, d.w, &d.ctl->stop, d.body,
+                 (const double4*)d.r4, d.z + 6 * size_t(d.nb), blockIdx.x - off[s], 0, 0);
+}
+
+// spreading fields of a batch descriptor (bin_start == nullptr: no gather plan)
+void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d) {
+  if (!sp || sp->BS != 8) {
+    d.bin_start = d.bin_end = d.perm = nullptr;
+    d.starts = nullptr;
+    d.w64 = nullptr;
+    d.w32 = nullptr;
+    d.nbin = d.K = d.C = 0;
+    return;
+  }
+  d.bin_start = sp->bin_start;
+  d.bin_end = sp->bin_end;
+  d.perm = sp->perm;
+  d.starts = sp->starts;
+  d.w64 = sp->weights;
+  d.w32 = sp->weights32;
+  d.nbin = sp->nbin;
+  d.K = sp->K;
+  const size_t rb = prec ? sizeof(float) : sizeof(double);
+  const size_t per = rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int);
+  d.C = int(std::min<size_t>(128, (size_t(64) << 10) / per)) & ~3;  // as launch_spread_gather
+}
+
+int batch_blocks(const BatchDesc& d, int kind) {
+  const int N = d.plan.n, H = N / 2 + 1;
+  switch (kind) {
+    case BK_PRECOND:
+    case BK_AGG:
+      return (d.na + 3) / 4;
+    case BK_REAL:
+      return int((size_t(d.nb) * kBatchLpr + kThreads - 1) / kThreads);
+    case BK_SPREAD:
+      return d.bin_start ? d.nbin * d.nbin * d.nbin : 0;
+    case BK_FFT_X:
+      return N * N / d.bx * 3;
+    case BK_FFT_Y:
+      return (H * N + d.by - 1) / d.by * 6;
+    case BK_FFT_Z:
+      return (H * N + d.bz - 1) / d.bz;
+    case BK_INTERP:
+      return (d.nb + 3) / 4;
+    case BK_CGS:
+      return d.ncgs;
+    default:
+      return 0;
+  }
+}
+
+size_t batch_shm(const BatchDesc& d, int kind, int prec) {
+  const size_t rb = prec ? sizeof(float) : sizeof(double), tb = 2 * rb;
+  const size_t N = d.plan.n;
+  switch (kind) {
+    case BK_SPREAD:
+      return (rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int)) * d.C;
+    case BK_FFT_X:
+      return tb * (2 * size_t(d.bx) * N + N);
+    case BK_FFT_Y:
+      return tb * (2 * size_t(d.by) * N + N);
+    case BK_FFT_Z:
+      return tb * (2 * size_t(6 * d.bz) * N + N);
+    default:
+      return 0;
+  }
+}
+
+namespace {
+template <typename R>
+void batch_mobility(int kind, int stage, const BatchDesc* D, const int* off, int nsys, int total, size_t shm,
+                    hipStream_t st) {
+  switch (kind) {
+    case BK_REAL:
+      kb_real<R><<<total, kThreads, 0, st>>>(D, off, nsys);
+      break;
+    case BK_SPREAD:
+      kb_spread<R><<<total, 256, shm, st>>>(D, off, nsys);
+      break;
+    case BK_FFT_X:
+      if (stage == 0)
+        kb_fft<R, 0><<<total, kThreads, shm, st>>>(D, off, nsys);
+      else
+        kb_fft<R, 4><<<total, kThreads, shm, st>>>(D, off, nsys);
+      break;
+    case BK_FFT_Y:
+      if (stage == 1)
+        kb_fft<R, 1><<<total, kThreads, shm, st>>>(D, off, nsys);
+      else
+        kb_fft<R, 3><<<total, kThreads, shm, st>>>(D, off, nsys);
+      break;
+    case BK_FFT_Z:
+      kb_fft<R, 2><<<total, kThreads, shm, st>>>(D, off, nsys);
+      break;
+    case BK_INTERP:
+      kb_interp<R><<<total, kThreads, 0, st>>>(D, off, nsys);
+      break;
+    default:
+      break;
+  }
+}
+}  // namespace
+
+void launch_batch_mobility(int kind, int prec, int stage, const BatchDesc* D, const int* off, int nsys, int total,
+                           size_t shm, hipStream_t st) {
+  if (total <= 0) return;
+  if (prec)
+    batch_mobility<float>(kind, stage, D, off, nsys, total, shm, st);
+  else
+    batch_mobility<double>(kind, stage, D, off, nsys, total, shm, st);
+}
+
 template void launch_wave_fft<double>(double*, double*, const FftPlan&, const double*, const WaveParams&, int,
                                       hipStream_t, const int*);
 template void launch_wave_fft<float>(float*, float*, const FftPlan&, const float*, const WaveParams&, int,

@@ -288,13 +288,13 @@ __device__ inline double wsum(double v) {
 
 // y2_j = Sigma_j (lambda + f_lub) with f_lub,i = -sum_k R_ik (u_i - u_k) and u the rigid
 // translational velocities of V (neighbour velocities rebuilt from V and body vectors)
-__global__ __launch_bounds__(256) void k_agg_lub(int na, const int* __restrict__ offsets, const int* __restrict__ body,
+__device__ __forceinline__ void agg_lub_body(int na, const int* __restrict__ offsets, const int* __restrict__ body,
                                                  const double4* __restrict__ r4, const double* __restrict__ lam,
                                                  const double* __restrict__ V, const int* __restrict__ lrow,
                                                  const uint32_t* __restrict__ lcol, const double* __restrict__ coef,
-                                                 double* __restrict__ y2, const int* __restrict__ skip) {
+                                                 double* __restrict__ y2, const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int j = bx_ * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= na) return;
   double F0 = 0, F1 = 0, F2 = 0, T0 = 0, T1 = 0, T2 = 0;
   for (int i = offsets[j] + lane; i < offsets[j + 1]; i += 64) {
@@ -345,6 +345,14 @@ __global__ __launch_bounds__(256) void k_agg_lub(int na, const int* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_agg_lub(int na, const int* __restrict__ offsets, const int* __restrict__ body,
+                                                 const double4* __restrict__ r4, const double* __restrict__ lam,
+                                                 const double* __restrict__ V, const int* __restrict__ lrow,
+                                                 const uint32_t* __restrict__ lcol, const double* __restrict__ coef,
+                                                 double* __restrict__ y2, const int* __restrict__ skip) {
+  agg_lub_body(na, offsets, body, r4, lam, V, lrow, lcol, coef, y2, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 void launch_agg_lub(int na, const int* offsets, const int* body, const double* r4, const double* lam,
                     const double* V, const int* lrow, const uint32_t* lcol, const double* coef, double* y2,
                     hipStream_t st, const int* skip) {
@@ -356,14 +364,14 @@ void launch_agg_lub(int na, const int* offsets, const int* body, const double* r
 // over its beads, solves z2 = -A_j^-1 y2 in lane 0, and writes z1 = M~^-1 (r1 - Sigma^T z2).
 // With scal != nullptr the input is r = scal[0] * src, and r is also stored to vout
 // (the next Krylov basis vector is formed here instead of in a separate launch).
-__global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int* __restrict__ offsets,
+__device__ __forceinline__ void precond_fused_body(int nb, int na, const int* __restrict__ offsets,
                                                        const double4* __restrict__ r4, const double* __restrict__ lu,
                                                        const int* __restrict__ piv, double drag_t, double drag_r,
                                                        const double* __restrict__ src, const double* __restrict__ scal,
                                                        double* __restrict__ vout, double* __restrict__ z,
-                                                       const int* __restrict__ skip) {
+                                                       const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int j = bx_ * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (j >= na) return;
   const double sc = scal ? scal[0] : 1.0;
   double p[6] = {0, 0, 0, 0, 0, 0};
@@ -422,6 +430,15 @@ __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int
     o[4] = drag_r * (l[4] - y[4]);
     o[5] = drag_r * (l[5] - y[5]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int* __restrict__ offsets,
+                                                       const double4* __restrict__ r4, const double* __restrict__ lu,
+                                                       const int* __restrict__ piv, double drag_t, double drag_r,
+                                                       const double* __restrict__ src, const double* __restrict__ scal,
+                                                       double* __restrict__ vout, double* __restrict__ z,
+                                                       const int* __restrict__ skip) {
+  precond_fused_body(nb, na, offsets, r4, lu, piv, drag_t, drag_r, src, scal, vout, z, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
@@ -551,16 +568,18 @@ void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const doubl
 }
 
 // ------------------------------------------------------------------------------------------
-// CGS2 passes with the basis in registers (restart length < kCgsMax).  One wavefront per
-// block: each lane holds its element of every basis vector, so the update and the new
-// inner products read the basis once, and the per-block sums need no LDS or barrier.
-// The nq block sums are reduced across the wavefront by recursive halving (31 lane
-// exchanges for 32 values instead of 6 per value).  The last block to finish adds the
-// per-block partials in a fixed order (deterministic) and resets its ticket.
+// CGS2 passes with the basis in registers (restart length < kCgsMax).  Each lane holds
+// its element of every basis vector, so the update and the new inner products read the
+// basis once.  The nq per-lane sums are reduced across a wavefront by recursive halving
+// (31 lane exchanges for 32 values instead of 6 per value), the four wavefronts of a
+// workgroup through LDS.  The last workgroup to finish adds the per-workgroup partials
+// in a fixed order (deterministic) and resets its ticket.
 // ------------------------------------------------------------------------------------------
 
 namespace {
 constexpr int kCgsMax = 32;
+constexpr int kCgsThreads = 256;
+constexpr int kCgsWaves = kCgsThreads / 64;
 constexpr int kCgsBlocks = 512;
 
 // halving step: lanes with (lane & D) keep the upper half of a[0..2C), the others the
@@ -596,30 +615,89 @@ __device__ inline double wave_total(double v) {
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+
+// workgroup sums of acc[q], q < nout (nout == 1: acc[0] only); valid in sh[0][q] after the call
+__device__ inline void block_sums(double (&acc)[kCgsMax], int nout, double (*sh)[kCgsMax]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (nout > 1) {
+    const double tot = wave_transpose_sum(acc, lane);
+    const int q = cgs_q(lane);
+    if (!(lane & 1)) sh[wave][q] = tot;
+  } else {
+    const double tot = wave_total(acc[0]);
+    if (lane == 0) sh[wave][0] = tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < nout) {
+    double s = 0.0;
+    for (int w = 0; w < kCgsWaves; ++w) s += sh[w][threadIdx.x];
+    sh[0][threadIdx.x] = s;  // each thread rewrites only its own column, after reading it
+  }
+  __syncthreads();
+}
+
+// Arnoldi update with the column, rotations and sines staged in LDS (j < kCgsMax)
+__device__ void arnoldi_update_staged(const ArnoldiArgs& a, double hn2, double* col, double* cs, double* sn) {
+  GmresCtl* ctl = a.ctl;
+  const int j = a.j;
+  const bool stop = ctl->stop;
+  if (!stop)
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      col[i] = a.h1[i] + a.h2[i];
+      cs[i] = a.cs[i];
+      sn[i] = a.sn[i];
+    }
+  __syncthreads();
+  if (stop || threadIdx.x != 0) return;
+  const int m = ctl->m;
+  const double hn = sqrt(fmax(hn2, 0.0));
+  double ci = col[0];
+  for (int i = 0; i < j; ++i) {
+    const double next = col[i + 1];
+    a.H[size_t(i) * m + j] = cs[i] * ci + sn[i] * next;
+    ci = -sn[i] * ci + cs[i] * next;
+  }
+  const double den = hypot(ci, hn);
+  const double c = den > 0 ? ci / den : 1.0, s = den > 0 ? hn / den : 0.0;
+  a.cs[j] = c;
+  a.sn[j] = s;
+  a.H[size_t(j) * m + j] = den;
+  const double gj = a.g[j];
+  a.g[j + 1] = -s * gj;
+  a.g[j] = c * gj;
+  ctl->k_used = j + 1;
+  ctl->its += 1;
+  ctl->resid = fabs(s * gj) / ctl->bn;
+  if (hn == 0.0) ctl->breakdown = 1;
+  if (ctl->resid <= ctl->tol || j + 1 == m || ctl->its >= ctl->maxit || hn == 0.0) ctl->stop = 1;
+  a.scal[0] = hn > 0 ? 1.0 / hn : 0.0;
+}
 }  // namespace
 
 int cgs_blocks(size_t n) {
-  long long b = (long long)((n + 63) / 64);
+  long long b = (long long)((n + kCgsThreads - 1) / kCgsThreads);
   return int(b < 1 ? 1 : (b > kCgsBlocks ? kCgsBlocks : b));
 }
 
 // MODE 0: out[q] = V_q . w                        (first Gram-Schmidt pass)
 // MODE 1: w -= sum_q hin[q] V_q; out[q] = V_q . w (second pass, fused with the first update)
-// MODE 2: w -= sum_q hin[q] V_q; out[0] = w . w, and the last block runs the Arnoldi update
+// MODE 2: w -= sum_q hin[q] V_q; out[0] = w . w, and the last workgroup runs the Arnoldi update
 template <int MODE>
-__global__ __launch_bounds__(64) void k_cgs(size_t n, int nq, const double* __restrict__ V, size_t ldv,
-                                            const double* __restrict__ hin, double* __restrict__ w,
-                                            double* __restrict__ partial, double* __restrict__ out,
-                                            unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn) {
+__device__ __forceinline__ void cgs_body(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                     const double* __restrict__ hin, double* __restrict__ w,
+                                                     double* __restrict__ partial, double* __restrict__ out,
+                                                     unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  const int lane = threadIdx.x;
+  __shared__ double sh[kCgsWaves][kCgsMax];
+  __shared__ double st[3][kCgsMax];
+  __shared__ unsigned ticket;
   double h[kCgsMax], acc[kCgsMax];
 #pragma unroll
   for (int q = 0; q < kCgsMax; ++q) {
     h[q] = (MODE >= 1 && q < nq) ? hin[q] : 0.0;
     acc[q] = 0.0;
   }
-  for (size_t i = size_t(blockIdx.x) * 64 + lane; i < n; i += size_t(gridDim.x) * 64) {
+  for (size_t i = size_t(bx_) * kCgsThreads + threadIdx.x; i < n; i += size_t(gx_) * kCgsThreads) {
     double v[kCgsMax];
 #pragma unroll
     for (int q = 0; q < kCgsMax; ++q) v[q] = q < nq ? V[size_t(q) * ldv + i] : 0.0;
@@ -639,40 +717,34 @@ __global__ __launch_bounds__(64) void k_cgs(size_t n, int nq, const double* __re
     }
   }
   const int nout = MODE <= 1 ? nq : 1;
-  const int nblk = gridDim.x;
-  if (MODE <= 1) {
-    const double tot = wave_transpose_sum(acc, lane);
-    const int q = cgs_q(lane);
-    if (!(lane & 1) && q < nout) partial[size_t(q) * nblk + blockIdx.x] = tot;
-  } else {
-    const double tot = wave_total(acc[0]);
-    if (lane == 0) partial[blockIdx.x] = tot;
-  }
+  const int nblk = gx_;
+  block_sums(acc, nout, sh);
+  if (threadIdx.x < nout) partial[size_t(threadIdx.x) * nblk + bx_] = sh[0][threadIdx.x];
   __threadfence();
-  unsigned ticket = 0;
-  if (lane == 0) ticket = atomicAdd(counter, 1u);
-  ticket = __shfl(ticket, 0, 64);
+  __syncthreads();
+  if (threadIdx.x == 0) ticket = atomicAdd(counter, 1u);
+  __syncthreads();
   if (ticket != unsigned(nblk - 1)) return;
   __threadfence();
 #pragma unroll
   for (int q = 0; q < kCgsMax; ++q) acc[q] = 0.0;
-  for (int b = lane; b < nblk; b += 64) {
+  for (int b = threadIdx.x; b < nblk; b += kCgsThreads) {
 #pragma unroll
     for (int q = 0; q < kCgsMax; ++q)
       if (q < nout) acc[q] += partial[size_t(q) * nblk + b];
   }
-  if (MODE <= 1) {
-    const double tot = wave_transpose_sum(acc, lane);
-    const int q = cgs_q(lane);
-    if (!(lane & 1) && q < nout) out[q] = tot;
-  } else {
-    const double tot = wave_total(acc[0]);
-    if (lane == 0) {
-      out[0] = tot;
-      arnoldi_update(arn, tot);
-    }
-  }
-  if (lane == 0) *counter = 0u;
+  block_sums(acc, nout, sh);
+  if (threadIdx.x < nout) out[threadIdx.x] = sh[0][threadIdx.x];
+  if (MODE == 2) arnoldi_update_staged(arn, sh[0][0], st[0], st[1], st[2]);
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kCgsThreads) void k_cgs(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                     const double* __restrict__ hin, double* __restrict__ w,
+                                                     double* __restrict__ partial, double* __restrict__ out,
+                                                     unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn) {
+  cgs_body<MODE>(n, nq, V, ldv, hin, w, partial, out, counter, skip, arn, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 bool cgs_fits(int nq) { return nq >= 1 && nq <= kCgsMax; }
@@ -683,11 +755,75 @@ void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const d
   const ArnoldiArgs a = arn ? *arn : ArnoldiArgs{};
   const int g = cgs_blocks(n);
   if (mode == 0)
-    k_cgs<0><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    k_cgs<0><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
   else if (mode == 1)
-    k_cgs<1><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    k_cgs<1><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
   else
-    k_cgs<2><<<g, 64, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    k_cgs<2><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+}
+
+// ------------------------------------------------------------------------------------------
+// multi-system launches of the preconditioner, the Sigma/lubrication reduction and the
+// CGS2 passes (block -> system by the prefix table; see BatchDesc)
+// ------------------------------------------------------------------------------------------
+
+namespace {
+__device__ inline int batch_sys_s(const int* __restrict__ off, int nsys, int b) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+}  // namespace
+
+// Arnoldi step j: v_j = scal * (j == 0 ? r : w) formed in the preconditioner, z = P^-1 v_j
+__global__ __launch_bounds__(256) void kb_precond(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                                 int nsys, int j) {
+  const int s = batch_sys_s(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  precond_fused_body(d.nb, d.na, d.offsets, (const double4*)d.r4, d.lu, d.piv, d.drag_t, d.drag_r, j == 0 ? d.r : d.w,
+                     d.scal, d.basis + size_t(j) * d.n, d.z, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+}
+
+__global__ __launch_bounds__(256) void kb_agg(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                             int nsys) {
+  const int s = batch_sys_s(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const size_t nb6 = 6 * size_t(d.nb);
+  agg_lub_body(d.na, d.offsets, d.body, (const double4*)d.r4, d.z, d.z + nb6, d.lrow, d.lcol, d.lcoef, d.w + nb6,
+               &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kCgsThreads) void kb_cgs(const BatchDesc* __restrict__ D, const int* __restrict__ off,
+                                                     int nsys, int j) {
+  const int s = batch_sys_s(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const ArnoldiArgs arn{j, d.ctl, d.h1, d.h2, d.H, d.gcs, d.gsn, d.g, d.scal};
+  const double* hin = MODE == 0 ? nullptr : (MODE == 1 ? d.h1 : d.h2);
+  double* out = MODE == 0 ? d.h1 : (MODE == 1 ? d.h2 : d.hn2);
+  cgs_body<MODE>(d.n, j + 1, d.basis, d.n, hin, d.w, d.part, out, d.counters, &d.ctl->stop, arn,
+                 blockIdx.x - off[s], 0, d.ncgs);
+}
+
+void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, const int* off, int nsys, int total,
+                         hipStream_t st) {
+  if (total <= 0) return;
+  if (kind == BK_PRECOND)
+    kb_precond<<<total, 256, 0, st>>>(D, off, nsys, j);
+  else if (kind == BK_AGG)
+    kb_agg<<<total, 256, 0, st>>>(D, off, nsys);
+  else if (kind == BK_CGS && cgs_mode == 0)
+    kb_cgs<0><<<total, kCgsThreads, 0, st>>>(D, off, nsys, j);
+  else if (kind == BK_CGS && cgs_mode == 1)
+    kb_cgs<1><<<total, kCgsThreads, 0, st>>>(D, off, nsys, j);
+  else if (kind == BK_CGS)
+    kb_cgs<2><<<total, kCgsThreads, 0, st>>>(D, off, nsys, j);
 }
 
 }  // namespace fsd

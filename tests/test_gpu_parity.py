@@ -204,7 +204,7 @@ def test_small_solve_matches_oracle(cluster_case):
 
 def test_small_solve_mixed_precision(F, cluster_case):
     kw, s, A = cluster_case
-    sm = _make(F, kw, precision=F.FSD_MIXED, gmres_tol=1e-9, inner_tol=1e-3)
+    sm = _make(F, kw, precision=F.FSD_MIXED, gmres_tol=1e-9, lanczos_tol=1e-4)
     U, _, info = sm.solve()
     F_o, V_o = saddle.solve_schur(A)
     Uo = V_o.reshape(-1, 6) + A.Uinf
@@ -267,8 +267,9 @@ def _small_uneven(n_sys=6):
                                  phi_range=(0.03, 0.2), tol=1e-8)
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_results_equal_alone(F, precision):
+def test_batch_results_equal_alone(F, precision, fused):
     systems = _small_uneven()
     alone = []
     for s0 in systems:
@@ -277,6 +278,7 @@ def test_batch_results_equal_alone(F, precision):
         alone.append(U)
         s.close()
     b = F.Batch(1 << 34, 16)
+    b.set_fused(fused)
     live = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
     slots = [b.admit(s) for s in live]
     assert b.solve() == 0
@@ -285,14 +287,18 @@ def test_batch_results_equal_alone(F, precision):
         assert info.status == 0 and info.rel_residual_fp64 <= 1e-8
         U, _, _ = live[k].solve()  # same configuration: the batch left the state unchanged
         assert np.abs(U - alone[k]).max() <= 1e-12 * np.abs(alone[k]).max()
-    # one Euler step in the batch equals one step alone
+    # one Euler step in the batch equals one step alone.  In FP64 both runs take the same
+    # arithmetic up to summation order; with FP32 matvecs the multi-system launches sum
+    # the real-space rows in another order, so the two solutions agree only to the
+    # solver tolerance (1e-8 relative): dt * 1e-7 * |U| bounds the position difference
     assert b.step(1e-3) == 0
     for k, s0 in enumerate(systems):
         s = F.System.from_suspension(s0, precision=precision)
         s.step(1e-3, 1)
         X1, q1 = s.state()
         X2, q2 = live[k].state()
-        assert np.abs(X1 - X2).max() < 1e-12 and np.abs(q1 - q2).max() < 1e-12
+        tol = 1e-12 if precision == 0 else 1e-3 * 1e-7 * np.abs(alone[k]).max()
+        assert np.abs(X1 - X2).max() < tol and np.abs(q1 - q2).max() < max(tol, 1e-12)
 
 
 def test_batch_against_oracle_and_failure_isolation(F):

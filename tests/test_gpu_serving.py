@@ -43,8 +43,17 @@ def test_request_in_mix_equals_alone(F, precision):
         X, q = r.result
         if r.n_steps == n_steps:
             Xa, qa = alone[r.rid]
-            assert np.abs(X - Xa).max() <= 1e-12 * r.suspension.L, r.rid
-            assert np.abs(q - qa).max() <= 1e-12, r.rid
+            s0 = r.suspension
+            if precision == 0:
+                tx, tq = 1e-12 * s0.L, 1e-12
+            else:
+                # FP32 matvecs summed in another order by the multi-system launches: the
+                # two runs agree to the solver tolerance (1e-5), 10x margin on the motion
+                L = s0.L
+                dX = np.abs((Xa - s0.com + L / 2) % L - L / 2).max()
+                tx, tq = 1e-4 * dX + 1e-12 * L, 1e-4 * np.abs(qa - s0.quat).max() + 1e-12
+            assert np.abs(X - Xa).max() <= tx, r.rid
+            assert np.abs(q - qa).max() <= tq, r.rid
     be.batch.close()
 
 
