@@ -171,7 +171,12 @@ def bench_serving(args, F, fsdgen, torch):
         eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
         t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
         rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
-        rep = eng.run(rs)
+
+        def tick(e):
+            if e.ticks % 5 == 0:
+                progress(f"tick {e.ticks}: {len(e.active)} active, {len(e.queue)} queued, {len(e.done)} done")
+
+        rep = eng.run(rs, on_tick=tick)
         torch.cuda.synchronize()
         be.batch.close()
         return rep
@@ -264,6 +269,30 @@ def bench_large(args, F, fsdgen, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy(args, torch):
+    """Device-to-device copy of 1 GiB: the measured HBM bandwidth next to the 8 TB/s
+    vendor figure, and the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE
+    counters (2 x 1 GiB of traffic per copy)."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.warmup)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    gbs = 2 * (1 << 30) / (ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "device copy bandwidth", "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+                      "higher_is_better": True, "config": {"workload": "copy of 1 GiB (float64)"},
+                      "frac_of_8TBps": round(gbs / PEAK_HBM_GBS, 4)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,9 +300,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["clusters", "large", "batched", "serving"], default="clusters")
+    ap.add_argument("--workload", choices=["clusters", "large", "batched", "serving", "copy"], default="clusters")
     ap.add_argument("--systems", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--requests", type=int, default=12)
     ap.add_argument("--req-steps", type=int, default=20)
     ap.add_argument("--max-beads", type=int, default=50000)
     ap.add_argument("--slots", type=int, default=16)
@@ -290,6 +319,8 @@ def main():
     import paper_2607_25161_amd as F
 
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        return bench_copy(args, torch)
     if args.workload == "batched":
         return bench_batched(args, F, fsdgen, torch)
     if args.workload == "serving":

@@ -409,14 +409,16 @@ def _split_sizes(n_tot, n_b):
 
 
 def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(4, 30),
-                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0):
+                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0, maxit=20000):
     """A stream of independent simulation requests for the serving form.
 
     Request r draws from its own Philox stream keyed by (seed, r): bead count
     log-uniform in n_range, beads per aggregate uniform in nb_range, volume
     fraction uniform in phi_range; shear and lubrication as in the other
     workloads; splitting parameter and grid left to the library's policy
-    (xi = 0, grid = 0); each request asks for n_steps time steps.
+    (xi = 0, grid = 0); each request asks for n_steps time steps.  Brownian motion
+    (kT > 0) brings bodies into near contact, where the lubrication makes the
+    saddle system stiff: the GMRES budget per solve is maxit.
     """
     out = []
     for r in range(n_req):
@@ -430,7 +432,7 @@ def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(
         g = _dense_assemble(f"request-{r}", sizes, L, rng, a=a, k_p=k_p)
         out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
                               xi=0.0, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
-                              r_precond=2.1 * a, kT=kT, n_steps=n_steps, **g))
+                              r_precond=2.1 * a, kT=kT, n_steps=n_steps, extra={"gmres_maxit": maxit}, **g))
     return out
 
 

@@ -332,6 +332,7 @@ class System:
         """Build from any object with the workload attributes (L, a, eta, offsets, ...)."""
         kw = dict(eta=s.eta, radius=s.a, xi=s.xi, ewald_tol=s.ewald_tol, grid=s.grid, r_lub=s.r_lub,
                   r_precond=s.r_precond, gmres_tol=s.gmres_tol, kT=getattr(s, "kT", 0.0))
+        kw.update({k: v for k, v in (getattr(s, "extra", None) or {}).items() if k in ("gmres_maxit", "seed")})
         kw.update(overrides)
         sysm = cls(default_params(**kw), stream=stream)
         sysm.init_box(s.L)

@@ -72,7 +72,7 @@ template <typename R>
 void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr,
                      const uint32_t* col, const R* table, const RealParams& rp, double* out,
                      bool accumulate, int lanes_per_row, hipStream_t st,
-                     const int* skip = nullptr);
+                     const int* skip = nullptr, const int* order = nullptr);
 template <typename R>
 void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
                    hipStream_t st, const int* skip = nullptr);
@@ -98,10 +98,13 @@ template <typename R>
 void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid,
                           hipStream_t st, const int* skip = nullptr);
 // out += interpolated grid velocities; with V != nullptr also += Sigma^T V (rigid velocities)
+// (sp != nullptr: beads in the plan's spatial order with its weights)
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
                    hipStream_t st, const int* skip = nullptr, const int* body = nullptr,
-                   const double* r4 = nullptr, const double* V = nullptr);
+                   const double* r4 = nullptr, const double* V = nullptr, const SpreadPlan* sp = nullptr);
+// the plan's sorted bead order (sorted index -> bead), nullptr without a plan
+const int* spread_plan_order(const SpreadPlan* sp);
 
 // ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,

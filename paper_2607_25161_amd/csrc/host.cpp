@@ -714,7 +714,7 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
     }
     Timed t(s, FSD_TIMER_REAL, 4.0 * (s->nb + 1) + 4.0 * s->nnz + 128.0 * s->nb);
     launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr, rs,
-                       skip);
+                       skip, spread_plan_order(s->spread));
     if (fork) HIPCHK(hipEventRecord(s->ev_join, s->st2));
   } else {
     launch_zero(out, sizeof(double) * 6 * s->nb, s->st);
@@ -743,7 +743,7 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
     }
     if (fork) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
     Timed t(s, FSD_TIMER_INTERP, full + beads + 80.0 * s->nb + (Vr ? 48.0 * s->na : 0.0));
-    launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr);
+    launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr, s->spread);
   }
 }
 
@@ -927,7 +927,7 @@ void brownian_terms(fsd_system* s) {
   for (int stage = 0; stage < 5; ++stage)
     launch_wave_fft<double>(grid, static_cast<double*>(s->d_half), s->plan, s->d_tw64, wb, stage, s->st);
   launch_zero(s->d_ub, sizeof(double) * 6 * nb, s->st);
-  launch_interp<double>(s->nb, s->d_pos4, grid, s->wp, s->d_ub, s->st);
+  launch_interp<double>(s->nb, s->d_pos4, grid, s->wp, s->d_ub, s->st, nullptr, nullptr, nullptr, nullptr, s->spread);
   // real space: Lanczos on the pair sum
   if (!s->psi_r_set) launch_normals(6 * nb, kr, s->d_psi_r, s->st);
   s->lan_its[0] = lanczos_sqrt(

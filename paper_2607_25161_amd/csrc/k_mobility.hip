@@ -11,6 +11,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fsd_impl.hpp"
 
@@ -32,6 +33,14 @@ struct C2<float> {
   using T = float2;
 };
 
+// Workgroups are dealt to the 8 XCDs round robin; map workgroup b of nblk so that each
+// XCD gets one contiguous range of logical blocks (neighbouring beads or grid blocks
+// then share that XCD's L2).  A bijection on [0, nblk).
+__device__ inline int xcd_remap(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
 template <typename R>
 __device__ inline R wave_sum(R v) {
 #pragma unroll
@@ -39,6 +48,22 @@ __device__ inline R wave_sum(R v) {
   return v;
 }
 }  // namespace
+
+// Gather-spreading plan: beads binned by the grid block holding the first point of
+// their support, in sorted order with their support starts and per-axis weights.
+struct SpreadPlan {
+  int nb = 0, BS = 0, nbin = 0, K = 0, P = 0;
+  int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *perm = nullptr;
+  int *bin_start = nullptr, *bin_end = nullptr;
+  int4* starts = nullptr;   // (sx, sy, sz, bin) per bead, sorted order
+  double* weights = nullptr;  // 3P weights per bead, sorted order
+  float* weights32 = nullptr;  // the same in FP32
+  double* wtmp = nullptr;
+  int4* stmp = nullptr;
+  void* temp = nullptr;
+  size_t temp_bytes = 0;
+  size_t rbytes = 0;
+};
 
 // ------------------------------------------------------------------------------------------
 // real-space pair sum: one group of LPR lanes per bead row
@@ -48,12 +73,17 @@ template <typename R, int LPR>
 __device__ __forceinline__ void real_sum_body(int nb, const double4* __restrict__ pos,
                                                   const double* __restrict__ lam, const int* __restrict__ rowptr,
                                                   const uint32_t* __restrict__ col, const R* __restrict__ tab,
-                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip, int bx_, int by_, int gx_) {
+                                                  RealParams rp, double* __restrict__ out, int accumulate,
+                                                  const int* __restrict__ order, const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  const int gt = bx_ * blockDim.x + threadIdx.x;
-  const int row = gt / LPR;
+  // with order (beads in spatially sorted order), rows are visited in that order and
+  // each XCD takes one contiguous range of them
+  const int nblk = gx_ > 0 ? gx_ : int((size_t(nb) * LPR + blockDim.x - 1) / blockDim.x);
+  const int gt = (order ? xcd_remap(bx_, nblk) : bx_) * blockDim.x + threadIdx.x;
+  const int rl = gt / LPR;
   const int lane = gt % LPR;
-  if (row >= nb) return;  // LPR divides the wavefront, so whole groups leave together
+  if (rl >= nb) return;  // LPR divides the wavefront, so whole groups leave together
+  const int row = order ? order[rl] : rl;
   const double4 pi = pos[row];
   const R a = R(rp.a);
   const R c8 = R(1.0 / (8.0 * M_PI * rp.eta));
@@ -141,19 +171,20 @@ template <typename R, int LPR>
 __global__ __launch_bounds__(256) void k_real_sum(int nb, const double4* __restrict__ pos,
                                                   const double* __restrict__ lam, const int* __restrict__ rowptr,
                                                   const uint32_t* __restrict__ col, const R* __restrict__ tab,
-                                                  RealParams rp, double* __restrict__ out, int accumulate, const int* __restrict__ skip) {
-  real_sum_body<R, LPR>(nb, pos, lam, rowptr, col, tab, rp, out, accumulate, skip, blockIdx.x, blockIdx.y, gridDim.x);
+                                                  RealParams rp, double* __restrict__ out, int accumulate,
+                                                  const int* __restrict__ order, const int* __restrict__ skip) {
+  real_sum_body<R, LPR>(nb, pos, lam, rowptr, col, tab, rp, out, accumulate, order, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename R>
 void launch_real_sum(int nb, const double* pos4, const double* lam, const int* rowptr, const uint32_t* col,
                      const R* table, const RealParams& rp, double* out, bool accumulate, int lpr, hipStream_t st,
-                     const int* skip) {
+                     const int* skip, const int* order) {
   const long long threads = (long long)nb * lpr;
   const int acc = accumulate ? 1 : 0;
   const double4* p = (const double4*)pos4;
 #define FSD_REAL(L_)                                                                                    \
-  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc, skip)
+  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc, order, skip)
   switch (lpr) {
     case 1: FSD_REAL(1); break;
     case 2: FSD_REAL(2); break;
@@ -241,16 +272,34 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
                                                 double* __restrict__ out, const int* __restrict__ skip,
                                                 const int* __restrict__ body, const double4* __restrict__ r4,
-                                                const double* __restrict__ V, int bx_, int by_, int gx_) {
+                                                const double* __restrict__ V, const int* __restrict__ order,
+                                                const int4* __restrict__ ostart, const R* __restrict__ ow,
+                                                int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  // one wavefront per bead
+  // one wavefront per bead.  With order (the spreading plan's sorted beads, their
+  // support starts and weights), beads are visited in spatial order, each XCD taking one
+  // contiguous range, and the weights come from the plan instead of being recomputed.
   __shared__ R wts[4][3 * kMaxP];
   __shared__ int sta[4][3];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = bx_ * 4 + wv;
-  const bool live = i < nb;
-  const double4 p = live ? pos[i] : make_double4(0, 0, 0, 0);
-  if (live) axis_weights<R>(p, wp, lane, wts[wv], sta[wv]);
+  const int nblk = gx_ > 0 ? gx_ : (nb + 3) / 4;
+  const int k = (order ? xcd_remap(bx_, nblk) : bx_) * 4 + wv;
+  const bool live = k < nb;
+  const int i = live ? (order ? order[k] : k) : 0;
+  if (live) {
+    if (order) {
+      const int P = wp.support;
+      if (lane < 3 * P) wts[wv][(lane / P) * kMaxP + lane % P] = ow[size_t(k) * 3 * P + lane];
+      if (lane == 0) {
+        const int4 s4 = ostart[k];
+        sta[wv][0] = s4.x;
+        sta[wv][1] = s4.y;
+        sta[wv][2] = s4.z;
+      }
+    } else {
+      axis_weights<R>(pos[i], wp, lane, wts[wv], sta[wv]);
+    }
+  }
   __syncthreads();
   if (!live) return;
   const int P = wp.support, N = wp.n;
@@ -300,17 +349,29 @@ __global__ __launch_bounds__(256) void k_interp(int nb, const double4* __restric
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
                                                 double* __restrict__ out, const int* __restrict__ skip,
                                                 const int* __restrict__ body, const double4* __restrict__ r4,
-                                                const double* __restrict__ V) {
-  interp_body<R>(nb, pos, grid, cs, wp, out, skip, body, r4, V, blockIdx.x, blockIdx.y, gridDim.x);
+                                                const double* __restrict__ V,
+                                                const int* __restrict__ order, const int4* __restrict__ ostart,
+                                                const R* __restrict__ ow) {
+  interp_body<R>(nb, pos, grid, cs, wp, out, skip, body, r4, V, order, ostart, ow, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename R>
 void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out, hipStream_t st,
-                   const int* skip, const int* body, const double* r4, const double* V) {
+                   const int* skip, const int* body, const double* r4, const double* V, const SpreadPlan* sp) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  const R* ow = nullptr;
+  if (sp) {
+    if (std::is_same<R, double>::value)
+      ow = reinterpret_cast<const R*>(sp->weights);
+    else
+      ow = reinterpret_cast<const R*>(sp->weights32);
+  }
   k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out, skip, body,
-                                                   (const double4*)r4, V);
+                                                   (const double4*)r4, V, sp ? sp->perm : nullptr,
+                                                   sp ? sp->starts : nullptr, ow);
 }
+
+const int* spread_plan_order(const SpreadPlan* sp) { return sp ? sp->perm : nullptr; }
 
 // ------------------------------------------------------------------------------------------
 // Gaussian spreading as a gather: beads are binned by the grid block that holds
@@ -320,19 +381,7 @@ void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& 
 // once.
 // ------------------------------------------------------------------------------------------
 
-struct SpreadPlan {
-  int nb = 0, BS = 0, nbin = 0, K = 0, P = 0;
-  int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *perm = nullptr;
-  int *bin_start = nullptr, *bin_end = nullptr;
-  int4* starts = nullptr;   // (sx, sy, sz, bin) per bead, sorted order
-  double* weights = nullptr;  // 3P weights per bead, sorted order
-  float* weights32 = nullptr;  // the same in FP32
-  double* wtmp = nullptr;
-  int4* stmp = nullptr;
-  void* temp = nullptr;
-  size_t temp_bytes = 0;
-  size_t rbytes = 0;
-};
+
 
 namespace {
 int pick_block(int N) {
@@ -597,7 +646,8 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
   int4* sh_s = reinterpret_cast<int4*>(sh_l + size_t(C) * 6); // C
   int* sh_k = reinterpret_cast<int*>(sh_s + C);              // C
   __shared__ int rb0[2 * 8 * 8], rlen[2 * 8 * 8], roff[2 * 8 * 8 + 1];
-  const int bx = bx_ % nbin, by = (bx_ / nbin) % nbin, bz = bx_ / (nbin * nbin);
+  const int bl = xcd_remap(bx_, nbin * nbin * nbin);  // each XCD takes a contiguous slab of blocks
+  const int bx = bl % nbin, by = (bl / nbin) % nbin, bz = bl / (nbin * nbin);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS + wave * ZW;
   const int mx = x0 + (lane & 7), my = y0 + (lane >> 3);
@@ -1478,7 +1528,7 @@ __global__ __launch_bounds__(256) void kb_real(const BatchDesc* __restrict__ D, 
   const int s = batch_sys(off, nsys, blockIdx.x);
   const BatchDesc& d = D[s];
   real_sum_body<R, kBatchLpr>(d.nb, (const double4*)d.pos4, d.z, d.nrow, d.ncol, pick<R>(d.tab64, d.tab32), d.rp,
-                              d.w, 0, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+                              d.w, 0, d.perm, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
 }
 
 template <typename R>
@@ -1524,7 +1574,8 @@ __global__ __launch_bounds__(256) void kb_interp(const BatchDesc* __restrict__ D
   const BatchDesc& d = D[s];
   const size_t cs = 2 * size_t(d.wp.n) * d.wp.n * d.wp.n;
   interp_body<R>(d.nb, (const double4*)d.pos4, static_cast<const R*>(d.grid), cs, d.wp, d.w, &d.ctl->stop, d.body,
-                 (const double4*)d.r4, d.z + 6 * size_t(d.nb), blockIdx.x - off[s], 0, 0);
+                 (const double4*)d.r4, d.z + 6 * size_t(d.nb), d.perm, d.starts, pick<R>(d.w64, d.w32),
+                 blockIdx.x - off[s], 0, 0);
 }
 
 // spreading fields of a batch descriptor (bin_start == nullptr: no gather plan)
@@ -1643,15 +1694,15 @@ template void launch_wave_fft<float>(float*, float*, const FftPlan&, const float
 template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t, const int*);
 template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t, const int*);
 template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
-                                      const RealParams&, double*, bool, int, hipStream_t, const int*);
+                                      const RealParams&, double*, bool, int, hipStream_t, const int*, const int*);
 template void launch_real_sum<float>(int, const double*, const double*, const int*, const uint32_t*, const float*,
-                                     const RealParams&, double*, bool, int, hipStream_t, const int*);
+                                     const RealParams&, double*, bool, int, hipStream_t, const int*, const int*);
 template void launch_spread<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*);
 template void launch_spread<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t, const int*);
 template void launch_interp<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t, const int*,
-                                    const int*, const double*, const double*);
+                                    const int*, const double*, const double*, const SpreadPlan*);
 template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t, const int*,
-                                   const int*, const double*, const double*);
+                                   const int*, const double*, const double*, const SpreadPlan*);
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t, const int*);

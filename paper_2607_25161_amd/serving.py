@@ -151,8 +151,9 @@ class BatchEngine:
                 self.done.append(req)
         return True
 
-    def run(self, requests: List[Request], start: Optional[float] = None):
-        """Open-loop run: requests enter the queue at their arrival times (engine clock)."""
+    def run(self, requests: List[Request], start: Optional[float] = None, on_tick: Optional[Callable] = None):
+        """Open-loop run: requests enter the queue at their arrival times (engine clock).
+        on_tick(engine) is called after every engine tick (progress reporting)."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         t0 = self.clock() if start is None else start
         for r in pending:
@@ -161,7 +162,10 @@ class BatchEngine:
             now = self.clock()
             while pending and pending[0].arrival <= now:
                 self.submit(pending.popleft())
-            if not self.tick() and pending:
+            ticked = self.tick()
+            if ticked and on_tick is not None:
+                on_tick(self)
+            if not ticked and pending:
                 # idle: wait for the next arrival
                 wait = pending[0].arrival - self.clock()
                 if wait > 0 and hasattr(self.clock, "advance"):
@@ -173,8 +177,13 @@ class BatchEngine:
     def report(self, t0: float):
         lat = [r.latency for r in self.done if r.status == 0]
         span = max((r.finished for r in self.done), default=t0) - t0
+        fails = {}
+        for r in self.done:
+            if r.status != 0:
+                fails[r.status] = fails.get(r.status, 0) + 1
         return {
             "completed": len(lat), "failed": sum(1 for r in self.done if r.status != 0),
+            "failed_by_status": fails,
             "bead_steps": self.bead_steps, "span_s": span,
             "bead_solves_per_s": self.bead_steps / span if span > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)) if lat else None,
