@@ -29,8 +29,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 # kernel behind each timer class (rocprofv3 names), for matching the two measurements
-KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_cols", "fft_x_split": "k_fft_x_split",
-             "fft_y": "k_fft_y_half", "fft_z_green": "k_fft_z_green", "fft_x_merge": "k_fft_x_merge",
+KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_cols", "fft_first": "k_fft_lines<2>",
+             "fft_y": "k_fft_lines<1>", "fft_green": "k_fft_xgreen", "fft_last": "k_fft_lines<2>",
              "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused", "cgs_dot": "k_cgs<0>",
              "cgs_update": "k_cgs<1>", "cgs_norm_arnoldi": "k_cgs<2>"}
 
@@ -195,7 +195,7 @@ def bench_serving(args, F, fsdgen, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
-                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear + lubrication + "
+                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate 0.01 + lubrication + "
                                f"Brownian kT {args.kT}, tol 1e-5, Poisson arrivals at {args.load} x capacity",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
                    "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,

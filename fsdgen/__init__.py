@@ -409,7 +409,8 @@ def _split_sizes(n_tot, n_b):
 
 
 def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(4, 30),
-                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0, maxit=20000):
+                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0, maxit=20000,
+                     shear_rate=0.01):
     """A stream of independent simulation requests for the serving form.
 
     Request r draws from its own Philox stream keyed by (seed, r): bead count
@@ -419,6 +420,12 @@ def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(
     (xi = 0, grid = 0); each request asks for n_steps time steps.  Brownian motion
     (kT > 0) brings bodies into near contact, where the lubrication makes the
     saddle system stiff: the GMRES budget per solve is maxit.
+
+    The imposed shear enters the right-hand side of a cubic periodic box (no
+    Lees-Edwards images), so bodies facing each other across the y boundary move
+    apart or together at shear_rate * L; shear_rate keeps that relative motion over
+    the request (shear_rate * L * n_steps * dt <= 0.05 a for L up to 220 a) below the
+    smallest gaps the generator leaves.
     """
     out = []
     for r in range(n_req):
@@ -430,7 +437,7 @@ def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(
         sizes = _split_sizes(n_tot, n_b)
         L = box_side(n_tot, phi, a)
         g = _dense_assemble(f"request-{r}", sizes, L, rng, a=a, k_p=k_p)
-        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
+        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(shear_rate),
                               xi=0.0, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
                               r_precond=2.1 * a, kT=kT, n_steps=n_steps, extra={"gmres_maxit": maxit}, **g))
     return out

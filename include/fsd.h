@@ -68,7 +68,8 @@ typedef struct {
                             under the Section 3.2 error rules (cost model of the pair
                             sum against the grid passes)                              */
   double ewald_tol;      /* truncation tolerance x_err of the cutoff rules (Sec. 3.2)  */
-  int grid;              /* spectral grid points per side; 0: from the k_c rule        */
+  int grid;              /* spectral grid points per side (2^a 3^b, at most 256); 0: from
+                            the k_c rule                                              */
   int support;           /* Gaussian support P (points per side); 0: from ewald_tol    */
   double r_lub;          /* lubrication cutoff (3a); 0 disables lubrication            */
   double r_precond;      /* cutoff of the preconditioner's sparse lubrication (2.1a)   */
@@ -260,10 +261,12 @@ void fsd_batch_destroy(fsd_batch* b);
 typedef enum {
   FSD_TIMER_REAL = 0,        /* real-space pair sum                                       */
   FSD_TIMER_SPREAD = 1,      /* Gaussian spreading to the grid                            */
-  FSD_TIMER_FFT_X_SPLIT = 2, /* forward x transform into the half spectrum                */
-  FSD_TIMER_FFT_Y = 3,       /* y transform passes over the half spectrum (2 per apply)   */
-  FSD_TIMER_GREEN = 4,       /* z transforms fused with the Green's-function scaling      */
-  FSD_TIMER_FFT_X_MERGE = 5, /* inverse x transform from the half spectrum                */
+  FSD_TIMER_FFT_FIRST = 2,   /* first transform pass (z; x with the half-spectrum split
+                                for grids above 256^3)                                    */
+  FSD_TIMER_FFT_Y = 3,       /* y transform passes (2 per apply)                          */
+  FSD_TIMER_GREEN = 4,       /* the pass with the Green's-function scaling: x transforms
+                                (z transforms above 256^3) around it                      */
+  FSD_TIMER_FFT_LAST = 5,    /* last transform pass (inverse of the first)                */
   FSD_TIMER_INTERP = 6,      /* interpolation back to the beads, plus Sigma^T V           */
   FSD_TIMER_RIGID = 7,       /* Sigma reductions with the lubrication product             */
   FSD_TIMER_PRECOND = 8,     /* preconditioner apply (forms the next basis vector)        */

@@ -105,7 +105,7 @@ _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
 _sig("fsd_batch_set_fused", C.c_int, C.c_void_p, C.c_int)
 
-TIMER_NAMES = ("real_sum", "spread", "fft_x_split", "fft_y", "fft_z_green", "fft_x_merge", "interp", "rigid_lub",
+TIMER_NAMES = ("real_sum", "spread", "fft_first", "fft_y", "fft_green", "fft_last", "interp", "rigid_lub",
                "precond", "cgs_dot", "cgs_update", "cgs_norm_arnoldi")
 
 

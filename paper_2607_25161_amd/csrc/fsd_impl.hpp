@@ -80,15 +80,13 @@ void launch_spread(int nb, const double* pos4, const double* lam, const WavePara
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
                   int sign, hipStream_t st, int pass = -1, const int* skip = nullptr);
-// Half-spectrum wave-space transforms: stage 0 x forward + split (grid -> half),
-// 1 y forward, 2 z forward + Green's scaling + z inverse, 3 y inverse, 4 x inverse +
-// merge (half -> grid).  half holds 6 (n/2+1) n^2 complex values.
+// Wave-space transforms, in place on the three packed complex grids (n <= 256):
+// stage 0 z forward, 1 y forward, 2 x forward + Green's scaling + x inverse,
+// 3 y inverse, 4 z inverse.
+constexpr int kMaxGrid = 256;
 template <typename R>
-void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
+void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
                      hipStream_t st, const int* skip = nullptr);
-template <typename R>
-void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st,
-                        const int* skip = nullptr);
 // Gaussian spreading as a gather over beads binned by grid block (no atomics).
 struct SpreadPlan;
 SpreadPlan* spread_plan_create(int nb, int n_grid, int support);  // nullptr if n_grid % 4 != 0
@@ -216,8 +214,8 @@ struct BatchDesc {
   const double* tw64;
   const float* tw32;
   void* grid;
-  void* half;
-  int bx, by, bz;  // FFT rows per block (x passes), lines per block (y), columns per block (z)
+  int bl;  // lines per workgroup of the z and y passes
+  int bg;  // row slots per workgroup of the x+Green pass
   // gather spreading (8^3 blocks)
   const int* bin_start;
   const int* bin_end;
@@ -244,9 +242,9 @@ enum BatchKind {
   BK_PRECOND = 0,
   BK_REAL,
   BK_SPREAD,
-  BK_FFT_X,  // split and merge share the geometry
-  BK_FFT_Y,
-  BK_FFT_Z,
+  BK_FFT_OUTER,  // first and last transform passes (z)
+  BK_FFT_MID,    // y passes
+  BK_FFT_GREEN,  // x transforms with the Green's-function scaling
   BK_INTERP,
   BK_AGG,
   BK_CGS,
@@ -254,9 +252,8 @@ enum BatchKind {
 };
 
 // FFT blocking used by both the single-system and the multi-system launches
-int fft_rows_x(int N);   // rows per workgroup of the x passes
-int fft_lines_y(int N);  // lines per workgroup of the y passes
-int fft_cols_z(int N);   // columns per workgroup of the fused z pass
+int fft_lines_b(int N, int rbytes);  // lines per workgroup of the z/y passes (rbytes: 8 FP64, 4 FP32)
+int fft_green_rows(int N);           // row slots per workgroup of the x+Green pass
 // fill the spreading fields of d from a gather plan (d.wp must be set first)
 void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d);
 // per-system block counts of each kind and the dynamic LDS the kinds need (prec: 0 FP64, 1 FP32)

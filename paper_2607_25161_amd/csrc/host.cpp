@@ -202,7 +202,7 @@ double pick_xi(const fsd_params& p, int nb, double L) {
     const double xi = lo * std::pow(hi / lo, k / 48.0);
     const double rc = 1.15 * lnt / xi;  // the grown cutoff sits ~15% above the rule
     const int N = next_smooth(int(std::ceil((2.0 * lnt * xi + 1.0 / a) * L / M_PI)));
-    if (N > 512) continue;
+    if (N > kMaxGrid) continue;
     const double pairs = nb * (4.0 * M_PI / 3.0) * rc * rc * rc * dens;
     const double cost = 2e-12 * pairs + 6e-11 * double(N) * N * N;
     if (cost < best_cost) best_cost = cost, best = xi;
@@ -256,7 +256,6 @@ struct fsd_system {
   double *d_rdiag = nullptr, *d_lu = nullptr;
   int *d_piv = nullptr, *d_flags = nullptr;
   void* d_grid = nullptr;
-  void* d_half = nullptr;  // six half-spectrum fields
   double* d_tw64 = nullptr;
   float* d_tw32 = nullptr;
   double *d_b = nullptr, *d_x = nullptr, *d_basis = nullptr, *d_z = nullptr, *d_w = nullptr, *d_t = nullptr;
@@ -503,6 +502,7 @@ void choose_parameters(fsd_system* s) {
   const double rc = lnt / xi;
   const double kc = 2.0 * lnt * xi + 1.0 / a;
   int N = p.grid > 0 ? p.grid : next_smooth(int(std::ceil(kc * L / M_PI)));
+  if (N > kMaxGrid) throw ApiError(FSD_EINVAL, "spectral grid above 256^3; raise xi or lower the tolerance");
   if (!make_plan(N, s->plan))
     throw ApiError(FSD_EINVAL, "grid size must be a product of powers of 2 and 3");
   int P = p.support > 0 ? p.support : int(std::ceil(2.0 / M_PI * std::log(1.0 / tol))) + 2;
@@ -723,8 +723,8 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
     const int N = s->wp.n;
     const size_t cs = 2 * size_t(N) * N * N;  // R elements per complex component grid
     R* grid = static_cast<R*>(s->d_grid);
-    // algorithmic bytes: six real component grids, six half spectra, bead inputs
-    const double full = 3.0 * cs * sizeof(R), half_sp = 12.0 * (N / 2 + 1) * double(N) * N * sizeof(R);
+    // algorithmic bytes: the three packed complex grids, bead inputs
+    const double full = 3.0 * cs * sizeof(R);
     const double beads = 80.0 * s->nb;
     if (s->spread) {
       Timed t(s, FSD_TIMER_SPREAD, full + beads);
@@ -734,12 +734,11 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
       Timed t(s, FSD_TIMER_SPREAD, full + beads);
       launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
     }
-    R* half = static_cast<R*>(s->d_half);
     for (int stage = 0; stage < 5; ++stage) {
-      static const int cls_of[5] = {FSD_TIMER_FFT_X_SPLIT, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
-                                    FSD_TIMER_FFT_X_MERGE};
-      Timed t(s, cls_of[stage], (stage == 0 || stage == 4) ? full + half_sp : 2.0 * half_sp);
-      launch_wave_fft<R>(grid, half, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
+      static const int cls_of[5] = {FSD_TIMER_FFT_FIRST, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
+                                    FSD_TIMER_FFT_LAST};
+      Timed t(s, cls_of[stage], 2.0 * full);  // every pass reads and writes the three packed grids
+      launch_wave_fft<R>(grid, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
     }
     if (fork) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
     Timed t(s, FSD_TIMER_INTERP, full + beads + 80.0 * s->nb + (Vr ? 48.0 * s->na : 0.0));
@@ -925,7 +924,7 @@ void brownian_terms(fsd_system* s) {
   WaveParams wb = s->wp;
   wb.brownian = 1;
   for (int stage = 0; stage < 5; ++stage)
-    launch_wave_fft<double>(grid, static_cast<double*>(s->d_half), s->plan, s->d_tw64, wb, stage, s->st);
+    launch_wave_fft<double>(grid, s->plan, s->d_tw64, wb, stage, s->st);
   launch_zero(s->d_ub, sizeof(double) * 6 * nb, s->st);
   launch_interp<double>(s->nb, s->d_pos4, grid, s->wp, s->d_ub, s->st, nullptr, nullptr, nullptr, nullptr, s->spread);
   // real space: Lanczos on the pair sum
@@ -1313,7 +1312,6 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_flags = dalloc<int>(o, 2);
     const size_t N = s->wp.n;
     s->d_grid = dalloc<double>(o, 3 * 2 * N * N * N);
-    s->d_half = dalloc<double>(o, 6 * 2 * (N / 2 + 1) * N * N);
     const size_t n = s->n;
     s->d_b = dalloc<double>(o, n);
     s->d_x = dalloc<double>(o, n);
@@ -1811,8 +1809,8 @@ struct fsd_batch {
   std::vector<size_t> bytes;
   std::vector<fsd_solve_info> last;
   std::string err;
-  // multi-system launches (fused mode): descriptor and block tables on the device,
-  // a stream of their own, and captured Arnoldi segments for the current composition
+  // multi-system launches (fused mode): descriptor and block tables on the device and
+  // a stream of their own
   bool fused = true;
   hipStream_t st = nullptr;
   BatchDesc* d_desc = nullptr;
@@ -1823,9 +1821,7 @@ struct fsd_batch {
   int nsys = 0, prec = 0;
   int total[BK_COUNT] = {0};
   size_t shm[BK_COUNT] = {0};
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (j0, cnt)
   ~fsd_batch() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (d_desc) (void)hipFree(d_desc);
     if (d_off) (void)hipFree(d_off);
     if (st) (void)hipStreamDestroy(st);
@@ -1930,10 +1926,8 @@ BatchDesc make_desc(fsd_system* s, int prec) {
   d.tw64 = s->d_tw64;
   d.tw32 = s->d_tw32;
   d.grid = s->d_grid;
-  d.half = s->d_half;
-  d.bx = fft_rows_x(N);
-  d.by = fft_lines_y(N);
-  d.bz = fft_cols_z(N);
+  d.bl = fft_lines_b(N, prec ? 4 : 8);
+  d.bg = fft_green_rows(N);
   spread_plan_desc(s->spread, prec, d);
   d.lrow = lub ? s->d_lrow : nullptr;
   d.lcol = s->d_lcol;
@@ -1973,8 +1967,7 @@ bool fusable(const std::vector<fsd_system*>& act) {
   return true;
 }
 
-// upload descriptors and block tables for the systems in cyc; drops captured segments
-// when anything that a graph bakes in (block counts, pointers) changed
+// upload descriptors and block tables for the systems in cyc (skipped when unchanged)
 void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
   const int ns = int(cyc.size());
   std::vector<BatchDesc> desc(ns);
@@ -1997,8 +1990,6 @@ void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
   const bool same = ns == b->nsys && prec == b->prec && off == b->h_off &&
                     std::memcmp(desc.data(), b->h_desc.data(), sizeof(BatchDesc) * ns) == 0;
   if (same) return;
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
   if (ns > b->cap) {
     if (b->d_desc) HIPCHK(hipFree(b->d_desc));
     if (b->d_off) HIPCHK(hipFree(b->d_off));
@@ -2029,7 +2020,7 @@ void batch_segment_body(fsd_batch* b, int j0, int cnt) {
     launch_batch_mobility(BK_SPREAD, prec, 0, b->d_desc, off(BK_SPREAD), ns, b->total[BK_SPREAD], b->shm[BK_SPREAD],
                           b->st);
     for (int stage = 0; stage < 5; ++stage) {
-      const int kind = (stage == 0 || stage == 4) ? BK_FFT_X : (stage == 2 ? BK_FFT_Z : BK_FFT_Y);
+      const int kind = (stage == 0 || stage == 4) ? BK_FFT_OUTER : (stage == 2 ? BK_FFT_GREEN : BK_FFT_MID);
       launch_batch_mobility(kind, prec, stage, b->d_desc, off(kind), ns, b->total[kind], b->shm[kind], b->st);
     }
     launch_batch_mobility(BK_INTERP, prec, 0, b->d_desc, off(BK_INTERP), ns, b->total[BK_INTERP], 0, b->st);
@@ -2039,26 +2030,11 @@ void batch_segment_body(fsd_batch* b, int j0, int cnt) {
   }
 }
 
-void batch_segment(fsd_batch* b, int j0, int cnt, bool graphs) {
-  if (!graphs) {
-    batch_segment_body(b, j0, cnt);
-    HIPCHK(hipGetLastError());
-    return;
-  }
-  const auto key = std::make_pair(j0, cnt);
-  auto it = b->graphs.find(key);
-  if (it == b->graphs.end()) {
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-    batch_segment_body(b, j0, cnt);
-    HIPCHK(hipStreamEndCapture(b->st, &g));
-    hipGraphExec_t ex = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    it = b->graphs.emplace(key, ex).first;
-  }
-  HIPCHK(hipGraphLaunch(it->second, b->st));
+// The multi-system kernels are large enough that launching them eagerly costs little;
+// graphs would have to be re-captured whenever the set of running systems changes.
+void batch_segment(fsd_batch* b, int j0, int cnt) {
+  batch_segment_body(b, j0, cnt);
+  HIPCHK(hipGetLastError());
 }
 
 // Lock-step solve of all admitted systems with multi-system launches.  Preparation,
@@ -2097,7 +2073,6 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     if (r != FSD_OK) fail_one(k, r);
   }
   const int S = std::max(1, std::min(act[0]->batch, act[0]->m));
-  const bool graphs = act[0]->use_graphs;
   const int prec = act[0]->p.precision == FSD_MIXED ? 1 : 0;
   while (true) {
     std::vector<fsd_system*> cyc;
@@ -2133,7 +2108,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
       set_tables(b, cyc, prec);
       for (int j0 = 0;; j0 += S) {
         const int cnt = std::min(S, cyc[0]->m - j0);
-        batch_segment(b, j0, cnt, graphs);
+        batch_segment(b, j0, cnt);
         for (auto* s : cyc)
           HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, b->st));
         HIPCHK(hipStreamSynchronize(b->st));

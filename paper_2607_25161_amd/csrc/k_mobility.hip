@@ -810,9 +810,10 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
   const int nblk = sp->nbin * sp->nbin * sp->nbin;
   if (sp->BS == 8) {
-    // candidates per LDS chunk: at most 128, within 64 KB of dynamic shared memory
+    // candidates per LDS chunk: at most 128, within 60 KB of dynamic shared memory (the
+    // static arrays take the rest of 64 KB)
     const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
-    const int C = int(std::min<size_t>(128, (size_t(64) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
+    const int C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
     k_spread_cols<R, 2><<<nblk, 256, per * C, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
                                                     plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, C, grid, cs,
                                                     skip);
@@ -998,19 +999,6 @@ void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, c
   if (pass < 0 || pass == 2) k_fft_pass<R, 2><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
 }
 
-// ------------------------------------------------------------------------------------------
-// Half-spectrum wave-space pipeline (5 passes per mobility apply):
-//   x_fwd : rows of Z_c = F_c + i T_c transformed along x and split, by the row-local
-//           Hermitian symmetry, into the half spectra F^_c, T^_c (kx = 0..N/2)
-//   y     : transforms along y of the six half-spectrum fields
-//   zgz   : forward transform along z, Green's-function scaling (local in k: all six
-//           fields of one column are in the workgroup), inverse transform along z
-//   y     : inverse transforms along y
-//   x_inv : rows rebuilt as Y_c = u_c + i w_c from the half spectra and transformed back
-// Half-spectrum field f (0..5 = F_x F_y F_z T_x T_y T_z, then U, W) holds (N/2+1) N^2
-// complex values at ((kz N + ky)(N/2+1) + kx).
-// ------------------------------------------------------------------------------------------
-
 namespace {
 // Stockham stages on `nl` lines of length N held in LDS (`in`, scratch `out`);
 // returns the buffer holding the result.
@@ -1085,87 +1073,6 @@ __device__ inline void load_twiddles(T* tw, const T* twg, int N, int sign) {
 }
 }  // namespace
 
-// x forward + split: rows (y, z) of component c -> half spectra of F_c (field c) and T_c (field 3 + c)
-template <typename R>
-__device__ __forceinline__ void fft_x_split_body(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
-                                                     size_t hs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
-  if (skip && *skip) return;
-  using T = typename C2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  const int N = plan.n, H = N / 2 + 1;
-  T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + B * N;
-  T* tw = buf1 + B * N;
-  const int c = by_;
-  const T* src = reinterpret_cast<const T*>(grid + c * cs);
-  T* dF = reinterpret_cast<T*>(half + c * hs);
-  T* dT = reinterpret_cast<T*>(half + (3 + c) * hs);
-  const size_t row0 = size_t(bx_) * B;
-  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) buf0[t] = src[row0 * N + t];
-  __syncthreads();
-  const T* X = stockham<T, R>(buf0, buf1, tw, N, B, plan, -1);
-  for (int t = threadIdx.x; t < B * H; t += blockDim.x) {
-    const int l = t / H, kx = t % H;
-    const T a = X[l * N + kx];
-    const T b = X[l * N + (N - kx) % N];  // partner; conj(b) enters
-    T f, tt;
-    f.x = R(0.5) * (a.x + b.x);
-    f.y = R(0.5) * (a.y - b.y);
-    tt.x = R(0.5) * (a.y + b.y);
-    tt.y = R(-0.5) * (a.x - b.x);
-    dF[(row0 + l) * H + kx] = f;
-    dT[(row0 + l) * H + kx] = tt;
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_split(const R* __restrict__ grid, size_t cs, R* __restrict__ half,
-                                                     size_t hs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip) {
-  fft_x_split_body<R>(grid, cs, half, hs, plan, twiddle, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-// transforms along y of the six half-spectrum fields (element stride H); lines are (kx, z)
-template <typename R>
-__device__ __forceinline__ void fft_y_half_body(R* __restrict__ half, size_t hs, FftPlan plan,
-                                                    const R* __restrict__ twiddle, int sign, int B,
-                                                    const int* __restrict__ skip, int bx_, int by_, int gx_) {
-  if (skip && *skip) return;
-  using T = typename C2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  const int N = plan.n, H = N / 2 + 1;
-  T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + B * N;
-  T* tw = buf1 + B * N;
-  T* base = reinterpret_cast<T*>(half + by_ * hs);
-  const int nlines = H * N;
-  const int l0 = bx_ * B;
-  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t % B, e = t / B, gl = l0 + l;
-    T v;
-    v.x = 0;
-    v.y = 0;
-    if (gl < nlines) v = base[(size_t(gl / H) * N + e) * H + gl % H];
-    buf0[l * N + e] = v;
-  }
-  __syncthreads();
-  const T* Y = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign);
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t % B, e = t / B, gl = l0 + l;
-    if (gl < nlines) base[(size_t(gl / H) * N + e) * H + gl % H] = Y[l * N + e];
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_fft_y_half(R* __restrict__ half, size_t hs, FftPlan plan,
-                                                    const R* __restrict__ twiddle, int sign, int B,
-                                                    const int* __restrict__ skip) {
-  fft_y_half_body<R>(half, hs, plan, twiddle, sign, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
 namespace {
 __device__ inline void sinc_jv_d(double x, double& s, double& j) {
   if (x < 0.5) {
@@ -1181,76 +1088,131 @@ __device__ inline void sinc_jv_d(double x, double& s, double& j) {
 }
 }  // namespace
 
-// z forward, Green's-function scaling, z inverse for B columns (kx, ky) of all six fields
-template <typename R>
-__device__ __forceinline__ void fft_z_green_body(R* __restrict__ half, size_t hs, FftPlan plan,
-                                                     const R* __restrict__ twiddle, WaveParams wp, int B,
-                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
+// ------------------------------------------------------------------------------------------
+// Coalesced wave-space pipeline for N <= 256 (5 passes, in place on the three packed
+// complex grids Z_c = F_c + i T_c):
+//   z, y  : transforms along z, then y; a workgroup takes B consecutive x of B lines,
+//           so every load and store is a run of B contiguous complex values
+//   x+G   : one workgroup per pair of rows (ky, kz) and (-ky, -kz) of all three grids:
+//           forward x transform, split of the packed spectra by Hermitian symmetry
+//           (F^(k) = (Z(k) + conj Z(-k)) / 2, T^(k) = (Z(k) - conj Z(-k)) / 2i, the -k
+//           partner lies in the paired row), Green's-function scaling, repacking as
+//           Y^ = U^ + i W^, inverse x transform
+//   y, z  : inverse transforms
+// The product is the same linear operator as the half-spectrum pipeline.
+// ------------------------------------------------------------------------------------------
+
+template <typename R, int DIR>
+__device__ __forceinline__ void fft_lines_body(R* __restrict__ grid, size_t cs, FftPlan plan,
+                                               const R* __restrict__ twiddle, int sign, int B,
+                                               const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
-  const int N = plan.n, H = N / 2 + 1;
-  const int NL = 6 * B;
+  const int N = plan.n;
+  T* buf0 = reinterpret_cast<T*>(smem_raw);
+  T* buf1 = buf0 + B * N;
+  T* tw = buf1 + B * N;
+  T* base = reinterpret_cast<T*>(grid + by_ * cs);
+  const int line0 = bx_ * B;  // line gl = o N + x: B consecutive x of one o
+  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int l = t % B, e = t / B, gl = line0 + l, o = gl / N, x = gl % N;
+    const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
+    buf0[l * N + e] = base[off];
+  }
+  __syncthreads();
+  const T* Y = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign);
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int l = t % B, e = t / B, gl = line0 + l, o = gl / N, x = gl % N;
+    const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
+    base[off] = Y[l * N + e];
+  }
+}
+
+template <typename R, int DIR>
+__global__ __launch_bounds__(256) void k_fft_lines(R* __restrict__ grid, size_t cs, FftPlan plan,
+                                                   const R* __restrict__ twiddle, int sign, int B,
+                                                   const int* __restrict__ skip) {
+  fft_lines_body<R, DIR>(grid, cs, plan, twiddle, sign, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename R>
+__device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs, FftPlan plan,
+                                                const R* __restrict__ twiddle, WaveParams wp, int G,
+                                                const int* __restrict__ skip, int bx_, int by_, int gx_) {
+  if (skip && *skip) return;
+  using T = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = plan.n, NN = N * N;
+  // G row slots per workgroup; slot g takes row r = bx G + g and its partner rp when
+  // r <= rp (each pair once).  Line (g, c, q) = component c of row q (0: r, 1: rp) sits
+  // at (6 g + 2 c + q) N; lines of idle slots are zero.
+  const int NL = 6 * G;
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + NL * N;
   T* tw = buf1 + NL * N;
-  const int ncol = H * N;
-  const int c0 = bx_ * B;
+  auto partner = [N](int r) { return ((N - r / N) % N) * N + (N - r % N) % N; };
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
-  // line index: l = f * B + b  (field f, column c0 + b)
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
-    const int b = t % B, f = (t / B) % 6, e = t / NL, col = c0 + b;
+    const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
+    const int r = bx_ * G + g;
     T v;
     v.x = 0;
     v.y = 0;
-    if (col < ncol) v = reinterpret_cast<const T*>(half + f * hs)[size_t(e) * ncol + col];
-    buf0[(f * B + b) * N + e] = v;
+    if (r < NN) {
+      const int rp = partner(r);
+      if (rp >= r && (q == 0 || rp != r)) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
+    }
+    buf0[line * N + x] = v;
   }
   __syncthreads();
   T* X = stockham<T, R>(buf0, buf1, tw, N, NL, plan, -1);
-  T* scratch = (X == buf0) ? buf1 : buf0;
+  T* O = (X == buf0) ? buf1 : buf0;
   const double tp = 2.0 * M_PI / wp.L;
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int b = t % B, kz = t / B, col = c0 + b;
-    const int kx = col % H, ky = col / H;
-    T* ln[6];
-    for (int f = 0; f < 6; ++f) ln[f] = X + (f * B + b) * N + kz;
+  for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
+    const int g = t / (2 * N), q = (t / N) & 1, kx = t % N;
+    const int r = bx_ * G + g;
+    if (r >= NN) continue;
+    const int rp = partner(r);
+    if (rp < r || (rp == r && q == 1)) continue;
+    const int qm = rp == r ? 0 : 1 - q, kxm = (N - kx) % N;
+    const int row = q ? rp : r;
+    const int kz = row / N, ky = row % N;
+    const int l0 = 6 * g;
     const bool nyq = (N % 2 == 0) && (kx == N / 2 || ky == N / 2 || kz == N / 2);
-    if (col >= ncol || nyq || (kx == 0 && ky == 0 && kz == 0)) {
-      for (int f = 0; f < 6; ++f) {
-        ln[f]->x = 0;
-        ln[f]->y = 0;
+    if (nyq || (kx == 0 && ky == 0 && kz == 0)) {
+      for (int c = 0; c < 3; ++c) {
+        O[(l0 + 2 * c + q) * N + kx].x = 0;
+        O[(l0 + 2 * c + q) * N + kx].y = 0;
       }
       continue;
     }
-    const double k[3] = {tp * kx, tp * (ky < N / 2 ? ky : ky - N), tp * (kz < N / 2 ? kz : kz - N)};
+    double Fr[3], Fi[3], Tr[3], Ti[3];
+    for (int c = 0; c < 3; ++c) {
+      const T z = X[(l0 + 2 * c + q) * N + kx], zm = X[(l0 + 2 * c + qm) * N + kxm];
+      Fr[c] = 0.5 * (double(z.x) + double(zm.x));
+      Fi[c] = 0.5 * (double(z.y) - double(zm.y));
+      Tr[c] = 0.5 * (double(z.y) + double(zm.y));
+      Ti[c] = -0.5 * (double(z.x) - double(zm.x));
+    }
+    const double k[3] = {tp * (kx <= N / 2 ? kx : kx - N), tp * (ky < N / 2 ? ky : ky - N),
+                         tp * (kz < N / 2 ? kz : kz - N)};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     const double kn = sqrt(k2);
     const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
     double sk, jk;
     sinc_jv_d(kn * wp.a, sk, jk);
-    const double q = k2 / (4.0 * wp.xi * wp.xi);
-    const double damp = (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / wp.eta;
-    double Fr[3], Fi[3], Tr[3], Ti[3];
-    for (int a = 0; a < 3; ++a) {
-      Fr[a] = ln[a]->x;
-      Fi[a] = ln[a]->y;
-      Tr[a] = ln[3 + a]->x;
-      Ti[a] = ln[3 + a]->y;
-    }
+    const double qq = k2 / (4.0 * wp.xi * wp.xi);
+    const double damp = (1.0 + qq) * exp(-(1.0 - wp.eta_t) * qq) / wp.eta;
     double gr[3], gi[3], Bk;
     if (wp.brownian) {
-      // square root of the wave-space operator applied to grid noise: with M_w =
-      // scale I F^-1 C^H b P C F I^T (F unnormalised, b = damp / k^2), the factor
-      // sqrt(scale / N^3) I F^-1 C^H sqrt(b) P F maps white grid noise to a vector
-      // of covariance M_w
       Bk = sqrt(wp.scale / (double(N) * N * N) * damp) / kn;
       for (int a = 0; a < 3; ++a) {
         gr[a] = Fr[a];
         gi[a] = Fi[a];
       }
     } else {
-      // g = sinc F + (i/2) jv (k x T), transverse part, times B(k)
       Bk = wp.scale * damp / k2;
       const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
       const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
@@ -1266,230 +1228,72 @@ __device__ __forceinline__ void fft_z_green_body(R* __restrict__ half, size_t hs
       ur[a] = Bk * (gr[a] - pr * kh[a]);
       ui[a] = Bk * (gi[a] - pim * kh[a]);
     }
-    // U = sinc u (fields 0..2), W = (i/2) jv (k x u) (fields 3..5)
+    // U^ = sinc u^, W^ = (i/2) jv (k x u^); Y^ = U^ + i W^
     const double kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
     const double kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
-    for (int a = 0; a < 3; ++a) {
-      ln[a]->x = R(sk * ur[a]);
-      ln[a]->y = R(sk * ui[a]);
-      ln[3 + a]->x = R(-0.5 * jk * kui[a]);
-      ln[3 + a]->y = R(0.5 * jk * kur[a]);
+    for (int c = 0; c < 3; ++c) {
+      const double Ur = sk * ur[c], Ui = sk * ui[c];
+      const double Wr = -0.5 * jk * kui[c], Wi = 0.5 * jk * kur[c];
+      T y;
+      y.x = R(Ur - Wi);
+      y.y = R(Ui + Wr);
+      O[(l0 + 2 * c + q) * N + kx] = y;
     }
   }
   __syncthreads();
-  // inverse transform along z with conjugated twiddles
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t].y = -tw[t].y;
   __syncthreads();
-  const T* Y = stockham<T, R>(X, scratch, tw, N, NL, plan, +1);
+  const T* Y = stockham<T, R>(O, X, tw, N, NL, plan, +1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
-    const int b = t % B, f = (t / B) % 6, e = t / NL, col = c0 + b;
-    if (col < ncol) reinterpret_cast<T*>(half + f * hs)[size_t(e) * ncol + col] = Y[(f * B + b) * N + e];
+    const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
+    const int r = bx_ * G + g;
+    if (r >= NN) continue;
+    const int rp = partner(r);
+    if (rp < r || (q == 1 && rp == r)) continue;
+    reinterpret_cast<T*>(grid + c * cs)[size_t(q ? rp : r) * N + x] = Y[line * N + x];
   }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_z_green(R* __restrict__ half, size_t hs, FftPlan plan,
-                                                     const R* __restrict__ twiddle, WaveParams wp, int B,
-                                                     const int* __restrict__ skip) {
-  fft_z_green_body<R>(half, hs, plan, twiddle, wp, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
+__global__ __launch_bounds__(256) void k_fft_xgreen(R* __restrict__ grid, size_t cs, FftPlan plan,
+                                                    const R* __restrict__ twiddle, WaveParams wp, int G,
+                                                    const int* __restrict__ skip) {
+  fft_xgreen_body<R>(grid, cs, plan, twiddle, wp, G, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-// x inverse + merge: rows (y, z): Y_c = u_c + i w_c rebuilt from the half spectra of
-// fields c (u) and 3 + c (w), transformed back into grid component c
-template <typename R>
-__device__ __forceinline__ void fft_x_merge_body(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
-                                                     size_t cs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip, int bx_, int by_, int gx_) {
-  if (skip && *skip) return;
-  using T = typename C2<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  const int N = plan.n, H = N / 2 + 1;
-  T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + B * N;
-  T* tw = buf1 + B * N;
-  const int c = by_;
-  const T* sU = reinterpret_cast<const T*>(half + c * hs);
-  const T* sW = reinterpret_cast<const T*>(half + (3 + c) * hs);
-  T* dst = reinterpret_cast<T*>(grid + c * cs);
-  const size_t row0 = size_t(bx_) * B;
-  load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, +1);
-  for (int t = threadIdx.x; t < B * H; t += blockDim.x) {
-    const int l = t / H, kx = t % H;
-    const T u = sU[(row0 + l) * H + kx], w = sW[(row0 + l) * H + kx];
-    T y;  // u + i w
-    y.x = u.x - w.y;
-    y.y = u.y + w.x;
-    if (kx == N / 2 && N % 2 == 0) {
-      y.x = 0;
-      y.y = 0;
-    }
-    buf0[l * N + kx] = y;
-    if (kx > 0 && kx < N - kx) {
-      T z;  // conj(u) + i conj(w)
-      z.x = u.x + w.y;
-      z.y = -u.y + w.x;
-      buf0[l * N + N - kx] = z;
-    }
-  }
-  __syncthreads();
-  const T* X = stockham<T, R>(buf0, buf1, tw, N, B, plan, +1);
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) dst[row0 * N + t] = X[t];
+// row slots per workgroup of the x+Green pass: 6 G N complex lines stay within 1536
+int fft_green_rows(int N) { return N >= 256 ? 1 : 256 / N; }
+
+// lines per workgroup of the coalesced y/z passes: largest B in {16, 8, 4, 2, 1} dividing N
+// whose two LDS buffers and twiddles fit in 64 KB
+int fft_lines_b(int N, int rbytes) {
+  for (int B = 16; B > 1; B /= 2)
+    if (N % B == 0 && size_t(2 * rbytes) * (2 * size_t(B) * N + N) <= (size_t(64) << 10)) return B;
+  return 1;
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_fft_x_merge(const R* __restrict__ half, size_t hs, R* __restrict__ grid,
-                                                     size_t cs, FftPlan plan, const R* __restrict__ twiddle, int B,
-                                                     const int* __restrict__ skip) {
-  fft_x_merge_body<R>(half, hs, grid, cs, plan, twiddle, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-int fft_rows_x(int N) {
-  int B = 1;
-  while (B * 2 * N <= 1024 && ((N * N) % (B * 2)) == 0) B *= 2;
-  return B;
-}
-
-int fft_lines_y(int N) {
-  int B = 1;
-  while (B * 2 * N <= 1024) B *= 2;
-  return B;
-}
-
-int fft_cols_z(int N) {
-  int B = 1;
-  while (B * 2 * 6 * N <= 1536) B *= 2;
-  return B;
-}
-
-template <typename R>
-void launch_wave_fft(R* grid, R* half, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
+void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveParams& wp, int stage,
                      hipStream_t st, const int* skip) {
   using T = typename C2<R>::T;
-  const int N = plan.n, H = N / 2 + 1;
+  const int N = plan.n;
   const size_t cs = 2 * size_t(N) * N * N;
-  const size_t hs = 2 * size_t(H) * N * N;
-  if (stage == 0 || stage == 4) {
-    const int B = fft_rows_x(N);
+  if (stage == 2) {
+    const int G = fft_green_rows(N);
+    const size_t shm = sizeof(T) * (12 * size_t(G) * N + N);
+    k_fft_xgreen<R><<<(N * N + G - 1) / G, kThreads, shm, st>>>(grid, cs, plan, twiddle, wp, G, skip);
+  } else {
+    const int B = fft_lines_b(N, sizeof(R));
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
     dim3 g(N * N / B, 3);
-    if (stage == 0)
-      k_fft_x_split<R><<<g, kThreads, shm, st>>>(grid, cs, half, hs, plan, twiddle, B, skip);
+    const int sign = stage < 2 ? -1 : +1;
+    if (stage == 0 || stage == 4)
+      k_fft_lines<R, 2><<<g, kThreads, shm, st>>>(grid, cs, plan, twiddle, sign, B, skip);
     else
-      k_fft_x_merge<R><<<g, kThreads, shm, st>>>(half, hs, grid, cs, plan, twiddle, B, skip);
-  } else if (stage == 1 || stage == 3) {
-    const int B = fft_lines_y(N);
-    const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
-    dim3 g((H * N + B - 1) / B, 6);
-    k_fft_y_half<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, stage == 1 ? -1 : +1, B, skip);
-  } else {
-    const int B = fft_cols_z(N);
-    const size_t shm = sizeof(T) * (2 * size_t(6 * B) * N + N);
-    dim3 g((H * N + B - 1) / B);
-    k_fft_z_green<R><<<g, kThreads, shm, st>>>(half, hs, plan, twiddle, wp, B, skip);
+      k_fft_lines<R, 1><<<g, kThreads, shm, st>>>(grid, cs, plan, twiddle, sign, B, skip);
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Green's-function scaling of the packed spectra (one thread per +-k pair)
-// ------------------------------------------------------------------------------------------
-
-namespace {
-__device__ inline void sinc_jv(double x, double& s, double& j) {
-  if (x < 0.5) {
-    const double x2 = x * x;
-    s = 1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0 * (1.0 - x2 / 110.0))));
-    j = 1.0 - x2 / 10.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0 * (1.0 - x2 / 88.0 * (1.0 - x2 / 130.0))));
-  } else {
-    double sn, cn;
-    sincos(x, &sn, &cn);
-    s = sn / x;
-    j = 3.0 * (sn - x * cn) / (x * x * x);
-  }
-}
-}  // namespace
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_green(R* __restrict__ grid, size_t cs, WaveParams wp, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  using T = typename C2<R>::T;
-  const int N = wp.n;
-  const size_t N3 = size_t(N) * N * N;
-  const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= N3) return;
-  const int ix = int(idx % N), iy = int((idx / N) % N), iz = int(idx / (size_t(N) * N));
-  const int jx = (N - ix) % N, jy = (N - iy) % N, jz = (N - iz) % N;
-  const size_t midx = (size_t(jz) * N + jy) * N + jx;
-  if (midx < idx) return;  // the partner thread handles this pair
-  T* Z[3] = {reinterpret_cast<T*>(grid), reinterpret_cast<T*>(grid + cs), reinterpret_cast<T*>(grid + 2 * cs)};
-  const bool nyq = (N % 2 == 0) && (ix == N / 2 || iy == N / 2 || iz == N / 2);
-  if (nyq || idx == midx) {
-    T zero;
-    zero.x = 0;
-    zero.y = 0;
-    for (int c = 0; c < 3; ++c) {
-      Z[c][idx] = zero;
-      Z[c][midx] = zero;
-    }
-    return;
-  }
-  const double tp = 2.0 * M_PI / wp.L;
-  const double k[3] = {tp * (ix < N / 2 ? ix : ix - N), tp * (iy < N / 2 ? iy : iy - N),
-                       tp * (iz < N / 2 ? iz : iz - N)};
-  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-  const double kn = sqrt(k2);
-  const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
-  double sk, jk;
-  sinc_jv(kn * wp.a, sk, jk);
-  const double q = k2 / (4.0 * wp.xi * wp.xi);
-  const double Bk = wp.scale * (1.0 + q) * exp(-(1.0 - wp.eta_t) * q) / (wp.eta * k2);
-  // unpack F(k), T(k) from Z(k) = F + i T and Z(-k) = conj(F(k)) + i conj(T(k))
-  double Fr[3], Fi[3], Tr[3], Ti[3];
-  for (int c = 0; c < 3; ++c) {
-    const T zk = Z[c][idx], zm = Z[c][midx];
-    const double ar = zk.x, ai = zk.y, br = zm.x, bi = -zm.y;  // b = conj(Z(-k))
-    Fr[c] = 0.5 * (ar + br);
-    Fi[c] = 0.5 * (ai + bi);
-    Tr[c] = 0.5 * (ai - bi);
-    Ti[c] = -0.5 * (ar - br);
-  }
-  // g = sinc F + (i/2) jv (k x T), projected transverse to k
-  double gr[3], gi[3];
-  const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
-  const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
-  for (int c = 0; c < 3; ++c) {
-    gr[c] = sk * Fr[c] - 0.5 * jk * cxi[c];
-    gi[c] = sk * Fi[c] + 0.5 * jk * cxr[c];
-  }
-  const double pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
-  const double pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
-  double ur[3], ui[3];
-  for (int c = 0; c < 3; ++c) {
-    ur[c] = Bk * (gr[c] - pr * kh[c]);
-    ui[c] = Bk * (gi[c] - pim * kh[c]);
-  }
-  // bead velocity U = sinc u, angular velocity W = (i/2) jv (k x u)
-  const double kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
-  const double kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
-  for (int c = 0; c < 3; ++c) {
-    const double Ur = sk * ur[c], Ui = sk * ui[c];
-    const double Wr = -0.5 * jk * kui[c], Wi = 0.5 * jk * kur[c];
-    T yk, ym;
-    yk.x = R(Ur - Wi);
-    yk.y = R(Ui + Wr);
-    ym.x = R(Ur + Wi);
-    ym.y = R(-Ui + Wr);
-    Z[c][idx] = yk;
-    Z[c][midx] = ym;
-  }
-}
-
-template <typename R>
-void launch_green_scale(R* grid, size_t comp_stride, const WaveParams& wp, hipStream_t st, const int* skip) {
-  const size_t N3 = size_t(wp.n) * wp.n * wp.n;
-  k_green<R><<<nblocks((long long)N3), kThreads, 0, st>>>(grid, comp_stride, wp, skip);
-}
-
-// explicit instantiations
 // ------------------------------------------------------------------------------------------
 // multi-system launches: block -> (system, local block) by the prefix table, then the
 // single-system body with that system's pointers (the Arnoldi step maps z -> w)
@@ -1547,23 +1351,19 @@ __global__ __launch_bounds__(256) void kb_fft(const BatchDesc* __restrict__ D, c
   const int s = batch_sys(off, nsys, blockIdx.x);
   const BatchDesc& d = D[s];
   const int lb = blockIdx.x - off[s];
-  const int N = d.plan.n, H = N / 2 + 1;
-  const size_t cs = 2 * size_t(N) * N * N, hs = 2 * size_t(H) * N * N;
+  const int N = d.plan.n;
+  const size_t cs = 2 * size_t(N) * N * N;
   R* grid = static_cast<R*>(d.grid);
-  R* half = static_cast<R*>(d.half);
   const R* tw = pick<R>(d.tw64, d.tw32);
   const int* stop = &d.ctl->stop;
-  if (STAGE == 0 || STAGE == 4) {
-    const int gx = N * N / d.bx;
-    if (STAGE == 0)
-      fft_x_split_body<R>(grid, cs, half, hs, d.plan, tw, d.bx, stop, lb % gx, lb / gx, gx);
-    else
-      fft_x_merge_body<R>(half, hs, grid, cs, d.plan, tw, d.bx, stop, lb % gx, lb / gx, gx);
-  } else if (STAGE == 1 || STAGE == 3) {
-    const int gx = (H * N + d.by - 1) / d.by;
-    fft_y_half_body<R>(half, hs, d.plan, tw, STAGE == 1 ? -1 : +1, d.by, stop, lb % gx, lb / gx, gx);
+  if (STAGE == 2) {
+    fft_xgreen_body<R>(grid, cs, d.plan, tw, d.wp, d.bg, stop, lb, 0, 0);
   } else {
-    fft_z_green_body<R>(half, hs, d.plan, tw, d.wp, d.bz, stop, lb, 0, 0);
+    const int gx = N * N / d.bl;
+    if (STAGE == 0 || STAGE == 4)
+      fft_lines_body<R, 2>(grid, cs, d.plan, tw, STAGE == 0 ? -1 : +1, d.bl, stop, lb % gx, lb / gx, gx);
+    else
+      fft_lines_body<R, 1>(grid, cs, d.plan, tw, STAGE == 1 ? -1 : +1, d.bl, stop, lb % gx, lb / gx, gx);
   }
 }
 
@@ -1598,11 +1398,11 @@ void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d) {
   d.K = sp->K;
   const size_t rb = prec ? sizeof(float) : sizeof(double);
   const size_t per = rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int);
-  d.C = int(std::min<size_t>(128, (size_t(64) << 10) / per)) & ~3;  // as launch_spread_gather
+  d.C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // as launch_spread_gather
 }
 
 int batch_blocks(const BatchDesc& d, int kind) {
-  const int N = d.plan.n, H = N / 2 + 1;
+  const int N = d.plan.n;
   switch (kind) {
     case BK_PRECOND:
     case BK_AGG:
@@ -1611,12 +1411,11 @@ int batch_blocks(const BatchDesc& d, int kind) {
       return int((size_t(d.nb) * kBatchLpr + kThreads - 1) / kThreads);
     case BK_SPREAD:
       return d.bin_start ? d.nbin * d.nbin * d.nbin : 0;
-    case BK_FFT_X:
-      return N * N / d.bx * 3;
-    case BK_FFT_Y:
-      return (H * N + d.by - 1) / d.by * 6;
-    case BK_FFT_Z:
-      return (H * N + d.bz - 1) / d.bz;
+    case BK_FFT_OUTER:
+    case BK_FFT_MID:
+      return N * N / d.bl * 3;
+    case BK_FFT_GREEN:
+      return (N * N + d.bg - 1) / d.bg;
     case BK_INTERP:
       return (d.nb + 3) / 4;
     case BK_CGS:
@@ -1632,12 +1431,11 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec) {
   switch (kind) {
     case BK_SPREAD:
       return (rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int)) * d.C;
-    case BK_FFT_X:
-      return tb * (2 * size_t(d.bx) * N + N);
-    case BK_FFT_Y:
-      return tb * (2 * size_t(d.by) * N + N);
-    case BK_FFT_Z:
-      return tb * (2 * size_t(6 * d.bz) * N + N);
+    case BK_FFT_OUTER:
+    case BK_FFT_MID:
+      return tb * (2 * size_t(d.bl) * N + N);
+    case BK_FFT_GREEN:
+      return tb * (12 * size_t(d.bg) * N + N);
     default:
       return 0;
   }
@@ -1654,19 +1452,19 @@ void batch_mobility(int kind, int stage, const BatchDesc* D, const int* off, int
     case BK_SPREAD:
       kb_spread<R><<<total, 256, shm, st>>>(D, off, nsys);
       break;
-    case BK_FFT_X:
+    case BK_FFT_OUTER:
       if (stage == 0)
         kb_fft<R, 0><<<total, kThreads, shm, st>>>(D, off, nsys);
       else
         kb_fft<R, 4><<<total, kThreads, shm, st>>>(D, off, nsys);
       break;
-    case BK_FFT_Y:
+    case BK_FFT_MID:
       if (stage == 1)
         kb_fft<R, 1><<<total, kThreads, shm, st>>>(D, off, nsys);
       else
         kb_fft<R, 3><<<total, kThreads, shm, st>>>(D, off, nsys);
       break;
-    case BK_FFT_Z:
+    case BK_FFT_GREEN:
       kb_fft<R, 2><<<total, kThreads, shm, st>>>(D, off, nsys);
       break;
     case BK_INTERP:
@@ -1687,10 +1485,10 @@ void launch_batch_mobility(int kind, int prec, int stage, const BatchDesc* D, co
     batch_mobility<double>(kind, stage, D, off, nsys, total, shm, st);
 }
 
-template void launch_wave_fft<double>(double*, double*, const FftPlan&, const double*, const WaveParams&, int,
-                                      hipStream_t, const int*);
-template void launch_wave_fft<float>(float*, float*, const FftPlan&, const float*, const WaveParams&, int,
-                                     hipStream_t, const int*);
+template void launch_wave_fft<double>(double*, const FftPlan&, const double*, const WaveParams&, int, hipStream_t,
+                                      const int*);
+template void launch_wave_fft<float>(float*, const FftPlan&, const float*, const WaveParams&, int, hipStream_t,
+                                     const int*);
 template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t, const int*);
 template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t, const int*);
 template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
@@ -1705,7 +1503,5 @@ template void launch_interp<float>(int, const double*, const float*, const WaveP
                                    const int*, const double*, const double*, const SpreadPlan*);
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
-template void launch_green_scale<double>(double*, size_t, const WaveParams&, hipStream_t, const int*);
-template void launch_green_scale<float>(float*, size_t, const WaveParams&, hipStream_t, const int*);
 
 }  // namespace fsd
