@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 
 
 # kernel behind each timer class (rocprofv3 names), for matching the two measurements
-KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_cols", "fft_first": "k_fft_lines<2>",
+KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_split", "fft_first": "k_fft_lines<2>",
              "fft_y": "k_fft_lines<1>", "fft_green": "k_fft_xgreen", "fft_last": "k_fft_lines<2>",
              "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused", "cgs_dot": "k_cgs<0>",
              "cgs_update": "k_cgs<1>", "cgs_norm_arnoldi": "k_cgs<2>"}

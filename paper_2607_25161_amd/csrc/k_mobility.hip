@@ -620,16 +620,18 @@ __global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restr
   g[2 * cs + 1] = a5;
 }
 
-// Column form of the gather for 8^3 blocks: lane (x, y) of a wavefront owns one grid
-// column of the block and ZW consecutive z planes; the 8 / ZW wavefronts of the
-// workgroup take the remaining planes.  A candidate whose support misses the block's
-// x, y or the wavefront's z range is skipped by the whole wavefront (a uniform test);
-// for the others each lane forms the x-y weight once and reuses it over its planes.
-// Candidates are staged in LDS in chunks of C (dynamic shared memory): first the
-// sorted bead index of each candidate, then the weights with independent loads in
-// flight, then start cells and force moments.
-template <typename R, int ZW>
-__device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_start,
+// Gather spreading on 8^3 blocks with the candidates split among the four wavefronts:
+// lane (x, y) owns one grid column and all 8 planes of the block; wavefront w takes
+// every fourth staged candidate, skips it as a whole when its support misses the block
+// (a uniform test), and otherwise forms the x-y weight once per lane and reuses it over
+// the planes.  The four partial blocks are added through LDS in a fixed order
+// (deterministic).  Candidates are staged in LDS in chunks of C (dynamic shared
+// memory): the sorted bead index, then the weights with independent loads in flight,
+// then start cells and force moments.
+constexpr int kSplitRedBytes64 = 2 * 48 * 64 * 8;  // LDS of the two-step reduction (FP64)
+
+template <typename R>
+__device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_start,
                                                                const int* __restrict__ bin_end,
                                                                const int* __restrict__ perm,
                                                                const int4* __restrict__ starts,
@@ -638,7 +640,7 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
                                                                int nbin, int K, int C, R* __restrict__ grid,
                                                                size_t cs, const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
-  constexpr int BS = 8, NT = 64 * (BS / ZW);
+  constexpr int BS = 8, NT = 256, ZW = 8, NW = NT / 64;
   const int P = wp.support, N = wp.n, P3 = 3 * P;
   extern __shared__ unsigned char smem_raw[];
   R* sh_w = reinterpret_cast<R*>(smem_raw);                 // C * 3P
@@ -649,7 +651,7 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
   const int bl = xcd_remap(bx_, nbin * nbin * nbin);  // each XCD takes a contiguous slab of blocks
   const int bx = bl % nbin, by = (bl / nbin) % nbin, bz = bl / (nbin * nbin);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS + wave * ZW;
+  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
   const int mx = x0 + (lane & 7), my = y0 + (lane >> 3);
   // candidate beads: per (kz, ky) one or two contiguous runs of the sorted bead array
   // (bins bx-K+1 .. bx along x, split where they wrap); thread r computes run r
@@ -733,7 +735,7 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
       for (int f = 0; f < 6; ++f) sh_l[6 * c + f] = R(l[f]);
     }
     __syncthreads();
-    for (int q = 0; q < n; ++q) {
+    for (int q = wave; q < n; q += NW) {
       const int4 s = sh_s[q];
       // offsets of the block (or the wave's planes) from the support start, mod N
       int ox = x0 - s.x, oy = y0 - s.y, oz = z0 - s.z;
@@ -766,6 +768,32 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
       }
     }
   }
+  // partial blocks of waves 2, 3 -> added by waves 0, 1; then wave 1 -> wave 0
+  __syncthreads();
+  R* red = reinterpret_cast<R*>(smem_raw);  // [2][48][64], reusing the staging area
+  if (wave >= 2)
+#pragma unroll
+    for (int zz = 0; zz < ZW; ++zz)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) red[((wave - 2) * 48 + zz * 6 + c) * 64 + lane] = a[zz][c];
+  __syncthreads();
+  if (wave < 2)
+#pragma unroll
+    for (int zz = 0; zz < ZW; ++zz)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a[zz][c] += red[(wave * 48 + zz * 6 + c) * 64 + lane];
+  __syncthreads();
+  if (wave == 1)
+#pragma unroll
+    for (int zz = 0; zz < ZW; ++zz)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) red[(zz * 6 + c) * 64 + lane] = a[zz][c];
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int zz = 0; zz < ZW; ++zz)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[zz][c] += red[(zz * 6 + c) * 64 + lane];
 #pragma unroll
   for (int zz = 0; zz < ZW; ++zz) {
     const size_t m = (size_t(z0 + zz) * N + my) * N + mx;
@@ -779,17 +807,16 @@ __device__ __forceinline__ void spread_cols_body(const int* __restrict__ bin_sta
   }
 }
 
-template <typename R, int ZW>
-__global__ __launch_bounds__(64 * (8 / ZW)) void k_spread_cols(const int* __restrict__ bin_start,
-                                                               const int* __restrict__ bin_end,
-                                                               const int* __restrict__ perm,
-                                                               const int4* __restrict__ starts,
-                                                               const R* __restrict__ weights,
-                                                               const double* __restrict__ lam, WaveParams wp,
-                                                               int nbin, int K, int C, R* __restrict__ grid,
-                                                               size_t cs, const int* __restrict__ skip) {
-  spread_cols_body<R, ZW>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, blockIdx.x, blockIdx.y, gridDim.x);
+template <typename R>
+__global__ __launch_bounds__(256) void k_spread_split(const int* __restrict__ bin_start, const int* __restrict__ bin_end,
+                                                      const int* __restrict__ perm, const int4* __restrict__ starts,
+                                                      const R* __restrict__ weights, const double* __restrict__ lam,
+                                                      WaveParams wp, int nbin, int K, int C, R* __restrict__ grid,
+                                                      size_t cs, const int* __restrict__ skip) {
+  spread_split_body<R>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, blockIdx.x,
+                       blockIdx.y, gridDim.x);
 }
+
 
 namespace {
 template <typename R>
@@ -814,9 +841,9 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
     // static arrays take the rest of 64 KB)
     const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
     const int C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
-    k_spread_cols<R, 2><<<nblk, 256, per * C, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
-                                                    plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, C, grid, cs,
-                                                    skip);
+    const size_t shm = std::max(per * C, size_t(kSplitRedBytes64) / sizeof(double) * sizeof(R));
+    k_spread_split<R><<<nblk, 256, shm, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts, plan_weights<R>(sp),
+                                              lam, wp, sp->nbin, sp->K, C, grid, cs, skip);
   }
   else
     k_spread_gather<R, 4><<<nblk, 64, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
@@ -1145,24 +1172,32 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int N = plan.n, NN = N * N;
-  // G row slots per workgroup; slot g takes row r = bx G + g and its partner rp when
-  // r <= rp (each pair once).  Line (g, c, q) = component c of row q (0: r, 1: rp) sits
-  // at (6 g + 2 c + q) N; lines of idle slots are zero.
+  // G row slots per workgroup; slot g takes the pair number p = bx G + g of the
+  // N^2/2 + 2 pairs {r, rp} (r = kz N + ky, rp = its (-kz, -ky) partner, r <= rp; the
+  // four self-paired rows have rp == r).  Line (g, c, q) = component c of row q (0: r,
+  // 1: rp) sits at (6 g + 2 c + q) N; lines of idle slots are zero.
   const int NL = 6 * G;
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + NL * N;
   T* tw = buf1 + NL * N;
+  const int H = N / 2, npair = NN / 2 + 2;
+  auto row_of = [N, H](int p) {  // pair number -> its first row r
+    if (p <= H) return p;                        // kz = 0, ky = 0 .. N/2
+    p -= H + 1;
+    if (p < (H - 1) * N) return (1 + p / N) * N + p % N;  // kz = 1 .. N/2 - 1, all ky
+    return H * N + (p - (H - 1) * N);                      // kz = N/2, ky = 0 .. N/2
+  };
   auto partner = [N](int r) { return ((N - r / N) % N) * N + (N - r % N) % N; };
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
     const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
-    const int r = bx_ * G + g;
+    const int pn = bx_ * G + g;
     T v;
     v.x = 0;
     v.y = 0;
-    if (r < NN) {
-      const int rp = partner(r);
-      if (rp >= r && (q == 0 || rp != r)) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
+    if (pn < npair) {
+      const int r = row_of(pn), rp = partner(r);
+      if (q == 0 || rp != r) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
     }
     buf0[line * N + x] = v;
   }
@@ -1172,10 +1207,10 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   const double tp = 2.0 * M_PI / wp.L;
   for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
     const int g = t / (2 * N), q = (t / N) & 1, kx = t % N;
-    const int r = bx_ * G + g;
-    if (r >= NN) continue;
-    const int rp = partner(r);
-    if (rp < r || (rp == r && q == 1)) continue;
+    const int pn = bx_ * G + g;
+    if (pn >= npair) continue;
+    const int r = row_of(pn), rp = partner(r);
+    if (rp == r && q == 1) continue;
     const int qm = rp == r ? 0 : 1 - q, kxm = (N - kx) % N;
     const int row = q ? rp : r;
     const int kz = row / N, ky = row % N;
@@ -1246,10 +1281,10 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   const T* Y = stockham<T, R>(O, X, tw, N, NL, plan, +1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
     const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
-    const int r = bx_ * G + g;
-    if (r >= NN) continue;
-    const int rp = partner(r);
-    if (rp < r || (q == 1 && rp == r)) continue;
+    const int pn = bx_ * G + g;
+    if (pn >= npair) continue;
+    const int r = row_of(pn), rp = partner(r);
+    if (q == 1 && rp == r) continue;
     reinterpret_cast<T*>(grid + c * cs)[size_t(q ? rp : r) * N + x] = Y[line * N + x];
   }
 }
@@ -1281,7 +1316,7 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
   if (stage == 2) {
     const int G = fft_green_rows(N);
     const size_t shm = sizeof(T) * (12 * size_t(G) * N + N);
-    k_fft_xgreen<R><<<(N * N + G - 1) / G, kThreads, shm, st>>>(grid, cs, plan, twiddle, wp, G, skip);
+    k_fft_xgreen<R><<<(N * N / 2 + 2 + G - 1) / G, kThreads, shm, st>>>(grid, cs, plan, twiddle, wp, G, skip);
   } else {
     const int B = fft_lines_b(N, sizeof(R));
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
@@ -1341,8 +1376,8 @@ __global__ __launch_bounds__(256) void kb_spread(const BatchDesc* __restrict__ D
   const int s = batch_sys(off, nsys, blockIdx.x);
   const BatchDesc& d = D[s];
   const size_t cs = 2 * size_t(d.wp.n) * d.wp.n * d.wp.n;
-  spread_cols_body<R, 2>(d.bin_start, d.bin_end, d.perm, d.starts, pick<R>(d.w64, d.w32), d.z, d.wp, d.nbin, d.K,
-                         d.C, static_cast<R*>(d.grid), cs, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
+  spread_split_body<R>(d.bin_start, d.bin_end, d.perm, d.starts, pick<R>(d.w64, d.w32), d.z, d.wp, d.nbin, d.K,
+                       d.C, static_cast<R*>(d.grid), cs, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
 }
 
 template <typename R, int STAGE>
@@ -1415,7 +1450,7 @@ int batch_blocks(const BatchDesc& d, int kind) {
     case BK_FFT_MID:
       return N * N / d.bl * 3;
     case BK_FFT_GREEN:
-      return (N * N + d.bg - 1) / d.bg;
+      return (N * N / 2 + 2 + d.bg - 1) / d.bg;
     case BK_INTERP:
       return (d.nb + 3) / 4;
     case BK_CGS:
@@ -1430,7 +1465,8 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec) {
   const size_t N = d.plan.n;
   switch (kind) {
     case BK_SPREAD:
-      return (rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int)) * d.C;
+      return std::max((rb * (3 * size_t(d.wp.support) + 6) + sizeof(int4) + sizeof(int)) * d.C,
+                      size_t(kSplitRedBytes64) / sizeof(double) * rb);
     case BK_FFT_OUTER:
     case BK_FFT_MID:
       return tb * (2 * size_t(d.bl) * N + N);
