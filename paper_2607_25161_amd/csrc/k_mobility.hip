@@ -308,18 +308,29 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
   const R* wy = wts[wv] + kMaxP;
   const R* wz = wts[wv] + 2 * kMaxP;
   R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-  const int P3 = P * P * P;
-  for (int idx = lane; idx < P3; idx += 64) {
-    const int kx = idx % P, ky = (idx / P) % P, kz = idx / (P * P);
-    const R w = wx[kx] * wy[ky] * wz[kz];
-    const size_t m = (size_t(wrapi(sz + kz, N)) * N + wrapi(sy + ky, N)) * N + wrapi(sx + kx, N);
-    const R* g = grid + 2 * m;
-    a0 += w * g[0];
-    a3 += w * g[1];
-    a1 += w * g[cs];
-    a4 += w * g[cs + 1];
-    a2 += w * g[2 * cs];
-    a5 += w * g[2 * cs + 1];
+  // lane -> (kx, ky) column of the support, each lane walking its column along z
+  // (one integer division per column; indices wrap by a conditional subtraction)
+  const int sxw = wrapi(sx, N), syw = wrapi(sy, N), szw = wrapi(sz, N);
+  const size_t plane = 2 * size_t(N) * N;
+  for (int pq = lane; pq < P * P; pq += 64) {
+    const int ky = pq / P, kx = pq - ky * P;
+    int x = sxw + kx, y = syw + ky;
+    x -= x >= N ? N : 0;
+    y -= y >= N ? N : 0;
+    const R wxy = wx[kx] * wy[ky];
+    const R* col = grid + 2 * (size_t(y) * N + x);
+    int z = szw;
+    for (int kz = 0; kz < P; ++kz) {
+      const R w = wxy * wz[kz];
+      const R* g = col + plane * z;
+      a0 += w * g[0];
+      a3 += w * g[1];
+      a1 += w * g[cs];
+      a4 += w * g[cs + 1];
+      a2 += w * g[2 * cs];
+      a5 += w * g[2 * cs + 1];
+      z = z + 1 == N ? 0 : z + 1;
+    }
   }
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
