@@ -282,7 +282,14 @@ typedef enum {
  * the neighbour-list storage or launch shapes change. */
 fsd_status fsd_set_graphs(fsd_system* s, int enable, int batch);
 
-/* Enable (1) or disable (0) event timing and reset the accumulators. */
+/* Enable (1) or disable (0) per-kernel event timing and reset the accumulators.  While
+ * timing is on, solves launch eagerly (no graphs), the real-space and wave-space parts of
+ * the mobility run one after the other on the system stream, GMRES checks its stop flag
+ * after every Arnoldi step (so no timed launch is one that returns at once), and each
+ * timed kernel is launched with hipExtLaunchKernel carrying its start/stop events; those
+ * intervals include the dispatch of the launch (a few microseconds).  Each change of the
+ * setting launches one empty kernel (fsd::k_timing_mark), so a profiler trace shows which
+ * launches were timed. */
 fsd_status fsd_set_timing(fsd_system* s, int enable);
 
 /* Accumulated milliseconds, launch counts and algorithmic HBM bytes (the minimum
@@ -290,6 +297,18 @@ fsd_status fsd_set_timing(fsd_system* s, int enable);
  * fsd_set_timing; each array holds FSD_TIMER_COUNT entries, bytes may be NULL.
  * Synchronises. */
 fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches, double* bytes);
+
+/* Average duration (ms) of one launch of the kernel behind timer class `timer`, in the
+ * system's Arnoldi precision and launch configuration: the kernel is launched `reps`
+ * times back to back on the system stream between one pair of HIP events, so the
+ * dispatch of each launch overlaps the previous one.  Inputs are the system's current
+ * scratch vectors; classes FSD_TIMER_REAL .. FSD_TIMER_PRECOND (the Gram-Schmidt classes
+ * give FSD_EINVAL).  The spectral grid and the scratch vectors are left undefined (every
+ * solve rewrites them); positions, lists and solution are untouched.  An empty kernel
+ * (fsd::k_timing_mark) is launched before and after the replays.  Neighbour lists, the
+ * spreading plan and the preconditioner factors are built first when the positions have
+ * moved since they were.  Synchronises the system stream. */
+fsd_status fsd_time_kernel(fsd_system* s, int timer, int reps, double* avg_ms);
 
 #ifdef __cplusplus
 }

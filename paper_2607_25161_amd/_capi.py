@@ -94,6 +94,7 @@ _sig("fsd_normals", C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c
 _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
+_sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
 
 _sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
 _sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
@@ -325,6 +326,14 @@ class System:
         cnt = (C.c_longlong * len(TIMER_NAMES))()
         self._check(lib.fsd_get_timers(self._h, _dptr(ms), cnt, _dptr(by)), "fsd_get_timers")
         return {n: (float(ms[k]), int(cnt[k]), float(by[k])) for k, n in enumerate(TIMER_NAMES)}
+
+    def time_kernel(self, timer, reps=200):
+        """Average ms of one launch of the kernel behind `timer` (a TIMER_NAMES entry),
+        replayed `reps` times back to back between one pair of events."""
+        out = C.c_double(0.0)
+        self._check(lib.fsd_time_kernel(self._h, TIMER_NAMES.index(timer), int(reps), C.byref(out)),
+                    "fsd_time_kernel")
+        return out.value
 
     # -- convenience ------------------------------------------------------------------
     @classmethod

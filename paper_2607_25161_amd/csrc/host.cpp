@@ -421,25 +421,28 @@ hipEvent_t next_event(fsd_system* s) {
   return s->ev_pool[s->ev_next++];
 }
 
-// Events around one eager kernel launch on the system stream when timing is on, with
-// the launch's algorithmic HBM bytes (the minimum traffic of its inputs and outputs).
-// (This runtime cannot time event nodes inside captured graphs, so timed runs
-// launch eagerly; see run_body.)
+// Start/stop events of one eager kernel launch when timing is on (stamped by the launch
+// itself, see launch_k), with the launch's algorithmic HBM bytes (the minimum traffic of
+// its inputs and outputs).  Launches that take no events (none made, or made inside a
+// capture) record nothing.  (This runtime cannot time kernels inside captured graphs,
+// so timed runs launch eagerly; see run_body.)
 struct Timed {
   fsd_system* s;
   int cls;
   double bytes;
-  hipEvent_t a = nullptr;
-  Timed(fsd_system* s_, int c, double b) : s(s_), cls(c), bytes(b) {
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(fsd_system* s_, int c, double by) : s(s_), cls(c), bytes(by) {
     if (!s->timing || s->capturing) return;
     a = next_event(s);
-    HIPCHK(hipEventRecord(a, s->st));
+    b = next_event(s);
+    g_launch_events = LaunchEvents{a, b, false, hipSuccess};
   }
   ~Timed() noexcept(false) {
     if (!a) return;
-    hipEvent_t b = next_event(s);
-    HIPCHK(hipEventRecord(b, s->st));
-    s->pending.push_back({cls, bytes, a, b});
+    const LaunchEvents e = g_launch_events;
+    g_launch_events = LaunchEvents{};
+    HIPCHK(e.status);
+    if (e.used) s->pending.push_back({cls, bytes, a, b});
   }
 };
 
@@ -701,6 +704,46 @@ const float* twiddle_of<float>(fsd_system* s) {
 // out = M lam (parts: 1 real space, 2 wave space); with Vr != nullptr the rigid
 // velocities Sigma^T Vr are added in the interpolation kernel.  Untimed, the
 // real-space sum runs on the side stream, overlapping spreading and the transforms.
+// One launch of each mobility kernel class (the wave-space ones work on the system grid).
+template <typename R>
+void mob_real(fsd_system* s, const double* lam, double* out, hipStream_t rs, const int* skip) {
+  launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr, rs, skip,
+                     spread_plan_order(s->spread));
+}
+
+template <typename R>
+void mob_spread(fsd_system* s, const double* lam, const int* skip) {
+  R* grid = static_cast<R*>(s->d_grid);
+  if (s->spread) {
+    launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st, skip);
+  } else {
+    const size_t N = s->wp.n;
+    launch_zero(grid, sizeof(R) * 6 * N * N * N, s->st);
+    launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
+  }
+}
+
+template <typename R>
+void mob_fft(fsd_system* s, int stage, const int* skip) {
+  launch_wave_fft<R>(static_cast<R*>(s->d_grid), s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
+}
+
+template <typename R>
+void mob_interp(fsd_system* s, double* out, const int* skip, const double* Vr) {
+  launch_interp<R>(s->nb, s->d_pos4, static_cast<const R*>(s->d_grid), s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr,
+                   s->spread);
+}
+
+// algorithmic bytes of the mobility launches: the real-space sum reads the row pointers,
+// column indices and 128 bytes per bead (position, input, output); every wave-space pass
+// moves the three packed complex grids, spreading and interpolation once plus the bead data
+double real_bytes(const fsd_system* s) { return 4.0 * (s->nb + 1) + 4.0 * s->nnz + 128.0 * s->nb; }
+template <typename R>
+double grid_bytes(const fsd_system* s) {
+  const double N = s->wp.n;
+  return 3.0 * 2.0 * N * N * N * sizeof(R);
+}
+
 template <typename R>
 void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, const int* skip = nullptr,
                     const double* Vr = nullptr) {
@@ -712,37 +755,29 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
       HIPCHK(hipStreamWaitEvent(s->st2, s->ev_fork, 0));
       rs = s->st2;
     }
-    Timed t(s, FSD_TIMER_REAL, 4.0 * (s->nb + 1) + 4.0 * s->nnz + 128.0 * s->nb);
-    launch_real_sum<R>(s->nb, s->d_pos4, lam, s->d_nrow, s->d_ncol, table_of<R>(s), s->rp, out, false, s->lpr, rs,
-                       skip, spread_plan_order(s->spread));
+    {
+      Timed t(s, FSD_TIMER_REAL, real_bytes(s));
+      mob_real<R>(s, lam, out, rs, skip);
+    }
     if (fork) HIPCHK(hipEventRecord(s->ev_join, s->st2));
   } else {
     launch_zero(out, sizeof(double) * 6 * s->nb, s->st);
   }
   if (parts & 2) {
-    const int N = s->wp.n;
-    const size_t cs = 2 * size_t(N) * N * N;  // R elements per complex component grid
-    R* grid = static_cast<R*>(s->d_grid);
-    // algorithmic bytes: the three packed complex grids, bead inputs
-    const double full = 3.0 * cs * sizeof(R);
-    const double beads = 80.0 * s->nb;
-    if (s->spread) {
+    const double full = grid_bytes<R>(s), beads = 80.0 * s->nb;
+    {
       Timed t(s, FSD_TIMER_SPREAD, full + beads);
-      launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st, skip);
-    } else {
-      launch_zero(grid, sizeof(R) * 3 * cs, s->st);
-      Timed t(s, FSD_TIMER_SPREAD, full + beads);
-      launch_spread<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
+      mob_spread<R>(s, lam, skip);
     }
     for (int stage = 0; stage < 5; ++stage) {
       static const int cls_of[5] = {FSD_TIMER_FFT_FIRST, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
                                     FSD_TIMER_FFT_LAST};
       Timed t(s, cls_of[stage], 2.0 * full);  // every pass reads and writes the three packed grids
-      launch_wave_fft<R>(grid, s->plan, twiddle_of<R>(s), s->wp, stage, s->st, skip);
+      mob_fft<R>(s, stage, skip);
     }
     if (fork) HIPCHK(hipStreamWaitEvent(s->st, s->ev_join, 0));
     Timed t(s, FSD_TIMER_INTERP, full + beads + 80.0 * s->nb + (Vr ? 48.0 * s->na : 0.0));
-    launch_interp<R>(s->nb, s->d_pos4, grid, s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr, s->spread);
+    mob_interp<R>(s, out, skip, Vr);
   }
 }
 
@@ -1003,11 +1038,16 @@ void seg_cycle_start(fsd_system* s) {
   HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, s->st));
 }
 
+// Arnoldi steps per segment.  A timed run ends a segment after every step, so the host
+// reads the stop flag before the next launch and no timed launch is one that returns at
+// once after convergence (those would pull the per-kernel averages down).
+int seg_len(const fsd_system* s) { return s->timing ? 1 : std::max(1, std::min(s->batch, s->m)); }
+
 void seg_batch(fsd_system* s, int j0) {
   auto& v = s->sv;
   const size_t n = s->n;
   const int m = s->m;
-  const int S = std::max(1, std::min(s->batch, m));
+  const int S = seg_len(s);
   const int cnt = std::min(S, m - j0);
   double* V = s->d_basis;
   double* h1 = s->d_h;
@@ -1132,7 +1172,7 @@ bool solve_advance(fsd_system* s) {
     }
     case SS::BATCH: {
       const GmresCtl& c = *s->h_ctl;
-      const int S = std::max(1, std::min(s->batch, s->m));
+      const int S = seg_len(s);
       if (c.stop) {
         seg_cycle_end(s);
         ++v.restarts;
@@ -1177,6 +1217,30 @@ fsd_status check_ready(fsd_system* s) {
   return FSD_OK;
 }
 
+// one launch of the kernel behind a timer class, on the scratch vectors of the system
+template <typename R>
+bool replay_one(fsd_system* s, int cls) {
+  const size_t nb6 = 6 * size_t(s->nb);
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  switch (cls) {
+    case FSD_TIMER_REAL: mob_real<R>(s, s->d_z, s->d_t, s->st, nullptr); return true;
+    case FSD_TIMER_SPREAD: mob_spread<R>(s, s->d_z, nullptr); return true;
+    case FSD_TIMER_FFT_FIRST: mob_fft<R>(s, 0, nullptr); return true;
+    case FSD_TIMER_FFT_Y: mob_fft<R>(s, 1, nullptr); return true;
+    case FSD_TIMER_GREEN: mob_fft<R>(s, 2, nullptr); return true;
+    case FSD_TIMER_FFT_LAST: mob_fft<R>(s, 4, nullptr); return true;
+    case FSD_TIMER_INTERP: mob_interp<R>(s, s->d_t, nullptr, s->d_z + nb6); return true;
+    case FSD_TIMER_RIGID:
+      launch_agg_lub(s->na, s->d_offsets, s->d_body, s->d_r4, s->d_z, s->d_z + nb6, lub ? s->d_lrow : nullptr,
+                     s->d_lcol, s->d_lcoef, s->d_t + nb6, s->st, nullptr);
+      return true;
+    case FSD_TIMER_PRECOND:
+      launch_precond_fused(s->nb, s->na, s->d_offsets, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, s->d_z,
+                           nullptr, nullptr, s->d_t, s->st, nullptr);
+      return true;
+    default: return false;
+  }
+}
 }  // namespace
 
 // ==========================================================================================
@@ -1661,7 +1725,10 @@ fsd_status fsd_set_timing(fsd_system* s, int enable) {
       s->t_n[k] = 0;
       s->t_bytes[k] = 0;
     }
-    if ((enable != 0) != s->timing) s->drop_graphs();  // event nodes are captured or not
+    if ((enable != 0) != s->timing) {
+      s->drop_graphs();
+      launch_timing_mark(s->st);  // brackets the timed launches in a profiler trace
+    }
     s->timing = enable != 0;
     return FSD_OK;
   });
@@ -1676,6 +1743,42 @@ fsd_status fsd_get_timers(fsd_system* s, double* total_ms, long long* launches, 
       launches[k] = s->t_n[k];
       if (bytes) bytes[k] = s->t_bytes[k];
     }
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_time_kernel(fsd_system* s, int timer, int reps, double* avg_ms) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!avg_ms || reps < 1 || timer < 0 || timer > FSD_TIMER_PRECOND)
+    return fail(s, FSD_EINVAL, "fsd_time_kernel: reps >= 1 and a mobility, rigid or preconditioner timer class");
+  return guarded(s, [&]() -> fsd_status {
+    if (!s->prepared) {  // lists, plan and factors for the current positions
+      prepare_begin(s);
+      HIPCHK(hipStreamSynchronize(s->st));
+      prepare_end(s);
+    }
+    const bool fp32 = s->p.precision == FSD_MIXED;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    float ms = 0;
+    try {
+      launch_timing_mark(s->st);
+      HIPCHK(hipEventRecord(ev[0], s->st));
+      for (int r = 0; r < reps; ++r) (void)(fp32 ? replay_one<float>(s, timer) : replay_one<double>(s, timer));
+      HIPCHK(hipEventRecord(ev[1], s->st));
+      launch_timing_mark(s->st);
+      HIPCHK(hipStreamSynchronize(s->st));
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    } catch (...) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      throw;
+    }
+    HIPCHK(hipEventDestroy(ev[0]));
+    HIPCHK(hipEventDestroy(ev[1]));
+    *avg_ms = double(ms) / reps;
     return FSD_OK;
   });
 }

@@ -184,7 +184,7 @@ void launch_real_sum(int nb, const double* pos4, const double* lam, const int* r
   const int acc = accumulate ? 1 : 0;
   const double4* p = (const double4*)pos4;
 #define FSD_REAL(L_)                                                                                    \
-  k_real_sum<R, L_><<<nblocks(threads), kThreads, 0, st>>>(nb, p, lam, rowptr, col, table, rp, out, acc, order, skip)
+  launch_k(k_real_sum<R, L_>, nblocks(threads), kThreads, 0, st, nb, p, lam, rowptr, col, table, rp, out, acc, order, skip)
   switch (lpr) {
     case 1: FSD_REAL(1); break;
     case 2: FSD_REAL(2); break;
@@ -264,7 +264,7 @@ template <typename R>
 void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid, hipStream_t st,
                    const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
-  k_spread<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, lam, wp, grid, cs, skip);
+  launch_k(k_spread<R>, nblocks(nb, 4), kThreads, 0, st, nb, (const double4*)pos4, lam, wp, grid, cs, skip);
 }
 
 template <typename R>
@@ -377,7 +377,7 @@ void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& 
     else
       ow = reinterpret_cast<const R*>(sp->weights32);
   }
-  k_interp<R><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, (const double4*)pos4, grid, cs, wp, out, skip, body,
+  launch_k(k_interp<R>, nblocks(nb, 4), kThreads, 0, st, nb, (const double4*)pos4, grid, cs, wp, out, skip, body,
                                                    (const double4*)r4, V, sp ? sp->perm : nullptr,
                                                    sp ? sp->starts : nullptr, ow);
 }
@@ -853,11 +853,11 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
     const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
     const int C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
     const size_t shm = std::max(per * C, size_t(kSplitRedBytes64) / sizeof(double) * sizeof(R));
-    k_spread_split<R><<<nblk, 256, shm, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts, plan_weights<R>(sp),
+    launch_k(k_spread_split<R>, nblk, 256, shm, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts, plan_weights<R>(sp),
                                               lam, wp, sp->nbin, sp->K, C, grid, cs, skip);
   }
   else
-    k_spread_gather<R, 4><<<nblk, 64, 0, st>>>(sp->bin_start, sp->bin_end, sp->perm, sp->starts,
+    launch_k(k_spread_gather<R, 4>, nblk, 64, 0, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts,
                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
 }
 
@@ -1327,16 +1327,16 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
   if (stage == 2) {
     const int G = fft_green_rows(N);
     const size_t shm = sizeof(T) * (12 * size_t(G) * N + N);
-    k_fft_xgreen<R><<<(N * N / 2 + 2 + G - 1) / G, kThreads, shm, st>>>(grid, cs, plan, twiddle, wp, G, skip);
+    launch_k(k_fft_xgreen<R>, (N * N / 2 + 2 + G - 1) / G, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
   } else {
     const int B = fft_lines_b(N, sizeof(R));
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
     dim3 g(N * N / B, 3);
     const int sign = stage < 2 ? -1 : +1;
     if (stage == 0 || stage == 4)
-      k_fft_lines<R, 2><<<g, kThreads, shm, st>>>(grid, cs, plan, twiddle, sign, B, skip);
+      launch_k(k_fft_lines<R, 2>, g, kThreads, shm, st, grid, cs, plan, twiddle, sign, B, skip);
     else
-      k_fft_lines<R, 1><<<g, kThreads, shm, st>>>(grid, cs, plan, twiddle, sign, B, skip);
+      launch_k(k_fft_lines<R, 1>, g, kThreads, shm, st, grid, cs, plan, twiddle, sign, B, skip);
   }
 }
 

@@ -151,6 +151,14 @@ void launch_zero(void* p, size_t bytes, hipStream_t st) {
   k_zero_words<<<nblocks((long long)n), kThreads, 0, st>>>(n, static_cast<uint32_t*>(p));
 }
 
+// An empty kernel launched when per-kernel timing is switched on and again when it is
+// switched off: in a profiler trace the launches between the two are the timed ones.
+__global__ void k_timing_mark() {}
+
+void launch_timing_mark(hipStream_t st) { k_timing_mark<<<1, 64, 0, st>>>(); }
+
+thread_local LaunchEvents g_launch_events;
+
 __global__ void k_sub(size_t n, const double* __restrict__ b, const double* __restrict__ ax, double* __restrict__ r) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(256) void k_agg_lub(int na, const int* __restrict__
 void launch_agg_lub(int na, const int* offsets, const int* body, const double* r4, const double* lam,
                     const double* V, const int* lrow, const uint32_t* lcol, const double* coef, double* y2,
                     hipStream_t st, const int* skip) {
-  k_agg_lub<<<(na + 3) / 4, 256, 0, st>>>(na, offsets, body, (const double4*)r4, lam, V, lrow, lcol, coef, y2, skip);
+  launch_k(k_agg_lub, (na + 3) / 4, 256, 0, st, na, offsets, body, (const double4*)r4, lam, V, lrow, lcol, coef, y2, skip);
 }
 
 // Preconditioner apply of Section 2.3.3 (block-triangular, block-diagonal Schur
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(256) void k_precond_fused(int nb, int na, const int
 void launch_precond_fused(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
                           double drag_t, double drag_r, const double* src, const double* scal, double* vout, double* z,
                           hipStream_t st, const int* skip) {
-  k_precond_fused<<<(na + 3) / 4, 256, 0, st>>>(nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, src,
+  launch_k(k_precond_fused, (na + 3) / 4, 256, 0, st, nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r, src,
                                                  scal, vout, z, skip);
 }
 
@@ -559,12 +567,12 @@ __global__ __launch_bounds__(kDotThreads) void k_axpy_dots(size_t n, int nq, con
 void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w, double* partial, double* out,
                  unsigned* counters, hipStream_t st, const int* skip) {
   dim3 g(dot_blocks(n), (nq + kDotChunk - 1) / kDotChunk);
-  k_dots<<<g, kDotThreads, 0, st>>>(n, nq, V, ldv, w, partial, out, counters, skip);
+  launch_k(k_dots, g, kDotThreads, 0, st, n, nq, V, ldv, w, partial, out, counters, skip);
 }
 
 void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
                       double* partial, double* out, unsigned* counters, hipStream_t st, const int* skip) {
-  k_axpy_dots<<<dot_blocks(n), kDotThreads, 0, st>>>(n, nq, V, ldv, h, w, mode, partial, out, counters, skip);
+  launch_k(k_axpy_dots, dot_blocks(n), kDotThreads, 0, st, n, nq, V, ldv, h, w, mode, partial, out, counters, skip);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -755,11 +763,11 @@ void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const d
   const ArnoldiArgs a = arn ? *arn : ArnoldiArgs{};
   const int g = cgs_blocks(n);
   if (mode == 0)
-    k_cgs<0><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    launch_k(k_cgs<0>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
   else if (mode == 1)
-    k_cgs<1><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    launch_k(k_cgs<1>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
   else
-    k_cgs<2><<<g, kCgsThreads, 0, st>>>(n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
+    launch_k(k_cgs<2>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -254,8 +254,36 @@ def test_graph_replays_match_eager(F, precision):
         assert np.abs(U_g - U_e).max() <= 1e-12 * np.abs(U_e).max(), rep
         assert inf_g.iterations == inf_e.iterations
         s.apply_saddle(x)          # eager work between replays
-        s.set_timing(rep % 2 == 0)  # alternate captured timing nodes on and off
+        s.set_timing(rep % 2 == 0)  # alternate timed solves (eager, one Arnoldi step per segment)
     s.set_timing(False)
+
+
+def test_timed_solve_and_kernel_replay(F):
+    """Timed solves give the untimed result and time every kernel class; the back-to-back
+    replay of a kernel class leaves the solution alone and refuses the Gram-Schmidt classes."""
+    kw = _cluster_system(seed=23)
+    s = _make(F, kw, gmres_tol=1e-9)
+    assert s.time_kernel("spread", 5) > 0  # builds the lists and plan itself
+    U0, _, inf0 = s.solve()
+    s.set_timing(True)
+    U1, _, inf1 = s.solve()
+    t = s.timers()
+    s.set_timing(False)
+    assert np.abs(U1 - U0).max() <= 1e-12 * np.abs(U0).max() and inf1.iterations == inf0.iterations
+    for name in F.TIMER_NAMES:
+        ms, n, by = t[name]
+        assert n > 0 and ms > 0 and by > 0, name
+    # one launch per Arnoldi step for the preconditioner and the Gram-Schmidt passes
+    assert t["cgs_dot"][1] == inf1.iterations
+    for name in F.TIMER_NAMES[:9]:
+        ms = s.time_kernel(name, 10)
+        assert 0 < ms < 100, (name, ms)
+    with pytest.raises(F.FsdError):
+        s.time_kernel("cgs_dot", 10)
+    U2, _, _ = s.solve()
+    assert np.abs(U2 - U0).max() <= 1e-12 * np.abs(U0).max()
+    s.step(1e-3, 1)
+    assert s.time_kernel("real_sum", 5) > 0  # positions moved: lists rebuilt first
 
 
 # ---------------------------------------------------------------------------------------
