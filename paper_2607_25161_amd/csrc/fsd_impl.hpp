@@ -128,6 +128,34 @@ hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WavePara
 template <typename R>
 void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid,
                           hipStream_t st, const int* skip = nullptr);
+// The first pass of the saddle operator in one launch: the Sigma/lubrication reduction
+// y2, the real-space sum out = M_r lam (overwritten) and the gather spreading of lam,
+// which all read only the input.  Needs a plan with 8^3 blocks (spread_fuses).
+struct RealArgs {
+  int nb;
+  const double4* pos;
+  const int* rowptr;
+  const uint32_t* col;
+  RealParams rp;
+  double* out;
+  const int* order;
+};
+struct RigidArgs {
+  int na;
+  const int* offsets;
+  const int* body;
+  const double4* r4;
+  const double* V;
+  const int* lrow;  // nullptr: no lubrication
+  const uint32_t* lcol;
+  const double* coef;
+  double* y2;
+};
+bool spread_fuses(const SpreadPlan* sp);
+template <typename R>
+void launch_spread_fused(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid, const R* table,
+                         int lanes_per_row, const RealArgs& ra, const RigidArgs& ga, hipStream_t st,
+                         const int* skip = nullptr);
 // out += interpolated grid velocities; with V != nullptr also += Sigma^T V (rigid velocities)
 // (sp != nullptr: beads in the plan's spatial order with its weights)
 template <typename R>

@@ -744,9 +744,11 @@ double grid_bytes(const fsd_system* s) {
   return 3.0 * 2.0 * N * N * N * sizeof(R);
 }
 
+// `side`, when given, is further work independent of the wave-space chain: it follows the
+// real-space sum on the side stream (on the system stream when nothing is forked).
 template <typename R>
 void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, const int* skip = nullptr,
-                    const double* Vr = nullptr) {
+                    const double* Vr = nullptr, const std::function<void(hipStream_t)>* side = nullptr) {
   const bool fork = (parts & 1) && (parts & 2) && !s->timing;
   if (parts & 1) {
     hipStream_t rs = s->st;
@@ -759,6 +761,7 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
       Timed t(s, FSD_TIMER_REAL, real_bytes(s));
       mob_real<R>(s, lam, out, rs, skip);
     }
+    if (side) (*side)(rs);
     if (fork) HIPCHK(hipEventRecord(s->ev_join, s->st2));
   } else {
     launch_zero(out, sizeof(double) * 6 * s->nb, s->st);
@@ -784,14 +787,52 @@ void apply_mobility(fsd_system* s, const double* lam, double* out, int parts, co
 // y = A x for the saddle matrix [[M, Sigma^T], [Sigma, -Sigma R_nf Sigma^T]]:
 // y1 = M lambda + Sigma^T V (rigid part added during interpolation),
 // y2 = Sigma (lambda - R_nf Sigma^T V) (lubrication evaluated inside the reduction)
+double rigid_bytes(const fsd_system* s) {
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  return 80.0 * s->nb + 96.0 * s->na + (lub ? 4.0 * (s->nb + 1) + 44.0 * s->nlub : 0.0);
+}
+
+// the fused first pass (Sigma/lubrication reduction, real-space sum, spreading) of y = A x
+template <typename R>
+void mob_first(fsd_system* s, const double* x, double* y, const int* skip) {
+  const size_t nb6 = 6 * size_t(s->nb);
+  const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+  const RealArgs ra{s->nb, reinterpret_cast<const double4*>(s->d_pos4), s->d_nrow, s->d_ncol, s->rp, y,
+                    spread_plan_order(s->spread)};
+  const RigidArgs ga{s->na, s->d_offsets, s->d_body, reinterpret_cast<const double4*>(s->d_r4), x + nb6,
+                     lub ? s->d_lrow : nullptr, s->d_lcol, s->d_lcoef, y + nb6};
+  launch_spread_fused<R>(s->spread, x, s->wp, static_cast<R*>(s->d_grid), table_of<R>(s), s->lpr, ra, ga, s->st, skip);
+}
+
+// y1 = M lambda + Sigma^T V, y2 = Sigma (lambda - R_nf Sigma^T V).  With a spreading plan
+// the reduction, the real-space sum and the spreading share one launch (they read only
+// x), timed as the spreading class; otherwise the reduction follows the real-space sum.
 template <typename R>
 void apply_saddle(fsd_system* s, const double* x, double* y, const int* skip = nullptr) {
   const size_t nb6 = 6 * size_t(s->nb);
+  if (spread_fuses(s->spread)) {
+    const double full = grid_bytes<R>(s), beads = 80.0 * s->nb;
+    {
+      Timed t(s, FSD_TIMER_SPREAD, full + beads + real_bytes(s) + rigid_bytes(s));
+      mob_first<R>(s, x, y, skip);
+    }
+    for (int stage = 0; stage < 5; ++stage) {
+      static const int cls_of[5] = {FSD_TIMER_FFT_FIRST, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
+                                    FSD_TIMER_FFT_LAST};
+      Timed t(s, cls_of[stage], 2.0 * full);
+      mob_fft<R>(s, stage, skip);
+    }
+    Timed t(s, FSD_TIMER_INTERP, full + beads + 80.0 * s->nb + 48.0 * s->na);
+    mob_interp<R>(s, y, skip, x + nb6);
+    return;
+  }
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
-  apply_mobility<R>(s, x, y, 3, skip, x + nb6);
-  Timed t(s, FSD_TIMER_RIGID, 80.0 * s->nb + 96.0 * s->na + (lub ? 4.0 * (s->nb + 1) + 44.0 * s->nlub : 0.0));
-  launch_agg_lub(s->na, s->d_offsets, s->d_body, s->d_r4, x, x + nb6, lub ? s->d_lrow : nullptr, s->d_lcol,
-                 s->d_lcoef, y + nb6, s->st, skip);
+  const std::function<void(hipStream_t)> rigid = [&](hipStream_t st) {
+    Timed t(s, FSD_TIMER_RIGID, rigid_bytes(s));
+    launch_agg_lub(s->na, s->d_offsets, s->d_body, s->d_r4, x, x + nb6, lub ? s->d_lrow : nullptr, s->d_lcol,
+                   s->d_lcoef, y + nb6, st, skip);
+  };
+  apply_mobility<R>(s, x, y, 3, skip, x + nb6, &rigid);
 }
 
 void apply_saddle_p(fsd_system* s, const double* x, double* y, bool fp32, const int* skip = nullptr) {
@@ -1224,7 +1265,12 @@ bool replay_one(fsd_system* s, int cls) {
   const bool lub = s->p.r_lub > 0 && s->nlub > 0;
   switch (cls) {
     case FSD_TIMER_REAL: mob_real<R>(s, s->d_z, s->d_t, s->st, nullptr); return true;
-    case FSD_TIMER_SPREAD: mob_spread<R>(s, s->d_z, nullptr); return true;
+    case FSD_TIMER_SPREAD:  // the kernel a solve runs for this class
+      if (spread_fuses(s->spread))
+        mob_first<R>(s, s->d_z, s->d_t, nullptr);
+      else
+        mob_spread<R>(s, s->d_z, nullptr);
+      return true;
     case FSD_TIMER_FFT_FIRST: mob_fft<R>(s, 0, nullptr); return true;
     case FSD_TIMER_FFT_Y: mob_fft<R>(s, 1, nullptr); return true;
     case FSD_TIMER_GREEN: mob_fft<R>(s, 2, nullptr); return true;

@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "fsd_impl.hpp"
+#include "k_rigid.hpp"
 
 namespace fsd {
 
@@ -861,6 +862,61 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
                                                 plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, grid, cs, skip);
 }
 
+// First pass of the saddle operator in one launch.  The Sigma/lubrication reduction, the
+// real-space sum and the gather spreading all read only the input vector, so instead of
+// three dependent launches (or a fork onto a second stream) they take three block ranges
+// of one grid: the reduction first, then the real-space rows, then the 8^3 spreading
+// blocks.  The two short ranges are padded to multiples of 8 blocks, so every spreading
+// block keeps the XCD (block index mod 8) its slab mapping assumes, and they finish early,
+// leaving their slots to the longer spreading blocks.
+template <typename R, int LPR>
+__global__ __launch_bounds__(256) void k_spread_fused(const int* __restrict__ bin_start, const int* __restrict__ bin_end,
+                                                      const int* __restrict__ perm, const int4* __restrict__ starts,
+                                                      const R* __restrict__ weights, const double* __restrict__ lam,
+                                                      WaveParams wp, int nbin, int K, int C, R* __restrict__ grid,
+                                                      size_t cs, const R* __restrict__ tab, RealArgs ra, RigidArgs ga,
+                                                      int na_blk, int nr_blk, const int* __restrict__ skip) {
+  int b = blockIdx.x;
+  if (b < na_blk) {
+    agg_lub_body(ga.na, ga.offsets, ga.body, ga.r4, lam, ga.V, ga.lrow, ga.lcol, ga.coef, ga.y2, skip, b, 0, na_blk);
+    return;
+  }
+  b -= na_blk;
+  if (b < nr_blk) {
+    real_sum_body<R, LPR>(ra.nb, ra.pos, lam, ra.rowptr, ra.col, tab, ra.rp, ra.out, 0, ra.order, skip, b, 0, nr_blk);
+    return;
+  }
+  spread_split_body<R>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, b - nr_blk, 0, 0);
+}
+
+bool spread_fuses(const SpreadPlan* sp) { return sp && sp->BS == 8; }
+
+template <typename R>
+void launch_spread_fused(const SpreadPlan* sp, const double* lam, const WaveParams& wp, R* grid, const R* table,
+                         int lpr, const RealArgs& ra, const RigidArgs& ga, hipStream_t st, const int* skip) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  const int nblk = sp->nbin * sp->nbin * sp->nbin;
+  const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
+  const int C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // as launch_spread_gather
+  const size_t shm = std::max(per * C, size_t(kSplitRedBytes64) / sizeof(double) * sizeof(R));
+  auto pad8 = [](long long n) { return int((n + 7) / 8 * 8); };
+  const int na_blk = pad8((ga.na + 3) / 4), nr_blk = pad8(((long long)ra.nb * lpr + 255) / 256);
+  const int total = na_blk + nr_blk + nblk;
+#define FSD_FUSED(L_)                                                                                       \
+  launch_k(k_spread_fused<R, L_>, total, 256, shm, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts,       \
+           plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, C, grid, cs, table, ra, ga, na_blk, nr_blk, skip)
+  switch (lpr) {
+    case 1: FSD_FUSED(1); break;
+    case 2: FSD_FUSED(2); break;
+    case 4: FSD_FUSED(4); break;
+    case 8: FSD_FUSED(8); break;
+    case 16: FSD_FUSED(16); break;
+    case 32: FSD_FUSED(32); break;
+    default: FSD_FUSED(64); break;
+  }
+#undef FSD_FUSED
+}
+
 // ------------------------------------------------------------------------------------------
 // 3D FFT: three passes of batched 1D transforms, each line staged in LDS and
 // transformed by mixed-radix (4, 2, 3) Stockham stages.
@@ -1538,6 +1594,10 @@ template void launch_wave_fft<float>(float*, const FftPlan&, const float*, const
                                      const int*);
 template void launch_spread_gather<double>(const SpreadPlan*, const double*, const WaveParams&, double*, hipStream_t, const int*);
 template void launch_spread_gather<float>(const SpreadPlan*, const double*, const WaveParams&, float*, hipStream_t, const int*);
+template void launch_spread_fused<double>(const SpreadPlan*, const double*, const WaveParams&, double*, const double*,
+                                          int, const RealArgs&, const RigidArgs&, hipStream_t, const int*);
+template void launch_spread_fused<float>(const SpreadPlan*, const double*, const WaveParams&, float*, const float*, int,
+                                         const RealArgs&, const RigidArgs&, hipStream_t, const int*);
 template void launch_real_sum<double>(int, const double*, const double*, const int*, const uint32_t*, const double*,
                                       const RealParams&, double*, bool, int, hipStream_t, const int*, const int*);
 template void launch_real_sum<float>(int, const double*, const double*, const int*, const uint32_t*, const float*,

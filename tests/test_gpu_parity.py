@@ -270,8 +270,12 @@ def test_timed_solve_and_kernel_replay(F):
     t = s.timers()
     s.set_timing(False)
     assert np.abs(U1 - U0).max() <= 1e-12 * np.abs(U0).max() and inf1.iterations == inf0.iterations
+    # with a spreading plan the real-space sum and the Sigma/lubrication reduction run
+    # inside the spreading launch and are timed with it
     for name in F.TIMER_NAMES:
         ms, n, by = t[name]
+        if name in ("real_sum", "rigid_lub") and n == 0:
+            continue
         assert n > 0 and ms > 0 and by > 0, name
     # one launch per Arnoldi step for the preconditioner and the Gram-Schmidt passes
     assert t["cgs_dot"][1] == inf1.iterations
