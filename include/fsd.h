@@ -256,19 +256,22 @@ fsd_status fsd_batch_set_fused(fsd_batch* b, int enable);
 
 void fsd_batch_destroy(fsd_batch* b);
 
-/* ---- kernel timing on the system stream (HIP events around each launch) ------------- */
+/* ---- kernel timing on the system stream (HIP events carried by each launch) -------- */
 
 typedef enum {
-  FSD_TIMER_REAL = 0,        /* real-space pair sum                                       */
-  FSD_TIMER_SPREAD = 1,      /* Gaussian spreading to the grid                            */
-  FSD_TIMER_FFT_FIRST = 2,   /* first transform pass (z; x with the half-spectrum split
-                                for grids above 256^3)                                    */
+  FSD_TIMER_REAL = 0,        /* real-space pair sum (its own launch outside the saddle
+                                operator, or without a spreading plan)                    */
+  FSD_TIMER_SPREAD = 1,      /* Gaussian spreading to the grid; in the saddle operator
+                                with a spreading plan one launch (fsd::k_spread_fused)
+                                also carries the real-space sum and the Sigma/lubrication
+                                reduction, all timed here                                 */
+  FSD_TIMER_FFT_FIRST = 2,   /* first transform pass (z lines)                            */
   FSD_TIMER_FFT_Y = 3,       /* y transform passes (2 per apply)                          */
-  FSD_TIMER_GREEN = 4,       /* the pass with the Green's-function scaling: x transforms
-                                (z transforms above 256^3) around it                      */
+  FSD_TIMER_GREEN = 4,       /* the pass with the Green's-function multiplier: x
+                                transforms around it                                      */
   FSD_TIMER_FFT_LAST = 5,    /* last transform pass (inverse of the first)                */
   FSD_TIMER_INTERP = 6,      /* interpolation back to the beads, plus Sigma^T V           */
-  FSD_TIMER_RIGID = 7,       /* Sigma reductions with the lubrication product             */
+  FSD_TIMER_RIGID = 7,       /* Sigma reductions with the lubrication product (see REAL)  */
   FSD_TIMER_PRECOND = 8,     /* preconditioner apply (forms the next basis vector)        */
   FSD_TIMER_CGS_DOT = 9,     /* first Gram-Schmidt pass, h = V^T w                        */
   FSD_TIMER_CGS_UPDATE = 10, /* second pass: w -= V h with the new inner products         */
