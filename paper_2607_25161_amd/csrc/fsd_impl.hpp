@@ -230,6 +230,15 @@ int cgs_blocks(size_t n);
 void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
                 double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
                 const ArnoldiArgs* arn);
+// The same passes as a chain without fences or tickets (one system): each pass writes only
+// its workgroup partial sums pout[q * cgs_blocks(n) + block]; the next launch's workgroups
+// each add the previous pass's partials pin in a fixed order (mode 1: h1, mode 2: h2, the
+// inner products of this step's column; workgroup 0 stores them to hout), and
+// launch_arnoldi_reduce adds the mode-2 partials (w.w) and runs the Arnoldi update.  The
+// three partial arrays must not overlap (nq * cgs_blocks(n) doubles each).
+void launch_cgs_chain(int mode, size_t n, int nq, const double* V, size_t ldv, const double* pin, double* w,
+                      double* pout, double* hout, hipStream_t st, const int* skip);
+void launch_arnoldi_reduce(const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
 
 // ---- Brownian terms (k_brownian.hip) ------------------------------------------------------

@@ -1104,16 +1104,22 @@ void seg_batch(fsd_system* s, int j0) {
       const ArnoldiArgs arn{j, s->d_ctl, h1, h2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal};
       const int nq = j + 1;
       if (cgs_fits(nq)) {
+        // fence-free chain: three partial arrays, each reduced by the next launch
+        const size_t G = cgs_blocks(n);
+        double *P0 = s->d_part, *P1 = s->d_part + 32 * G, *P2 = s->d_part + 64 * G;
         {
           Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));
-          launch_cgs(0, n, nq, V, n, nullptr, s->d_w, s->d_part, h1, s->d_counters, s->st, stop, nullptr);
+          launch_cgs_chain(0, n, nq, V, n, nullptr, s->d_w, P0, nullptr, s->st, stop);
         }
         {
           Timed t(s, FSD_TIMER_CGS_UPDATE, 8.0 * n * (nq + 2));
-          launch_cgs(1, n, nq, V, n, h1, s->d_w, s->d_part, h2, s->d_counters, s->st, stop, nullptr);
+          launch_cgs_chain(1, n, nq, V, n, P0, s->d_w, P1, h1, s->st, stop);
         }
-        Timed t(s, FSD_TIMER_CGS_NORM, 8.0 * n * (nq + 2));
-        launch_cgs(2, n, nq, V, n, h2, s->d_w, s->d_part, hn2, s->d_counters, s->st, stop, &arn);
+        {
+          Timed t(s, FSD_TIMER_CGS_NORM, 8.0 * n * (nq + 2));
+          launch_cgs_chain(2, n, nq, V, n, P1, s->d_w, P2, h2, s->st, stop);
+        }
+        launch_arnoldi_reduce(arn, P2, int(G), hn2, s->st);
       } else {
         {
           Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));
@@ -1433,7 +1439,7 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_wt = dalloc<double>(o, 3 * size_t(nb));
     s->d_fl = dalloc<double>(o, 3 * size_t(nb));
     s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 16);
-    s->d_part = dalloc<double>(o, std::max(size_t(s->m + 2) * 1024, size_t(32) * cgs_blocks(n)));
+    s->d_part = dalloc<double>(o, std::max(size_t(s->m + 2) * 1024, size_t(96) * cgs_blocks(n)));
     s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
     HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
     HIPCHK(hipHostMalloc((void**)&s->h_ctl, sizeof(GmresCtl)));

@@ -682,6 +682,82 @@ __device__ __forceinline__ void cgs_body(size_t n, int nq, const double* __restr
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// out[q] = sum over b of part[q * nblk + b] for q < nq (<= kCgsMax), in the same fixed order
+// in every workgroup: thread t adds the terms b = t / 32 + 8 k of column q = t % 32, and the
+// eight partial sums of a column are then added in order.  Valid in out[] after the call.
+__device__ inline void reduce_partials(const double* __restrict__ part, int nblk, int nq, double* shq, double* out) {
+  static_assert(kCgsThreads == 256 && kCgsMax == 32, "8 parts of 32 columns");
+  const int q = threadIdx.x & 31, p = threadIdx.x >> 5;
+  double v = 0.0;
+  if (q < nq)
+    for (int b = p; b < nblk; b += 8) v += part[size_t(q) * nblk + b];
+  shq[p * 32 + q] = v;
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    double t = 0.0;
+    for (int k = 0; k < 8; ++k) t += shq[k * 32 + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// One CGS2 pass of the fence-free chain (see launch_cgs_chain).
+template <int MODE>
+__global__ __launch_bounds__(kCgsThreads) void k_cgs_chain(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                           const double* __restrict__ pin, double* __restrict__ w,
+                                                           double* __restrict__ pout, double* __restrict__ hout,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double sh[kCgsWaves][kCgsMax];
+  __shared__ double shq[8 * 32];
+  __shared__ double hq[kCgsMax];
+  const int nblk = gridDim.x, bx = blockIdx.x;
+  if (MODE >= 1) {
+    reduce_partials(pin, nblk, nq, shq, hq);
+    if (bx == 0 && threadIdx.x < nq) hout[threadIdx.x] = hq[threadIdx.x];
+  }
+  double h[kCgsMax], acc[kCgsMax];
+#pragma unroll
+  for (int q = 0; q < kCgsMax; ++q) {
+    h[q] = (MODE >= 1 && q < nq) ? hq[q] : 0.0;
+    acc[q] = 0.0;
+  }
+  for (size_t i = size_t(bx) * kCgsThreads + threadIdx.x; i < n; i += size_t(nblk) * kCgsThreads) {
+    double v[kCgsMax];
+#pragma unroll
+    for (int q = 0; q < kCgsMax; ++q) v[q] = q < nq ? V[size_t(q) * ldv + i] : 0.0;
+    double wi = w[i];
+    if (MODE >= 1) {
+      double sv = 0.0;
+#pragma unroll
+      for (int q = 0; q < kCgsMax; ++q) sv += h[q] * v[q];
+      wi -= sv;
+      w[i] = wi;
+    }
+    if (MODE <= 1) {
+#pragma unroll
+      for (int q = 0; q < kCgsMax; ++q) acc[q] += v[q] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  const int nout = MODE <= 1 ? nq : 1;
+  block_sums(acc, nout, sh);
+  if (threadIdx.x < nout) pout[size_t(threadIdx.x) * nblk + bx] = sh[0][threadIdx.x];
+}
+
+// w.w from the mode-2 partials, then the Arnoldi update (one workgroup)
+__global__ __launch_bounds__(kCgsThreads) void k_arnoldi_reduce(ArnoldiArgs a, const double* __restrict__ pin, int nblk,
+                                                                double* __restrict__ hn2) {
+  if (a.ctl->stop) return;
+  __shared__ double shq[8 * 32];
+  __shared__ double tot[kCgsMax];
+  __shared__ double st[3][kCgsMax];
+  reduce_partials(pin, nblk, 1, shq, tot);
+  if (threadIdx.x == 0) *hn2 = tot[0];
+  arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kCgsThreads) void k_cgs(size_t n, int nq, const double* __restrict__ V, size_t ldv,
                                                      const double* __restrict__ hin, double* __restrict__ w,
@@ -691,6 +767,21 @@ __global__ __launch_bounds__(kCgsThreads) void k_cgs(size_t n, int nq, const dou
 }
 
 bool cgs_fits(int nq) { return nq >= 1 && nq <= kCgsMax; }
+
+void launch_cgs_chain(int mode, size_t n, int nq, const double* V, size_t ldv, const double* pin, double* w,
+                      double* pout, double* hout, hipStream_t st, const int* skip) {
+  const int g = cgs_blocks(n);
+  if (mode == 0)
+    launch_k(k_cgs_chain<0>, g, kCgsThreads, 0, st, n, nq, V, ldv, pin, w, pout, hout, skip);
+  else if (mode == 1)
+    launch_k(k_cgs_chain<1>, g, kCgsThreads, 0, st, n, nq, V, ldv, pin, w, pout, hout, skip);
+  else
+    launch_k(k_cgs_chain<2>, g, kCgsThreads, 0, st, n, nq, V, ldv, pin, w, pout, hout, skip);
+}
+
+void launch_arnoldi_reduce(const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st) {
+  k_arnoldi_reduce<<<1, kCgsThreads, 0, st>>>(a, pin, nblk, hn2);
+}
 
 void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
                 double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
