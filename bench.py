@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0
 # kernel behind each timer class (rocprofv3 names), for matching the two measurements
 KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_fused", "fft_first": "k_fft_lines<2>",
              "fft_y": "k_fft_lines<1>", "fft_green": "k_fft_xgreen", "fft_last": "k_fft_lines<2>",
-             "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused", "cgs_dot": "k_cgs<0>",
-             "cgs_update": "k_cgs<1>", "cgs_norm_arnoldi": "k_cgs<2>"}
+             "interp": "k_interp", "rigid_lub": "k_agg_lub", "precond": "k_precond_fused",
+             "cgs_dot": "k_cgs_chain<0>", "cgs_update": "k_cgs_chain<1>", "cgs_norm_arnoldi": "k_cgs_chain<2>"}
 
 
 def progress(msg):
@@ -56,8 +56,8 @@ def kernel_table(timers, steps):
 # source file of each kernel, whose hash the counter summaries record
 SOURCE_OF = {"k_real_sum": "k_mobility.hip", "k_spread_fused": "k_mobility.hip", "k_spread_split": "k_mobility.hip", "k_fft_lines<1>": "k_mobility.hip",
              "k_fft_lines<2>": "k_mobility.hip", "k_fft_xgreen": "k_mobility.hip", "k_interp": "k_mobility.hip",
-             "k_agg_lub": "k_solver.hip", "k_precond_fused": "k_solver.hip", "k_cgs<0>": "k_solver.hip",
-             "k_cgs<1>": "k_solver.hip", "k_cgs<2>": "k_solver.hip"}
+             "k_agg_lub": "k_solver.hip", "k_precond_fused": "k_solver.hip", "k_cgs_chain<0>": "k_solver.hip",
+             "k_cgs_chain<1>": "k_solver.hip", "k_cgs_chain<2>": "k_solver.hip"}
 
 
 def measured_traffic(counters_file, kernel):
