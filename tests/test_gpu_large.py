@@ -1,0 +1,75 @@
+"""The 4096x20-cluster workload at full size (81,920 beads, 128^3 grid) on the GPU.
+
+The dense oracle cannot run at this size, so these tests check properties that hold at
+any size, on the same kernels and launch configuration the benchmark times:
+
+- the PSE mobility (Section 2.2) is symmetric: u . (M v) = v . (M u) for random u, v
+  (a pair missing from one side of the neighbour list, or interpolation that is not the
+  adjoint of spreading, breaks it);
+- M lambda does not depend on the splitting parameter xi, to the Ewald tolerance: two
+  values of xi give different real-space cutoffs and grids, so an error in either part
+  shows up as a dependence on xi;
+- a full FP64 saddle solve (Algorithm 1) meets its tolerance on the true residual, and
+  the mixed-precision solve agrees with it to the solver tolerance.
+"""
+import numpy as np
+import pytest
+
+import fsdgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F(gpu):
+    import paper_2607_25161_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def large():
+    return fsdgen.config(2)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_large_mobility_is_symmetric(F, large):
+    s = F.System.from_suspension(large)
+    assert s.n_bead == 81920 and s.info().grid == 128
+    rng = np.random.default_rng(61)
+    u, v = rng.normal(size=(2, 6 * s.n_bead))
+    Mu, Mv = s.apply_mobility(u), s.apply_mobility(v)
+    a, b = float(u @ Mv), float(v @ Mu)
+    assert abs(a - b) <= 1e-12 * np.sqrt(abs(u @ Mu) * abs(v @ Mv)), (a, b)
+    assert u @ Mu > 0 and v @ Mv > 0
+    s.close()
+
+
+def test_large_mobility_independent_of_xi(F, large):
+    rng = np.random.default_rng(62)
+    lam = rng.normal(size=6 * large.n_bead)
+    out, grids = [], []
+    for xi in (0.348, 0.45):
+        s = F.System.from_suspension(large, xi=xi, grid=0, ewald_tol=1e-9)
+        info = s.info()
+        grids.append((info.grid, round(info.r_cut, 2)))
+        out.append(s.apply_mobility(lam))
+        s.close()
+    assert grids[0] != grids[1]
+    assert _rel(out[1], out[0]) < 1e-6, (grids, _rel(out[1], out[0]))
+
+
+def test_large_solve_meets_tolerance_fp64_and_mixed(F, large):
+    U = {}
+    for prec in (F.FSD_FP64, F.FSD_MIXED):
+        s = F.System.from_suspension(large, precision=prec)
+        Up, _, info = s.solve()
+        assert info.status == 0 and info.rel_residual_fp64 <= large.gmres_tol, info.rel_residual_fp64
+        U[prec] = Up
+        s.close()
+    ref = U[F.FSD_FP64]
+    # both meet 1e-5 on the true residual; the velocities agree to that order
+    assert _rel(U[F.FSD_MIXED][:, :3], ref[:, :3]) < 1e-4
+    assert _rel(U[F.FSD_MIXED][:, 3:], ref[:, 3:]) < 1e-4
