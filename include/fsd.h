@@ -156,6 +156,26 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, do
 const char* fsd_last_error(const fsd_system* s);
 void fsd_destroy(fsd_system* s);
 
+/* ---- conservative bead-pair forces (Section 4.2, Eqs. `dlvo_potential` and the Hertz
+ * contact force) ------------------------------------------------------------------------
+ * Between beads of different bodies closer than r_cut (2a <= r_cut <= fsd_info.r_cut), with
+ * r the centre distance, h = r - 2a and n the unit vector from the other bead:
+ *   Hertz contact  f = k_n (2a - r)^1.5 n                                  for r < 2a;
+ *   van der Waals  f = -dV/ds n, V(s) = -(A/6) [2a^2/(s^2 - 4a^2) + 2a^2/s^2
+ *                                              + ln((s^2 - 4a^2)/s^2)],  s = max(r, 2a) + h_c
+ *                  (separation regularised by h_c > 0; for r < 2a the force keeps its
+ *                  contact value);
+ *   double layer   f = -dV/dr n, V(r) = (a^2/r) Z exp(-kappa (r - 2a)).
+ * The bead forces are summed into each body's force and torque (Sigma) and added to the
+ * forces of fsd_set_forces at every solve, from the positions of that solve.  All three
+ * coefficients zero switches the forces off (the default).  FSD_EINVAL for negative k_n
+ * or A, A > 0 with h_c <= 0, Z != 0 with kappa <= 0, or r_cut outside the range. */
+fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double Z, double kappa, double h_c,
+                               double r_cut);
+
+/* The conservative bead forces at the current positions (3 per bead, host array). */
+fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
+
 /* ---- Brownian motion (kT > 0) --------------------------------------------------------
  * Eq. `SP2` and Algorithm 1 step 3: with kT > 0 every solve adds the Brownian slip
  * velocity u_B = sqrt(2 kT/dt) (M_r^{1/2} psi_r + M_w^{1/2} psi_w) to the bead rows of the

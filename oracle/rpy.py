@@ -6,7 +6,7 @@ paper (Section 2.2, the M-infinity block of Eq. `SP1`; Section 2.3,
 Eq. `spm_agg`) is taken at force-torque level: per bead pair a 6x6 block
 [[tt, tr], [rt, rr]].
 
-Spectral definition (periodic cube of side L, V = L^3, k in (2 pi / L) Z^3 \ 0,
+Spectral definition (periodic cube of side L, V = L^3, k in (2 pi / L) Z^3 minus 0,
 sinc(x) = sin x / x, jv(x) = 3 (sin x - x cos x) / x^3, r = x_i - x_j):
 
     tt(r) = 1/(eta V) sum_k sinc^2(ka)             (I - kk/k^2) / k^2 cos(k.r)

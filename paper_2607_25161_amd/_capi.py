@@ -94,6 +94,8 @@ _sig("fsd_normals", C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c
 _sig("fsd_set_timing", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
+_sig("fsd_set_pair_forces", C.c_int, _SYS, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double)
+_sig("fsd_get_pair_forces", C.c_int, _SYS, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
 
 _sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
@@ -297,6 +299,19 @@ class System:
         return out
 
     # -- launch mode and timing ---------------------------------------------------------
+    def set_pair_forces(self, k_n=0.0, hamaker=0.0, Z=0.0, kappa=0.0, h_c=0.0, r_cut=None):
+        """Hertz contact, van der Waals and double-layer forces between beads of different
+        bodies (all zero: off).  r_cut defaults to 3a."""
+        rc = 3.0 * self.params.radius if r_cut is None else float(r_cut)
+        self._check(lib.fsd_set_pair_forces(self._h, float(k_n), float(hamaker), float(Z), float(kappa),
+                                            float(h_c), rc), "fsd_set_pair_forces")
+
+    def pair_forces(self):
+        """(n_bead, 3) conservative bead forces at the current positions."""
+        out = np.zeros(3 * self.n_bead)
+        self._check(lib.fsd_get_pair_forces(self._h, _dptr(out)), "fsd_get_pair_forces")
+        return out.reshape(-1, 3)
+
     def set_brownian(self, dt, step=0, stream=0):
         self._check(lib.fsd_set_brownian(self._h, float(dt), int(step), int(stream)), "fsd_set_brownian")
 

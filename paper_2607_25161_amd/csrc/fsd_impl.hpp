@@ -166,6 +166,19 @@ void launch_interp(int nb, const double* pos4, const R* grid, const WaveParams& 
 const int* spread_plan_order(const SpreadPlan* sp);
 
 // ---- constraint, lubrication, preconditioner, Krylov vectors (k_solver.hip) ---------------
+// Conservative bead-pair forces between beads of different bodies (Section 4.2): Hertz
+// normal contact k_n delta^1.5 n, van der Waals (Hamaker sphere-sphere, separation
+// regularised h -> h + h_c, the force held at its contact value for h < 0) and the
+// screened double layer, for pairs closer than r_cut, over the real-space list.
+struct PairForceParams {
+  double kn, hamaker, Z, kappa, hc, r_cut, a, L;
+};
+// fe[3 i] = (accumulate ? fe[3 i] : 0) - f_i  (the right-hand side takes -F_P through Sigma)
+void launch_pair_forces(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
+                        const PairForceParams& pf, double* fe, int accumulate, hipStream_t st);
+// *flag |= 1 when beads of different bodies in the real-space list are closer than 1.5 a
+void launch_overlap_check(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
+                          double L, double a, int* flag, hipStream_t st);
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,
                       const double* wt, double* f, hipStream_t st, const int* skip = nullptr);
 // fused: y2 = Sigma (lambda - R_nf Sigma^T V) with lubrication evaluated on the fly

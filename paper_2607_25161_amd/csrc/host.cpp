@@ -302,6 +302,8 @@ struct fsd_system {
     hipEvent_t a, b;
   };
   bool timing = false;
+  bool pair_forces = false;  // conservative bead-pair forces in the right-hand side
+  PairForceParams pf{};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -637,6 +639,7 @@ void prepare_end(fsd_system* s) {
   } else {
     launch_zero(s->d_rdiag, sizeof(double) * 6 * s->nb, s->st);
     s->nlub = 0;
+    launch_overlap_check(s->nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->L, s->p.radius, s->d_flags, s->st);
   }
   launch_precond_factor(s->na, s->d_offsets, s->d_r4, s->d_rdiag, s->drag_t, s->drag_r, s->d_lu, s->d_piv,
                         s->d_flags + 1, s->st);
@@ -1039,7 +1042,11 @@ void assemble_rhs(fsd_system* s) {
     // b2 = -(F_P + Sigma F_B + Sigma R_nf e) = -F_P + Sigma (f_e - F_B), f_e = -R_nf e
     if (brown) launch_axpby(3 * size_t(s->nb), -1.0, s->d_fb, 1.0, s->d_fl, s->st);
   }
-  launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_force, lub ? s->d_fl : nullptr, s->d_b + nb6, s->st);
+  // conservative bead-pair forces join F_P through Sigma: b2 gains -Sigma f_c
+  if (s->pair_forces)
+    launch_pair_forces(s->nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->pf, s->d_fl, lub ? 1 : 0, s->st);
+  launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_force, (lub || s->pair_forces) ? s->d_fl : nullptr,
+                 s->d_b + nb6, s->st);
 }
 
 // ||v|| with a synchronisation (operator-access paths only)
@@ -1831,6 +1838,47 @@ fsd_status fsd_time_kernel(fsd_system* s, int timer, int reps, double* avg_ms) {
     HIPCHK(hipEventDestroy(ev[0]));
     HIPCHK(hipEventDestroy(ev[1]));
     *avg_ms = double(ms) / reps;
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double Z, double kappa, double h_c,
+                               double r_cut) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  const double a = s->p.radius;
+  const double v[6] = {k_n, hamaker, Z, kappa, h_c, r_cut};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(s, FSD_EINVAL, "non-finite pair-force parameter");
+  if (k_n == 0 && hamaker == 0 && Z == 0) {
+    s->pair_forces = false;
+    return FSD_OK;
+  }
+  if (k_n < 0 || hamaker < 0) return fail(s, FSD_EINVAL, "k_n and the Hamaker constant must be >= 0");
+  if (hamaker > 0 && !(h_c > 0)) return fail(s, FSD_EINVAL, "the van der Waals term needs h_c > 0");
+  if (Z != 0 && !(kappa > 0)) return fail(s, FSD_EINVAL, "the double layer needs kappa > 0");
+  if (!(r_cut >= 2 * a) || r_cut > s->rp.r_cut)
+    return fail(s, FSD_EINVAL, "r_cut must lie in [2a, the real-space cutoff]");
+  s->pf = PairForceParams{k_n, hamaker, Z, kappa, h_c, r_cut, a, s->L};
+  s->pair_forces = true;
+  return FSD_OK;
+}
+
+fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!f_bead) return fail(s, FSD_EINVAL, "null output");
+  return guarded(s, [&]() -> fsd_status {
+    prepare(s);
+    const size_t n3 = 3 * size_t(s->nb);
+    if (!s->pair_forces) {
+      std::fill(f_bead, f_bead + n3, 0.0);
+      return FSD_OK;
+    }
+    launch_pair_forces(s->nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->pf, s->d_t, 0, s->st);
+    HIPCHK(hipMemcpyAsync(f_bead, s->d_t, sizeof(double) * n3, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (size_t i = 0; i < n3; ++i) f_bead[i] = -f_bead[i];
     return FSD_OK;
   });
 }

@@ -10,6 +10,91 @@ constexpr int kThreads = 256;
 inline int nblocks(long long n, int t = kThreads) { return int((n + t - 1) / t); }
 }  // namespace
 
+// Magnitude of the conservative force between two beads of radius a at centre distance r,
+// positive when repulsive (Section 4.2): van der Waals from the sphere-sphere Hamaker
+// potential with the separation shifted by h_c (held at the contact value for r < 2a),
+// the screened double layer a^2 Z exp(-kappa (r - 2a)) / r, and the Hertz contact
+// k_n delta^1.5 for delta = 2a - r > 0.
+__device__ inline double pair_force_mag(double r, const PairForceParams& p) {
+  const double a = p.a, a2 = a * a;
+  double f = 0.0;
+  if (p.hamaker != 0.0) {
+    // -dV/ds of V(s) = -(A/6) [2a^2/(s^2 - 4a^2) + 2a^2/s^2 + ln((s^2 - 4a^2)/s^2)], s = r + h_c
+    const double sv = fmax(r, 2.0 * a) + p.hc, s2 = sv * sv, d = s2 - 4.0 * a2;
+    f += (p.hamaker / 6.0) * (-4.0 * a2 * sv / (d * d) - 4.0 * a2 / (s2 * sv) + 2.0 * sv / d - 2.0 / sv);
+  }
+  if (p.Z != 0.0) f += p.Z * a2 * exp(-p.kappa * (r - 2.0 * a)) * (1.0 / (r * r) + p.kappa / r);
+  if (r < 2.0 * a && p.kn > 0.0) {
+    const double dl = 2.0 * a - r;
+    f += p.kn * dl * sqrt(dl);
+  }
+  return f;
+}
+
+__global__ void k_pair_forces(int nb, const double4* __restrict__ pos, const int* __restrict__ body,
+                              const int* __restrict__ rowptr, const uint32_t* __restrict__ col, PairForceParams p,
+                              double* __restrict__ fe, int accumulate) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 pi = pos[i];
+  const int bi = body[i];
+  double fx = 0, fy = 0, fz = 0;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const uint32_t c = col[e];
+    const int j = int(c & 0x3FFFFFu);
+    if (body[j] == bi) continue;
+    const double4 pj = pos[j];
+    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * p.L;
+    const double dy = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * p.L;
+    const double dz = pi.z - pj.z + (int((c >> 28) & 7u) - 3) * p.L;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(r < p.r_cut) || r == 0.0) continue;
+    const double g = pair_force_mag(r, p) / r;  // along the unit vector from j to i
+    fx += g * dx;
+    fy += g * dy;
+    fz += g * dz;
+  }
+  double* o = fe + 3 * size_t(i);
+  const double b0 = accumulate ? o[0] : 0.0, b1 = accumulate ? o[1] : 0.0, b2 = accumulate ? o[2] : 0.0;
+  o[0] = b0 - fx;
+  o[1] = b1 - fy;
+  o[2] = b2 - fz;
+}
+
+// flag = 1 when two beads of different bodies are closer than 1.5 a (the real-space list
+// holds every pair within its cutoff; used when there is no lubrication list to check)
+__global__ void k_overlap_check(int nb, const double4* __restrict__ pos, const int* __restrict__ body,
+                                const int* __restrict__ rowptr, const uint32_t* __restrict__ col, double L, double a,
+                                int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 pi = pos[i];
+  const double lim2 = 2.25 * a * a;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const uint32_t c = col[e];
+    const int j = int(c & 0x3FFFFFu);
+    if (body[j] == body[i]) continue;
+    const double4 pj = pos[j];
+    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * L;
+    const double dy = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * L;
+    const double dz = pi.z - pj.z + (int((c >> 28) & 7u) - 3) * L;
+    if (dx * dx + dy * dy + dz * dz < lim2) {
+      atomicOr(flag, 1);
+      return;
+    }
+  }
+}
+
+void launch_overlap_check(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
+                          double L, double a, int* flag, hipStream_t st) {
+  k_overlap_check<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, body, rowptr, col, L, a, flag);
+}
+
+void launch_pair_forces(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
+                        const PairForceParams& pf, double* fe, int accumulate, hipStream_t st) {
+  k_pair_forces<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, body, rowptr, col, pf, fe, accumulate);
+}
+
 // f_i = -sum_k R_pair,ik (w_i - w_k), R_pair = X nn + Y (I - nn)
 __global__ void k_lub_apply(int nb, const int* __restrict__ rowptr, const uint32_t* __restrict__ col,
                             const double* __restrict__ coef, const double* __restrict__ wt, double* __restrict__ f, const int* __restrict__ skip) {
