@@ -1363,8 +1363,8 @@ __global__ __launch_bounds__(256) void k_fft_xgreen(R* __restrict__ grid, size_t
   fft_xgreen_body<R>(grid, cs, plan, twiddle, wp, G, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-// row slots per workgroup of the x+Green pass: 6 G N complex lines stay within 1536
-int fft_green_rows(int N) { return N >= 256 ? 1 : 256 / N; }
+// row slots per workgroup of the x+Green pass (measured: 2 is fastest at 64^3 and 128^3)
+int fft_green_rows(int N) { return N >= 256 ? 1 : N >= 64 ? 2 : 256 / N; }
 
 // lines per workgroup of the coalesced y/z passes: largest B in {16, 8, 4, 2, 1} dividing N
 // whose two LDS buffers and twiddles fit in 64 KB
