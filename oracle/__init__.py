@@ -23,4 +23,4 @@ Everything here is plain, dense and FP64:
 Paper sections cited are those of "Fast Stokesian Dynamics for Rigid
 Aggregates" (Mangal et al.).
 """
-from . import rpy, lub, rigid, saddle, integrate, pse, brownian, forces  # noqa: F401
+from . import rpy, lub, rigid, saddle, integrate, pse, brownian, forces, drift  # noqa: F401
