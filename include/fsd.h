@@ -188,6 +188,21 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
  * purpose 0 = grid, 1 = real space, 2 = near field; fsd_step advances step by one per
  * time step and sets dt. */
 
+/* Brownian drift by random finite differences (Appendix A, Eq. `rfd`).  mode 1: every
+ * fsd_step with kT > 0 first draws dq (6 per aggregate, Philox purpose 3 of the step),
+ * solves the saddle system at the configurations displaced by +-(eps/2) dq (centroids
+ * moved by (eps/2) dq_t, bodies turned by the exact rotation with rotation vector
+ * (eps/2) dq_r) with right-hand side (0, -dq) and no other forcing, and adds
+ * kT (U+ - U-) / eps to the aggregate velocities before the update.  mode 0: off (default).
+ * eps <= 0 selects gmres_tol^(1/3) * radius.  Not applied by fsd_batch_step, which
+ * returns FSD_EINVAL while an admitted system has the drift on and kT > 0. */
+fsd_status fsd_set_drift(fsd_system* s, int mode, double eps);
+
+/* The drift kT (U+ - U-) / eps at the current configuration (6 per aggregate, host), for
+ * the given dq (6 per aggregate, host) or, with dq == NULL, for the dq of the next step.
+ * Three solves' worth of work; leaves the configuration unchanged. */
+fsd_status fsd_rfd_drift(fsd_system* s, const double* dq, double* u_drift);
+
 /* Time step used by the Brownian amplitude, noise step index and noise stream id. */
 fsd_status fsd_set_brownian(fsd_system* s, double dt, uint64_t step, uint64_t stream);
 

@@ -96,6 +96,8 @@ _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
 _sig("fsd_set_pair_forces", C.c_int, _SYS, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double)
 _sig("fsd_get_pair_forces", C.c_int, _SYS, _D)
+_sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
+_sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
 
 _sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
@@ -311,6 +313,17 @@ class System:
         out = np.zeros(3 * self.n_bead)
         self._check(lib.fsd_get_pair_forces(self._h, _dptr(out)), "fsd_get_pair_forces")
         return out.reshape(-1, 3)
+
+    def set_drift(self, mode=1, eps=0.0):
+        """Brownian drift by random finite differences in every step (mode 1) or off (0)."""
+        self._check(lib.fsd_set_drift(self._h, int(mode), float(eps)), "fsd_set_drift")
+
+    def rfd_drift(self, dq=None):
+        """(n_agg, 6) drift kT (U+ - U-) / eps for dq (n_agg, 6), or the next step's dq."""
+        out = np.zeros(6 * self.n_agg)
+        a = _f64(dq, 6 * self.n_agg) if dq is not None else None
+        self._check(lib.fsd_rfd_drift(self._h, _dptr(a) if a is not None else None, _dptr(out)), "fsd_rfd_drift")
+        return out.reshape(-1, 6)
 
     def set_brownian(self, dt, step=0, stream=0):
         self._check(lib.fsd_set_brownian(self._h, float(dt), int(step), int(stream)), "fsd_set_brownian")

@@ -77,6 +77,9 @@ void launch_bead_positions(int nb, int na, const int* body, const double* xbody,
                            const double* quat, double L, double* r4, double* pos4, hipStream_t st);
 void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat,
                       hipStream_t st);
+// com = wrap(com0 + h dq_t), quat = r(h dq_r) (x) quat0 (exact rotation), 6 dq per aggregate
+void launch_displace(int na, const double* com0, const double* quat0, const double* dq, double h, double L,
+                     double* com, double* quat, hipStream_t st);
 
 // Neighbour lists in CSR form.  Column entries pack the bead index (22 bits)
 // and the periodic image shift (3 x 3 bits, offset by 3).

@@ -280,6 +280,7 @@ struct fsd_system {
     int its = 0, restarts = 0, outer = 0;
     double rel = 0;
     bool converged = false;
+    bool drift_rhs = false;  // right-hand side (0, -dq), result V without ambient flow
     fsd_status status = FSD_OK;
   } sv;
   // Brownian terms (kT > 0): time step and noise stream of the next solve, optional
@@ -303,6 +304,10 @@ struct fsd_system {
   };
   bool timing = false;
   bool pair_forces = false;  // conservative bead-pair forces in the right-hand side
+  // Brownian drift by random finite differences (fsd_set_drift)
+  int drift_mode = 0;
+  double drift_eps = 0;  // <= 0: gmres_tol^(1/3) a
+  double *d_dq = nullptr, *d_udrift = nullptr, *d_vplus = nullptr, *d_com0 = nullptr, *d_quat0 = nullptr;
   PairForceParams pf{};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
@@ -1177,7 +1182,12 @@ void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp
 
 void finish_solve(fsd_system* s, bool ok) {
   const size_t nb6 = 6 * size_t(s->nb);
-  launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
+  if (s->sv.drift_rhs) {  // U = V: no ambient flow in the drift solves
+    launch_zero(s->d_U, sizeof(double) * 6 * s->na, s->st);
+    launch_axpby(6 * size_t(s->na), 1.0, s->d_x + nb6, 1.0, s->d_U, s->st);
+  } else {
+    launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
+  }
   s->sv.converged = ok;
   s->sv.status = ok ? FSD_OK : FSD_ENOCONV;
   if (!ok) s->err = "GMRES did not reach the tolerance within gmres_maxit iterations";
@@ -1206,7 +1216,13 @@ bool solve_advance(fsd_system* s) {
   switch (v.phase) {
     case SS::PREP: {
       if (!s->prepared) prepare_end(s);
-      assemble_rhs(s);
+      if (v.drift_rhs) {  // b = (0, -dq)
+        const size_t nb6 = 6 * size_t(s->nb);
+        launch_zero(s->d_b, sizeof(double) * s->n, s->st);
+        launch_axpby(6 * size_t(s->na), -1.0, s->d_dq, 1.0, s->d_b + nb6, s->st);
+      } else {
+        assemble_rhs(s);
+      }
       gmres_launch(s, s->d_b, s->d_x, s->p.gmres_tol, mixed, s->p.gmres_maxit);
       return true;
     }
@@ -1255,14 +1271,54 @@ fsd_solve_info info_of(const fsd_system* s) {
   return inf;
 }
 
-fsd_status solve_current(fsd_system* s, fsd_solve_info* info) {
+fsd_status solve_current(fsd_system* s, fsd_solve_info* info, bool drift_rhs = false) {
   solve_begin(s);
+  s->sv.drift_rhs = drift_rhs;
   while (true) {
     HIPCHK(hipStreamSynchronize(s->st));
     if (!solve_advance(s)) break;
   }
   if (info) *info = info_of(s);
   return s->sv.status;
+}
+
+// ---- Brownian drift by random finite differences (Appendix A, Eq. `rfd`) ------------------
+// kT (U+ - U-) / eps with U+- the aggregate velocities of the saddle solves at the
+// configurations displaced by +-(eps/2) dq, each with right-hand side (0, -dq); dq is
+// Gaussian (6 per aggregate, Philox purpose 3 of this step) unless dq_host is given.
+// Leaves the drift in d_udrift and the configuration as it found it.
+void rfd_drift(fsd_system* s, const double* dq_host) {
+  auto& o = s->owned;
+  const size_t na = s->na;
+  if (!s->d_dq) {
+    s->d_dq = dalloc<double>(o, 6 * na);
+    s->d_udrift = dalloc<double>(o, 6 * na);
+    s->d_vplus = dalloc<double>(o, 6 * na);
+    s->d_com0 = dalloc<double>(o, 3 * na);
+    s->d_quat0 = dalloc<double>(o, 4 * na);
+  }
+  const double eps = s->drift_eps > 0 ? s->drift_eps : std::cbrt(s->p.gmres_tol) * s->p.radius;
+  if (dq_host)
+    HIPCHK(hipMemcpyAsync(s->d_dq, dq_host, sizeof(double) * 6 * na, hipMemcpyHostToDevice, s->st));
+  else
+    launch_normals(6 * na, NoiseKey{s->p.seed, s->bstream, 3, s->bstep}, s->d_dq, s->st);
+  HIPCHK(hipMemcpyAsync(s->d_com0, s->d_com, sizeof(double) * 3 * na, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->d_quat0, s->d_quat, sizeof(double) * 4 * na, hipMemcpyDeviceToDevice, s->st));
+  const double c = s->p.kT / eps;
+  fsd_status r = FSD_OK;
+  for (int sign = 1; sign >= -1 && r == FSD_OK; sign -= 2) {
+    launch_displace(int(na), s->d_com0, s->d_quat0, s->d_dq, 0.5 * sign * eps, s->L, s->d_com, s->d_quat, s->st);
+    s->prepared = false;
+    r = solve_current(s, nullptr, true);
+    if (sign > 0) HIPCHK(hipMemcpyAsync(s->d_vplus, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
+  }
+  HIPCHK(hipMemcpyAsync(s->d_com, s->d_com0, sizeof(double) * 3 * na, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->d_quat, s->d_quat0, sizeof(double) * 4 * na, hipMemcpyDeviceToDevice, s->st));
+  s->prepared = false;
+  if (r != FSD_OK) throw ApiError(r, std::string("drift solve: ") + s->err);
+  launch_zero(s->d_udrift, sizeof(double) * 6 * na, s->st);
+  launch_axpby(6 * na, c, s->d_vplus, 1.0, s->d_udrift, s->st);
+  launch_axpby(6 * na, -c, s->d_U, 1.0, s->d_udrift, s->st);
 }
 
 fsd_status check_ready(fsd_system* s) {
@@ -1595,9 +1651,12 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
   return guarded(s, [&]() -> fsd_status {
     fsd_status r = FSD_OK;
     s->bdt = dt;
+    const bool drift = s->drift_mode == 1 && s->p.kT > 0;
     for (int k = 0; k < n_steps; ++k) {
+      if (drift) rfd_drift(s, nullptr);
       r = solve_current(s, last);
       if (r != FSD_OK) return r;
+      if (drift) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
       launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
       s->prepared = false;
       ++s->bstep;
@@ -1879,6 +1938,30 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead) {
     HIPCHK(hipMemcpyAsync(f_bead, s->d_t, sizeof(double) * n3, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     for (size_t i = 0; i < n3; ++i) f_bead[i] = -f_bead[i];
+    return FSD_OK;
+  });
+}
+
+fsd_status fsd_set_drift(fsd_system* s, int mode, double eps) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if ((mode != 0 && mode != 1) || !std::isfinite(eps)) return fail(s, FSD_EINVAL, "drift mode 0 or 1, finite eps");
+  s->drift_mode = mode;
+  s->drift_eps = eps;
+  return FSD_OK;
+}
+
+fsd_status fsd_rfd_drift(fsd_system* s, const double* dq, double* u_drift) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!u_drift) return fail(s, FSD_EINVAL, "null output");
+  if (dq)
+    for (int i = 0; i < 6 * s->na; ++i)
+      if (!std::isfinite(dq[i])) return fail(s, FSD_EINVAL, "non-finite dq");
+  return guarded(s, [&]() -> fsd_status {
+    rfd_drift(s, dq);
+    HIPCHK(hipMemcpyAsync(u_drift, s->d_udrift, sizeof(double) * 6 * s->na, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
     return FSD_OK;
   });
 }
@@ -2421,6 +2504,9 @@ fsd_status fsd_batch_solve(fsd_batch* b) {
 
 fsd_status fsd_batch_step(fsd_batch* b, double dt) {
   if (!b || !(dt > 0)) return FSD_EINVAL;
+  for (auto* s : b->slot)
+    if (s && s->drift_mode != 0 && s->p.kT > 0)
+      return fail(s, FSD_EINVAL, "the random-finite-difference drift is applied by fsd_step only");
   return batch_run(b, dt, true);
 }
 

@@ -77,6 +77,43 @@ __global__ void k_integrate(int na, const double* __restrict__ U, double dt, dou
   quat[4 * j + 3] = z * inv;
 }
 
+// Displaced configuration of the random finite differences for the Brownian drift
+// (Appendix A, Eq. `rfd`): centroid com0 + h dq_t (wrapped as by the integrator) and
+// orientation r(h dq_r) (x) quat0, with the exact rotation quaternion
+// r(phi) = (cos(|phi|/2), sin(|phi|/2) phi / |phi|).
+__global__ void k_displace(int na, const double* __restrict__ com0, const double* __restrict__ quat0,
+                           const double* __restrict__ dq, double h, double L, double* __restrict__ com,
+                           double* __restrict__ quat) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  for (int c = 0; c < 3; ++c) {
+    double x = com0[3 * j + c] + h * dq[6 * j + c];
+    x -= L * floor((x + 0.5 * L) / L);
+    if (x >= 0.5 * L) x -= L;
+    com[3 * j + c] = x;
+  }
+  const double px = h * dq[6 * j + 3], py = h * dq[6 * j + 4], pz = h * dq[6 * j + 5];
+  const double ang = sqrt(px * px + py * py + pz * pz);
+  const double rw = cos(0.5 * ang), sc = ang > 0 ? sin(0.5 * ang) / ang : 0.0;
+  const double rx = sc * px, ry = sc * py, rz = sc * pz;
+  const double w = quat0[4 * j], x = quat0[4 * j + 1], y = quat0[4 * j + 2], z = quat0[4 * j + 3];
+  // (rw, r) (x) (w, v) = (rw w - r.v, rw v + w r + r x v)
+  double qw = rw * w - (rx * x + ry * y + rz * z);
+  double qx = rw * x + w * rx + (ry * z - rz * y);
+  double qy = rw * y + w * ry + (rz * x - rx * z);
+  double qz = rw * z + w * rz + (rx * y - ry * x);
+  const double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  quat[4 * j] = qw * inv;
+  quat[4 * j + 1] = qx * inv;
+  quat[4 * j + 2] = qy * inv;
+  quat[4 * j + 3] = qz * inv;
+}
+
+void launch_displace(int na, const double* com0, const double* quat0, const double* dq, double h, double L,
+                     double* com, double* quat, hipStream_t st) {
+  k_displace<<<nblocks(na), kThreads, 0, st>>>(na, com0, quat0, dq, h, L, com, quat);
+}
+
 void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat, hipStream_t st) {
   k_integrate<<<nblocks(na), kThreads, 0, st>>>(na, U, dt, L, com, quat);
 }

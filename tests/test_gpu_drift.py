@@ -1,0 +1,90 @@
+"""Brownian drift by random finite differences on the GPU (Appendix A, Eq. `rfd`).
+
+- the drift for a given dq against the oracle's two dense saddle solves at the displaced
+  configurations, with and without lubrication;
+- a time step with the drift on moves the bodies by (U + drift) dt, with U the saddle
+  solve's velocities and the drift that of the step's own dq;
+- the batched step refuses systems with the drift on.
+"""
+import numpy as np
+import pytest
+
+import fsdgen
+from oracle import drift, integrate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F(gpu):
+    import paper_2607_25161_amd as F
+    return F
+
+
+def _system(seed=31, sizes=(3, 4, 1, 5, 2), L=11.0, lub_on=True):
+    rng = fsdgen.rng_from(seed)
+    shapes = [fsdgen.sticking_cluster(rng, nb) for nb in sizes]
+    com, quat = fsdgen.place_clusters(rng, shapes, L, gap=0.1)
+    offs = np.r_[0, np.cumsum([len(s) for s in shapes])].astype(np.int32)
+    return dict(L=L, a=1.0, eta=1.0, offsets=offs, x_body=np.concatenate(shapes), com=com, quat=quat,
+                force=np.zeros((len(sizes), 6)), grad_u=np.zeros((3, 3)), r_lub=3.0 if lub_on else 0.0)
+
+
+def _make(F, kw, **p):
+    par = dict(xi=0.6, ewald_tol=1e-10, r_lub=kw["r_lub"], r_precond=2.1 if kw["r_lub"] else 0.0,
+               gmres_tol=1e-12, gmres_restart=40, gmres_maxit=4000, kT=0.7)
+    par.update(p)
+    s = F.System(F.default_params(**par))
+    s.init_box(kw["L"])
+    s.init_aggregates(kw["offsets"], kw["x_body"], kw["com"], kw["quat"])
+    s.set_forces(kw["force"])
+    s.set_shear(kw["grad_u"])
+    return s
+
+
+@pytest.mark.parametrize("lub_on", [False, True])
+def test_drift_matches_oracle(F, lub_on):
+    kw = _system(lub_on=lub_on)
+    s = _make(F, kw)
+    eps = 1e-3
+    s.set_drift(0, eps)  # eps only; the drift below is computed on request
+    dq = np.random.default_rng(32).normal(size=(len(kw["offsets"]) - 1, 6))
+    d = s.rfd_drift(dq)
+    ref = drift.rfd_drift(kw["L"], 1.0, 1.0, kw["offsets"], kw["x_body"], kw["com"], kw["quat"], dq, eps, 0.7,
+                          r_lub=kw["r_lub"])
+    assert np.abs(ref).max() > 0
+    assert np.linalg.norm(d - ref) <= 1e-6 * np.linalg.norm(ref), np.linalg.norm(d - ref) / np.linalg.norm(ref)
+    X, q = s.state()  # the drift leaves the configuration as it found it
+    X0 = (np.asarray(kw["com"]) + kw["L"] / 2) % kw["L"] - kw["L"] / 2
+    assert np.abs(X - X0).max() < 1e-12
+    s.close()
+
+
+def test_step_adds_the_drift(F):
+    kw = _system(seed=33)
+    s = _make(F, kw)
+    s.set_brownian(1e-3, step=5)
+    na = len(kw["offsets"]) - 1
+    nb = int(kw["offsets"][-1])
+    s.set_noise(psi_w=np.zeros(3 * s.info().grid ** 3), psi_r=np.zeros(6 * nb), psi_nf=np.zeros(3 * nb))
+    U, _, _ = s.solve()        # no Brownian terms (zero noise): the solve's velocities
+    dr = s.rfd_drift()         # the drift for the next step's dq
+    X0, q0 = s.state()
+    s.set_drift(1)
+    s.set_brownian(1e-3, step=5)
+    s.step(1e-3, 1)
+    X1, q1 = s.state()
+    Xo, qo = integrate.euler_step(X0, q0, U + dr, 1e-3, kw["L"])
+    assert np.abs(X1 - Xo).max() < 1e-12 and np.abs(q1 - qo).max() < 1e-12
+    assert np.abs(dr).max() * 1e-3 > 1e-9  # the drift moved the bodies measurably
+    s.close()
+
+
+def test_batch_refuses_the_drift(F):
+    kw = _system(seed=34)
+    s = _make(F, kw)
+    s.set_drift(1)
+    b = F.Batch(1 << 32, 2)
+    b.admit(s)
+    assert b.step(1e-3) == -1  # FSD_EINVAL
+    b.close()
