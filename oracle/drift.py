@@ -1,4 +1,5 @@
-"""Brownian drift by random finite differences (oracle), Appendix A, Eq. `rfd`.
+"""Brownian drift (oracle), Appendix A: random finite differences (Eq. `rfd`) and
+Fixman's midpoint scheme.
 
 TEST INFRASTRUCTURE: used only by the tests, the smoke check and the CPU baseline.
 
@@ -78,3 +79,24 @@ def divergence(L, a, eta, offsets, x_body, com, quat, h=1e-4, r_lub=0.0, xi=None
         Nm = mobility_matrix(L, a, eta, offsets, x_body, Xm, qm, r_lub, xi)
         div += (Np[:, k] - Nm[:, k]) / (2 * h)
     return div.reshape(na, 6)
+
+
+def brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub=0.0, xi=None):
+    """Aggregate velocities of the saddle solve whose right-hand side holds only the given
+    Brownian slip u_b (6 per bead) and near-field force f_b (3 per bead)."""
+    na = len(offsets) - 1
+    fb6 = np.zeros((len(f_b), 6))
+    fb6[:, :3] = np.asarray(f_b, dtype=float).reshape(-1, 3)
+    U, *_ = saddle.solve(L, a, eta, offsets, x_body, com, quat, np.zeros((na, 6)), np.zeros((3, 3)), r_lub=r_lub,
+                         xi=xi, u_brown=np.asarray(u_b, dtype=float).reshape(-1, 6), f_brown_nf=fb6)
+    return U
+
+
+def fixman_drift(L, a, eta, offsets, x_body, com, quat, u_b, f_b, m, dt, r_lub=0.0, xi=None):
+    """Fixman's midpoint estimate (Appendix A): U0 from the Brownian terms at x, the
+    configuration advanced by U0 dt/m, U' from the same Brownian terms there, and
+    drift = (m/2) (U' - U0)."""
+    U0 = brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub, xi)
+    X1, q1 = integrate.euler_step(com, quat, U0, dt / m, L)
+    U1 = brownian_velocity(L, a, eta, offsets, x_body, X1, q1, u_b, f_b, r_lub, xi)
+    return 0.5 * m * (U1 - U0)

@@ -56,3 +56,41 @@ def test_single_sphere_has_no_drift():
     d = drift.rfd_drift(L, a, eta, offs, np.zeros((1, 3)), np.array([[0.4, -1.0, 2.0]]),
                         np.array([[1.0, 0, 0, 0]]), dq, 1e-2, kT=1.0)
     assert np.abs(d).max() < 1e-9
+
+
+def _brownian_terms(rng, nb):
+    return rng.normal(size=(nb, 6)), rng.normal(size=(nb, 3))
+
+
+def test_fixman_single_sphere_has_no_drift():
+    offs = np.array([0, 1], dtype=np.int32)
+    ub, fb = _brownian_terms(np.random.default_rng(8), 1)
+    d = drift.fixman_drift(L, a, eta, offs, np.zeros((1, 3)), np.array([[0.4, -1.0, 2.0]]),
+                           np.array([[1.0, 0, 0, 0]]), ub, fb, m=100, dt=1e-3)
+    assert np.abs(d).max() < 1e-9
+
+
+def test_fixman_large_m_is_the_directional_derivative():
+    """(m/2)(U' - U0) -> (dt/2) (dN/dq . U0) f for large m, when the Brownian terms act as a
+    fixed generalised force f (U0 = N f): two spheres, near-field force only.  The derivative
+    comes from central differences of the aggregate mobility along U0 (the displacement path
+    of the random finite differences)."""
+    offs = np.array([0, 1, 2], dtype=np.int32)
+    xb = np.zeros((2, 3))
+    com = np.array([[0.0, 0.2, 0.0], [2.4, -0.3, 0.5]])
+    quat = np.tile([1.0, 0, 0, 0], (2, 1))
+    fb = np.random.default_rng(9).normal(size=(2, 3))
+    ub = np.zeros((2, 6))
+    dt, m = 1e-2, 1e4
+    est = drift.fixman_drift(L, a, eta, offs, xb, com, quat, ub, fb, m, dt)
+    U0 = drift.brownian_velocity(L, a, eta, offs, xb, com, quat, ub, fb)
+    f = np.zeros((2, 6))
+    f[:, :3] = fb  # the near-field force acts like an external force on each sphere
+    assert np.allclose(drift.mobility_matrix(L, a, eta, offs, xb, com, quat) @ f.ravel(), U0.ravel(), atol=1e-12)
+    h = 1e-4
+    Xp, qp = drift.displace(com, quat, U0, +h, L)
+    Xm, qm = drift.displace(com, quat, U0, -h, L)
+    dN = (drift.mobility_matrix(L, a, eta, offs, xb, Xp, qp) - drift.mobility_matrix(L, a, eta, offs, xb, Xm, qm)) / (2 * h)
+    want = (0.5 * dt * dN @ f.ravel()).reshape(-1, 6)
+    assert np.abs(want).max() > 1e-8
+    assert np.abs(est - want).max() <= 1e-3 * np.abs(want).max()
