@@ -188,14 +188,18 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
  * purpose 0 = grid, 1 = real space, 2 = near field; fsd_step advances step by one per
  * time step and sets dt. */
 
-/* Brownian drift by random finite differences (Appendix A, Eq. `rfd`).  mode 1: every
+/* Brownian drift (Appendix A).  mode 1, random finite differences (Eq. `rfd`): every
  * fsd_step with kT > 0 first draws dq (6 per aggregate, Philox purpose 3 of the step),
  * solves the saddle system at the configurations displaced by +-(eps/2) dq (centroids
  * moved by (eps/2) dq_t, bodies turned by the exact rotation with rotation vector
  * (eps/2) dq_r) with right-hand side (0, -dq) and no other forcing, and adds
- * kT (U+ - U-) / eps to the aggregate velocities before the update.  mode 0: off (default).
- * eps <= 0 selects gmres_tol^(1/3) * radius.  Not applied by fsd_batch_step, which
- * returns FSD_EINVAL while an admitted system has the drift on and kT > 0. */
+ * kT (U+ - U-) / eps to the aggregate velocities before the update; eps <= 0 selects
+ * gmres_tol^(1/3) * radius.  mode 2, Fixman's midpoint scheme: after the step's solve at x,
+ * U0 solves with that step's Brownian terms alone (u_B, -Sigma F_B; no ambient flow or other
+ * forcing) at x and U' with the same terms at x + (dt/m) U0 (an Euler move), and
+ * (m/2) (U' - U0) is added; the second argument is then m (<= 0: 100).  mode 0: off
+ * (default).  Not applied by fsd_batch_step, which returns FSD_EINVAL while an admitted
+ * system has a drift on and kT > 0. */
 fsd_status fsd_set_drift(fsd_system* s, int mode, double eps);
 
 /* The drift kT (U+ - U-) / eps at the current configuration (6 per aggregate, host), for

@@ -315,7 +315,8 @@ class System:
         return out.reshape(-1, 3)
 
     def set_drift(self, mode=1, eps=0.0):
-        """Brownian drift by random finite differences in every step (mode 1) or off (0)."""
+        """Brownian drift in every step: 1 random finite differences (eps; <= 0: default),
+        2 Fixman's midpoint scheme (eps is m; <= 0: 100), 0 off."""
         self._check(lib.fsd_set_drift(self._h, int(mode), float(eps)), "fsd_set_drift")
 
     def rfd_drift(self, dq=None):

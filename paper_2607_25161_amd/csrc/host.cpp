@@ -280,7 +280,9 @@ struct fsd_system {
     int its = 0, restarts = 0, outer = 0;
     double rel = 0;
     bool converged = false;
-    bool drift_rhs = false;  // right-hand side (0, -dq), result V without ambient flow
+    // right-hand side: 0 the full one; 1 (0, -dq) of the random finite differences; 2 the
+    // stored Brownian terms alone (Fixman).  Kinds 1 and 2 return V without ambient flow.
+    int rhs_kind = 0;
     fsd_status status = FSD_OK;
   } sv;
   // Brownian terms (kT > 0): time step and noise stream of the next solve, optional
@@ -307,7 +309,8 @@ struct fsd_system {
   // Brownian drift by random finite differences (fsd_set_drift)
   int drift_mode = 0;
   double drift_eps = 0;  // <= 0: gmres_tol^(1/3) a
-  double *d_dq = nullptr, *d_udrift = nullptr, *d_vplus = nullptr, *d_com0 = nullptr, *d_quat0 = nullptr;
+  double *d_dq = nullptr, *d_udrift = nullptr, *d_vplus = nullptr, *d_umain = nullptr, *d_com0 = nullptr,
+         *d_quat0 = nullptr;
   PairForceParams pf{};
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
@@ -1182,7 +1185,7 @@ void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp
 
 void finish_solve(fsd_system* s, bool ok) {
   const size_t nb6 = 6 * size_t(s->nb);
-  if (s->sv.drift_rhs) {  // U = V: no ambient flow in the drift solves
+  if (s->sv.rhs_kind != 0) {  // U = V: no ambient flow in the drift solves
     launch_zero(s->d_U, sizeof(double) * 6 * s->na, s->st);
     launch_axpby(6 * size_t(s->na), 1.0, s->d_x + nb6, 1.0, s->d_U, s->st);
   } else {
@@ -1216,10 +1219,17 @@ bool solve_advance(fsd_system* s) {
   switch (v.phase) {
     case SS::PREP: {
       if (!s->prepared) prepare_end(s);
-      if (v.drift_rhs) {  // b = (0, -dq)
-        const size_t nb6 = 6 * size_t(s->nb);
+      const size_t nb6 = 6 * size_t(s->nb);
+      if (v.rhs_kind == 1) {  // b = (0, -dq)
         launch_zero(s->d_b, sizeof(double) * s->n, s->st);
         launch_axpby(6 * size_t(s->na), -1.0, s->d_dq, 1.0, s->d_b + nb6, s->st);
+      } else if (v.rhs_kind == 2) {  // b = (u_B, -Sigma F_B) with the stored Brownian terms
+        launch_zero(s->d_b, sizeof(double) * s->n, s->st);
+        launch_axpby(nb6, 1.0, s->d_ub, 1.0, s->d_b, s->st);
+        launch_zero(s->d_fl, sizeof(double) * 3 * s->nb, s->st);
+        launch_axpby(3 * size_t(s->nb), -1.0, s->d_fb, 1.0, s->d_fl, s->st);
+        launch_zero(s->d_vplus, sizeof(double) * 6 * s->na, s->st);  // no other force
+        launch_rhs_agg(s->na, s->d_offsets, s->d_r4, s->d_vplus, s->d_fl, s->d_b + nb6, s->st);
       } else {
         assemble_rhs(s);
       }
@@ -1271,9 +1281,9 @@ fsd_solve_info info_of(const fsd_system* s) {
   return inf;
 }
 
-fsd_status solve_current(fsd_system* s, fsd_solve_info* info, bool drift_rhs = false) {
+fsd_status solve_current(fsd_system* s, fsd_solve_info* info, int rhs_kind = 0) {
   solve_begin(s);
-  s->sv.drift_rhs = drift_rhs;
+  s->sv.rhs_kind = rhs_kind;
   while (true) {
     HIPCHK(hipStreamSynchronize(s->st));
     if (!solve_advance(s)) break;
@@ -1287,16 +1297,21 @@ fsd_status solve_current(fsd_system* s, fsd_solve_info* info, bool drift_rhs = f
 // configurations displaced by +-(eps/2) dq, each with right-hand side (0, -dq); dq is
 // Gaussian (6 per aggregate, Philox purpose 3 of this step) unless dq_host is given.
 // Leaves the drift in d_udrift and the configuration as it found it.
-void rfd_drift(fsd_system* s, const double* dq_host) {
+void ensure_drift(fsd_system* s) {
+  if (s->d_dq) return;
   auto& o = s->owned;
   const size_t na = s->na;
-  if (!s->d_dq) {
-    s->d_dq = dalloc<double>(o, 6 * na);
-    s->d_udrift = dalloc<double>(o, 6 * na);
-    s->d_vplus = dalloc<double>(o, 6 * na);
-    s->d_com0 = dalloc<double>(o, 3 * na);
-    s->d_quat0 = dalloc<double>(o, 4 * na);
-  }
+  s->d_dq = dalloc<double>(o, 6 * na);
+  s->d_udrift = dalloc<double>(o, 6 * na);
+  s->d_vplus = dalloc<double>(o, 6 * na);
+  s->d_umain = dalloc<double>(o, 6 * na);
+  s->d_com0 = dalloc<double>(o, 3 * na);
+  s->d_quat0 = dalloc<double>(o, 4 * na);
+}
+
+void rfd_drift(fsd_system* s, const double* dq_host) {
+  ensure_drift(s);
+  const size_t na = s->na;
   const double eps = s->drift_eps > 0 ? s->drift_eps : std::cbrt(s->p.gmres_tol) * s->p.radius;
   if (dq_host)
     HIPCHK(hipMemcpyAsync(s->d_dq, dq_host, sizeof(double) * 6 * na, hipMemcpyHostToDevice, s->st));
@@ -1309,7 +1324,7 @@ void rfd_drift(fsd_system* s, const double* dq_host) {
   for (int sign = 1; sign >= -1 && r == FSD_OK; sign -= 2) {
     launch_displace(int(na), s->d_com0, s->d_quat0, s->d_dq, 0.5 * sign * eps, s->L, s->d_com, s->d_quat, s->st);
     s->prepared = false;
-    r = solve_current(s, nullptr, true);
+    r = solve_current(s, nullptr, 1);
     if (sign > 0) HIPCHK(hipMemcpyAsync(s->d_vplus, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
   }
   HIPCHK(hipMemcpyAsync(s->d_com, s->d_com0, sizeof(double) * 3 * na, hipMemcpyDeviceToDevice, s->st));
@@ -1319,6 +1334,33 @@ void rfd_drift(fsd_system* s, const double* dq_host) {
   launch_zero(s->d_udrift, sizeof(double) * 6 * na, s->st);
   launch_axpby(6 * na, c, s->d_vplus, 1.0, s->d_udrift, s->st);
   launch_axpby(6 * na, -c, s->d_U, 1.0, s->d_udrift, s->st);
+}
+
+// Fixman's midpoint drift (Appendix A), after a solve at x that computed this step's
+// Brownian terms (d_ub, d_fb) and left its velocities in d_U: U0 from those terms alone at
+// x, U' from the same terms at x + (dt/m) U0, drift (m/2) (U' - U0) into d_udrift; the
+// configuration is restored and d_U holds the first solve's velocities again.
+void fixman_drift(fsd_system* s, double dt) {
+  ensure_drift(s);
+  const size_t na = s->na;
+  const double m = s->drift_eps > 0 ? s->drift_eps : 100.0;
+  HIPCHK(hipMemcpyAsync(s->d_umain, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->d_com0, s->d_com, sizeof(double) * 3 * na, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->d_quat0, s->d_quat, sizeof(double) * 4 * na, hipMemcpyDeviceToDevice, s->st));
+  fsd_status r = solve_current(s, nullptr, 2);  // U0 (positions unchanged: still prepared)
+  if (r == FSD_OK) {
+    HIPCHK(hipMemcpyAsync(s->d_udrift, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
+    launch_integrate(int(na), s->d_U, dt / m, s->L, s->d_com, s->d_quat, s->st);
+    s->prepared = false;
+    r = solve_current(s, nullptr, 2);  // U'
+  }
+  HIPCHK(hipMemcpyAsync(s->d_com, s->d_com0, sizeof(double) * 3 * na, hipMemcpyDeviceToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->d_quat, s->d_quat0, sizeof(double) * 4 * na, hipMemcpyDeviceToDevice, s->st));
+  s->prepared = false;
+  if (r != FSD_OK) throw ApiError(r, std::string("Fixman drift solve: ") + s->err);
+  // d_udrift = (m/2) (U' - U0), d_U = the first solve's velocities
+  launch_axpby(6 * na, 0.5 * m, s->d_U, -0.5 * m, s->d_udrift, s->st);
+  HIPCHK(hipMemcpyAsync(s->d_U, s->d_umain, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
 }
 
 fsd_status check_ready(fsd_system* s) {
@@ -1651,12 +1693,13 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
   return guarded(s, [&]() -> fsd_status {
     fsd_status r = FSD_OK;
     s->bdt = dt;
-    const bool drift = s->drift_mode == 1 && s->p.kT > 0;
+    const bool rfd = s->drift_mode == 1 && s->p.kT > 0, fixman = s->drift_mode == 2 && s->p.kT > 0;
     for (int k = 0; k < n_steps; ++k) {
-      if (drift) rfd_drift(s, nullptr);
+      if (rfd) rfd_drift(s, nullptr);
       r = solve_current(s, last);
       if (r != FSD_OK) return r;
-      if (drift) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
+      if (fixman) fixman_drift(s, dt);
+      if (rfd || fixman) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
       launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
       s->prepared = false;
       ++s->bstep;
@@ -1945,7 +1988,7 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead) {
 fsd_status fsd_set_drift(fsd_system* s, int mode, double eps) {
   fsd_status c = check_ready(s);
   if (c) return c;
-  if ((mode != 0 && mode != 1) || !std::isfinite(eps)) return fail(s, FSD_EINVAL, "drift mode 0 or 1, finite eps");
+  if (mode < 0 || mode > 2 || !std::isfinite(eps)) return fail(s, FSD_EINVAL, "drift mode 0, 1 or 2, finite eps");
   s->drift_mode = mode;
   s->drift_eps = eps;
   return FSD_OK;

@@ -1,10 +1,13 @@
-"""Brownian drift by random finite differences on the GPU (Appendix A, Eq. `rfd`).
+"""Brownian drift on the GPU (Appendix A): random finite differences (Eq. `rfd`) and
+Fixman's midpoint scheme.
 
 - the drift for a given dq against the oracle's two dense saddle solves at the displaced
   configurations, with and without lubrication;
 - a time step with the drift on moves the bodies by (U + drift) dt, with U the saddle
   solve's velocities and the drift that of the step's own dq;
-- the batched step refuses systems with the drift on.
+- the batched step refuses systems with the drift on;
+- a step with Fixman's drift moves the bodies by (U + (m/2)(U' - U0)) dt, against the
+  oracle's two dense solves with the Brownian terms the library drew.
 """
 import numpy as np
 import pytest
@@ -88,3 +91,32 @@ def test_batch_refuses_the_drift(F):
     b.admit(s)
     assert b.step(1e-3) == -1  # FSD_EINVAL
     b.close()
+
+
+def test_fixman_step_matches_oracle(F):
+    """A step with Fixman's midpoint drift: the library's update equals the oracle's Euler
+    update with U + (m/2)(U' - U0), the oracle taking U0 and U' from its dense solves with the
+    Brownian terms the library drew."""
+    kw = _system(seed=35)
+    s = _make(F, kw)
+    dt, m = 1e-3, 100.0
+    nb = int(kw["offsets"][-1])
+    rng = np.random.default_rng(36)
+    s.set_brownian(dt, step=3)
+    s.set_noise(psi_w=np.zeros(3 * s.info().grid ** 3), psi_r=rng.normal(size=6 * nb), psi_nf=rng.normal(size=3 * nb))
+    U, _, _ = s.solve()
+    ub, fb, _ = s.brownian_terms()
+    X0, q0 = s.state()
+    s.set_drift(2, m)
+    s.step(dt, 1)
+    X1, q1 = s.state()
+    d = drift.fixman_drift(kw["L"], 1.0, 1.0, kw["offsets"], kw["x_body"], kw["com"], kw["quat"], ub, fb, m, dt,
+                           r_lub=kw["r_lub"])
+    Xo, qo = integrate.euler_step(X0, q0, U + d, dt, kw["L"])
+    Xn, qn = integrate.euler_step(X0, q0, U, dt, kw["L"])
+    # the drift moves the bodies measurably; the library's move agrees with the oracle's to a
+    # small fraction of it ((m/2) amplifies the solves' common error, which mostly cancels)
+    for got, want, base in ((X1, Xo, Xn), (q1, qo, qn)):
+        assert np.abs(want - base).max() > 1e-8
+        assert np.abs(got - want).max() <= 1e-4 * np.abs(want - base).max(), np.abs(got - want).max()
+    s.close()
