@@ -15,6 +15,15 @@ both vanish at the cutoff r = 3a (eps = 1).  The force on bead i is
 -sum_k R_pair (v_i - v_k).  Rotational rows are zero.  The sparse
 preconditioner copy (Section 2.2.2: pairs with r < 2.1a) uses the same
 functions with the smaller cutoff.
+
+Surface roughness (Section 4.2, Eq. `tan_fric`) strengthens the tangential
+(sliding) resistance below an asperity height h0: Y gains
+
+    f(h) = alpha (a/h0) (h0/h - 3 h/h0 + 2 h^2/h0^2)  for h < h0, else 0,
+
+with h = eps a the regularised gap.  The squeeze function X is unchanged, and
+rolling is absent with the rotational rows; the FE and SE strengths belong to
+the stresslet level.
 """
 from __future__ import annotations
 
@@ -31,6 +40,15 @@ def X_squeeze(eps):
 
 def Y_shear(eps):
     return np.log(1.0 / np.asarray(eps, dtype=float)) / 6.0
+
+
+def roughness(h, a, alpha, h0):
+    """Tangential roughness correction f(h) (dimensionless, like Y)."""
+    h = np.asarray(h, dtype=float)
+    if alpha == 0:
+        return np.zeros_like(h)
+    t = h / h0
+    return np.where(h < h0, alpha * (a / h0) * (1.0 / t - 3.0 * t + 2.0 * t * t), 0.0)
 
 
 def pairs(x, body, L, r_cut):
@@ -52,24 +70,24 @@ def pairs(x, body, L, r_cut):
     return i, k, d[i, k]
 
 
-def pair_blocks(d, a, eta, eps_min=1e-3):
-    """3x3 pair resistance blocks for separations d (m, 3)."""
+def pair_blocks(d, a, eta, eps_min=1e-3, rough=(0.0, 0.0)):
+    """3x3 pair resistance blocks for separations d (m, 3); rough = (alpha, h0)."""
     r = np.linalg.norm(d, axis=1)
     n = d / r[:, None]
     eps = np.maximum(r / a - 2.0, eps_min)
     z = 6.0 * math.pi * eta * a
-    X, Y = X_squeeze(eps), Y_shear(eps)
+    X, Y = X_squeeze(eps), Y_shear(eps) + roughness(eps * a, a, *rough)
     nn = n[:, :, None] * n[:, None, :]
     return z * (X[:, None, None] * nn + Y[:, None, None] * (np.eye(3) - nn))
 
 
-def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3):
+def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3, rough=(0.0, 0.0)):
     """Dense 6N x 6N R_nf (translational rows/columns only)."""
     n = len(x)
     R = np.zeros((n, 6, n, 6))
     i, k, d = pairs(x, body, L, r_cut)
     if len(i):
-        B = pair_blocks(d, a, eta, eps_min)
+        B = pair_blocks(d, a, eta, eps_min, rough)
         for m in range(len(i)):
             R[i[m], :3, i[m], :3] += B[m]
             R[k[m], :3, k[m], :3] += B[m]
