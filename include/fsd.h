@@ -176,6 +176,17 @@ fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double
 /* The conservative bead forces at the current positions (3 per bead, host array). */
 fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
 
+/* Surface roughness of lubrication (Section 4.2, Eq. `tan_fric`): for inter-body pairs with
+ * gap h = r - 2a below the asperity height h0, the tangential (sliding) resistance function Y
+ * gains alpha (a/h0)(h0/h - 3h/h0 + 2h^2/h0^2), which diverges as alpha a / h at contact and
+ * switches on with zero value and slope at h0; h is floored at lub_eps_min * a like the other
+ * functions.  The squeeze function is unchanged; the stresslet strengths (FE, SE) belong to
+ * the FTS level, which this library does not build.  The correction enters the solves, the
+ * preconditioner copy and the near-field Brownian force.  alpha = 0 switches it off (h0 is
+ * then ignored); otherwise FSD_EINVAL unless lubrication is on (r_lub > 0), alpha > 0 and
+ * 0 < h0 <= r_lub - 2a.  Default off. */
+fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0);
+
 /* ---- Brownian motion (kT > 0) --------------------------------------------------------
  * Eq. `SP2` and Algorithm 1 step 3: with kT > 0 every solve adds the Brownian slip
  * velocity u_B = sqrt(2 kT/dt) (M_r^{1/2} psi_r + M_w^{1/2} psi_w) to the bead rows of the

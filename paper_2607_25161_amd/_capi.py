@@ -96,6 +96,7 @@ _sig("fsd_set_graphs", C.c_int, _SYS, C.c_int, C.c_int)
 _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
 _sig("fsd_set_pair_forces", C.c_int, _SYS, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double)
 _sig("fsd_get_pair_forces", C.c_int, _SYS, _D)
+_sig("fsd_set_roughness", C.c_int, _SYS, C.c_double, C.c_double)
 _sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
@@ -313,6 +314,11 @@ class System:
         out = np.zeros(3 * self.n_bead)
         self._check(lib.fsd_get_pair_forces(self._h, _dptr(out)), "fsd_get_pair_forces")
         return out.reshape(-1, 3)
+
+    def set_roughness(self, alpha=0.0, h0=0.0):
+        """Tangential roughness of lubrication: strength alpha below the asperity height h0
+        (alpha 0: off)."""
+        self._check(lib.fsd_set_roughness(self._h, float(alpha), float(h0)), "fsd_set_roughness")
 
     def set_drift(self, mode=1, eps=0.0):
         """Brownian drift in every step: 1 random finite differences (eps; <= 0: default),

@@ -97,8 +97,8 @@ hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4, const int
                           hipStream_t st);
 
 void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col,
-                      double a, double eta, double eps_min, double r_pre, double* coef,
-                      double* rdiag, int* overlap_flag, hipStream_t st);
+                      double a, double eta, double eps_min, double r_pre, double rough_alpha,
+                      double rough_h0, double* coef, double* rdiag, int* overlap_flag, hipStream_t st);
 void launch_precond_factor(int na, const int* offsets, const double* r4, const double* rdiag,
                            double drag_t, double drag_r, double* lu, int* piv, int* singular,
                            hipStream_t st);

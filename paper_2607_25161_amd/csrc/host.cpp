@@ -312,6 +312,7 @@ struct fsd_system {
   double *d_dq = nullptr, *d_udrift = nullptr, *d_vplus = nullptr, *d_umain = nullptr, *d_com0 = nullptr,
          *d_quat0 = nullptr;
   PairForceParams pf{};
+  double rough_alpha = 0.0, rough_h0 = 0.0;  // tangential roughness of lubrication (h0 = 0: off)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -643,7 +644,7 @@ void prepare_end(fsd_system* s) {
     }
     HIPCHK(neighbors_fill(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->p.r_lub, true, s->d_lrow, s->d_lcol, s->st));
     launch_lub_setup(s->nb, s->d_pos4, s->L, s->d_lrow, s->d_lcol, s->p.radius, s->p.eta, s->p.lub_eps_min,
-                     s->p.r_precond, s->d_lcoef, s->d_rdiag, s->d_flags, s->st);
+                     s->p.r_precond, s->rough_alpha, s->rough_h0, s->d_lcoef, s->d_rdiag, s->d_flags, s->st);
   } else {
     launch_zero(s->d_rdiag, sizeof(double) * 6 * s->nb, s->st);
     s->nlub = 0;
@@ -1963,6 +1964,25 @@ fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double
     return fail(s, FSD_EINVAL, "r_cut must lie in [2a, the real-space cutoff]");
   s->pf = PairForceParams{k_n, hamaker, Z, kappa, h_c, r_cut, a, s->L};
   s->pair_forces = true;
+  return FSD_OK;
+}
+
+fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!std::isfinite(alpha) || !std::isfinite(h0)) return fail(s, FSD_EINVAL, "non-finite roughness parameter");
+  if (alpha < 0) return fail(s, FSD_EINVAL, "the roughness strength must be >= 0");
+  if (alpha > 0) {
+    if (!(s->p.r_lub > 0)) return fail(s, FSD_EINVAL, "roughness acts through lubrication, which is off");
+    if (!(h0 > 0) || 2 * s->p.radius + h0 > s->p.r_lub)
+      return fail(s, FSD_EINVAL, "h0 must lie in (0, r_lub - 2a]");
+  }
+  const double ra = alpha > 0 ? alpha : 0.0, rh = alpha > 0 ? h0 : 0.0;
+  if (ra != s->rough_alpha || rh != s->rough_h0) {
+    s->rough_alpha = ra;
+    s->rough_h0 = rh;
+    s->prepared = false;  // the lubrication coefficients and the preconditioner change
+  }
   return FSD_OK;
 }
 

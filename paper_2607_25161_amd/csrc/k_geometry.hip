@@ -329,12 +329,16 @@ hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const in
 
 // ------------------------------------------------------------------------------------------
 // lubrication pairs: the stated model (squeeze X and shear Y of two equal spheres,
-// shifted to vanish at r = 3a) acting on translational disturbance velocities
+// shifted to vanish at r = 3a) acting on translational disturbance velocities.  Surface
+// roughness (Section 4.2, Eq. `tan_fric`) adds to Y, below the asperity height h0, the
+// correction alpha (a/h0)(h0/h - 3h/h0 + 2h^2/h0^2) = alpha (a/h)(1 - t)^2 (1 + 2t), t = h/h0,
+// with h = eps a the regularised gap
 // ------------------------------------------------------------------------------------------
 
 __global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, const int* __restrict__ rowptr,
                             const uint32_t* __restrict__ col, double a, double eta, double eps_min, double r_pre,
-                            double* __restrict__ coef, double* __restrict__ rdiag, int* overlap_flag) {
+                            double rough_alpha, double rough_h0, double* __restrict__ coef,
+                            double* __restrict__ rdiag, int* overlap_flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const double4 p = pos[i];
@@ -353,7 +357,12 @@ __global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, c
     const double eps = fmax(r / a - 2.0, eps_min);
     const double lg = log(1.0 / eps);
     const double X = z * (0.25 / eps + 0.225 * lg + (3.0 / 112.0) * eps * lg - 0.25);
-    const double Y = z * (lg / 6.0);
+    double Y = z * (lg / 6.0);
+    const double h = eps * a;
+    if (h < rough_h0) {  // rough_h0 = 0 when roughness is off
+      const double t = h / rough_h0, u = 1.0 - t;
+      Y += z * rough_alpha * (a / h) * u * u * (1.0 + 2.0 * t);
+    }
     coef[5 * e] = X;
     coef[5 * e + 1] = Y;
     coef[5 * e + 2] = nx;
@@ -373,10 +382,10 @@ __global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, c
 }
 
 void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col, double a,
-                      double eta, double eps_min, double r_pre, double* coef, double* rdiag, int* overlap_flag,
-                      hipStream_t st) {
+                      double eta, double eps_min, double r_pre, double rough_alpha, double rough_h0, double* coef,
+                      double* rdiag, int* overlap_flag, hipStream_t st) {
   k_lub_setup<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, L, rowptr, col, a, eta, eps_min, r_pre,
-                                                 coef, rdiag, overlap_flag);
+                                                 rough_alpha, rough_h0, coef, rdiag, overlap_flag);
 }
 
 // ------------------------------------------------------------------------------------------
