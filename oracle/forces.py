@@ -66,13 +66,15 @@ def pair_force(r, a, k_n=0.0, hamaker=0.0, Z=0.0, kappa=0.0, h_c=0.0):
     return f
 
 
-def bead_forces(x, body, L, a, r_cut, **coef):
+def bead_forces(x, body, L, a, r_cut, strain=0.0, **coef):
     """Force on every bead (n, 3): brute force over bead pairs of different bodies and over
-    periodic images within r_cut."""
+    periodic images within r_cut (image n at (n_x + gamma n_y, n_y, n_z) L for strain gamma)."""
     x = np.asarray(x, dtype=float)
     n = len(x)
-    m = int(math.ceil(r_cut / L))
-    shifts = np.array(list(itertools.product(range(-m, m + 1), repeat=3)), dtype=float) * L
+    m = int(math.ceil(r_cut / L)) + 1
+    shifts = np.array(list(itertools.product(range(-m, m + 1), repeat=3)), dtype=float)
+    shifts[:, 0] += strain * shifts[:, 1]
+    shifts *= L
     f = np.zeros((n, 3))
     for i in range(n):
         for j in range(n):

@@ -24,7 +24,8 @@ def quat_mul(p, q):
     return np.concatenate([w, v], axis=-1)
 
 
-def euler_step(com, quat, U, dt, L):
+def euler_step(com, quat, U, dt, L, strain=0.0):
+    """One step; centroids folded into the lattice of the given (end-of-step) strain."""
     U = np.asarray(U, dtype=float).reshape(-1, 6)
     X = np.asarray(com, dtype=float) + U[:, :3] * dt
     om = np.concatenate([np.zeros((len(U), 1)), U[:, 3:]], axis=1)
@@ -32,4 +33,4 @@ def euler_step(com, quat, U, dt, L):
     q = q / np.linalg.norm(q, axis=1, keepdims=True)
     q = q + 0.5 * dt * quat_mul(om, q)
     q = q / np.linalg.norm(q, axis=1, keepdims=True)
-    return rigid.wrap(X, L), q
+    return rigid.wrap(X, L, strain), q

@@ -51,18 +51,30 @@ def roughness(h, a, alpha, h0):
     return np.where(h < h0, alpha * (a / h0) * (1.0 / t - 3.0 * t + 2.0 * t * t), 0.0)
 
 
-def pairs(x, body, L, r_cut):
+def min_image(d, L, strain=0.0):
+    """Nearest image of separations d (..., 3) in the (sheared) lattice: y first, each
+    period of y carrying gamma L of x, then x and z.  Exact for |d| < L/2."""
+    d = np.array(d, dtype=float)
+    ny = np.round(d[..., 1] / L)
+    d[..., 1] -= ny * L
+    d[..., 0] -= ny * strain * L
+    d[..., 0] -= L * np.round(d[..., 0] / L)
+    d[..., 2] -= L * np.round(d[..., 2] / L)
+    return d
+
+
+def pairs(x, body, L, r_cut, strain=0.0):
     """Inter-body bead pairs (i < k) with minimum-image distance < r_cut.
 
-    Returns (i, k, d) with d = x_i - x_k (minimum image).  Requires r_cut < L/2.
+    Returns (i, k, d) with d = x_i - x_k (minimum image; strain as in `min_image`).
+    Requires r_cut < L/2.
     """
     if r_cut <= 0:
         return np.zeros(0, int), np.zeros(0, int), np.zeros((0, 3))
     if r_cut >= L / 2:
         raise ValueError("lubrication cutoff must be below half the box side")
     n = len(x)
-    d = x[:, None, :] - x[None, :, :]
-    d -= L * np.round(d / L)
+    d = min_image(x[:, None, :] - x[None, :, :], L, strain)
     r = np.linalg.norm(d, axis=-1)
     iu = np.triu_indices(n, 1)
     sel = (r[iu] < r_cut) & (body[iu[0]] != body[iu[1]])
@@ -81,11 +93,11 @@ def pair_blocks(d, a, eta, eps_min=1e-3, rough=(0.0, 0.0)):
     return z * (X[:, None, None] * nn + Y[:, None, None] * (np.eye(3) - nn))
 
 
-def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3, rough=(0.0, 0.0)):
+def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3, rough=(0.0, 0.0), strain=0.0):
     """Dense 6N x 6N R_nf (translational rows/columns only)."""
     n = len(x)
     R = np.zeros((n, 6, n, 6))
-    i, k, d = pairs(x, body, L, r_cut)
+    i, k, d = pairs(x, body, L, r_cut, strain)
     if len(i):
         B = pair_blocks(d, a, eta, eps_min, rough)
         for m in range(len(i)):

@@ -56,7 +56,15 @@ def bead_vectors(quat, x_body, offsets):
     return np.einsum("iab,ib->ia", R[b], x_body)
 
 
-def wrap(X, L):
+def wrap(X, L, strain=0.0):
+    """Fold points into the primary cell [-L/2, L/2)^3.  With a sheared lattice (strain
+    gamma: the image across the +y face sits at +gamma L in x), y is folded first and every
+    crossing moves x by -gamma L per period before x and z are folded."""
+    X = np.array(X, dtype=float)
+    if strain:
+        ny = np.floor((X[..., 1] + L / 2) / L)
+        X[..., 1] -= ny * L
+        X[..., 0] -= ny * strain * L
     return (X + L / 2) % L - L / 2
 
 

@@ -277,13 +277,17 @@ def default_xi(L, n_bead, r_cut_factor=6.5):
     return float(best[1])
 
 
-def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2048):
+def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2048, strain=0.0):
     """Dense 6N x 6N periodic FT-RPY mobility (row/col order: bead, then f/t).
 
-    Real space: all images n with |x_i - x_j + n L| < r_cut_factor / xi.
+    Real space: all images n with |x_i - x_j + A n| < r_cut_factor / xi.
     Wave space: all k != 0 with |k| < 2 r_cut_factor xi.  r_cut_factor = 6.5
     leaves truncation errors near 1e-14 relative (exp(-42) times the
     polynomial prefactors of the split).
+
+    The lattice is A n = (n_x L + n_y gamma L, n_y L, n_z L) for strain gamma (a cube at
+    gamma = 0); its reciprocal vectors are k = 2 pi A^-T m = (2 pi / L)(m_x, m_y - gamma m_x,
+    m_z) and the cell volume stays L^3.
     """
     x = np.asarray(x, dtype=float)
     n = len(x)
@@ -297,10 +301,11 @@ def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2
     nmax = int(math.ceil(rc / L)) + 1
     d0 = x[:, None, :] - x[None, :, :]
     rng = range(-nmax, nmax + 1)
-    for nx in rng:
+    mx = nmax + int(math.ceil(abs(strain) * nmax))
+    for nx in range(-mx, mx + 1):
         for ny in rng:
             for nz in rng:
-                d = d0 + L * np.array([nx, ny, nz], dtype=float)
+                d = d0 + L * np.array([nx + strain * ny, ny, nz], dtype=float)
                 r = np.linalg.norm(d, axis=-1)
                 mask = (r < rc) & (r > 0)
                 if not mask.any():
@@ -315,7 +320,7 @@ def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2
     M = M.transpose(0, 2, 1, 3).reshape(6 * n, 6 * n)
 
     # ---- wave space (half space of k; k and -k combined) --------------------
-    kv, k2 = wave_vectors(L, 2 * r_cut_factor * xi)
+    kv, k2 = wave_vectors(L, 2 * r_cut_factor * xi, strain)
     u = k2 / (4 * xi * xi)
     hb = (1 + u + 2 * u * u) * np.exp(-u)
     Mt, Mr, Mrt = wave_sum(x, L, kv, (1 - a * a * k2 / 3) * hb / k2, 0.25 * hb, hb / np.sqrt(k2),
@@ -324,13 +329,18 @@ def periodic_mobility(x, L, a=1.0, eta=1.0, xi=None, r_cut_factor=6.5, k_chunk=2
 
 
 
-def wave_vectors(L, kc):
-    """Half space of k = 2 pi n / L, 0 < |k| < kc (one of each +-k pair)."""
+def wave_vectors(L, kc, strain=0.0):
+    """Half space of the reciprocal lattice k = (2 pi / L)(m_x, m_y - gamma m_x, m_z),
+    0 < |k| < kc (one of each +-k pair)."""
     m = int(math.ceil(kc * L / (2 * math.pi)))
     g = np.arange(-m, m + 1)
-    ks = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    my = m + int(math.ceil(abs(strain) * m))
+    gy = np.arange(-my, my + 1)
+    ks = np.stack(np.meshgrid(g, gy, g, indexing="ij"), -1).reshape(-1, 3)
     pos = (ks[:, 0] > 0) | ((ks[:, 0] == 0) & ((ks[:, 1] > 0) | ((ks[:, 1] == 0) & (ks[:, 2] > 0))))
-    kv = (2 * math.pi / L) * ks[pos].astype(float)
+    ms = ks[pos].astype(float)
+    ms[:, 1] -= strain * ms[:, 0]
+    kv = (2 * math.pi / L) * ms
     k2 = np.einsum("ij,ij->i", kv, kv)
     keep = k2 < kc * kc
     return kv[keep], k2[keep]

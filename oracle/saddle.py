@@ -49,17 +49,17 @@ class Assembled:
 
 
 def assemble(L, a, eta, offsets, x_body, com, quat, force, grad_u, r_lub=0.0,
-             eps_min=1e-3, xi=None, u_brown=None, f_brown_nf=None, M=None, rough=(0.0, 0.0)):
+             eps_min=1e-3, xi=None, u_brown=None, f_brown_nf=None, M=None, rough=(0.0, 0.0), strain=0.0):
     offsets = np.asarray(offsets)
     nb, na = int(offsets[-1]), len(offsets) - 1
     xb = rigid.centre_bodies(x_body, offsets)
-    X = rigid.wrap(np.asarray(com, dtype=float), L)
+    X = rigid.wrap(np.asarray(com, dtype=float), L, strain)
     r = rigid.bead_vectors(quat, xb, offsets)
     body = rigid.body_index(offsets)
     x = X[body] + r
     if M is None:
-        M = rpy.periodic_mobility(x, L, a, eta, xi=xi)
-    Rnf = lub.resistance_matrix(x, body, L, a, eta, r_lub, eps_min, rough)
+        M = rpy.periodic_mobility(x, L, a, eta, xi=xi, strain=strain)
+    Rnf = lub.resistance_matrix(x, body, L, a, eta, r_lub, eps_min, rough, strain)
     Sig = rigid.sigma_matrix(r, offsets)
     Ragg = Sig @ Rnf @ Sig.T
     E, W = rigid.strain_and_spin(grad_u)
@@ -191,11 +191,12 @@ def gmres(K, b, Pinv=None, tol=1e-10, restart=50, maxit=2000):
 
 
 def solve(L, a, eta, offsets, x_body, com, quat, force, grad_u, r_lub=0.0, eps_min=1e-3,
-          xi=None, u_brown=None, f_brown_nf=None, rough=(0.0, 0.0)):
+          xi=None, u_brown=None, f_brown_nf=None, rough=(0.0, 0.0), strain=0.0):
     """Aggregate velocities U (N, 6) = V + U_inf, bead forces F (Nb, 6), residual;
-    rough = (alpha, h0) adds the tangential roughness correction to lubrication."""
+    rough = (alpha, h0) adds the tangential roughness correction to lubrication; strain is
+    that of a sheared periodic lattice."""
     A = assemble(L, a, eta, offsets, x_body, com, quat, force, grad_u, r_lub, eps_min, xi,
-                 u_brown, f_brown_nf, rough=rough)
+                 u_brown, f_brown_nf, rough=rough, strain=strain)
     F, V = solve_schur(A)
     na = len(offsets) - 1
     U = V.reshape(na, 6) + A.Uinf
