@@ -176,6 +176,26 @@ fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double
 /* The conservative bead forces at the current positions (3 per bead, host array). */
 fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
 
+/* Sheared periodic lattice (Lees-Edwards), the boundary of long steady-shear runs
+ * (Section 4.3).  At strain gamma the lattice vectors are (L, 0, 0), (gamma L, L, 0),
+ * (0, 0, L): the image of a point across the +y face sits gamma L further along x.  Every
+ * step advances gamma by G_xy dt (flow u_x = G_xy y) and keeps it in [-1/2, 1/2), the lattice
+ * repeating with period 1; centroids crossing a y face move by -+gamma L along x.  The
+ * mobility's Ewald sums run on this lattice (real-space images, and wave vectors
+ * (2 pi / L)(m_x, m_y - gamma m_x, m_z) on a grid of sheared coordinates, sized
+ * sqrt(5)/2 finer than the cube's so that its spectral cutoff holds at any strain), and
+ * lubrication, pair forces and overlap checks take the nearest image on it.  Switch it on
+ * after fsd_init_box and before fsd_init_aggregates (FSD_ESTATE after); the strain may be
+ * reset at any time while on.  Requires a velocity gradient with G_xy as its only non-zero
+ * entry (FSD_EINVAL otherwise, also from a later fsd_set_shear) and kT = 0 (Brownian motion
+ * on this lattice is not built).  Systems on it run through fsd_solve and fsd_step (not
+ * the batch calls, which refuse them at admission), without captured graphs.  enable 0
+ * returns to the cube. */
+fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain);
+
+/* The current strain gamma in [-1/2, 1/2) (0 on the cube). */
+fsd_status fsd_get_strain(const fsd_system* s, double* strain);
+
 /* Surface roughness of lubrication (Section 4.2, Eq. `tan_fric`): for inter-body pairs with
  * gap h = r - 2a below the asperity height h0, the tangential (sliding) resistance function Y
  * gains alpha (a/h0)(h0/h - 3h/h0 + 2h^2/h0^2), which diverges as alpha a / h at contact and

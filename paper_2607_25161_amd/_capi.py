@@ -97,6 +97,8 @@ _sig("fsd_get_timers", C.c_int, _SYS, _D, C.POINTER(C.c_longlong), _D)
 _sig("fsd_set_pair_forces", C.c_int, _SYS, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double)
 _sig("fsd_get_pair_forces", C.c_int, _SYS, _D)
 _sig("fsd_set_roughness", C.c_int, _SYS, C.c_double, C.c_double)
+_sig("fsd_set_lees_edwards", C.c_int, _SYS, C.c_int, C.c_double)
+_sig("fsd_get_strain", C.c_int, _SYS, _D)
 _sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
@@ -314,6 +316,16 @@ class System:
         out = np.zeros(3 * self.n_bead)
         self._check(lib.fsd_get_pair_forces(self._h, _dptr(out)), "fsd_get_pair_forces")
         return out.reshape(-1, 3)
+
+    def set_lees_edwards(self, enable=True, strain=0.0):
+        """Sheared periodic lattice of the given strain (before init_aggregates to switch
+        on; the strain may be reset later)."""
+        self._check(lib.fsd_set_lees_edwards(self._h, int(bool(enable)), float(strain)), "fsd_set_lees_edwards")
+
+    def strain(self):
+        out = C.c_double(0.0)
+        self._check(lib.fsd_get_strain(self._h, C.byref(out)), "fsd_get_strain")
+        return out.value
 
     def set_roughness(self, alpha=0.0, h0=0.0):
         """Tangential roughness of lubrication: strength alpha below the asperity height h0

@@ -61,6 +61,7 @@ struct WaveParams {
   double a, eta;    // bead radius and viscosity
   double scale;     // h^6 / V * (normalisation of the two Gaussians)^2
   int brownian;     // 1: the z pass applies the square-root multiplier to grid noise
+  double gam;       // strain of the sheared lattice (0: cube); see launch_bead_positions
 };
 
 // Constants of the real-space part.
@@ -70,16 +71,24 @@ struct RealParams {
   double inv_ht;    // 1 / table spacing
   int ntab;         // table nodes covering [0, r_cut] (plus 3 guard nodes)
   double self_t, self_r;
+  double gam;       // strain of the sheared lattice (0: cube)
 };
 
 // ---- geometry (k_geometry.hip) ----------------------------------------------------------
+// Sheared lattice (Lees-Edwards) of strain gam: lattice vectors (L, 0, 0), (gam L, L, 0),
+// (0, 0, L).  Bead positions pos4 are kept in sheared coordinates s = (x - gam y, y, z),
+// each folded into [0, L); a pair's Cartesian separation is then
+// (ds_x + gam ds_y, ds_y, ds_z) with ds the sheared difference plus the image shift n L.
+// gam = 0 is the cube.
 void launch_bead_positions(int nb, int na, const int* body, const double* xbody, const double* com,
-                           const double* quat, double L, double* r4, double* pos4, hipStream_t st);
-void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat,
+                           const double* quat, double L, double gam, double* r4, double* pos4, hipStream_t st);
+// centroids folded into [-L/2, L/2)^3 of the lattice of strain gam (crossing a y face moves x
+// by -+gam L)
+void launch_integrate(int na, const double* U, double dt, double L, double gam, double* com, double* quat,
                       hipStream_t st);
 // com = wrap(com0 + h dq_t), quat = r(h dq_r) (x) quat0 (exact rotation), 6 dq per aggregate
 void launch_displace(int na, const double* com0, const double* quat0, const double* dq, double h, double L,
-                     double* com, double* quat, hipStream_t st);
+                     double gam, double* com, double* quat, hipStream_t st);
 
 // Neighbour lists in CSR form.  Column entries pack the bead index (22 bits)
 // and the periodic image shift (3 x 3 bits, offset by 3).
@@ -89,14 +98,14 @@ void neighbor_work_destroy(NeighborWork* w);
 // Two phases: neighbors_count launches per-row counts and the scan into rowptr
 // and copies the total to pinned memory (read it with neighbors_total once the
 // stream has drained); neighbors_fill then writes the columns.
-hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
+hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4, const int* body, double L, double gam,
                            double cutoff, bool exclude_same_body, int* rowptr, hipStream_t st);
 long long neighbors_total(const NeighborWork* w);
-hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4, const int* body, double L,
+hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4, const int* body, double L, double gam,
                           double cutoff, bool exclude_same_body, const int* rowptr, uint32_t* col,
                           hipStream_t st);
 
-void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col,
+void launch_lub_setup(int nb, const double* pos4, double L, double gam, const int* rowptr, const uint32_t* col,
                       double a, double eta, double eps_min, double r_pre, double rough_alpha,
                       double rough_h0, double* coef, double* rdiag, int* overlap_flag, hipStream_t st);
 void launch_precond_factor(int na, const int* offsets, const double* r4, const double* rdiag,
@@ -112,6 +121,16 @@ void launch_real_sum(int nb, const double* pos4, const double* lam, const int* r
 template <typename R>
 void launch_spread(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
                    hipStream_t st, const int* skip = nullptr);
+// Spreading and interpolation on the grid of a sheared lattice (wp.gam): grid point
+// (i, j, k) sits at sheared coordinates (i, j, k) h, and each grid row j takes the P x-points
+// around its own centre p_x - gam (j h - p_y).  Spreading scatters with atomic adds into a
+// zeroed grid; interpolation adds into out as launch_interp does (with V: + Sigma^T V).
+template <typename R>
+void launch_spread_sheared(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
+                           hipStream_t st, const int* skip = nullptr);
+template <typename R>
+void launch_interp_sheared(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
+                           hipStream_t st, const int* skip, const int* body, const double* r4, const double* V);
 // pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
@@ -175,13 +194,14 @@ const int* spread_plan_order(const SpreadPlan* sp);
 // screened double layer, for pairs closer than r_cut, over the real-space list.
 struct PairForceParams {
   double kn, hamaker, Z, kappa, hc, r_cut, a, L;
+  double gam;  // strain of the sheared lattice
 };
 // fe[3 i] = (accumulate ? fe[3 i] : 0) - f_i  (the right-hand side takes -F_P through Sigma)
 void launch_pair_forces(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
                         const PairForceParams& pf, double* fe, int accumulate, hipStream_t st);
 // *flag |= 1 when beads of different bodies in the real-space list are closer than 1.5 a
 void launch_overlap_check(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
-                          double L, double a, int* flag, hipStream_t st);
+                          double L, double gam, double a, int* flag, hipStream_t st);
 void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const double* coef,
                       const double* wt, double* f, hipStream_t st, const int* skip = nullptr);
 // fused: y2 = Sigma (lambda - R_nf Sigma^T V) with lubrication evaluated on the fly

@@ -313,6 +313,9 @@ struct fsd_system {
          *d_quat0 = nullptr;
   PairForceParams pf{};
   double rough_alpha = 0.0, rough_h0 = 0.0;  // tangential roughness of lubrication (h0 = 0: off)
+  bool le = false;      // sheared periodic lattice (Lees-Edwards)
+  double strain = 0.0;  // its strain gamma, kept in [-1/2, 1/2)
+  double gam() const { return le ? strain : 0.0; }
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -490,7 +493,7 @@ GraphEntry* graph_for(fsd_system* s, const fsd_system::GraphKey& key, const std:
 
 // run body captured (cached) or eagerly
 GraphEntry* run_body(fsd_system* s, const fsd_system::GraphKey& key, const std::function<void()>& body) {
-  if (!s->use_graphs || s->timing) {
+  if (!s->use_graphs || s->timing || s->le) {  // the strain changes every step: eager launches
     body();
     return nullptr;
   }
@@ -515,7 +518,10 @@ void choose_parameters(fsd_system* s) {
   const double lnt = std::sqrt(-std::log(tol));
   const double rc = lnt / xi;
   const double kc = 2.0 * lnt * xi + 1.0 / a;
-  int N = p.grid > 0 ? p.grid : next_smooth(int(std::ceil(kc * L / M_PI)));
+  // on a sheared lattice the grid's modes reach |k| >= (N pi / L) / sqrt(1 + gamma^2) in every
+  // direction, so the grid grows by sqrt(5)/2 (|gamma| <= 1/2) to keep the cutoff k_c
+  const double le_margin = s->le ? std::sqrt(1.25) : 1.0;
+  int N = p.grid > 0 ? p.grid : next_smooth(int(std::ceil(kc * L / M_PI * le_margin)));
   if (N > kMaxGrid) throw ApiError(FSD_EINVAL, "spectral grid above 256^3; raise xi or lower the tolerance");
   if (!make_plan(N, s->plan))
     throw ApiError(FSD_EINVAL, "grid size must be a product of powers of 2 and 3");
@@ -619,16 +625,20 @@ void ensure_cols(fsd_system* s, uint32_t*& col, long long& cap, long long need) 
 // prepare_end (after the stream drained) fills the lists, lubrication coefficients,
 // preconditioner factors and the spreading plan.
 void prepare_begin(fsd_system* s) {
-  launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->d_r4, s->d_pos4, s->st);
-  HIPCHK(neighbors_count(s->nw, s->nb, s->d_pos4, s->d_body, s->L, s->rp.r_cut, false, s->d_nrow, s->st));
+  const double g = s->gam();
+  s->rp.gam = s->wp.gam = s->pf.gam = g;
+  launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, g, s->d_r4, s->d_pos4,
+                        s->st);
+  HIPCHK(neighbors_count(s->nw, s->nb, s->d_pos4, s->d_body, s->L, g, s->rp.r_cut, false, s->d_nrow, s->st));
   if (s->p.r_lub > 0)
-    HIPCHK(neighbors_count(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->p.r_lub, true, s->d_lrow, s->st));
+    HIPCHK(neighbors_count(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, g, s->p.r_lub, true, s->d_lrow, s->st));
 }
 
 void prepare_end(fsd_system* s) {
   s->nnz = neighbors_total(s->nw);
   ensure_cols(s, s->d_ncol, s->ncap, s->nnz);
-  HIPCHK(neighbors_fill(s->nw, s->nb, s->d_pos4, s->d_body, s->L, s->rp.r_cut, false, s->d_nrow, s->d_ncol, s->st));
+  HIPCHK(
+      neighbors_fill(s->nw, s->nb, s->d_pos4, s->d_body, s->L, s->gam(), s->rp.r_cut, false, s->d_nrow, s->d_ncol, s->st));
   launch_zero(s->d_flags, 2 * sizeof(int), s->st);
   if (s->p.r_lub > 0) {
     s->nlub = neighbors_total(s->nwl);
@@ -642,13 +652,15 @@ void prepare_end(fsd_system* s) {
       s->d_lcoef = dalloc<double>(s->owned, size_t(5 * s->lcap));
       s->lcoef_cap = s->lcap;
     }
-    HIPCHK(neighbors_fill(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->p.r_lub, true, s->d_lrow, s->d_lcol, s->st));
-    launch_lub_setup(s->nb, s->d_pos4, s->L, s->d_lrow, s->d_lcol, s->p.radius, s->p.eta, s->p.lub_eps_min,
+    HIPCHK(neighbors_fill(s->nwl, s->nb, s->d_pos4, s->d_body, s->L, s->gam(), s->p.r_lub, true, s->d_lrow, s->d_lcol,
+                          s->st));
+    launch_lub_setup(s->nb, s->d_pos4, s->L, s->gam(), s->d_lrow, s->d_lcol, s->p.radius, s->p.eta, s->p.lub_eps_min,
                      s->p.r_precond, s->rough_alpha, s->rough_h0, s->d_lcoef, s->d_rdiag, s->d_flags, s->st);
   } else {
     launch_zero(s->d_rdiag, sizeof(double) * 6 * s->nb, s->st);
     s->nlub = 0;
-    launch_overlap_check(s->nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->L, s->p.radius, s->d_flags, s->st);
+    launch_overlap_check(s->nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->L, s->gam(), s->p.radius, s->d_flags,
+                         s->st);
   }
   launch_precond_factor(s->na, s->d_offsets, s->d_r4, s->d_rdiag, s->drag_t, s->drag_r, s->d_lu, s->d_piv,
                         s->d_flags + 1, s->st);
@@ -726,7 +738,11 @@ void mob_real(fsd_system* s, const double* lam, double* out, hipStream_t rs, con
 template <typename R>
 void mob_spread(fsd_system* s, const double* lam, const int* skip) {
   R* grid = static_cast<R*>(s->d_grid);
-  if (s->spread) {
+  if (s->le) {
+    const size_t N = s->wp.n;
+    launch_zero(grid, sizeof(R) * 6 * N * N * N, s->st);
+    launch_spread_sheared<R>(s->nb, s->d_pos4, lam, s->wp, grid, s->st, skip);
+  } else if (s->spread) {
     launch_spread_gather<R>(s->spread, lam, s->wp, grid, s->st, skip);
   } else {
     const size_t N = s->wp.n;
@@ -742,6 +758,11 @@ void mob_fft(fsd_system* s, int stage, const int* skip) {
 
 template <typename R>
 void mob_interp(fsd_system* s, double* out, const int* skip, const double* Vr) {
+  if (s->le) {
+    launch_interp_sheared<R>(s->nb, s->d_pos4, static_cast<const R*>(s->d_grid), s->wp, out, s->st, skip, s->d_body,
+                             s->d_r4, Vr);
+    return;
+  }
   launch_interp<R>(s->nb, s->d_pos4, static_cast<const R*>(s->d_grid), s->wp, out, s->st, skip, s->d_body, s->d_r4, Vr,
                    s->spread);
 }
@@ -822,7 +843,7 @@ void mob_first(fsd_system* s, const double* x, double* y, const int* skip) {
 template <typename R>
 void apply_saddle(fsd_system* s, const double* x, double* y, const int* skip = nullptr) {
   const size_t nb6 = 6 * size_t(s->nb);
-  if (spread_fuses(s->spread)) {
+  if (spread_fuses(s->spread) && !s->le) {
     const double full = grid_bytes<R>(s), beads = 80.0 * s->nb;
     {
       Timed t(s, FSD_TIMER_SPREAD, full + beads + real_bytes(s) + rigid_bytes(s));
@@ -1001,6 +1022,7 @@ int lanczos_sqrt(fsd_system* s, size_t n, Apply&& apply, const double* z, double
 // u_B = sqrt(2 kT / dt) (M_w^{1/2} psi_w + M_r^{1/2} psi_r) into d_ub (6 per bead) and
 // F_B = sqrt(2 kT / dt) R_nf^{1/2} psi_nf into d_fb (3 per bead, translational)
 void brownian_terms(fsd_system* s) {
+  if (s->le) throw ApiError(FSD_EINVAL, "Brownian motion on the sheared lattice is not built");
   ensure_brownian(s);
   const size_t nb = s->nb;
   const double amp = std::sqrt(2.0 * s->p.kT / s->bdt);
@@ -1323,7 +1345,8 @@ void rfd_drift(fsd_system* s, const double* dq_host) {
   const double c = s->p.kT / eps;
   fsd_status r = FSD_OK;
   for (int sign = 1; sign >= -1 && r == FSD_OK; sign -= 2) {
-    launch_displace(int(na), s->d_com0, s->d_quat0, s->d_dq, 0.5 * sign * eps, s->L, s->d_com, s->d_quat, s->st);
+    launch_displace(int(na), s->d_com0, s->d_quat0, s->d_dq, 0.5 * sign * eps, s->L, s->gam(), s->d_com, s->d_quat,
+                    s->st);
     s->prepared = false;
     r = solve_current(s, nullptr, 1);
     if (sign > 0) HIPCHK(hipMemcpyAsync(s->d_vplus, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
@@ -1351,7 +1374,7 @@ void fixman_drift(fsd_system* s, double dt) {
   fsd_status r = solve_current(s, nullptr, 2);  // U0 (positions unchanged: still prepared)
   if (r == FSD_OK) {
     HIPCHK(hipMemcpyAsync(s->d_udrift, s->d_U, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
-    launch_integrate(int(na), s->d_U, dt / m, s->L, s->d_com, s->d_quat, s->st);
+    launch_integrate(int(na), s->d_U, dt / m, s->L, s->gam(), s->d_com, s->d_quat, s->st);
     s->prepared = false;
     r = solve_current(s, nullptr, 2);  // U'
   }
@@ -1378,7 +1401,7 @@ bool replay_one(fsd_system* s, int cls) {
   switch (cls) {
     case FSD_TIMER_REAL: mob_real<R>(s, s->d_z, s->d_t, s->st, nullptr); return true;
     case FSD_TIMER_SPREAD:  // the kernel a solve runs for this class
-      if (spread_fuses(s->spread))
+      if (spread_fuses(s->spread) && !s->le)
         mob_first<R>(s, s->d_z, s->d_t, nullptr);
       else
         mob_spread<R>(s, s->d_z, nullptr);
@@ -1497,9 +1520,16 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     const double Rc[3] = {(1 - 2 * (y * y + z * z)) * c[0] + 2 * (x * y - w * z) * c[1] + 2 * (x * z + w * y) * c[2],
                           2 * (x * y + w * z) * c[0] + (1 - 2 * (x * x + z * z)) * c[1] + 2 * (y * z - w * x) * c[2],
                           2 * (x * z - w * y) * c[0] + 2 * (y * z + w * x) * c[1] + (1 - 2 * (x * x + y * y)) * c[2]};
+    double v3[3];
     for (int d = 0; d < 3; ++d) {
       if (!std::isfinite(com[3 * j + d])) return fail(s, FSD_EINVAL, "non-finite centroid");
-      double v = com[3 * j + d] + Rc[d];
+      v3[d] = com[3 * j + d] + Rc[d];
+    }
+    const double ny = std::floor((v3[1] + 0.5 * L) / L);  // y first on a sheared lattice
+    v3[1] -= ny * L;
+    v3[0] -= ny * s->gam() * L;
+    for (int d = 0; d < 3; ++d) {
+      double v = v3[d];
       v -= L * std::floor((v + 0.5 * L) / L);
       if (v >= 0.5 * L) v -= L;
       X[3 * j + d] = v;
@@ -1644,6 +1674,9 @@ fsd_status fsd_set_shear(fsd_system* s, const double g[9]) {
     if (!std::isfinite(g[i])) return fail(s, FSD_EINVAL, "non-finite velocity gradient");
   if (std::fabs(g[0] + g[4] + g[8]) > 1e-12 * (1 + std::fabs(g[0]) + std::fabs(g[4]) + std::fabs(g[8])))
     return fail(s, FSD_EINVAL, "velocity gradient must be traceless");
+  if (s->le)
+    for (int i = 0; i < 9; ++i)
+      if (i != 1 && g[i] != 0) return fail(s, FSD_EINVAL, "the sheared lattice takes simple shear u_x = G_xy y only");
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
       s->G[3 * a + b] = g[3 * a + b];
@@ -1701,7 +1734,11 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
       if (r != FSD_OK) return r;
       if (fixman) fixman_drift(s, dt);
       if (rfd || fixman) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
-      launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+      if (s->le) {  // the lattice shears with the flow u_x = G_xy y; fold into the new lattice
+        const double g = s->strain + s->G[1] * dt;
+        s->strain = g - std::floor(g + 0.5);
+      }
+      launch_integrate(s->na, s->d_U, dt, s->L, s->gam(), s->d_com, s->d_quat, s->st);
       s->prepared = false;
       ++s->bstep;
     }
@@ -1718,8 +1755,8 @@ fsd_status fsd_get_state(const fsd_system* cs, double* com, double* quat, double
     if (com) HIPCHK(hipMemcpyAsync(com, s->d_com, sizeof(double) * 3 * s->na, hipMemcpyDeviceToHost, s->st));
     if (quat) HIPCHK(hipMemcpyAsync(quat, s->d_quat, sizeof(double) * 4 * s->na, hipMemcpyDeviceToHost, s->st));
     if (x_bead) {
-      launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->d_r4, s->d_pos4,
-                            s->st);
+      launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, s->gam(), s->d_r4,
+                            s->d_pos4, s->st);
       std::vector<double> r4(4 * size_t(s->nb)), X(3 * size_t(s->na));
       HIPCHK(hipMemcpyAsync(r4.data(), s->d_r4, sizeof(double) * 4 * s->nb, hipMemcpyDeviceToHost, s->st));
       HIPCHK(hipMemcpyAsync(X.data(), s->d_com, sizeof(double) * 3 * s->na, hipMemcpyDeviceToHost, s->st));
@@ -1962,7 +1999,7 @@ fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double
   if (Z != 0 && !(kappa > 0)) return fail(s, FSD_EINVAL, "the double layer needs kappa > 0");
   if (!(r_cut >= 2 * a) || r_cut > s->rp.r_cut)
     return fail(s, FSD_EINVAL, "r_cut must lie in [2a, the real-space cutoff]");
-  s->pf = PairForceParams{k_n, hamaker, Z, kappa, h_c, r_cut, a, s->L};
+  s->pf = PairForceParams{k_n, hamaker, Z, kappa, h_c, r_cut, a, s->L, s->gam()};
   s->pair_forces = true;
   return FSD_OK;
 }
@@ -1983,6 +2020,32 @@ fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0) {
     s->rough_h0 = rh;
     s->prepared = false;  // the lubrication coefficients and the preconditioner change
   }
+  return FSD_OK;
+}
+
+fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain) {
+  if (!s) return FSD_EINVAL;
+  if (!std::isfinite(strain)) return fail(s, FSD_EINVAL, "non-finite strain");
+  if (enable) {
+    if (!s->le && s->have_agg) return fail(s, FSD_ESTATE, "switch the sheared lattice on before fsd_init_aggregates");
+    if (s->p.kT > 0) return fail(s, FSD_EINVAL, "Brownian motion on the sheared lattice is not built");
+    for (int i = 0; i < 9; ++i)
+      if (i != 1 && s->G[i] != 0) return fail(s, FSD_EINVAL, "the sheared lattice takes simple shear u_x = G_xy y only");
+  }
+  const double g = strain - std::floor(strain + 0.5);  // the lattice repeats with period 1
+  if (bool(enable) != s->le || (enable && g != s->strain)) {
+    // centroids need no refolding: bead positions are folded into the lattice at every
+    // preparation, and the next step folds the centroids
+    s->le = enable != 0;
+    s->strain = s->le ? g : 0.0;
+    s->prepared = false;
+  }
+  return FSD_OK;
+}
+
+fsd_status fsd_get_strain(const fsd_system* s, double* strain) {
+  if (!s || !strain) return FSD_EINVAL;
+  *strain = s->le ? s->strain : 0.0;
   return FSD_OK;
 }
 
@@ -2230,7 +2293,7 @@ fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
         --remaining;
         if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
         if (integrate && s->sv.status == FSD_OK) {
-          launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+          launch_integrate(s->na, s->d_U, dt, s->L, 0.0, s->d_com, s->d_quat, s->st);
           s->prepared = false;
           ++s->bstep;
         }
@@ -2484,7 +2547,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     fsd_system* s = act[k];
     if (integrate && s->sv.status == FSD_OK) {
       fsd_status r = guarded(s, [&]() -> fsd_status {
-        launch_integrate(s->na, s->d_U, dt, s->L, s->d_com, s->d_quat, s->st);
+        launch_integrate(s->na, s->d_U, dt, s->L, 0.0, s->d_com, s->d_quat, s->st);
         s->prepared = false;
         ++s->bstep;
         return FSD_OK;
@@ -2534,6 +2597,7 @@ fsd_status fsd_batch_admit(fsd_batch* b, fsd_system* s, int* slot) {
   if (!s->have_agg) return FSD_ESTATE;
   for (auto* q : b->slot)
     if (q == s) return FSD_EINVAL;
+  if (s->le) return fail(s, FSD_EINVAL, "systems on a sheared lattice run through fsd_step and fsd_solve only");
   const size_t need = system_bytes(s);
   if (b->used + need > b->budget) {
     b->err = "memory budget exhausted";

@@ -22,42 +22,55 @@ __device__ inline double wrap01(double p, double L) {
   double q = p - L * floor(p / L);
   return (q >= L) ? q - L : q;
 }
+
+// fold a centroid into [-L/2, L/2)^3 of the lattice of strain gam: y first, each period of
+// y moving x by gam L, then x and z
+__device__ inline void fold_centroid(double* c, double L, double gam) {
+  const double ny = floor((c[1] + 0.5 * L) / L);
+  c[1] -= ny * L;
+  c[0] -= ny * gam * L;
+  for (int d = 0; d < 3; ++d) {
+    double x = c[d];
+    x -= L * floor((x + 0.5 * L) / L);
+    if (x >= 0.5 * L) x -= L;
+    c[d] = x;
+  }
+}
 }  // namespace
 
 // Eq. `EM3`: x_i = X_j + R(q_j) x_body,i.  r4 holds the body vector R x_body,
-// pos4 the bead centre wrapped into [0, L)^3.
+// pos4 the bead centre in sheared coordinates (x - gam y, y, z), each folded into [0, L)
+// (the Cartesian position itself when gam = 0).
 __global__ void k_bead_positions(int nb, const int* __restrict__ body, const double* __restrict__ xbody,
                                  const double* __restrict__ com, const double* __restrict__ quat, double L,
-                                 double4* __restrict__ r4, double4* __restrict__ pos4) {
+                                 double gam, double4* __restrict__ r4, double4* __restrict__ pos4) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const int j = body[i];
   double r[3];
   quat_rotate(quat + 4 * j, xbody + 3 * i, r);
   r4[i] = make_double4(r[0], r[1], r[2], 0.0);
-  pos4[i] = make_double4(wrap01(com[3 * j] + r[0], L), wrap01(com[3 * j + 1] + r[1], L),
-                         wrap01(com[3 * j + 2] + r[2], L), 0.0);
+  const double x = com[3 * j] + r[0], y = com[3 * j + 1] + r[1], z = com[3 * j + 2] + r[2];
+  pos4[i] = make_double4(wrap01(x - gam * y, L), wrap01(y, L), wrap01(z, L), 0.0);
 }
 
 void launch_bead_positions(int nb, int na, const int* body, const double* xbody, const double* com,
-                           const double* quat, double L, double* r4, double* pos4, hipStream_t st) {
+                           const double* quat, double L, double gam, double* r4, double* pos4, hipStream_t st) {
   (void)na;
-  k_bead_positions<<<nblocks(nb), kThreads, 0, st>>>(nb, body, xbody, com, quat, L, (double4*)r4,
+  k_bead_positions<<<nblocks(nb), kThreads, 0, st>>>(nb, body, xbody, com, quat, L, gam, (double4*)r4,
                                                      (double4*)pos4);
 }
 
-// Eqs. `EM1` and `EM2`: X += U dt; q += (dt/2) (0, W) (x) q, normalised; X wrapped
-// into [-L/2, L/2)^3.
-__global__ void k_integrate(int na, const double* __restrict__ U, double dt, double L, double* __restrict__ com,
-                            double* __restrict__ quat) {
+// Eqs. `EM1` and `EM2`: X += U dt; q += (dt/2) (0, W) (x) q, normalised; X folded
+// into [-L/2, L/2)^3 of the lattice of strain gam.
+__global__ void k_integrate(int na, const double* __restrict__ U, double dt, double L, double gam,
+                            double* __restrict__ com, double* __restrict__ quat) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= na) return;
-  for (int c = 0; c < 3; ++c) {
-    double x = com[3 * j + c] + U[6 * j + c] * dt;
-    x -= L * floor((x + 0.5 * L) / L);
-    if (x >= 0.5 * L) x -= L;
-    com[3 * j + c] = x;
-  }
+  double c3[3];
+  for (int c = 0; c < 3; ++c) c3[c] = com[3 * j + c] + U[6 * j + c] * dt;
+  fold_centroid(c3, L, gam);
+  for (int c = 0; c < 3; ++c) com[3 * j + c] = c3[c];
   const double ox = U[6 * j + 3], oy = U[6 * j + 4], oz = U[6 * j + 5];
   double w = quat[4 * j], x = quat[4 * j + 1], y = quat[4 * j + 2], z = quat[4 * j + 3];
   // (0, o) (x) (w, v) = (-o.v, w o + o x v)
@@ -82,16 +95,14 @@ __global__ void k_integrate(int na, const double* __restrict__ U, double dt, dou
 // orientation r(h dq_r) (x) quat0, with the exact rotation quaternion
 // r(phi) = (cos(|phi|/2), sin(|phi|/2) phi / |phi|).
 __global__ void k_displace(int na, const double* __restrict__ com0, const double* __restrict__ quat0,
-                           const double* __restrict__ dq, double h, double L, double* __restrict__ com,
+                           const double* __restrict__ dq, double h, double L, double gam, double* __restrict__ com,
                            double* __restrict__ quat) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= na) return;
-  for (int c = 0; c < 3; ++c) {
-    double x = com0[3 * j + c] + h * dq[6 * j + c];
-    x -= L * floor((x + 0.5 * L) / L);
-    if (x >= 0.5 * L) x -= L;
-    com[3 * j + c] = x;
-  }
+  double c3[3];
+  for (int c = 0; c < 3; ++c) c3[c] = com0[3 * j + c] + h * dq[6 * j + c];
+  fold_centroid(c3, L, gam);
+  for (int c = 0; c < 3; ++c) com[3 * j + c] = c3[c];
   const double px = h * dq[6 * j + 3], py = h * dq[6 * j + 4], pz = h * dq[6 * j + 5];
   const double ang = sqrt(px * px + py * py + pz * pz);
   const double rw = cos(0.5 * ang), sc = ang > 0 ? sin(0.5 * ang) / ang : 0.0;
@@ -110,12 +121,13 @@ __global__ void k_displace(int na, const double* __restrict__ com0, const double
 }
 
 void launch_displace(int na, const double* com0, const double* quat0, const double* dq, double h, double L,
-                     double* com, double* quat, hipStream_t st) {
-  k_displace<<<nblocks(na), kThreads, 0, st>>>(na, com0, quat0, dq, h, L, com, quat);
+                     double gam, double* com, double* quat, hipStream_t st) {
+  k_displace<<<nblocks(na), kThreads, 0, st>>>(na, com0, quat0, dq, h, L, gam, com, quat);
 }
 
-void launch_integrate(int na, const double* U, double dt, double L, double* com, double* quat, hipStream_t st) {
-  k_integrate<<<nblocks(na), kThreads, 0, st>>>(na, U, dt, L, com, quat);
+void launch_integrate(int na, const double* U, double dt, double L, double gam, double* com, double* quat,
+                      hipStream_t st) {
+  k_integrate<<<nblocks(na), kThreads, 0, st>>>(na, U, dt, L, gam, com, quat);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -190,10 +202,13 @@ __global__ void k_cell_bounds(int nb, const int* __restrict__ keys, int* start, 
 }
 
 // One thread per bead scans the 27 surrounding cells (nc >= 3, so each cell is
-// visited once and the minimum image is unique).
+// visited once and the minimum image is unique).  Cells live in sheared coordinates; their
+// side covers the cutoff sphere's sheared extent r_c sqrt(1 + gam^2), and distances are
+// Cartesian.
 template <bool FILL>
 __global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int* __restrict__ body, double L,
-                             double cs, int nc, double rc2, int exclude_same_body, const int* __restrict__ start,
+                             double gam, double cs, int nc, double rc2, int exclude_same_body,
+                             const int* __restrict__ start,
                              const int* __restrict__ end, const int* __restrict__ sorted, int* counts,
                              const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,6 +234,7 @@ __global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int*
           ddx += sx * L;
           ddy += sy * L;
           ddz += sz * L;
+          ddx += gam * ddy;
           if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
             if (FILL) col[base + cnt] = pack_entry(j, int(sx), int(sy), int(sz));
             ++cnt;
@@ -234,7 +250,7 @@ __global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int*
 // the cutoff, including images of a bead itself.
 template <bool FILL>
 __global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int* __restrict__ body, double L,
-                              double rc2, int nmax, int exclude_same_body, int* counts,
+                              double gam, double rc2, int nmax, int exclude_same_body, int* counts,
                               const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
@@ -249,7 +265,8 @@ __global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int
       for (int sy = -nmax; sy <= nmax; ++sy)
         for (int sx = -nmax; sx <= nmax; ++sx) {
           if (j == i && sx == 0 && sy == 0 && sz == 0) continue;
-          const double ddx = p.x - q.x + sx * L, ddy = p.y - q.y + sy * L, ddz = p.z - q.z + sz * L;
+          const double ddy = p.y - q.y + sy * L, ddz = p.z - q.z + sz * L;
+          const double ddx = p.x - q.x + sx * L + gam * ddy;
           if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
             if (FILL) col[base + cnt] = pack_entry(j, sx, sy, sz);
             ++cnt;
@@ -261,11 +278,12 @@ __global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int
 
 // Count phase: per-bead pair counts, exclusive scan into rowptr, and an
 // asynchronous copy of the total into pinned memory (valid once the stream drains).
-hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
-                           bool exclude_same_body, int* rowptr, hipStream_t st) {
+hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double gam,
+                           double cutoff, bool exclude_same_body, int* rowptr, hipStream_t st) {
   const double4* pos = (const double4*)pos4v;
   const double rc2 = cutoff * cutoff;
-  int nc = int(L / cutoff);
+  const double reach = cutoff * sqrt(1.0 + gam * gam);  // sheared extent of the cutoff sphere
+  int nc = int(L / reach);
   if (nc > 1024) nc = 1024;
   w->nc = nc;
   hipError_t e;
@@ -291,12 +309,12 @@ hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const i
     if ((e = hipMemsetAsync(w->cell_start, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(w->cell_end, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
     k_cell_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, w->keys_out, w->cell_start, w->cell_end);
-    k_cell_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, cs, nc, rc2, exclude_same_body,
+    k_cell_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
                                                            w->cell_start, w->cell_end, w->vals_out, w->counts,
                                                            nullptr, nullptr);
   } else {
-    const int nmax = int(cutoff / L) + 1;
-    k_brute_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, rc2, nmax, exclude_same_body,
+    const int nmax = int(reach / L) + 1;
+    k_brute_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, rc2, nmax, exclude_same_body,
                                                             w->counts, nullptr, nullptr);
   }
   if ((e = hipMemsetAsync(w->counts + nb, 0, sizeof(int), st)) != hipSuccess) return e;
@@ -309,19 +327,19 @@ hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const i
 long long neighbors_total(const NeighborWork* w) { return *w->total; }
 
 // Fill phase (after the count phase has drained; col holds at least the total).
-hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double cutoff,
-                          bool exclude_same_body, const int* rowptr, uint32_t* col, hipStream_t st) {
+hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const int* body, double L, double gam,
+                          double cutoff, bool exclude_same_body, const int* rowptr, uint32_t* col, hipStream_t st) {
   const double4* pos = (const double4*)pos4v;
   const double rc2 = cutoff * cutoff;
   const int nc = w->nc;
   if (nc >= 3) {
     const double cs = L / nc;
-    k_cell_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, cs, nc, rc2, exclude_same_body,
+    k_cell_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
                                                           w->cell_start, w->cell_end, w->vals_out, nullptr, rowptr,
                                                           col);
   } else {
-    const int nmax = int(cutoff / L) + 1;
-    k_brute_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, rc2, nmax, exclude_same_body, nullptr,
+    const int nmax = int(cutoff * sqrt(1.0 + gam * gam) / L) + 1;
+    k_brute_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, rc2, nmax, exclude_same_body, nullptr,
                                                            rowptr, col);
   }
   return hipGetLastError();
@@ -335,7 +353,7 @@ hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const in
 // with h = eps a the regularised gap
 // ------------------------------------------------------------------------------------------
 
-__global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, const int* __restrict__ rowptr,
+__global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, double gam, const int* __restrict__ rowptr,
                             const uint32_t* __restrict__ col, double a, double eta, double eps_min, double r_pre,
                             double rough_alpha, double rough_h0, double* __restrict__ coef,
                             double* __restrict__ rdiag, int* overlap_flag) {
@@ -348,8 +366,8 @@ __global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, c
     const uint32_t c = col[e];
     const int j = int(c & 0x3FFFFFu);
     const double4 q = pos[j];
-    const double dx = p.x - q.x + (int((c >> 22) & 7u) - 3) * L;
     const double dy = p.y - q.y + (int((c >> 25) & 7u) - 3) * L;
+    const double dx = p.x - q.x + (int((c >> 22) & 7u) - 3) * L + gam * dy;
     const double dz = p.z - q.z + (int((c >> 28) & 7u) - 3) * L;
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (r < 1.5 * a) atomicOr(overlap_flag, 1);
@@ -381,10 +399,10 @@ __global__ void k_lub_setup(int nb, const double4* __restrict__ pos, double L, c
   for (int k = 0; k < 6; ++k) rdiag[6 * i + k] = d6[k];
 }
 
-void launch_lub_setup(int nb, const double* pos4, double L, const int* rowptr, const uint32_t* col, double a,
-                      double eta, double eps_min, double r_pre, double rough_alpha, double rough_h0, double* coef,
-                      double* rdiag, int* overlap_flag, hipStream_t st) {
-  k_lub_setup<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, L, rowptr, col, a, eta, eps_min, r_pre,
+void launch_lub_setup(int nb, const double* pos4, double L, double gam, const int* rowptr, const uint32_t* col,
+                      double a, double eta, double eps_min, double r_pre, double rough_alpha, double rough_h0,
+                      double* coef, double* rdiag, int* overlap_flag, hipStream_t st) {
+  k_lub_setup<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, L, gam, rowptr, col, a, eta, eps_min, r_pre,
                                                  rough_alpha, rough_h0, coef, rdiag, overlap_flag);
 }
 

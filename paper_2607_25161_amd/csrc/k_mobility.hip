@@ -97,8 +97,9 @@ __device__ __forceinline__ void real_sum_body(int nb, const double4* __restrict_
     const uint32_t c = col[e];
     const int j = int(c & 0x3FFFFFu);
     const double4 pj = pos[j];
-    const R dx = R(pi.x - pj.x + (int((c >> 22) & 7u) - 3) * rp.L);
-    const R dy = R(pi.y - pj.y + (int((c >> 25) & 7u) - 3) * rp.L);
+    const double dyd = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * rp.L;  // Cartesian from sheared
+    const R dx = R(pi.x - pj.x + (int((c >> 22) & 7u) - 3) * rp.L + rp.gam * dyd);
+    const R dy = R(dyd);
     const R dz = R(pi.z - pj.z + (int((c >> 28) & 7u) - 3) * rp.L);
     const R r = sqrt(dx * dx + dy * dy + dz * dz);
     const R ir = R(1) / r;
@@ -266,6 +267,144 @@ void launch_spread(int nb, const double* pos4, const double* lam, const WavePara
                    const int* skip) {
   const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
   launch_k(k_spread<R>, nblocks(nb, 4), kThreads, 0, st, nb, (const double4*)pos4, lam, wp, grid, cs, skip);
+}
+
+// ---- sheared lattice: one wavefront per bead, grid row j shifted along x -------------------
+namespace {
+// Weights of bead p in sheared coordinates: y and z as on the cube; for each of the P rows
+// ky the start sxr[ky] and P x-weights, centred at p_x - gam (y_m - p_y), y_m = (sy + ky) h.
+template <typename R>
+__device__ inline void sheared_weights(const double4& p, const WaveParams& wp, int lane, R* wyz, int* st, R* wxr,
+                                       int* sxr) {
+  const int P = wp.support;
+  const double h = wp.h;
+  const int sy = int(ceil(p.y / h - 0.5 * P)), sz = int(ceil(p.z / h - 0.5 * P));
+  if (lane < 2 * P) {
+    const int d = lane / P, k = lane % P;
+    const double xm = d == 0 ? (sy + k) * h - p.y : (sz + k) * h - p.z;
+    wyz[d * kMaxP + k] = R(exp(-wp.alpha * xm * xm));
+  }
+  if (lane == 0) {
+    st[0] = sy;
+    st[1] = sz;
+  }
+  for (int t = lane; t < P * P; t += 64) {
+    const int ky = t / P, kx = t - ky * P;
+    const double cx = p.x - wp.gam * ((sy + ky) * h - p.y);  // the row's centre along x
+    const int sx = int(ceil(cx / h - 0.5 * P));
+    const double xm = (sx + kx) * h - cx;
+    wxr[ky * kMaxP + kx] = R(exp(-wp.alpha * xm * xm));
+    if (kx == 0) sxr[ky] = sx;
+  }
+}
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_spread_sheared(int nb, const double4* __restrict__ pos,
+                                                        const double* __restrict__ lam, WaveParams wp,
+                                                        R* __restrict__ grid, size_t cs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ R wyz[4][2 * kMaxP];
+  __shared__ R wxr[4][kMaxP * kMaxP];
+  __shared__ int sxr[4][kMaxP];
+  __shared__ int sta[4][2];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  const bool live = i < nb;
+  if (live) sheared_weights<R>(pos[i], wp, lane, wyz[wv], sta[wv], wxr[wv], sxr[wv]);
+  __syncthreads();
+  if (!live) return;
+  const int P = wp.support, N = wp.n;
+  const double* li = lam + 6 * i;
+  const R f0 = R(li[0]), f1 = R(li[1]), f2 = R(li[2]);
+  const R t0 = R(li[3]), t1 = R(li[4]), t2 = R(li[5]);
+  const int sy = sta[wv][0], sz = sta[wv][1];
+  const int P3 = P * P * P;
+  for (int idx = lane; idx < P3; idx += 64) {
+    const int kx = idx % P, ky = (idx / P) % P, kz = idx / (P * P);
+    const R w = wxr[wv][ky * kMaxP + kx] * wyz[wv][ky] * wyz[wv][kMaxP + kz];
+    const size_t m = (size_t(wrapi(sz + kz, N)) * N + wrapi(sy + ky, N)) * N + wrapi(sxr[wv][ky] + kx, N);
+    R* g = grid + 2 * m;
+    atomicAdd(g, w * f0);
+    atomicAdd(g + 1, w * t0);
+    atomicAdd(g + cs, w * f1);
+    atomicAdd(g + cs + 1, w * t1);
+    atomicAdd(g + 2 * cs, w * f2);
+    atomicAdd(g + 2 * cs + 1, w * t2);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_interp_sheared(int nb, const double4* __restrict__ pos,
+                                                        const R* __restrict__ grid, size_t cs, WaveParams wp,
+                                                        double* __restrict__ out, const int* __restrict__ skip,
+                                                        const int* __restrict__ body, const double4* __restrict__ r4,
+                                                        const double* __restrict__ V) {
+  if (skip && *skip) return;
+  __shared__ R wyz[4][2 * kMaxP];
+  __shared__ R wxr[4][kMaxP * kMaxP];
+  __shared__ int sxr[4][kMaxP];
+  __shared__ int sta[4][2];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  const bool live = i < nb;
+  if (live) sheared_weights<R>(pos[i], wp, lane, wyz[wv], sta[wv], wxr[wv], sxr[wv]);
+  __syncthreads();
+  if (!live) return;
+  const int P = wp.support, N = wp.n;
+  const int sy = sta[wv][0], sz = sta[wv][1];
+  R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+  for (int pq = lane; pq < P * P; pq += 64) {  // lane -> (kx, ky) column, walking z
+    const int ky = pq / P, kx = pq - ky * P;
+    const int x = wrapi(sxr[wv][ky] + kx, N), y = wrapi(sy + ky, N);
+    const R wxy = wxr[wv][ky * kMaxP + kx] * wyz[wv][ky];
+    for (int kz = 0; kz < P; ++kz) {
+      const R w = wxy * wyz[wv][kMaxP + kz];
+      const R* g = grid + 2 * ((size_t(wrapi(sz + kz, N)) * N + y) * N + x);
+      a0 += w * g[0];
+      a3 += w * g[1];
+      a1 += w * g[cs];
+      a4 += w * g[cs + 1];
+      a2 += w * g[2 * cs];
+      a5 += w * g[2 * cs + 1];
+    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  a3 = wave_sum(a3);
+  a4 = wave_sum(a4);
+  a5 = wave_sum(a5);
+  if (lane == 0) {
+    double* o = out + 6 * size_t(i);
+    double add[6] = {double(a0), double(a1), double(a2), double(a3), double(a4), double(a5)};
+    if (V) {  // Sigma^T V: (U + W x r, W) of the bead's body
+      const double* v = V + 6 * body[i];
+      const double4 r = r4[i];
+      add[0] += v[0] + (v[4] * r.z - v[5] * r.y);
+      add[1] += v[1] + (v[5] * r.x - v[3] * r.z);
+      add[2] += v[2] + (v[3] * r.y - v[4] * r.x);
+      add[3] += v[3];
+      add[4] += v[4];
+      add[5] += v[5];
+    }
+    for (int k = 0; k < 6; ++k) o[k] += add[k];
+  }
+}
+
+template <typename R>
+void launch_spread_sheared(int nb, const double* pos4, const double* lam, const WaveParams& wp, R* grid,
+                           hipStream_t st, const int* skip) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  launch_k(k_spread_sheared<R>, nblocks(nb, 4), kThreads, 0, st, nb, (const double4*)pos4, lam, wp, grid, cs, skip);
+}
+
+template <typename R>
+void launch_interp_sheared(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
+                           hipStream_t st, const int* skip, const int* body, const double* r4, const double* V) {
+  const size_t cs = 2 * size_t(wp.n) * wp.n * wp.n;
+  launch_k(k_interp_sheared<R>, nblocks(nb, 4), kThreads, 0, st, nb, (const double4*)pos4, grid, cs, wp, out, skip,
+           body, (const double4*)r4, V);
 }
 
 template <typename R>
@@ -1298,8 +1437,10 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
       Tr[c] = 0.5 * (double(z.y) + double(zm.y));
       Ti[c] = -0.5 * (double(z.x) - double(zm.x));
     }
-    const double k[3] = {tp * (kx <= N / 2 ? kx : kx - N), tp * (ky < N / 2 ? ky : ky - N),
-                         tp * (kz < N / 2 ? kz : kz - N)};
+    // Cartesian wave vector of grid mode m: (2 pi / L)(m_x, m_y - gam m_x, m_z) (the
+    // reciprocal lattice of the sheared lattice; gam = 0 for the cube)
+    const int mx = kx <= N / 2 ? kx : kx - N;
+    const double k[3] = {tp * mx, tp * ((ky < N / 2 ? ky : ky - N) - wp.gam * mx), tp * (kz < N / 2 ? kz : kz - N)};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     const double kn = sqrt(k2);
     const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
@@ -1608,6 +1749,14 @@ template void launch_interp<double>(int, const double*, const double*, const Wav
                                     const int*, const double*, const double*, const SpreadPlan*);
 template void launch_interp<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t, const int*,
                                    const int*, const double*, const double*, const SpreadPlan*);
+template void launch_spread_sheared<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t,
+                                            const int*);
+template void launch_spread_sheared<float>(int, const double*, const double*, const WaveParams&, float*, hipStream_t,
+                                           const int*);
+template void launch_interp_sheared<double>(int, const double*, const double*, const WaveParams&, double*, hipStream_t,
+                                            const int*, const int*, const double*, const double*);
+template void launch_interp_sheared<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t,
+                                           const int*, const int*, const double*, const double*);
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 

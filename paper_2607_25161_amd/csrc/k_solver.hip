@@ -44,8 +44,8 @@ __global__ void k_pair_forces(int nb, const double4* __restrict__ pos, const int
     const int j = int(c & 0x3FFFFFu);
     if (body[j] == bi) continue;
     const double4 pj = pos[j];
-    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * p.L;
-    const double dy = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * p.L;
+    const double dy = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * p.L;  // Cartesian from sheared
+    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * p.L + p.gam * dy;
     const double dz = pi.z - pj.z + (int((c >> 28) & 7u) - 3) * p.L;
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(r < p.r_cut) || r == 0.0) continue;
@@ -64,8 +64,8 @@ __global__ void k_pair_forces(int nb, const double4* __restrict__ pos, const int
 // flag = 1 when two beads of different bodies are closer than 1.5 a (the real-space list
 // holds every pair within its cutoff; used when there is no lubrication list to check)
 __global__ void k_overlap_check(int nb, const double4* __restrict__ pos, const int* __restrict__ body,
-                                const int* __restrict__ rowptr, const uint32_t* __restrict__ col, double L, double a,
-                                int* __restrict__ flag) {
+                                const int* __restrict__ rowptr, const uint32_t* __restrict__ col, double L,
+                                double gam, double a, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const double4 pi = pos[i];
@@ -75,8 +75,8 @@ __global__ void k_overlap_check(int nb, const double4* __restrict__ pos, const i
     const int j = int(c & 0x3FFFFFu);
     if (body[j] == body[i]) continue;
     const double4 pj = pos[j];
-    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * L;
     const double dy = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * L;
+    const double dx = pi.x - pj.x + (int((c >> 22) & 7u) - 3) * L + gam * dy;
     const double dz = pi.z - pj.z + (int((c >> 28) & 7u) - 3) * L;
     if (dx * dx + dy * dy + dz * dz < lim2) {
       atomicOr(flag, 1);
@@ -86,8 +86,8 @@ __global__ void k_overlap_check(int nb, const double4* __restrict__ pos, const i
 }
 
 void launch_overlap_check(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,
-                          double L, double a, int* flag, hipStream_t st) {
-  k_overlap_check<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, body, rowptr, col, L, a, flag);
+                          double L, double gam, double a, int* flag, hipStream_t st) {
+  k_overlap_check<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, body, rowptr, col, L, gam, a, flag);
 }
 
 void launch_pair_forces(int nb, const double* pos4, const int* body, const int* rowptr, const uint32_t* col,

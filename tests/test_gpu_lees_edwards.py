@@ -1,0 +1,169 @@
+"""Sheared periodic lattice (Lees-Edwards) on the GPU through the C ABI: the boundary of
+long steady-shear runs (Section 4.3).
+
+- saddle solves at strains 0.37 and -0.45 against the oracle's dense solves on the same
+  lattice (Ewald sums over sheared images and reciprocal vectors, nearest-image lubrication),
+  with a bead pair that meets only through the sheared image across the y faces;
+- the conservative pair forces over the same images;
+- a step that carries a body across a y face: centroid folded with the new strain, which
+  advances by G_xy dt;
+- a sheared run of many steps with lubrication stays free of overlaps;
+- argument and state checks.
+"""
+import numpy as np
+import pytest
+
+import fsdgen
+from oracle import forces, integrate, lub, rigid, saddle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F(gpu):
+    import paper_2607_25161_amd as F
+    return F
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def _system(strain, seed=61, sizes=(3, 4, 1, 5, 2), L=11.0, r_lub=3.0):
+    """Clusters by random addition plus two single beads that meet only through the sheared
+    image across the y faces: one just below +L/2, the other just above -L/2 and gamma L back
+    along x, so that the image of the second lies 2.1 a from the first."""
+    rng = fsdgen.rng_from(seed)
+    shapes = [fsdgen.sticking_cluster(rng, nb) for nb in sizes]
+    offs0 = np.r_[0, np.cumsum(sizes)]
+    xb0 = rigid.centre_bodies(np.concatenate(shapes), offs0)
+    body0 = rigid.body_index(offs0)
+    for _ in range(100):  # random addition keeps cube images apart; the sheared ones are checked here
+        com, quat = fsdgen.place_clusters(rng, shapes, L, gap=0.1)
+        placed = com[body0] + rigid.bead_vectors(quat, xb0, offs0)
+        d = np.linalg.norm(lub.min_image(placed[:, None, :] - placed[None, :, :], L, strain), axis=-1)
+        if d[body0[:, None] != body0[None, :]].min() > 2.05:
+            break
+    else:
+        raise RuntimeError("placement failed")
+    for _ in range(10000):
+        x0, z0 = rng.uniform(-L / 2, L / 2, 2)
+        p1 = np.array([x0, L / 2 - 0.9, z0])
+        p2 = np.array([x0 + 0.3 - strain * L, -L / 2 + 1.2, z0 + 0.2])
+        d = lub.min_image(np.vstack([p1, p2])[:, None, :] - placed[None, :, :], L, strain)
+        if np.linalg.norm(d, axis=-1).min() > 2.2:
+            break
+    else:
+        raise RuntimeError("placement failed")
+    xb = shapes + [np.zeros((1, 3))] * 2
+    com = np.vstack([com, p1, p2])
+    quat = np.vstack([quat, np.tile([1.0, 0, 0, 0], (2, 1))])
+    offs = np.r_[0, np.cumsum([len(x) for x in xb])].astype(np.int32)
+    return dict(L=L, a=1.0, eta=1.0, offsets=offs, x_body=np.concatenate(xb), com=com, quat=quat,
+                force=rng.normal(size=(len(xb), 6)), grad_u=fsdgen.simple_shear(1.0), r_lub=r_lub)
+
+
+def _make(F, kw, strain, **p):
+    par = dict(xi=0.6, ewald_tol=1e-10, r_lub=kw["r_lub"], r_precond=2.1 if kw["r_lub"] else 0.0,
+               gmres_tol=1e-11, gmres_restart=40, gmres_maxit=3000)
+    par.update(p)
+    s = F.System(F.default_params(**par))
+    s.init_box(kw["L"])
+    s.set_lees_edwards(True, strain)
+    s.init_aggregates(kw["offsets"], kw["x_body"], kw["com"], kw["quat"])
+    s.set_forces(kw["force"])
+    s.set_shear(kw["grad_u"])
+    return s
+
+
+@pytest.mark.parametrize("strain", [0.37, -0.45])
+def test_solve_matches_oracle(F, strain):
+    kw = _system(strain)
+    A = saddle.assemble(**kw, strain=strain)
+    i, k, d = lub.pairs(A.x, rigid.body_index(kw["offsets"]), kw["L"], 2.2, strain)
+    nbd = int(kw["offsets"][-1])
+    assert any({a, b} == {nbd - 2, nbd - 1} for a, b in zip(i, k))  # the pair across the faces
+    s = _make(F, kw, strain)
+    assert abs(s.strain() - strain) < 1e-15
+    U, _, info = s.solve()
+    Uo, *_ = saddle.solve(**kw, strain=strain)
+    Uc, *_ = saddle.solve(**kw)
+    assert _rel(Uo, Uc) > 1e-3  # the lattice matters
+    for sl in (slice(0, 3), slice(3, 6)):
+        assert _rel(U[:, sl], Uo[:, sl]) < 1e-8, (sl, _rel(U[:, sl], Uo[:, sl]))
+    s.close()
+
+
+def test_pair_forces_on_sheared_lattice(F):
+    strain = 0.29
+    kw = _system(strain, seed=62, r_lub=0.0)
+    s = _make(F, kw, strain)
+    coef = dict(k_n=50.0, hamaker=0.5, Z=2.0, kappa=1.5, h_c=0.05)
+    s.set_pair_forces(r_cut=3.0, **coef)
+    A = saddle.assemble(**kw, strain=strain)
+    ref = forces.bead_forces(A.x, rigid.body_index(kw["offsets"]), kw["L"], 1.0, 3.0, strain=strain, **coef)
+    nbd = int(kw["offsets"][-1])
+    assert np.abs(ref[nbd - 2:]).max() > 1e-3  # the beads across the faces feel each other
+    f = s.pair_forces()
+    assert np.abs(f - ref).max() <= 1e-12 * np.abs(ref).max()
+    s.close()
+
+
+def test_step_across_a_y_face(F):
+    strain, dt, rate = 0.41, 0.5, 1.0
+    kw = _system(strain, seed=63)
+    na = len(kw["offsets"]) - 1
+    kw["force"] = np.zeros((na, 6))
+    kw["force"][na - 2:, 1] = 40.0  # lifts the two single beads together: the upper one crosses +L/2
+    s = _make(F, kw, strain)
+    U, _, _ = s.solve()
+    X0, q0 = s.state()
+    s.step(dt, 1)
+    X1, q1 = s.state()
+    g1 = strain + rate * dt
+    g1 -= np.floor(g1 + 0.5)
+    assert abs(s.strain() - g1) < 1e-14
+    Xo, qo = integrate.euler_step(X0, q0, U, dt, kw["L"], strain=g1)
+    assert X0[na - 2, 1] + U[na - 2, 1] * dt > kw["L"] / 2  # it did cross
+    assert X1[na - 2, 1] < 0  # and re-entered at the bottom, shifted along x
+    assert np.abs(X1 - Xo).max() < 1e-12 and np.abs(q1 - qo).max() < 1e-12
+    s.close()
+
+
+def test_sheared_run_keeps_bodies_apart(F):
+    strain = -0.2
+    kw = _system(strain, seed=64)
+    kw["force"] = np.zeros_like(kw["force"])
+    s = _make(F, kw, strain, ewald_tol=1e-6, gmres_tol=1e-6)
+    dt, n = 0.02, 60
+    for _ in range(n):
+        assert s.step(dt, 1).status == 0
+    g = strain + n * dt
+    assert abs(s.strain() - (g - np.floor(g + 0.5))) < 1e-12
+    s.close()
+
+
+def test_lees_edwards_arguments(F):
+    kw = _system(0.1, seed=65)
+    s = _make(F, kw, 0.1)
+    with pytest.raises(F.FsdError):
+        s.set_shear(np.diag([1.0, -1.0, 0.0]))  # not simple shear
+    s.set_lees_edwards(True, 0.7)  # strain may be reset; folded into [-1/2, 1/2)
+    assert abs(s.strain() - (-0.3)) < 1e-15
+    b = F.Batch(1 << 32, 2)
+    with pytest.raises(F.FsdError):
+        b.admit(s)
+    b.close()
+    s.close()
+    s = F.System(F.default_params(xi=0.6, ewald_tol=1e-6))
+    s.init_box(kw["L"])
+    s.init_aggregates(kw["offsets"], kw["x_body"], kw["com"], kw["quat"])
+    with pytest.raises(F.FsdError) as e:
+        s.set_lees_edwards(True, 0.1)  # after the aggregates: the grid is fixed
+    assert e.value.code == -5  # FSD_ESTATE
+    s.close()
+    s = F.System(F.default_params(xi=0.6, ewald_tol=1e-6, kT=1.0))
+    s.init_box(kw["L"])
+    with pytest.raises(F.FsdError):
+        s.set_lees_edwards(True, 0.1)
+    s.close()
