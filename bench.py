@@ -269,6 +269,7 @@ def bench_large(args, F, fsdgen, torch):
     res = {}
     for prec_name, prec in (("fp64", F.FSD_FP64), ("mixed", F.FSD_MIXED)):
         sysm = F.System.from_suspension(s, stream=stream, precision=prec)
+        sysm.set_warm_start(not args.cold)
         U0, _, _ = sysm.solve()              # warm-up: lists sized, graphs captured
         torch.cuda.synchronize()
         progress(f"{prec_name}: warm-up solve done")
@@ -305,7 +306,7 @@ def bench_large(args, F, fsdgen, torch):
         "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead, "n_agg": s.n_agg,
                    "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid, "support": info.support,
                    "xi": info.xi, "r_cut": round(info.r_cut, 3), "nnz_real": int(info.nnz_real), "tol": s.gmres_tol,
-                   "precision": "mixed", "parallelism": "single GPU"},
+                   "precision": "mixed", "warm_start": not args.cold, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(m["lat"], 50)), 3),
                        "p99": round(1e3 * float(np.percentile(m["lat"], 99)), 3)},
         "gmres_iterations_mean": round(m["its"], 2), "max_rel_residual": m["max_res"],
@@ -359,6 +360,9 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--load", type=float, default=0.5)
     ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
+    ap.add_argument("--cold", action="store_true",
+                    help="GMRES from zero in every solve (default: warm starts from the previous step's solution; "
+                         "the stopping test is the same)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
@@ -381,25 +385,34 @@ def main():
     stream = torch.cuda.current_stream()
     s = fsdgen.config(1)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
-    sysm = F.System.from_suspension(s, stream=stream.cuda_stream, precision=prec)
-    for _ in range(args.warmup):
-        sysm.step(s.dt, 1)
-    info = sysm.info()
+    def timed_run(warm):
+        sysm = F.System.from_suspension(s, stream=stream.cuda_stream, precision=prec)
+        sysm.set_warm_start(warm)
+        for _ in range(args.warmup):
+            sysm.step(s.dt, 1)
+        info = sysm.info()
+        # timed region: graph-replayed GMRES, no instrumentation
+        torch.cuda.synchronize()
+        lat, its, res = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            si = sysm.step(s.dt, 1)
+            lat.append(time.perf_counter() - a)
+            its.append(si.iterations)
+            res.append(si.rel_residual_fp64)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        sysm.close()
+        return info, lat, its, res, elapsed
 
-    # timed region: graph-replayed GMRES, no instrumentation
-    torch.cuda.synchronize()
-    lat, its, res = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        si = sysm.step(s.dt, 1)
-        lat.append(time.perf_counter() - a)
-        its.append(si.iterations)
-        res.append(si.rel_residual_fp64)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    sysm.close()
+    info, lat, its, res, elapsed = timed_run(not args.cold)
+    cold = None
+    if not args.cold:  # the same steps with every solve from zero, for comparison
+        _, _, c_its, c_res, c_el = timed_run(False)
+        cold = {"value": round(s.n_bead * sum(1 for r in c_res if r <= 1e-5) / c_el, 1),
+                "ms_per_step": round(1e3 * c_el / args.steps, 3),
+                "gmres_iterations_mean": round(float(np.mean(c_its)), 2)}
 
     # kernel durations: the same trajectory again from the same start (a fresh system,
     # the same warm-up), with start/stop events carried by every timed launch on the
@@ -407,6 +420,7 @@ def main():
     # pass launches eagerly; the kernels are the same), then the dominant kernel replayed
     # back to back for its launch duration without dispatch gaps
     sysm = F.System.from_suspension(s, stream=stream.cuda_stream, precision=prec)
+    sysm.set_warm_start(not args.cold)
     for _ in range(args.warmup):
         sysm.step(s.dt, 1)
     sysm.set_timing(True)
@@ -430,11 +444,12 @@ def main():
         "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead,
                    "n_agg": s.n_agg, "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid,
                    "support": info.support, "xi": info.xi, "r_cut": round(info.r_cut, 3), "tol": s.gmres_tol,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "precision": args.precision, "warm_start": not args.cold, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "gmres_iterations_mean": round(float(np.mean(its)), 2),
         "max_rel_residual": float(max(res)),
+        "cold_start": cold,
         "kernels": table,
         "kernel_timing": ("start/stop HIP events carried by each timed launch on the library stream, eager pass "
                           "over the same steps from the same start (each interval includes the launch's dispatch)"),

@@ -99,6 +99,7 @@ _sig("fsd_get_pair_forces", C.c_int, _SYS, _D)
 _sig("fsd_set_roughness", C.c_int, _SYS, C.c_double, C.c_double)
 _sig("fsd_set_lees_edwards", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_get_strain", C.c_int, _SYS, _D)
+_sig("fsd_set_warm_start", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
@@ -321,6 +322,10 @@ class System:
         """Sheared periodic lattice of the given strain (before init_aggregates to switch
         on; the strain may be reset later)."""
         self._check(lib.fsd_set_lees_edwards(self._h, int(bool(enable)), float(strain)), "fsd_set_lees_edwards")
+
+    def set_warm_start(self, enable=True):
+        """GMRES from the previous converged solution instead of zero (same stopping test)."""
+        self._check(lib.fsd_set_warm_start(self._h, int(bool(enable))), "fsd_set_warm_start")
 
     def strain(self):
         out = C.c_double(0.0)

@@ -313,6 +313,9 @@ struct fsd_system {
          *d_quat0 = nullptr;
   PairForceParams pf{};
   double rough_alpha = 0.0, rough_h0 = 0.0;  // tangential roughness of lubrication (h0 = 0: off)
+  bool warm = false;        // GMRES starts from the previous converged solution
+  bool have_xprev = false;  // d_xprev holds one
+  double* d_xprev = nullptr;
   bool le = false;      // sheared periodic lattice (Lees-Edwards)
   double strain = 0.0;  // its strain gamma, kept in [-1/2, 1/2)
   double gam() const { return le ? strain : 0.0; }
@@ -1198,7 +1201,12 @@ void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp
   v.x = x;
   v.tol = tol;
   v.fp32 = fp32;
-  launch_zero(x, sizeof(double) * s->n, s->st);
+  // initial guess: zero, or with warm starts the previous converged solution of a full
+  // right-hand side (the first cycle forms the true residual b - A x either way)
+  if (s->warm && s->have_xprev && v.rhs_kind == 0)
+    HIPCHK(hipMemcpyAsync(x, s->d_xprev, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
+  else
+    launch_zero(x, sizeof(double) * s->n, s->st);
   double* bb = s->d_h + 2 * (s->m + 1) + 1;
   launch_dots(s->n, 1, b, s->n, b, s->d_part, bb, s->d_counters, s->st);
   launch_gmres_init(s->d_ctl, bb, tol, std::max(1, maxit), s->m, s->st);
@@ -1213,6 +1221,11 @@ void finish_solve(fsd_system* s, bool ok) {
     launch_axpby(6 * size_t(s->na), 1.0, s->d_x + nb6, 1.0, s->d_U, s->st);
   } else {
     launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
+  }
+  if (ok && s->warm && s->sv.rhs_kind == 0) {
+    if (!s->d_xprev) s->d_xprev = dalloc<double>(s->owned, s->n);
+    HIPCHK(hipMemcpyAsync(s->d_xprev, s->d_x, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
+    s->have_xprev = true;
   }
   s->sv.converged = ok;
   s->sv.status = ok ? FSD_OK : FSD_ENOCONV;
@@ -2040,6 +2053,13 @@ fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain) {
     s->strain = s->le ? g : 0.0;
     s->prepared = false;
   }
+  return FSD_OK;
+}
+
+fsd_status fsd_set_warm_start(fsd_system* s, int enable) {
+  if (!s) return FSD_EINVAL;
+  s->warm = enable != 0;
+  if (!s->warm) s->have_xprev = false;
   return FSD_OK;
 }
 

@@ -397,6 +397,35 @@ def test_clusters256x8_ten_steps_match_oracle(F, precision):
     print("worst relative velocity error over 10 steps:", worst)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_warm_start_same_trajectory_fewer_iterations(F, precision):
+    """Warm starts change the initial guess only: every solve still meets the tolerance on
+    its true residual, the trajectory agrees with cold starts to that tolerance, and a repeated
+    solve at an unchanged configuration needs no iteration."""
+    kw = _cluster_system(seed=17)
+    prec = F.FSD_MIXED if precision == "mixed" else F.FSD_FP64
+    cold, warm = _make(F, kw, gmres_tol=1e-8, precision=prec), _make(F, kw, gmres_tol=1e-8, precision=prec)
+    warm.set_warm_start(True)
+    its = {"cold": [], "warm": []}
+    for _ in range(6):
+        for name, s in (("cold", cold), ("warm", warm)):
+            info = s.step(2e-3, 1)
+            assert info.status == 0 and info.rel_residual_fp64 <= 1e-8
+            its[name].append(info.iterations)
+    assert its["warm"][0] == its["cold"][0]  # nothing stored before the first solve
+    assert sum(its["warm"][1:]) < 0.8 * sum(its["cold"][1:]), its
+    (Xc, qc), (Xw, qw) = cold.state(), warm.state()
+    assert np.abs(Xc - Xw).max() < 1e-9 and np.abs(qc - qw).max() < 1e-9
+    U1, _, i1 = warm.solve()
+    U2, _, i2 = warm.solve()  # same configuration: the stored solution already meets the tolerance
+    assert i2.iterations == 0 and i2.rel_residual_fp64 <= 1e-8
+    assert _rel(U2, U1) < 1e-7
+    warm.set_warm_start(False)
+    assert warm.solve()[2].iterations > 0
+    cold.close()
+    warm.close()
+
+
 # ---------------------------------------------------------------------------------------
 # error paths
 # ---------------------------------------------------------------------------------------
