@@ -269,7 +269,7 @@ def bench_large(args, F, fsdgen, torch):
     res = {}
     for prec_name, prec in (("fp64", F.FSD_FP64), ("mixed", F.FSD_MIXED)):
         sysm = F.System.from_suspension(s, stream=stream, precision=prec)
-        sysm.set_warm_start(not args.cold)
+        sysm.set_warm_start(0 if args.cold else args.warm_mode)
         U0, _, _ = sysm.solve()              # warm-up: lists sized, graphs captured
         torch.cuda.synchronize()
         progress(f"{prec_name}: warm-up solve done")
@@ -306,7 +306,7 @@ def bench_large(args, F, fsdgen, torch):
         "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead, "n_agg": s.n_agg,
                    "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid, "support": info.support,
                    "xi": info.xi, "r_cut": round(info.r_cut, 3), "nnz_real": int(info.nnz_real), "tol": s.gmres_tol,
-                   "precision": "mixed", "warm_start": not args.cold, "parallelism": "single GPU"},
+                   "precision": "mixed", "warm_start": 0 if args.cold else args.warm_mode, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(m["lat"], 50)), 3),
                        "p99": round(1e3 * float(np.percentile(m["lat"], 99)), 3)},
         "gmres_iterations_mean": round(m["its"], 2), "max_rel_residual": m["max_res"],
@@ -361,8 +361,10 @@ def main():
     ap.add_argument("--load", type=float, default=0.5)
     ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
     ap.add_argument("--cold", action="store_true",
-                    help="GMRES from zero in every solve (default: warm starts from the previous step's solution; "
-                         "the stopping test is the same)")
+                    help="GMRES from zero in every solve (default: warm starts; the stopping test is the same)")
+    ap.add_argument("--warm-mode", type=int, choices=[1, 2, 3], default=2,
+                    help="warm start from the previous solution (1) or the linear (2) or quadratic (3) "
+                         "extrapolation of the last solutions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
@@ -406,10 +408,10 @@ def main():
         sysm.close()
         return info, lat, its, res, elapsed
 
-    info, lat, its, res, elapsed = timed_run(not args.cold)
+    info, lat, its, res, elapsed = timed_run(0 if args.cold else args.warm_mode)
     cold = None
     if not args.cold:  # the same steps with every solve from zero, for comparison
-        _, _, c_its, c_res, c_el = timed_run(False)
+        _, _, c_its, c_res, c_el = timed_run(0)
         cold = {"value": round(s.n_bead * sum(1 for r in c_res if r <= 1e-5) / c_el, 1),
                 "ms_per_step": round(1e3 * c_el / args.steps, 3),
                 "gmres_iterations_mean": round(float(np.mean(c_its)), 2)}
@@ -420,7 +422,7 @@ def main():
     # pass launches eagerly; the kernels are the same), then the dominant kernel replayed
     # back to back for its launch duration without dispatch gaps
     sysm = F.System.from_suspension(s, stream=stream.cuda_stream, precision=prec)
-    sysm.set_warm_start(not args.cold)
+    sysm.set_warm_start(0 if args.cold else args.warm_mode)
     for _ in range(args.warmup):
         sysm.step(s.dt, 1)
     sysm.set_timing(True)
@@ -444,7 +446,7 @@ def main():
         "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead,
                    "n_agg": s.n_agg, "phi": round(s.phi, 3), "L": round(s.L, 3), "grid": info.grid,
                    "support": info.support, "xi": info.xi, "r_cut": round(info.r_cut, 3), "tol": s.gmres_tol,
-                   "precision": args.precision, "warm_start": not args.cold, "parallelism": "single GPU"},
+                   "precision": args.precision, "warm_start": 0 if args.cold else args.warm_mode, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "gmres_iterations_mean": round(float(np.mean(its)), 2),

@@ -193,13 +193,16 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
  * returns to the cube. */
 fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain);
 
-/* Warm starts (Algorithm 1 step 2): with enable != 0 every GMRES solve of a full right-hand
- * side starts from the last converged solution of such a solve (lambda and V), instead of
- * zero; the first cycle then forms the true residual b - A x0 as usual, and the stopping
- * test ||b - A x|| <= gmres_tol ||b|| is unchanged, so only the iteration count differs.
- * Solves of the drift right-hand sides start from zero.  Default off; enable 0 forgets
- * the stored solution. */
-fsd_status fsd_set_warm_start(fsd_system* s, int enable);
+/* Warm starts (Algorithm 1 step 2): the initial guess of every GMRES solve of a full
+ * right-hand side.  mode 0: zero (default).  mode 1: the last converged solution of such a
+ * solve (lambda and V).  mode 2: the linear extrapolation 2 x_n - x_(n-1) of the last two.
+ * mode 3: the quadratic one, 3 x_n - 3 x_(n-1) + x_(n-2).  Until enough solutions are held
+ * the highest available order is used; the extrapolations assume steps of equal length.  The
+ * first cycle forms the true residual b - A x0 as usual and the stopping test
+ * ||b - A x|| <= gmres_tol ||b|| is unchanged, so only the iteration count differs.  Solves
+ * of the drift right-hand sides start from zero.  Changing the mode forgets the stored
+ * solutions; FSD_EINVAL for modes outside 0-3. */
+fsd_status fsd_set_warm_start(fsd_system* s, int mode);
 
 /* The current strain gamma in [-1/2, 1/2) (0 on the cube). */
 fsd_status fsd_get_strain(const fsd_system* s, double* strain);

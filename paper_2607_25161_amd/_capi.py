@@ -323,9 +323,11 @@ class System:
         on; the strain may be reset later)."""
         self._check(lib.fsd_set_lees_edwards(self._h, int(bool(enable)), float(strain)), "fsd_set_lees_edwards")
 
-    def set_warm_start(self, enable=True):
-        """GMRES from the previous converged solution instead of zero (same stopping test)."""
-        self._check(lib.fsd_set_warm_start(self._h, int(bool(enable))), "fsd_set_warm_start")
+    def set_warm_start(self, mode=1):
+        """GMRES initial guess: 0 (or False) zero, 1 (or True) the previous converged solution,
+        2 and 3 the linear and quadratic extrapolations of the last two and three (same
+        stopping test)."""
+        self._check(lib.fsd_set_warm_start(self._h, int(mode)), "fsd_set_warm_start")
 
     def strain(self):
         out = C.c_double(0.0)

@@ -313,9 +313,10 @@ struct fsd_system {
          *d_quat0 = nullptr;
   PairForceParams pf{};
   double rough_alpha = 0.0, rough_h0 = 0.0;  // tangential roughness of lubrication (h0 = 0: off)
-  bool warm = false;        // GMRES starts from the previous converged solution
-  bool have_xprev = false;  // d_xprev holds one
-  double* d_xprev = nullptr;
+  int warm = 0;     // GMRES initial guess: 0 zero, else the polynomial extrapolation through
+                    // the last `warm` converged solutions (1: the previous one)
+  int nprev = 0;    // converged solutions held, newest first in d_xp
+  double* d_xp[3] = {nullptr, nullptr, nullptr};
   bool le = false;      // sheared periodic lattice (Lees-Edwards)
   double strain = 0.0;  // its strain gamma, kept in [-1/2, 1/2)
   double gam() const { return le ? strain : 0.0; }
@@ -1203,10 +1204,18 @@ void gmres_launch(fsd_system* s, const double* b, double* x, double tol, bool fp
   v.fp32 = fp32;
   // initial guess: zero, or with warm starts the previous converged solution of a full
   // right-hand side (the first cycle forms the true residual b - A x either way)
-  if (s->warm && s->have_xprev && v.rhs_kind == 0)
-    HIPCHK(hipMemcpyAsync(x, s->d_xprev, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
-  else
+  if (s->warm && s->nprev > 0 && v.rhs_kind == 0) {
+    // x0 = sum_i c_i x_(n-i): the value at the next step of the polynomial through the last
+    // q solutions (steps of equal length): q = 1: x_n; 2: 2 x_n - x_(n-1);
+    // 3: 3 x_n - 3 x_(n-1) + x_(n-2)
+    static const double coef[3][3] = {{1, 0, 0}, {2, -1, 0}, {3, -3, 1}};
+    const int q = std::min(s->warm, s->nprev);
+    HIPCHK(hipMemcpyAsync(x, s->d_xp[0], sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
+    if (q > 1) launch_axpby(s->n, coef[q - 1][1], s->d_xp[1], coef[q - 1][0], x, s->st);
+    if (q > 2) launch_axpby(s->n, coef[q - 1][2], s->d_xp[2], 1.0, x, s->st);
+  } else {
     launch_zero(x, sizeof(double) * s->n, s->st);
+  }
   double* bb = s->d_h + 2 * (s->m + 1) + 1;
   launch_dots(s->n, 1, b, s->n, b, s->d_part, bb, s->d_counters, s->st);
   launch_gmres_init(s->d_ctl, bb, tol, std::max(1, maxit), s->m, s->st);
@@ -1222,10 +1231,15 @@ void finish_solve(fsd_system* s, bool ok) {
   } else {
     launch_add_ambient(s->na, s->d_x + nb6, s->d_com, s->d_G, s->d_W, s->d_U, s->st);
   }
-  if (ok && s->warm && s->sv.rhs_kind == 0) {
-    if (!s->d_xprev) s->d_xprev = dalloc<double>(s->owned, s->n);
-    HIPCHK(hipMemcpyAsync(s->d_xprev, s->d_x, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
-    s->have_xprev = true;
+  if (ok && s->warm && s->sv.rhs_kind == 0) {  // keep the newest `warm` solutions, newest first
+    const int q = s->warm;
+    for (int i = 0; i < q; ++i)
+      if (!s->d_xp[i]) s->d_xp[i] = dalloc<double>(s->owned, s->n);
+    double* last = s->d_xp[q - 1];
+    for (int i = q - 1; i > 0; --i) s->d_xp[i] = s->d_xp[i - 1];
+    s->d_xp[0] = last;
+    HIPCHK(hipMemcpyAsync(s->d_xp[0], s->d_x, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
+    s->nprev = std::min(s->nprev + 1, q);
   }
   s->sv.converged = ok;
   s->sv.status = ok ? FSD_OK : FSD_ENOCONV;
@@ -2056,10 +2070,11 @@ fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain) {
   return FSD_OK;
 }
 
-fsd_status fsd_set_warm_start(fsd_system* s, int enable) {
+fsd_status fsd_set_warm_start(fsd_system* s, int mode) {
   if (!s) return FSD_EINVAL;
-  s->warm = enable != 0;
-  if (!s->warm) s->have_xprev = false;
+  if (mode < 0 || mode > 3) return fail(s, FSD_EINVAL, "warm-start mode 0 to 3");
+  if (mode != s->warm) s->nprev = 0;
+  s->warm = mode;
   return FSD_OK;
 }
 

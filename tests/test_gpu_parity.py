@@ -426,6 +426,31 @@ def test_warm_start_same_trajectory_fewer_iterations(F, precision):
     warm.close()
 
 
+def test_extrapolated_warm_start(F):
+    """Modes 2 and 3 start from the linear and quadratic extrapolations: the same trajectory
+    to the tolerance, every solve meeting it, and no more iterations than mode 1 once enough
+    solutions are held."""
+    kw = _cluster_system(seed=18, shear=False)
+    runs = {}
+    for mode in (1, 2, 3):
+        s = _make(F, kw, gmres_tol=1e-8)
+        s.set_warm_start(mode)
+        its = []
+        for _ in range(8):
+            info = s.step(5e-3, 1)
+            assert info.status == 0 and info.rel_residual_fp64 <= 1e-8
+            its.append(info.iterations)
+        runs[mode] = (its, s.state())
+        s.close()
+    (i1, (X1, q1)), (i2, (X2, q2)), (i3, (X3, q3)) = runs[1], runs[2], runs[3]
+    assert i2[:2] == i1[:2] and i3[:3] == i2[:3]  # identical until enough solutions are held
+    assert sum(i2[2:]) <= sum(i1[2:]) and sum(i3[3:]) <= sum(i1[3:]), (i1, i2, i3)
+    for X, q in ((X2, q2), (X3, q3)):
+        assert np.abs(X1 - X).max() < 1e-9 and np.abs(q1 - q).max() < 1e-9
+    with pytest.raises(F.FsdError):
+        _make(F, kw).set_warm_start(4)
+
+
 # ---------------------------------------------------------------------------------------
 # error paths
 # ---------------------------------------------------------------------------------------
