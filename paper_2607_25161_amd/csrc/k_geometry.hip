@@ -201,21 +201,25 @@ __global__ void k_cell_bounds(int nb, const int* __restrict__ keys, int* start, 
   if (k == nb - 1 || keys[k + 1] != c) end[c] = k + 1;
 }
 
-// One thread per bead scans the 27 surrounding cells (nc >= 3, so each cell is
-// visited once and the minimum image is unique).  Cells live in sheared coordinates; their
-// side covers the cutoff sphere's sheared extent r_c sqrt(1 + gam^2), and distances are
-// Cartesian.
+// One wavefront per bead scans the 27 surrounding cells (nc >= 3, so each cell is visited
+// once and the minimum image is unique), its lanes testing 64 candidates of a cell at a
+// time; a ballot gives each hit its place, so a row lists its pairs cell by cell in sorted
+// order whatever the wavefront width.  Cells live in sheared coordinates; their side covers
+// the cutoff sphere's sheared extent r_c sqrt(1 + gam^2), and distances are Cartesian.
 template <bool FILL>
-__global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int* __restrict__ body, double L,
-                             double gam, double cs, int nc, double rc2, int exclude_same_body,
-                             const int* __restrict__ start,
-                             const int* __restrict__ end, const int* __restrict__ sorted, int* counts,
-                             const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
+__global__ __launch_bounds__(256) void k_cell_pairs(int nb, const double4* __restrict__ pos,
+                                                    const int* __restrict__ body, double L, double gam, double cs,
+                                                    int nc, double rc2, int exclude_same_body,
+                                                    const int* __restrict__ start, const int* __restrict__ end,
+                                                    const int* __restrict__ sorted, int* counts,
+                                                    const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nb) return;  // whole wavefronts leave together
   const double4 p = pos[i];
   const int bi = body[i];
   const int cx = min(nc - 1, int(p.x / cs)), cy = min(nc - 1, int(p.y / cs)), cz = min(nc - 1, int(p.z / cs));
+  const unsigned long long below = (1ull << lane) - 1ull;
   int cnt = 0;
   const int base = FILL ? rowptr[i] : 0;
   for (int dz = -1; dz <= 1; ++dz) {
@@ -225,25 +229,33 @@ __global__ void k_cell_pairs(int nb, const double4* __restrict__ pos, const int*
       for (int dx = -1; dx <= 1; ++dx) {
         const int x = (cx + dx + nc) % nc;
         const int c = (z * nc + y) * nc + x;
-        for (int k = start[c]; k < end[c]; ++k) {
-          const int j = sorted[k];
-          if (j == i || (exclude_same_body && body[j] == bi)) continue;
-          const double4 q = pos[j];
-          double ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
-          const double sx = -rint(ddx / L), sy = -rint(ddy / L), sz = -rint(ddz / L);
-          ddx += sx * L;
-          ddy += sy * L;
-          ddz += sz * L;
-          ddx += gam * ddy;
-          if (ddx * ddx + ddy * ddy + ddz * ddz < rc2) {
-            if (FILL) col[base + cnt] = pack_entry(j, int(sx), int(sy), int(sz));
-            ++cnt;
+        const int k1 = end[c];
+        for (int k0 = start[c]; k0 < k1; k0 += 64) {
+          const int k = k0 + lane;
+          bool hit = false;
+          uint32_t entry = 0;
+          if (k < k1) {
+            const int j = sorted[k];
+            if (j != i && !(exclude_same_body && body[j] == bi)) {
+              const double4 q = pos[j];
+              double ddx = p.x - q.x, ddy = p.y - q.y, ddz = p.z - q.z;
+              const double sx = -rint(ddx / L), sy = -rint(ddy / L), sz = -rint(ddz / L);
+              ddx += sx * L;
+              ddy += sy * L;
+              ddz += sz * L;
+              ddx += gam * ddy;
+              hit = ddx * ddx + ddy * ddy + ddz * ddz < rc2;
+              if (FILL && hit) entry = pack_entry(j, int(sx), int(sy), int(sz));
+            }
           }
+          const unsigned long long m = __ballot(hit);
+          if (FILL && hit) col[base + cnt + __popcll(m & below)] = entry;
+          cnt += __popcll(m);
         }
       }
     }
   }
-  if (!FILL) counts[i] = cnt;
+  if (!FILL && lane == 0) counts[i] = cnt;
 }
 
 // Small boxes (fewer than 3 cells per side): all pairs and all images within
@@ -309,7 +321,7 @@ hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const i
     if ((e = hipMemsetAsync(w->cell_start, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(w->cell_end, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
     k_cell_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, w->keys_out, w->cell_start, w->cell_end);
-    k_cell_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
+    k_cell_pairs<false><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
                                                            w->cell_start, w->cell_end, w->vals_out, w->counts,
                                                            nullptr, nullptr);
   } else {
@@ -334,7 +346,7 @@ hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4v, const in
   const int nc = w->nc;
   if (nc >= 3) {
     const double cs = L / nc;
-    k_cell_pairs<true><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
+    k_cell_pairs<true><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
                                                           w->cell_start, w->cell_end, w->vals_out, nullptr, rowptr,
                                                           col);
   } else {
