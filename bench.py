@@ -136,8 +136,12 @@ def bench_batched(args, F, fsdgen, torch):
     systems = fsdgen.uneven_systems(n_sys=args.systems)
     n_tot = sum(s.n_bead for s in systems)
 
+    warm = 0 if args.cold else args.warm_mode
+
     def run_plain(steps):
         sys_ = [F.System.from_suspension(s0) for s0 in systems]
+        for s in sys_:
+            s.set_warm_start(warm)
         for s in sys_:          # warm-up: graphs captured, lists sized
             s.step(s0.dt if False else 1e-3, 1)
         torch.cuda.synchronize()
@@ -155,6 +159,8 @@ def bench_batched(args, F, fsdgen, torch):
 
     def run_batch(steps, precision, fused=True):
         sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+        for s in sys_:
+            s.set_warm_start(warm)
         b = F.Batch(1 << 40, len(sys_))
         b.set_fused(fused)
         slots = [b.admit(s) for s in sys_]
@@ -194,7 +200,8 @@ def bench_batched(args, F, fsdgen, torch):
         "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads, "
                                f"phi 0.02-0.25, xi = 25/L, tol 1e-5", "n_bead_total": n_tot,
-                   "grids_sampled": grids, "precision": "mixed", "parallelism": "single GPU, multi-system launches"},
+                   "grids_sampled": grids, "precision": "mixed", "warm_start": warm,
+                   "parallelism": "single GPU, multi-system launches"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
         "plain_fp64_one_at_a_time": {"value": round(plain, 1), "ms_per_step": round(1e3 * plain_step, 3)},
@@ -217,7 +224,8 @@ def bench_serving(args, F, fsdgen, torch):
 
     def run(rate, seed, subset=None, n_steps=args.req_steps):
         sel = reqs if subset is None else subset
-        be = LibBackend(F, budget, args.slots, dict(precision=prec))
+        # Brownian requests: the previous solution, not an extrapolation of noisy ones
+        be = LibBackend(F, budget, args.slots, dict(precision=prec), warm_start=0 if args.cold else 1)
         eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
         t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
         rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
@@ -248,7 +256,7 @@ def bench_serving(args, F, fsdgen, torch):
                                f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate 0.01 + lubrication + "
                                f"Brownian kT {args.kT}, tol 1e-5, Poisson arrivals at {args.load} x capacity",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
-                   "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,
+                   "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision, "warm_start": 0 if args.cold else 1,
                    "parallelism": "single GPU, continuous batching"},
         "latency_ms": {"p50": round(1e3 * open_["p50_latency_s"], 1), "p99": round(1e3 * open_["p99_latency_s"], 1)},
         "capacity_requests_per_s": round(cap, 3), "arrival_rate": round(rate, 3),

@@ -44,11 +44,12 @@ class Request:
 class LibBackend:
     """The real backend: one System per request, one fsd_batch for all."""
 
-    def __init__(self, F, mem_budget: int, max_slots: int, params: dict):
+    def __init__(self, F, mem_budget: int, max_slots: int, params: dict, warm_start: int = 0):
         self.F = F
         self.batch = F.Batch(mem_budget, max_slots)
         self.params = params
         self.budget = mem_budget
+        self.warm_start = warm_start  # GMRES initial guess of each request's solves (fsd_set_warm_start)
 
     def estimate(self, req: Request) -> int:
         s = req.suspension
@@ -72,6 +73,8 @@ class LibBackend:
     def admit(self, req: Request):
         s = req.suspension
         sysm = self.F.System.from_suspension(s, **self.params)
+        if self.warm_start:
+            sysm.set_warm_start(self.warm_start)
         slot = self.batch.try_admit(sysm)
         if slot is None:
             sysm.close()
