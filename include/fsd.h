@@ -184,13 +184,14 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
  * mobility's Ewald sums run on this lattice (real-space images, and wave vectors
  * (2 pi / L)(m_x, m_y - gamma m_x, m_z) on a grid of sheared coordinates, sized
  * sqrt(5)/2 finer than the cube's so that its spectral cutoff holds at any strain), and
- * lubrication, pair forces and overlap checks take the nearest image on it.  Switch it on
- * after fsd_init_box and before fsd_init_aggregates (FSD_ESTATE after); the strain may be
- * reset at any time while on.  Requires a velocity gradient with G_xy as its only non-zero
- * entry (FSD_EINVAL otherwise, also from a later fsd_set_shear) and kT = 0 (Brownian motion
- * on this lattice is not built).  Systems on it run through fsd_solve and fsd_step (not
- * the batch calls, which refuse them at admission), without captured graphs.  enable 0
- * returns to the cube. */
+ * lubrication, pair forces and overlap checks take the nearest image on it; the Brownian
+ * terms come from the same operators (grid noise through the sheared wave vectors, Lanczos
+ * roots of the sheared real-space and near-field parts).  Switch it on after fsd_init_box
+ * and before fsd_init_aggregates (FSD_ESTATE after); the strain may be reset at any time
+ * while on.  Requires a velocity gradient with G_xy as its only non-zero entry (FSD_EINVAL
+ * otherwise, also from a later fsd_set_shear).  Systems on it run through fsd_solve and
+ * fsd_step (not the batch calls, which refuse them at admission), without captured graphs.
+ * enable 0 returns to the cube. */
 fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain);
 
 /* Warm starts (Algorithm 1 step 2): the initial guess of every GMRES solve of a full

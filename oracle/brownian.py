@@ -32,16 +32,16 @@ def amplitude(kT, dt):
     return math.sqrt(2.0 * kT / dt)
 
 
-def real_space_slip(x, L, a, eta, xi, r_cut, psi_r, kT, dt):
+def real_space_slip(x, L, a, eta, xi, r_cut, psi_r, kT, dt, strain=0.0):
     """sqrt(2 kT/dt) M_r^{1/2} psi_r (6 per bead) for the PSE real-space part."""
-    Mr = pse.real_mobility(x, L, a, eta, xi, r_cut)
+    Mr = pse.real_mobility(x, L, a, eta, xi, r_cut, strain)
     return amplitude(kT, dt) * sqrt_apply(Mr, np.ravel(psi_r)).reshape(-1, 6)
 
 
-def near_field_force(x, body, L, a, eta, r_lub, psi_nf, kT, dt, eps_min=1e-3, rough=(0.0, 0.0)):
+def near_field_force(x, body, L, a, eta, r_lub, psi_nf, kT, dt, eps_min=1e-3, rough=(0.0, 0.0), strain=0.0):
     """sqrt(2 kT/dt) R_nf^{1/2} psi_nf: 3 per bead (the lubrication model acts on the
     translational rows only); rough = (alpha, h0) as in the lubrication model."""
     n = len(x)
-    R = lub.resistance_matrix(x, body, L, a, eta, r_lub, eps_min, rough).reshape(n, 6, n, 6)
+    R = lub.resistance_matrix(x, body, L, a, eta, r_lub, eps_min, rough, strain).reshape(n, 6, n, 6)
     Rt = R[:, :3, :, :3].reshape(3 * n, 3 * n)
     return amplitude(kT, dt) * sqrt_apply(Rt, np.ravel(psi_nf)).reshape(n, 3)

@@ -88,18 +88,20 @@ def self_terms(a, eta, xi):
     return rpy.mu_t(a, eta) - S[0], rpy.mu_r(a, eta) - S[2]
 
 
-def real_mobility(x, L, a, eta, xi, r_cut):
-    """Dense real-space part: sum over images with |x_i - x_j + n L| < r_cut, plus self."""
+def real_mobility(x, L, a, eta, xi, r_cut, strain=0.0):
+    """Dense real-space part: sum over images with |x_i - x_j + A n| < r_cut, plus self
+    (A n = (n_x + strain n_y, n_y, n_z) L, the sheared lattice; the cube at strain 0)."""
     x = np.asarray(x, dtype=float)
     n = len(x)
     M = np.zeros((n, n, 6, 6))
     nmax = int(math.ceil(r_cut / L)) + 1
     d0 = x[:, None, :] - x[None, :, :]
     rng = range(-nmax, nmax + 1)
-    for nx in rng:
+    mx = nmax + int(math.ceil(abs(strain) * nmax))
+    for nx in range(-mx, mx + 1):
         for ny in rng:
             for nz in rng:
-                d = d0 + L * np.array([nx, ny, nz], dtype=float)
+                d = d0 + L * np.array([nx + strain * ny, ny, nz], dtype=float)
                 r = np.linalg.norm(d, axis=-1)
                 mask = (r < r_cut) & (r > 0)
                 if not mask.any():
@@ -114,11 +116,12 @@ def real_mobility(x, L, a, eta, xi, r_cut):
     return M.transpose(0, 2, 1, 3).reshape(6 * n, 6 * n)
 
 
-def wave_mobility(x, L, a, eta, xi, kc=None):
-    """Dense wave-space part by a direct sum over |k| < kc (default: Gaussian below 1e-20)."""
+def wave_mobility(x, L, a, eta, xi, kc=None, strain=0.0):
+    """Dense wave-space part by a direct sum over |k| < kc (default: Gaussian below 1e-20),
+    over the reciprocal lattice of the (sheared) lattice."""
     if kc is None:
         kc = 2 * xi * math.sqrt(46.0)
-    kv, k2 = rpy.wave_vectors(L, kc)
+    kv, k2 = rpy.wave_vectors(L, kc, strain)
     kn = np.sqrt(k2)
     y = kn * a
     s = np.sin(y) / y

@@ -1026,7 +1026,6 @@ int lanczos_sqrt(fsd_system* s, size_t n, Apply&& apply, const double* z, double
 // u_B = sqrt(2 kT / dt) (M_w^{1/2} psi_w + M_r^{1/2} psi_r) into d_ub (6 per bead) and
 // F_B = sqrt(2 kT / dt) R_nf^{1/2} psi_nf into d_fb (3 per bead, translational)
 void brownian_terms(fsd_system* s) {
-  if (s->le) throw ApiError(FSD_EINVAL, "Brownian motion on the sheared lattice is not built");
   ensure_brownian(s);
   const size_t nb = s->nb;
   const double amp = std::sqrt(2.0 * s->p.kT / s->bdt);
@@ -1040,7 +1039,7 @@ void brownian_terms(fsd_system* s) {
   for (int stage = 0; stage < 5; ++stage)
     launch_wave_fft<double>(grid, s->plan, s->d_tw64, wb, stage, s->st);
   launch_zero(s->d_ub, sizeof(double) * 6 * nb, s->st);
-  launch_interp<double>(s->nb, s->d_pos4, grid, s->wp, s->d_ub, s->st, nullptr, nullptr, nullptr, nullptr, s->spread);
+  mob_interp<double>(s, s->d_ub, nullptr, nullptr);  // the sheared grid's own interpolation when on
   // real space: Lanczos on the pair sum
   if (!s->psi_r_set) launch_normals(6 * nb, kr, s->d_psi_r, s->st);
   s->lan_its[0] = lanczos_sqrt(
@@ -2055,7 +2054,6 @@ fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain) {
   if (!std::isfinite(strain)) return fail(s, FSD_EINVAL, "non-finite strain");
   if (enable) {
     if (!s->le && s->have_agg) return fail(s, FSD_ESTATE, "switch the sheared lattice on before fsd_init_aggregates");
-    if (s->p.kT > 0) return fail(s, FSD_EINVAL, "Brownian motion on the sheared lattice is not built");
     for (int i = 0; i < 9; ++i)
       if (i != 1 && s->G[i] != 0) return fail(s, FSD_EINVAL, "the sheared lattice takes simple shear u_x = G_xy y only");
   }

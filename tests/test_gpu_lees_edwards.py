@@ -8,6 +8,9 @@ long steady-shear runs (Section 4.3).
 - a step that carries a body across a y face: centroid folded with the new strain, which
   advances by G_xy dt;
 - a sheared run of many steps with lubrication stays free of overlaps;
+- the real- and wave-space mobility parts against the oracle's PSE parts on the lattice;
+- the wave-space Brownian root reproduces the sheared wave-space mobility, and a Brownian
+  solve matches the oracle's exact roots and dense solve;
 - argument and state checks.
 """
 import numpy as np
@@ -162,8 +165,84 @@ def test_lees_edwards_arguments(F):
         s.set_lees_edwards(True, 0.1)  # after the aggregates: the grid is fixed
     assert e.value.code == -5  # FSD_ESTATE
     s.close()
-    s = F.System(F.default_params(xi=0.6, ewald_tol=1e-6, kT=1.0))
-    s.init_box(kw["L"])
-    with pytest.raises(F.FsdError):
-        s.set_lees_edwards(True, 0.1)
+
+
+def _beads_system(strain, n=7, L=9.0, seed=66):
+    """Single beads, at least 2.2 a apart in the sheared lattice."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(-L / 2, L / 2, 3)
+        if all(np.linalg.norm(lub.min_image(p - q, L, strain)) >= 2.2 for q in pts):
+            pts.append(p)
+    return dict(L=L, a=1.0, eta=1.0, offsets=np.arange(n + 1, dtype=np.int32), x_body=np.zeros((n, 3)),
+                com=np.array(pts), quat=np.tile([1.0, 0, 0, 0], (n, 1)), force=np.zeros((n, 6)),
+                grad_u=np.zeros((3, 3)), r_lub=0.0)
+
+
+@pytest.mark.parametrize("strain", [0.43, -0.27])
+def test_mobility_parts_match_oracle(F, strain):
+    """The real- and wave-space parts of the mobility on the sheared lattice against the
+    oracle's PSE parts on the same lattice, and their sum against its Ewald sum."""
+    from oracle import pse, rpy
+    kw = _beads_system(strain)
+    s = _make(F, kw, strain, xi=0.7)
+    inf = s.info()
+    n = len(kw["com"])
+    lam = np.random.default_rng(4).normal(size=6 * n)
+    x = rigid.wrap(kw["com"], kw["L"], strain)
+    ref_r = pse.real_mobility(x, kw["L"], 1.0, 1.0, 0.7, inf.r_cut, strain) @ lam
+    ref_w = pse.wave_mobility(x, kw["L"], 1.0, 1.0, 0.7, strain=strain) @ lam
+    sc = np.abs(ref_r + ref_w).max()
+    assert np.abs(s.apply_mobility(lam, parts=1) - ref_r).max() < 1e-8 * sc
+    assert np.abs(s.apply_mobility(lam, parts=2) - ref_w).max() < 1e-8 * sc
+    ref = rpy.periodic_mobility(x, kw["L"], 1.0, 1.0, strain=strain) @ lam
+    assert np.abs(s.apply_mobility(lam, parts=3) - ref).max() < 1e-8 * sc
+    s.close()
+
+
+def test_wave_square_root_on_sheared_lattice(F):
+    """sum over unit grid noises e_m of (B e_m)(B e_m)^T = M_w on the sheared grid."""
+    kw = _beads_system(0.37, n=3, L=9.0, seed=67)
+    s = _make(F, kw, 0.37, xi=0.4, ewald_tol=1e-3, grid=8, kT=0.5)
+    s.set_brownian(1.0)
+    N, nb = s.info().grid, s.n_bead
+    assert N == 8
+    zr = np.zeros(6 * nb)
+    cols = []
+    e = np.zeros(3 * N ** 3)
+    for m in range(3 * N ** 3):
+        e[:] = 0
+        e[m] = 1.0
+        s.set_noise(psi_w=e, psi_r=zr)
+        u, _, _ = s.brownian_terms()
+        cols.append(u.ravel())
+    Bm = np.array(cols).T
+    Mw = np.column_stack([s.apply_mobility(c, parts=2) for c in np.eye(6 * nb)])
+    assert np.abs(Bm @ Bm.T - Mw).max() <= 1e-12 * np.abs(Mw).max()
+    s.close()
+
+
+def test_brownian_solve_on_sheared_lattice(F):
+    """A Brownian solve with explicit real-space and near-field noise (grid noise zero)
+    against the oracle's exact roots and dense solve on the same lattice."""
+    from oracle import brownian
+    strain = -0.33
+    kw = _system(strain, seed=68)
+    s = _make(F, kw, strain, kT=0.8, lanczos_tol=1e-12)
+    s.set_brownian(0.01)
+    info = s.info()
+    nb = s.n_bead
+    rng = np.random.default_rng(69)
+    psi_r, psi_nf = rng.normal(size=6 * nb), rng.normal(size=3 * nb)
+    s.set_noise(psi_w=np.zeros(3 * info.grid ** 3), psi_r=psi_r, psi_nf=psi_nf)
+    U, _, _ = s.solve()
+    A = saddle.assemble(**kw, strain=strain)
+    body = rigid.body_index(kw["offsets"])
+    ub = brownian.real_space_slip(A.x, kw["L"], 1.0, 1.0, info.xi, info.r_cut, psi_r, 0.8, 0.01, strain=strain)
+    fb3 = brownian.near_field_force(A.x, body, kw["L"], 1.0, 1.0, 3.0, psi_nf, 0.8, 0.01, strain=strain)
+    fb = np.zeros((nb, 6))
+    fb[:, :3] = fb3
+    Uo, *_ = saddle.solve(**kw, u_brown=ub, f_brown_nf=fb, strain=strain)
+    assert _rel(U[:, :3], Uo[:, :3]) < 1e-7 and _rel(U[:, 3:], Uo[:, 3:]) < 1e-7
     s.close()

@@ -17,7 +17,7 @@ import itertools
 
 import numpy as np
 
-from oracle import forces, lub, rigid, rpy
+from oracle import forces, lub, pse, rigid, rpy
 
 L = 7.0
 
@@ -95,3 +95,14 @@ def test_force_images_agree_with_nearest_image_pairs():
         ref[a] += fv
         ref[b] -= fv
     assert np.allclose(f, ref, atol=1e-12)
+
+
+def test_pse_split_sums_to_the_ewald_mobility_on_sheared_lattice():
+    """The PSE (Hasimoto) real- and wave-space parts on the sheared lattice add up to the
+    Beenakker-split mobility on the same lattice: two different splits of one lattice sum."""
+    x = _beads()[:3]
+    g, xi = -0.31, 0.8
+    Mr = pse.real_mobility(x, L, 1.0, 1.0, xi, 7.0 / xi, strain=g)
+    Mw = pse.wave_mobility(x, L, 1.0, 1.0, xi, strain=g)
+    M = rpy.periodic_mobility(x, L, xi=0.9, strain=g)
+    assert np.abs(Mr + Mw - M).max() <= 1e-9 * np.abs(M).max()
