@@ -889,6 +889,17 @@ void apply_precond(fsd_system* s, const double* src, double* z, const int* skip 
                        z, s->st, skip);
 }
 
+// Euler update of the centroids and orientations by the velocities in d_U (Eqs. `EM1`,
+// `EM2`); on the sheared lattice the strain first advances with the flow u_x = G_xy y, and
+// the centroids are folded into the new lattice
+void integrate_step(fsd_system* s, double dt) {
+  if (s->le) {
+    const double g = s->strain + s->G[1] * dt;
+    s->strain = g - std::floor(g + 0.5);
+  }
+  launch_integrate(s->na, s->d_U, dt, s->L, s->gam(), s->d_com, s->d_quat, s->st);
+}
+
 // ---- Brownian terms (Eq. `SP2`, Algorithm 1 step 3) ------------------------------------------
 
 void ensure_brownian(fsd_system* s) {
@@ -1760,11 +1771,7 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
       if (r != FSD_OK) return r;
       if (fixman) fixman_drift(s, dt);
       if (rfd || fixman) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
-      if (s->le) {  // the lattice shears with the flow u_x = G_xy y; fold into the new lattice
-        const double g = s->strain + s->G[1] * dt;
-        s->strain = g - std::floor(g + 0.5);
-      }
-      launch_integrate(s->na, s->d_U, dt, s->L, s->gam(), s->d_com, s->d_quat, s->st);
+      integrate_step(s, dt);
       s->prepared = false;
       ++s->bstep;
     }
@@ -2326,7 +2333,7 @@ fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
         --remaining;
         if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
         if (integrate && s->sv.status == FSD_OK) {
-          launch_integrate(s->na, s->d_U, dt, s->L, 0.0, s->d_com, s->d_quat, s->st);
+          integrate_step(s, dt);
           s->prepared = false;
           ++s->bstep;
         }
@@ -2406,7 +2413,7 @@ bool fusable(const std::vector<fsd_system*>& act) {
   if (act.empty()) return false;
   const int prec = act[0]->p.precision, m = act[0]->m;
   for (auto* s : act) {
-    if (s->p.precision != prec || s->m != m || !cgs_fits(m + 1) || s->timing) return false;
+    if (s->p.precision != prec || s->m != m || !cgs_fits(m + 1) || s->timing || s->le) return false;
     if (!s->spread || s->wp.n % 8) return false;
   }
   return true;
@@ -2580,7 +2587,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     fsd_system* s = act[k];
     if (integrate && s->sv.status == FSD_OK) {
       fsd_status r = guarded(s, [&]() -> fsd_status {
-        launch_integrate(s->na, s->d_U, dt, s->L, 0.0, s->d_com, s->d_quat, s->st);
+        integrate_step(s, dt);
         s->prepared = false;
         ++s->bstep;
         return FSD_OK;
@@ -2630,7 +2637,6 @@ fsd_status fsd_batch_admit(fsd_batch* b, fsd_system* s, int* slot) {
   if (!s->have_agg) return FSD_ESTATE;
   for (auto* q : b->slot)
     if (q == s) return FSD_EINVAL;
-  if (s->le) return fail(s, FSD_EINVAL, "systems on a sheared lattice run through fsd_step and fsd_solve only");
   const size_t need = system_bytes(s);
   if (b->used + need > b->budget) {
     b->err = "memory budget exhausted";

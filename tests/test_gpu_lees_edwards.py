@@ -11,6 +11,7 @@ long steady-shear runs (Section 4.3).
 - the real- and wave-space mobility parts against the oracle's PSE parts on the lattice;
 - the wave-space Brownian root reproduces the sheared wave-space mobility, and a Brownian
   solve matches the oracle's exact roots and dense solve;
+- a batch with a sheared system steps every system as it steps alone;
 - argument and state checks.
 """
 import numpy as np
@@ -153,10 +154,6 @@ def test_lees_edwards_arguments(F):
         s.set_shear(np.diag([1.0, -1.0, 0.0]))  # not simple shear
     s.set_lees_edwards(True, 0.7)  # strain may be reset; folded into [-1/2, 1/2)
     assert abs(s.strain() - (-0.3)) < 1e-15
-    b = F.Batch(1 << 32, 2)
-    with pytest.raises(F.FsdError):
-        b.admit(s)
-    b.close()
     s.close()
     s = F.System(F.default_params(xi=0.6, ewald_tol=1e-6))
     s.init_box(kw["L"])
@@ -246,3 +243,29 @@ def test_brownian_solve_on_sheared_lattice(F):
     Uo, *_ = saddle.solve(**kw, u_brown=ub, f_brown_nf=fb, strain=strain)
     assert _rel(U[:, :3], Uo[:, :3]) < 1e-7 and _rel(U[:, 3:], Uo[:, 3:]) < 1e-7
     s.close()
+
+
+def test_batch_with_a_sheared_system(F):
+    """A batch holding a system on the sheared lattice beside one on the cube runs each on
+    its own stream: every system steps exactly as it does alone, strain included."""
+    kw1, kw2 = _system(0.21, seed=70), _system(0.0, seed=71)
+    alone = [_make(F, kw1, 0.21), _make(F, kw2, 0.0)]
+    alone[1].set_lees_edwards(False)
+    mixed = [_make(F, kw1, 0.21), _make(F, kw2, 0.0)]
+    mixed[1].set_lees_edwards(False)
+    b = F.Batch(1 << 34, 2)
+    b.set_fused(True)  # asks for the multi-system launches; the sheared system declines them
+    for s in mixed:
+        b.admit(s)
+    for _ in range(3):
+        assert b.step(0.01) == 0
+        for s in alone:
+            assert s.step(0.01, 1).status == 0
+    for s, t in zip(alone, mixed):
+        (Xa, qa), (Xb, qb) = s.state(), t.state()
+        assert np.abs(Xa - Xb).max() < 1e-12 and np.abs(qa - qb).max() < 1e-12
+        assert s.strain() == t.strain()
+    assert abs(mixed[0].strain() - 0.24) < 1e-14
+    b.close()
+    for s in alone + mixed:
+        s.close()
