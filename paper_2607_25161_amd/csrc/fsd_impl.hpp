@@ -62,6 +62,9 @@ struct WaveParams {
   double scale;     // h^6 / V * (normalisation of the two Gaussians)^2
   int brownian;     // 1: the z pass applies the square-root multiplier to grid noise
   double gam;       // strain of the sheared lattice (0: cube); see launch_bead_positions
+  // Green's multipliers by |m|^2 = m_x^2 + m_y^2 + m_z^2 on the cube (5 per entry: sinc(ka),
+  // jv(ka), the solve's and the Brownian root's scalar factors, 1/|k|), or nullptr
+  const double* gtab;
 };
 
 // Constants of the real-space part.

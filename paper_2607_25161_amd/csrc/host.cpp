@@ -610,6 +610,36 @@ void upload_tables(fsd_system* s) {
   s->d_tw32 = dalloc<float>(s->owned, 2 * N);
   HIPCHK(hipMemcpy(s->d_tw64, tw.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(s->d_tw32, twf.data(), 2 * N * sizeof(float), hipMemcpyHostToDevice));
+  // Green's multipliers on the cube by q = |m|^2 (k = 2 pi m / L): sinc(ka), jv(ka) =
+  // 3 (sin x - x cos x) / x^3, the solve's factor scale H~(k) / k^2 and the Brownian root's
+  // sqrt(scale H~(k) / N^3) / k, with H~ = (1 + q~) e^{-(1 - eta~) q~} / eta, q~ = k^2 / 4 xi^2
+  const WaveParams& w = s->wp;
+  const int Q = 3 * (N / 2) * (N / 2);
+  std::vector<double> gt(5 * size_t(Q + 1), 0.0);
+  const double tp = 2.0 * M_PI / w.L;
+  for (int q = 1; q <= Q; ++q) {
+    const double k2 = tp * tp * q, kn = std::sqrt(k2), x = kn * w.a;
+    double sk, jk;
+    if (x < 0.5) {  // the same series the device uses below 0.5
+      const double x2 = x * x;
+      sk = 1.0 - x2 / 6.0 * (1.0 - x2 / 20.0 * (1.0 - x2 / 42.0 * (1.0 - x2 / 72.0 * (1.0 - x2 / 110.0))));
+      jk = 1.0 - x2 / 10.0 * (1.0 - x2 / 28.0 * (1.0 - x2 / 54.0 * (1.0 - x2 / 88.0 * (1.0 - x2 / 130.0))));
+    } else {
+      sk = std::sin(x) / x;
+      jk = 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+    }
+    const double qq = k2 / (4.0 * w.xi * w.xi);
+    const double damp = (1.0 + qq) * std::exp(-(1.0 - w.eta_t) * qq) / w.eta;
+    double* g = &gt[5 * size_t(q)];
+    g[0] = sk;
+    g[1] = jk;
+    g[2] = w.scale * damp / k2;
+    g[3] = std::sqrt(w.scale / (double(N) * N * N) * damp) / kn;
+    g[4] = 1.0 / kn;
+  }
+  double* d_gt = dalloc<double>(s->owned, gt.size());
+  HIPCHK(hipMemcpy(d_gt, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice));
+  s->wp.gtab = d_gt;
 }
 
 // grow a column buffer (the only allocation after set-up)
@@ -2282,7 +2312,9 @@ struct fsd_batch {
 
 namespace {
 size_t system_bytes(const fsd_system* s) {
-  return fsd_estimate_bytes(&s->p, s->nb, s->na, s->L);
+  fsd_params p = s->p;
+  p.grid = s->wp.n;  // the grid it holds (larger on a sheared lattice than the rule gives)
+  return fsd_estimate_bytes(&p, s->nb, s->na, s->L);
 }
 
 // One solve (and optionally an Euler step) for every admitted system.  Each system

@@ -1439,24 +1439,34 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     }
     // Cartesian wave vector of grid mode m: (2 pi / L)(m_x, m_y - gam m_x, m_z) (the
     // reciprocal lattice of the sheared lattice; gam = 0 for the cube)
-    const int mx = kx <= N / 2 ? kx : kx - N;
-    const double k[3] = {tp * mx, tp * ((ky < N / 2 ? ky : ky - N) - wp.gam * mx), tp * (kz < N / 2 ? kz : kz - N)};
-    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    const double kn = sqrt(k2);
-    const double kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
-    double sk, jk;
-    sinc_jv_d(kn * wp.a, sk, jk);
-    const double qq = k2 / (4.0 * wp.xi * wp.xi);
-    const double damp = (1.0 + qq) * exp(-(1.0 - wp.eta_t) * qq) / wp.eta;
-    double gr[3], gi[3], Bk;
+    // signed mode numbers in [-N/2, N/2] (an even N's N/2 modes were zeroed above; an odd N
+    // keeps the symmetric range), so |m|^2 <= 3 (N/2)^2 indexes the multiplier table
+    const int mx = kx <= N / 2 ? kx : kx - N, my = ky <= N / 2 ? ky : ky - N, mz = kz <= N / 2 ? kz : kz - N;
+    const double k[3] = {tp * mx, tp * (my - wp.gam * mx), tp * mz};
+    double sk, jk, Bk, ikn;
+    if (wp.gtab && wp.gam == 0.0) {  // the multipliers depend on the integer |m|^2 alone
+      const double* gt = wp.gtab + 5 * (mx * mx + my * my + mz * mz);
+      sk = gt[0];
+      jk = gt[1];
+      Bk = wp.brownian ? gt[3] : gt[2];
+      ikn = gt[4];
+    } else {
+      const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+      const double kn = sqrt(k2);
+      ikn = 1.0 / kn;
+      sinc_jv_d(kn * wp.a, sk, jk);
+      const double qq = k2 / (4.0 * wp.xi * wp.xi);
+      const double damp = (1.0 + qq) * exp(-(1.0 - wp.eta_t) * qq) / wp.eta;
+      Bk = wp.brownian ? sqrt(wp.scale / (double(N) * N * N) * damp) * ikn : wp.scale * damp / k2;
+    }
+    const double kh[3] = {k[0] * ikn, k[1] * ikn, k[2] * ikn};
+    double gr[3], gi[3];
     if (wp.brownian) {
-      Bk = sqrt(wp.scale / (double(N) * N * N) * damp) / kn;
       for (int a = 0; a < 3; ++a) {
         gr[a] = Fr[a];
         gi[a] = Fi[a];
       }
     } else {
-      Bk = wp.scale * damp / k2;
       const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
       const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
       for (int a = 0; a < 3; ++a) {

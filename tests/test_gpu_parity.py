@@ -123,6 +123,19 @@ def test_mobility_real_and_wave_parts(F, xi, L, n):
     assert np.abs(ut - Mb @ lam).max() < 1e-8 * sc
 
 
+@pytest.mark.parametrize("grid", [27, 36])
+def test_wave_part_on_odd_and_uneven_grids(F, grid):
+    """Explicit grids that are odd (no Nyquist modes, symmetric mode range) or not a multiple
+    of 8 (scatter spreading) give the oracle's wave-space part."""
+    kw = _single_beads(6, 11.0, 31)
+    s = _make(F, kw, xi=0.6, grid=grid)
+    assert s.info().grid == grid
+    lam = np.random.default_rng(5).normal(size=36)
+    ref = pse.wave_mobility(kw["com"], 11.0, 1.0, 1.0, 0.6) @ lam
+    assert np.abs(s.apply_mobility(lam, parts=2) - ref).max() < 1e-8 * np.abs(ref).max()
+    s.close()
+
+
 def test_mobility_fp32_within_single_precision(F):
     kw = _single_beads(12, 13.0, 5)
     s = _make(F, kw, xi=0.6, ewald_tol=1e-6)
