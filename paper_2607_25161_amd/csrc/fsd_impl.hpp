@@ -278,6 +278,12 @@ void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const d
 void launch_cgs_chain(int mode, size_t n, int nq, const double* V, size_t ldv, const double* pin, double* w,
                       double* pout, double* hout, hipStream_t st, const int* skip);
 void launch_arnoldi_reduce(const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st);
+// the preconditioner of step j+1 (z = P^-1 v, v_(j+1) = w / ||w|| stored to vout) with step
+// j's Arnoldi update (a.j = j; ||w||^2 partials pin of nblk workgroups) folded in
+void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
+                            double drag_t, double drag_r, const double* src, double* vout, double* z,
+                            const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st,
+                            const int* skip);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
 
 // ---- Brownian terms (k_brownian.hip) ------------------------------------------------------

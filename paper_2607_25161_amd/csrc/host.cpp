@@ -1179,16 +1179,26 @@ void seg_batch(fsd_system* s, int j0) {
   const int* stop = &s->d_ctl->stop;
   const bool fp32 = v.fp32;
   run_body(s, {1, j0, cnt, fp32 ? 1 : 0, nullptr, nullptr}, [&] {
+    const size_t G = cgs_blocks(n);
+    double *P0 = s->d_part, *P1 = s->d_part + 32 * G, *P2 = s->d_part + 64 * G;
     for (int j = j0; j < j0 + cnt; ++j) {
-      // v_j = w / H[j, j-1] (r / beta for j = 0) is formed inside the preconditioner
-      apply_precond(s, j == 0 ? s->d_r : s->d_w, s->d_z, stop, s->d_scal, V + size_t(j) * n);
+      // v_j = w / H[j, j-1] (r / beta for j = 0) is formed inside the preconditioner.  Inside
+      // a segment the Arnoldi update of step j-1 rides in this launch (its ||w||^2 partials
+      // are in P2); a segment's last step makes its update alone, so the host reads a current
+      // stop flag after every segment.
+      if (j > j0 && cgs_fits(j)) {
+        Timed t(s, FSD_TIMER_PRECOND, 8.0 * n * 3 + 32.0 * s->nb + 312.0 * s->na);
+        const ArnoldiArgs prev{j - 1, s->d_ctl, h1, h2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal};
+        launch_precond_arnoldi(s->nb, s->na, s->d_offsets, s->d_r4, s->d_lu, s->d_piv, s->drag_t, s->drag_r, s->d_w,
+                               V + size_t(j) * n, s->d_z, prev, P2, int(G), hn2, s->st, stop);
+      } else {
+        apply_precond(s, j == 0 ? s->d_r : s->d_w, s->d_z, stop, s->d_scal, V + size_t(j) * n);
+      }
       apply_saddle_p(s, s->d_z, s->d_w, fp32, stop);
       const ArnoldiArgs arn{j, s->d_ctl, h1, h2, s->d_H, s->d_cs, s->d_sn, s->d_g, s->d_scal};
       const int nq = j + 1;
       if (cgs_fits(nq)) {
         // fence-free chain: three partial arrays, each reduced by the next launch
-        const size_t G = cgs_blocks(n);
-        double *P0 = s->d_part, *P1 = s->d_part + 32 * G, *P2 = s->d_part + 64 * G;
         {
           Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));
           launch_cgs_chain(0, n, nq, V, n, nullptr, s->d_w, P0, nullptr, s->st, stop);
@@ -1201,7 +1211,7 @@ void seg_batch(fsd_system* s, int j0) {
           Timed t(s, FSD_TIMER_CGS_NORM, 8.0 * n * (nq + 2));
           launch_cgs_chain(2, n, nq, V, n, P1, s->d_w, P2, h2, s->st, stop);
         }
-        launch_arnoldi_reduce(arn, P2, int(G), hn2, s->st);
+        if (j == j0 + cnt - 1) launch_arnoldi_reduce(arn, P2, int(G), hn2, s->st);  // else folded into step j+1
       } else {
         {
           Timed t(s, FSD_TIMER_CGS_DOT, 8.0 * n * (nq + 1));

@@ -868,6 +868,45 @@ void launch_arnoldi_reduce(const ArnoldiArgs& a, const double* pin, int nblk, do
   k_arnoldi_reduce<<<1, kCgsThreads, 0, st>>>(a, pin, nblk, hn2);
 }
 
+// The preconditioner of Arnoldi step j+1 with step j's Arnoldi update folded in: every
+// workgroup reduces the ||w||^2 partials in the same fixed order (so all hold the same
+// value), takes v_(j+1) = w / ||w|| and applies the preconditioner; workgroup 0 also makes
+// the Hessenberg/Givens update and the stop decision of step j.  Once that update stops the
+// cycle, the vectors this launch writes are not used.
+__global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const int* __restrict__ offsets,
+                                                         const double4* __restrict__ r4, const double* __restrict__ lu,
+                                                         const int* __restrict__ piv, double drag_t, double drag_r,
+                                                         const double* __restrict__ src, double* __restrict__ vout,
+                                                         double* __restrict__ z, ArnoldiArgs a,
+                                                         const double* __restrict__ pin, int nblk,
+                                                         double* __restrict__ hn2, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double shq[8 * 32];
+  __shared__ double tot[kCgsMax];
+  __shared__ double st[3][kCgsMax];
+  __shared__ double sc;
+  reduce_partials(pin, nblk, 1, shq, tot);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *hn2 = tot[0];
+    arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
+  }
+  if (threadIdx.x == 0) {
+    const double hn = sqrt(fmax(tot[0], 0.0));  // as the update's scal
+    sc = hn > 0 ? 1.0 / hn : 0.0;
+  }
+  __syncthreads();
+  precond_fused_body(nb, na, offsets, r4, lu, piv, drag_t, drag_r, src, &sc, vout, z, nullptr, blockIdx.x, blockIdx.y,
+                     gridDim.x);
+}
+
+void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
+                            double drag_t, double drag_r, const double* src, double* vout, double* z,
+                            const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st,
+                            const int* skip) {
+  launch_k(k_precond_arnoldi, (na + 3) / 4, 256, 0, st, nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r,
+           src, vout, z, a, pin, nblk, hn2, skip);
+}
+
 void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
                 double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
                 const ArnoldiArgs* arn) {
