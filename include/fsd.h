@@ -363,7 +363,7 @@ typedef enum {
 
 /* GMRES launch mode: enable = 1 replays cached HIP graphs (cycle start, batches of
  * `batch` Arnoldi steps, cycle end; default), 0 launches every kernel eagerly.
- * batch = 0 keeps the current batch size (default 4).  Graphs are rebuilt when
+ * batch = 0 keeps the current batch size (default 8).  Graphs are rebuilt when
  * the neighbour-list storage or launch shapes change. */
 fsd_status fsd_set_graphs(fsd_system* s, int enable, int batch);
 
