@@ -613,18 +613,18 @@ __global__ void k_bead_prep(int nb, const double4* __restrict__ pos, WaveParams 
   vals[i] = i;
 }
 
+// one thread per copied weight: consecutive threads move consecutive weights of a bead
 __global__ void k_bead_permute(int nb, int P3, const int* __restrict__ perm, const double* __restrict__ w_in,
                                const int4* __restrict__ s_in, double* __restrict__ w_out, float* __restrict__ w32,
                                int4* __restrict__ s_out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nb) return;
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= size_t(nb) * P3) return;
+  const int k = int(t / P3), q = int(t - size_t(k) * P3);
   const int i = perm[k];
-  for (int q = 0; q < P3; ++q) {
-    const double v = w_in[size_t(i) * P3 + q];
-    w_out[size_t(k) * P3 + q] = v;
-    w32[size_t(k) * P3 + q] = float(v);
-  }
-  s_out[k] = s_in[i];
+  const double v = w_in[size_t(i) * P3 + q];
+  w_out[t] = v;
+  w32[t] = float(v);
+  if (q == 0) s_out[k] = s_in[i];
 }
 
 __global__ void k_bin_bounds(int nb, const int* __restrict__ keys, int* start, int* end) {
@@ -650,7 +650,8 @@ hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WavePara
   if ((e = hipMemsetAsync(sp->bin_start, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(sp->bin_end, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
   k_bin_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, sp->keys_out, sp->bin_start, sp->bin_end);
-  k_bead_permute<<<nblocks(nb), kThreads, 0, st>>>(nb, 3 * sp->P, sp->perm, w, sp->stmp, sp->weights,
+  k_bead_permute<<<nblocks((long long)nb * 3 * sp->P), kThreads, 0, st>>>(nb, 3 * sp->P, sp->perm, w, sp->stmp,
+                                                                         sp->weights,
                                                    sp->weights32, sp->starts);
   return hipGetLastError();
 }

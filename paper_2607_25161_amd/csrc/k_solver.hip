@@ -336,13 +336,29 @@ void launch_arnoldi_step(const ArnoldiArgs& a, const double* hn2, hipStream_t st
 }
 
 // y = R^-1 g over the k_used leading rows of the rotated Hessenberg matrix
-__global__ void k_gmres_solve(const GmresCtl* ctl, const double* __restrict__ H, const double* __restrict__ g,
-                              double* __restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int k = ctl->k_used, m = ctl->m;
+// y = H^-1 g for the k_used x k_used upper-triangular Hessenberg part (row stride m).  Up to
+// 64 columns one wavefront works column by column from LDS: lane q holds row q's running
+// value, lane i divides, and y_i reaches the lanes above by a shuffle; larger k go row by row.
+__global__ __launch_bounds__(64) void k_gmres_solve(const GmresCtl* ctl, const double* __restrict__ H,
+                                                    const double* __restrict__ g, double* __restrict__ y) {
+  if (blockIdx.x != 0) return;
+  const int k = ctl->k_used, m = ctl->m, q = threadIdx.x;
+  if (k <= 64) {
+    __shared__ double sh[64 * 64];
+    for (int e = q; e < k * k; e += 64) sh[e] = H[size_t(e / k) * m + e % k];
+    __syncthreads();
+    double t = q < k ? g[q] : 0.0;
+    for (int i = k - 1; i >= 0; --i) {
+      const double yi = __shfl(q == i ? t / sh[i * k + i] : 0.0, i, 64);
+      if (q == i) y[i] = yi;
+      if (q < i) t -= sh[q * k + i] * yi;
+    }
+    return;
+  }
+  if (q != 0) return;
   for (int i = k - 1; i >= 0; --i) {
     double t = g[i];
-    for (int q = i + 1; q < k; ++q) t -= H[size_t(i) * m + q] * y[q];
+    for (int c = i + 1; c < k; ++c) t -= H[size_t(i) * m + c] * y[c];
     y[i] = t / H[size_t(i) * m + i];
   }
 }
