@@ -896,7 +896,13 @@ __global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const i
                                                          double* __restrict__ z, ArnoldiArgs a,
                                                          const double* __restrict__ pin, int nblk,
                                                          double* __restrict__ hn2, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  // workgroup 0 of this very launch may raise the stop flag while others start, so each
+  // workgroup reads it once and all its wavefronts take the same branch (the barriers
+  // below need every wavefront)
+  __shared__ int quit;
+  if (threadIdx.x == 0) quit = skip ? __atomic_load_n(skip, __ATOMIC_RELAXED) : 0;
+  __syncthreads();
+  if (quit) return;
   __shared__ double shq[8 * 32];
   __shared__ double tot[kCgsMax];
   __shared__ double st[3][kCgsMax];
