@@ -31,26 +31,27 @@ def rotate(quat, phi):
     return q / np.linalg.norm(q, axis=1, keepdims=True)
 
 
-def displace(com, quat, dq, h, L):
+def displace(com, quat, dq, h, L, strain=0.0):
     dq = np.asarray(dq, dtype=float).reshape(-1, 6)
-    X = rigid.wrap(np.asarray(com, dtype=float) + h * dq[:, :3], L)
+    X = rigid.wrap(np.asarray(com, dtype=float) + h * dq[:, :3], L, strain)
     return X, rotate(quat, h * dq[:, 3:])
 
 
-def mobility_velocity(L, a, eta, offsets, x_body, com, quat, ft, r_lub=0.0, xi=None):
-    """U = N(q) ft: the saddle solve with aggregate forces and torques ft and nothing else."""
+def mobility_velocity(L, a, eta, offsets, x_body, com, quat, ft, r_lub=0.0, xi=None, strain=0.0):
+    """U = N(q) ft: the saddle solve with aggregate forces and torques ft and nothing else
+    (on the lattice of the given strain)."""
     na = len(offsets) - 1
     U, *_ = saddle.solve(L, a, eta, offsets, x_body, com, quat, np.asarray(ft, dtype=float).reshape(na, 6),
-                         np.zeros((3, 3)), r_lub=r_lub, xi=xi)
+                         np.zeros((3, 3)), r_lub=r_lub, xi=xi, strain=strain)
     return U
 
 
-def rfd_drift(L, a, eta, offsets, x_body, com, quat, dq, eps, kT, r_lub=0.0, xi=None):
+def rfd_drift(L, a, eta, offsets, x_body, com, quat, dq, eps, kT, r_lub=0.0, xi=None, strain=0.0):
     """kT (U+ - U-) / eps for the given Gaussian vector dq (N, 6)."""
-    Xp, qp = displace(com, quat, dq, +0.5 * eps, L)
-    Xm, qm = displace(com, quat, dq, -0.5 * eps, L)
-    Up = mobility_velocity(L, a, eta, offsets, x_body, Xp, qp, dq, r_lub, xi)
-    Um = mobility_velocity(L, a, eta, offsets, x_body, Xm, qm, dq, r_lub, xi)
+    Xp, qp = displace(com, quat, dq, +0.5 * eps, L, strain)
+    Xm, qm = displace(com, quat, dq, -0.5 * eps, L, strain)
+    Up = mobility_velocity(L, a, eta, offsets, x_body, Xp, qp, dq, r_lub, xi, strain)
+    Um = mobility_velocity(L, a, eta, offsets, x_body, Xm, qm, dq, r_lub, xi, strain)
     return kT * (Up - Um) / eps
 
 
@@ -81,22 +82,22 @@ def divergence(L, a, eta, offsets, x_body, com, quat, h=1e-4, r_lub=0.0, xi=None
     return div.reshape(na, 6)
 
 
-def brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub=0.0, xi=None):
+def brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub=0.0, xi=None, strain=0.0):
     """Aggregate velocities of the saddle solve whose right-hand side holds only the given
     Brownian slip u_b (6 per bead) and near-field force f_b (3 per bead)."""
     na = len(offsets) - 1
     fb6 = np.zeros((len(f_b), 6))
     fb6[:, :3] = np.asarray(f_b, dtype=float).reshape(-1, 3)
     U, *_ = saddle.solve(L, a, eta, offsets, x_body, com, quat, np.zeros((na, 6)), np.zeros((3, 3)), r_lub=r_lub,
-                         xi=xi, u_brown=np.asarray(u_b, dtype=float).reshape(-1, 6), f_brown_nf=fb6)
+                         xi=xi, u_brown=np.asarray(u_b, dtype=float).reshape(-1, 6), f_brown_nf=fb6, strain=strain)
     return U
 
 
-def fixman_drift(L, a, eta, offsets, x_body, com, quat, u_b, f_b, m, dt, r_lub=0.0, xi=None):
+def fixman_drift(L, a, eta, offsets, x_body, com, quat, u_b, f_b, m, dt, r_lub=0.0, xi=None, strain=0.0):
     """Fixman's midpoint estimate (Appendix A): U0 from the Brownian terms at x, the
-    configuration advanced by U0 dt/m, U' from the same Brownian terms there, and
-    drift = (m/2) (U' - U0)."""
-    U0 = brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub, xi)
-    X1, q1 = integrate.euler_step(com, quat, U0, dt / m, L)
-    U1 = brownian_velocity(L, a, eta, offsets, x_body, X1, q1, u_b, f_b, r_lub, xi)
+    configuration advanced by U0 dt/m (on the same lattice), U' from the same Brownian terms
+    there, and drift = (m/2) (U' - U0)."""
+    U0 = brownian_velocity(L, a, eta, offsets, x_body, com, quat, u_b, f_b, r_lub, xi, strain)
+    X1, q1 = integrate.euler_step(com, quat, U0, dt / m, L, strain)
+    U1 = brownian_velocity(L, a, eta, offsets, x_body, X1, q1, u_b, f_b, r_lub, xi, strain)
     return 0.5 * m * (U1 - U0)

@@ -12,6 +12,7 @@ long steady-shear runs (Section 4.3).
 - the wave-space Brownian root reproduces the sheared wave-space mobility, and a Brownian
   solve matches the oracle's exact roots and dense solve;
 - a batch with a sheared system steps every system as it steps alone;
+- both Brownian-drift estimators against the oracle's solves on the lattice;
 - argument and state checks.
 """
 import numpy as np
@@ -269,3 +270,39 @@ def test_batch_with_a_sheared_system(F):
     b.close()
     for s in alone + mixed:
         s.close()
+
+
+def test_drift_estimators_on_sheared_lattice(F):
+    """The random-finite-difference drift for a given dq, and a step with Fixman's drift,
+    against the oracle's dense solves on the same lattice."""
+    from oracle import drift
+    strain = 0.27
+    kw = _system(strain, seed=72)
+    kw["grad_u"] = np.zeros((3, 3))  # drift right-hand sides hold no ambient flow; keep the step's simple
+    s = _make(F, kw, strain, kT=0.7, gmres_tol=1e-12)
+    eps = 1e-3
+    s.set_drift(0, eps)
+    dq = np.random.default_rng(73).normal(size=(len(kw["offsets"]) - 1, 6))
+    d = s.rfd_drift(dq)
+    ref = drift.rfd_drift(kw["L"], 1.0, 1.0, kw["offsets"], kw["x_body"], kw["com"], kw["quat"], dq, eps, 0.7,
+                          r_lub=kw["r_lub"], strain=strain)
+    assert np.linalg.norm(d - ref) <= 1e-6 * np.linalg.norm(ref)
+    dt, m = 1e-3, 100.0
+    nb = s.n_bead
+    rng = np.random.default_rng(74)
+    s.set_brownian(dt, step=3)
+    s.set_noise(psi_w=np.zeros(3 * s.info().grid ** 3), psi_r=rng.normal(size=6 * nb), psi_nf=rng.normal(size=3 * nb))
+    U, _, _ = s.solve()
+    ub, fb, _ = s.brownian_terms()
+    X0, q0 = s.state()
+    s.set_drift(2, m)
+    s.step(dt, 1)
+    X1, q1 = s.state()
+    dfx = drift.fixman_drift(kw["L"], 1.0, 1.0, kw["offsets"], kw["x_body"], kw["com"], kw["quat"], ub, fb, m, dt,
+                             r_lub=kw["r_lub"], strain=strain)
+    Xo, qo = integrate.euler_step(X0, q0, U + dfx, dt, kw["L"], strain=strain)  # no shear: the strain stays
+    Xn, qn = integrate.euler_step(X0, q0, U, dt, kw["L"], strain=strain)
+    for got, want, base in ((X1, Xo, Xn), (q1, qo, qn)):
+        assert np.abs(want - base).max() > 1e-8
+        assert np.abs(got - want).max() <= 1e-4 * np.abs(want - base).max(), np.abs(got - want).max()
+    s.close()
