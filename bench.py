@@ -5,7 +5,10 @@ lubrication and preconditioner set-up, the right-hand side, the GMRES saddle
 solve (PSE mobility, lubrication, rigid constraints, block-triangular
 preconditioner) and the explicit Euler update.  The default workload is 256
 random-sticking clusters of 8 beads (2048 beads, phi = 0.10) in simple shear
-with lubrication, a 64^3 spectral grid and tolerance 1e-6, in FP64.
+with lubrication, a 64^3 spectral grid and tolerance 1e-6, in FP64.  GMRES starts each
+solve from the linear extrapolation of the two previous steps' solutions (--warm-mode,
+--cold for zero); every counted solve meets the tolerance on its true residual, and the
+line also reports the same steps solved from zero (cold_start).
 
 Prints one JSON line (rank 0).  --gpus above 1 is not supported: this build
 runs on a single GPU.
