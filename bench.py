@@ -220,7 +220,9 @@ def bench_batched(args, F, fsdgen, torch):
 def bench_serving(args, F, fsdgen, torch):
     """Request stream (Poisson arrivals) served by the continuous-batching engine."""
     from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request, poisson_arrivals
-    reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps, kT=args.kT)
+    reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps, kT=args.kT,
+                                   shear_rate=args.shear_rate)
+    sheared = args.shear_rate > 0.01  # faster shear needs the sheared lattice's images across the y faces
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
@@ -228,7 +230,8 @@ def bench_serving(args, F, fsdgen, torch):
     def run(rate, seed, subset=None, n_steps=args.req_steps):
         sel = reqs if subset is None else subset
         # Brownian requests: the previous solution, not an extrapolation of noisy ones
-        be = LibBackend(F, budget, args.slots, dict(precision=prec), warm_start=0 if args.cold else 1)
+        be = LibBackend(F, budget, args.slots, dict(precision=prec), warm_start=0 if args.cold else 1,
+                        lees_edwards=sheared)
         eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
         t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
         rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
@@ -256,7 +259,8 @@ def bench_serving(args, F, fsdgen, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
-                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate 0.01 + lubrication + "
+                               f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate {args.shear_rate} "
+                               f"({'sheared lattice' if sheared else 'cube'}) + lubrication + "
                                f"Brownian kT {args.kT}, tol 1e-5, Poisson arrivals at {args.load} x capacity",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
                    "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision, "warm_start": 0 if args.cold else 1,
@@ -371,6 +375,8 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--load", type=float, default=0.5)
     ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
+    ap.add_argument("--shear-rate", type=float, default=1.0,
+                    help="shear rate of the serving requests (on the sheared lattice; 0.01 or less keeps the cube)")
     ap.add_argument("--cold", action="store_true",
                     help="GMRES from zero in every solve (default: warm starts; the stopping test is the same)")
     ap.add_argument("--warm-mode", type=int, choices=[1, 2, 3], default=2,

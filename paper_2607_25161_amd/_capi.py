@@ -391,14 +391,17 @@ class System:
 
     # -- convenience ------------------------------------------------------------------
     @classmethod
-    def from_suspension(cls, s, stream=None, **overrides):
-        """Build from any object with the workload attributes (L, a, eta, offsets, ...)."""
+    def from_suspension(cls, s, stream=None, lees_edwards=False, **overrides):
+        """Build from any object with the workload attributes (L, a, eta, offsets, ...);
+        lees_edwards=True puts it on the sheared lattice (strain 0) before the aggregates."""
         kw = dict(eta=s.eta, radius=s.a, xi=s.xi, ewald_tol=s.ewald_tol, grid=s.grid, r_lub=s.r_lub,
                   r_precond=s.r_precond, gmres_tol=s.gmres_tol, kT=getattr(s, "kT", 0.0))
         kw.update({k: v for k, v in (getattr(s, "extra", None) or {}).items() if k in ("gmres_maxit", "seed")})
         kw.update(overrides)
         sysm = cls(default_params(**kw), stream=stream)
         sysm.init_box(s.L)
+        if lees_edwards:
+            sysm.set_lees_edwards(True, 0.0)
         sysm.init_aggregates(s.offsets, s.x_body, s.com, s.quat)
         sysm.set_forces(s.force)
         sysm.set_shear(s.grad_u)

@@ -44,12 +44,16 @@ class Request:
 class LibBackend:
     """The real backend: one System per request, one fsd_batch for all."""
 
-    def __init__(self, F, mem_budget: int, max_slots: int, params: dict, warm_start: int = 0):
+    def __init__(self, F, mem_budget: int, max_slots: int, params: dict, warm_start: int = 0,
+                 lees_edwards: bool = False):
         self.F = F
         self.batch = F.Batch(mem_budget, max_slots)
         self.params = params
         self.budget = mem_budget
         self.warm_start = warm_start  # GMRES initial guess of each request's solves (fsd_set_warm_start)
+        # requests on the sheared lattice: their grid is larger than `estimate` assumes, which
+        # the batch's own admission (it counts the grid a system holds) catches
+        self.lees_edwards = lees_edwards
 
     def estimate(self, req: Request) -> int:
         s = req.suspension
@@ -72,7 +76,7 @@ class LibBackend:
 
     def admit(self, req: Request):
         s = req.suspension
-        sysm = self.F.System.from_suspension(s, **self.params)
+        sysm = self.F.System.from_suspension(s, lees_edwards=self.lees_edwards, **self.params)
         if self.warm_start:
             sysm.set_warm_start(self.warm_start)
         slot = self.batch.try_admit(sysm)

@@ -79,3 +79,25 @@ def test_served_trajectory_matches_oracle(F):
     assert np.linalg.norm(dX - dXo) <= 1e-5 * np.linalg.norm(dXo)
     assert np.abs(q - quat).max() <= 1e-5 * dt
     be.batch.close()
+
+
+def test_sheared_requests_in_mix_equal_alone(F):
+    """Requests on the sheared lattice (shear rate 1, Brownian) served in a mix: each result
+    equals the same request stepped alone, strain included."""
+    from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request
+    reqs = fsdgen.serving_requests(3, seed=91, n_range=(100, 400), n_steps=3, kT=1.0, shear_rate=1.0)
+    be = LibBackend(F, 1 << 34, 3, {}, lees_edwards=True)
+    eng = BatchEngine(be, max_slots=3, dt=1e-3)
+    rep = eng.run([Request(k, s, 3) for k, s in enumerate(reqs)])
+    assert rep["completed"] == 3 and rep["failed"] == 0
+    served = {r.rid: r.result for r in eng.done}
+    for k, s in enumerate(reqs):
+        alone = F.System.from_suspension(s, lees_edwards=True)
+        for _ in range(3):
+            assert alone.step(1e-3, 1).status == 0
+        X, q = alone.state()
+        Xm, qm = served[k]
+        assert np.abs(X - Xm).max() < 1e-9 and np.abs(q - qm).max() < 1e-9, k
+        assert abs(alone.strain() - 3e-3) < 1e-15
+        alone.close()
+    be.batch.close()
