@@ -189,8 +189,9 @@ fsd_status fsd_get_pair_forces(fsd_system* s, double* f_bead);
  * roots of the sheared real-space and near-field parts).  Switch it on after fsd_init_box
  * and before fsd_init_aggregates (FSD_ESTATE after); the strain may be reset at any time
  * while on.  Requires a velocity gradient with G_xy as its only non-zero entry (FSD_EINVAL
- * otherwise, also from a later fsd_set_shear).  Systems on it run without captured graphs;
- * a batch holding one runs every system on its own stream (not the multi-system
+ * otherwise, also from a later fsd_set_shear).  Captured graphs read the strain from device
+ * memory, so they follow it from step to step; a batch holding such a system runs every
+ * system on its own stream (not the multi-system
  * launches).  enable 0 returns to the cube. */
 fsd_status fsd_set_lees_edwards(fsd_system* s, int enable, double strain);
 

@@ -61,7 +61,8 @@ struct WaveParams {
   double a, eta;    // bead radius and viscosity
   double scale;     // h^6 / V * (normalisation of the two Gaussians)^2
   int brownian;     // 1: the z pass applies the square-root multiplier to grid noise
-  double gam;       // strain of the sheared lattice (0: cube); see launch_bead_positions
+  const double* gam;  // device scalar: strain of the sheared lattice (nullptr: the cube); read
+                      // at run time so captured graphs follow the strain; see launch_bead_positions
   // Green's multipliers by |m|^2 = m_x^2 + m_y^2 + m_z^2 on the cube (5 per entry: sinc(ka),
   // jv(ka), the solve's and the Brownian root's scalar factors, 1/|k|), or nullptr
   const double* gtab;
@@ -74,7 +75,7 @@ struct RealParams {
   double inv_ht;    // 1 / table spacing
   int ntab;         // table nodes covering [0, r_cut] (plus 3 guard nodes)
   double self_t, self_r;
-  double gam;       // strain of the sheared lattice (0: cube)
+  const double* gam;  // device scalar: strain of the sheared lattice (nullptr: the cube)
 };
 
 // ---- geometry (k_geometry.hip) ----------------------------------------------------------
@@ -284,6 +285,8 @@ void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4
                             double drag_t, double drag_r, const double* src, double* vout, double* z,
                             const ArnoldiArgs& a, const double* pin, int nblk, double* hn2, hipStream_t st,
                             const int* skip);
+// *p = v (a one-thread kernel, so it is ordered on the stream like the kernels around it)
+void launch_set_value(double* p, double v, hipStream_t st);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
 
 // ---- Brownian terms (k_brownian.hip) ------------------------------------------------------

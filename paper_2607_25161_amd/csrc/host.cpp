@@ -320,6 +320,7 @@ struct fsd_system {
   bool le = false;      // sheared periodic lattice (Lees-Edwards)
   double strain = 0.0;  // its strain gamma, kept in [-1/2, 1/2)
   double gam() const { return le ? strain : 0.0; }
+  double* d_gam = nullptr;  // the strain where graphed kernels read it
   std::vector<hipEvent_t> ev_pool;
   size_t ev_next = 0;
   std::vector<Pending> pending;
@@ -497,7 +498,7 @@ GraphEntry* graph_for(fsd_system* s, const fsd_system::GraphKey& key, const std:
 
 // run body captured (cached) or eagerly
 GraphEntry* run_body(fsd_system* s, const fsd_system::GraphKey& key, const std::function<void()>& body) {
-  if (!s->use_graphs || s->timing || s->le) {  // the strain changes every step: eager launches
+  if (!s->use_graphs || s->timing) {
     body();
     return nullptr;
   }
@@ -660,7 +661,13 @@ void ensure_cols(fsd_system* s, uint32_t*& col, long long& cap, long long need) 
 // preconditioner factors and the spreading plan.
 void prepare_begin(fsd_system* s) {
   const double g = s->gam();
-  s->rp.gam = s->wp.gam = s->pf.gam = g;
+  s->pf.gam = g;
+  // graphed kernels read the strain from device memory (set here, outside any graph)
+  if (s->le) {
+    if (!s->d_gam) s->d_gam = dalloc<double>(s->owned, 1);
+    launch_set_value(s->d_gam, g, s->st);
+  }
+  s->rp.gam = s->wp.gam = s->le ? s->d_gam : nullptr;
   launch_bead_positions(s->nb, s->na, s->d_body, s->d_xbody, s->d_com, s->d_quat, s->L, g, s->d_r4, s->d_pos4,
                         s->st);
   HIPCHK(neighbors_count(s->nw, s->nb, s->d_pos4, s->d_body, s->L, g, s->rp.r_cut, false, s->d_nrow, s->st));
@@ -706,7 +713,7 @@ void prepare_end(fsd_system* s) {
   s->lpr = l;
   // captured graphs hold buffer pointers and launch shapes: drop them when those change
   auto sig = std::make_tuple((const void*)s->d_ncol, (const void*)s->d_lcol, (const void*)s->d_lcoef, s->lpr,
-                             int(s->p.r_lub > 0 && s->nlub > 0), (const void*)s->spread);
+                             int(s->p.r_lub > 0 && s->nlub > 0) | (s->le ? 2 : 0), (const void*)s->spread);
   if (sig != s->graph_sig) {
     s->drop_graphs();
     s->graph_sig = sig;

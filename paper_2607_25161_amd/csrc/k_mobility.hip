@@ -91,6 +91,7 @@ __device__ __forceinline__ void real_sum_body(int nb, const double4* __restrict_
   const R mt = R(1.0 / (6.0 * M_PI * rp.eta * rp.a));
   const R mr = R(1.0 / (8.0 * M_PI * rp.eta * rp.a * rp.a * rp.a));
   const R inv_ht = R(rp.inv_ht);
+  const double gam = rp.gam ? *rp.gam : 0.0;
   R u0 = 0, u1 = 0, u2 = 0, w0 = 0, w1 = 0, w2 = 0;
   const int e1 = rowptr[row + 1];
   for (int e = rowptr[row] + lane; e < e1; e += LPR) {
@@ -98,7 +99,7 @@ __device__ __forceinline__ void real_sum_body(int nb, const double4* __restrict_
     const int j = int(c & 0x3FFFFFu);
     const double4 pj = pos[j];
     const double dyd = pi.y - pj.y + (int((c >> 25) & 7u) - 3) * rp.L;  // Cartesian from sheared
-    const R dx = R(pi.x - pj.x + (int((c >> 22) & 7u) - 3) * rp.L + rp.gam * dyd);
+    const R dx = R(pi.x - pj.x + (int((c >> 22) & 7u) - 3) * rp.L + gam * dyd);
     const R dy = R(dyd);
     const R dz = R(pi.z - pj.z + (int((c >> 28) & 7u) - 3) * rp.L);
     const R r = sqrt(dx * dx + dy * dy + dz * dz);
@@ -277,7 +278,7 @@ template <typename R>
 __device__ inline void sheared_weights(const double4& p, const WaveParams& wp, int lane, R* wyz, int* st, R* wxr,
                                        int* sxr) {
   const int P = wp.support;
-  const double h = wp.h;
+  const double h = wp.h, gam = wp.gam ? *wp.gam : 0.0;
   const int sy = int(ceil(p.y / h - 0.5 * P)), sz = int(ceil(p.z / h - 0.5 * P));
   if (lane < 2 * P) {
     const int d = lane / P, k = lane % P;
@@ -290,7 +291,7 @@ __device__ inline void sheared_weights(const double4& p, const WaveParams& wp, i
   }
   for (int t = lane; t < P * P; t += 64) {
     const int ky = t / P, kx = t - ky * P;
-    const double cx = p.x - wp.gam * ((sy + ky) * h - p.y);  // the row's centre along x
+    const double cx = p.x - gam * ((sy + ky) * h - p.y);  // the row's centre along x
     const int sx = int(ceil(cx / h - 0.5 * P));
     const double xm = (sx + kx) * h - cx;
     wxr[ky * kMaxP + kx] = R(exp(-wp.alpha * xm * xm));
@@ -1411,7 +1412,7 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   __syncthreads();
   T* X = stockham<T, R>(buf0, buf1, tw, N, NL, plan, -1);
   T* O = (X == buf0) ? buf1 : buf0;
-  const double tp = 2.0 * M_PI / wp.L;
+  const double tp = 2.0 * M_PI / wp.L, gam = wp.gam ? *wp.gam : 0.0;
   for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
     const int g = t / (2 * N), q = (t / N) & 1, kx = t % N;
     const int pn = bx_ * G + g;
@@ -1443,9 +1444,9 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     // signed mode numbers in [-N/2, N/2] (an even N's N/2 modes were zeroed above; an odd N
     // keeps the symmetric range), so |m|^2 <= 3 (N/2)^2 indexes the multiplier table
     const int mx = kx <= N / 2 ? kx : kx - N, my = ky <= N / 2 ? ky : ky - N, mz = kz <= N / 2 ? kz : kz - N;
-    const double k[3] = {tp * mx, tp * (my - wp.gam * mx), tp * mz};
+    const double k[3] = {tp * mx, tp * (my - gam * mx), tp * mz};
     double sk, jk, Bk, ikn;
-    if (wp.gtab && wp.gam == 0.0) {  // the multipliers depend on the integer |m|^2 alone
+    if (wp.gtab && gam == 0.0) {  // the multipliers depend on the integer |m|^2 alone
       const double* gt = wp.gtab + 5 * (mx * mx + my * my + mz * mz);
       sk = gt[0];
       jk = gt[1];

@@ -222,6 +222,12 @@ __global__ void k_axpby(size_t n, double a, const double* __restrict__ x, double
   y[i] = a * x[i] + b * y[i];
 }
 
+__global__ void k_set_value(double* p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void launch_set_value(double* p, double v, hipStream_t st) { k_set_value<<<1, 64, 0, st>>>(p, v); }
+
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st) {
   k_axpby<<<nblocks((long long)n), kThreads, 0, st>>>(n, a, x, b, y);
 }

@@ -13,6 +13,7 @@ long steady-shear runs (Section 4.3).
   solve matches the oracle's exact roots and dense solve;
 - a batch with a sheared system steps every system as it steps alone;
 - both Brownian-drift estimators against the oracle's solves on the lattice;
+- solves after steps that advance the strain (graphs replayed) follow the new lattice;
 - argument and state checks.
 """
 import numpy as np
@@ -305,4 +306,22 @@ def test_drift_estimators_on_sheared_lattice(F):
     for got, want, base in ((X1, Xo, Xn), (q1, qo, qn)):
         assert np.abs(want - base).max() > 1e-8
         assert np.abs(got - want).max() <= 1e-4 * np.abs(want - base).max(), np.abs(got - want).max()
+    s.close()
+
+
+def test_solves_follow_the_strain_across_steps(F):
+    """Steps advance the strain (here through its fold at 1/2) while the solves replay
+    captured graphs: a solve after them matches the oracle on the lattice of the new strain."""
+    strain0 = 0.4
+    kw = _system(strain0, seed=75)
+    s = _make(F, kw, strain0)
+    for _ in range(3):
+        assert s.step(0.05, 1).status == 0
+    g = s.strain()
+    assert abs(g - (-0.45)) < 1e-12
+    X, q = s.state()
+    U, _, _ = s.solve()
+    Uo, *_ = saddle.solve(**dict(kw, com=X, quat=q), strain=g)
+    for sl in (slice(0, 3), slice(3, 6)):
+        assert _rel(U[:, sl], Uo[:, sl]) < 1e-8, (sl, _rel(U[:, sl], Uo[:, sl]))
     s.close()
