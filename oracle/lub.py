@@ -11,8 +11,17 @@ the *translational disturbance* velocity of bead pairs on different bodies
     Y(eps) = (1/6) ln(1/eps),
 
 the leading squeeze and shear terms of two equal spheres, shifted so that
-both vanish at the cutoff r = 3a (eps = 1).  The force on bead i is
--sum_k R_pair (v_i - v_k).  Rotational rows are zero.  The sparse
+both vanish at the cutoff r = 3a (eps = 1).  Rotational rows are zero.
+
+What the pair resists is the relative velocity of the two bead centres with
+the ambient rotation taken out, w = (u_i - u_k) - W d, d = x_i - x_k (the
+minimum image), W the antisymmetric part of the velocity gradient; the force
+on bead i is -sum_k R_pair w.  Its normal part is then the lab-frame rate at
+which the gap closes, and a pair turning rigidly with the ambient vorticity
+feels nothing.  Split into the two terms of Eq. `FH_agg`: with v = u - u_inf
+the bead velocity relative to the ambient flow at its centre (Eq. `gc`),
+w = (v_i - v_k) + E d, so the pair contributes -R_pair (v_i - v_k) to
+-R_FU (U - U_inf) and -R_pair E d to R_FE : E_inf (`strain_forces`).  The sparse
 preconditioner copy (Section 2.2.2: pairs with r < 2.1a) uses the same
 functions with the smaller cutoff.
 
@@ -91,6 +100,21 @@ def pair_blocks(d, a, eta, eps_min=1e-3, rough=(0.0, 0.0)):
     X, Y = X_squeeze(eps), Y_shear(eps) + roughness(eps * a, a, *rough)
     nn = n[:, :, None] * n[:, None, :]
     return z * (X[:, None, None] * nn + Y[:, None, None] * (np.eye(3) - nn))
+
+
+def strain_forces(x, body, L, a, eta, r_cut, E, eps_min=1e-3, rough=(0.0, 0.0), strain=0.0):
+    """Bead forces (Nb, 3) of R_FE : E_inf at the bead level: -sum_k R_pair E d_ik over the
+    inter-body pairs, d_ik = x_i - x_k (minimum image).  This is the near-field force on beads
+    that all move with the ambient flow at their own centres."""
+    n = len(x)
+    f = np.zeros((n, 3))
+    i, k, d = pairs(x, body, L, r_cut, strain)
+    if len(i):
+        B = pair_blocks(d, a, eta, eps_min, rough)
+        g = np.einsum("mab,bc,mc->ma", B, np.asarray(E, dtype=float), d)
+        np.add.at(f, i, -g)
+        np.add.at(f, k, g)
+    return f
 
 
 def resistance_matrix(x, body, L, a, eta, r_cut, eps_min=1e-3, rough=(0.0, 0.0), strain=0.0):

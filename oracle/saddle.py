@@ -9,12 +9,20 @@ F_h = hydrodynamic (force, torque) on the beads, V = U - U_inf per aggregate
 (translation, rotation), and
 
     b1_i = (E_inf r_i + u_B,i, w_B,i),
-    b2_j = -(F_P,j + [Sigma F_B,nf]_j + [Sigma R_nf e]_j),   e_i = (E_inf r_i, 0).
+    b2_j = -(F_P,j + [Sigma F_B,nf]_j + [R_FE : E_inf]_j),
 
 The right-hand side uses E_inf (x - X) as printed in Eq. `spm_agg` (derived
-from Eq. `gc`); the table of Section 2.3.3 prints the opposite sign.  The term
-R_FE : E_inf of Eq. `FH_agg` is read as lubrication acting on the ambient flow
-relative to the body, Sigma R_nf e.
+from Eq. `gc`); the table of Section 2.3.3 prints the opposite sign.
+
+The aggregate term R_FE : E_inf of Eq. `FH_agg` is the near-field force on
+the aggregates when each moves with the ambient flow at its centroid
+(V = 0).  By Eq. `gc` the beads then move relative to the ambient flow at
+their own centres by -e_i, e_i = (E_inf r_i, 0); the bead-level pair force
+adds -R_pair E d_ik (see `lub`), so
+
+    R_FE : E_inf = Sigma (R_nf e + f_E),   f_E,i = -sum_k R_pair E_inf d_ik,
+
+which makes every inter-body pair resist the lab-frame closing of its gap.
 
 The block-triangular preconditioner (Section 2.3.3 and its table; Algorithm 1
 step 1) approximates M by the bead self-mobility M~ = diag(mu_t I, mu_r I) and
@@ -71,7 +79,11 @@ def assemble(L, a, eta, offsets, x_body, com, quat, force, grad_u, r_lub=0.0,
     fb = np.asarray(force, dtype=float).reshape(na * 6).copy()
     if f_brown_nf is not None:
         fb += Sig @ np.asarray(f_brown_nf).reshape(nb * 6)
-    b2 = -(fb + Sig @ (Rnf @ e.reshape(-1)))
+    fe = Rnf @ e.reshape(-1)
+    if r_lub > 0:
+        fE = lub.strain_forces(x, body, L, a, eta, r_lub, E, eps_min, rough, strain)
+        fe.reshape(nb, 6)[:, :3] += fE
+    b2 = -(fb + Sig @ fe)
     G = np.asarray(grad_u, dtype=float)
     Uinf = np.zeros((na, 6))
     Uinf[:, :3] = X @ G.T

@@ -220,6 +220,108 @@ def test_reynolds_squeeze_limit():
 
 
 # --------------------------------------------------------------------------
+# near-contact asymptotics of two equal spheres (lubrication theory: the squeeze
+# resistance grows as 1/(4 eps) + (9/40) ln(1/eps), the sliding one as (1/6) ln(1/eps);
+# Jeffrey & Onishi's expansions, which the paper's Section 2.1 lubrication relies on)
+# --------------------------------------------------------------------------
+
+def pair_drag(eps, axis):
+    """F / (6 pi eta a dU) of two one-bead aggregates at gap eps a, pushed by equal and
+    opposite unit forces along `axis` (0: the line of centres, 1: across it)."""
+    L = 40.0
+    com = np.array([[0.0, 0, 0], [2 * A + eps * A, 0, 0]])
+    quat = np.tile([1.0, 0, 0, 0], (2, 1))
+    force = np.zeros((2, 6))
+    force[0, axis], force[1, axis] = 1.0, -1.0
+    U, *_ = saddle.solve(L, A, ETA, [0, 1, 2], np.zeros((2, 3)), com, quat, force,
+                         np.zeros((3, 3)), r_lub=3 * A, eps_min=1e-7)
+    return 1.0 / (6 * math.pi * ETA * A * (U[0, axis] - U[1, axis]))
+
+
+def log_coefficients():
+    """(squeeze, sliding) log coefficients read off the full solve between the gaps 1e-4 a
+    and 1e-5 a: the far field changes by O(1e-4) there, so the differences isolate the
+    near-contact terms (the 1/(4 eps) pole is taken out of the squeeze difference)."""
+    e1, e2 = 1e-4, 1e-5
+    sq = pair_drag(e2, 0) - pair_drag(e1, 0) - 0.25 * (1 / e2 - 1 / e1)
+    sl = pair_drag(e2, 1) - pair_drag(e1, 1)
+    return sq / math.log(10.0), sl / math.log(10.0)
+
+
+def test_lubrication_log_coefficients():
+    sq, sl = log_coefficients()
+    assert abs(sq - 9 / 40) < 1e-3
+    assert abs(sl - 1 / 6) < 1e-3
+
+
+@pytest.mark.parametrize("which,bad", [("Y_shear", lambda e: np.log(1 / np.asarray(e, float)) / 4),
+                                       ("X_squeeze", lambda e: 0.25 / np.asarray(e, float) + 0.3 * np.log(1 / np.asarray(e, float)) - 0.25)])
+def test_log_coefficient_pin_catches_a_wrong_coefficient(monkeypatch, which, bad):
+    # a mistake planted in the oracle (1/4 for 1/6, 3/10 for 9/40) must fail the pin above
+    monkeypatch.setattr(lub, which, bad)
+    sq, sl = log_coefficients()
+    assert abs(sq - 9 / 40) > 1e-2 or abs(sl - 1 / 6) > 1e-2
+
+
+def _sheared_pair(eps):
+    """Two three-bead aggregates whose only inter-body pair (bead 0 of each) sits at gap
+    eps a along n = (1, 1, 0)/sqrt(2), in simple shear u_x = y.  Returns the lab-frame
+    rate at which that gap closes, (u_p - u_q) . n with u = U + Omega x r, and the rate
+    affine motion with the flow would give, n . G d."""
+    n = np.array([1.0, 1.0, 0.0]) / math.sqrt(2)
+    d = (2 + eps) * A
+    arm = np.array([[0.0, 0, 0], [-2.0, 0, 0], [-2.0, 0, 2.0]])     # bead 0 at the tip
+    xb = np.concatenate([arm, -arm])    # body 0 reaches towards -x, body 1 towards +x
+    X = np.array([arm.mean(0),          # bead 0 of body 0 at the origin
+                  d * n - arm.mean(0)])  # bead 0 of body 1 at d n
+    G = np.zeros((3, 3))
+    G[0, 1] = 1.0
+    quat = np.tile([1.0, 0, 0, 0], (2, 1))
+    U, _, _, asm = saddle.solve(40.0, A, ETA, [0, 3, 6], xb, X, quat, np.zeros((2, 6)), G,
+                                r_lub=3 * A, eps_min=1e-7)
+    pairs_ = lub.pairs(asm.x, rigid.body_index([0, 3, 6]), 40.0, 3 * A)
+    assert len(pairs_[0]) == 1 and (pairs_[0][0], pairs_[1][0]) == (0, 3)
+    u = U[rigid.body_index([0, 3, 6]), :3] + np.cross(U[rigid.body_index([0, 3, 6]), 3:], asm.r)
+    dd = asm.x[0] - asm.x[3]
+    return (u[0] - u[3]) @ n, n @ G @ dd
+
+
+def test_sheared_pair_stops_closing_at_contact():
+    # R_FE : E_inf (Eq. `FH_agg`) read as the pair force on the lab-frame closing rate: the
+    # gap of a near-touching inter-body pair closes at a rate that vanishes like 1/X(eps),
+    # however fast the shear would bring the two bodies together
+    r4, a4 = _sheared_pair(1e-4)
+    r5, a5 = _sheared_pair(1e-5)
+    assert abs(a4) > 0.4 and abs(a5) > 0.4
+    assert abs(r4 / a4) < 2e-3 and abs(r5 / a5) < 2e-4
+    assert 0.05 < (r5 / a5) / (r4 / a4) < 0.2
+
+
+def test_sheared_pair_pin_catches_a_flipped_strain_term(monkeypatch):
+    # planted in the oracle: the bead-level strain force with the wrong sign, or left out
+    real = lub.strain_forces
+    for scale in (-1.0, 0.0):
+        monkeypatch.setattr(lub, "strain_forces", lambda *a, _s=scale, **k: _s * real(*a, **k))
+        r5, a5 = _sheared_pair(1e-5)
+        assert abs(r5 / a5) > 0.1
+
+
+def test_ambient_rotation_moves_bodies_rigidly():
+    # a purely rotational ambient flow carries every body with it: U = (W X, Omega_inf)
+    # with no lubrication force, whatever the gaps
+    rng = np.random.default_rng(11)
+    xb = np.concatenate([rng.normal(size=(3, 3)), rng.normal(size=(3, 3))])
+    com = np.array([[0.0, 0, 0], [2.6, 0.3, -0.2]])
+    quat = np.tile([1.0, 0, 0, 0], (2, 1))
+    Wm = np.array([[0.0, -0.7, 0.2], [0.7, 0.0, -0.4], [-0.2, 0.4, 0.0]])
+    U, _, _, asm = saddle.solve(30.0, A, ETA, [0, 3, 6], xb * 0.8, com, quat, np.zeros((2, 6)), Wm,
+                                r_lub=3 * A)
+    E, W = rigid.strain_and_spin(Wm)
+    assert np.allclose(U[:, :3], asm.com @ Wm.T, atol=1e-12)
+    assert np.allclose(U[:, 3:], W, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # rigid-body constraint and solves
 # --------------------------------------------------------------------------
 
