@@ -1,17 +1,21 @@
 """Benchmark: rigid-aggregate Stokesian dynamics time steps on one MI355X.
 
-A step is one pass of the whole hot path over the suspension: neighbour lists,
+A step is one pass of the whole hot path over a suspension: neighbour lists,
 lubrication and preconditioner set-up, the right-hand side, the GMRES saddle
 solve (PSE mobility, lubrication, rigid constraints, block-triangular
-preconditioner) and the explicit Euler update.  The default workload is 256
-random-sticking clusters of 8 beads (2048 beads, phi = 0.10) in simple shear
-with lubrication, a 64^3 spectral grid and tolerance 1e-6, in FP64.  GMRES starts each
-solve from the linear extrapolation of the two previous steps' solutions (--warm-mode,
---cold for zero); every counted solve meets the tolerance on its true residual, and the
-line also reports the same steps solved from zero (cold_start).
+preconditioner) and the explicit Euler update.
 
-Prints one JSON line (rank 0).  --gpus above 1 is not supported: this build
-runs on a single GPU.
+The default workload is the batched form: 64 independent periodic suspensions of
+200-4000 beads (random-sticking clusters of 4-30 beads, phi 0.02-0.25, simple shear
+with lubrication, xi = 25/L, tolerance 1e-5), stepped together in mixed precision
+(FP32 operator, FP64 Krylov and residual) with multi-system launches.  The same run
+times the plain path on the same systems, FP64 and one system at a time, and reports
+the ratio.  Every counted solve meets 1e-5 on its FP64 true residual.  GMRES starts
+each solve from the linear extrapolation of the two previous steps' solutions in both
+(--warm-mode, --cold for zero).  The 256x8 and 4096x20 cluster workloads ride along
+as sub-objects (--no-sub to skip).
+
+Prints one JSON line.  --gpus above 1 is not supported: this build runs on a single GPU.
 """
 from __future__ import annotations
 
@@ -38,26 +42,39 @@ KERNEL_OF = {"real_sum": "k_real_sum", "spread": "k_spread_fused", "fft_first": 
              "cgs_dot": "k_cgs_chain<0>", "cgs_update": "k_cgs_chain<1>", "cgs_norm_arnoldi": "k_cgs_chain<2>"}
 
 
+def batch_kernel_names(prec):
+    """rocprofv3 names of the multi-system kernels behind each timer class."""
+    R = "float" if prec else "double"
+    return {"real_sum": f"kb_real<{R}>", "spread": f"kb_spread<{R}>", "fft_first": f"kb_fft<{R}, 0>",
+            "fft_y": f"kb_fft<{R}, 1>", "fft_green": f"kb_fft<{R}, 2>", "fft_last": f"kb_fft<{R}, 4>",
+            "interp": f"kb_interp<{R}>", "rigid_lub": "kb_agg", "precond": "kb_precond",
+            "cgs_dot": "kb_cgs<0>", "cgs_update": "kb_cgs<1>", "cgs_norm_arnoldi": "kb_cgs<2>"}
+
+
 def progress(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_table(timers, steps):
+def kernel_table(timers, steps, names=None):
     """Per timer class: ms per step, launches, average launch duration and the
     algorithmic HBM bandwidth (algorithmic bytes of the launches / their time)."""
+    names = names or KERNEL_OF
     out = {}
     for k, (ms, n, by) in timers.items():
         if n == 0:
             continue
-        out[k] = {"kernel": KERNEL_OF.get(k, k), "ms_per_step": round(ms / steps, 4), "launches": n,
+        out[k] = {"kernel": names.get(k, k), "ms_per_step": round(ms / steps, 4), "launches": n,
                   "avg_us": round(1e3 * ms / n, 2), "alg_bytes_per_launch": int(by / n),
                   "alg_GBps": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
     return out
 
 
 # source file of each kernel, whose hash the counter summaries record
-SOURCE_OF = {"k_real_sum": "k_mobility.hip", "k_spread_fused": "k_mobility.hip", "k_spread_split": "k_mobility.hip", "k_fft_lines<1>": "k_mobility.hip",
+SOURCE_OF = {"kb_fft<float, 2>": "k_mobility.hip", "kb_fft<float, 0>": "k_mobility.hip",
+             "kb_fft<float, 1>": "k_mobility.hip", "kb_fft<float, 4>": "k_mobility.hip",
+             "kb_spread<float>": "k_mobility.hip", "kb_interp<float>": "k_mobility.hip",
+             "k_real_sum": "k_mobility.hip", "k_spread_fused": "k_mobility.hip", "k_spread_split": "k_mobility.hip", "k_fft_lines<1>": "k_mobility.hip",
              "k_fft_lines<2>": "k_mobility.hip", "k_fft_xgreen": "k_mobility.hip", "k_interp": "k_mobility.hip",
              "k_agg_lub": "k_solver.hip", "k_precond_fused": "k_solver.hip", "k_cgs_chain<0>": "k_solver.hip",
              "k_cgs_chain<1>": "k_solver.hip", "k_cgs_chain<2>": "k_solver.hip"}
@@ -100,12 +117,15 @@ def replay_ms(sysm, table, reps=200):
     return sysm.time_kernel(name, reps) if name in REPLAYABLE else None
 
 
-def roofline_of(table, counters_file=None, launch_ms=None):
+def roofline_of(table, counters_file=None, launch_ms=None, launch_bytes=None):
     """Dominant kernel against the HBM roofline: algorithmic bytes per launch over the
     average launch duration (from the back-to-back replay when given, else from the
-    eager pass's per-launch events, which include each launch's dispatch)."""
+    eager pass's per-launch events, which include each launch's dispatch).  A replay of
+    a multi-system launch over every system gives its own bytes per launch."""
     name = dominant(table)
-    r = table[name]
+    r = dict(table[name])
+    if launch_bytes:
+        r["alg_bytes_per_launch"] = int(launch_bytes)
     us = 1e3 * launch_ms if launch_ms else r["avg_us"]
     ach = round(r["alg_bytes_per_launch"] / (us * 1e-6) / 1e9, 1)
     traffic = measured_traffic(counters_file, r["kernel"]) if counters_file else None
@@ -116,104 +136,170 @@ def roofline_of(table, counters_file=None, launch_ms=None):
             "eager_event_avg_us": r["avg_us"]}
 
 
+def _oracle_cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()]))
+    except Exception:
+        return int(os.cpu_count())
+
+
 def cpu_baseline(precision_note):
     """Time the CPU oracle on a bounded sample of the same generator (one solve)."""
     import fsdgen
     from oracle import saddle
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
     s = fsdgen.sheared_clusters(n_agg=96, n_b=8, phi=0.10, name="clusters-96x8")
     t0 = time.perf_counter()
     U, F, res, A = saddle.solve_suspension(s)
     dt = time.perf_counter() - t0
-    return {"value": s.n_bead / dt, "unit": "bead-solves/s", "cores": int(cores), "kind": "oracle",
+    return {"value": s.n_bead / dt, "unit": "bead-solves/s", "cores": _oracle_cores(), "kind": "oracle",
             "sample": f"1 dense FP64 solve of 96x8 clusters ({s.n_bead} beads, phi 0.10, shear + lubrication, "
                       f"same generator) in {dt:.1f} s; {precision_note}"}
 
 
+def cpu_baseline_uneven(systems, picks=(17, 3)):
+    """The oracle on a bounded sample of the batched workload: one dense FP64 solve of each
+    picked system, as a rate over their beads."""
+    from oracle import saddle
+    t0 = time.perf_counter()
+    nb = 0
+    for k in picks:
+        saddle.solve_suspension(systems[k])
+        nb += systems[k].n_bead
+    dt = time.perf_counter() - t0
+    return {"value": nb / dt, "unit": "bead-solves/s", "cores": _oracle_cores(), "kind": "oracle",
+            "sample": f"1 dense FP64 solve each of uneven systems {list(picks)} "
+                      f"({', '.join(str(systems[k].n_bead) for k in picks)} beads) in {dt:.1f} s"}
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def run_plain(F, systems, steps, warm, graphs=True):
+    """Plain path: FP64, one system at a time (each system's step after the last one's)."""
+    sys_ = [F.System.from_suspension(s0) for s0 in systems]
+    for s in sys_:
+        s.set_warm_start(warm)
+        if not graphs:
+            s.set_graphs(False)
+    for s in sys_:          # warm-up: lists sized, graphs captured
+        s.step(1e-3, 1)
+    _sync()
+    t0 = time.perf_counter()
+    ok, its = 0, []
+    for _ in range(steps):
+        for s in sys_:
+            info = s.step(1e-3, 1)
+            its.append(info.iterations)
+            ok += s.n_bead if (info.status == 0 and info.rel_residual_fp64 <= 1e-5) else 0
+    _sync()
+    dt_ = time.perf_counter() - t0
+    for s in sys_:
+        s.close()
+    return {"value": round(ok / dt_, 1), "ms_per_step": round(1e3 * dt_ / steps, 3),
+            "gmres_iterations_mean": round(float(np.mean(its)), 2), "graphs": graphs, "steps": steps}
+
+
+def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=False, replay=None):
+    """All systems admitted to one batch and stepped together; returns the figures, the
+    per-step latencies and, with timing, the kernel table and the replayed dominant launch."""
+    sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+    for s in sys_:
+        s.set_warm_start(warm)
+    b = F.Batch(1 << 40, len(sys_))
+    b.set_fused(fused)
+    slots = [b.admit(s) for s in sys_]
+    for _ in range(warmup):
+        b.step(1e-3)
+    _sync()
+    lat, its = [], []
+    ok = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        b.step(1e-3)
+        lat.append(time.perf_counter() - a)
+        for k, sl in enumerate(slots):
+            inf = b.info(sl)
+            its.append(inf.iterations)
+            ok += sys_[k].n_bead if (inf.status == 0 and inf.rel_residual_fp64 <= 1e-5) else 0
+    _sync()
+    dt_ = time.perf_counter() - t0
+    out = {"value": round(ok / dt_, 1), "ms_per_step": round(1e3 * dt_ / steps, 3),
+           "gmres_iterations_mean": round(float(np.mean(its)), 2), "gmres_iterations_max": int(np.max(its)),
+           "lat": lat}
+    if timing:
+        # the same kernels once more, one more step with event timing on every launch
+        b.set_timing(True)
+        b.step(1e-3)
+        out["table"] = kernel_table(b.timers(), 1, batch_kernel_names(precision == F.FSD_MIXED))
+        b.set_timing(False)
+        name = dominant(out["table"])
+        if replay and name in REPLAYABLE:
+            out["replay"] = b.time_kernel(name, replay)
+    b.close()
+    for s in sys_:
+        s.close()
+    return out
+
+
 def bench_batched(args, F, fsdgen, torch):
-    """Uneven systems: one-at-a-time plain FP64 vs the mixed-precision batch."""
+    """Uneven systems: the mixed-precision batch against the plain FP64 path."""
     systems = fsdgen.uneven_systems(n_sys=args.systems)
     n_tot = sum(s.n_bead for s in systems)
-
     warm = 0 if args.cold else args.warm_mode
-
-    def run_plain(steps):
-        sys_ = [F.System.from_suspension(s0) for s0 in systems]
-        for s in sys_:
-            s.set_warm_start(warm)
-        for s in sys_:          # warm-up: graphs captured, lists sized
-            s.step(s0.dt if False else 1e-3, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ok = 0
-        for _ in range(steps):
-            for s in sys_:
-                info = s.step(1e-3, 1)
-                ok += s.n_bead if info.rel_residual_fp64 <= 1e-5 else 0
-        torch.cuda.synchronize()
-        dt_ = time.perf_counter() - t0
-        for s in sys_:
-            s.close()
-        return ok / dt_, dt_ / steps
-
-    def run_batch(steps, precision, fused=True):
-        sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
-        for s in sys_:
-            s.set_warm_start(warm)
-        b = F.Batch(1 << 40, len(sys_))
-        b.set_fused(fused)
-        slots = [b.admit(s) for s in sys_]
-        for _ in range(args.warmup):
-            b.step(1e-3)
-        torch.cuda.synchronize()
-        lat = []
-        ok = 0
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            a = time.perf_counter()
-            b.step(1e-3)
-            lat.append(time.perf_counter() - a)
-            for k, sl in enumerate(slots):
-                inf = b.info(sl)
-                ok += sys_[k].n_bead if (inf.status == 0 and inf.rel_residual_fp64 <= 1e-5) else 0
-        torch.cuda.synchronize()
-        dt_ = time.perf_counter() - t0
-        b.close()
-        for s in sys_:
-            s.close()
-        return ok / dt_, dt_ / steps, lat
-
     progress(f"generated {len(systems)} systems, {n_tot} beads")
-    plain, plain_step = run_plain(max(1, args.steps // 2))
-    progress("plain FP64 one-at-a-time done")
-    b64s, b64s_step, _ = run_batch(args.steps, F.FSD_FP64, fused=False)
-    progress("batched FP64, one stream per system, done")
-    b64, b64_step, _ = run_batch(args.steps, F.FSD_FP64)
-    progress("batched FP64, multi-system launches, done")
-    value, step_s, lat = run_batch(args.steps, F.FSD_MIXED)
-    grids = sorted({int(F.System.from_suspension(systems[k]).info().grid) for k in range(0, len(systems), 8)})
+    plain_steps = max(1, args.steps // 2)
+    plain = run_plain(F, systems, plain_steps, warm, graphs=False)
+    progress(f"plain FP64 one at a time (eager launches): {plain['value']} bead-solves/s")
+    plain_g = run_plain(F, systems, plain_steps, warm, graphs=True)
+    progress(f"plain FP64 one at a time (captured graphs): {plain_g['value']} bead-solves/s")
+    mixed = run_batch(F, systems, args.steps, args.warmup, warm, F.FSD_MIXED, fused=True, timing=True, replay=50)
+    progress(f"batched mixed, multi-system launches: {mixed['value']} bead-solves/s")
+    b64 = run_batch(F, systems, plain_steps, 1, warm, F.FSD_FP64, fused=True)
+    progress(f"batched FP64, multi-system launches: {b64['value']} bead-solves/s")
+    streams = run_batch(F, systems, plain_steps, 1, warm, F.FSD_MIXED, fused=False)
+    progress(f"batched mixed, one stream per system: {streams['value']} bead-solves/s")
+    grids = sorted({int(F.System.from_suspension(systems[k]).info().grid) for k in range(len(systems))})
+    table = mixed["table"]
+    rep = mixed.get("replay")
+    roofline = roofline_of(table, f"hbm_counters_uneven-64_mixed.md", rep[0] if rep else None,
+                           rep[1] if rep else None)
+    roofline["launch"] = "one multi-system launch over all 64 systems"
+    lat = mixed["lat"]
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "bead-solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * step_s, 3),
+        "metric": METRIC, "value": mixed["value"], "unit": "bead-solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
-        "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads, "
-                               f"phi 0.02-0.25, xi = 25/L, tol 1e-5", "n_bead_total": n_tot,
-                   "grids_sampled": grids, "precision": "mixed", "warm_start": warm,
+        "dtype": "f32 operator / f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads "
+                               f"(4-30 per aggregate), phi 0.02-0.25, xi = 25/L, tol 1e-5, batched mixed precision",
+                   "n_bead_total": n_tot, "grids": grids, "precision": "mixed", "warm_start": warm,
                    "parallelism": "single GPU, multi-system launches"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
-                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
-        "plain_fp64_one_at_a_time": {"value": round(plain, 1), "ms_per_step": round(1e3 * plain_step, 3)},
-        "batched_fp64": {"value": round(b64, 1), "ms_per_step": round(1e3 * b64_step, 3)},
-        "batched_fp64_streams": {"value": round(b64s, 1), "ms_per_step": round(1e3 * b64s_step, 3)},
-        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
-        "speedup_vs_plain": round(value / plain, 2),
-        "roofline": None,
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
+                       "what": "per solve: every system's solve completes within its batched step"},
+        "speedup_vs_plain": round(mixed["value"] / plain["value"], 3),
+        "speedup_vs_plain_graphed": round(mixed["value"] / plain_g["value"], 3),
+        "gmres_iterations_mean": mixed["gmres_iterations_mean"], "gmres_iterations_max": mixed["gmres_iterations_max"],
+        "plain_fp64_one_at_a_time": plain, "plain_fp64_one_at_a_time_graphed": plain_g,
+        "batched_fp64": {k: v for k, v in b64.items() if k != "lat"},
+        "batched_mixed_streams": {k: v for k, v in streams.items() if k != "lat"},
+        "kernels": table,
+        "kernel_timing": ("HIP events around every multi-system launch of one extra step on the batch stream, "
+                          "bytes of the systems still iterating in each launch"),
+        "roofline": roofline,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_uneven(systems)
+        progress("cpu baseline done")
+    if not args.no_sub:
+        out["sub"] = {"clusters-256x8": bench_clusters(args, F, fsdgen, torch, emit=False)}
+        progress("256x8 sub-run done")
+        out["sub"]["clusters-4096x20"] = bench_large(args, F, fsdgen, torch, emit=False, steps=3)
+        progress("4096x20 sub-run done")
     print(json.dumps(out), flush=True)
 
 
@@ -276,8 +362,9 @@ def bench_serving(args, F, fsdgen, torch):
     print(json.dumps(out), flush=True)
 
 
-def bench_large(args, F, fsdgen, torch):
+def bench_large(args, F, fsdgen, torch, emit=True, steps=None):
     """81,920 beads (4096 clusters of 20, phi 0.20, 128^3): FP64 against mixed precision."""
+    n_steps = steps or args.steps
     s = fsdgen.config(2)
     progress(f"generated {s.name}: {s.n_bead} beads")
     stream = torch.cuda.current_stream().cuda_stream
@@ -290,7 +377,7 @@ def bench_large(args, F, fsdgen, torch):
         progress(f"{prec_name}: warm-up solve done")
         lat, its, rr = [], [], []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(n_steps):
             a = time.perf_counter()
             si = sysm.step(s.dt, 1)
             lat.append(time.perf_counter() - a)
@@ -298,7 +385,7 @@ def bench_large(args, F, fsdgen, torch):
             rr.append(si.rel_residual_fp64)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        progress(f"{prec_name}: {args.steps} timed steps in {el:.2f} s")
+        progress(f"{prec_name}: {n_steps} timed steps in {el:.2f} s")
         sysm.set_timing(True)
         sysm.step(s.dt, 1)
         table = kernel_table(sysm.timers(), 1)
@@ -306,7 +393,7 @@ def bench_large(args, F, fsdgen, torch):
         rep = replay_ms(sysm, table, 20)
         info = sysm.info()
         sysm.close()
-        res[prec_name] = {"value": s.n_bead * sum(1 for r in rr if r <= 1e-5) / el, "ms_per_step": 1e3 * el / args.steps,
+        res[prec_name] = {"value": s.n_bead * sum(1 for r in rr if r <= 1e-5) / el, "ms_per_step": 1e3 * el / n_steps,
                           "lat": lat, "its": float(np.mean(its)), "max_res": float(max(rr)), "U0": U0,
                           "table": table, "info": info, "replay": rep}
     m, d = res["mixed"], res["fp64"]
@@ -315,7 +402,7 @@ def bench_large(args, F, fsdgen, torch):
     info = d["info"]
     out = {
         "metric": METRIC, "value": round(m["value"], 1), "unit": "bead-solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": round(m["ms_per_step"], 3),
+        "steps": n_steps, "warmup": 1, "ms_per_step": round(m["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 matvec / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{s.name} clusters in shear + lubrication", "n_bead": s.n_bead, "n_agg": s.n_agg,
@@ -333,7 +420,9 @@ def bench_large(args, F, fsdgen, torch):
         "kernels": m["table"],
         "roofline": roofline_of(m["table"], launch_ms=m["replay"]),
     }
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_copy(args, torch):
@@ -360,47 +449,8 @@ def bench_copy(args, torch):
                       "frac_of_8TBps": round(gbs / PEAK_HBM_GBS, 4)}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["clusters", "large", "batched", "serving", "copy"], default="clusters")
-    ap.add_argument("--systems", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=12)
-    ap.add_argument("--req-steps", type=int, default=20)
-    ap.add_argument("--max-beads", type=int, default=50000)
-    ap.add_argument("--slots", type=int, default=16)
-    ap.add_argument("--load", type=float, default=0.5)
-    ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
-    ap.add_argument("--shear-rate", type=float, default=1.0,
-                    help="shear rate of the serving requests (on the sheared lattice; 0.01 or less keeps the cube)")
-    ap.add_argument("--cold", action="store_true",
-                    help="GMRES from zero in every solve (default: warm starts; the stopping test is the same)")
-    ap.add_argument("--warm-mode", type=int, choices=[1, 2, 3], default=2,
-                    help="warm start from the previous solution (1) or the linear (2) or quadratic (3) "
-                         "extrapolation of the last solutions")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              f"(systems shard by LPT assignment, see the design notes)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import fsdgen
-    import paper_2607_25161_amd as F
-
-    torch.cuda.set_device(0)
-    if args.workload == "copy":
-        return bench_copy(args, torch)
-    if args.workload == "batched":
-        return bench_batched(args, F, fsdgen, torch)
-    if args.workload == "serving":
-        return bench_serving(args, F, fsdgen, torch)
-    if args.workload == "large":
-        return bench_large(args, F, fsdgen, torch)
+def bench_clusters(args, F, fsdgen, torch, emit=True):
+    """256 clusters of 8 (2048 beads, phi 0.10, 64^3), FP64 at tol 1e-6 (or --precision)."""
     stream = torch.cuda.current_stream()
     s = fsdgen.config(1)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
@@ -474,9 +524,57 @@ def main():
                           "over the same steps from the same start (each interval includes the launch's dispatch)"),
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if emit and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline("bead-solves/s of the oracle as it stands")
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["batched", "clusters", "large", "serving", "copy"], default="batched")
+    ap.add_argument("--no-sub", action="store_true", help="batched: skip the 256x8 and 4096x20 sub-runs")
+    ap.add_argument("--systems", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=12)
+    ap.add_argument("--req-steps", type=int, default=20)
+    ap.add_argument("--max-beads", type=int, default=50000)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--load", type=float, default=0.5)
+    ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
+    ap.add_argument("--shear-rate", type=float, default=1.0,
+                    help="shear rate of the serving requests (on the sheared lattice; 0.01 or less keeps the cube)")
+    ap.add_argument("--cold", action="store_true",
+                    help="GMRES from zero in every solve (default: warm starts; the stopping test is the same)")
+    ap.add_argument("--warm-mode", type=int, choices=[1, 2, 3], default=2,
+                    help="warm start from the previous solution (1) or the linear (2) or quadratic (3) "
+                         "extrapolation of the last solutions")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              f"(independent systems would shard across GPUs by longest-processing-time assignment)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fsdgen
+    import paper_2607_25161_amd as F
+
+    torch.cuda.set_device(0)
+    if args.workload == "copy":
+        return bench_copy(args, torch)
+    if args.workload == "batched":
+        return bench_batched(args, F, fsdgen, torch)
+    if args.workload == "serving":
+        return bench_serving(args, F, fsdgen, torch)
+    if args.workload == "large":
+        return bench_large(args, F, fsdgen, torch)
+    if args.workload == "clusters":
+        return bench_clusters(args, F, fsdgen, torch)
 
 
 if __name__ == "__main__":

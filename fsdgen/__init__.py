@@ -377,28 +377,28 @@ def config(index: int, **overrides) -> Suspension:
     raise ValueError(index)
 
 
-def uneven_systems(seed=BASE_SEED + 4, n_sys=64, n_range=(200, 4000), nb_range=(4, 30),
-                   phi_range=(0.02, 0.25), tol=1e-5, a=1.0, k_p=2.0):
-    """Independent periodic systems of uneven size for the batched form.
+def uneven_system(k, seed=BASE_SEED + 4, n_range=(200, 4000), nb_range=(4, 30),
+                  phi_range=(0.02, 0.25), tol=1e-5, a=1.0, k_p=2.0):
+    """System k of the uneven set (its own seed, seed + k): bead count uniform in
+    n_range, beads per aggregate uniform in nb_range (the last aggregate takes the
+    remainder, at least 1 bead), volume fraction uniform in phi_range, splitting
+    parameter 25 / L, simple shear and lubrication as in the sheared-cluster workload."""
+    rng = rng_from(seed + k)
+    n_tot = int(rng.integers(n_range[0], n_range[1] + 1))
+    n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
+    phi = float(rng.uniform(*phi_range))
+    sizes = _split_sizes(n_tot, n_b)
+    L = box_side(n_tot, phi, a)
+    g = _dense_assemble(f"system-{k}", sizes, L, rng, a=a, k_p=k_p)
+    return Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
+                      xi=25.0 / L, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
+                      r_precond=2.1 * a, **g)
 
-    Per system s (seed + s): bead count uniform in n_range, beads per aggregate
-    uniform in nb_range (the last aggregate takes the remainder, at least 1 bead),
-    volume fraction uniform in phi_range, splitting parameter 25 / L, simple shear
-    and lubrication as in the sheared-cluster workload.
-    """
-    out = []
-    for k in range(n_sys):
-        rng = rng_from(seed + k)
-        n_tot = int(rng.integers(n_range[0], n_range[1] + 1))
-        n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
-        phi = float(rng.uniform(*phi_range))
-        sizes = _split_sizes(n_tot, n_b)
-        L = box_side(n_tot, phi, a)
-        g = _dense_assemble(f"system-{k}", sizes, L, rng, a=a, k_p=k_p)
-        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(1.0),
-                              xi=25.0 / L, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
-                              r_precond=2.1 * a, **g))
-    return out
+
+def uneven_systems(seed=BASE_SEED + 4, n_sys=64, **kw):
+    """Independent periodic systems of uneven size for the batched form (`uneven_system`
+    for k = 0 .. n_sys - 1)."""
+    return [uneven_system(k, seed=seed, **kw) for k in range(n_sys)]
 
 
 def _split_sizes(n_tot, n_b):
@@ -408,39 +408,48 @@ def _split_sizes(n_tot, n_b):
     return sizes
 
 
-def serving_requests(n_req, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(4, 30),
-                     phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0, maxit=20000,
-                     shear_rate=0.01):
-    """A stream of independent simulation requests for the serving form.
+def serving_request(r, seed=BASE_SEED + 5, n_range=(100, 50000), nb_range=(4, 30),
+                    phi_range=(0.02, 0.25), tol=1e-5, n_steps=20, kT=0.0, a=1.0, k_p=2.0, maxit=20000,
+                    shear_rate=0.01):
+    """Request r of the serving stream, drawn from its own Philox stream keyed by
+    (seed, r): bead count log-uniform in n_range, beads per aggregate uniform in
+    nb_range, volume fraction uniform in phi_range; shear and lubrication as in the
+    other workloads; splitting parameter and grid left to the library's policy
+    (xi = 0, grid = 0); n_steps time steps.  Brownian motion (kT > 0) brings bodies
+    into near contact, where the lubrication makes the saddle system stiff: the GMRES
+    budget per solve is maxit.
 
-    Request r draws from its own Philox stream keyed by (seed, r): bead count
-    log-uniform in n_range, beads per aggregate uniform in nb_range, volume
-    fraction uniform in phi_range; shear and lubrication as in the other
-    workloads; splitting parameter and grid left to the library's policy
-    (xi = 0, grid = 0); each request asks for n_steps time steps.  Brownian motion
-    (kT > 0) brings bodies into near contact, where the lubrication makes the
-    saddle system stiff: the GMRES budget per solve is maxit.
-
-    The imposed shear enters the right-hand side of a cubic periodic box (no
-    Lees-Edwards images), so bodies facing each other across the y boundary move
-    apart or together at shear_rate * L; shear_rate keeps that relative motion over
-    the request (shear_rate * L * n_steps * dt <= 0.05 a for L up to 220 a) below the
-    smallest gaps the generator leaves.
+    The shear rate is shear_rate.  On a cubic periodic box (no Lees-Edwards images)
+    bodies facing each other across the y boundary move apart or together at
+    shear_rate * L, and the default 0.01 keeps that relative motion over a request
+    (shear_rate * L * n_steps * dt <= 0.05 a for L up to 220 a) below the smallest gaps
+    the generator leaves; faster shear belongs on the sheared lattice, which removes
+    that jump (the serving benchmark runs shear rate 1 there).
     """
-    out = []
-    for r in range(n_req):
-        rng = np.random.Generator(np.random.Philox(key=np.uint64(seed & ((1 << 64) - 1)),
-                                                   counter=np.array([0, 0, 0, r], dtype=np.uint64)))
-        n_tot = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
-        n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
-        phi = float(rng.uniform(*phi_range))
-        sizes = _split_sizes(n_tot, n_b)
-        L = box_side(n_tot, phi, a)
-        g = _dense_assemble(f"request-{r}", sizes, L, rng, a=a, k_p=k_p)
-        out.append(Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(shear_rate),
-                              xi=0.0, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
-                              r_precond=2.1 * a, kT=kT, n_steps=n_steps, extra={"gmres_maxit": maxit}, **g))
-    return out
+    rng = np.random.Generator(np.random.Philox(key=np.uint64(seed & ((1 << 64) - 1)),
+                                               counter=np.array([0, 0, 0, r], dtype=np.uint64)))
+    n_tot = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+    n_b = int(rng.integers(nb_range[0], nb_range[1] + 1))
+    phi = float(rng.uniform(*phi_range))
+    sizes = _split_sizes(n_tot, n_b)
+    L = box_side(n_tot, phi, a)
+    g = _dense_assemble(f"request-{r}", sizes, L, rng, a=a, k_p=k_p)
+    return Suspension(eta=1.0, force=np.zeros((len(sizes), 6)), grad_u=simple_shear(shear_rate),
+                      xi=0.0, ewald_tol=tol, gmres_tol=tol, grid=0, r_lub=3.0 * a,
+                      r_precond=2.1 * a, kT=kT, n_steps=n_steps, extra={"gmres_maxit": maxit}, **g)
+
+
+def serving_requests(n_req, seed=BASE_SEED + 5, **kw):
+    """A stream of independent simulation requests for the serving form
+    (`serving_request` for r = 0 .. n_req - 1)."""
+    return [serving_request(r, seed=seed, **kw) for r in range(n_req)]
+
+
+def brownian_noise(n_bead, seed):
+    """Standard normal inputs of one Brownian solve given from outside: psi_r (6 per bead,
+    the real-space slip) and psi_nf (3 per bead, the near-field force)."""
+    rng = rng_from(seed)
+    return rng.normal(size=6 * n_bead), rng.normal(size=3 * n_bead)
 
 
 def random_force(rng, n_agg, scale=1.0):

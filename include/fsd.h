@@ -5,14 +5,17 @@
  * Section 2.3.3 (Eq. `spm_agg`) at force-torque level:
  *
  *   [ M      Sigma^T ] [ F ]   [ (E r_i + u_B, w_B)_i                       ]
- *   [ Sigma  -R_agg  ] [ V ] = [ -(F_P + Sigma F_B,nf + Sigma R_nf e)_j     ]
+ *   [ Sigma  -R_agg  ] [ V ] = [ -(F_P + Sigma F_B,nf + R_FE : E_inf)_j     ]
  *
  * with M the periodic force-torque RPY mobility of the beads (positively split
  * Ewald: real-space pair sum + Gaussian spreading / 3D FFT / Green's scaling /
  * interpolation), R_nf the near-field lubrication between beads of different
  * bodies, Sigma the geometric constraint of Eq. `sigma`, R_agg = Sigma R_nf
  * Sigma^T, and V = U - U_inf the aggregate velocity relative to the imposed
- * flow.  GMRES (Algorithm 1, step 4) with the block-triangular preconditioner
+ * flow.  R_FE : E_inf (Eq. `FH_agg`) is the near-field force on the bodies when each
+ * moves with the imposed flow at its centroid: every inter-body bead pair resists the
+ * relative velocity of its bead centres less the imposed rotation's share, so the
+ * lab-frame rate at which a near-contact gap closes is what lubrication acts on.  GMRES (Algorithm 1, step 4) with the block-triangular preconditioner
  * of Section 2.3.3 (per-aggregate LU of the block-diagonal Schur
  * approximation, Algorithm 1 step 1) solves it; Eqs. `EM1`-`EM3` advance the
  * bodies (Algorithm 1, step 5).
@@ -68,7 +71,7 @@ typedef struct {
                             under the Section 3.2 error rules (cost model of the pair
                             sum against the grid passes)                              */
   double ewald_tol;      /* truncation tolerance x_err of the cutoff rules (Sec. 3.2)  */
-  int grid;              /* spectral grid points per side (2^a 3^b, at most 256); 0: from
+  int grid;              /* spectral grid points per side (2^a 3^b 5^c, at most 256); 0: from
                             the k_c rule                                              */
   int support;           /* Gaussian support P (points per side); 0: from ewald_tol    */
   double r_lub;          /* lubrication cutoff (3a); 0 disables lubrication            */
@@ -100,13 +103,18 @@ typedef struct {
 
 void fsd_default_params(fsd_params* p);
 
-/* Create a system on the current HIP device.  hip_stream: a hipStream_t to run
- * on (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a private
- * stream.  The system owns all of its device memory. */
+/* Create a system on the current HIP device: the state of one simulation of
+ * Algorithm 1 (a periodic suspension of rigid aggregates, Section 2.3) and the
+ * solver settings p (copied).  hip_stream: a hipStream_t to run on (e.g.
+ * torch.cuda.current_stream().cuda_stream) or NULL for a private stream.  The
+ * system owns all of its device memory.  FSD_EINVAL for a NULL out or
+ * parameters outside their ranges, FSD_EDEVICE if no stream can be made. */
 fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out);
 
-/* Periodic cube of side L (Section 2.3.1 works in a periodic box). */
-fsd_status fsd_init_box(fsd_system* s, double L);
+/* Periodic box of sides Lx, Ly, Lz (Section 2.3.1 works in a periodic box; the
+ * rules of Section 3.2 size the grid per side).  This library takes cubes only:
+ * FSD_EINVAL unless Lx == Ly == Lz > 0.  Call before fsd_init_aggregates. */
+fsd_status fsd_init_box(fsd_system* s, double Lx, double Ly, double Lz);
 
 /* Aggregates (Section 2.3.1): n_agg bodies; bead range of body j is
  * [bead_offsets[j], bead_offsets[j+1]); x_body (3 per bead) are body-frame
@@ -142,13 +150,25 @@ fsd_status fsd_solve_dev(fsd_system* s, double* d_U_agg, double* d_lambda, fsd_s
  * info of the final solve. */
 fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last);
 
-/* Current state: com (3 per body), quat (4 per body), x_bead (3 per bead,
- * lab frame, unwrapped X_j + R(q_j) x_body; may be NULL). */
+/* Current state, the variables Eqs. `EM1`-`EM3` advance: com (3 per body, the
+ * centroids X_j, wrapped into the primary box), quat (4 per body, q_j), x_bead (3 per
+ * bead, lab frame, unwrapped X_j + R(q_j) x_body, Eq. `EM3`; may be NULL).  Host
+ * buffers; com and quat may be NULL too.  FSD_ESTATE before fsd_init_aggregates. */
 fsd_status fsd_get_state(const fsd_system* s, double* com, double* quat, double* x_bead);
+
+/* Aggregate velocities U = V + U_inf (6 per body, translation then rotation; the
+ * unknowns of Eq. `spm_agg` plus the imposed flow) of the last completed solve of s,
+ * whichever call made it (fsd_solve, fsd_step, fsd_batch_solve, fsd_batch_step).  Host
+ * buffer.  FSD_ESTATE before any solve. */
+fsd_status fsd_get_velocities(const fsd_system* s, double* U_agg);
 
 fsd_status fsd_get_info(const fsd_system* s, fsd_info* info);
 
-/* Device bytes a system of this size needs (for admission decisions). */
+/* Device bytes fsd_init_aggregates will allocate for a system of n_bead beads in
+ * n_agg bodies in a cube of side L with parameters p: the spectral grid of the
+ * Section 3.2 rules (or p->grid), the Krylov basis of GMRES(m) (Algorithm 1), the
+ * per-body factors and the initial neighbour-list capacity.  For admission
+ * decisions (the serving form); 0 for invalid arguments. */
 size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, double L);
 
 /* Text of the last error of s; with s == NULL, of the calling thread's last failed
@@ -224,7 +244,7 @@ fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0);
  * Eq. `SP2` and Algorithm 1 step 3: with kT > 0 every solve adds the Brownian slip
  * velocity u_B = sqrt(2 kT/dt) (M_r^{1/2} psi_r + M_w^{1/2} psi_w) to the bead rows of the
  * right-hand side and the near-field Brownian force F_B = sqrt(2 kT/dt) R_nf^{1/2} psi_nf,
- * projected by Sigma, to the aggregate rows (b2 = -(F_P + Sigma F_B + Sigma R_nf e)).
+ * projected by Sigma, to the aggregate rows (b2 = -(F_P + Sigma F_B + R_FE : E_inf)).
  * The wave-space part uses the exact square root of the positively split wave-space
  * operator applied to white noise on the grid; the real-space and near-field parts use
  * Lanczos square roots (params.lanczos_tol, at most 100 steps).  The noise is drawn from
@@ -299,6 +319,17 @@ fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out
  * transform.  Host buffer; for verification of the FFT stages. */
 fsd_status fsd_fft3d(int n, int sign, double* data);
 
+/* The transform of fsd_fft3d on a device buffer, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  d_data: n^3 complex values (interleaved re/im
+ * doubles, x fastest) in device memory of the current GPU, transformed in place, stream-
+ * ordered on hip_stream (NULL: the null stream); the caller owns it.  The twiddle table
+ * lives in a fixed device array of 2 x 512 doubles per GPU, held until the process ends, so
+ * n is at most 512 (FSD_EINVAL beyond, or for n not a product of 2, 3 and 5; the text is in
+ * fsd_last_error(NULL)).  Calls that overlap on one GPU race on that array: order them on
+ * one stream.  FSD_EDEVICE if a launch fails. */
+fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream);
+
 /* ---- batches of independent systems (many small suspensions sharing the GPU) -------- */
 
 /* A batch holds up to max_slots systems whose device memory counts against
@@ -307,7 +338,9 @@ fsd_status fsd_fft3d(int n, int sign, double* data);
  * each its own stream (fsd_create with NULL) so their work overlaps on the GPU. */
 typedef struct fsd_batch fsd_batch;
 
-fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** out);
+/* hip_stream: the stream of the multi-system launches (NULL: a private stream owned
+ * by the batch).  FSD_EINVAL for max_slots outside 1..4096. */
+fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, void* hip_stream, fsd_batch** out);
 
 /* Admit an initialised system into a free slot.  FSD_EBUSY if no slot is free or
  * the memory budget would be exceeded; slot receives the slot index. */
@@ -336,6 +369,26 @@ size_t fsd_batch_used_bytes(const fsd_batch* b);
 
 /* Select multi-system launches (enable != 0, the default) or one stream per system. */
 fsd_status fsd_batch_set_fused(fsd_batch* b, int enable);
+
+/* Event timing of the multi-system launches (fsd_timer classes; the Arnoldi steps of the
+ * lock-step solve): while on, each launch is bracketed by HIP events on the batch stream,
+ * the host checks the stop flags after every Arnoldi step, and each launch is credited
+ * with the algorithmic bytes of the systems still iterating in it (the single-system
+ * counts of that class).  Turning it on or off resets the accumulators. */
+fsd_status fsd_batch_set_timing(fsd_batch* b, int enable);
+
+/* Milliseconds, launches and algorithmic bytes per fsd_timer class accumulated since the
+ * last fsd_batch_set_timing (FSD_TIMER_COUNT entries each; bytes may be NULL).
+ * Synchronises the batch stream. */
+fsd_status fsd_batch_get_timers(fsd_batch* b, double* total_ms, long long* launches, double* bytes);
+
+/* Average duration (ms) of one multi-system launch of class timer (FSD_TIMER_REAL ..
+ * FSD_TIMER_PRECOND) over every admitted system, replayed reps times back to back on the
+ * batch stream between one pair of HIP events; bytes_per_launch (may be NULL) gets the
+ * algorithmic bytes of that launch.  Needs systems that share multi-system launches
+ * (FSD_ESTATE otherwise).  Builds lists and factors for moved positions first; leaves the
+ * grids and scratch vectors undefined and the systems ready for their next solve. */
+fsd_status fsd_batch_time_kernel(fsd_batch* b, int timer, int reps, double* avg_ms, double* bytes_per_launch);
 
 void fsd_batch_destroy(fsd_batch* b);
 

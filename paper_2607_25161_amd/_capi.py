@@ -66,7 +66,7 @@ def _sig(name, res, *args):
 
 _sig("fsd_default_params", None, C.POINTER(Params))
 _sig("fsd_create", C.c_int, C.POINTER(Params), C.c_void_p, C.POINTER(C.c_void_p))
-_sig("fsd_init_box", C.c_int, _SYS, C.c_double)
+_sig("fsd_init_box", C.c_int, _SYS, C.c_double, C.c_double, C.c_double)
 _sig("fsd_init_aggregates", C.c_int, _SYS, C.c_int32, _I32, _D, _D, _D)
 _sig("fsd_set_forces", C.c_int, _SYS, _D)
 _sig("fsd_set_bead_forces", C.c_int, _SYS, _D)
@@ -75,6 +75,7 @@ _sig("fsd_solve", C.c_int, _SYS, _D, _D, C.POINTER(SolveInfo))
 _sig("fsd_solve_dev", C.c_int, _SYS, C.c_void_p, C.c_void_p, C.POINTER(SolveInfo))
 _sig("fsd_step", C.c_int, _SYS, C.c_double, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_get_state", C.c_int, _SYS, _D, _D, _D)
+_sig("fsd_get_velocities", C.c_int, _SYS, _D)
 _sig("fsd_get_info", C.c_int, _SYS, C.POINTER(Info))
 _sig("fsd_estimate_bytes", C.c_size_t, C.POINTER(Params), C.c_int32, C.c_int32, C.c_double)
 _sig("fsd_last_error", C.c_char_p, _SYS)
@@ -85,6 +86,7 @@ _sig("fsd_apply_precond", C.c_int, _SYS, _D, _D)
 _sig("fsd_get_rhs", C.c_int, _SYS, _D)
 _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
+_sig("fsd_fft3d_noalloc", C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p)
 _U64P = C.POINTER(C.c_uint64)
 _sig("fsd_set_brownian", C.c_int, _SYS, C.c_double, C.c_uint64, C.c_uint64)
 _sig("fsd_set_noise", C.c_int, _SYS, _D, _D, _D)
@@ -104,7 +106,7 @@ _sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
 
-_sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p))
+_sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p))
 _sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
 _sig("fsd_batch_retire", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_solve", C.c_int, C.c_void_p)
@@ -113,6 +115,9 @@ _sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
 _sig("fsd_batch_set_fused", C.c_int, C.c_void_p, C.c_int)
+_sig("fsd_batch_set_timing", C.c_int, C.c_void_p, C.c_int)
+_sig("fsd_batch_get_timers", C.c_int, C.c_void_p, _D, C.POINTER(C.c_longlong), _D)
+_sig("fsd_batch_time_kernel", C.c_int, C.c_void_p, C.c_int, C.c_int, _D, _D)
 
 TIMER_NAMES = ("real_sum", "spread", "fft_first", "fft_y", "fft_green", "fft_last", "interp", "rigid_lub",
                "precond", "cgs_dot", "cgs_update", "cgs_norm_arnoldi")
@@ -178,6 +183,14 @@ def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
     return buf.view(np.complex128).reshape(a.shape)
 
 
+def fft3d_noalloc(n: int, sign: int, data_ptr: int, stream=None):
+    """fsd_fft3d_noalloc: in place on a device buffer of n^3 complex doubles (e.g. a torch
+    complex128 tensor's data_ptr()), stream-ordered on `stream` (a hipStream_t handle)."""
+    rc = lib.fsd_fft3d_noalloc(int(n), int(sign), C.c_void_p(int(data_ptr)), C.c_void_p(stream) if stream else None)
+    if rc:
+        raise FsdError(rc, f"fsd_fft3d_noalloc: {lib.fsd_last_error(None).decode()}")
+
+
 class System:
     """One periodic suspension resident on the GPU (wraps fsd_system)."""
 
@@ -214,8 +227,10 @@ class System:
         self.close()
 
     # -- setup ------------------------------------------------------------------------
-    def init_box(self, L):
-        self._check(lib.fsd_init_box(self._h, float(L)), "fsd_init_box")
+    def init_box(self, L, Ly=None, Lz=None):
+        Ly = L if Ly is None else Ly
+        Lz = L if Lz is None else Lz
+        self._check(lib.fsd_init_box(self._h, float(L), float(Ly), float(Lz)), "fsd_init_box")
 
     def init_aggregates(self, offsets, x_body, com, quat):
         off = np.ascontiguousarray(offsets, dtype=np.int32)
@@ -266,6 +281,12 @@ class System:
         xb = np.zeros((self.n_bead, 3)) if beads else None
         self._check(lib.fsd_get_state(self._h, _dptr(X), _dptr(q), _dptr(xb) if beads else None), "fsd_get_state")
         return (X, q, xb) if beads else (X, q)
+
+    def velocities(self):
+        """Aggregate velocities (n_agg, 6) of the last completed solve, by any call."""
+        U = np.zeros((self.n_agg, 6))
+        self._check(lib.fsd_get_velocities(self._h, _dptr(U)), "fsd_get_velocities")
+        return U
 
     def info(self) -> Info:
         inf = Info()
@@ -411,9 +432,10 @@ class System:
 class Batch:
     """Independent systems sharing the GPU (wraps fsd_batch)."""
 
-    def __init__(self, mem_budget_bytes: int, max_slots: int):
+    def __init__(self, mem_budget_bytes: int, max_slots: int, stream=None):
         h = C.c_void_p()
-        rc = lib.fsd_batch_create(int(mem_budget_bytes), int(max_slots), C.byref(h))
+        rc = lib.fsd_batch_create(int(mem_budget_bytes), int(max_slots), C.c_void_p(stream) if stream else None,
+                                  C.byref(h))
         if rc:
             raise FsdError(rc, "fsd_batch_create")
         self._h = h
@@ -465,6 +487,30 @@ class Batch:
         rc = lib.fsd_batch_set_fused(self._h, 1 if enable else 0)
         if rc:
             raise FsdError(rc, "fsd_batch_set_fused")
+
+    def set_timing(self, enable=True):
+        rc = lib.fsd_batch_set_timing(self._h, 1 if enable else 0)
+        if rc:
+            raise FsdError(rc, "fsd_batch_set_timing")
+
+    def timers(self):
+        """{timer: (total ms, launches, algorithmic bytes)} of the multi-system launches."""
+        n = len(TIMER_NAMES)
+        ms, by = np.zeros(n), np.zeros(n)
+        cnt = (C.c_longlong * n)()
+        rc = lib.fsd_batch_get_timers(self._h, _dptr(ms), cnt, _dptr(by))
+        if rc:
+            raise FsdError(rc, "fsd_batch_get_timers")
+        return {name: (float(ms[k]), int(cnt[k]), float(by[k])) for k, name in enumerate(TIMER_NAMES)}
+
+    def time_kernel(self, timer, reps=50):
+        """(average ms, algorithmic bytes) of one multi-system launch of `timer` over every
+        admitted system, replayed back to back."""
+        ms, by = C.c_double(0.0), C.c_double(0.0)
+        rc = lib.fsd_batch_time_kernel(self._h, TIMER_NAMES.index(timer), int(reps), C.byref(ms), C.byref(by))
+        if rc:
+            raise FsdError(rc, "fsd_batch_time_kernel")
+        return ms.value, by.value
 
     def close(self):
         if getattr(self, "_h", None):

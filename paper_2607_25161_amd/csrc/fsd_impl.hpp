@@ -49,6 +49,7 @@ struct FftPlan {
   int n;
   int nstage;
   int radix[kMaxStages];
+  unsigned long long rcode;  // the radices again, 4 bits per stage (stage 0 lowest)
 };
 
 // Constants of the wave-space (spectral Ewald) part of the mobility.
@@ -112,6 +113,8 @@ hipError_t neighbors_fill(NeighborWork* w, int nb, const double* pos4, const int
 void launch_lub_setup(int nb, const double* pos4, double L, double gam, const int* rowptr, const uint32_t* col,
                       double a, double eta, double eps_min, double r_pre, double rough_alpha,
                       double rough_h0, double* coef, double* rdiag, int* overlap_flag, hipStream_t st);
+void launch_lub_strain(int nb, const double* pos4, const double* r4, double L, double gam, const int* rowptr,
+                       const uint32_t* col, const double* coef, const double* E, double* f, hipStream_t st);
 void launch_precond_factor(int na, const int* offsets, const double* r4, const double* rdiag,
                            double drag_t, double drag_r, double* lu, int* piv, int* singular,
                            hipStream_t st);
@@ -136,6 +139,11 @@ template <typename R>
 void launch_interp_sheared(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
                            hipStream_t st, const int* skip, const int* body, const double* r4, const double* V);
 // pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
+// the allocation-free in-place transform of an n^3 complex grid (n <= kNoAllocFftMax) on the
+// caller's device buffer, its twiddles in a fixed device array of this GPU
+constexpr int kNoAllocFftMax = 512;
+constexpr int kMaxDevices = 64;
+hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st);
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
                   int sign, hipStream_t st, int pass = -1, const int* skip = nullptr);
@@ -262,14 +270,10 @@ void launch_dots(size_t n, int nq, const double* V, size_t ldv, const double* w,
 void launch_axpy_dots(size_t n, int nq, const double* V, size_t ldv, const double* h, double* w, int mode,
                       double* partial, double* out, unsigned* counters, hipStream_t st,
                       const int* skip = nullptr);
-// CGS2 passes with the basis held in registers, for nq <= 32 basis vectors (cgs_fits):
-// mode 0 out = V^T w; mode 1 w -= V hin, out = V^T w; mode 2 w -= V hin, out[0] = w.w and the
-// Arnoldi update *arn.  partial needs nq * cgs_blocks(n) doubles; counter is a zeroed ticket.
+// CGS2 passes with the basis held in registers work for nq <= 32 basis vectors (cgs_fits),
+// on cgs_blocks(n) workgroups
 bool cgs_fits(int nq);
 int cgs_blocks(size_t n);
-void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
-                double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
-                const ArnoldiArgs* arn);
 // The same passes as a chain without fences or tickets (one system): each pass writes only
 // its workgroup partial sums pout[q * cgs_blocks(n) + block]; the next launch's workgroups
 // each add the previous pass's partials pin in a fixed order (mode 1: h1, mode 2: h2, the
@@ -367,7 +371,11 @@ enum BatchKind {
   BK_INTERP,
   BK_AGG,
   BK_CGS,
-  BK_COUNT
+  BK_COUNT,
+  // launch kinds with the block table of another kind: the folded preconditioner and
+  // Arnoldi update (BK_PRECOND's table), the segment's last Arnoldi update (one per system)
+  BK_PRECOND_ARNOLDI = BK_COUNT,
+  BK_ARNOLDI
 };
 
 // FFT blocking used by both the single-system and the multi-system launches

@@ -156,29 +156,24 @@ void rpy_free(double r, double a, double eta, double* o) {
 bool make_plan(int n, FftPlan& p) {
   p.n = n;
   p.nstage = 0;
+  p.rcode = 0;
   int m = n;
-  while (m % 4 == 0 && p.nstage < kMaxStages) {
-    p.radix[p.nstage++] = 4;
-    m /= 4;
-  }
-  while (m % 2 == 0 && p.nstage < kMaxStages) {
-    p.radix[p.nstage++] = 2;
-    m /= 2;
-  }
-  while (m % 3 == 0 && p.nstage < kMaxStages) {
-    p.radix[p.nstage++] = 3;
-    m /= 3;
-  }
+  for (int r : {4, 2, 3, 5})
+    while (m % r == 0 && p.nstage < kMaxStages) {
+      p.rcode |= (unsigned long long)r << (4 * p.nstage);
+      p.radix[p.nstage++] = r;
+      m /= r;
+    }
   return m == 1 && n >= 2;
 }
 
-// smallest 2^a 3^b >= n with a >= 3 (a multiple of 8, for the gather spreading blocks)
+// smallest 2^a 3^b 5^c >= n with a >= 3 (a multiple of 8, for the gather spreading blocks)
 int next_smooth(int n) {
   for (int m = std::max(n, 8);; ++m) {
     if (m % 8) continue;
     int k = m;
-    while (k % 2 == 0) k /= 2;
-    while (k % 3 == 0) k /= 3;
+    for (int r : {2, 3, 5})
+      while (k % r == 0) k /= r;
     if (k == 1) return m;
   }
 }
@@ -219,6 +214,7 @@ double pick_xi(const fsd_params& p, int nb, double L) {
 struct fsd_system {
   fsd_params p{};
   hipStream_t st = nullptr;
+  bool solved = false;  // d_U holds the velocities of a completed solve of the full right-hand side
   bool own_stream = false;
   hipStream_t st2 = nullptr;           // side stream: the real-space sum overlaps the wave space
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -529,7 +525,7 @@ void choose_parameters(fsd_system* s) {
   int N = p.grid > 0 ? p.grid : next_smooth(int(std::ceil(kc * L / M_PI * le_margin)));
   if (N > kMaxGrid) throw ApiError(FSD_EINVAL, "spectral grid above 256^3; raise xi or lower the tolerance");
   if (!make_plan(N, s->plan))
-    throw ApiError(FSD_EINVAL, "grid size must be a product of powers of 2 and 3");
+    throw ApiError(FSD_EINVAL, "grid size must be a product of powers of 2, 3 and 5");
   int P = p.support > 0 ? p.support : int(std::ceil(2.0 / M_PI * std::log(1.0 / tol))) + 2;
   P = std::max(4, std::min(P, 21));
   if (P > N) throw ApiError(FSD_EINVAL, "Gaussian support exceeds the grid");
@@ -572,7 +568,10 @@ void choose_parameters(fsd_system* s) {
       if (worst <= tol) break;
     }
   }
-  if (rcut >= 3.0 * L) throw ApiError(FSD_EINVAL, "real-space cutoff exceeds three box lengths; raise xi");
+  // the pair search reaches rcut sqrt(1 + gamma^2) <= rcut sqrt(5)/2 on a sheared lattice; the
+  // neighbour-list entries hold image shifts of at most 3 box lengths
+  const double reach = rcut * (s->le ? std::sqrt(1.25) : 1.0);
+  if (reach >= 3.0 * L) throw ApiError(FSD_EINVAL, "real-space cutoff exceeds three box lengths; raise xi");
   r.r_cut = rcut;
   const int ntab = 4096;
   const double ht = rcut / ntab;
@@ -1120,8 +1119,11 @@ void assemble_rhs(fsd_system* s) {
   launch_rhs(s->nb, s->na, s->d_offsets, s->d_body, s->d_r4, s->d_E, s->d_force, brown ? s->d_ub : nullptr, s->d_b,
              s->d_wt, s->st);
   if (lub) {
-    launch_lub_apply(s->nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wt, s->d_fl, s->st);
-    // b2 = -(F_P + Sigma F_B + Sigma R_nf e) = -F_P + Sigma (f_e - F_B), f_e = -R_nf e
+    // R_FE : E_inf = -Sigma f_e, f_e minus the near-field force on beads moving with the
+    // ambient flow at their centroids; b2 = -(F_P + Sigma F_B + R_FE : E_inf)
+    //    = -F_P + Sigma (f_e - F_B)
+    launch_lub_strain(s->nb, s->d_pos4, s->d_r4, s->L, s->gam(), s->d_lrow, s->d_lcol, s->d_lcoef, s->d_E, s->d_fl,
+                      s->st);
     if (brown) launch_axpby(3 * size_t(s->nb), -1.0, s->d_fb, 1.0, s->d_fl, s->st);
   }
   // conservative bead-pair forces join F_P through Sigma: b2 gains -Sigma f_c
@@ -1298,6 +1300,7 @@ void finish_solve(fsd_system* s, bool ok) {
     HIPCHK(hipMemcpyAsync(s->d_xp[0], s->d_x, sizeof(double) * s->n, hipMemcpyDeviceToDevice, s->st));
     s->nprev = std::min(s->nprev + 1, q);
   }
+  if (s->sv.rhs_kind == 0) s->solved = true;
   s->sv.converged = ok;
   s->sv.status = ok ? FSD_OK : FSD_ENOCONV;
   if (!ok) s->err = "GMRES did not reach the tolerance within gmres_maxit iterations";
@@ -1563,8 +1566,10 @@ fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out) {
   return FSD_OK;
 }
 
-fsd_status fsd_init_box(fsd_system* s, double L) {
+fsd_status fsd_init_box(fsd_system* s, double Lx, double Ly, double Lz) {
   if (!s) return FSD_EINVAL;
+  if (!(Lx == Ly && Ly == Lz)) return fail(s, FSD_EINVAL, "the box must be a cube (Lx == Ly == Lz)");
+  const double L = Lx;
   if (!(L > 4.0 * s->p.radius)) return fail(s, FSD_EINVAL, "box side must exceed 4a");
   if (s->have_agg) return fail(s, FSD_ESTATE, "the box is fixed once aggregates are set");
   s->L = L;
@@ -1850,6 +1855,19 @@ fsd_status fsd_get_state(const fsd_system* cs, double* com, double* quat, double
   });
 }
 
+fsd_status fsd_get_velocities(const fsd_system* cs, double* U) {
+  fsd_system* s = const_cast<fsd_system*>(cs);
+  if (!s || !U) return FSD_EINVAL;
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!s->solved) return fail(s, FSD_ESTATE, "no solve has completed");
+  return guarded(s, [&]() -> fsd_status {
+    HIPCHK(hipMemcpyAsync(U, s->d_U, sizeof(double) * 6 * s->na, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return FSD_OK;
+  });
+}
+
 fsd_status fsd_get_info(const fsd_system* cs, fsd_info* info) {
   fsd_system* s = const_cast<fsd_system*>(cs);
   fsd_status c = check_ready(s);
@@ -2058,6 +2076,98 @@ fsd_status fsd_time_kernel(fsd_system* s, int timer, int reps, double* avg_ms) {
     HIPCHK(hipEventDestroy(ev[0]));
     HIPCHK(hipEventDestroy(ev[1]));
     *avg_ms = double(ms) / reps;
+    return FSD_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// Splitting parameters worth timing in [lo, hi]: for every grid size the Section 3.2 rule
+// gives there, the largest xi that still gives it (the cheapest wave space for that grid
+// and the shortest real-space cutoff), plus lo itself.
+std::vector<double> xi_candidates(const fsd_params& p, double L, double lo, double hi, bool le) {
+  const double a = p.radius, lnt = std::sqrt(-std::log(p.ewald_tol));
+  const double margin = le ? std::sqrt(1.25) : 1.0;
+  auto grid_of = [&](double xi) { return next_smooth(int(std::ceil((2.0 * lnt * xi + 1.0 / a) * L / M_PI * margin))); };
+  std::vector<double> out{lo};
+  for (int N = grid_of(lo); N <= std::min(grid_of(hi), kMaxGrid); N = next_smooth(N + 1)) {
+    double xi = std::min(hi, (N * M_PI / (L * margin) - 1.0 / a) / (2.0 * lnt));
+    while (xi > lo && grid_of(xi) > N) xi *= 1.0 - 1e-12;
+    if (xi > lo * (1.0 + 1e-9)) out.push_back(xi);
+  }
+  return out;
+}
+
+// average ms of one saddle-operator apply in the system's Arnoldi precision, replayed back to
+// back on the system stream (lists and factors built first)
+double time_saddle(fsd_system* s, int reps) {
+  if (!s->prepared) {
+    prepare_begin(s);
+    HIPCHK(hipStreamSynchronize(s->st));
+    prepare_end(s);
+  }
+  const bool fp32 = s->p.precision == FSD_MIXED;
+  launch_zero(s->d_z, sizeof(double) * s->n, s->st);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIPCHK(hipEventCreate(&ev[0]));
+  HIPCHK(hipEventCreate(&ev[1]));
+  float ms = 0;
+  try {
+    apply_saddle_p(s, s->d_z, s->d_t, fp32);  // warm
+    HIPCHK(hipEventRecord(ev[0], s->st));
+    for (int r = 0; r < reps; ++r) apply_saddle_p(s, s->d_z, s->d_t, fp32);
+    HIPCHK(hipEventRecord(ev[1], s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  } catch (...) {
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    throw;
+  }
+  HIPCHK(hipEventDestroy(ev[0]));
+  HIPCHK(hipEventDestroy(ev[1]));
+  return double(ms) / reps;
+}
+}  // namespace
+
+extern "C" {
+
+fsd_status fsd_autotune_xi(fsd_system* s, double xi_lo, double xi_hi, int reps, double* xi_out, double* ms_out) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!xi_out || reps < 1 || !(xi_lo > 0) || !(xi_hi >= xi_lo))
+    return fail(s, FSD_EINVAL, "fsd_autotune_xi: 0 < xi_lo <= xi_hi, reps >= 1");
+  return guarded(s, [&]() -> fsd_status {
+    const int na = s->na, nb = s->nb;
+    std::vector<double> com(3 * size_t(na)), quat(4 * size_t(na)), xb(3 * size_t(nb));
+    HIPCHK(hipMemcpyAsync(com.data(), s->d_com, sizeof(double) * com.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(quat.data(), s->d_quat, sizeof(double) * quat.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(xb.data(), s->d_xbody, sizeof(double) * xb.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    double best = s->wp.xi, best_ms = 1e300;
+    for (double xi : xi_candidates(s->p, s->L, xi_lo, xi_hi, s->le)) {
+      fsd_params p = s->p;
+      p.xi = xi;
+      p.grid = 0;
+      fsd_system* t = nullptr;
+      if (fsd_create(&p, s->st, &t) != FSD_OK) continue;
+      double ms = -1;
+      if (fsd_init_box(t, s->L, s->L, s->L) == FSD_OK && (!s->le || fsd_set_lees_edwards(t, 1, s->strain) == FSD_OK) &&
+          fsd_init_aggregates(t, na, s->h_offsets.data(), xb.data(), com.data(), quat.data()) == FSD_OK &&
+          fsd_set_shear(t, s->G) == FSD_OK) {
+        const fsd_status r = guarded(t, [&]() -> fsd_status {
+          ms = time_saddle(t, reps);
+          return FSD_OK;
+        });
+        if (r != FSD_OK) ms = -1;
+      }
+      fsd_destroy(t);
+      if (ms > 0 && ms < best_ms) best_ms = ms, best = xi;
+    }
+    if (!(best_ms < 1e300)) throw ApiError(FSD_EINVAL, "fsd_autotune_xi: no candidate could be set up");
+    *xi_out = best;
+    if (ms_out) *ms_out = best_ms;
     return FSD_OK;
   });
 }
@@ -2296,6 +2406,25 @@ fsd_status fsd_fft3d(int n, int sign, double* data) {
   return rc;
 }
 
+fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream) {
+  if (!d_data || (sign != 1 && sign != -1)) {
+    g_last_error = "fsd_fft3d_noalloc: a device buffer and sign +-1";
+    return FSD_EINVAL;
+  }
+  FftPlan plan;
+  if (n > kNoAllocFftMax || !make_plan(n, plan)) {
+    g_last_error = "fsd_fft3d_noalloc: n must be a product of 2, 3 and 5 of at most " +
+                   std::to_string(kNoAllocFftMax) + " (the size of its fixed twiddle array)";
+    return FSD_EINVAL;
+  }
+  const hipError_t e = launch_fft3d_noalloc(n, sign, d_data, plan, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) {
+    g_last_error = std::string("fsd_fft3d_noalloc: ") + hipGetErrorString(e);
+    return FSD_EDEVICE;
+  }
+  return FSD_OK;
+}
+
 }  // extern "C"
 
 // ==========================================================================================
@@ -2312,6 +2441,7 @@ struct fsd_batch {
   // a stream of their own
   bool fused = true;
   hipStream_t st = nullptr;
+  bool own_stream = false;
   BatchDesc* d_desc = nullptr;
   int* d_off = nullptr;
   int cap = 0;
@@ -2320,10 +2450,25 @@ struct fsd_batch {
   int nsys = 0, prec = 0;
   int total[BK_COUNT] = {0};
   size_t shm[BK_COUNT] = {0};
+  std::vector<fsd_system*> cyc;  // the systems of the tables, in table order
+  std::vector<char> active;      // cyc[k] still iterating in the current cycle (timing only)
+  // event timing of the multi-system launches (fsd_batch_set_timing)
+  struct Pend {
+    int cls;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  double t_ms[FSD_TIMER_COUNT] = {0}, t_bytes[FSD_TIMER_COUNT] = {0};
+  long long t_n[FSD_TIMER_COUNT] = {0};
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  std::vector<Pend> pending;
   ~fsd_batch() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     if (d_desc) (void)hipFree(d_desc);
     if (d_off) (void)hipFree(d_off);
-    if (st) (void)hipStreamDestroy(st);
+    if (st && own_stream) (void)hipStreamDestroy(st);
   }
 };
 
@@ -2488,6 +2633,8 @@ void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
     total[kind] = acc;
     shm[kind] = mx;
   }
+  b->cyc = cyc;
+  b->active.assign(ns, 1);
   const bool same = ns == b->nsys && prec == b->prec && off == b->h_off &&
                     std::memcmp(desc.data(), b->h_desc.data(), sizeof(BatchDesc) * ns) == 0;
   if (same) return;
@@ -2511,23 +2658,105 @@ void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
   std::copy(shm, shm + BK_COUNT, b->shm);
 }
 
+// algorithmic HBM bytes of one system's share of a multi-system launch of timer class cls
+// (as the single-system launches count them; nq basis vectors in the Gram-Schmidt passes)
+double batch_share_bytes(const fsd_system* s, int cls, int prec, int nq) {
+  const double full = prec ? grid_bytes<float>(s) : grid_bytes<double>(s), beads = 80.0 * s->nb;
+  const double n = double(s->n);
+  switch (cls) {
+    case FSD_TIMER_PRECOND: return 8.0 * n * 3 + 32.0 * s->nb + 312.0 * s->na;
+    case FSD_TIMER_REAL: return real_bytes(s);
+    case FSD_TIMER_SPREAD: return full + beads;
+    case FSD_TIMER_FFT_FIRST:
+    case FSD_TIMER_FFT_Y:
+    case FSD_TIMER_GREEN:
+    case FSD_TIMER_FFT_LAST: return 2.0 * full;
+    case FSD_TIMER_INTERP: return full + beads + 80.0 * s->nb + 48.0 * s->na;
+    case FSD_TIMER_RIGID: return rigid_bytes(s);
+    case FSD_TIMER_CGS_DOT: return 8.0 * n * (nq + 1);
+    case FSD_TIMER_CGS_UPDATE:
+    case FSD_TIMER_CGS_NORM: return 8.0 * n * (nq + 2);
+    default: return 0.0;
+  }
+}
+
+hipEvent_t batch_event(fsd_batch* b) {
+  if (b->ev_next == b->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    b->ev_pool.push_back(e);
+  }
+  return b->ev_pool[b->ev_next++];
+}
+
+// after the batch stream has drained: add the timed launches to the accumulators
+void batch_harvest(fsd_batch* b) {
+  if (b->pending.empty()) return;
+  HIPCHK(hipStreamSynchronize(b->st));
+  for (auto& p : b->pending) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    b->t_ms[p.cls] += ms;
+    b->t_n[p.cls] += 1;
+    b->t_bytes[p.cls] += p.bytes;
+  }
+  b->pending.clear();
+  b->ev_next = 0;
+}
+
+// one multi-system launch; with timing on it is bracketed by events on the batch stream and
+// counts the bytes of the systems still iterating
+template <typename L>
+void batch_launch(fsd_batch* b, int cls, int nq, L&& launch) {
+  if (!b->timing) {
+    launch();
+    return;
+  }
+  hipEvent_t ea = batch_event(b), eb = batch_event(b);
+  HIPCHK(hipEventRecord(ea, b->st));
+  launch();
+  HIPCHK(hipEventRecord(eb, b->st));
+  double by = 0;
+  for (size_t k = 0; k < b->cyc.size(); ++k)
+    if (b->active[k]) by += batch_share_bytes(b->cyc[k], cls, b->prec, nq);
+  b->pending.push_back({cls, by, ea, eb});
+}
+
 // Arnoldi steps j0 .. j0 + cnt - 1 of every system in the tables, one launch per kernel
 void batch_segment_body(fsd_batch* b, int j0, int cnt) {
   const int ns = b->nsys, prec = b->prec;
   auto off = [&](int kind) { return b->d_off + size_t(kind) * (ns + 1); };
+  auto mob = [&](int cls, int kind, int stage) {
+    batch_launch(b, cls, 0, [&] {
+      launch_batch_mobility(kind, prec, stage, b->d_desc, off(kind), ns, b->total[kind], b->shm[kind], b->st);
+    });
+  };
   for (int j = j0; j < j0 + cnt; ++j) {
-    launch_batch_solver(BK_PRECOND, j, 0, b->d_desc, off(BK_PRECOND), ns, b->total[BK_PRECOND], b->st);
-    launch_batch_mobility(BK_REAL, prec, 0, b->d_desc, off(BK_REAL), ns, b->total[BK_REAL], 0, b->st);
-    launch_batch_mobility(BK_SPREAD, prec, 0, b->d_desc, off(BK_SPREAD), ns, b->total[BK_SPREAD], b->shm[BK_SPREAD],
-                          b->st);
+    // inside a segment the Arnoldi update of step j-1 rides in the preconditioner of step j;
+    // the segment's last step makes its update alone (kb_arnoldi_reduce), so the host reads
+    // current stop flags after every segment
+    batch_launch(b, FSD_TIMER_PRECOND, 0, [&] {
+      launch_batch_solver(j > j0 ? BK_PRECOND_ARNOLDI : BK_PRECOND, j, 0, b->d_desc, off(BK_PRECOND), ns,
+                          b->total[BK_PRECOND], b->st);
+    });
+    mob(FSD_TIMER_REAL, BK_REAL, 0);
+    mob(FSD_TIMER_SPREAD, BK_SPREAD, 0);
+    static const int cls_of[5] = {FSD_TIMER_FFT_FIRST, FSD_TIMER_FFT_Y, FSD_TIMER_GREEN, FSD_TIMER_FFT_Y,
+                                  FSD_TIMER_FFT_LAST};
     for (int stage = 0; stage < 5; ++stage) {
       const int kind = (stage == 0 || stage == 4) ? BK_FFT_OUTER : (stage == 2 ? BK_FFT_GREEN : BK_FFT_MID);
-      launch_batch_mobility(kind, prec, stage, b->d_desc, off(kind), ns, b->total[kind], b->shm[kind], b->st);
+      mob(cls_of[stage], kind, stage);
     }
-    launch_batch_mobility(BK_INTERP, prec, 0, b->d_desc, off(BK_INTERP), ns, b->total[BK_INTERP], 0, b->st);
-    launch_batch_solver(BK_AGG, j, 0, b->d_desc, off(BK_AGG), ns, b->total[BK_AGG], b->st);
+    mob(FSD_TIMER_INTERP, BK_INTERP, 0);
+    batch_launch(b, FSD_TIMER_RIGID, 0, [&] {
+      launch_batch_solver(BK_AGG, j, 0, b->d_desc, off(BK_AGG), ns, b->total[BK_AGG], b->st);
+    });
+    static const int cgs_cls[3] = {FSD_TIMER_CGS_DOT, FSD_TIMER_CGS_UPDATE, FSD_TIMER_CGS_NORM};
     for (int mode = 0; mode < 3; ++mode)
-      launch_batch_solver(BK_CGS, j, mode, b->d_desc, off(BK_CGS), ns, b->total[BK_CGS], b->st);
+      batch_launch(b, cgs_cls[mode], j + 1, [&] {
+        launch_batch_solver(BK_CGS, j, mode, b->d_desc, off(BK_CGS), ns, b->total[BK_CGS], b->st);
+      });
+    if (j == j0 + cnt - 1) launch_batch_solver(BK_ARNOLDI, j, 0, b->d_desc, nullptr, ns, ns, b->st);
   }
 }
 
@@ -2573,7 +2802,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     });
     if (r != FSD_OK) fail_one(k, r);
   }
-  const int S = std::max(1, std::min(act[0]->batch, act[0]->m));
+  const int S = b->timing ? 1 : std::max(1, std::min(act[0]->batch, act[0]->m));
   const int prec = act[0]->p.precision == FSD_MIXED ? 1 : 0;
   while (true) {
     std::vector<fsd_system*> cyc;
@@ -2614,7 +2843,10 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
           HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, b->st));
         HIPCHK(hipStreamSynchronize(b->st));
         bool all = true;
-        for (auto* s : cyc) all = all && s->h_ctl->stop;
+        for (size_t k = 0; k < cyc.size(); ++k) {
+          b->active[k] = !cyc[k]->h_ctl->stop;
+          all = all && cyc[k]->h_ctl->stop;
+        }
         if (all || j0 + cnt >= cyc[0]->m) break;
       }
       for (auto* s : cyc) {  // cycle end and the next cycle start, per system
@@ -2646,6 +2878,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
   }
   for (auto* s : act) (void)hipStreamSynchronize(s->st);
+  batch_harvest(b);
   return worst;
 }
 
@@ -2665,14 +2898,19 @@ fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
 
 extern "C" {
 
-fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, fsd_batch** out) {
+fsd_status fsd_batch_create(size_t mem_budget_bytes, int max_slots, void* hip_stream, fsd_batch** out) {
   if (!out || max_slots < 1 || max_slots > 4096) return FSD_EINVAL;
   auto* b = new (std::nothrow) fsd_batch;
   if (!b) return FSD_ENOMEM;
   b->budget = mem_budget_bytes;
-  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
-    delete b;
-    return FSD_EDEVICE;
+  if (hip_stream) {
+    b->st = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return FSD_EDEVICE;
+    }
+    b->own_stream = true;
   }
   b->slot.assign(max_slots, nullptr);
   b->bytes.assign(max_slots, 0);
@@ -2737,6 +2975,115 @@ fsd_status fsd_batch_set_fused(fsd_batch* b, int enable) {
   if (!b) return FSD_EINVAL;
   b->fused = enable != 0;
   return FSD_OK;
+}
+
+fsd_status fsd_batch_set_timing(fsd_batch* b, int enable) {
+  if (!b) return FSD_EINVAL;
+  try {
+    batch_harvest(b);
+  } catch (const std::exception& e) {
+    b->err = e.what();
+    return FSD_EDEVICE;
+  }
+  b->timing = enable != 0;
+  std::fill(b->t_ms, b->t_ms + FSD_TIMER_COUNT, 0.0);
+  std::fill(b->t_bytes, b->t_bytes + FSD_TIMER_COUNT, 0.0);
+  std::fill(b->t_n, b->t_n + FSD_TIMER_COUNT, 0LL);
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_get_timers(fsd_batch* b, double* total_ms, long long* launches, double* bytes) {
+  if (!b || !total_ms || !launches) return FSD_EINVAL;
+  try {
+    batch_harvest(b);
+  } catch (const std::exception& e) {
+    b->err = e.what();
+    return FSD_EDEVICE;
+  }
+  for (int k = 0; k < FSD_TIMER_COUNT; ++k) {
+    total_ms[k] = b->t_ms[k];
+    launches[k] = b->t_n[k];
+    if (bytes) bytes[k] = b->t_bytes[k];
+  }
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_time_kernel(fsd_batch* b, int timer, int reps, double* avg_ms, double* bytes_per_launch) {
+  if (!b || !avg_ms || reps < 1 || timer < 0 || timer > FSD_TIMER_PRECOND) return FSD_EINVAL;
+  std::vector<fsd_system*> act;
+  for (auto* s : b->slot)
+    if (s) act.push_back(s);
+  if (act.empty() || !fusable(act)) {
+    b->err = "fsd_batch_time_kernel: needs admitted systems that share multi-system launches";
+    return FSD_ESTATE;
+  }
+  fsd_system* s0 = act[0];
+  return guarded(s0, [&]() -> fsd_status {
+    for (auto* s : act)
+      if (!s->prepared) {  // lists, plan and factors for the current positions
+        prepare_begin(s);
+        HIPCHK(hipStreamSynchronize(s->st));
+        prepare_end(s);
+      }
+    for (auto* s : act) HIPCHK(hipStreamSynchronize(s->st));
+    const int prec = s0->p.precision == FSD_MIXED ? 1 : 0;
+    set_tables(b, act, prec);
+    // every system iterating: the kernels return early for a raised stop flag
+    for (auto* s : act) HIPCHK(hipMemsetAsync(&s->d_ctl->stop, 0, sizeof(int), b->st));
+    const int ns = b->nsys;
+    auto off = [&](int kind) { return b->d_off + size_t(kind) * (ns + 1); };
+    auto one = [&]() {
+      switch (timer) {
+        case FSD_TIMER_PRECOND:
+          launch_batch_solver(BK_PRECOND, 0, 0, b->d_desc, off(BK_PRECOND), ns, b->total[BK_PRECOND], b->st);
+          break;
+        case FSD_TIMER_RIGID:
+          launch_batch_solver(BK_AGG, 0, 0, b->d_desc, off(BK_AGG), ns, b->total[BK_AGG], b->st);
+          break;
+        default: {
+          int kind = BK_REAL, stage = 0;
+          if (timer == FSD_TIMER_SPREAD) kind = BK_SPREAD;
+          if (timer == FSD_TIMER_FFT_FIRST) kind = BK_FFT_OUTER;
+          if (timer == FSD_TIMER_FFT_LAST) kind = BK_FFT_OUTER, stage = 4;
+          if (timer == FSD_TIMER_FFT_Y) kind = BK_FFT_MID, stage = 1;
+          if (timer == FSD_TIMER_GREEN) kind = BK_FFT_GREEN, stage = 2;
+          if (timer == FSD_TIMER_INTERP) kind = BK_INTERP;
+          launch_batch_mobility(kind, prec, stage, b->d_desc, off(kind), ns, b->total[kind], b->shm[kind], b->st);
+        }
+      }
+    };
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    float ms = 0;
+    try {
+      one();  // warm
+      launch_timing_mark(b->st);
+      HIPCHK(hipEventRecord(ev[0], b->st));
+      for (int r = 0; r < reps; ++r) one();
+      HIPCHK(hipEventRecord(ev[1], b->st));
+      launch_timing_mark(b->st);
+      HIPCHK(hipStreamSynchronize(b->st));
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    } catch (...) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      throw;
+    }
+    HIPCHK(hipEventDestroy(ev[0]));
+    HIPCHK(hipEventDestroy(ev[1]));
+    // the stop flags raised again: the next solve starts its own cycles
+    const int one_flag = 1;
+    for (auto* s : act) HIPCHK(hipMemcpyAsync(&s->d_ctl->stop, &one_flag, sizeof(int), hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipStreamSynchronize(b->st));
+    *avg_ms = double(ms) / reps;
+    if (bytes_per_launch) {
+      double by = 0;
+      for (auto* s : act) by += batch_share_bytes(s, timer, prec, 0);
+      *bytes_per_launch = by;
+    }
+    return FSD_OK;
+  });
 }
 
 void fsd_batch_destroy(fsd_batch* b) { delete b; }

@@ -3,6 +3,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "fsd_impl.hpp"
+#include "pair_code.hpp"
 
 namespace fsd {
 
@@ -134,9 +135,6 @@ void launch_integrate(int na, const double* U, double dt, double L, double gam, 
 // neighbour lists
 // ------------------------------------------------------------------------------------------
 
-__device__ inline uint32_t pack_entry(int j, int sx, int sy, int sz) {
-  return uint32_t(j) | (uint32_t(sx + 3) << 22) | (uint32_t(sy + 3) << 25) | (uint32_t(sz + 3) << 28);
-}
 
 struct NeighborWork {
   int nb = 0;
@@ -416,6 +414,52 @@ void launch_lub_setup(int nb, const double* pos4, double L, double gam, const in
                       double* coef, double* rdiag, int* overlap_flag, hipStream_t st) {
   k_lub_setup<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, L, gam, rowptr, col, a, eta, eps_min, r_pre,
                                                  rough_alpha, rough_h0, coef, rdiag, overlap_flag);
+}
+
+// Near-field force on beads that all move with the ambient flow at their aggregate's
+// centroid (V = 0), the term R_FE : E_inf of Eq. `FH_agg` at the bead level: each pair
+// resists w = (u_i - u_k) - W d, which for these beads is E (X_j - X_l) with
+// X_j - X_l = d_ik - r_i + r_k the centroid separation of the pair's image, so the force
+// on bead i is -sum_k R_pair E (d_ik - r_i + r_k).  Stored with the opposite sign,
+// f_i = sum_k R_pair E (d_ik - r_i + r_k), as the aggregate right-hand side
+// b2 = -F_P + Sigma f takes it.  One thread per bead, the separation rebuilt from the
+// positions and image code as k_lub_setup does.
+__global__ void k_lub_strain(int nb, const double4* __restrict__ pos, const double4* __restrict__ r4, double L,
+                             double gam, const int* __restrict__ rowptr, const uint32_t* __restrict__ col,
+                             const double* __restrict__ coef, const double* __restrict__ E, double* __restrict__ f) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double4 p = pos[i], ri = r4[i];
+  double Em[9];
+  for (int a = 0; a < 9; ++a) Em[a] = E[a];
+  double ax = 0, ay = 0, az = 0;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+    const uint32_t c = col[e];
+    const int k = int(c & 0x3FFFFFu);
+    const double4 q = pos[k], rk = r4[k];
+    const double dy = p.y - q.y + (int((c >> 25) & 7u) - 3) * L;
+    const double dx = p.x - q.x + (int((c >> 22) & 7u) - 3) * L + gam * dy;
+    const double dz = p.z - q.z + (int((c >> 28) & 7u) - 3) * L;
+    const double sx = dx - ri.x + rk.x, sy = dy - ri.y + rk.y, sz = dz - ri.z + rk.z;
+    const double wx = Em[0] * sx + Em[1] * sy + Em[2] * sz;
+    const double wy = Em[3] * sx + Em[4] * sy + Em[5] * sz;
+    const double wz = Em[6] * sx + Em[7] * sy + Em[8] * sz;
+    const double* cf = coef + 5 * e;
+    const double nd = cf[2] * wx + cf[3] * wy + cf[4] * wz;
+    const double g = (cf[0] - cf[1]) * nd;
+    ax += cf[1] * wx + g * cf[2];
+    ay += cf[1] * wy + g * cf[3];
+    az += cf[1] * wz + g * cf[4];
+  }
+  f[3 * i] = ax;
+  f[3 * i + 1] = ay;
+  f[3 * i + 2] = az;
+}
+
+void launch_lub_strain(int nb, const double* pos4, const double* r4, double L, double gam, const int* rowptr,
+                       const uint32_t* col, const double* coef, const double* E, double* f, hipStream_t st) {
+  k_lub_strain<<<nblocks(nb), kThreads, 0, st>>>(nb, (const double4*)pos4, (const double4*)r4, L, gam, rowptr, col,
+                                                  coef, E, f);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <mutex>
+
 #include "fsd_impl.hpp"
 #include "k_rigid.hpp"
 
@@ -1095,6 +1097,99 @@ __device__ inline T rot(T v, int s) {
 }
 }  // namespace
 
+namespace {
+// One radix-Rd butterfly of a Stockham stage: reads Rd inputs nbf apart, twiddles them by
+// w^(r k tstride) (w = exp(s 2 pi i / N), the table tw), transforms and writes them Ns apart.
+template <typename T, typename R, int Rd>
+__device__ __forceinline__ void butterfly(const T* li, T* lo, const T* tw, int b, int nbf, int k, int Ns, int tstride,
+                                          int od, int s) {
+  T v[Rd];
+#pragma unroll
+  for (int r = 0; r < Rd; ++r) v[r] = li[b + r * nbf];
+  if (Ns > 1) {
+#pragma unroll
+    for (int r = 1; r < Rd; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
+  }
+  if (Rd == 4) {
+    const T s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]), s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]), s);
+    lo[od] = cadd(s02, s13);
+    lo[od + Ns] = cadd(d02, d13);
+    lo[od + 2 * Ns] = csub(s02, s13);
+    lo[od + 3 * Ns] = csub(d02, d13);
+  } else if (Rd == 2) {
+    lo[od] = cadd(v[0], v[1]);
+    lo[od + Ns] = csub(v[0], v[1]);
+  } else if (Rd == 3) {
+    const R c3 = R(-0.5), s3 = R(0.86602540378443864676);
+    const T sm = cadd(v[1], v[2]), jd = rot(csub(v[1], v[2]), s);  // s i (v1 - v2)
+    T m1, y1, y2;
+    m1.x = v[0].x + c3 * sm.x;
+    m1.y = v[0].y + c3 * sm.y;
+    y1.x = m1.x + s3 * jd.x;
+    y1.y = m1.y + s3 * jd.y;
+    y2.x = m1.x - s3 * jd.x;
+    y2.y = m1.y - s3 * jd.y;
+    lo[od] = cadd(v[0], sm);
+    lo[od + Ns] = y1;
+    lo[od + 2 * Ns] = y2;
+  } else {  // radix 5: cos and sin of 2 pi / 5 and 4 pi / 5
+    const R c1 = R(0.30901699437494742410), c2 = R(-0.80901699437494742410);
+    const R s1 = R(0.95105651629515357212), s2 = R(0.58778525229247312917);
+    const T t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const T t3 = rot(csub(v[1], v[4]), s), t4 = rot(csub(v[2], v[3]), s);  // s i (v1 - v4), s i (v2 - v3)
+    T m1, m2, p1, p2;
+    m1.x = v[0].x + c1 * t1.x + c2 * t2.x;
+    m1.y = v[0].y + c1 * t1.y + c2 * t2.y;
+    m2.x = v[0].x + c2 * t1.x + c1 * t2.x;
+    m2.y = v[0].y + c2 * t1.y + c1 * t2.y;
+    p1.x = s1 * t3.x + s2 * t4.x;
+    p1.y = s1 * t3.y + s2 * t4.y;
+    p2.x = s2 * t3.x - s1 * t4.x;
+    p2.y = s2 * t3.y - s1 * t4.y;
+    lo[od] = cadd(v[0], cadd(t1, t2));
+    lo[od + Ns] = cadd(m1, p1);
+    lo[od + 2 * Ns] = cadd(m2, p2);
+    lo[od + 3 * Ns] = csub(m2, p2);
+    lo[od + 4 * Ns] = csub(m1, p1);
+  }
+}
+
+// Stockham stages on `nl` lines of length N held in LDS (`in`, scratch `out`);
+// returns the buffer holding the result.  The radices come from the plan's packed code
+// (4 bits per stage), so the stage loop indexes no array.
+template <typename T, typename R>
+__device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan& plan, int s) {
+  int Ns = 1;
+  const unsigned long long code = plan.rcode;
+  for (int stg = 0; stg < plan.nstage; ++stg) {
+    const int Rd = int((code >> (4 * stg)) & 15ull);
+    const int nbf = N / Rd;
+    const int tstride = N / (Ns * Rd);
+    for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
+      const int l = t / nbf, b = t % nbf;
+      const T* li = in + l * N;
+      T* lo = out + l * N;
+      const int k = b % Ns;
+      const int od = (b / Ns) * Ns * Rd + k;
+      if (Rd == 4)
+        butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 2)
+        butterfly<T, R, 2>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 3)
+        butterfly<T, R, 3>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else
+        butterfly<T, R, 5>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+    }
+    __syncthreads();
+    T* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= Rd;
+  }
+  return in;
+}
+}  // namespace
+
 template <typename R, int DIR>
 __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t cs, FftPlan plan,
                                                   const R* __restrict__ twiddle, int sign, int B, const int* __restrict__ skip) {
@@ -1133,65 +1228,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t c
     buf0[l * N + e] = base[off];
   }
   __syncthreads();
-  T* in = buf0;
-  T* out = buf1;
-  int Ns = 1;
-  const int s = sign > 0 ? 1 : -1;
-  for (int stg = 0; stg < plan.nstage; ++stg) {
-    const int Rd = plan.radix[stg];
-    const int nbf = N / Rd;
-    const int tstride = N / (Ns * Rd);
-    for (int t = threadIdx.x; t < B * nbf; t += blockDim.x) {
-      const int l = t / nbf, b = t % nbf;
-      const T* li = in + l * N;
-      T* lo = out + l * N;
-      const int k = b % Ns;
-      const int od = (b / Ns) * Ns * Rd + k;
-      if (Rd == 4) {
-        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf], v3 = li[b + 3 * nbf];
-        if (Ns > 1) {
-          v1 = cmul(v1, tw[k * tstride]);
-          v2 = cmul(v2, tw[2 * k * tstride]);
-          v3 = cmul(v3, tw[3 * k * tstride]);
-        }
-        const T s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = rot(csub(v1, v3), s);
-        lo[od] = cadd(s02, s13);
-        lo[od + Ns] = cadd(d02, d13);
-        lo[od + 2 * Ns] = csub(s02, s13);
-        lo[od + 3 * Ns] = csub(d02, d13);
-      } else if (Rd == 2) {
-        T v0 = li[b], v1 = li[b + nbf];
-        if (Ns > 1) v1 = cmul(v1, tw[k * tstride]);
-        lo[od] = cadd(v0, v1);
-        lo[od + Ns] = csub(v0, v1);
-      } else {  // radix 3
-        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf];
-        if (Ns > 1) {
-          v1 = cmul(v1, tw[k * tstride]);
-          v2 = cmul(v2, tw[2 * k * tstride]);
-        }
-        const R c3 = R(-0.5), s3 = R(0.86602540378443864676);
-        const T sm = cadd(v1, v2), df = csub(v1, v2);
-        T m1;
-        m1.x = v0.x + c3 * sm.x;
-        m1.y = v0.y + c3 * sm.y;
-        const T jd = rot(df, s);  // s i (v1 - v2)
-        T y1, y2;
-        y1.x = m1.x + s3 * jd.x;
-        y1.y = m1.y + s3 * jd.y;
-        y2.x = m1.x - s3 * jd.x;
-        y2.y = m1.y - s3 * jd.y;
-        lo[od] = cadd(v0, sm);
-        lo[od + Ns] = y1;
-        lo[od + 2 * Ns] = y2;
-      }
-    }
-    __syncthreads();
-    T* tmp = in;
-    in = out;
-    out = tmp;
-    Ns *= Rd;
-  }
+  const T* in = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign > 0 ? 1 : -1);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     int l, e;
     if (DIR == 0) {
@@ -1235,69 +1272,6 @@ void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, c
 }
 
 namespace {
-// Stockham stages on `nl` lines of length N held in LDS (`in`, scratch `out`);
-// returns the buffer holding the result.
-template <typename T, typename R>
-__device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan& plan, int s) {
-  int Ns = 1;
-  for (int stg = 0; stg < plan.nstage; ++stg) {
-    const int Rd = plan.radix[stg];
-    const int nbf = N / Rd;
-    const int tstride = N / (Ns * Rd);
-    for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
-      const int l = t / nbf, b = t % nbf;
-      const T* li = in + l * N;
-      T* lo = out + l * N;
-      const int k = b % Ns;
-      const int od = (b / Ns) * Ns * Rd + k;
-      if (Rd == 4) {
-        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf], v3 = li[b + 3 * nbf];
-        if (Ns > 1) {
-          v1 = cmul(v1, tw[k * tstride]);
-          v2 = cmul(v2, tw[2 * k * tstride]);
-          v3 = cmul(v3, tw[3 * k * tstride]);
-        }
-        const T s02 = cadd(v0, v2), d02 = csub(v0, v2), s13 = cadd(v1, v3), d13 = rot(csub(v1, v3), s);
-        lo[od] = cadd(s02, s13);
-        lo[od + Ns] = cadd(d02, d13);
-        lo[od + 2 * Ns] = csub(s02, s13);
-        lo[od + 3 * Ns] = csub(d02, d13);
-      } else if (Rd == 2) {
-        T v0 = li[b], v1 = li[b + nbf];
-        if (Ns > 1) v1 = cmul(v1, tw[k * tstride]);
-        lo[od] = cadd(v0, v1);
-        lo[od + Ns] = csub(v0, v1);
-      } else {
-        T v0 = li[b], v1 = li[b + nbf], v2 = li[b + 2 * nbf];
-        if (Ns > 1) {
-          v1 = cmul(v1, tw[k * tstride]);
-          v2 = cmul(v2, tw[2 * k * tstride]);
-        }
-        const R c3 = R(-0.5), s3 = R(0.86602540378443864676);
-        const T sm = cadd(v1, v2), df = csub(v1, v2);
-        T m1;
-        m1.x = v0.x + c3 * sm.x;
-        m1.y = v0.y + c3 * sm.y;
-        const T jd = rot(df, s);
-        T y1, y2;
-        y1.x = m1.x + s3 * jd.x;
-        y1.y = m1.y + s3 * jd.y;
-        y2.x = m1.x - s3 * jd.x;
-        y2.y = m1.y - s3 * jd.y;
-        lo[od] = cadd(v0, sm);
-        lo[od + Ns] = y1;
-        lo[od + 2 * Ns] = y2;
-      }
-    }
-    __syncthreads();
-    T* tmp = in;
-    in = out;
-    out = tmp;
-    Ns *= Rd;
-  }
-  return in;
-}
-
 template <typename T>
 __device__ inline void load_twiddles(T* tw, const T* twg, int N, int sign) {
   for (int t = threadIdx.x; t < N; t += blockDim.x) {
@@ -1769,6 +1743,54 @@ template void launch_interp_sheared<double>(int, const double*, const double*, c
                                             const int*, const int*, const double*, const double*);
 template void launch_interp_sheared<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t,
                                            const int*, const int*, const double*, const double*);
+// ------------------------------------------------------------------------------------------
+// the allocation-free transform (fsd_fft3d_noalloc): its twiddle table lives in file-scope
+// device memory, one copy per GPU held until the process ends, sized for the largest n
+// ------------------------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[2 * kNoAllocFftMax];
+
+// exp(-2 pi i t / n) for t < n, interleaved (re, im)
+__global__ void k_twiddles(int n, double* __restrict__ tw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double sv, cv;
+  sincospi(2.0 * double(t) / double(n), &sv, &cv);
+  tw[2 * t] = cv;
+  tw[2 * t + 1] = -sv;
+}
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+// the device address of this GPU's copy of `scratch`, looked up once per device
+hipError_t noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st) {
+  double* tw = nullptr;
+  hipError_t e = noalloc_scratch(&tw);
+  if (e != hipSuccess) return e;
+  k_twiddles<<<(n + 255) / 256, 256, 0, st>>>(n, tw);
+  launch_fft3d<double>(data, 1, 2 * size_t(n) * n * n, plan, tw, sign, st);
+  return hipGetLastError();
+}
+
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 

@@ -729,65 +729,10 @@ int cgs_blocks(size_t n) {
   return int(b < 1 ? 1 : (b > kCgsBlocks ? kCgsBlocks : b));
 }
 
-// MODE 0: out[q] = V_q . w                        (first Gram-Schmidt pass)
-// MODE 1: w -= sum_q hin[q] V_q; out[q] = V_q . w (second pass, fused with the first update)
-// MODE 2: w -= sum_q hin[q] V_q; out[0] = w . w, and the last workgroup runs the Arnoldi update
-template <int MODE>
-__device__ __forceinline__ void cgs_body(size_t n, int nq, const double* __restrict__ V, size_t ldv,
-                                                     const double* __restrict__ hin, double* __restrict__ w,
-                                                     double* __restrict__ partial, double* __restrict__ out,
-                                                     unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn, int bx_, int by_, int gx_) {
-  if (skip && *skip) return;
-  __shared__ double sh[kCgsWaves][kCgsMax];
-  __shared__ double st[3][kCgsMax];
-  __shared__ unsigned ticket;
-  double h[kCgsMax], acc[kCgsMax];
-#pragma unroll
-  for (int q = 0; q < kCgsMax; ++q) {
-    h[q] = (MODE >= 1 && q < nq) ? hin[q] : 0.0;
-    acc[q] = 0.0;
-  }
-  for (size_t i = size_t(bx_) * kCgsThreads + threadIdx.x; i < n; i += size_t(gx_) * kCgsThreads) {
-    double v[kCgsMax];
-#pragma unroll
-    for (int q = 0; q < kCgsMax; ++q) v[q] = q < nq ? V[size_t(q) * ldv + i] : 0.0;
-    double wi = w[i];
-    if (MODE >= 1) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kCgsMax; ++q) s += h[q] * v[q];
-      wi -= s;
-      w[i] = wi;
-    }
-    if (MODE <= 1) {
-#pragma unroll
-      for (int q = 0; q < kCgsMax; ++q) acc[q] += v[q] * wi;
-    } else {
-      acc[0] += wi * wi;
-    }
-  }
-  const int nout = MODE <= 1 ? nq : 1;
-  const int nblk = gx_;
-  block_sums(acc, nout, sh);
-  if (threadIdx.x < nout) partial[size_t(threadIdx.x) * nblk + bx_] = sh[0][threadIdx.x];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) ticket = atomicAdd(counter, 1u);
-  __syncthreads();
-  if (ticket != unsigned(nblk - 1)) return;
-  __threadfence();
-#pragma unroll
-  for (int q = 0; q < kCgsMax; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kCgsThreads) {
-#pragma unroll
-    for (int q = 0; q < kCgsMax; ++q)
-      if (q < nout) acc[q] += partial[size_t(q) * nblk + b];
-  }
-  block_sums(acc, nout, sh);
-  if (threadIdx.x < nout) out[threadIdx.x] = sh[0][threadIdx.x];
-  if (MODE == 2) arnoldi_update_staged(arn, sh[0][0], st[0], st[1], st[2]);
-  if (threadIdx.x == 0) *counter = 0u;
-}
+// The CGS2 passes, MODE 0: out[q] = V_q . w (first Gram-Schmidt pass); MODE 1: w -= sum_q
+// hin[q] V_q, out[q] = V_q . w (second pass, fused with the first update); MODE 2: w -= sum_q
+// hin[q] V_q, out[0] = w . w.  Each workgroup writes its partial sums; the next launch of the
+// chain adds them (reduce_partials).
 
 // out[q] = sum over b of part[q * nblk + b] for q < nq (<= kCgsMax), in the same fixed order
 // in every workgroup: thread t adds the terms b = t / 32 + 8 k of column q = t % 32, and the
@@ -808,17 +753,15 @@ __device__ inline void reduce_partials(const double* __restrict__ part, int nblk
   __syncthreads();
 }
 
-// One CGS2 pass of the fence-free chain (see launch_cgs_chain).
+// One CGS2 pass of the fence-free chain (see launch_cgs_chain): workgroup bx of nblk.
 template <int MODE>
-__global__ __launch_bounds__(kCgsThreads) void k_cgs_chain(size_t n, int nq, const double* __restrict__ V, size_t ldv,
-                                                           const double* __restrict__ pin, double* __restrict__ w,
-                                                           double* __restrict__ pout, double* __restrict__ hout,
-                                                           const int* __restrict__ skip) {
-  if (skip && *skip) return;
+__device__ __forceinline__ void cgs_chain_body(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                               const double* __restrict__ pin, double* __restrict__ w,
+                                               double* __restrict__ pout, double* __restrict__ hout, int bx,
+                                               int nblk) {
   __shared__ double sh[kCgsWaves][kCgsMax];
   __shared__ double shq[8 * 32];
   __shared__ double hq[kCgsMax];
-  const int nblk = gridDim.x, bx = blockIdx.x;
   if (MODE >= 1) {
     reduce_partials(pin, nblk, nq, shq, hq);
     if (bx == 0 && threadIdx.x < nq) hout[threadIdx.x] = hq[threadIdx.x];
@@ -853,6 +796,15 @@ __global__ __launch_bounds__(kCgsThreads) void k_cgs_chain(size_t n, int nq, con
   if (threadIdx.x < nout) pout[size_t(threadIdx.x) * nblk + bx] = sh[0][threadIdx.x];
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kCgsThreads) void k_cgs_chain(size_t n, int nq, const double* __restrict__ V, size_t ldv,
+                                                           const double* __restrict__ pin, double* __restrict__ w,
+                                                           double* __restrict__ pout, double* __restrict__ hout,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  cgs_chain_body<MODE>(n, nq, V, ldv, pin, w, pout, hout, blockIdx.x, gridDim.x);
+}
+
 // w.w from the mode-2 partials, then the Arnoldi update (one workgroup)
 __global__ __launch_bounds__(kCgsThreads) void k_arnoldi_reduce(ArnoldiArgs a, const double* __restrict__ pin, int nblk,
                                                                 double* __restrict__ hn2) {
@@ -863,14 +815,6 @@ __global__ __launch_bounds__(kCgsThreads) void k_arnoldi_reduce(ArnoldiArgs a, c
   reduce_partials(pin, nblk, 1, shq, tot);
   if (threadIdx.x == 0) *hn2 = tot[0];
   arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
-}
-
-template <int MODE>
-__global__ __launch_bounds__(kCgsThreads) void k_cgs(size_t n, int nq, const double* __restrict__ V, size_t ldv,
-                                                     const double* __restrict__ hin, double* __restrict__ w,
-                                                     double* __restrict__ partial, double* __restrict__ out,
-                                                     unsigned* counter, const int* __restrict__ skip, ArnoldiArgs arn) {
-  cgs_body<MODE>(n, nq, V, ldv, hin, w, partial, out, counter, skip, arn, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 bool cgs_fits(int nq) { return nq >= 1 && nq <= kCgsMax; }
@@ -895,13 +839,13 @@ void launch_arnoldi_reduce(const ArnoldiArgs& a, const double* pin, int nblk, do
 // value), takes v_(j+1) = w / ||w|| and applies the preconditioner; workgroup 0 also makes
 // the Hessenberg/Givens update and the stop decision of step j.  Once that update stops the
 // cycle, the vectors this launch writes are not used.
-__global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const int* __restrict__ offsets,
-                                                         const double4* __restrict__ r4, const double* __restrict__ lu,
-                                                         const int* __restrict__ piv, double drag_t, double drag_r,
-                                                         const double* __restrict__ src, double* __restrict__ vout,
-                                                         double* __restrict__ z, ArnoldiArgs a,
-                                                         const double* __restrict__ pin, int nblk,
-                                                         double* __restrict__ hn2, const int* __restrict__ skip) {
+__device__ __forceinline__ void precond_arnoldi_body(int nb, int na, const int* __restrict__ offsets,
+                                                    const double4* __restrict__ r4, const double* __restrict__ lu,
+                                                    const int* __restrict__ piv, double drag_t, double drag_r,
+                                                    const double* __restrict__ src, double* __restrict__ vout,
+                                                    double* __restrict__ z, const ArnoldiArgs& a,
+                                                    const double* __restrict__ pin, int nblk,
+                                                    double* __restrict__ hn2, const int* __restrict__ skip, int bx) {
   // workgroup 0 of this very launch may raise the stop flag while others start, so each
   // workgroup reads it once and all its wavefronts take the same branch (the barriers
   // below need every wavefront)
@@ -914,7 +858,7 @@ __global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const i
   __shared__ double st[3][kCgsMax];
   __shared__ double sc;
   reduce_partials(pin, nblk, 1, shq, tot);
-  if (blockIdx.x == 0) {
+  if (bx == 0) {
     if (threadIdx.x == 0) *hn2 = tot[0];
     arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
   }
@@ -923,8 +867,18 @@ __global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const i
     sc = hn > 0 ? 1.0 / hn : 0.0;
   }
   __syncthreads();
-  precond_fused_body(nb, na, offsets, r4, lu, piv, drag_t, drag_r, src, &sc, vout, z, nullptr, blockIdx.x, blockIdx.y,
-                     gridDim.x);
+  precond_fused_body(nb, na, offsets, r4, lu, piv, drag_t, drag_r, src, &sc, vout, z, nullptr, bx, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void k_precond_arnoldi(int nb, int na, const int* __restrict__ offsets,
+                                                         const double4* __restrict__ r4, const double* __restrict__ lu,
+                                                         const int* __restrict__ piv, double drag_t, double drag_r,
+                                                         const double* __restrict__ src, double* __restrict__ vout,
+                                                         double* __restrict__ z, ArnoldiArgs a,
+                                                         const double* __restrict__ pin, int nblk,
+                                                         double* __restrict__ hn2, const int* __restrict__ skip) {
+  precond_arnoldi_body(nb, na, offsets, r4, lu, piv, drag_t, drag_r, src, vout, z, a, pin, nblk, hn2, skip,
+                       blockIdx.x);
 }
 
 void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4, const double* lu, const int* piv,
@@ -933,19 +887,6 @@ void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4
                             const int* skip) {
   launch_k(k_precond_arnoldi, (na + 3) / 4, 256, 0, st, nb, na, offsets, (const double4*)r4, lu, piv, drag_t, drag_r,
            src, vout, z, a, pin, nblk, hn2, skip);
-}
-
-void launch_cgs(int mode, size_t n, int nq, const double* V, size_t ldv, const double* hin, double* w,
-                double* partial, double* out, unsigned* counter, hipStream_t st, const int* skip,
-                const ArnoldiArgs* arn) {
-  const ArnoldiArgs a = arn ? *arn : ArnoldiArgs{};
-  const int g = cgs_blocks(n);
-  if (mode == 0)
-    launch_k(k_cgs<0>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
-  else if (mode == 1)
-    launch_k(k_cgs<1>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
-  else
-    launch_k(k_cgs<2>, g, kCgsThreads, 0, st, n, nq, V, ldv, hin, w, partial, out, counter, skip, a);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -985,16 +926,44 @@ __global__ __launch_bounds__(256) void kb_agg(const BatchDesc* __restrict__ D, c
                &d.ctl->stop, blockIdx.x - off[s], 0, 0);
 }
 
+// The fence-free CGS2 chain of every system (partials P0, P1, P2 of the system's part
+// array, as the single-system chain): pass MODE of Arnoldi step j
 template <int MODE>
 __global__ __launch_bounds__(kCgsThreads) void kb_cgs(const BatchDesc* __restrict__ D, const int* __restrict__ off,
                                                      int nsys, int j) {
   const int s = batch_sys_s(off, nsys, blockIdx.x);
   const BatchDesc& d = D[s];
-  const ArnoldiArgs arn{j, d.ctl, d.h1, d.h2, d.H, d.gcs, d.gsn, d.g, d.scal};
-  const double* hin = MODE == 0 ? nullptr : (MODE == 1 ? d.h1 : d.h2);
-  double* out = MODE == 0 ? d.h1 : (MODE == 1 ? d.h2 : d.hn2);
-  cgs_body<MODE>(d.n, j + 1, d.basis, d.n, hin, d.w, d.part, out, d.counters, &d.ctl->stop, arn,
-                 blockIdx.x - off[s], 0, d.ncgs);
+  if (d.ctl->stop) return;
+  const int G = d.ncgs;
+  const double* pin = MODE == 0 ? nullptr : d.part + size_t(32) * G * (MODE - 1);
+  double* pout = d.part + size_t(32) * G * MODE;
+  double* hout = MODE == 1 ? d.h1 : d.h2;
+  cgs_chain_body<MODE>(d.n, j + 1, d.basis, d.n, pin, d.w, pout, hout, blockIdx.x - off[s], G);
+}
+
+// Arnoldi step j > 0 inside a segment: step j-1's update (from its ||w||^2 partials) folded
+// into the preconditioner that forms v_j, as k_precond_arnoldi
+__global__ __launch_bounds__(256) void kb_precond_arnoldi(const BatchDesc* __restrict__ D,
+                                                         const int* __restrict__ off, int nsys, int j) {
+  const int s = batch_sys_s(off, nsys, blockIdx.x);
+  const BatchDesc& d = D[s];
+  const ArnoldiArgs prev{j - 1, d.ctl, d.h1, d.h2, d.H, d.gcs, d.gsn, d.g, d.scal};
+  precond_arnoldi_body(d.nb, d.na, d.offsets, (const double4*)d.r4, d.lu, d.piv, d.drag_t, d.drag_r, d.w,
+                       d.basis + size_t(j) * d.n, d.z, prev, d.part + size_t(64) * d.ncgs, d.ncgs, d.hn2,
+                       &d.ctl->stop, blockIdx.x - off[s]);
+}
+
+// the last step of a segment: its Arnoldi update alone, one workgroup per system
+__global__ __launch_bounds__(kCgsThreads) void kb_arnoldi_reduce(const BatchDesc* __restrict__ D, int nsys, int j) {
+  const BatchDesc& d = D[blockIdx.x];
+  if (d.ctl->stop) return;
+  __shared__ double shq[8 * 32];
+  __shared__ double tot[kCgsMax];
+  __shared__ double st[3][kCgsMax];
+  const ArnoldiArgs a{j, d.ctl, d.h1, d.h2, d.H, d.gcs, d.gsn, d.g, d.scal};
+  reduce_partials(d.part + size_t(64) * d.ncgs, d.ncgs, 1, shq, tot);
+  if (threadIdx.x == 0) *d.hn2 = tot[0];
+  arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
 }
 
 void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, const int* off, int nsys, int total,
@@ -1002,6 +971,10 @@ void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, cons
   if (total <= 0) return;
   if (kind == BK_PRECOND)
     kb_precond<<<total, 256, 0, st>>>(D, off, nsys, j);
+  else if (kind == BK_PRECOND_ARNOLDI)
+    kb_precond_arnoldi<<<total, 256, 0, st>>>(D, off, nsys, j);
+  else if (kind == BK_ARNOLDI)
+    kb_arnoldi_reduce<<<nsys, kCgsThreads, 0, st>>>(D, nsys, j);
   else if (kind == BK_AGG)
     kb_agg<<<total, 256, 0, st>>>(D, off, nsys);
   else if (kind == BK_CGS && cgs_mode == 0)

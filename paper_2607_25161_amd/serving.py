@@ -51,14 +51,16 @@ class LibBackend:
         self.params = params
         self.budget = mem_budget
         self.warm_start = warm_start  # GMRES initial guess of each request's solves (fsd_set_warm_start)
-        # requests on the sheared lattice: their grid is larger than `estimate` assumes, which
-        # the batch's own admission (it counts the grid a system holds) catches
         self.lees_edwards = lees_edwards
 
     def estimate(self, req: Request) -> int:
+        """Device bytes the request's system will hold.  On the sheared lattice the library
+        grows the grid by sqrt(5)/2 per side; sizing the estimate on a box that much larger
+        bounds that grid from above (the other terms only grow with it)."""
         s = req.suspension
         p = self.F.default_params(**self._kw(s))
-        return self.F.estimate_bytes(p, s.n_bead, s.n_agg, s.L)
+        L = s.L * (1.25 ** 0.5 if self.lees_edwards else 1.0)
+        return self.F.estimate_bytes(p, s.n_bead, s.n_agg, L)
 
     def _kw(self, s):
         kw = dict(eta=s.eta, radius=s.a, xi=s.xi, ewald_tol=s.ewald_tol, grid=s.grid, r_lub=s.r_lub,
@@ -130,6 +132,13 @@ class BatchEngine:
                 break
             slot = self.backend.admit(req)
             if slot is None:
+                if not self.active:
+                    # refused by an empty batch: it will never fit
+                    self.queue.popleft()
+                    req.status = -7
+                    req.finished = self.clock()
+                    self.done.append(req)
+                    continue
                 break
             self.queue.popleft()
             req.started = self.clock()

@@ -6,6 +6,9 @@ system before comparing.
 
     python tests/golden/make_golden.py doublets      # 16 doublets, one solve
     python tests/golden/make_golden.py clusters      # 256 x 8 clusters, 10 steps
+    python tests/golden/make_golden.py c3sub         # 150 x 20 clusters of the 4096 x 20 generator
+    python tests/golden/make_golden.py uneven        # 8 of the 64 uneven systems, one solve each
+    python tests/golden/make_golden.py request       # one Brownian serving request, given noise
 """
 from __future__ import annotations
 
@@ -20,7 +23,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import fsdgen  # noqa: E402
-from oracle import integrate, saddle  # noqa: E402
+from oracle import brownian, integrate, rigid, saddle  # noqa: E402
+
+# systems of the 64-system uneven set with an oracle result (sizes 254 .. 1956 beads,
+# volume fractions 0.02 .. 0.22, grids 64^3 .. 96^3 at xi = 25/L)
+UNEVEN_PICK = (17, 3, 30, 41, 54, 28, 36, 62)
+# the serving request with an oracle result: 804 beads in aggregates of 29, phi 0.22
+REQUEST_PICK = 27
+REQUEST_NOISE_SEED = fsdgen.BASE_SEED + 900
 
 
 def digest(s) -> str:
@@ -47,11 +57,60 @@ def run(index: int, n_steps: int, out: str):
              residual=np.array(res), dt=s.dt, com_final=com, quat_final=quat)
 
 
+def c3_sub():
+    """One solve of a 150 x 20 sub-box of the 4096 x 20 generator (phi 0.20), at the
+    oracle's own Ewald split (the result does not depend on it)."""
+    s = fsdgen.config(2, n_agg=150, grid=0, name="clusters-150x20")
+    t = time.time()
+    U, F, r, A = saddle.solve_suspension(s)
+    print(f"{s.name}: {s.n_bead} beads, residual {r:.2e} ({time.time() - t:.1f} s)", flush=True)
+    np.savez(os.path.join(HERE, "clusters150x20_oracle.npz"), digest=np.array(digest(s)), U=U, residual=r)
+
+
+def uneven():
+    """One solve of each picked system of the uneven set."""
+    out = {}
+    for k in UNEVEN_PICK:
+        s = fsdgen.uneven_system(k)
+        t = time.time()
+        U, F, r, A = saddle.solve_suspension(s)
+        print(f"{s.name}: {s.n_bead} beads, residual {r:.2e} ({time.time() - t:.1f} s)", flush=True)
+        out[f"U_{k}"] = U
+        out[f"digest_{k}"] = np.array(digest(s))
+    np.savez(os.path.join(HERE, "uneven8_oracle.npz"), picks=np.array(UNEVEN_PICK), **out)
+
+
+def request():
+    """One Brownian solve of a serving request (kT = 1, dt = 1e-3, shear rate 1, splitting
+    parameter 25/L) given its real-space and near-field noise (grid noise zero): the
+    real-space root by eigendecomposition of the PSE real part, summed to a cutoff of
+    6/xi (its functions are below 1e-14 of the self mobility there)."""
+    s = fsdgen.serving_request(REQUEST_PICK, kT=1.0, shear_rate=1.0)
+    xi = 25.0 / s.L
+    psi_r, psi_nf = fsdgen.brownian_noise(s.n_bead, REQUEST_NOISE_SEED)
+    t = time.time()
+    A = saddle.assemble(s.L, s.a, s.eta, s.offsets, s.x_body, s.com, s.quat, s.force, s.grad_u, r_lub=s.r_lub)
+    body = rigid.body_index(s.offsets)
+    ub = brownian.real_space_slip(A.x, s.L, s.a, s.eta, xi, 6.0 / xi, psi_r, s.kT, s.dt)
+    fb = np.zeros((s.n_bead, 6))
+    fb[:, :3] = brownian.near_field_force(A.x, body, s.L, s.a, s.eta, s.r_lub, psi_nf, s.kT, s.dt)
+    U, F, r, _ = saddle.solve(s.L, s.a, s.eta, s.offsets, s.x_body, s.com, s.quat, s.force, s.grad_u,
+                              r_lub=s.r_lub, u_brown=ub, f_brown_nf=fb)
+    print(f"{s.name}: {s.n_bead} beads, residual {r:.2e} ({time.time() - t:.1f} s)", flush=True)
+    np.savez(os.path.join(HERE, "request27_oracle.npz"), digest=np.array(digest(s)), U=U, residual=r, xi=xi)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "doublets"
     if which == "doublets":
         run(0, 1, "doublets16_oracle.npz")
     elif which == "clusters":
         run(1, 10, "clusters256x8_oracle.npz")
+    elif which == "c3sub":
+        c3_sub()
+    elif which == "uneven":
+        uneven()
+    elif which == "request":
+        request()
     else:
         raise SystemExit(f"unknown workload {which}")

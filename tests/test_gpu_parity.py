@@ -61,7 +61,7 @@ def _make(F, kw, **p):
 # FFT stages
 # ---------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [8, 12, 24, 32, 48, 64, 72])
+@pytest.mark.parametrize("n", [8, 12, 24, 25, 32, 40, 48, 64, 72, 80, 120])
 def test_fft3d_matches_numpy(F, n):
     rng = np.random.default_rng(n)
     a = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
@@ -330,8 +330,10 @@ def test_batch_results_equal_alone(F, precision, fused):
     for k, sl in enumerate(slots):
         info = b.info(sl)
         assert info.status == 0 and info.rel_residual_fp64 <= 1e-8
-        U, _, _ = live[k].solve()  # same configuration: the batch left the state unchanged
-        assert np.abs(U - alone[k]).max() <= 1e-12 * np.abs(alone[k]).max()
+        U = live[k].velocities()  # the batch's own solution
+        # FP64: the same arithmetic up to summation order; FP32 matvecs: within the solver tolerance
+        tol = 1e-11 if precision == 0 else 1e-7
+        assert np.abs(U - alone[k]).max() <= tol * np.abs(alone[k]).max(), (k, np.abs(U - alone[k]).max())
     # one Euler step in the batch equals one step alone.  In FP64 both runs take the same
     # arithmetic up to summation order; with FP32 matvecs the multi-system launches sum
     # the real-space rows in another order, so the two solutions agree only to the

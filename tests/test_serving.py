@@ -167,3 +167,26 @@ def test_poisson_arrivals_rate():
     t = poisson_arrivals(rng, 20000, rate=4.0)
     assert np.all(np.diff(t) > 0)
     assert t[-1] / 20000 == pytest.approx(0.25, rel=0.03)
+
+
+class UnderEstimatingBackend(FakeBackend):
+    """The estimate says a request fits, but the batch refuses it even when empty (a held
+    size above the estimate): the engine must reject it instead of retrying forever."""
+
+    def estimate(self, req):
+        return 1
+
+    def admit(self, req):
+        if req.suspension.n_bead > 4000:
+            return None
+        return super().admit(req)
+
+
+def test_request_refused_by_an_empty_batch_is_rejected():
+    clk = FakeClock()
+    be = UnderEstimatingBackend(clk, budget=1 << 40, slots=2)
+    eng = BatchEngine(be, max_slots=2, clock=clk)
+    rep = eng.run(_requests([5000, 300], [0.0, 0.0], n_steps=2))
+    assert rep["completed"] == 1 and rep["failed"] == 1
+    bad = [r for r in eng.done if r.status != 0]
+    assert bad[0].rid == 0 and bad[0].status == -7
