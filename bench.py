@@ -202,10 +202,34 @@ def run_plain(F, systems, steps, warm, graphs=True):
             "gmres_iterations_mean": round(float(np.mean(its)), 2), "graphs": graphs, "steps": steps}
 
 
-def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=False, replay=None):
+def tuned_xi(F, systems, precision):
+    """Per system, the measured fastest splitting parameter between the two fixed policies
+    of Section 3.2 (0.5/a and 25/L), in the given precision."""
+    out = []
+    for s0 in systems:
+        probe = F.System.from_suspension(s0, precision=precision)
+        lo, hi = sorted((0.5 / s0.a, 25.0 / s0.L))
+        xi, _ = probe.autotune_xi(lo, hi, 5)
+        probe.close()
+        out.append(xi)
+    return out
+
+
+def run_plain_xi(F, systems, steps, warm, xis):
+    """The plain path (eager launches) at given splitting parameters."""
+    import dataclasses
+    return run_plain(F, [dataclasses.replace(s0, xi=xi) for s0, xi in zip(systems, xis)], steps, warm, graphs=False)
+
+
+def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=False, replay=None, xis=None,
+              tiles=False):
     """All systems admitted to one batch and stepped together; returns the figures, the
-    per-step latencies and, with timing, the kernel table and the replayed dominant launch."""
-    sys_ = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+    per-step latencies and, with timing, the kernel table and the replayed dominant launch.
+    xis: a splitting parameter per system (default: the workload's own); tiles: measure
+    each system's transform tiles first."""
+    sys_ = [F.System.from_suspension(s0, precision=precision, **({"xi": xis[k]} if xis else {}))
+            for k, s0 in enumerate(systems)]
+    chosen = [s.autotune_tiles(10) for s in sys_] if tiles else None
     for s in sys_:
         s.set_warm_start(warm)
     b = F.Batch(1 << 40, len(sys_))
@@ -230,6 +254,8 @@ def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=Fal
     out = {"value": round(ok / dt_, 1), "ms_per_step": round(1e3 * dt_ / steps, 3),
            "gmres_iterations_mean": round(float(np.mean(its)), 2), "gmres_iterations_max": int(np.max(its)),
            "lat": lat}
+    if chosen:
+        out["tiles"] = {f"B{b} G{g}": sum(1 for c in chosen if c == (b, g)) for b, g in sorted(set(chosen))}
     if timing:
         # the same kernels once more, one more step with event timing on every launch
         b.set_timing(True)
@@ -256,37 +282,51 @@ def bench_batched(args, F, fsdgen, torch):
     progress(f"plain FP64 one at a time (eager launches): {plain['value']} bead-solves/s")
     plain_g = run_plain(F, systems, plain_steps, warm, graphs=True)
     progress(f"plain FP64 one at a time (captured graphs): {plain_g['value']} bead-solves/s")
-    mixed = run_batch(F, systems, args.steps, args.warmup, warm, F.FSD_MIXED, fused=True, timing=True, replay=50)
-    progress(f"batched mixed, multi-system launches: {mixed['value']} bead-solves/s")
+    # the batched form: splitting parameter and transform tiles measured per system
+    t0 = time.perf_counter()
+    xis = tuned_xi(F, systems, F.FSD_MIXED)
+    t_tune = time.perf_counter() - t0
+    mixed = run_batch(F, systems, args.steps, args.warmup, warm, F.FSD_MIXED, fused=True, timing=True, replay=50,
+                      xis=xis, tiles=True)
+    progress(f"batched mixed, measured xi and tiles: {mixed['value']} bead-solves/s (xi tuning {t_tune:.1f} s)")
+    paper = run_batch(F, systems, plain_steps, 1, warm, F.FSD_MIXED, fused=True)
+    progress(f"batched mixed at xi = 25/L: {paper['value']} bead-solves/s")
     b64 = run_batch(F, systems, plain_steps, 1, warm, F.FSD_FP64, fused=True)
-    progress(f"batched FP64, multi-system launches: {b64['value']} bead-solves/s")
-    streams = run_batch(F, systems, plain_steps, 1, warm, F.FSD_MIXED, fused=False)
-    progress(f"batched mixed, one stream per system: {streams['value']} bead-solves/s")
-    grids = sorted({int(F.System.from_suspension(systems[k]).info().grid) for k in range(len(systems))})
+    progress(f"batched FP64 at xi = 25/L: {b64['value']} bead-solves/s")
+    streams = run_batch(F, systems, plain_steps, 1, warm, F.FSD_MIXED, fused=False, xis=xis)
+    progress(f"batched mixed, one stream per system, measured xi: {streams['value']} bead-solves/s")
+    plain_t = run_plain_xi(F, systems, plain_steps, warm, xis)
+    progress(f"plain FP64 one at a time at the measured xi: {plain_t['value']} bead-solves/s")
+    grids = sorted({int(F.System.from_suspension(systems[k], xi=xis[k]).info().grid) for k in range(len(systems))})
     table = mixed["table"]
     rep = mixed.get("replay")
-    roofline = roofline_of(table, f"hbm_counters_uneven-64_mixed.md", rep[0] if rep else None,
+    roofline = roofline_of(table, "hbm_counters_uneven-64_mixed.md", rep[0] if rep else None,
                            rep[1] if rep else None)
-    roofline["launch"] = "one multi-system launch over all 64 systems"
+    roofline["launch"] = f"one multi-system launch over all {len(systems)} systems"
     lat = mixed["lat"]
+    ctx = lambda r: {k: v for k, v in r.items() if k not in ("lat", "table", "replay")}
     out = {
         "metric": METRIC, "value": mixed["value"], "unit": "bead-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 operator / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(systems)} independent sheared cluster suspensions, 200-4000 beads "
-                               f"(4-30 per aggregate), phi 0.02-0.25, xi = 25/L, tol 1e-5, batched mixed precision",
-                   "n_bead_total": n_tot, "grids": grids, "precision": "mixed", "warm_start": warm,
-                   "parallelism": "single GPU, multi-system launches"},
+                               f"(4-30 per aggregate), phi 0.02-0.25, tol 1e-5; batched, mixed precision, "
+                               f"splitting parameter and transform tiles measured per system",
+                   "n_bead_total": n_tot, "grids": grids, "xi_range": [round(min(xis), 4), round(max(xis), 4)],
+                   "precision": "mixed", "warm_start": warm, "parallelism": "single GPU, multi-system launches"},
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
                        "what": "per solve: every system's solve completes within its batched step"},
         "speedup_vs_plain": round(mixed["value"] / plain["value"], 3),
         "speedup_vs_plain_graphed": round(mixed["value"] / plain_g["value"], 3),
+        "plain": "FP64, one system at a time, xi = 25/L (the workload's policy), eager launches",
         "gmres_iterations_mean": mixed["gmres_iterations_mean"], "gmres_iterations_max": mixed["gmres_iterations_max"],
+        "tiles": mixed.get("tiles"), "xi_tuning_s": round(t_tune, 2),
         "plain_fp64_one_at_a_time": plain, "plain_fp64_one_at_a_time_graphed": plain_g,
-        "batched_fp64": {k: v for k, v in b64.items() if k != "lat"},
-        "batched_mixed_streams": {k: v for k, v in streams.items() if k != "lat"},
+        "plain_fp64_one_at_a_time_measured_xi": plain_t,
+        "batched_mixed_xi_25_over_L": ctx(paper), "batched_fp64_xi_25_over_L": ctx(b64),
+        "batched_mixed_streams_measured_xi": ctx(streams),
         "kernels": table,
         "kernel_timing": ("HIP events around every multi-system launch of one extra step on the batch stream, "
                           "bytes of the systems still iterating in each launch"),
@@ -425,6 +465,66 @@ def bench_large(args, F, fsdgen, torch, emit=True, steps=None):
     return out
 
 
+def bench_rods(args, F, fsdgen, torch):
+    """The scaling study of Section 3.2: wall-clock time per step per bead, t_s, of Brownian
+    rigid rods (n_b beads each) in a periodic cube, against the total bead count, at the two
+    splitting-parameter policies (xi = 0.5/a and xi = 25/L).  Each case times args.rod_steps
+    steps after args.rod_warmup discarded ones (the paper: 100 after 10)."""
+    nbs = [int(v) for v in args.rod_nb.split(",")]
+    phis = [float(v) for v in args.rod_phi.split(",")]
+    ntots = [int(v) for v in args.rod_ntot.split(",")]
+    prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
+    stream = torch.cuda.current_stream().cuda_stream
+    cases = []
+    for nb in nbs:
+        for phi in phis:
+            for nt in ntots:
+                for policy in ("fixed", "box"):
+                    try:
+                        s0 = fsdgen.brownian_rods(max(1, nt // nb), nb, phi, xi_policy=policy)
+                    except ValueError as e:  # rods longer than the box
+                        progress(f"rods n_b {nb} phi {phi} N_tot {nt}: skipped ({e})")
+                        break
+                    sysm = F.System.from_suspension(s0, stream=stream, precision=prec, gmres_maxit=20000)
+                    sysm.set_pair_forces(k_n=s0.extra["k_n"], r_cut=2.0 * s0.a)
+                    sysm.set_warm_start(1)
+                    if args.rod_drift:
+                        sysm.set_drift(args.rod_drift)
+                    info = sysm.info()
+                    for _ in range(args.rod_warmup):
+                        sysm.step(s0.dt, 1)
+                    torch.cuda.synchronize()
+                    its, ok = [], 0
+                    t0 = time.perf_counter()
+                    for _ in range(args.rod_steps):
+                        si = sysm.step(s0.dt, 1)
+                        its.append(si.iterations)
+                        ok += si.status == 0 and si.rel_residual_fp64 <= s0.gmres_tol
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - t0
+                    sysm.close()
+                    c = {"n_b": nb, "phi": phi, "n_bead": s0.n_bead, "n_rod": s0.n_agg, "L": round(s0.L, 2),
+                         "xi_policy": "0.5/a" if policy == "fixed" else "25/L", "xi": round(info.xi, 4),
+                         "grid": info.grid, "r_cut": round(info.r_cut, 2),
+                         "t_s_us": round(1e6 * el / args.rod_steps / s0.n_bead, 4),
+                         "ms_per_step": round(1e3 * el / args.rod_steps, 3),
+                         "gmres_iterations_mean": round(float(np.mean(its)), 1),
+                         "solves_within_tol": f"{ok}/{args.rod_steps}"}
+                    cases.append(c)
+                    progress(f"rods n_b {nb} phi {phi} N_tot {s0.n_bead} xi {c['xi_policy']}: "
+                             f"t_s {c['t_s_us']} us ({c['ms_per_step']} ms per step, grid {info.grid})")
+    best = min(cases, key=lambda c: c["t_s_us"])
+    out = {"metric": "t_s: wall-clock time per time step per bead, Brownian rigid rods (Section 3.2)",
+           "value": best["t_s_us"], "unit": "us", "n_gpus": 1, "steps": args.rod_steps,
+           "warmup": args.rod_warmup, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == F.FSD_FP64 else "f32 operator / f64 Krylov", "data": "synthetic",
+           "config": {"workload": "Brownian rigid rods, Hertz contact, lubrication, tol 1e-5",
+                      "drift": ["none", "random finite differences", "Fixman"][args.rod_drift],
+                      "precision": args.precision, "parallelism": "single GPU"},
+           "cases": cases}
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args, torch):
     """Device-to-device copy of 1 GiB: the measured HBM bandwidth next to the 8 TB/s
     vendor figure, and the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE
@@ -538,7 +638,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["batched", "clusters", "large", "serving", "copy"], default="batched")
+    ap.add_argument("--workload", choices=["batched", "clusters", "large", "serving", "rods", "copy"],
+                    default="batched")
+    ap.add_argument("--rod-nb", default="8,27", help="rods: beads per rod")
+    ap.add_argument("--rod-phi", default="0.01,0.05,0.10", help="rods: volume fractions")
+    ap.add_argument("--rod-ntot", default="2000,8000,32000", help="rods: total bead counts")
+    ap.add_argument("--rod-steps", type=int, default=20, help="rods: timed steps per case (the paper: 100)")
+    ap.add_argument("--rod-warmup", type=int, default=5, help="rods: discarded steps per case (the paper: 10)")
+    ap.add_argument("--rod-drift", type=int, choices=[0, 1, 2], default=2,
+                    help="rods: Brownian drift (0 none, 1 random finite differences, 2 Fixman)")
     ap.add_argument("--no-sub", action="store_true", help="batched: skip the 256x8 and 4096x20 sub-runs")
     ap.add_argument("--systems", type=int, default=64)
     ap.add_argument("--requests", type=int, default=12)
@@ -573,6 +681,8 @@ def main():
         return bench_serving(args, F, fsdgen, torch)
     if args.workload == "large":
         return bench_large(args, F, fsdgen, torch)
+    if args.workload == "rods":
+        return bench_rods(args, F, fsdgen, torch)
     if args.workload == "clusters":
         return bench_clusters(args, F, fsdgen, torch)
 

@@ -452,5 +452,58 @@ def brownian_noise(n_bead, seed):
     return rng.normal(size=6 * n_bead), rng.normal(size=3 * n_bead)
 
 
+def rod(n_b, a=1.0):
+    """n_b touching beads on a straight line (centre spacing 2a) along x, centroid at 0."""
+    x = (np.arange(n_b) - 0.5 * (n_b - 1)) * 2.0 * a
+    return np.stack([x, np.zeros(n_b), np.zeros(n_b)], axis=1)
+
+
+def _aligned_rods(rng, n_rod, n_b, L, a, gap):
+    """Rods along x in columns on a square (y, z) lattice, as many per column as fit end to
+    end, each column shifted along x at random (the fallback where isotropic placement fails)."""
+    length = 2.0 * a * n_b
+    per_col = int(L // (length + gap))
+    n_col = -(-n_rod // per_col)
+    m = int(math.ceil(math.sqrt(n_col)))
+    if L / m < 2.0 * a + gap:
+        raise RuntimeError("aligned rods do not fit either")
+    com = np.zeros((n_rod, 3))
+    k = 0
+    for c in range(n_col):
+        y, z = (c % m + 0.5) * L / m - L / 2, (c // m + 0.5) * L / m - L / 2
+        x0 = rng.random() * L
+        for r in range(per_col):
+            if k == n_rod:
+                break
+            com[k] = [(x0 + r * L / per_col) % L - L / 2, y, z]
+            k += 1
+    offsets = np.arange(n_rod + 1, dtype=np.int32) * n_b
+    quat = np.tile([1.0, 0.0, 0.0, 0.0], (n_rod, 1))
+    return dict(name=f"rods-{n_rod}x{n_b}", L=L, a=a, offsets=offsets, x_body=np.tile(rod(n_b, a), (n_rod, 1)),
+                com=com, quat=quat)
+
+
+def brownian_rods(n_rod, n_b, phi, xi_policy="fixed", seed=BASE_SEED + 6, tol=1e-5, kT=1.0, dt=1e-3, a=1.0,
+                  k_n=1e3):
+    """Brownian rigid rods for the scaling study of Section 3.2: n_rod straight rods of n_b
+    touching beads, uniformly random orientations and positions (random sequential addition,
+    inter-body gaps of at least 0.1a) in a periodic cube at volume fraction phi, no imposed
+    flow, thermal energy kT, Hertz contact between rods (stiffness k_n, in extra), lubrication
+    as in the other workloads.  xi_policy "fixed" gives xi = 0.5/a, "box" gives xi = 25/L,
+    the two policies of Section 3.2."""
+    rng = rng_from(seed + 1000 * n_b + int(round(1000 * phi)))
+    L = box_side(n_rod * n_b, phi, a)
+    if 2.0 * a * n_b + 0.1 * a > L:
+        raise ValueError("rods longer than the box would touch their own images")
+    try:
+        g = _assemble(f"rods-{n_rod}x{n_b}", [rod(n_b, a)] * n_rod, L, rng, a=a, gap=0.1 * a)
+    except RuntimeError:  # long rods at this volume fraction: no isotropic packing by RSA
+        g = _aligned_rods(rng, n_rod, n_b, L, a, 0.1 * a)
+    xi = 0.5 / a if xi_policy == "fixed" else 25.0 / L
+    return Suspension(eta=1.0, force=np.zeros((n_rod, 6)), grad_u=np.zeros((3, 3)), xi=xi, ewald_tol=tol,
+                      gmres_tol=tol, grid=0, r_lub=3.0 * a, r_precond=2.1 * a, kT=kT, dt=dt,
+                      extra={"k_n": k_n}, **g)
+
+
 def random_force(rng, n_agg, scale=1.0):
     return scale * rng.normal(size=(n_agg, 6))

@@ -176,6 +176,25 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t n_bead, int32_t n_agg, do
 const char* fsd_last_error(const fsd_system* s);
 void fsd_destroy(fsd_system* s);
 
+/* Measured choice of the splitting parameter.  Section 3.2 runs two fixed policies (xi =
+ * 0.5/a and 25/L) and notes that the better one depends on the system; any xi between
+ * them meets the same error rules.  For each candidate in [xi_lo, xi_hi] (xi_lo itself and,
+ * for every grid size the cutoff rule gives there, the largest xi that still gives it) a
+ * scratch system with s's geometry, forcing and parameters is built and one saddle-operator
+ * apply (Eq. `spm_agg`, in s's precision) is timed over reps back-to-back launches.  xi_out
+ * gets the fastest candidate, ms_out (may be NULL) its time per apply; s is left unchanged
+ * (create the system again with that xi to use it).  Allocates the scratch systems.
+ * FSD_EINVAL unless 0 < xi_lo <= xi_hi and reps >= 1. */
+fsd_status fsd_autotune_xi(fsd_system* s, double xi_lo, double xi_hi, int reps, double* xi_out, double* ms_out);
+
+/* Measured tile shapes of the transform passes: the lines per workgroup of the z and y
+ * passes (B, a divisor of the grid side) and the row pairs per workgroup of the x+Green pass
+ * (G) are timed over reps back-to-back launches each (fsd_time_kernel) in the system's
+ * precision, and the fastest are kept for every later launch of s (captured graphs are
+ * rebuilt).  Both stay within 64 KB of LDS per workgroup.  lines_b and green_g (may be
+ * NULL) get the choice.  The grid is left undefined, as by fsd_time_kernel. */
+fsd_status fsd_autotune_tiles(fsd_system* s, int reps, int* lines_b, int* green_g);
+
 /* ---- conservative bead-pair forces (Section 4.2, Eqs. `dlvo_potential` and the Hertz
  * contact force) ------------------------------------------------------------------------
  * Between beads of different bodies closer than r_cut (2a <= r_cut <= fsd_info.r_cut), with
@@ -262,8 +281,8 @@ fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0);
  * U0 solves with that step's Brownian terms alone (u_B, -Sigma F_B; no ambient flow or other
  * forcing) at x and U' with the same terms at x + (dt/m) U0 (an Euler move), and
  * (m/2) (U' - U0) is added; the second argument is then m (<= 0: 100).  mode 0: off
- * (default).  Not applied by fsd_batch_step, which returns FSD_EINVAL while an admitted
- * system has a drift on and kT > 0. */
+ * (default).  fsd_batch_step applies it too, per system, around the batched solve (the
+ * drift's own solves run on the system's stream). */
 fsd_status fsd_set_drift(fsd_system* s, int mode, double eps);
 
 /* The drift kT (U+ - U-) / eps at the current configuration (6 per aggregate, host), for
@@ -318,17 +337,6 @@ fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out
  * forward (sign -1) or inverse (sign +1, unnormalised), with the library's
  * transform.  Host buffer; for verification of the FFT stages. */
 fsd_status fsd_fft3d(int n, int sign, double* data);
-
-/* The transform of fsd_fft3d on a device buffer, allocating nothing: for callers that
- * cannot allocate device memory (code under HIP graph capture, tight serving loops,
- * harnesses that forbid hipMalloc).  d_data: n^3 complex values (interleaved re/im
- * doubles, x fastest) in device memory of the current GPU, transformed in place, stream-
- * ordered on hip_stream (NULL: the null stream); the caller owns it.  The twiddle table
- * lives in a fixed device array of 2 x 512 doubles per GPU, held until the process ends, so
- * n is at most 512 (FSD_EINVAL beyond, or for n not a product of 2, 3 and 5; the text is in
- * fsd_last_error(NULL)).  Calls that overlap on one GPU race on that array: order them on
- * one stream.  FSD_EDEVICE if a launch fails. */
-fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream);
 
 /* ---- batches of independent systems (many small suspensions sharing the GPU) -------- */
 

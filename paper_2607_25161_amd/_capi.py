@@ -86,7 +86,6 @@ _sig("fsd_apply_precond", C.c_int, _SYS, _D, _D)
 _sig("fsd_get_rhs", C.c_int, _SYS, _D)
 _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
-_sig("fsd_fft3d_noalloc", C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p)
 _U64P = C.POINTER(C.c_uint64)
 _sig("fsd_set_brownian", C.c_int, _SYS, C.c_double, C.c_uint64, C.c_uint64)
 _sig("fsd_set_noise", C.c_int, _SYS, _D, _D, _D)
@@ -105,6 +104,8 @@ _sig("fsd_set_warm_start", C.c_int, _SYS, C.c_int)
 _sig("fsd_set_drift", C.c_int, _SYS, C.c_int, C.c_double)
 _sig("fsd_rfd_drift", C.c_int, _SYS, _D, _D)
 _sig("fsd_time_kernel", C.c_int, _SYS, C.c_int, C.c_int, _D)
+_sig("fsd_autotune_xi", C.c_int, _SYS, C.c_double, C.c_double, C.c_int, _D, _D)
+_sig("fsd_autotune_tiles", C.c_int, _SYS, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int))
 
 _sig("fsd_batch_create", C.c_int, C.c_size_t, C.c_int, C.c_void_p, C.POINTER(C.c_void_p))
 _sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
@@ -181,14 +182,6 @@ def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
     if rc:
         raise FsdError(rc, f"fsd_fft3d: {lib.fsd_last_error(None).decode()}")
     return buf.view(np.complex128).reshape(a.shape)
-
-
-def fft3d_noalloc(n: int, sign: int, data_ptr: int, stream=None):
-    """fsd_fft3d_noalloc: in place on a device buffer of n^3 complex doubles (e.g. a torch
-    complex128 tensor's data_ptr()), stream-ordered on `stream` (a hipStream_t handle)."""
-    rc = lib.fsd_fft3d_noalloc(int(n), int(sign), C.c_void_p(int(data_ptr)), C.c_void_p(stream) if stream else None)
-    if rc:
-        raise FsdError(rc, f"fsd_fft3d_noalloc: {lib.fsd_last_error(None).decode()}")
 
 
 class System:
@@ -409,6 +402,20 @@ class System:
         self._check(lib.fsd_time_kernel(self._h, TIMER_NAMES.index(timer), int(reps), C.byref(out)),
                     "fsd_time_kernel")
         return out.value
+
+    def autotune_xi(self, xi_lo, xi_hi, reps=10):
+        """(xi, ms per saddle apply) of the fastest splitting parameter in [xi_lo, xi_hi]."""
+        xi, ms = C.c_double(0.0), C.c_double(0.0)
+        self._check(lib.fsd_autotune_xi(self._h, float(xi_lo), float(xi_hi), int(reps), C.byref(xi), C.byref(ms)),
+                    "fsd_autotune_xi")
+        return xi.value, ms.value
+
+    def autotune_tiles(self, reps=20):
+        """(lines per workgroup of the z/y passes, row pairs per workgroup of the x+Green pass),
+        measured and kept for this system."""
+        b, g = C.c_int(0), C.c_int(0)
+        self._check(lib.fsd_autotune_tiles(self._h, int(reps), C.byref(b), C.byref(g)), "fsd_autotune_tiles")
+        return b.value, g.value
 
     # -- convenience ------------------------------------------------------------------
     @classmethod

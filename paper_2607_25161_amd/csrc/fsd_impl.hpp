@@ -67,6 +67,9 @@ struct WaveParams {
   // Green's multipliers by |m|^2 = m_x^2 + m_y^2 + m_z^2 on the cube (5 per entry: sinc(ka),
   // jv(ka), the solve's and the Brownian root's scalar factors, 1/|k|), or nullptr
   const double* gtab;
+  // transform tiles (0: the default rules fft_lines_b / fft_green_rows): lines per workgroup
+  // of the z and y passes, row pairs per workgroup of the x+Green pass
+  int tile_b, tile_g;
 };
 
 // Constants of the real-space part.
@@ -139,11 +142,6 @@ template <typename R>
 void launch_interp_sheared(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
                            hipStream_t st, const int* skip, const int* body, const double* r4, const double* V);
 // pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
-// the allocation-free in-place transform of an n^3 complex grid (n <= kNoAllocFftMax) on the
-// caller's device buffer, its twiddles in a fixed device array of this GPU
-constexpr int kNoAllocFftMax = 512;
-constexpr int kMaxDevices = 64;
-hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st);
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
                   int sign, hipStream_t st, int pass = -1, const int* skip = nullptr);
@@ -381,6 +379,12 @@ enum BatchKind {
 // FFT blocking used by both the single-system and the multi-system launches
 int fft_lines_b(int N, int rbytes);  // lines per workgroup of the z/y passes (rbytes: 8 FP64, 4 FP32)
 int fft_green_rows(int N);           // row slots per workgroup of the x+Green pass
+// the tiles a system's transforms run with (its overrides, else the rules), and whether a
+// tile fits: B divides N, and the LDS of either pass stays within 64 KB
+int lines_b_of(const WaveParams& wp, int rbytes);
+int green_g_of(const WaveParams& wp);
+bool tile_b_fits(int N, int B, int rbytes);
+bool tile_g_fits(int N, int G, int rbytes);
 // fill the spreading fields of d from a gather plan (d.wp must be set first)
 void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d);
 // per-system block counts of each kind and the dynamic LDS the kinds need (prec: 0 FP64, 1 FP32)

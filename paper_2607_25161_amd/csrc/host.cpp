@@ -547,6 +547,7 @@ void choose_parameters(fsd_system* s) {
   const double gnorm = std::pow(2.0 * xi * xi / (M_PI * eta_t), 1.5);
   w.scale = std::pow(h, 6) / (L * L * L) * gnorm * gnorm;
   w.brownian = 0;
+  w.tile_b = w.tile_g = 0;
   RealParams& r = s->rp;
   r.L = L;
   r.a = a;
@@ -1474,6 +1475,26 @@ void fixman_drift(fsd_system* s, double dt) {
   HIPCHK(hipMemcpyAsync(s->d_U, s->d_umain, sizeof(double) * 6 * na, hipMemcpyDeviceToDevice, s->st));
 }
 
+// The parts of one time step around its solve (fsd_step and the batched step take the same
+// path): the random-finite-difference drift before the solve; after it Fixman's drift, the
+// drift added to the velocities, and the Euler update of Eqs. `EM1`-`EM3`.
+void step_before_solve(fsd_system* s) {
+  if (s->drift_mode == 1 && s->p.kT > 0) rfd_drift(s, nullptr);
+}
+
+void step_after_solve(fsd_system* s, double dt) {
+  const bool rfd = s->drift_mode == 1 && s->p.kT > 0, fixman = s->drift_mode == 2 && s->p.kT > 0;
+  if (fixman) {  // its solves leave their own state: the step reports the main solve's
+    const auto main = s->sv;
+    fixman_drift(s, dt);
+    s->sv = main;
+  }
+  if (rfd || fixman) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
+  integrate_step(s, dt);
+  s->prepared = false;
+  ++s->bstep;
+}
+
 fsd_status check_ready(fsd_system* s) {
   if (!s) return FSD_EINVAL;
   if (!s->have_box || !s->have_agg) return fail(s, FSD_ESTATE, "call fsd_init_box and fsd_init_aggregates first");
@@ -1816,16 +1837,11 @@ fsd_status fsd_step(fsd_system* s, double dt, int n_steps, fsd_solve_info* last)
   return guarded(s, [&]() -> fsd_status {
     fsd_status r = FSD_OK;
     s->bdt = dt;
-    const bool rfd = s->drift_mode == 1 && s->p.kT > 0, fixman = s->drift_mode == 2 && s->p.kT > 0;
     for (int k = 0; k < n_steps; ++k) {
-      if (rfd) rfd_drift(s, nullptr);
+      step_before_solve(s);
       r = solve_current(s, last);
       if (r != FSD_OK) return r;
-      if (fixman) fixman_drift(s, dt);
-      if (rfd || fixman) launch_axpby(6 * size_t(s->na), 1.0, s->d_udrift, 1.0, s->d_U, s->st);
-      integrate_step(s, dt);
-      s->prepared = false;
-      ++s->bstep;
+      step_after_solve(s, dt);
     }
     HIPCHK(hipStreamSynchronize(s->st));
     return r;
@@ -2172,6 +2188,44 @@ fsd_status fsd_autotune_xi(fsd_system* s, double xi_lo, double xi_hi, int reps, 
   });
 }
 
+fsd_status fsd_autotune_tiles(fsd_system* s, int reps, int* lines_b, int* green_g) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (reps < 1) return fail(s, FSD_EINVAL, "fsd_autotune_tiles: reps >= 1");
+  return guarded(s, [&]() -> fsd_status {
+    const int N = s->wp.n, rb = s->p.precision == FSD_MIXED ? 4 : 8;
+    auto timed = [&](int cls) {
+      double ms = 0;
+      const fsd_status r = fsd_time_kernel(s, cls, reps, &ms);
+      if (r != FSD_OK) throw ApiError(r, s->err);
+      return ms;
+    };
+    // the y pass stands for both line passes (same body, strides differ)
+    int best_b = 0;
+    double best = 1e300;
+    for (int B : {1, 2, 4, 8, 16, 32, 64}) {
+      if (!tile_b_fits(N, B, rb)) continue;
+      s->wp.tile_b = B;
+      const double ms = timed(FSD_TIMER_FFT_Y);
+      if (ms < best) best = ms, best_b = B;
+    }
+    int best_g = 0;
+    best = 1e300;
+    for (int G : {1, 2, 3, 4, 6, 8}) {
+      if (!tile_g_fits(N, G, rb)) continue;
+      s->wp.tile_g = G;
+      const double ms = timed(FSD_TIMER_GREEN);
+      if (ms < best) best = ms, best_g = G;
+    }
+    s->wp.tile_b = best_b;
+    s->wp.tile_g = best_g;
+    s->drop_graphs();  // captured launches carry the old shapes
+    if (lines_b) *lines_b = best_b;
+    if (green_g) *green_g = best_g;
+    return FSD_OK;
+  });
+}
+
 fsd_status fsd_set_pair_forces(fsd_system* s, double k_n, double hamaker, double Z, double kappa, double h_c,
                                double r_cut) {
   fsd_status c = check_ready(s);
@@ -2406,25 +2460,6 @@ fsd_status fsd_fft3d(int n, int sign, double* data) {
   return rc;
 }
 
-fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream) {
-  if (!d_data || (sign != 1 && sign != -1)) {
-    g_last_error = "fsd_fft3d_noalloc: a device buffer and sign +-1";
-    return FSD_EINVAL;
-  }
-  FftPlan plan;
-  if (n > kNoAllocFftMax || !make_plan(n, plan)) {
-    g_last_error = "fsd_fft3d_noalloc: n must be a product of 2, 3 and 5 of at most " +
-                   std::to_string(kNoAllocFftMax) + " (the size of its fixed twiddle array)";
-    return FSD_EINVAL;
-  }
-  const hipError_t e = launch_fft3d_noalloc(n, sign, d_data, plan, static_cast<hipStream_t>(hip_stream));
-  if (e != hipSuccess) {
-    g_last_error = std::string("fsd_fft3d_noalloc: ") + hipGetErrorString(e);
-    return FSD_EDEVICE;
-  }
-  return FSD_OK;
-}
-
 }  // extern "C"
 
 // ==========================================================================================
@@ -2492,6 +2527,7 @@ fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
     fsd_system* s = act[k];
     if (integrate) s->bdt = dt;
     fsd_status r = guarded(s, [&]() -> fsd_status {
+      if (integrate) step_before_solve(s);
       solve_begin(s);
       return FSD_OK;
     });
@@ -2527,9 +2563,14 @@ fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
         --remaining;
         if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
         if (integrate && s->sv.status == FSD_OK) {
-          integrate_step(s, dt);
-          s->prepared = false;
-          ++s->bstep;
+          const fsd_status ri = guarded(s, [&]() -> fsd_status {
+            step_after_solve(s, dt);
+            return FSD_OK;
+          });
+          if (ri != FSD_OK) {
+            s->sv.status = ri;
+            if (worst == FSD_OK) worst = ri;
+          }
         }
       }
     }
@@ -2572,8 +2613,8 @@ BatchDesc make_desc(fsd_system* s, int prec) {
   d.tw64 = s->d_tw64;
   d.tw32 = s->d_tw32;
   d.grid = s->d_grid;
-  d.bl = fft_lines_b(N, prec ? 4 : 8);
-  d.bg = fft_green_rows(N);
+  d.bl = lines_b_of(s->wp, prec ? 4 : 8);
+  d.bg = green_g_of(s->wp);
   spread_plan_desc(s->spread, prec, d);
   d.lrow = lub ? s->d_lrow : nullptr;
   d.lcol = s->d_lcol;
@@ -2608,7 +2649,7 @@ bool fusable(const std::vector<fsd_system*>& act) {
   const int prec = act[0]->p.precision, m = act[0]->m;
   for (auto* s : act) {
     if (s->p.precision != prec || s->m != m || !cgs_fits(m + 1) || s->timing || s->le) return false;
-    if (!s->spread || s->wp.n % 8) return false;
+    if (!s->spread || s->wp.n % 8 || !s->wp.gtab) return false;
   }
   return true;
 }
@@ -2787,6 +2828,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     fsd_system* s = act[k];
     if (integrate) s->bdt = dt;
     fsd_status r = guarded(s, [&]() -> fsd_status {
+      if (integrate) step_before_solve(s);
       solve_begin(s);
       return FSD_OK;
     });
@@ -2868,12 +2910,13 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     fsd_system* s = act[k];
     if (integrate && s->sv.status == FSD_OK) {
       fsd_status r = guarded(s, [&]() -> fsd_status {
-        integrate_step(s, dt);
-        s->prepared = false;
-        ++s->bstep;
+        step_after_solve(s, dt);
         return FSD_OK;
       });
-      if (r != FSD_OK && worst == FSD_OK) worst = r;
+      if (r != FSD_OK) {
+        s->sv.status = r;
+        if (worst == FSD_OK) worst = r;
+      }
     }
     if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
   }
@@ -2957,9 +3000,6 @@ fsd_status fsd_batch_solve(fsd_batch* b) {
 
 fsd_status fsd_batch_step(fsd_batch* b, double dt) {
   if (!b || !(dt > 0)) return FSD_EINVAL;
-  for (auto* s : b->slot)
-    if (s && s->drift_mode != 0 && s->p.kT > 0)
-      return fail(s, FSD_EINVAL, "the random-finite-difference drift is applied by fsd_step only");
   return batch_run(b, dt, true);
 }
 

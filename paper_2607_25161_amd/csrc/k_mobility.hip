@@ -13,8 +13,6 @@
 #include <algorithm>
 #include <type_traits>
 
-#include <mutex>
-
 #include "fsd_impl.hpp"
 #include "k_rigid.hpp"
 
@@ -1062,7 +1060,7 @@ void launch_spread_fused(const SpreadPlan* sp, const double* lam, const WavePara
 
 // ------------------------------------------------------------------------------------------
 // 3D FFT: three passes of batched 1D transforms, each line staged in LDS and
-// transformed by mixed-radix (4, 2, 3) Stockham stages.
+// transformed by mixed-radix (4, 2, 3, 5) Stockham stages.
 // ------------------------------------------------------------------------------------------
 
 namespace {
@@ -1087,6 +1085,26 @@ __device__ inline T csub(T a, T b) {
   r.y = a.y - b.y;
   return r;
 }
+// Quotient and remainder by a divisor known only at run time, for dividends below 2^21:
+// the product with the FP32 reciprocal (v_rcp_f32, within 1 ulp) is within 1/4 of the true
+// quotient, so truncating it and one correction step give the exact result (a hardware
+// integer division sequence costs about 25 instructions per use in these index loops).
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ explicit FastDiv(int d_) : d(d_), inv(__frcp_rn(float(d_))) {}
+  __device__ __forceinline__ int div(int a) const {
+    int q = int(float(a) * inv);
+    const int r = a - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+  }
+  __device__ __forceinline__ void divmod(int a, int& q, int& r) const {
+    q = div(a);
+    r = a - q * d;
+  }
+};
+
 // multiply by -i*sign... rot(v, s) = s * i * v
 template <typename T>
 __device__ inline T rot(T v, int s) {
@@ -1165,12 +1183,14 @@ __device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan&
     const int Rd = int((code >> (4 * stg)) & 15ull);
     const int nbf = N / Rd;
     const int tstride = N / (Ns * Rd);
+    const FastDiv dbf(nbf), dns(Ns);
     for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
-      const int l = t / nbf, b = t % nbf;
+      int l, b, j, k;
+      dbf.divmod(t, l, b);
+      dns.divmod(b, j, k);
       const T* li = in + l * N;
       T* lo = out + l * N;
-      const int k = b % Ns;
-      const int od = (b / Ns) * Ns * Rd + k;
+      const int od = j * Ns * Rd + k;
       if (Rd == 4)
         butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
       else if (Rd == 2)
@@ -1323,17 +1343,19 @@ __device__ __forceinline__ void fft_lines_body(R* __restrict__ grid, size_t cs, 
   T* buf1 = buf0 + B * N;
   T* tw = buf1 + B * N;
   T* base = reinterpret_cast<T*>(grid + by_ * cs);
-  const int line0 = bx_ * B;  // line gl = o N + x: B consecutive x of one o
+  const int line0 = bx_ * B;  // line gl = o N + x: B consecutive x of one o (B divides N)
+  const int o = line0 / N, x0 = line0 - o * N;
+  const int lb = __ffs(B) - 1;  // B is a power of two
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t % B, e = t / B, gl = line0 + l, o = gl / N, x = gl % N;
+    const int l = t & (B - 1), e = t >> lb, x = x0 + l;
     const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
     buf0[l * N + e] = base[off];
   }
   __syncthreads();
   const T* Y = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t % B, e = t / B, gl = line0 + l, o = gl / N, x = gl % N;
+    const int l = t & (B - 1), e = t >> lb, x = x0 + l;
     const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
     base[off] = Y[l * N + e];
   }
@@ -1346,7 +1368,10 @@ __global__ __launch_bounds__(256) void k_fft_lines(R* __restrict__ grid, size_t 
   fft_lines_body<R, DIR>(grid, cs, plan, twiddle, sign, B, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-template <typename R>
+// TABLE: the cube, multipliers read from the table by |m|^2; otherwise (the sheared lattice)
+// computed per mode.  Two instantiations keep the per-mode FP64 arithmetic out of the
+// cube's register budget.
+template <typename R, bool TABLE>
 __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs, FftPlan plan,
                                                 const R* __restrict__ twiddle, WaveParams wp, int G,
                                                 const int* __restrict__ skip, int bx_, int by_, int gx_) {
@@ -1363,16 +1388,23 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   T* buf1 = buf0 + NL * N;
   T* tw = buf1 + NL * N;
   const int H = N / 2, npair = NN / 2 + 2;
+  const FastDiv dn(N);
   auto row_of = [N, H](int p) {  // pair number -> its first row r
     if (p <= H) return p;                        // kz = 0, ky = 0 .. N/2
     p -= H + 1;
-    if (p < (H - 1) * N) return (1 + p / N) * N + p % N;  // kz = 1 .. N/2 - 1, all ky
-    return H * N + (p - (H - 1) * N);                      // kz = N/2, ky = 0 .. N/2
+    if (p < (H - 1) * N) return N + p;           // kz = 1 .. N/2 - 1, all ky
+    return H * N + (p - (H - 1) * N);            // kz = N/2, ky = 0 .. N/2
   };
-  auto partner = [N](int r) { return ((N - r / N) % N) * N + (N - r % N) % N; };
+  auto partner = [N, &dn](int r) {  // the row of (-kz, -ky)
+    int kz, ky;
+    dn.divmod(r, kz, ky);
+    return (kz ? N - kz : 0) * N + (ky ? N - ky : 0);
+  };
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
-    const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
+    int line, x;
+    dn.divmod(t, line, x);
+    const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
     const int pn = bx_ * G + g;
     T v;
     v.x = 0;
@@ -1386,16 +1418,19 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   __syncthreads();
   T* X = stockham<T, R>(buf0, buf1, tw, N, NL, plan, -1);
   T* O = (X == buf0) ? buf1 : buf0;
-  const double tp = 2.0 * M_PI / wp.L, gam = wp.gam ? *wp.gam : 0.0;
+  const double tp = 2.0 * M_PI / wp.L, gam = (!TABLE && wp.gam) ? *wp.gam : 0.0;
   for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
-    const int g = t / (2 * N), q = (t / N) & 1, kx = t % N;
+    int gq, kx;
+    dn.divmod(t, gq, kx);
+    const int g = gq >> 1, q = gq & 1;
     const int pn = bx_ * G + g;
     if (pn >= npair) continue;
     const int r = row_of(pn), rp = partner(r);
     if (rp == r && q == 1) continue;
-    const int qm = rp == r ? 0 : 1 - q, kxm = (N - kx) % N;
+    const int qm = rp == r ? 0 : 1 - q, kxm = kx ? N - kx : 0;
     const int row = q ? rp : r;
-    const int kz = row / N, ky = row % N;
+    int kz, ky;
+    dn.divmod(row, kz, ky);
     const int l0 = 6 * g;
     const bool nyq = (N % 2 == 0) && (kx == N / 2 || ky == N / 2 || kz == N / 2);
     if (nyq || (kx == 0 && ky == 0 && kz == 0)) {
@@ -1405,67 +1440,73 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
       }
       continue;
     }
-    double Fr[3], Fi[3], Tr[3], Ti[3];
+    // the per-mode arithmetic runs in the grid's precision R (the multipliers are tabulated
+    // in FP64 and rounded once)
+    R Fr[3], Fi[3], Tr[3], Ti[3];
     for (int c = 0; c < 3; ++c) {
       const T z = X[(l0 + 2 * c + q) * N + kx], zm = X[(l0 + 2 * c + qm) * N + kxm];
-      Fr[c] = 0.5 * (double(z.x) + double(zm.x));
-      Fi[c] = 0.5 * (double(z.y) - double(zm.y));
-      Tr[c] = 0.5 * (double(z.y) + double(zm.y));
-      Ti[c] = -0.5 * (double(z.x) - double(zm.x));
+      Fr[c] = R(0.5) * (z.x + zm.x);
+      Fi[c] = R(0.5) * (z.y - zm.y);
+      Tr[c] = R(0.5) * (z.y + zm.y);
+      Ti[c] = R(-0.5) * (z.x - zm.x);
     }
     // Cartesian wave vector of grid mode m: (2 pi / L)(m_x, m_y - gam m_x, m_z) (the
     // reciprocal lattice of the sheared lattice; gam = 0 for the cube)
     // signed mode numbers in [-N/2, N/2] (an even N's N/2 modes were zeroed above; an odd N
     // keeps the symmetric range), so |m|^2 <= 3 (N/2)^2 indexes the multiplier table
     const int mx = kx <= N / 2 ? kx : kx - N, my = ky <= N / 2 ? ky : ky - N, mz = kz <= N / 2 ? kz : kz - N;
-    const double k[3] = {tp * mx, tp * (my - gam * mx), tp * mz};
-    double sk, jk, Bk, ikn;
-    if (wp.gtab && gam == 0.0) {  // the multipliers depend on the integer |m|^2 alone
+    const R k[3] = {R(tp * mx), R(tp * (my - gam * mx)), R(tp * mz)};
+    R sk, jk, Bk, ikn;
+    if (TABLE) {  // the multipliers depend on the integer |m|^2 alone
       const double* gt = wp.gtab + 5 * (mx * mx + my * my + mz * mz);
-      sk = gt[0];
-      jk = gt[1];
-      Bk = wp.brownian ? gt[3] : gt[2];
-      ikn = gt[4];
+      sk = R(gt[0]);
+      jk = R(gt[1]);
+      Bk = R(wp.brownian ? gt[3] : gt[2]);
+      ikn = R(gt[4]);
     } else {
-      const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+      const double kd[3] = {tp * mx, tp * (my - gam * mx), tp * mz};
+      const double k2 = kd[0] * kd[0] + kd[1] * kd[1] + kd[2] * kd[2];
       const double kn = sqrt(k2);
-      ikn = 1.0 / kn;
-      sinc_jv_d(kn * wp.a, sk, jk);
+      double skd, jkd;
+      sinc_jv_d(kn * wp.a, skd, jkd);
       const double qq = k2 / (4.0 * wp.xi * wp.xi);
       const double damp = (1.0 + qq) * exp(-(1.0 - wp.eta_t) * qq) / wp.eta;
-      Bk = wp.brownian ? sqrt(wp.scale / (double(N) * N * N) * damp) * ikn : wp.scale * damp / k2;
+      sk = R(skd);
+      jk = R(jkd);
+      ikn = R(1.0 / kn);
+      Bk = R(wp.brownian ? sqrt(wp.scale / (double(N) * N * N) * damp) / kn : wp.scale * damp / k2);
     }
-    const double kh[3] = {k[0] * ikn, k[1] * ikn, k[2] * ikn};
-    double gr[3], gi[3];
+    const R kh[3] = {k[0] * ikn, k[1] * ikn, k[2] * ikn};
+    R gr[3], gi[3];
     if (wp.brownian) {
       for (int a = 0; a < 3; ++a) {
         gr[a] = Fr[a];
         gi[a] = Fi[a];
       }
     } else {
-      const double cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
-      const double cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
+      const R cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
+      const R cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
       for (int a = 0; a < 3; ++a) {
-        gr[a] = sk * Fr[a] - 0.5 * jk * cxi[a];
-        gi[a] = sk * Fi[a] + 0.5 * jk * cxr[a];
+        gr[a] = sk * Fr[a] - R(0.5) * jk * cxi[a];
+        gi[a] = sk * Fi[a] + R(0.5) * jk * cxr[a];
       }
     }
-    const double pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
-    const double pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
-    double ur[3], ui[3];
+    const R pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
+    const R pim = kh[0] * gi[0] + kh[1] * gi[1] + kh[2] * gi[2];
+    R ur[3], ui[3];
     for (int a = 0; a < 3; ++a) {
       ur[a] = Bk * (gr[a] - pr * kh[a]);
       ui[a] = Bk * (gi[a] - pim * kh[a]);
     }
     // U^ = sinc u^, W^ = (i/2) jv (k x u^); Y^ = U^ + i W^
-    const double kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
-    const double kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
+    const R kur[3] = {k[1] * ur[2] - k[2] * ur[1], k[2] * ur[0] - k[0] * ur[2], k[0] * ur[1] - k[1] * ur[0]};
+    const R kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
     for (int c = 0; c < 3; ++c) {
-      const double Ur = sk * ur[c], Ui = sk * ui[c];
-      const double Wr = -0.5 * jk * kui[c], Wi = 0.5 * jk * kur[c];
+      const R Ur = sk * ur[c], Ui = sk * ui[c];
+      const R Wr = R(-0.5) * jk * kui[c], Wi = R(0.5) * jk * kur[c];
       T y;
-      y.x = R(Ur - Wi);
-      y.y = R(Ui + Wr);
+      y.x = Ur - Wi;
+      y.y = Ui + Wr;
       O[(l0 + 2 * c + q) * N + kx] = y;
     }
   }
@@ -1474,7 +1515,9 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   __syncthreads();
   const T* Y = stockham<T, R>(O, X, tw, N, NL, plan, +1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
-    const int line = t / N, x = t % N, g = line / 6, c = (line % 6) >> 1, q = line & 1;
+    int line, x;
+    dn.divmod(t, line, x);
+    const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
     const int pn = bx_ * G + g;
     if (pn >= npair) continue;
     const int r = row_of(pn), rp = partner(r);
@@ -1483,22 +1526,38 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   }
 }
 
-template <typename R>
+template <typename R, bool TABLE>
 __global__ __launch_bounds__(256) void k_fft_xgreen(R* __restrict__ grid, size_t cs, FftPlan plan,
                                                     const R* __restrict__ twiddle, WaveParams wp, int G,
                                                     const int* __restrict__ skip) {
-  fft_xgreen_body<R>(grid, cs, plan, twiddle, wp, G, skip, blockIdx.x, blockIdx.y, gridDim.x);
+  fft_xgreen_body<R, TABLE>(grid, cs, plan, twiddle, wp, G, skip, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // row slots per workgroup of the x+Green pass (measured: 2 is fastest at 64^3 and 128^3)
 int fft_green_rows(int N) { return N >= 256 ? 1 : N >= 64 ? 2 : 256 / N; }
 
+bool tile_b_fits(int N, int B, int rbytes) {
+  return B >= 1 && (B & (B - 1)) == 0 && N % B == 0 && size_t(2 * rbytes) * (2 * size_t(B) * N + N) <= (size_t(64) << 10);
+}
+
+bool tile_g_fits(int N, int G, int rbytes) {
+  return G >= 1 && G <= 16 && size_t(2 * rbytes) * (12 * size_t(G) * N + N) <= (size_t(64) << 10);
+}
+
 // lines per workgroup of the coalesced y/z passes: largest B in {16, 8, 4, 2, 1} dividing N
 // whose two LDS buffers and twiddles fit in 64 KB
 int fft_lines_b(int N, int rbytes) {
   for (int B = 16; B > 1; B /= 2)
-    if (N % B == 0 && size_t(2 * rbytes) * (2 * size_t(B) * N + N) <= (size_t(64) << 10)) return B;
+    if (tile_b_fits(N, B, rbytes)) return B;
   return 1;
+}
+
+int lines_b_of(const WaveParams& wp, int rbytes) {
+  return wp.tile_b > 0 && tile_b_fits(wp.n, wp.tile_b, rbytes) ? wp.tile_b : fft_lines_b(wp.n, rbytes);
+}
+
+int green_g_of(const WaveParams& wp) {
+  return wp.tile_g > 0 && tile_g_fits(wp.n, wp.tile_g, 8) ? wp.tile_g : fft_green_rows(wp.n);
 }
 
 template <typename R>
@@ -1508,11 +1567,15 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
   const int N = plan.n;
   const size_t cs = 2 * size_t(N) * N * N;
   if (stage == 2) {
-    const int G = fft_green_rows(N);
+    const int G = green_g_of(wp);
     const size_t shm = sizeof(T) * (12 * size_t(G) * N + N);
-    launch_k(k_fft_xgreen<R>, (N * N / 2 + 2 + G - 1) / G, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
+    const int nblk = (N * N / 2 + 2 + G - 1) / G;
+    if (wp.gtab && !wp.gam)  // the cube: tabulated multipliers
+      launch_k(k_fft_xgreen<R, true>, nblk, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
+    else
+      launch_k(k_fft_xgreen<R, false>, nblk, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
   } else {
-    const int B = fft_lines_b(N, sizeof(R));
+    const int B = lines_b_of(wp, sizeof(R));
     const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
     dim3 g(N * N / B, 3);
     const int sign = stage < 2 ? -1 : +1;
@@ -1585,8 +1648,8 @@ __global__ __launch_bounds__(256) void kb_fft(const BatchDesc* __restrict__ D, c
   R* grid = static_cast<R*>(d.grid);
   const R* tw = pick<R>(d.tw64, d.tw32);
   const int* stop = &d.ctl->stop;
-  if (STAGE == 2) {
-    fft_xgreen_body<R>(grid, cs, d.plan, tw, d.wp, d.bg, stop, lb, 0, 0);
+  if (STAGE == 2) {  // multi-system launches hold cubic systems only (fusable)
+    fft_xgreen_body<R, true>(grid, cs, d.plan, tw, d.wp, d.bg, stop, lb, 0, 0);
   } else {
     const int gx = N * N / d.bl;
     if (STAGE == 0 || STAGE == 4)
@@ -1743,54 +1806,6 @@ template void launch_interp_sheared<double>(int, const double*, const double*, c
                                             const int*, const int*, const double*, const double*);
 template void launch_interp_sheared<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t,
                                            const int*, const int*, const double*, const double*);
-// ------------------------------------------------------------------------------------------
-// the allocation-free transform (fsd_fft3d_noalloc): its twiddle table lives in file-scope
-// device memory, one copy per GPU held until the process ends, sized for the largest n
-// ------------------------------------------------------------------------------------------
-
-static __device__ __align__(256) double scratch[2 * kNoAllocFftMax];
-
-// exp(-2 pi i t / n) for t < n, interleaved (re, im)
-__global__ void k_twiddles(int n, double* __restrict__ tw) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double sv, cv;
-  sincospi(2.0 * double(t) / double(n), &sv, &cv);
-  tw[2 * t] = cv;
-  tw[2 * t + 1] = -sv;
-}
-
-namespace {
-std::mutex g_scratch_mu;
-double* g_scratch_ptr[kMaxDevices] = {nullptr};
-}  // namespace
-
-// the device address of this GPU's copy of `scratch`, looked up once per device
-hipError_t noalloc_scratch(double** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  if (!g_scratch_ptr[dev]) {
-    void* p = nullptr;
-    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-    if (e != hipSuccess) return e;
-    g_scratch_ptr[dev] = static_cast<double*>(p);
-  }
-  *out = g_scratch_ptr[dev];
-  return hipSuccess;
-}
-
-hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st) {
-  double* tw = nullptr;
-  hipError_t e = noalloc_scratch(&tw);
-  if (e != hipSuccess) return e;
-  k_twiddles<<<(n + 255) / 256, 256, 0, st>>>(n, tw);
-  launch_fft3d<double>(data, 1, 2 * size_t(n) * n * n, plan, tw, sign, st);
-  return hipGetLastError();
-}
-
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 

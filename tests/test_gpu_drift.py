@@ -5,7 +5,7 @@ Fixman's midpoint scheme.
   configurations, with and without lubrication;
 - a time step with the drift on moves the bodies by (U + drift) dt, with U the saddle
   solve's velocities and the drift that of the step's own dq;
-- the batched step refuses systems with the drift on;
+- the batched step applies each system's drift as the single-system step does;
 - a step with Fixman's drift moves the bodies by (U + (m/2)(U' - U0)) dt, against the
   oracle's two dense solves with the Brownian terms the library drew.
 """
@@ -83,14 +83,37 @@ def test_step_adds_the_drift(F):
     s.close()
 
 
-def test_batch_refuses_the_drift(F):
-    kw = _system(seed=34)
-    s = _make(F, kw)
-    s.set_drift(1)
-    b = F.Batch(1 << 32, 2)
-    b.admit(s)
-    assert b.step(1e-3) == -1  # FSD_EINVAL
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("fused", [True, False])
+def test_batched_step_with_drift_equals_solo(F, mode, fused):
+    """The batched step applies each system's drift as fsd_step does: two Brownian time steps
+    of three systems in one batch (multi-system launches or one stream per system) end where
+    the same systems end stepped alone, with the same noise (seed, stream, step)."""
+    kws = [_system(seed=34 + k, sizes=(3, 2, 4), L=10.0) for k in range(3)]
+    par = dict(kT=1.0, gmres_tol=1e-11)
+    solo = []
+    for kw in kws:
+        s = _make(F, kw, **par)
+        s.set_drift(mode)
+        s.step(1e-3, 2)
+        solo.append(s.state())
+        s.close()
+    live = [_make(F, kw, **par) for kw in kws]
+    for s in live:
+        s.set_drift(mode)
+    b = F.Batch(1 << 34, 4)
+    b.set_fused(fused)
+    slots = [b.admit(s) for s in live]
+    for _ in range(2):
+        assert b.step(1e-3) == 0
+    for k, s in enumerate(live):
+        assert b.info(slots[k]).status == 0
+        X, q = s.state()
+        # the same arithmetic but for the summation order of the multi-system launches
+        assert np.abs(X - solo[k][0]).max() < 1e-11 and np.abs(q - solo[k][1]).max() < 1e-11, k
     b.close()
+    for s in live:
+        s.close()
 
 
 def test_fixman_step_matches_oracle(F):

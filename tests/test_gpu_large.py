@@ -9,8 +9,9 @@ any size, on the same kernels and launch configuration the benchmark times:
 - M lambda does not depend on the splitting parameter xi, to the Ewald tolerance: two
   values of xi give different real-space cutoffs and grids, so an error in either part
   shows up as a dependence on xi;
-- a full FP64 saddle solve (Algorithm 1) meets its tolerance on the true residual, and
-  the mixed-precision solve agrees with it to the solver tolerance.
+- a full FP64 saddle solve (Algorithm 1) and the mixed-precision one meet the workload's
+  tolerance on the true residual, and solved to 1e-7 they agree to 1e-5 (the oracle itself
+  is checked on a 150 x 20 sub-box of the same generator in test_gpu_configs.py).
 """
 import numpy as np
 import pytest
@@ -62,14 +63,20 @@ def test_large_mobility_independent_of_xi(F, large):
 
 
 def test_large_solve_meets_tolerance_fp64_and_mixed(F, large):
-    U = {}
+    # at the workload's own tolerance both precisions meet 1e-5 on the true FP64 residual
     for prec in (F.FSD_FP64, F.FSD_MIXED):
         s = F.System.from_suspension(large, precision=prec)
-        Up, _, info = s.solve()
+        _, _, info = s.solve()
         assert info.status == 0 and info.rel_residual_fp64 <= large.gmres_tol, info.rel_residual_fp64
+        s.close()
+    # solved to 1e-7, the FP32-operator velocities agree with FP64 to the 1e-5 bar
+    U = {}
+    for prec in (F.FSD_FP64, F.FSD_MIXED):
+        s = F.System.from_suspension(large, precision=prec, gmres_tol=1e-7, gmres_maxit=5000)
+        Up, _, info = s.solve()
+        assert info.status == 0 and info.rel_residual_fp64 <= 1e-7, info.rel_residual_fp64
         U[prec] = Up
         s.close()
     ref = U[F.FSD_FP64]
-    # both meet 1e-5 on the true residual; the velocities agree to that order
-    assert _rel(U[F.FSD_MIXED][:, :3], ref[:, :3]) < 1e-4
-    assert _rel(U[F.FSD_MIXED][:, 3:], ref[:, 3:]) < 1e-4
+    assert _rel(U[F.FSD_MIXED][:, :3], ref[:, :3]) < 1e-5
+    assert _rel(U[F.FSD_MIXED][:, 3:], ref[:, 3:]) < 1e-5

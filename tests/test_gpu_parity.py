@@ -399,14 +399,17 @@ def test_clusters256x8_ten_steps_match_oracle(F, precision):
     g = _golden("clusters256x8_oracle.npz")
     s1 = fsdgen.config(1)
     assert str(g["digest"]) == digest(s1)
-    s = F.System.from_suspension(s1, precision=precision, gmres_tol=1e-6)
+    # the parity setting: the solver tolerance 1e-7, below the workload's 1e-6, so that the
+    # solver error does not build up along the trajectory (each step integrates the GPU's own
+    # velocities, the stored trajectory the oracle's)
+    s = F.System.from_suspension(s1, precision=precision, gmres_tol=1e-7)
     worst = 0.0
     for step in range(len(g["U"])):
         U, _, info = s.solve()
         et, er = _vel_errors(U, g["U"][step])
         worst = max(worst, et, er)
         assert et < 1e-5 and er < 1e-5, (step, et, er)
-        assert info.rel_residual_fp64 <= 1e-6
+        assert info.rel_residual_fp64 <= 1e-7
         # advance with the same Euler rule the oracle used (re-solves, then integrates)
         s.step(s1.dt, 1)
     print("worst relative velocity error over 10 steps:", worst)
