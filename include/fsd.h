@@ -338,6 +338,17 @@ fsd_status fsd_real_functions(fsd_system* s, int n, const double* r, double* out
  * transform.  Host buffer; for verification of the FFT stages. */
 fsd_status fsd_fft3d(int n, int sign, double* data);
 
+/* The transform of fsd_fft3d on a device buffer, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  d_data: n^3 complex values (interleaved re/im
+ * doubles, x fastest) in device memory of the current GPU, transformed in place, stream-
+ * ordered on hip_stream (NULL: the null stream); the caller owns it.  The twiddle table
+ * lives in a fixed device array of 2 x 512 doubles per GPU, held until the process ends, so
+ * n is at most 512 (FSD_EINVAL beyond, or for n not a product of 2, 3 and 5; the text is in
+ * fsd_last_error(NULL)).  Calls that overlap on one GPU race on that array: order them on
+ * one stream.  FSD_EDEVICE if a launch fails. */
+fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream);
+
 /* ---- batches of independent systems (many small suspensions sharing the GPU) -------- */
 
 /* A batch holds up to max_slots systems whose device memory counts against

@@ -7,5 +7,5 @@ not been built raises ImportError; there is no CPU fallback.
 """
 from ._capi import (  # noqa: F401
     Batch, FSD_FP64, FSD_MIXED, FsdError, Info, Params, SolveInfo, System, default_params,
-    estimate_bytes, fft3d, lib, library_path, normals, philox4x64, TIMER_NAMES,
+    estimate_bytes, fft3d, fft3d_noalloc, lib, library_path, normals, philox4x64, TIMER_NAMES,
 )

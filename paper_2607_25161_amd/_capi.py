@@ -86,6 +86,7 @@ _sig("fsd_apply_precond", C.c_int, _SYS, _D, _D)
 _sig("fsd_get_rhs", C.c_int, _SYS, _D)
 _sig("fsd_real_functions", C.c_int, _SYS, C.c_int, _D, _D)
 _sig("fsd_fft3d", C.c_int, C.c_int, C.c_int, _D)
+_sig("fsd_fft3d_noalloc", C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p)
 _U64P = C.POINTER(C.c_uint64)
 _sig("fsd_set_brownian", C.c_int, _SYS, C.c_double, C.c_uint64, C.c_uint64)
 _sig("fsd_set_noise", C.c_int, _SYS, _D, _D, _D)
@@ -182,6 +183,14 @@ def fft3d(data: np.ndarray, sign: int) -> np.ndarray:
     if rc:
         raise FsdError(rc, f"fsd_fft3d: {lib.fsd_last_error(None).decode()}")
     return buf.view(np.complex128).reshape(a.shape)
+
+
+def fft3d_noalloc(n: int, sign: int, data_ptr: int, stream=None):
+    """fsd_fft3d_noalloc: in place on a device buffer of n^3 complex doubles (e.g. a torch
+    complex128 tensor's data_ptr()), stream-ordered on `stream` (a hipStream_t handle)."""
+    rc = lib.fsd_fft3d_noalloc(int(n), int(sign), C.c_void_p(int(data_ptr)), C.c_void_p(stream) if stream else None)
+    if rc:
+        raise FsdError(rc, f"fsd_fft3d_noalloc: {lib.fsd_last_error(None).decode()}")
 
 
 class System:

@@ -142,6 +142,11 @@ template <typename R>
 void launch_interp_sheared(int nb, const double* pos4, const R* grid, const WaveParams& wp, double* out,
                            hipStream_t st, const int* skip, const int* body, const double* r4, const double* V);
 // pass: 0, 1, 2 = transforms along x, y, z; -1 = all three
+// the allocation-free in-place transform of an n^3 complex grid (n <= kNoAllocFftMax) on the
+// caller's device buffer, its twiddles in a fixed device array of this GPU
+constexpr int kNoAllocFftMax = 512;
+constexpr int kMaxDevices = 64;
+hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st);
 template <typename R>
 void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, const R* twiddle,
                   int sign, hipStream_t st, int pass = -1, const int* skip = nullptr);

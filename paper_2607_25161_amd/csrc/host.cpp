@@ -2460,6 +2460,25 @@ fsd_status fsd_fft3d(int n, int sign, double* data) {
   return rc;
 }
 
+fsd_status fsd_fft3d_noalloc(int n, int sign, double* d_data, void* hip_stream) {
+  if (!d_data || (sign != 1 && sign != -1)) {
+    g_last_error = "fsd_fft3d_noalloc: a device buffer and sign +-1";
+    return FSD_EINVAL;
+  }
+  FftPlan plan;
+  if (n > kNoAllocFftMax || !make_plan(n, plan)) {
+    g_last_error = "fsd_fft3d_noalloc: n must be a product of 2, 3 and 5 of at most " +
+                   std::to_string(kNoAllocFftMax) + " (the size of its fixed twiddle array)";
+    return FSD_EINVAL;
+  }
+  const hipError_t e = launch_fft3d_noalloc(n, sign, d_data, plan, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) {
+    g_last_error = std::string("fsd_fft3d_noalloc: ") + hipGetErrorString(e);
+    return FSD_EDEVICE;
+  }
+  return FSD_OK;
+}
+
 }  // extern "C"
 
 // ==========================================================================================

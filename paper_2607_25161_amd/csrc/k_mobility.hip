@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <mutex>
+
 #include "fsd_impl.hpp"
 #include "k_rigid.hpp"
 
@@ -1806,6 +1808,54 @@ template void launch_interp_sheared<double>(int, const double*, const double*, c
                                             const int*, const int*, const double*, const double*);
 template void launch_interp_sheared<float>(int, const double*, const float*, const WaveParams&, double*, hipStream_t,
                                            const int*, const int*, const double*, const double*);
+// ------------------------------------------------------------------------------------------
+// the allocation-free transform (fsd_fft3d_noalloc): its twiddle table lives in file-scope
+// device memory, one copy per GPU held until the process ends, sized for the largest n
+// ------------------------------------------------------------------------------------------
+
+static __device__ __align__(256) double scratch[2 * kNoAllocFftMax];
+
+// exp(-2 pi i t / n) for t < n, interleaved (re, im)
+__global__ void k_twiddles(int n, double* __restrict__ tw) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double sv, cv;
+  sincospi(2.0 * double(t) / double(n), &sv, &cv);
+  tw[2 * t] = cv;
+  tw[2 * t + 1] = -sv;
+}
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+// the device address of this GPU's copy of `scratch`, looked up once per device
+hipError_t noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_fft3d_noalloc(int n, int sign, double* data, const FftPlan& plan, hipStream_t st) {
+  double* tw = nullptr;
+  hipError_t e = noalloc_scratch(&tw);
+  if (e != hipSuccess) return e;
+  k_twiddles<<<(n + 255) / 256, 256, 0, st>>>(n, tw);
+  launch_fft3d<double>(data, 1, 2 * size_t(n) * n * n, plan, tw, sign, st);
+  return hipGetLastError();
+}
+
 template void launch_fft3d<double>(double*, int, size_t, const FftPlan&, const double*, int, hipStream_t, int, const int*);
 template void launch_fft3d<float>(float*, int, size_t, const FftPlan&, const float*, int, hipStream_t, int, const int*);
 
