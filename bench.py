@@ -92,13 +92,19 @@ def measured_traffic(counters_file, kernel):
     if not src or not os.path.exists(path):
         return None
     text = open(path).read()
-    want = re.search(r"^source %s sha256 ([0-9a-f]{64})$" % re.escape(src), text, re.M)
+    # every source the summary lists (the kernel's file and the headers it includes) must
+    # be the one the counters were taken with
+    recorded = dict(re.findall(r"^source (\S+) sha256 ([0-9a-f]{64})$", text, re.M))
     row = re.search(r"^traffic %s (\d+)$" % re.escape(kernel), text, re.M)
-    if not want or not row:
+    if src not in recorded or not row:
         return None
-    with open(os.path.join(ROOT, "paper_2607_25161_amd", "csrc", src), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != want.group(1):
+    for name, digest in recorded.items():
+        fn = os.path.join(ROOT, "paper_2607_25161_amd", "csrc", name)
+        if not os.path.exists(fn):
             return None
+        with open(fn, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     return int(row.group(1))
 
 
@@ -235,6 +241,9 @@ def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=Fal
     b = F.Batch(1 << 40, len(sys_))
     b.set_fused(fused)
     slots = [b.admit(s) for s in sys_]
+    # a multi-system launch reserves its largest system's LDS for every workgroup: measure
+    # the caps on the systems' transform tiles that make the shared launches fastest
+    caps = b.autotune_tiles(10) if fused else None
     for _ in range(warmup):
         b.step(1e-3)
     _sync()
@@ -256,6 +265,8 @@ def run_batch(F, systems, steps, warmup, warm, precision, fused=True, timing=Fal
            "lat": lat}
     if chosen:
         out["tiles"] = {f"B{b} G{g}": sum(1 for c in chosen if c == (b, g)) for b, g in sorted(set(chosen))}
+    if caps:
+        out["lds_caps_kb"] = {"lines": caps[0] // 1024 or None, "x_green": caps[1] // 1024 or None}
     if timing:
         # the same kernels once more, one more step with event timing on every launch
         b.set_timing(True)
@@ -322,7 +333,7 @@ def bench_batched(args, F, fsdgen, torch):
         "speedup_vs_plain_graphed": round(mixed["value"] / plain_g["value"], 3),
         "plain": "FP64, one system at a time, xi = 25/L (the workload's policy), eager launches",
         "gmres_iterations_mean": mixed["gmres_iterations_mean"], "gmres_iterations_max": mixed["gmres_iterations_max"],
-        "tiles": mixed.get("tiles"), "xi_tuning_s": round(t_tune, 2),
+        "tiles": mixed.get("tiles"), "lds_caps_kb": mixed.get("lds_caps_kb"), "xi_tuning_s": round(t_tune, 2),
         "plain_fp64_one_at_a_time": plain, "plain_fp64_one_at_a_time_graphed": plain_g,
         "plain_fp64_one_at_a_time_measured_xi": plain_t,
         "batched_mixed_xi_25_over_L": ctx(paper), "batched_fp64_xi_25_over_L": ctx(b64),
@@ -344,21 +355,24 @@ def bench_batched(args, F, fsdgen, torch):
 
 
 def bench_serving(args, F, fsdgen, torch):
-    """Request stream (Poisson arrivals) served by the continuous-batching engine."""
+    """Request stream served by the continuous-batching engine: capacity from a closed loop,
+    then Poisson arrivals swept over multiples of it; the plain path (FP64, one request at a
+    time) serves the same requests for comparison."""
     from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request, poisson_arrivals
     reqs = fsdgen.serving_requests(args.requests, n_range=(100, args.max_beads), n_steps=args.req_steps, kT=args.kT,
                                    shear_rate=args.shear_rate)
     sheared = args.shear_rate > 0.01  # faster shear needs the sheared lattice's images across the y faces
+    args.precision = args.precision or "mixed"
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
 
-    def run(rate, seed, subset=None, n_steps=args.req_steps):
+    def run(rate, seed, subset=None, n_steps=args.req_steps, precision=prec, slots=args.slots, multi=8):
         sel = reqs if subset is None else subset
         # Brownian requests: the previous solution, not an extrapolation of noisy ones
-        be = LibBackend(F, budget, args.slots, dict(precision=prec), warm_start=0 if args.cold else 1,
+        be = LibBackend(F, budget, slots, dict(precision=precision), warm_start=0 if args.cold else 1,
                         lees_edwards=sheared)
-        eng = BatchEngine(be, max_slots=args.slots, dt=1e-3)
+        eng = BatchEngine(be, max_slots=slots, dt=1e-3, max_steps_per_tick=multi)
         t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
         rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
 
@@ -371,32 +385,45 @@ def bench_serving(args, F, fsdgen, torch):
         be.batch.close()
         return rep
 
-    progress(f"generated {len(reqs)} requests")
+    def summary(rep):
+        return {"bead_solves_per_s": round(rep["bead_solves_per_s"], 1),
+                "p50_ms": round(1e3 * rep["p50_latency_s"], 1) if rep["p50_latency_s"] is not None else None,
+                "p99_ms": round(1e3 * rep["p99_latency_s"], 1) if rep["p99_latency_s"] is not None else None,
+                "completed": rep["completed"], "failed": rep["failed"], "span_s": round(rep["span_s"], 2)}
+
+    progress(f"generated {len(reqs)} requests, {sum(s.n_bead for s in reqs)} beads")
     if args.warmup:                                 # code objects loaded, first-touch allocations
         run(None, 0, sorted(reqs, key=lambda s: s.n_bead)[:2], 2)
     closed = run(None, 0)                           # every request queued at t = 0: capacity
-    progress(f"closed loop: {closed}")
+    progress(f"closed loop: {summary(closed)}")
     cap = closed["completed"] / closed["span_s"]
-    rate = args.load * cap
-    open_ = run(rate, 1)
+    rates = {}
+    for load in [float(v) for v in args.loads.split(",")]:
+        rep = run(load * cap, 1)
+        rates[str(load)] = dict(summary(rep), arrival_rate=round(load * cap, 4))
+        progress(f"load {load}: {rates[str(load)]}")
+    plain = run(None, 0, precision=F.FSD_FP64, slots=1, multi=1)
+    progress(f"plain FP64, one request at a time: {summary(plain)}")
+    head = rates.get("1.0") or next(iter(rates.values()))
     out = {
-        "metric": METRIC, "value": round(open_["bead_solves_per_s"], 1), "unit": "bead-solves/s", "n_gpus": 1,
+        "metric": METRIC, "value": summary(closed)["bead_solves_per_s"], "unit": "bead-solves/s", "n_gpus": 1,
         "steps": args.req_steps, "warmup": args.warmup, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == F.FSD_FP64 else "f32 matvec / f64 Krylov", "data": "synthetic",
+        "dtype": "f64" if prec == F.FSD_FP64 else "f32 operator / f64 Krylov", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
                                f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate {args.shear_rate} "
                                f"({'sheared lattice' if sheared else 'cube'}) + lubrication + "
-                               f"Brownian kT {args.kT}, tol 1e-5, Poisson arrivals at {args.load} x capacity",
+                               f"Brownian kT {args.kT} with Fixman's drift off, tol 1e-5, closed loop",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
-                   "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision, "warm_start": 0 if args.cold else 1,
-                   "parallelism": "single GPU, continuous batching"},
-        "latency_ms": {"p50": round(1e3 * open_["p50_latency_s"], 1), "p99": round(1e3 * open_["p99_latency_s"], 1)},
-        "capacity_requests_per_s": round(cap, 3), "arrival_rate": round(rate, 3),
-        "closed_loop": {"bead_solves_per_s": round(closed["bead_solves_per_s"], 1),
-                        "p50_ms": round(1e3 * closed["p50_latency_s"], 1),
-                        "p99_ms": round(1e3 * closed["p99_latency_s"], 1)},
-        "failed": open_["failed"] + closed["failed"],
+                   "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,
+                   "warm_start": 0 if args.cold else 1, "parallelism": "single GPU, continuous batching"},
+        "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"], "at_load": 1.0 if "1.0" in rates else None},
+        "capacity_requests_per_s": round(cap, 4),
+        "closed_loop": summary(closed),
+        "poisson_loads": rates,
+        "plain_fp64_one_at_a_time": summary(plain),
+        "speedup_vs_plain": round(closed["bead_solves_per_s"] / plain["bead_solves_per_s"], 3),
+        "failed": closed["failed"] + sum(r["failed"] for r in rates.values()),
         "roofline": None,
     }
     print(json.dumps(out), flush=True)
@@ -470,6 +497,7 @@ def bench_rods(args, F, fsdgen, torch):
     rigid rods (n_b beads each) in a periodic cube, against the total bead count, at the two
     splitting-parameter policies (xi = 0.5/a and xi = 25/L).  Each case times args.rod_steps
     steps after args.rod_warmup discarded ones (the paper: 100 after 10)."""
+    args.precision = args.precision or "mixed"
     nbs = [int(v) for v in args.rod_nb.split(",")]
     phis = [float(v) for v in args.rod_phi.split(",")]
     ntots = [int(v) for v in args.rod_ntot.split(",")]
@@ -485,7 +513,13 @@ def bench_rods(args, F, fsdgen, torch):
                     except ValueError as e:  # rods longer than the box
                         progress(f"rods n_b {nb} phi {phi} N_tot {nt}: skipped ({e})")
                         break
-                    sysm = F.System.from_suspension(s0, stream=stream, precision=prec, gmres_maxit=20000)
+                    try:
+                        sysm = F.System.from_suspension(s0, stream=stream, precision=prec, gmres_maxit=20000)
+                    except F.FsdError as e:  # e.g. a spectral grid above 256 at xi = 0.5/a in a large box
+                        progress(f"rods n_b {nb} phi {phi} N_tot {nt} {policy}: skipped ({e})")
+                        cases.append({"n_b": nb, "phi": phi, "n_bead": s0.n_bead,
+                                      "xi_policy": "0.5/a" if policy == "fixed" else "25/L", "skipped": str(e)})
+                        continue
                     sysm.set_pair_forces(k_n=s0.extra["k_n"], r_cut=2.0 * s0.a)
                     sysm.set_warm_start(1)
                     if args.rod_drift:
@@ -513,7 +547,7 @@ def bench_rods(args, F, fsdgen, torch):
                     cases.append(c)
                     progress(f"rods n_b {nb} phi {phi} N_tot {s0.n_bead} xi {c['xi_policy']}: "
                              f"t_s {c['t_s_us']} us ({c['ms_per_step']} ms per step, grid {info.grid})")
-    best = min(cases, key=lambda c: c["t_s_us"])
+    best = min((c for c in cases if "t_s_us" in c), key=lambda c: c["t_s_us"])
     out = {"metric": "t_s: wall-clock time per time step per bead, Brownian rigid rods (Section 3.2)",
            "value": best["t_s_us"], "unit": "us", "n_gpus": 1, "steps": args.rod_steps,
            "warmup": args.rod_warmup, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -551,6 +585,7 @@ def bench_copy(args, torch):
 
 def bench_clusters(args, F, fsdgen, torch, emit=True):
     """256 clusters of 8 (2048 beads, phi 0.10, 64^3), FP64 at tol 1e-6 (or --precision)."""
+    args.precision = args.precision or "fp64"
     stream = torch.cuda.current_stream()
     s = fsdgen.config(1)
     prec = F.FSD_MIXED if args.precision == "mixed" else F.FSD_FP64
@@ -636,7 +671,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="clusters: fp64 by default; serving and rods: mixed by default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["batched", "clusters", "large", "serving", "rods", "copy"],
                     default="batched")
@@ -649,11 +685,12 @@ def main():
                     help="rods: Brownian drift (0 none, 1 random finite differences, 2 Fixman)")
     ap.add_argument("--no-sub", action="store_true", help="batched: skip the 256x8 and 4096x20 sub-runs")
     ap.add_argument("--systems", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=12)
+    ap.add_argument("--requests", type=int, default=8)
     ap.add_argument("--req-steps", type=int, default=20)
     ap.add_argument("--max-beads", type=int, default=50000)
     ap.add_argument("--slots", type=int, default=16)
-    ap.add_argument("--load", type=float, default=0.5)
+    ap.add_argument("--loads", default="0.25,0.5,1.0,2.0,4.0",
+                    help="serving: Poisson arrival rates as multiples of the measured capacity")
     ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
     ap.add_argument("--shear-rate", type=float, default=1.0,
                     help="shear rate of the serving requests (on the sheared lattice; 0.01 or less keeps the cube)")

@@ -82,8 +82,10 @@ typedef struct {
   int gmres_maxit;       /* total inner iterations allowed per solve                   */
   int precision;         /* fsd_precision                                              */
   double lanczos_tol;    /* relative stopping tolerance of the Lanczos square roots of
-                            the Brownian terms (1e-4); at most 100 Lanczos steps      */
+                            the Brownian terms (1e-4)                                 */
   uint64_t seed;         /* key of the counter-based noise generator                   */
+  int lanczos_maxit;     /* most Lanczos steps per square root (100, at most 2000); the
+                            basis takes (lanczos_maxit + 1) 6 n_bead doubles           */
 } fsd_params;
 
 typedef struct {
@@ -163,6 +165,20 @@ fsd_status fsd_get_state(const fsd_system* s, double* com, double* quat, double*
 fsd_status fsd_get_velocities(const fsd_system* s, double* U_agg);
 
 fsd_status fsd_get_info(const fsd_system* s, fsd_info* info);
+
+/* Constraint stresslets of the last solve (Section 3.1.4, Eq. `stress_comp`).  At the
+ * force-torque level the beads carry no stresslet of their own, so an aggregate's particle
+ * stress is its constraint stress S^C_j = sum_{i in j} sym(r_i f_i), r_i = x_i - X_j and f_i
+ * the total force on bead i: the far-field hydrodynamic force (the force moments of the
+ * solve), the lubrication force at the solved velocities (with its R_FE : E_inf part), the
+ * conservative pair forces and, with kT > 0, the near-field Brownian force.  S_agg (9 per
+ * body, row-major, may be NULL) gets S^C_j; S_mean (9, may be NULL) gets the suspension's
+ * particle stress (1/V) sum_j S^C_j.  The FTS terms of Eq. `stress_comp` (the far-field
+ * stresslets, R_SU and R_SE, the Brownian divergence) need the stresslet level, which this
+ * library does not build.  Needs a completed solve at the current configuration
+ * (fsd_solve or fsd_solve_dev; FSD_ESTATE after a step moved the bodies).  Allocates
+ * 15 doubles per bead on first use. */
+fsd_status fsd_get_stresslets(fsd_system* s, double* S_agg, double* S_mean);
 
 /* Device bytes fsd_init_aggregates will allocate for a system of n_bead beads in
  * n_agg bodies in a cube of side L with parameters p: the spectral grid of the
@@ -266,7 +282,7 @@ fsd_status fsd_set_roughness(fsd_system* s, double alpha, double h0);
  * projected by Sigma, to the aggregate rows (b2 = -(F_P + Sigma F_B + R_FE : E_inf)).
  * The wave-space part uses the exact square root of the positively split wave-space
  * operator applied to white noise on the grid; the real-space and near-field parts use
- * Lanczos square roots (params.lanczos_tol, at most 100 steps).  The noise is drawn from
+ * Lanczos square roots (params.lanczos_tol, at most params.lanczos_maxit steps).  The noise is drawn from
  * Philox4x64-10 keyed by (params.seed, stream) with counters (e/4 + 1, purpose, step, 0),
  * purpose 0 = grid, 1 = real space, 2 = near field; fsd_step advances step by one per
  * time step and sets dt. */
@@ -380,6 +396,13 @@ fsd_status fsd_batch_solve(fsd_batch* b);
  * system whose solve succeeded. */
 fsd_status fsd_batch_step(fsd_batch* b, double dt);
 
+/* As fsd_batch_step with a number of time steps per slot: n_steps has one entry per slot
+ * (max_slots of fsd_batch_create; empty slots ignored, 0 leaves a system where it is), so a
+ * small system can take several steps while a large one takes one.  The systems still
+ * stepping run together, round by round; a slot whose solve fails stops there and keeps
+ * its status.  FSD_EINVAL for a negative count. */
+fsd_status fsd_batch_step_counts(fsd_batch* b, double dt, const int* n_steps);
+
 /* Info of the last solve in a slot. */
 fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* info);
 
@@ -408,6 +431,22 @@ fsd_status fsd_batch_get_timers(fsd_batch* b, double* total_ms, long long* launc
  * (FSD_ESTATE otherwise).  Builds lists and factors for moved positions first; leaves the
  * grids and scratch vectors undefined and the systems ready for their next solve. */
 fsd_status fsd_batch_time_kernel(fsd_batch* b, int timer, int reps, double* avg_ms, double* bytes_per_launch);
+
+/* Measured LDS caps of the multi-system transform launches (Section 2.5: the wave-space
+ * passes of every admitted system in one launch).  Such a launch reserves its largest
+ * system's LDS for every workgroup, so one system's wide tile lowers the occupancy of all.
+ * For the z/y line passes and then the x+Green pass this times the launch
+ * (fsd_batch_time_kernel, reps replays) with each system's tile narrowed to fit caps of
+ * 16, 24, 32, 40 and 48 KB and with no cap, and keeps the fastest; later launches of the
+ * batch use the caps.  lines_lds and green_lds (may be NULL) get them in bytes (0: no
+ * cap).  Needs systems that share multi-system launches (FSD_ESTATE otherwise); leaves the
+ * grids and scratch vectors undefined, as fsd_batch_time_kernel does. */
+fsd_status fsd_batch_autotune_tiles(fsd_batch* b, int reps, size_t* lines_lds, size_t* green_lds);
+
+/* Sets those caps directly (bytes; 0: no cap).  A system's tile is narrowed (halving the
+ * lines per workgroup, or one row pair fewer) until its LDS fits, down to one line or one
+ * pair whatever the cap.  The transforms compute the same values at any tile. */
+fsd_status fsd_batch_set_lds_caps(fsd_batch* b, size_t lines_lds, size_t green_lds);
 
 void fsd_batch_destroy(fsd_batch* b);
 

@@ -19,8 +19,9 @@ Everything here is plain, dense and FP64:
 * integrate -- explicit Euler update of centroids and quaternions.
 * brownian -- the Brownian right-hand-side terms with exact (eigendecomposition)
               square roots of the real-space mobility and the lubrication matrix.
+* stress   -- the constraint stresslet of each aggregate from the solved bead forces.
 
 Paper sections cited are those of "Fast Stokesian Dynamics for Rigid
 Aggregates" (Mangal et al.).
 """
-from . import rpy, lub, rigid, saddle, integrate, pse, brownian, forces, drift  # noqa: F401
+from . import rpy, lub, rigid, saddle, integrate, pse, brownian, forces, drift, stress  # noqa: F401

@@ -30,7 +30,7 @@ class Params(C.Structure):
         ("ewald_tol", C.c_double), ("grid", C.c_int), ("support", C.c_int), ("r_lub", C.c_double),
         ("r_precond", C.c_double), ("lub_eps_min", C.c_double), ("gmres_tol", C.c_double),
         ("gmres_restart", C.c_int), ("gmres_maxit", C.c_int), ("precision", C.c_int),
-        ("lanczos_tol", C.c_double), ("seed", C.c_uint64),
+        ("lanczos_tol", C.c_double), ("seed", C.c_uint64), ("lanczos_maxit", C.c_int),
     ]
 
 
@@ -77,6 +77,7 @@ _sig("fsd_step", C.c_int, _SYS, C.c_double, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_get_state", C.c_int, _SYS, _D, _D, _D)
 _sig("fsd_get_velocities", C.c_int, _SYS, _D)
 _sig("fsd_get_info", C.c_int, _SYS, C.POINTER(Info))
+_sig("fsd_get_stresslets", C.c_int, _SYS, _D, _D)
 _sig("fsd_estimate_bytes", C.c_size_t, C.POINTER(Params), C.c_int32, C.c_int32, C.c_double)
 _sig("fsd_last_error", C.c_char_p, _SYS)
 _sig("fsd_destroy", None, _SYS)
@@ -113,6 +114,7 @@ _sig("fsd_batch_admit", C.c_int, C.c_void_p, _SYS, C.POINTER(C.c_int))
 _sig("fsd_batch_retire", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_solve", C.c_int, C.c_void_p)
 _sig("fsd_batch_step", C.c_int, C.c_void_p, C.c_double)
+_sig("fsd_batch_step_counts", C.c_int, C.c_void_p, C.c_double, C.POINTER(C.c_int))
 _sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
@@ -120,6 +122,8 @@ _sig("fsd_batch_set_fused", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_set_timing", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_get_timers", C.c_int, C.c_void_p, _D, C.POINTER(C.c_longlong), _D)
 _sig("fsd_batch_time_kernel", C.c_int, C.c_void_p, C.c_int, C.c_int, _D, _D)
+_sig("fsd_batch_autotune_tiles", C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t))
+_sig("fsd_batch_set_lds_caps", C.c_int, C.c_void_p, C.c_size_t, C.c_size_t)
 
 TIMER_NAMES = ("real_sum", "spread", "fft_first", "fft_y", "fft_green", "fft_last", "interp", "rigid_lub",
                "precond", "cgs_dot", "cgs_update", "cgs_norm_arnoldi")
@@ -283,6 +287,14 @@ class System:
         xb = np.zeros((self.n_bead, 3)) if beads else None
         self._check(lib.fsd_get_state(self._h, _dptr(X), _dptr(q), _dptr(xb) if beads else None), "fsd_get_state")
         return (X, q, xb) if beads else (X, q)
+
+    def stresslets(self):
+        """(per-aggregate constraint stresslets (n_agg, 3, 3), suspension particle stress (3, 3))
+        of the last solve."""
+        S = np.zeros((self.n_agg, 3, 3))
+        m = np.zeros((3, 3))
+        self._check(lib.fsd_get_stresslets(self._h, _dptr(S), _dptr(m)), "fsd_get_stresslets")
+        return S, m
 
     def velocities(self):
         """Aggregate velocities (n_agg, 6) of the last completed solve, by any call."""
@@ -455,6 +467,7 @@ class Batch:
         if rc:
             raise FsdError(rc, "fsd_batch_create")
         self._h = h
+        self.max_slots = int(max_slots)
         self.systems = {}
 
     def admit(self, system: "System") -> int:
@@ -487,6 +500,13 @@ class Batch:
 
     def step(self, dt: float):
         return lib.fsd_batch_step(self._h, float(dt))
+
+    def step_counts(self, dt: float, counts: dict):
+        """Time steps per slot in one call ({slot: n}; slots left out take none)."""
+        n = (C.c_int * self.max_slots)()
+        for sl, k in counts.items():
+            n[int(sl)] = int(k)
+        return lib.fsd_batch_step_counts(self._h, float(dt), n)
 
     def info(self, slot: int) -> SolveInfo:
         inf = SolveInfo()
@@ -527,6 +547,21 @@ class Batch:
         if rc:
             raise FsdError(rc, "fsd_batch_time_kernel")
         return ms.value, by.value
+
+    def autotune_tiles(self, reps=20):
+        """Measured LDS caps (bytes, 0: none) of the multi-system line passes and x+Green
+        pass; later launches of the batch use them."""
+        a, g = C.c_size_t(0), C.c_size_t(0)
+        rc = lib.fsd_batch_autotune_tiles(self._h, int(reps), C.byref(a), C.byref(g))
+        if rc:
+            raise FsdError(rc, "fsd_batch_autotune_tiles")
+        return a.value, g.value
+
+    def set_lds_caps(self, lines, green):
+        """LDS caps (bytes, 0: none) of the multi-system line passes and x+Green pass."""
+        rc = lib.fsd_batch_set_lds_caps(self._h, int(lines), int(green))
+        if rc:
+            raise FsdError(rc, "fsd_batch_set_lds_caps")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -52,6 +52,19 @@ struct FftPlan {
   unsigned long long rcode;  // the radices again, 4 bits per stage (stage 0 lowest)
 };
 
+// LDS distance, in elements of elem_bytes, between the B lines that one workgroup of a z
+// or y pass transforms.  Loading B consecutive x of a grid row puts neighbouring lanes on
+// different lines, so with a stride of N (a multiple of the 64 banks' width for every even
+// N) they would all hit one bank.  A stride S with S / t odd, t = max(1, E / B) and E the
+// elements per bank row, sends the lanes of one LDS cycle to distinct banks.
+__host__ __device__ inline int fft_line_stride(int N, int B, int elem_bytes) {
+  if (B <= 1) return N;
+  const int E = 256 / elem_bytes, t = E / B > 1 ? E / B : 1;
+  int S = N;
+  while (S % (2 * t) != t) ++S;
+  return S;
+}
+
 // Constants of the wave-space (spectral Ewald) part of the mobility.
 struct WaveParams {
   int n;            // grid points per side
@@ -295,6 +308,15 @@ void launch_precond_arnoldi(int nb, int na, const int* offsets, const double* r4
 // *p = v (a one-thread kernel, so it is ordered on the stream like the kernels around it)
 void launch_set_value(double* p, double v, hipStream_t st);
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st);
+// translational rigid-body bead velocities U + Omega x r from the aggregate vector V
+void launch_bead_rigid_vel(int nb, const int* body, const double* r4, const double* V, double* w, hipStream_t st);
+// S_j = sum_i sym(r_i (F_i + f_i)) per aggregate (9 each); f may be null
+void launch_stresslets(int na, const int* offsets, const double* r4, const double* F, const double* f, double* S,
+                       hipStream_t st);
+// Lanczos step k: alpha[k] = h1[k] + h2[k], beta[k] = sqrt(nrm2[0]), scal[0] = 1 / beta[k]
+void launch_lanczos_coef(int k, const double* h1, const double* h2, const double* nrm2, double* alpha, double* beta,
+                         double* scal, hipStream_t st);
+void launch_scale_dev(size_t n, const double* a, const double* x, double* y, hipStream_t st);  // y = a[0] x
 
 // ---- Brownian terms (k_brownian.hip) ------------------------------------------------------
 // Noise stream: Philox4x64-10 under key (k0, k1); normal e of the stream comes from the
@@ -342,7 +364,10 @@ struct BatchDesc {
   void* grid;
   int bl;  // lines per workgroup of the z and y passes
   int bg;  // row slots per workgroup of the x+Green pass
-  // gather spreading (8^3 blocks)
+  // gather spreading (8^3 blocks): per-block candidate lists
+  const int* blk_start;
+  const int* blk_end;
+  const int* cand;
   const int* bin_start;
   const int* bin_end;
   const int* perm;

@@ -215,6 +215,7 @@ struct fsd_system {
   fsd_params p{};
   hipStream_t st = nullptr;
   bool solved = false;  // d_U holds the velocities of a completed solve of the full right-hand side
+  double *d_fst = nullptr, *d_wst = nullptr, *d_sst = nullptr;  // stresslet scratch (allocated on first use)
   bool own_stream = false;
   hipStream_t st2 = nullptr;           // side stream: the real-space sum overlaps the wave space
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -950,7 +951,7 @@ void ensure_brownian(fsd_system* s) {
   s->d_psi_nf = dalloc<double>(o, 3 * nb);
   s->d_lan = dalloc<double>(o, size_t(s->lan_max + 1) * 6 * nb);
   s->d_lc = dalloc<double>(o, s->lan_max + 1);
-  s->d_lh = dalloc<double>(o, 2 * size_t(s->lan_max + 2));
+  s->d_lh = dalloc<double>(o, 5 * size_t(s->lan_max + 2));  // h1, h2, ||w||^2, alpha, beta (and 1/beta)
   s->d_lpart = dalloc<double>(o, size_t(s->lan_max + 2) * 1024);  // launch_dots partials: <= 1024 blocks
 }
 
@@ -1018,37 +1019,50 @@ std::vector<double> tridiag_sqrt_e1(const std::vector<double>& al, const std::ve
 }
 
 // out = A^{1/2} z for a symmetric positive semi-definite operator by the Lanczos
-// method (Chow and Saad's square-root approximation): out = |z| V_k T_k^{1/2} e1,
-// stopped when the coefficient vector changes by less than tol (relative).
-// Returns the number of Lanczos steps.
+// method (Chow and Saad's square-root approximation): out = |z| V_k T_k^{1/2} e1.  Each step
+// orthogonalises A v_k against the whole basis twice (classical Gram-Schmidt; it keeps the
+// vectors orthogonal when the operator is ill-conditioned, as the lubrication matrix is) and
+// keeps alpha_k, beta_k and the next vector on the device; the host reads the coefficients
+// every kCheck steps and stops once T^{1/2} e1 changes by less than tol (relative) between
+// two reads, or at a breakdown.  Returns the number of Lanczos steps.
 template <typename Apply>
 int lanczos_sqrt(fsd_system* s, size_t n, Apply&& apply, const double* z, double* out, double tol) {
+  constexpr int kCheck = 4;
   const double b0 = std::sqrt(std::max(dev_dot(s, n, z, z), 0.0));
   if (b0 == 0.0) {
     launch_zero(out, sizeof(double) * n, s->st);
     return 0;
   }
+  const int L = s->lan_max + 2;
+  double *h1 = s->d_lh, *h2 = s->d_lh + L, *nrm2 = s->d_lh + 2 * L, *alpha = s->d_lh + 3 * L,
+         *beta = s->d_lh + 4 * L;
+  double* scal = nrm2 + 1;
   double* V = s->d_lan;
   double* w = s->d_t;
   launch_scale(n, 1.0 / b0, z, V, s->st);
-  std::vector<double> al, be, prev;
+  std::vector<double> al(s->lan_max), be(s->lan_max), prev;
   int k = 0;
-  for (; k < s->lan_max; ++k) {
-    double* vk = V + size_t(k) * n;
-    apply(vk, w);
-    const double a = dev_dot(s, n, vk, w);
-    launch_axpby(n, -a, vk, 1.0, w, s->st);
-    if (k > 0) launch_axpby(n, -be.back(), V + size_t(k - 1) * n, 1.0, w, s->st);
-    // full reorthogonalisation against the basis (keeps the Lanczos vectors orthogonal
-    // when the operator is ill-conditioned, as the lubrication matrix is); the second
-    // pass returns ||w||^2
-    launch_dots(n, k + 1, V, n, w, s->d_lpart, s->d_lh, s->d_counters, s->st);
-    launch_axpy_dots(n, k + 1, V, n, s->d_lh, w, 1, s->d_lpart, s->d_lh + s->lan_max + 1, s->d_counters, s->st);
-    HIPCHK(hipMemcpyAsync(s->h_small, s->d_lh + s->lan_max + 1, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  for (int j = 0; j < s->lan_max; ++j) {
+    double* vj = V + size_t(j) * n;
+    apply(vj, w);
+    launch_dots(n, j + 1, V, n, w, s->d_lpart, h1, s->d_counters, s->st);
+    launch_axpy_dots(n, j + 1, V, n, h1, w, 0, s->d_lpart, h2, s->d_counters, s->st);
+    launch_axpy_dots(n, j + 1, V, n, h2, w, 1, s->d_lpart, nrm2, s->d_counters, s->st);
+    launch_lanczos_coef(j, h1, h2, nrm2, alpha, beta, scal, s->st);
+    if (j + 1 < s->lan_max) launch_scale_dev(n, scal, w, V + size_t(j + 1) * n, s->st);
+    if ((j + 1) % kCheck != 0 && j + 1 != s->lan_max) continue;
+    HIPCHK(hipMemcpyAsync(s->h_small, alpha, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(s->h_small + L, beta, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    const double b = std::sqrt(std::max(s->h_small[0], 0.0));
-    al.push_back(a);
-    std::vector<double> cur = tridiag_sqrt_e1(al, be);
+    // the first breakdown ends the basis
+    k = j + 1;
+    for (int i = 0; i <= j; ++i)
+      if (s->h_small[L + i] <= 1e-14 * std::fabs(s->h_small[i])) {
+        k = i + 1;
+        break;
+      }
+    std::vector<double> a(s->h_small, s->h_small + k), b(s->h_small + L, s->h_small + L + std::max(k - 1, 0));
+    std::vector<double> cur = tridiag_sqrt_e1(a, b);
     double diff = 0, nrm = 0;
     for (size_t i = 0; i < cur.size(); ++i) {
       const double d = cur[i] - (i < prev.size() ? prev[i] : 0.0);
@@ -1056,12 +1070,7 @@ int lanczos_sqrt(fsd_system* s, size_t n, Apply&& apply, const double* z, double
       nrm += cur[i] * cur[i];
     }
     prev.swap(cur);
-    if ((k > 0 && diff <= tol * tol * nrm) || b <= 1e-14 * std::fabs(a) || k + 1 == s->lan_max) {
-      ++k;
-      break;
-    }
-    be.push_back(b);
-    launch_scale(n, 1.0 / b, w, V + size_t(k + 1) * n, s->st);
+    if (diff <= tol * tol * nrm || k <= j || j + 1 == s->lan_max) break;
   }
   std::vector<double> c(prev.size());
   for (size_t i = 0; i < c.size(); ++i) c[i] = b0 * prev[i];
@@ -1557,6 +1566,7 @@ void fsd_default_params(fsd_params* p) {
   p->precision = FSD_FP64;
   p->lanczos_tol = 1e-4;
   p->seed = 2607251610ull;
+  p->lanczos_maxit = 100;
 }
 
 fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out) {
@@ -1564,12 +1574,14 @@ fsd_status fsd_create(const fsd_params* p, void* hip_stream, fsd_system** out) {
   if (!(p->eta > 0) || !(p->radius > 0) || !(p->ewald_tol > 0 && p->ewald_tol < 1) || !(p->gmres_tol > 0) ||
       p->gmres_restart < 1 || p->gmres_restart > 200 || p->gmres_maxit < 1 || p->grid < 0 || p->support < 0 ||
       p->support > 21 || p->r_lub < 0 || (p->precision != FSD_FP64 && p->precision != FSD_MIXED) ||
-      !(p->lanczos_tol > 0 && p->lanczos_tol < 1) || p->kT < 0)
+      !(p->lanczos_tol > 0 && p->lanczos_tol < 1) || p->kT < 0 || p->lanczos_maxit < 1 ||
+      p->lanczos_maxit > 2000)
     return FSD_EINVAL;
   fsd_system* s = new (std::nothrow) fsd_system;
   if (!s) return FSD_ENOMEM;
   s->p = *p;
   s->m = p->gmres_restart;
+  s->lan_max = p->lanczos_maxit;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return FSD_EDEVICE;
@@ -1687,7 +1699,9 @@ fsd_status fsd_init_aggregates(fsd_system* s, int32_t n_agg, const int32_t* off,
     s->d_h = dalloc<double>(o, 2 * size_t(s->m + 1) + 16);
     s->d_part = dalloc<double>(o, std::max(size_t(s->m + 2) * 1024, size_t(96) * cgs_blocks(n)));
     s->d_U = dalloc<double>(o, 6 * size_t(n_agg));
-    HIPCHK(hipHostMalloc((void**)&s->h_small, sizeof(double) * (2 * size_t(s->m + 1) + 8)));
+    // small read-backs: GMRES columns, and the Lanczos alpha and beta (lan_max + 2 each)
+    HIPCHK(hipHostMalloc((void**)&s->h_small,
+                         sizeof(double) * std::max(2 * size_t(s->m + 1) + 8, 2 * size_t(s->lan_max + 2))));
     HIPCHK(hipHostMalloc((void**)&s->h_ctl, sizeof(GmresCtl)));
     s->d_ctl = reinterpret_cast<GmresCtl*>(dalloc<double>(o, (sizeof(GmresCtl) + 7) / 8));
     s->d_H = dalloc<double>(o, size_t(s->m + 1) * s->m);
@@ -1884,6 +1898,55 @@ fsd_status fsd_get_velocities(const fsd_system* cs, double* U) {
   });
 }
 
+fsd_status fsd_get_stresslets(fsd_system* s, double* S_agg, double* S_mean) {
+  fsd_status c = check_ready(s);
+  if (c) return c;
+  if (!S_agg && !S_mean) return fail(s, FSD_EINVAL, "fsd_get_stresslets: no output");
+  if (!s->solved || !s->prepared || s->sv.rhs_kind != 0)
+    return fail(s, FSD_ESTATE, "fsd_get_stresslets: needs a completed solve at the current configuration");
+  return guarded(s, [&]() -> fsd_status {
+    const int nb = s->nb, na = s->na;
+    const size_t nb6 = 6 * size_t(nb);
+    if (!s->d_fst) {
+      s->d_fst = dalloc<double>(s->owned, 3 * size_t(nb));
+      s->d_wst = dalloc<double>(s->owned, 3 * size_t(nb));
+      s->d_sst = dalloc<double>(s->owned, 9 * size_t(na));
+    }
+    // the near-field force on the beads at the solved velocities:
+    // -sum_k R_pair (w_i - w_k) - (the strain term), w the rigid-body bead velocities
+    const bool lub = s->p.r_lub > 0 && s->nlub > 0;
+    launch_zero(s->d_fst, sizeof(double) * 3 * nb, s->st);
+    if (lub) {
+      launch_bead_rigid_vel(nb, s->d_body, s->d_r4, s->d_x + nb6, s->d_wst, s->st);
+      launch_lub_apply(nb, s->d_lrow, s->d_lcol, s->d_lcoef, s->d_wst, s->d_fst, s->st);
+      launch_lub_strain(nb, s->d_pos4, s->d_r4, s->L, s->gam(), s->d_lrow, s->d_lcol, s->d_lcoef, s->d_E, s->d_wst,
+                        s->st);
+      launch_axpby(3 * size_t(nb), -1.0, s->d_wst, 1.0, s->d_fst, s->st);
+    }
+    // conservative pair forces (the kernel returns their negative) and the near-field
+    // Brownian force of this solve
+    if (s->pair_forces) {
+      launch_pair_forces(nb, s->d_pos4, s->d_body, s->d_nrow, s->d_ncol, s->pf, s->d_wst, 0, s->st);
+      launch_axpby(3 * size_t(nb), -1.0, s->d_wst, 1.0, s->d_fst, s->st);
+    }
+    if (s->p.kT > 0 && s->d_fb) launch_axpby(3 * size_t(nb), 1.0, s->d_fb, 1.0, s->d_fst, s->st);
+    launch_stresslets(na, s->d_offsets, s->d_r4, s->d_x, s->d_fst, s->d_sst, s->st);
+    std::vector<double> S(9 * size_t(na));
+    HIPCHK(hipMemcpyAsync(S.data(), s->d_sst, sizeof(double) * S.size(), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (S_agg) std::copy(S.begin(), S.end(), S_agg);
+    if (S_mean) {
+      const double V = s->L * s->L * s->L;
+      for (int k = 0; k < 9; ++k) {
+        double t = 0;
+        for (int j = 0; j < na; ++j) t += S[9 * size_t(j) + k];
+        S_mean[k] = t / V;
+      }
+    }
+    return FSD_OK;
+  });
+}
+
 fsd_status fsd_get_info(const fsd_system* cs, fsd_info* info) {
   fsd_system* s = const_cast<fsd_system*>(cs);
   fsd_status c = check_ready(s);
@@ -1923,7 +1986,14 @@ size_t fsd_estimate_bytes(const fsd_params* p, int32_t nb, int32_t na, double L)
   const int m = p->gmres_restart;
   double bytes = 48.0 * double(N) * N * N + 4.0 * nnz + 44.0 * nl + 8.0 * n * (m + 9) + 200.0 * nb + 400.0 * na +
                  8.0 * (m + 2) * 1024 + 8.0 * 8 * 4100 + (1 << 20);
-  if (p->kT > 0) bytes += 8.0 * nb * (6.0 * 101 + 24) + 8.0 * 102 * 1024;  // Lanczos basis, Brownian vectors
+  if (p->kT > 0) {  // Lanczos basis and partials, Brownian vectors
+    const double lm = p->lanczos_maxit > 0 ? p->lanczos_maxit : 100;
+    bytes += 8.0 * nb * (6.0 * (lm + 1) + 24) + 8.0 * (lm + 2) * 1024;
+  }
+  // spreading plan: 3P weights per bead (FP64, FP32 and a staging copy) and up to 27 block
+  // slots per bead (keys and values, sorted copies and the sort's temporary storage)
+  const int P = p->support > 0 ? p->support : int(std::ceil(2.0 / M_PI * std::log(1.0 / p->ewald_tol))) + 2;
+  bytes += double(nb) * (20.0 * 3 * P + 27.0 * 32.0);
   return size_t(bytes);
 }
 
@@ -2506,6 +2576,10 @@ struct fsd_batch {
   size_t shm[BK_COUNT] = {0};
   std::vector<fsd_system*> cyc;  // the systems of the tables, in table order
   std::vector<char> active;      // cyc[k] still iterating in the current cycle (timing only)
+  // LDS per workgroup allowed to the z/y line passes and to the x+Green pass (0: no cap).
+  // A multi-system launch reserves the largest system's LDS for every workgroup, so one
+  // system's wide tile lowers the occupancy of all; fsd_batch_autotune_tiles measures these.
+  size_t lds_cap[2] = {0, 0};
   // event timing of the multi-system launches (fsd_batch_set_timing)
   struct Pend {
     int cls;
@@ -2536,10 +2610,7 @@ size_t system_bytes(const fsd_system* s) {
 // One solve (and optionally an Euler step) for every admitted system.  Each system
 // runs on its own stream; the host advances their state machines round-robin, so
 // while it waits on one system the others keep the GPU busy.
-fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
-  std::vector<fsd_system*> act;
-  for (auto* s : b->slot)
-    if (s) act.push_back(s);
+fsd_status batch_run_streams(fsd_batch* b, const std::vector<fsd_system*>& act, double dt, bool integrate) {
   fsd_status worst = FSD_OK;
   std::vector<char> done(act.size(), 0);
   for (size_t k = 0; k < act.size(); ++k) {
@@ -2601,11 +2672,7 @@ fsd_status batch_run_streams(fsd_batch* b, double dt, bool integrate) {
         }
     }
   }
-  for (size_t q = 0; q < b->slot.size(); ++q)
-    if (b->slot[q]) {
-      (void)hipStreamSynchronize(b->slot[q]->st);
-      b->last[q] = info_of(b->slot[q]);
-    }
+  for (auto* s : act) (void)hipStreamSynchronize(s->st);
   return worst;
 }
 }  // namespace
@@ -2677,7 +2744,15 @@ bool fusable(const std::vector<fsd_system*>& act) {
 void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
   const int ns = int(cyc.size());
   std::vector<BatchDesc> desc(ns);
-  for (int k = 0; k < ns; ++k) desc[k] = make_desc(cyc[k], prec);
+  for (int k = 0; k < ns; ++k) {
+    BatchDesc& d = desc[k];
+    d = make_desc(cyc[k], prec);
+    // narrower tiles (fewer lines, fewer row pairs) within the batch's LDS caps
+    if (b->lds_cap[0])
+      while (d.bl > 1 && batch_shm(d, BK_FFT_OUTER, prec) > b->lds_cap[0]) d.bl /= 2;
+    if (b->lds_cap[1])
+      while (d.bg > 1 && batch_shm(d, BK_FFT_GREEN, prec) > b->lds_cap[1]) --d.bg;
+  }
   std::vector<int> off(size_t(BK_COUNT) * (ns + 1), 0);
   int total[BK_COUNT];
   size_t shm[BK_COUNT];
@@ -2827,11 +2902,55 @@ void batch_segment(fsd_batch* b, int j0, int cnt) {
   HIPCHK(hipGetLastError());
 }
 
+// Advances every solve in sys to its end, each on its own stream with its captured GMRES
+// segments, polling whichever stream has drained (a failure ends only that solve).
+void advance_solves(const std::vector<fsd_system*>& sys) {
+  std::vector<char> live(sys.size(), 1);
+  size_t left = sys.size();
+  while (left > 0) {
+    bool progressed = false;
+    for (size_t k = 0; k < sys.size(); ++k) {
+      if (!live[k]) continue;
+      fsd_system* s = sys[k];
+      const hipError_t q = hipStreamQuery(s->st);
+      if (q == hipErrorNotReady) continue;
+      progressed = true;
+      bool more = false;
+      const fsd_status r = guarded(s, [&]() -> fsd_status {
+        HIPCHK(q);
+        more = solve_advance(s);
+        return FSD_OK;
+      });
+      if (r != FSD_OK) {
+        s->sv.status = r;
+        more = false;
+      }
+      if (!more) {
+        live[k] = 0;
+        --left;
+      }
+    }
+    if (!progressed)
+      for (size_t k = 0; k < sys.size(); ++k)
+        if (live[k]) {
+          (void)hipStreamSynchronize(sys[k]->st);
+          break;
+        }
+  }
+}
+
+// at most this many systems still iterating: they leave the lock step and finish alone
+constexpr size_t kSoloTail = 4;
+
 // Lock-step solve of all admitted systems with multi-system launches.  Preparation,
 // right-hand sides and GMRES cycle starts/ends run per system on the systems' own
 // streams (they overlap); the Arnoldi steps of all systems whose cycle is running are
 // one launch per kernel on the batch stream.  Systems that converge drop out at the
-// next cycle boundary; the others restart together (equal restart length).
+// next cycle boundary; the others restart together (equal restart length).  Once no
+// more than kSoloTail systems are left after a cycle (the slow tail of an uneven
+// batch), they finish on their own streams with captured segments, where a launch over a
+// few small systems would cost its launch latency; the timing pass keeps them in the
+// lock step.
 fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, double dt, bool integrate) {
   using SS = fsd_system::SolveState;
   const size_t na = act.size();
@@ -2865,6 +2984,7 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
   }
   const int S = b->timing ? 1 : std::max(1, std::min(act[0]->batch, act[0]->m));
   const int prec = act[0]->p.precision == FSD_MIXED ? 1 : 0;
+  int cycles = 0;  // lock-step cycles run
   while (true) {
     std::vector<fsd_system*> cyc;
     for (size_t k = 0; k < na; ++k) {  // cycle starts drained: finish or join the cycle
@@ -2895,6 +3015,11 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
         done[k] = 1;
     }
     if (cyc.empty()) break;
+    if (!b->timing && cycles > 0 && cyc.size() <= kSoloTail) {
+      advance_solves(cyc);
+      break;
+    }
+    ++cycles;
     fsd_status r = guarded(cyc[0], [&]() -> fsd_status {
       set_tables(b, cyc, prec);
       for (int j0 = 0;; j0 += S) {
@@ -2946,15 +3071,32 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
 
 // one solve (and optionally an Euler step) for every admitted system: multi-system
 // launches when the systems allow them, otherwise one stream per system
-fsd_status batch_run(fsd_batch* b, double dt, bool integrate) {
-  std::vector<fsd_system*> act;
-  for (auto* s : b->slot)
-    if (s) act.push_back(s);
-  if (!b->fused || !fusable(act)) return batch_run_streams(b, dt, integrate);
-  const fsd_status r = batch_run_fused(b, act, dt, integrate);
+// counts (per slot, may be null: one each): the solves (and steps) each slot makes in this
+// call.  Rounds of multi-system launches (or streams) run until every slot has made its
+// count; a slot whose solve fails stops there.
+fsd_status batch_run(fsd_batch* b, double dt, bool integrate, const int* counts = nullptr) {
+  std::vector<int> left(b->slot.size(), 0);
   for (size_t q = 0; q < b->slot.size(); ++q)
-    if (b->slot[q]) b->last[q] = info_of(b->slot[q]);
-  return r;
+    if (b->slot[q]) left[q] = counts ? std::max(counts[q], 0) : 1;
+  fsd_status worst = FSD_OK;
+  while (true) {
+    std::vector<fsd_system*> act;
+    std::vector<size_t> qs;
+    for (size_t q = 0; q < b->slot.size(); ++q)
+      if (b->slot[q] && left[q] > 0) {
+        act.push_back(b->slot[q]);
+        qs.push_back(q);
+      }
+    if (act.empty()) break;
+    const fsd_status r = (b->fused && fusable(act)) ? batch_run_fused(b, act, dt, integrate)
+                                                    : batch_run_streams(b, act, dt, integrate);
+    for (size_t k = 0; k < act.size(); ++k) {
+      b->last[qs[k]] = info_of(act[k]);
+      left[qs[k]] = act[k]->sv.status == FSD_OK ? left[qs[k]] - 1 : 0;
+    }
+    if (worst == FSD_OK) worst = r;
+  }
+  return worst;
 }
 }  // namespace
 
@@ -3020,6 +3162,13 @@ fsd_status fsd_batch_solve(fsd_batch* b) {
 fsd_status fsd_batch_step(fsd_batch* b, double dt) {
   if (!b || !(dt > 0)) return FSD_EINVAL;
   return batch_run(b, dt, true);
+}
+
+fsd_status fsd_batch_step_counts(fsd_batch* b, double dt, const int* n_steps) {
+  if (!b || !(dt > 0) || !n_steps) return FSD_EINVAL;
+  for (size_t q = 0; q < b->slot.size(); ++q)
+    if (n_steps[q] < 0) return FSD_EINVAL;
+  return batch_run(b, dt, true, n_steps);
 }
 
 fsd_status fsd_batch_slot_info(const fsd_batch* b, int slot, fsd_solve_info* info) {
@@ -3143,6 +3292,39 @@ fsd_status fsd_batch_time_kernel(fsd_batch* b, int timer, int reps, double* avg_
     }
     return FSD_OK;
   });
+}
+
+fsd_status fsd_batch_set_lds_caps(fsd_batch* b, size_t lines_lds, size_t green_lds) {
+  if (!b) return FSD_EINVAL;
+  b->lds_cap[0] = lines_lds;
+  b->lds_cap[1] = green_lds;
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_autotune_tiles(fsd_batch* b, int reps, size_t* lines_lds, size_t* green_lds) {
+  if (!b || reps < 1) return FSD_EINVAL;
+  constexpr size_t kCaps[] = {16u << 10, 24u << 10, 32u << 10, 40u << 10, 48u << 10, 0};
+  const int timers[2] = {FSD_TIMER_FFT_Y, FSD_TIMER_GREEN};
+  const size_t keep[2] = {b->lds_cap[0], b->lds_cap[1]};
+  for (int w = 0; w < 2; ++w) {
+    double best = 1e300;
+    size_t best_cap = 0;
+    for (size_t cap : kCaps) {
+      b->lds_cap[w] = cap;
+      double ms = 0;
+      const fsd_status r = fsd_batch_time_kernel(b, timers[w], reps, &ms, nullptr);
+      if (r != FSD_OK) {
+        b->lds_cap[0] = keep[0];
+        b->lds_cap[1] = keep[1];
+        return r;
+      }
+      if (ms < best) best = ms, best_cap = cap;
+    }
+    b->lds_cap[w] = best_cap;
+  }
+  if (lines_lds) *lines_lds = b->lds_cap[0];
+  if (green_lds) *green_lds = b->lds_cap[1];
+  return FSD_OK;
 }
 
 void fsd_batch_destroy(fsd_batch* b) { delete b; }

@@ -58,6 +58,14 @@ struct SpreadPlan {
   int nb = 0, BS = 0, nbin = 0, K = 0, P = 0;
   int *keys_in = nullptr, *keys_out = nullptr, *vals_in = nullptr, *perm = nullptr;
   int *bin_start = nullptr, *bin_end = nullptr;
+  // 8^3 blocks: for every block, the sorted indices of exactly the beads whose support
+  // reaches it (cand[blk_start[b] .. blk_end[b]), in bead order); each bead files kc^3 slots
+  // (its blocks, then sentinels) that one stable sort groups by block
+  int kc = 0;
+  int *blk_start = nullptr, *blk_end = nullptr, *pk_in = nullptr, *pk_out = nullptr, *pv_in = nullptr,
+      *cand = nullptr;
+  void* ptemp = nullptr;
+  size_t ptemp_bytes = 0;
   int4* starts = nullptr;   // (sx, sy, sz, bin) per bead, sorted order
   double* weights = nullptr;  // 3P weights per bead, sorted order
   float* weights32 = nullptr;  // the same in FP32
@@ -570,6 +578,20 @@ SpreadPlan* spread_plan_create(int nb, int N, int P) {
   hipcub::DeviceRadixSort::SortPairs(nullptr, b, sp->keys_in, sp->keys_out, sp->vals_in, sp->perm, nb);
   sp->temp_bytes = b;
   ok = ok && hipMalloc(&sp->temp, b) == hipSuccess;
+  if (ok && BS == 8) {
+    sp->kc = std::min(sp->K, sp->nbin);
+    const size_t slots = size_t(nb) * sp->kc * sp->kc * sp->kc;
+    ok = hipMalloc(&sp->blk_start, sizeof(int) * nbins) == hipSuccess &&
+         hipMalloc(&sp->blk_end, sizeof(int) * nbins) == hipSuccess &&
+         hipMalloc(&sp->pk_in, sizeof(int) * slots) == hipSuccess &&
+         hipMalloc(&sp->pk_out, sizeof(int) * slots) == hipSuccess &&
+         hipMalloc(&sp->pv_in, sizeof(int) * slots) == hipSuccess &&
+         hipMalloc(&sp->cand, sizeof(int) * slots) == hipSuccess;
+    size_t pb = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, pb, sp->pk_in, sp->pk_out, sp->pv_in, sp->cand, int(slots));
+    sp->ptemp_bytes = pb;
+    ok = ok && hipMalloc(&sp->ptemp, pb) == hipSuccess;
+  }
   if (!ok) {
     spread_plan_destroy(sp);
     return nullptr;
@@ -591,6 +613,13 @@ void spread_plan_destroy(SpreadPlan* sp) {
   (void)hipFree(sp->weights32);
   (void)hipFree(sp->wtmp);
   (void)hipFree(sp->temp);
+  (void)hipFree(sp->blk_start);
+  (void)hipFree(sp->blk_end);
+  (void)hipFree(sp->pk_in);
+  (void)hipFree(sp->pk_out);
+  (void)hipFree(sp->pv_in);
+  (void)hipFree(sp->cand);
+  (void)hipFree(sp->ptemp);
   delete sp;
 }
 
@@ -638,6 +667,42 @@ __global__ void k_bin_bounds(int nb, const int* __restrict__ keys, int* start, i
   if (k == nb - 1 || keys[k + 1] != c) end[c] = k + 1;
 }
 
+// the kc^3 slots of sorted bead k: the blocks its support reaches (their index as the key,
+// k as the value), the remaining slots a sentinel key past the last block
+__global__ void k_block_slots(int nb, const int4* __restrict__ starts, int P, int nbin, int kc,
+                              int* __restrict__ keys, int* __restrict__ vals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb) return;
+  const int4 s = starts[k];
+  const int cnt[3] = {min(((s.x & 7) + P - 1) / 8 + 1, nbin), min(((s.y & 7) + P - 1) / 8 + 1, nbin),
+                      min(((s.z & 7) + P - 1) / 8 + 1, nbin)};
+  const int b0[3] = {s.x >> 3, s.y >> 3, s.z >> 3};
+  const int per = kc * kc * kc, sentinel = nbin * nbin * nbin;
+  int q = 0;
+  for (int jz = 0; jz < cnt[2]; ++jz)
+    for (int jy = 0; jy < cnt[1]; ++jy)
+      for (int jx = 0; jx < cnt[0]; ++jx) {
+        const int bz = (b0[2] + jz) % nbin, by = (b0[1] + jy) % nbin, bx = (b0[0] + jx) % nbin;
+        keys[size_t(k) * per + q] = (bz * nbin + by) * nbin + bx;
+        vals[size_t(k) * per + q] = k;
+        ++q;
+      }
+  for (; q < per; ++q) {
+    keys[size_t(k) * per + q] = sentinel;
+    vals[size_t(k) * per + q] = k;
+  }
+}
+
+// list bounds per block from the sorted slot keys (sentinels ignored)
+__global__ void k_block_bounds(int n, int nblk, const int* __restrict__ keys, int* start, int* end) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int c = keys[p];
+  if (c >= nblk) return;
+  if (p == 0 || keys[p - 1] != c) start[c] = p;
+  if (p == n - 1 || keys[p + 1] != c) end[c] = p + 1;
+}
+
 hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WaveParams& wp, hipStream_t st) {
   const int nb = sp->nb;
   double* w = sp->wtmp;
@@ -656,6 +721,19 @@ hipError_t spread_plan_update(SpreadPlan* sp, const double* pos4, const WavePara
   k_bead_permute<<<nblocks((long long)nb * 3 * sp->P), kThreads, 0, st>>>(nb, 3 * sp->P, sp->perm, w, sp->stmp,
                                                                          sp->weights,
                                                    sp->weights32, sp->starts);
+  if (sp->BS == 8) {  // the candidate list of every block
+    const int kc = sp->kc, slots = nb * kc * kc * kc;
+    k_block_slots<<<nblocks(nb), kThreads, 0, st>>>(nb, sp->starts, sp->P, sp->nbin, kc, sp->pk_in, sp->pv_in);
+    int pbits = 1;
+    while ((1 << pbits) <= nbins) ++pbits;  // the sentinel nbins included
+    size_t pb = sp->ptemp_bytes;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(sp->ptemp, pb, sp->pk_in, sp->pk_out, sp->pv_in, sp->cand, slots, 0,
+                                                pbits, st)) != hipSuccess)
+      return e;
+    if ((e = hipMemsetAsync(sp->blk_start, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(sp->blk_end, 0, sizeof(int) * nbins, st)) != hipSuccess) return e;
+    k_block_bounds<<<nblocks(slots), kThreads, 0, st>>>(slots, nbins, sp->pk_out, sp->blk_start, sp->blk_end);
+  }
   return hipGetLastError();
 }
 
@@ -777,22 +855,22 @@ __global__ __launch_bounds__(BS* BS* BS) void k_spread_gather(const int* __restr
 
 // Gather spreading on 8^3 blocks with the candidates split among the four wavefronts:
 // lane (x, y) owns one grid column and all 8 planes of the block; wavefront w takes
-// every fourth staged candidate, skips it as a whole when its support misses the block
-// (a uniform test), and otherwise forms the x-y weight once per lane and reuses it over
-// the planes.  The four partial blocks are added through LDS in a fixed order
-// (deterministic).  Candidates are staged in LDS in chunks of C (dynamic shared
-// memory): the sorted bead index, then the weights with independent loads in flight,
-// then start cells and force moments.
+// every fourth candidate of the block's list (the beads whose support reaches it, built
+// with the plan) and forms the x-y weight once per lane, reusing it over the planes.  The
+// four partial blocks are added through LDS in a fixed order (deterministic).  Candidates
+// are staged in LDS in chunks of C (dynamic shared memory): the sorted bead index, then
+// the weights with independent loads in flight, then start cells and force moments.
 constexpr int kSplitRedBytes64 = 2 * 48 * 64 * 8;  // LDS of the two-step reduction (FP64)
 
 template <typename R>
-__device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_start,
-                                                               const int* __restrict__ bin_end,
+__device__ __forceinline__ void spread_split_body(const int* __restrict__ blk_start,
+                                                               const int* __restrict__ blk_end,
+                                                               const int* __restrict__ cand,
                                                                const int* __restrict__ perm,
                                                                const int4* __restrict__ starts,
                                                                const R* __restrict__ weights,
                                                                const double* __restrict__ lam, WaveParams wp,
-                                                               int nbin, int K, int C, R* __restrict__ grid,
+                                                               int nbin, int C, R* __restrict__ grid,
                                                                size_t cs, const int* __restrict__ skip, int bx_, int by_, int gx_) {
   if (skip && *skip) return;
   constexpr int BS = 8, NT = 256, ZW = 8, NW = NT / 64;
@@ -802,56 +880,12 @@ __device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_st
   R* sh_l = sh_w + size_t(C) * P3;                           // C * 6
   int4* sh_s = reinterpret_cast<int4*>(sh_l + size_t(C) * 6); // C
   int* sh_k = reinterpret_cast<int*>(sh_s + C);              // C
-  __shared__ int rb0[2 * 8 * 8], rlen[2 * 8 * 8], roff[2 * 8 * 8 + 1];
   const int bl = xcd_remap(bx_, nbin * nbin * nbin);  // each XCD takes a contiguous slab of blocks
   const int bx = bl % nbin, by = (bl / nbin) % nbin, bz = bl / (nbin * nbin);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
   const int mx = x0 + (lane & 7), my = y0 + (lane >> 3);
-  // candidate beads: per (kz, ky) one or two contiguous runs of the sorted bead array
-  // (bins bx-K+1 .. bx along x, split where they wrap); thread r computes run r
-  const int xb0 = bx - K + 1;
-  const int nparts = xb0 >= 0 ? 1 : 2;
-  const int nruns = K * K * nparts;
-  for (int rr = t; rr < nruns; rr += NT) {
-    const int part = rr % nparts, ky = (rr / nparts) % K, kz = rr / (nparts * K);
-    const int cz = (bz - kz + nbin) % nbin, cy = (by - ky + nbin) % nbin;
-    int lo, hi;
-    if (xb0 >= 0) {
-      lo = xb0;
-      hi = bx;
-    } else if (part == 0) {
-      lo = 0;
-      hi = bx;
-    } else {
-      lo = xb0 + nbin;
-      hi = nbin - 1;
-    }
-    const int row = (cz * nbin + cy) * nbin;
-    int b0 = 0, b1 = 0;
-    bool any = false;
-    for (int c = lo; c <= hi; ++c) {
-      const int e0 = bin_start[row + c], e1 = bin_end[row + c];
-      if (e1 > e0) {
-        if (!any) b0 = e0;
-        b1 = e1;
-        any = true;
-      }
-    }
-    rb0[rr] = b0;
-    rlen[rr] = any ? b1 - b0 : 0;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int r = 0; r < nruns; ++r) {
-      roff[r] = acc;
-      acc += rlen[r];
-    }
-    roff[nruns] = acc;
-  }
-  __syncthreads();
-  const int total = roff[nruns];
+  const int cb = blk_start[bl], total = blk_end[bl] - cb;
   R a[ZW][6];
 #pragma unroll
   for (int zz = 0; zz < ZW; ++zz)
@@ -860,12 +894,7 @@ __device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_st
   for (int c0 = 0; c0 < total; c0 += C) {
     const int n = min(C, total - c0);
     if (c0 > 0) __syncthreads();
-    for (int c = t; c < n; c += NT) {
-      const int gidx = c0 + c;
-      int r = 0;
-      while (roff[r + 1] <= gidx) ++r;
-      sh_k[c] = rb0[r] + (gidx - roff[r]);
-    }
+    for (int c = t; c < n; c += NT) sh_k[c] = cand[cb + c0 + c];
     __syncthreads();
     const int nw = n * P3;
     for (int q0 = t; q0 < nw; q0 += 4 * NT) {
@@ -874,8 +903,8 @@ __device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_st
       for (int u = 0; u < 4; ++u) {
         const int q = q0 + u * NT;
         if (q < nw) {
-          const int cand = q / P3;
-          v[u] = weights[size_t(sh_k[cand]) * P3 + (q - cand * P3)];
+          const int cq = q / P3;
+          v[u] = weights[size_t(sh_k[cq]) * P3 + (q - cq * P3)];
         }
       }
 #pragma unroll
@@ -963,12 +992,12 @@ __device__ __forceinline__ void spread_split_body(const int* __restrict__ bin_st
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_spread_split(const int* __restrict__ bin_start, const int* __restrict__ bin_end,
-                                                      const int* __restrict__ perm, const int4* __restrict__ starts,
-                                                      const R* __restrict__ weights, const double* __restrict__ lam,
-                                                      WaveParams wp, int nbin, int K, int C, R* __restrict__ grid,
-                                                      size_t cs, const int* __restrict__ skip) {
-  spread_split_body<R>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, blockIdx.x,
+__global__ __launch_bounds__(256) void k_spread_split(const int* __restrict__ blk_start, const int* __restrict__ blk_end,
+                                                      const int* __restrict__ cand, const int* __restrict__ perm,
+                                                      const int4* __restrict__ starts, const R* __restrict__ weights,
+                                                      const double* __restrict__ lam, WaveParams wp, int nbin, int C,
+                                                      R* __restrict__ grid, size_t cs, const int* __restrict__ skip) {
+  spread_split_body<R>(blk_start, blk_end, cand, perm, starts, weights, lam, wp, nbin, C, grid, cs, skip, blockIdx.x,
                        blockIdx.y, gridDim.x);
 }
 
@@ -997,8 +1026,8 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
     const size_t per = sizeof(R) * (3 * size_t(wp.support) + 6) + sizeof(int4) + sizeof(int);
     const int C = int(std::min<size_t>(128, (size_t(60) << 10) / per)) & ~3;  // int4 array stays 16-byte aligned
     const size_t shm = std::max(per * C, size_t(kSplitRedBytes64) / sizeof(double) * sizeof(R));
-    launch_k(k_spread_split<R>, nblk, 256, shm, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts, plan_weights<R>(sp),
-                                              lam, wp, sp->nbin, sp->K, C, grid, cs, skip);
+    launch_k(k_spread_split<R>, nblk, 256, shm, st, sp->blk_start, sp->blk_end, sp->cand, sp->perm, sp->starts,
+             plan_weights<R>(sp), lam, wp, sp->nbin, C, grid, cs, skip);
   }
   else
     launch_k(k_spread_gather<R, 4>, nblk, 64, 0, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts,
@@ -1013,10 +1042,11 @@ void launch_spread_gather(const SpreadPlan* sp, const double* lam, const WavePar
 // block keeps the XCD (block index mod 8) its slab mapping assumes, and they finish early,
 // leaving their slots to the longer spreading blocks.
 template <typename R, int LPR>
-__global__ __launch_bounds__(256) void k_spread_fused(const int* __restrict__ bin_start, const int* __restrict__ bin_end,
-                                                      const int* __restrict__ perm, const int4* __restrict__ starts,
+__global__ __launch_bounds__(256) void k_spread_fused(const int* __restrict__ blk_start, const int* __restrict__ blk_end,
+                                                      const int* __restrict__ cand, const int* __restrict__ perm,
+                                                      const int4* __restrict__ starts,
                                                       const R* __restrict__ weights, const double* __restrict__ lam,
-                                                      WaveParams wp, int nbin, int K, int C, R* __restrict__ grid,
+                                                      WaveParams wp, int nbin, int C, R* __restrict__ grid,
                                                       size_t cs, const R* __restrict__ tab, RealArgs ra, RigidArgs ga,
                                                       int na_blk, int nr_blk, const int* __restrict__ skip) {
   int b = blockIdx.x;
@@ -1029,7 +1059,8 @@ __global__ __launch_bounds__(256) void k_spread_fused(const int* __restrict__ bi
     real_sum_body<R, LPR>(ra.nb, ra.pos, lam, ra.rowptr, ra.col, tab, ra.rp, ra.out, 0, ra.order, skip, b, 0, nr_blk);
     return;
   }
-  spread_split_body<R>(bin_start, bin_end, perm, starts, weights, lam, wp, nbin, K, C, grid, cs, skip, b - nr_blk, 0, 0);
+  spread_split_body<R>(blk_start, blk_end, cand, perm, starts, weights, lam, wp, nbin, C, grid, cs, skip, b - nr_blk, 0,
+                       0);
 }
 
 bool spread_fuses(const SpreadPlan* sp) { return sp && sp->BS == 8; }
@@ -1046,8 +1077,8 @@ void launch_spread_fused(const SpreadPlan* sp, const double* lam, const WavePara
   const int na_blk = pad8((ga.na + 3) / 4), nr_blk = pad8(((long long)ra.nb * lpr + 255) / 256);
   const int total = na_blk + nr_blk + nblk;
 #define FSD_FUSED(L_)                                                                                       \
-  launch_k(k_spread_fused<R, L_>, total, 256, shm, st, sp->bin_start, sp->bin_end, sp->perm, sp->starts,       \
-           plan_weights<R>(sp), lam, wp, sp->nbin, sp->K, C, grid, cs, table, ra, ga, na_blk, nr_blk, skip)
+  launch_k(k_spread_fused<R, L_>, total, 256, shm, st, sp->blk_start, sp->blk_end, sp->cand, sp->perm,        \
+           sp->starts, plan_weights<R>(sp), lam, wp, sp->nbin, C, grid, cs, table, ra, ga, na_blk, nr_blk, skip)
   switch (lpr) {
     case 1: FSD_FUSED(1); break;
     case 2: FSD_FUSED(2); break;
@@ -1174,11 +1205,11 @@ __device__ __forceinline__ void butterfly(const T* li, T* lo, const T* tw, int b
   }
 }
 
-// Stockham stages on `nl` lines of length N held in LDS (`in`, scratch `out`);
-// returns the buffer holding the result.  The radices come from the plan's packed code
-// (4 bits per stage), so the stage loop indexes no array.
+// Stockham stages on `nl` lines of length N held in LDS `ls` elements apart (`in`, scratch
+// `out`); returns the buffer holding the result.  The radices come from the plan's packed
+// code (4 bits per stage), so the stage loop indexes no array.
 template <typename T, typename R>
-__device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan& plan, int s) {
+__device__ T* stockham(T* in, T* out, const T* tw, int N, int ls, int nl, const FftPlan& plan, int s) {
   int Ns = 1;
   const unsigned long long code = plan.rcode;
   for (int stg = 0; stg < plan.nstage; ++stg) {
@@ -1190,8 +1221,8 @@ __device__ T* stockham(T* in, T* out, const T* tw, int N, int nl, const FftPlan&
       int l, b, j, k;
       dbf.divmod(t, l, b);
       dns.divmod(b, j, k);
-      const T* li = in + l * N;
-      T* lo = out + l * N;
+      const T* li = in + l * ls;
+      T* lo = out + l * ls;
       const int od = j * Ns * Rd + k;
       if (Rd == 4)
         butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
@@ -1219,9 +1250,10 @@ __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t c
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int N = plan.n;
+  const int S = fft_line_stride(N, B, int(sizeof(T)));
   T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + B * N;
-  T* tw = buf1 + B * N;
+  T* buf1 = buf0 + B * S;
+  T* tw = buf1 + B * S;
   T* base = reinterpret_cast<T*>(data + blockIdx.y * cs);
   const int line0 = blockIdx.x * B;
   const T* twg = reinterpret_cast<const T*>(twiddle);
@@ -1247,10 +1279,10 @@ __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t c
       off = ((gl / N) * N + e) * N + (gl % N);
     else
       off = (size_t(e) * N + (gl / N)) * N + (gl % N);
-    buf0[l * N + e] = base[off];
+    buf0[l * S + e] = base[off];
   }
   __syncthreads();
-  const T* in = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign > 0 ? 1 : -1);
+  const T* in = stockham<T, R>(buf0, buf1, tw, N, S, B, plan, sign > 0 ? 1 : -1);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     int l, e;
     if (DIR == 0) {
@@ -1268,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(R* __restrict__ data, size_t c
       off = ((gl / N) * N + e) * N + (gl % N);
     else
       off = (size_t(e) * N + (gl / N)) * N + (gl % N);
-    base[off] = in[l * N + e];
+    base[off] = in[l * S + e];
   }
 }
 
@@ -1286,7 +1318,7 @@ void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, c
   using T = typename C2<R>::T;
   const int N = plan.n;
   const int B = lines_per_block(N);
-  const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
+  const size_t shm = sizeof(T) * (2 * size_t(B) * fft_line_stride(N, B, int(sizeof(T))) + N);
   dim3 g(N * N / B, ncomp);
   if (pass < 0 || pass == 0) k_fft_pass<R, 0><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
   if (pass < 0 || pass == 1) k_fft_pass<R, 1><<<g, kThreads, shm, st>>>(grid, comp_stride, plan, twiddle, sign, B, skip);
@@ -1294,6 +1326,26 @@ void launch_fft3d(R* grid, int ncomp, size_t comp_stride, const FftPlan& plan, c
 }
 
 namespace {
+// Block-wide copy of `count` elements, t -> store(t, load(t)), with U loads in flight per
+// thread: each thread issues its next U loads before it writes any of them, so one wait
+// covers U memory latencies (a plain strided loop waits once per element).
+template <int U, typename T, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int count, Load&& load, Store&& store) {
+  for (int t0 = threadIdx.x; t0 < count; t0 += U * int(blockDim.x)) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * int(blockDim.x);
+      if (t < count) v[u] = load(t);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * int(blockDim.x);
+      if (t < count) store(t, v[u]);
+    }
+  }
+}
+
 template <typename T>
 __device__ inline void load_twiddles(T* tw, const T* twg, int N, int sign) {
   for (int t = threadIdx.x; t < N; t += blockDim.x) {
@@ -1341,25 +1393,28 @@ __device__ __forceinline__ void fft_lines_body(R* __restrict__ grid, size_t cs, 
   using T = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
   const int N = plan.n;
+  const int S = fft_line_stride(N, B, int(sizeof(T)));
   T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + B * N;
-  T* tw = buf1 + B * N;
+  T* buf1 = buf0 + B * S;
+  T* tw = buf1 + B * S;
   T* base = reinterpret_cast<T*>(grid + by_ * cs);
   const int line0 = bx_ * B;  // line gl = o N + x: B consecutive x of one o (B divides N)
   const int o = line0 / N, x0 = line0 - o * N;
   const int lb = __ffs(B) - 1;  // B is a power of two
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
-  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t & (B - 1), e = t >> lb, x = x0 + l;
-    const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
-    buf0[l * N + e] = base[off];
-  }
+  staged_copy<8, T>(
+      B * N,
+      [&](int t) {
+        const int l = t & (B - 1), e = t >> lb, x = x0 + l;
+        return base[DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x];
+      },
+      [&](int t, const T& v) { buf0[(t & (B - 1)) * S + (t >> lb)] = v; });
   __syncthreads();
-  const T* Y = stockham<T, R>(buf0, buf1, tw, N, B, plan, sign);
+  const T* Y = stockham<T, R>(buf0, buf1, tw, N, S, B, plan, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int l = t & (B - 1), e = t >> lb, x = x0 + l;
     const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
-    base[off] = Y[l * N + e];
+    base[off] = Y[l * S + e];
   }
 }
 
@@ -1403,22 +1458,25 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     return (kz ? N - kz : 0) * N + (ky ? N - ky : 0);
   };
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
-  for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
-    int line, x;
-    dn.divmod(t, line, x);
-    const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
-    const int pn = bx_ * G + g;
-    T v;
-    v.x = 0;
-    v.y = 0;
-    if (pn < npair) {
-      const int r = row_of(pn), rp = partner(r);
-      if (q == 0 || rp != r) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
-    }
-    buf0[line * N + x] = v;
-  }
+  staged_copy<8, T>(
+      NL * N,
+      [&](int t) {
+        int line, x;
+        dn.divmod(t, line, x);
+        const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
+        const int pn = bx_ * G + g;
+        T v;
+        v.x = 0;
+        v.y = 0;
+        if (pn < npair) {
+          const int r = row_of(pn), rp = partner(r);
+          if (q == 0 || rp != r) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
+        }
+        return v;
+      },
+      [&](int t, const T& v) { buf0[t] = v; });
   __syncthreads();
-  T* X = stockham<T, R>(buf0, buf1, tw, N, NL, plan, -1);
+  T* X = stockham<T, R>(buf0, buf1, tw, N, N, NL, plan, -1);
   T* O = (X == buf0) ? buf1 : buf0;
   const double tp = 2.0 * M_PI / wp.L, gam = (!TABLE && wp.gam) ? *wp.gam : 0.0;
   for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
@@ -1515,7 +1573,7 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   __syncthreads();
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t].y = -tw[t].y;
   __syncthreads();
-  const T* Y = stockham<T, R>(O, X, tw, N, NL, plan, +1);
+  const T* Y = stockham<T, R>(O, X, tw, N, N, NL, plan, +1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
     int line, x;
     dn.divmod(t, line, x);
@@ -1539,7 +1597,8 @@ __global__ __launch_bounds__(256) void k_fft_xgreen(R* __restrict__ grid, size_t
 int fft_green_rows(int N) { return N >= 256 ? 1 : N >= 64 ? 2 : 256 / N; }
 
 bool tile_b_fits(int N, int B, int rbytes) {
-  return B >= 1 && (B & (B - 1)) == 0 && N % B == 0 && size_t(2 * rbytes) * (2 * size_t(B) * N + N) <= (size_t(64) << 10);
+  return B >= 1 && (B & (B - 1)) == 0 && N % B == 0 &&
+         size_t(2 * rbytes) * (2 * size_t(B) * fft_line_stride(N, B, 2 * rbytes) + N) <= (size_t(64) << 10);
 }
 
 bool tile_g_fits(int N, int G, int rbytes) {
@@ -1578,7 +1637,7 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
       launch_k(k_fft_xgreen<R, false>, nblk, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
   } else {
     const int B = lines_b_of(wp, sizeof(R));
-    const size_t shm = sizeof(T) * (2 * size_t(B) * N + N);
+    const size_t shm = sizeof(T) * (2 * size_t(B) * fft_line_stride(N, B, int(sizeof(T))) + N);
     dim3 g(N * N / B, 3);
     const int sign = stage < 2 ? -1 : +1;
     if (stage == 0 || stage == 4)
@@ -1635,7 +1694,7 @@ __global__ __launch_bounds__(256) void kb_spread(const BatchDesc* __restrict__ D
   const int s = batch_sys(off, nsys, blockIdx.x);
   const BatchDesc& d = D[s];
   const size_t cs = 2 * size_t(d.wp.n) * d.wp.n * d.wp.n;
-  spread_split_body<R>(d.bin_start, d.bin_end, d.perm, d.starts, pick<R>(d.w64, d.w32), d.z, d.wp, d.nbin, d.K,
+  spread_split_body<R>(d.blk_start, d.blk_end, d.cand, d.perm, d.starts, pick<R>(d.w64, d.w32), d.z, d.wp, d.nbin,
                        d.C, static_cast<R*>(d.grid), cs, &d.ctl->stop, blockIdx.x - off[s], 0, 0);
 }
 
@@ -1675,6 +1734,7 @@ __global__ __launch_bounds__(256) void kb_interp(const BatchDesc* __restrict__ D
 // spreading fields of a batch descriptor (bin_start == nullptr: no gather plan)
 void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d) {
   if (!sp || sp->BS != 8) {
+    d.blk_start = d.blk_end = d.cand = nullptr;
     d.bin_start = d.bin_end = d.perm = nullptr;
     d.starts = nullptr;
     d.w64 = nullptr;
@@ -1684,6 +1744,9 @@ void spread_plan_desc(const SpreadPlan* sp, int prec, BatchDesc& d) {
   }
   d.bin_start = sp->bin_start;
   d.bin_end = sp->bin_end;
+  d.blk_start = sp->blk_start;
+  d.blk_end = sp->blk_end;
+  d.cand = sp->cand;
   d.perm = sp->perm;
   d.starts = sp->starts;
   d.w64 = sp->weights;
@@ -1728,7 +1791,7 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec) {
                       size_t(kSplitRedBytes64) / sizeof(double) * rb);
     case BK_FFT_OUTER:
     case BK_FFT_MID:
-      return tb * (2 * size_t(d.bl) * N + N);
+      return tb * (2 * size_t(d.bl) * fft_line_stride(int(N), d.bl, int(tb)) + N);
     case BK_FFT_GREEN:
       return tb * (12 * size_t(d.bg) * N + N);
     default:

@@ -124,6 +124,51 @@ void launch_lub_apply(int nb, const int* rowptr, const uint32_t* col, const doub
 }
 
 // ------------------------------------------------------------------------------------------
+// constraint stresslets (Eq. `stress_comp`)
+// ------------------------------------------------------------------------------------------
+
+// w_i = U_j + Omega_j x r_i: the translational rigid-body velocity of bead i from the
+// aggregate part V of the solution (relative to the imposed flow)
+__global__ void k_bead_rigid_vel(int nb, const int* __restrict__ body, const double4* __restrict__ r4,
+                                 const double* __restrict__ V, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const double* v = V + 6 * size_t(body[i]);
+  const double4 r = r4[i];
+  w[3 * i] = v[0] + v[4] * r.z - v[5] * r.y;
+  w[3 * i + 1] = v[1] + v[5] * r.x - v[3] * r.z;
+  w[3 * i + 2] = v[2] + v[3] * r.y - v[4] * r.x;
+}
+
+void launch_bead_rigid_vel(int nb, const int* body, const double* r4, const double* V, double* w, hipStream_t st) {
+  k_bead_rigid_vel<<<nblocks(nb), kThreads, 0, st>>>(nb, body, (const double4*)r4, V, w);
+}
+
+// S_j = sum_{i in j} sym(r_i (F_i + f_i)): F the bead force moments (6 per bead, the
+// translational three used), f further forces on the beads (3 per bead, may be null);
+// one thread per aggregate, 9 values each (row-major)
+__global__ void k_stresslets(int na, const int* __restrict__ offsets, const double4* __restrict__ r4,
+                             const double* __restrict__ F, const double* __restrict__ f, double* __restrict__ S) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= na) return;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = offsets[j]; i < offsets[j + 1]; ++i) {
+    const double4 r = r4[i];
+    const double rv[3] = {r.x, r.y, r.z};
+    double fv[3];
+    for (int a = 0; a < 3; ++a) fv[a] = F[6 * size_t(i) + a] + (f ? f[3 * size_t(i) + a] : 0.0);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] += 0.5 * (rv[a] * fv[b] + rv[b] * fv[a]);
+  }
+  for (int k = 0; k < 9; ++k) S[9 * size_t(j) + k] = acc[k];
+}
+
+void launch_stresslets(int na, const int* offsets, const double* r4, const double* F, const double* f, double* S,
+                       hipStream_t st) {
+  k_stresslets<<<nblocks(na, 128), 128, 0, st>>>(na, offsets, (const double4*)r4, F, f, S);
+}
+
+// ------------------------------------------------------------------------------------------
 // right-hand side of Eq. `spm_agg`
 // ------------------------------------------------------------------------------------------
 
@@ -227,6 +272,35 @@ __global__ void k_set_value(double* p, double v) {
 }
 
 void launch_set_value(double* p, double v, hipStream_t st) { k_set_value<<<1, 64, 0, st>>>(p, v); }
+
+// Lanczos step k's coefficients on the device: alpha_k = the two Gram-Schmidt passes'
+// projections on v_k, beta_k = ||w||, scal = 1 / beta_k (0 at a breakdown)
+__global__ void k_lanczos_coef(int k, const double* __restrict__ h1, const double* __restrict__ h2,
+                               const double* __restrict__ nrm2, double* __restrict__ alpha, double* __restrict__ beta,
+                               double* __restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  alpha[k] = h1[k] + h2[k];
+  const double b = sqrt(fmax(nrm2[0], 0.0));
+  beta[k] = b;
+  scal[0] = b > 0 ? 1.0 / b : 0.0;
+}
+
+void launch_lanczos_coef(int k, const double* h1, const double* h2, const double* nrm2, double* alpha, double* beta,
+                         double* scal, hipStream_t st) {
+  k_lanczos_coef<<<1, 64, 0, st>>>(k, h1, h2, nrm2, alpha, beta, scal);
+}
+
+// y = a[0] x, the factor read from device memory
+__global__ void k_scale_dev(size_t n, const double* __restrict__ a, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = a[0] * x[i];
+}
+
+void launch_scale_dev(size_t n, const double* a, const double* x, double* y, hipStream_t st) {
+  k_scale_dev<<<nblocks((long long)n), kThreads, 0, st>>>(n, a, x, y);
+}
 
 void launch_axpby(size_t n, double a, const double* x, double b, double* y, hipStream_t st) {
   k_axpby<<<nblocks((long long)n), kThreads, 0, st>>>(n, a, x, b, y);

@@ -4,10 +4,13 @@ Requests are whole simulations (a suspension and a number of time steps).  The
 engine admits queued requests while the batch has a free slot and the device
 memory estimate of the new system fits the budget and the free device memory;
 admitted systems keep their grids, neighbour lists and factors resident; every
-engine tick advances all active systems by one time step (one batched solve +
-Euler update); finished requests retire and free their slot and memory, and
-queued requests take their place at the next tick.  Latency is measured from a
-request's arrival to the end of its last step.
+engine tick advances every active system by at least one time step (batched
+solves + Euler updates).  A tick is paced by its largest system: a system whose
+estimated size is k times smaller takes up to k steps in the same tick (at most
+max_steps_per_tick), so small requests do not wait on large ones step for step.
+Finished requests retire and free their slot and memory, and queued requests
+take their place at the next tick.  Latency is measured from a request's arrival
+to the end of its last step.
 
 The compute all happens in libfsd (fsd_batch_step); this module only schedules.
 The backend and the clock are injectable so the scheduling logic can be tested
@@ -86,8 +89,12 @@ class LibBackend:
             sysm.close()
         return slot
 
-    def step(self, dt: float) -> Dict[int, int]:
-        self.batch.step(dt)
+    def step(self, dt: float, counts: Optional[Dict[int, int]] = None) -> Dict[int, int]:
+        """One tick: counts[slot] time steps per system (one each when None)."""
+        if counts is None:
+            self.batch.step(dt)
+        else:
+            self.batch.step_counts(dt, counts)
         return {slot: self.batch.info(slot).status for slot in list(self.batch.systems)}
 
     def retire(self, slot: int):
@@ -102,10 +109,12 @@ class LibBackend:
 
 class BatchEngine:
     def __init__(self, backend, max_slots: int, dt: float = 1e-3, clock: Callable[[], float] = time.perf_counter,
-                 mem_budget: Optional[int] = None):
+                 mem_budget: Optional[int] = None, max_steps_per_tick: int = 8):
         self.backend = backend
         self.max_slots = max_slots
         self.dt = dt
+        self.max_steps_per_tick = max(1, int(max_steps_per_tick))
+        self.cost: Dict[int, int] = {}
         self.clock = clock
         self.mem_budget = mem_budget if mem_budget is not None else getattr(backend, "budget", 1 << 62)
         self.queue: Deque[Request] = deque()
@@ -144,13 +153,18 @@ class BatchEngine:
             req.started = self.clock()
             req.n_bead = req.suspension.n_bead
             self.active[slot] = req
+            self.cost[slot] = max(1, need)
 
     def tick(self):
         """Admit what fits, advance every active request by one step, retire the finished."""
         self._admit()
         if not self.active:
             return False
-        status = self.backend.step(self.dt)
+        # the largest system paces the tick; a system k times smaller takes up to k steps
+        ref = max(self.cost[slot] for slot in self.active)
+        counts = {slot: max(1, min(self.max_steps_per_tick, ref // self.cost[slot], req.n_steps - req.steps_done))
+                  for slot, req in self.active.items()}
+        status = self.backend.step(self.dt, counts if self.max_steps_per_tick > 1 else None)
         now = self.clock()
         self.ticks += 1
         for slot, req in list(self.active.items()):
@@ -158,12 +172,13 @@ class BatchEngine:
             if st != 0:
                 req.status = st
             else:
-                req.steps_done += 1
-                self.bead_steps += req.n_bead
+                req.steps_done += counts[slot]
+                self.bead_steps += req.n_bead * counts[slot]
             if st != 0 or req.steps_done >= req.n_steps:
                 req.finished = now
                 req.result = self.backend.retire(slot)
                 del self.active[slot]
+                del self.cost[slot]
                 self.done.append(req)
         return True
 

@@ -42,6 +42,16 @@ def test_traffic_only_for_the_source_it_was_counted_with(tmp_path, monkeypatch):
     assert bench.measured_traffic("missing.md", "k_spread_fused") is None
     src.write_text("// kernel source, changed\n")
     assert bench.measured_traffic("c.md", "k_spread_fused") is None  # counters are stale
+    # a header the summary also lists must be unchanged too
+    src.write_text("// kernel source\n")
+    hdr = csrc / "fsd_impl.hpp"
+    hdr.write_text("// header\n")
+    hsha = hashlib.sha256(hdr.read_bytes()).hexdigest()
+    (tmp_path / "profiles" / "c.md").write_text(
+        f"source k_mobility.hip sha256 {sha}\nsource fsd_impl.hpp sha256 {hsha}\ntraffic k_spread_fused 18012039\n")
+    assert bench.measured_traffic("c.md", "k_spread_fused") == 18012039
+    hdr.write_text("// header, changed\n")
+    assert bench.measured_traffic("c.md", "k_spread_fused") is None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -51,8 +51,33 @@ def test_estimate_bytes_grows_with_size(F):
     assert F.estimate_bytes(p, 0, 1, 10.0) == 0
 
 
-def test_binding_structs_match_header_layout(F):
+def test_binding_structs_match_header_layout(F, tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's size and field
+    offsets (a small C program built against include/fsd.h prints them)."""
     import ctypes
-    # fsd_params: 5 doubles, 2 ints, 4 doubles, 3 ints, double, uint64 (C alignment)
-    assert ctypes.sizeof(F.Params) == 5 * 8 + 2 * 4 + 4 * 8 + 3 * 4 + 4 + 8 + 8
-    assert ctypes.sizeof(F.SolveInfo) == 4 * 4 + 8
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"fsd_params": F.Params, "fsd_solve_info": F.SolveInfo, "fsd_info": F.Info}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fsd.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in ct._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, field, value = line.split()
+        ct = structs[cname]
+        want = ctypes.sizeof(ct) if field == "sizeof" else getattr(ct, field).offset
+        assert int(value) == want, (cname, field, value, want)
+        seen += 1
+    assert seen == sum(len(ct._fields_) + 1 for ct in structs.values())

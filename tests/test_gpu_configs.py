@@ -128,13 +128,18 @@ def test_brownian_request_matches_oracle(F):
     assert xi == 25.0 / s0.L
     psi_r, psi_nf = fsdgen.brownian_noise(s0.n_bead, REQUEST_NOISE_SEED)
     print(f"\n[request {REQUEST_PICK}] {s0.n_bead} beads, sheared lattice", flush=True)
-    s = F.System.from_suspension(s0, lees_edwards=True, xi=xi, lanczos_tol=1e-9, **PARITY)
+    k = int(g["lanczos_steps"])
+    # the near-field root takes exactly k Lanczos steps (the tolerance is below what k steps
+    # reach on the singular lubrication matrix); the real-space root converges well before k
+    s = F.System.from_suspension(s0, lees_edwards=True, xi=xi, lanczos_tol=1e-10, lanczos_maxit=k, **PARITY)
     s.set_brownian(s0.dt)
     grid = s.info().grid
     s.set_noise(psi_w=np.zeros(3 * grid ** 3), psi_r=psi_r, psi_nf=psi_nf)
+    _, _, steps = s.brownian_terms()
+    assert steps[1] == k and steps[0] < k, steps
     U, _, info = s.solve()
     et, er = _errors(U, g["U"])
-    print(f"  grid {grid}, its {info.iterations}, err {et:.2e} {er:.2e}")
+    print(f"  grid {grid}, its {info.iterations}, lanczos {steps}, err {et:.2e} {er:.2e}")
     assert info.rel_residual_fp64 <= 1e-7
     assert et < 1e-5 and er < 1e-5, (et, er)
     s.close()

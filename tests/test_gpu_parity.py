@@ -348,6 +348,40 @@ def test_batch_results_equal_alone(F, precision, fused):
         assert np.abs(X1 - X2).max() < tol and np.abs(q1 - q2).max() < max(tol, 1e-12)
 
 
+def test_batch_lds_caps_keep_results(F):
+    """Narrowed transform tiles in the multi-system launches (LDS caps) and the measured caps
+    leave the FP64 solutions as they are alone (same arithmetic up to summation order)."""
+    systems = _small_uneven()
+    alone = []
+    for s0 in systems:
+        s = F.System.from_suspension(s0, precision=0)
+        s.autotune_tiles(2)  # wide tiles where they are fastest
+        U, _, _ = s.solve()
+        alone.append(U)
+        s.close()
+    live = [F.System.from_suspension(s0, precision=0) for s0 in systems]
+    for s in live:
+        s.autotune_tiles(2)
+    b = F.Batch(1 << 34, 16)
+    slots = [b.admit(s) for s in live]
+    for caps in [(4096, 4096), (16 << 10, 24 << 10), None]:
+        if caps is None:
+            caps = b.autotune_tiles(2)
+            assert all(c in (0, 16 << 10, 24 << 10, 32 << 10, 40 << 10, 48 << 10) for c in caps), caps
+        else:
+            b.set_lds_caps(*caps)
+        for s in live:
+            s.set_warm_start(0)
+        assert b.solve() == 0
+        for k, sl in enumerate(slots):
+            assert b.info(sl).status == 0
+            U = live[k].velocities()
+            assert np.abs(U - alone[k]).max() <= 1e-11 * np.abs(alone[k]).max(), (caps, k)
+    b.close()
+    for s in live:
+        s.close()
+
+
 def test_batch_against_oracle_and_failure_isolation(F):
     systems = _small_uneven(4)
     b = F.Batch(1 << 34, 8)

@@ -52,12 +52,18 @@ class FakeBackend:
         self.peak_slots = max(self.peak_slots, len(self.active))
         return slot
 
-    def step(self, dt):
-        self.clock.advance(1e-6 * sum(r.suspension.n_bead for r in self.active.values()))
+    def step(self, dt, counts=None):
+        counts = counts or {slot: 1 for slot in self.active}
+        # the systems work side by side: a tick lasts as long as its busiest system
+        self.clock.advance(1e-6 * max(r.suspension.n_bead * counts[slot] for slot, r in self.active.items()))
         out = {}
         for slot, r in self.active.items():
-            self.steps[r.rid] = self.steps.get(r.rid, 0) + 1
-            out[slot] = -3 if (r.rid in self.fail and self.steps[r.rid] == 2) else 0
+            out[slot] = 0
+            for _ in range(counts[slot]):
+                self.steps[r.rid] = self.steps.get(r.rid, 0) + 1
+                if r.rid in self.fail and self.steps[r.rid] == 2:
+                    out[slot] = -3
+                    break
         return out
 
     def retire(self, slot):
@@ -89,6 +95,7 @@ def test_continuous_batching_refills_freed_slot_at_next_step():
     be = FakeBackend(clk, budget=1 << 40, slots=2)
     eng = BatchEngine(be, max_slots=2, clock=clk)
     reqs = [Request(0, FakeSusp(100), 2), Request(1, FakeSusp(100), 10), Request(2, FakeSusp(100), 3)]
+    # equal sizes: one step per tick each
     for r in reqs:
         eng.submit(r)
     eng.tick()                       # admits 0 and 1
@@ -113,7 +120,7 @@ def test_admission_by_memory_is_first_come_first_served():
     while eng.active or eng.queue:
         eng.tick()
         assert be.used_bytes() <= 3_000_000
-    assert [r.rid for r in sorted(eng.done, key=lambda r: r.started)] == [0, 1, 2]
+    assert [r.rid for r in sorted(eng.done, key=lambda r: (r.started, r.rid))] == [0, 1, 2]
 
 
 def test_oversized_request_is_rejected_not_blocking():
@@ -190,3 +197,33 @@ def test_request_refused_by_an_empty_batch_is_rejected():
     assert rep["completed"] == 1 and rep["failed"] == 1
     bad = [r for r in eng.done if r.status != 0]
     assert bad[0].rid == 0 and bad[0].status == -7
+
+
+def test_small_requests_take_several_steps_per_tick():
+    """A request 4 times smaller than the largest active one takes 4 steps per tick (capped
+    by its remaining steps), so it finishes in a quarter of the ticks."""
+    clk = FakeClock()
+    be = FakeBackend(clk, budget=1 << 40, slots=2)
+    eng = BatchEngine(be, max_slots=2, clock=clk, max_steps_per_tick=8)
+    big, small = Request(0, FakeSusp(4000), 8), Request(1, FakeSusp(1000), 8)
+    eng.submit(big)
+    eng.submit(small)
+    eng.tick()
+    assert small.steps_done == 4 and big.steps_done == 1
+    eng.tick()
+    assert small.finished is not None and small.steps_done == 8 and big.steps_done == 2
+    while eng.active:
+        eng.tick()
+    assert be.steps[0] == 8 and be.steps[1] == 8
+    # the small request's latency is two ticks of the big one
+    assert small.latency == pytest.approx(2 * 4000e-6)
+
+
+def test_one_step_per_tick_when_multi_step_is_off():
+    clk = FakeClock()
+    be = FakeBackend(clk, budget=1 << 40, slots=2)
+    eng = BatchEngine(be, max_slots=2, clock=clk, max_steps_per_tick=1)
+    eng.submit(Request(0, FakeSusp(4000), 3))
+    eng.submit(Request(1, FakeSusp(1000), 3))
+    eng.tick()
+    assert [r.steps_done for r in eng.active.values()] == [1, 1]
