@@ -158,7 +158,7 @@ bool make_plan(int n, FftPlan& p) {
   p.nstage = 0;
   p.rcode = 0;
   int m = n;
-  for (int r : {4, 2, 3, 5})
+  for (int r : {8, 4, 2, 3, 5})
     while (m % r == 0 && p.nstage < kMaxStages) {
       p.rcode |= (unsigned long long)r << (4 * p.nstage);
       p.radix[p.nstage++] = r;

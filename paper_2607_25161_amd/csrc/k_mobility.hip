@@ -1161,7 +1161,30 @@ __device__ __forceinline__ void butterfly(const T* li, T* lo, const T* tw, int b
 #pragma unroll
     for (int r = 1; r < Rd; ++r) v[r] = cmul(v[r], tw[r * k * tstride]);
   }
-  if (Rd == 4) {
+  if (Rd == 8) {
+    // even and odd halves by 4-point transforms, joined by w^k = exp(s 2 pi i k / 8)
+    const T es02 = cadd(v[0], v[4]), ed02 = csub(v[0], v[4]), es13 = cadd(v[2], v[6]),
+            ed13 = rot(csub(v[2], v[6]), s);
+    const T os02 = cadd(v[1], v[5]), od02 = csub(v[1], v[5]), os13 = cadd(v[3], v[7]),
+            od13 = rot(csub(v[3], v[7]), s);
+    const T e0 = cadd(es02, es13), e1 = cadd(ed02, ed13), e2 = csub(es02, es13), e3 = csub(ed02, ed13);
+    const T o0 = cadd(os02, os13), o1 = cadd(od02, od13), o2 = csub(os02, os13), o3 = csub(od02, od13);
+    const R h8 = R(0.70710678118654752440), sr = R(s);
+    T t1, t3;
+    t1.x = h8 * (o1.x - sr * o1.y);  // w o1, w = (1 + s i) / sqrt 2
+    t1.y = h8 * (o1.y + sr * o1.x);
+    t3.x = -h8 * (o3.x + sr * o3.y);  // w^3 o3, w^3 = (-1 + s i) / sqrt 2
+    t3.y = h8 * (sr * o3.x - o3.y);
+    const T t2 = rot(o2, s);
+    lo[od] = cadd(e0, o0);
+    lo[od + 4 * Ns] = csub(e0, o0);
+    lo[od + Ns] = cadd(e1, t1);
+    lo[od + 5 * Ns] = csub(e1, t1);
+    lo[od + 2 * Ns] = cadd(e2, t2);
+    lo[od + 6 * Ns] = csub(e2, t2);
+    lo[od + 3 * Ns] = cadd(e3, t3);
+    lo[od + 7 * Ns] = csub(e3, t3);
+  } else if (Rd == 4) {
     const T s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]), s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]), s);
     lo[od] = cadd(s02, s13);
     lo[od + Ns] = cadd(d02, d13);
@@ -1205,11 +1228,13 @@ __device__ __forceinline__ void butterfly(const T* li, T* lo, const T* tw, int b
   }
 }
 
-// Stockham stages on `nl` lines of length N held in LDS `ls` elements apart (`in`, scratch
-// `out`); returns the buffer holding the result.  The radices come from the plan's packed
-// code (4 bits per stage), so the stage loop indexes no array.
+// Stockham stages (radices 8, 4, 2, 3, 5) on `nl` lines of length N held in LDS `ls`
+// elements apart (`in`, scratch `out`); returns the buffer holding the result.  The
+// radices come from the plan's packed code (4 bits per stage), so the stage loop indexes
+// no array.
 template <typename T, typename R>
-__device__ T* stockham(T* in, T* out, const T* tw, int N, int ls, int nl, const FftPlan& plan, int s) {
+__device__ __forceinline__ T* stockham(T* in, T* out, const T* tw, int N, int ls, int nl, const FftPlan& plan,
+                                       int s) {
   int Ns = 1;
   const unsigned long long code = plan.rcode;
   for (int stg = 0; stg < plan.nstage; ++stg) {
@@ -1224,7 +1249,50 @@ __device__ T* stockham(T* in, T* out, const T* tw, int N, int ls, int nl, const 
       const T* li = in + l * ls;
       T* lo = out + l * ls;
       const int od = j * Ns * Rd + k;
-      if (Rd == 4)
+      if (Rd == 8)
+        butterfly<T, R, 8>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 4)
+        butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 2)
+        butterfly<T, R, 2>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 3)
+        butterfly<T, R, 3>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else
+        butterfly<T, R, 5>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+    }
+    __syncthreads();
+    T* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= Rd;
+  }
+  return in;
+}
+
+// Stockham stages on B lines (B a power of two, 2^lb) held S elements apart, with the
+// line as the fastest thread index: t -> (line t & (B - 1), butterfly t >> lb).  Lanes
+// that differ in the line meet distinct banks (the stride of fft_line_stride), and the
+// mapping needs one division per butterfly (by the stage's Ns) instead of two.
+template <typename T, typename R>
+__device__ __forceinline__ T* stockham_lines(T* in, T* out, const T* tw, int N, int S, int B, int lb,
+                                             const FftPlan& plan, int s) {
+  int Ns = 1;
+  const unsigned long long code = plan.rcode;
+  for (int stg = 0; stg < plan.nstage; ++stg) {
+    const int Rd = int((code >> (4 * stg)) & 15ull);
+    const int nbf = N / Rd;
+    const int tstride = N / (Ns * Rd);
+    const FastDiv dns(Ns);
+    for (int t = threadIdx.x; t < (nbf << lb); t += blockDim.x) {
+      const int l = t & (B - 1), b = t >> lb;
+      int j, k;
+      dns.divmod(b, j, k);
+      const T* li = in + l * S;
+      T* lo = out + l * S;
+      const int od = j * Ns * Rd + k;
+      if (Rd == 8)
+        butterfly<T, R, 8>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 4)
         butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
       else if (Rd == 2)
         butterfly<T, R, 2>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
@@ -1401,20 +1469,19 @@ __device__ __forceinline__ void fft_lines_body(R* __restrict__ grid, size_t cs, 
   const int line0 = bx_ * B;  // line gl = o N + x: B consecutive x of one o (B divides N)
   const int o = line0 / N, x0 = line0 - o * N;
   const int lb = __ffs(B) - 1;  // B is a power of two
+  // element e of line l sits at g[e * es + l]: a workgroup-uniform base and a 32-bit
+  // offset (N^3 < 2^31 for N <= 256)
+  T* g = base + (DIR == 1 ? size_t(o) * N * N : size_t(o) * N) + x0;
+  const int es = DIR == 1 ? N : N * N;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
   staged_copy<8, T>(
-      B * N,
-      [&](int t) {
-        const int l = t & (B - 1), e = t >> lb, x = x0 + l;
-        return base[DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x];
-      },
+      B * N, [&](int t) { return g[(t >> lb) * es + (t & (B - 1))]; },
       [&](int t, const T& v) { buf0[(t & (B - 1)) * S + (t >> lb)] = v; });
   __syncthreads();
-  const T* Y = stockham<T, R>(buf0, buf1, tw, N, S, B, plan, sign);
+  const T* Y = stockham_lines<T, R>(buf0, buf1, tw, N, S, B, lb, plan, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
-    const int l = t & (B - 1), e = t >> lb, x = x0 + l;
-    const size_t off = DIR == 1 ? (size_t(o) * N + e) * N + x : (size_t(e) * N + o) * N + x;
-    base[off] = Y[l * S + e];
+    const int l = t & (B - 1), e = t >> lb;
+    g[e * es + l] = Y[l * S + e];
   }
 }
 
