@@ -418,6 +418,35 @@ void launch_interp_sheared(int nb, const double* pos4, const R* grid, const Wave
            body, (const double4*)r4, V);
 }
 
+// Element i of a device array read as global memory (32-bit index from a base the
+// workgroup shares), so the load takes a 32-bit offset instead of a 64-bit address.
+template <typename R>
+__device__ __forceinline__ R ldg(const R* p, unsigned i) {
+  const unsigned bytes = i * unsigned(sizeof(R));  // the caller keeps this below 2^32
+  return *(__attribute__((address_space(1))) const R*)((__attribute__((address_space(1))) const char*)p + bytes);
+}
+
+// The pair p[i], p[i + 1] (i even) stored in one store, addressed as ldg addresses.
+template <typename R>
+__device__ __forceinline__ void stg2(R* p, unsigned i, R a, R b) {
+  typedef R V2 __attribute__((ext_vector_type(2)));
+  const unsigned bytes = i * unsigned(sizeof(R));
+  V2 v;
+  v.x = a;
+  v.y = b;
+  *(__attribute__((address_space(1))) V2*)((__attribute__((address_space(1))) char*)p + bytes) = v;
+}
+
+// The pair p[i], p[i + 1] (i even) in one load, as ldg.
+template <typename R>
+__device__ __forceinline__ void ldg2(const R* p, unsigned i, R& a, R& b) {
+  typedef R V2 __attribute__((ext_vector_type(2)));
+  const unsigned bytes = i * unsigned(sizeof(R));
+  const V2 v = *(__attribute__((address_space(1))) const V2*)((__attribute__((address_space(1))) const char*)p + bytes);
+  a = v.x;
+  b = v.y;
+}
+
 template <typename R>
 __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ pos,
                                                 const R* __restrict__ grid, size_t cs, WaveParams wp,
@@ -460,27 +489,37 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
   const R* wz = wts[wv] + 2 * kMaxP;
   R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
   // lane -> (kx, ky) column of the support, each lane walking its column along z
-  // (one integer division per column; indices wrap by a conditional subtraction)
+  // (one integer division per column; indices wrap by a conditional subtraction).  The
+  // grid is read through 32-bit offsets from the three component bases (2 N^3 < 2^31 for
+  // N <= 256), in two runs split where the column wraps in z.
   const int sxw = wrapi(sx, N), syw = wrapi(sy, N), szw = wrapi(sz, N);
-  const size_t plane = 2 * size_t(N) * N;
+  const unsigned plane = 2 * N * N;
+  const int n1 = min(P, N - szw);
+  const R* g0 = grid;
+  const R* g1 = grid + cs;
+  const R* g2 = grid + 2 * cs;
   for (int pq = lane; pq < P * P; pq += 64) {
     const int ky = pq / P, kx = pq - ky * P;
     int x = sxw + kx, y = syw + ky;
     x -= x >= N ? N : 0;
     y -= y >= N ? N : 0;
     const R wxy = wx[kx] * wy[ky];
-    const R* col = grid + 2 * (size_t(y) * N + x);
-    int z = szw;
+    const unsigned col = 2 * (y * N + x);
+    unsigned off = col + szw * plane;
     for (int kz = 0; kz < P; ++kz) {
+      if (kz == n1) off = col;  // the column wraps to z = 0
       const R w = wxy * wz[kz];
-      const R* g = col + plane * z;
-      a0 += w * g[0];
-      a3 += w * g[1];
-      a1 += w * g[cs];
-      a4 += w * g[cs + 1];
-      a2 += w * g[2 * cs];
-      a5 += w * g[2 * cs + 1];
-      z = z + 1 == N ? 0 : z + 1;
+      R v0, v1, v2, v3, v4, v5;
+      ldg2(g0, off, v0, v3);
+      ldg2(g1, off, v1, v4);
+      ldg2(g2, off, v2, v5);
+      a0 += w * v0;
+      a3 += w * v3;
+      a1 += w * v1;
+      a4 += w * v4;
+      a2 += w * v2;
+      a5 += w * v5;
+      off += plane;
     }
   }
   a0 = wave_sum(a0);
@@ -1273,6 +1312,46 @@ __device__ __forceinline__ T* stockham(T* in, T* out, const T* tw, int N, int ls
 // line as the fastest thread index: t -> (line t & (B - 1), butterfly t >> lb).  Lanes
 // that differ in the line meet distinct banks (the stride of fft_line_stride), and the
 // mapping needs one division per butterfly (by the stage's Ns) instead of two.
+// As stockham_lines for any number of lines nl (held S apart, S odd so that consecutive
+// lines start on distinct banks): t -> (line t mod nl, butterfly t / nl).
+template <typename T, typename R>
+__device__ __forceinline__ T* stockham_lm(T* in, T* out, const T* tw, int N, int S, int nl, const FftPlan& plan,
+                                          int s) {
+  int Ns = 1;
+  const unsigned long long code = plan.rcode;
+  const FastDiv dnl(nl);
+  for (int stg = 0; stg < plan.nstage; ++stg) {
+    const int Rd = int((code >> (4 * stg)) & 15ull);
+    const int nbf = N / Rd;
+    const int tstride = N / (Ns * Rd);
+    const FastDiv dns(Ns);
+    for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
+      int b, l, j, k;
+      dnl.divmod(t, b, l);
+      dns.divmod(b, j, k);
+      const T* li = in + l * S;
+      T* lo = out + l * S;
+      const int od = j * Ns * Rd + k;
+      if (Rd == 8)
+        butterfly<T, R, 8>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 4)
+        butterfly<T, R, 4>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 2)
+        butterfly<T, R, 2>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else if (Rd == 3)
+        butterfly<T, R, 3>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+      else
+        butterfly<T, R, 5>(li, lo, tw, b, nbf, k, Ns, tstride, od, s);
+    }
+    __syncthreads();
+    T* tmp = in;
+    in = out;
+    out = tmp;
+    Ns *= Rd;
+  }
+  return in;
+}
+
 template <typename T, typename R>
 __device__ __forceinline__ T* stockham_lines(T* in, T* out, const T* tw, int N, int S, int B, int lb,
                                              const FftPlan& plan, int s) {
@@ -1309,6 +1388,85 @@ __device__ __forceinline__ T* stockham_lines(T* in, T* out, const T* tw, int N, 
   }
   return in;
 }
+
+// stockham_lines for a grid side N known at compile time: the radices (8s, then 4, 2, 3s,
+// 5s), the butterfly counts, the divisions by Ns and the LDS offsets of every stage fold
+// into constants.  Used for the common grid sides; others take stockham_lines.
+template <int Rem>
+constexpr int pick_radix() {
+  return Rem % 8 == 0 ? 8 : Rem % 4 == 0 ? 4 : Rem % 2 == 0 ? 2 : Rem % 3 == 0 ? 3 : 5;
+}
+
+template <typename T, typename R, int N, int Ns, int Rem>
+__device__ __forceinline__ T* stockham_n(T* in, T* out, const T* tw, int S, int B, int lb, int s) {
+  if constexpr (Rem == 1) {
+    return in;
+  } else {
+    constexpr int Rd = pick_radix<Rem>(), nbf = N / Rd, tstride = N / (Ns * Rd);
+    for (int t = threadIdx.x; t < (nbf << lb); t += blockDim.x) {
+      const int l = t & (B - 1), b = t >> lb;
+      const int j = b / Ns, k = b - j * Ns;
+      butterfly<T, R, Rd>(in + l * S, out + l * S, tw, b, nbf, k, Ns, tstride, j * Ns * Rd + k, s);
+    }
+    __syncthreads();
+    return stockham_n<T, R, N, Ns * Rd, Rem / Rd>(out, in, tw, S, B, lb, s);
+  }
+}
+
+// stockham_lm for a compile-time grid side (nl lines, dnl its divider)
+template <typename T, typename R, int N, int Ns, int Rem>
+__device__ __forceinline__ T* stockham_lm_n(T* in, T* out, const T* tw, int S, int nl, const FastDiv& dnl, int s) {
+  if constexpr (Rem == 1) {
+    return in;
+  } else {
+    constexpr int Rd = pick_radix<Rem>(), nbf = N / Rd, tstride = N / (Ns * Rd);
+    for (int t = threadIdx.x; t < nl * nbf; t += blockDim.x) {
+      int b, l;
+      dnl.divmod(t, b, l);
+      const int j = b / Ns, k = b - j * Ns;
+      butterfly<T, R, Rd>(in + l * S, out + l * S, tw, b, nbf, k, Ns, tstride, j * Ns * Rd + k, s);
+    }
+    __syncthreads();
+    return stockham_lm_n<T, R, N, Ns * Rd, Rem / Rd>(out, in, tw, S, nl, dnl, s);
+  }
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ T* stockham_lm_any(T* in, T* out, const T* tw, int N, int S, int nl, const FftPlan& plan,
+                                              int s) {
+  const FastDiv dnl(nl);
+  switch (N) {
+    case 32: return stockham_lm_n<T, R, 32, 1, 32>(in, out, tw, S, nl, dnl, s);
+    case 40: return stockham_lm_n<T, R, 40, 1, 40>(in, out, tw, S, nl, dnl, s);
+    case 48: return stockham_lm_n<T, R, 48, 1, 48>(in, out, tw, S, nl, dnl, s);
+    case 64: return stockham_lm_n<T, R, 64, 1, 64>(in, out, tw, S, nl, dnl, s);
+    case 72: return stockham_lm_n<T, R, 72, 1, 72>(in, out, tw, S, nl, dnl, s);
+    case 80: return stockham_lm_n<T, R, 80, 1, 80>(in, out, tw, S, nl, dnl, s);
+    case 96: return stockham_lm_n<T, R, 96, 1, 96>(in, out, tw, S, nl, dnl, s);
+    case 120: return stockham_lm_n<T, R, 120, 1, 120>(in, out, tw, S, nl, dnl, s);
+    case 128: return stockham_lm_n<T, R, 128, 1, 128>(in, out, tw, S, nl, dnl, s);
+    default: return stockham_lm<T, R>(in, out, tw, N, S, nl, plan, s);
+  }
+}
+
+// stockham_lines with the grid side dispatched to a compile-time instance where there is one
+template <typename T, typename R>
+__device__ __forceinline__ T* stockham_lines_any(T* in, T* out, const T* tw, int N, int S, int B, int lb,
+                                                 const FftPlan& plan, int s) {
+  switch (N) {
+    case 32: return stockham_n<T, R, 32, 1, 32>(in, out, tw, S, B, lb, s);
+    case 40: return stockham_n<T, R, 40, 1, 40>(in, out, tw, S, B, lb, s);
+    case 48: return stockham_n<T, R, 48, 1, 48>(in, out, tw, S, B, lb, s);
+    case 64: return stockham_n<T, R, 64, 1, 64>(in, out, tw, S, B, lb, s);
+    case 72: return stockham_n<T, R, 72, 1, 72>(in, out, tw, S, B, lb, s);
+    case 80: return stockham_n<T, R, 80, 1, 80>(in, out, tw, S, B, lb, s);
+    case 96: return stockham_n<T, R, 96, 1, 96>(in, out, tw, S, B, lb, s);
+    case 120: return stockham_n<T, R, 120, 1, 120>(in, out, tw, S, B, lb, s);
+    case 128: return stockham_n<T, R, 128, 1, 128>(in, out, tw, S, B, lb, s);
+    default: return stockham_lines<T, R>(in, out, tw, N, S, B, lb, plan, s);
+  }
+}
+
 }  // namespace
 
 template <typename R, int DIR>
@@ -1470,18 +1628,24 @@ __device__ __forceinline__ void fft_lines_body(R* __restrict__ grid, size_t cs, 
   const int o = line0 / N, x0 = line0 - o * N;
   const int lb = __ffs(B) - 1;  // B is a power of two
   // element e of line l sits at g[e * es + l]: a workgroup-uniform base and a 32-bit
-  // offset (N^3 < 2^31 for N <= 256)
-  T* g = base + (DIR == 1 ? size_t(o) * N * N : size_t(o) * N) + x0;
-  const int es = DIR == 1 ? N : N * N;
+  // offset (its byte offset stays below 2 N^3 sizeof(R) <= 2^28 for N <= 256)
+  R* g = reinterpret_cast<R*>(base + (DIR == 1 ? size_t(o) * N * N : size_t(o) * N) + x0);
+  const unsigned es = DIR == 1 ? N : N * N;
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, sign);
   staged_copy<8, T>(
-      B * N, [&](int t) { return g[(t >> lb) * es + (t & (B - 1))]; },
+      B * N,
+      [&](int t) {
+        T v;
+        ldg2(g, 2 * (unsigned(t >> lb) * es + unsigned(t & (B - 1))), v.x, v.y);
+        return v;
+      },
       [&](int t, const T& v) { buf0[(t & (B - 1)) * S + (t >> lb)] = v; });
   __syncthreads();
-  const T* Y = stockham_lines<T, R>(buf0, buf1, tw, N, S, B, lb, plan, sign);
+  const T* Y = stockham_lines_any<T, R>(buf0, buf1, tw, N, S, B, lb, plan, sign);
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int l = t & (B - 1), e = t >> lb;
-    g[e * es + l] = Y[l * S + e];
+    const T y = Y[l * S + e];
+    stg2(g, 2 * (unsigned(e) * es + unsigned(l)), y.x, y.y);
   }
 }
 
@@ -1507,10 +1671,10 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   // N^2/2 + 2 pairs {r, rp} (r = kz N + ky, rp = its (-kz, -ky) partner, r <= rp; the
   // four self-paired rows have rp == r).  Line (g, c, q) = component c of row q (0: r,
   // 1: rp) sits at (6 g + 2 c + q) N; lines of idle slots are zero.
-  const int NL = 6 * G;
+  const int NL = 6 * G, S = N | 1;  // lines S apart: an odd stride spreads them over the banks
   T* buf0 = reinterpret_cast<T*>(smem_raw);
-  T* buf1 = buf0 + NL * N;
-  T* tw = buf1 + NL * N;
+  T* buf1 = buf0 + NL * S;
+  T* tw = buf1 + NL * S;
   const int H = N / 2, npair = NN / 2 + 2;
   const FastDiv dn(N);
   auto row_of = [N, H](int p) {  // pair number -> its first row r
@@ -1537,13 +1701,17 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
         v.y = 0;
         if (pn < npair) {
           const int r = row_of(pn), rp = partner(r);
-          if (q == 0 || rp != r) v = reinterpret_cast<const T*>(grid + c * cs)[size_t(q ? rp : r) * N + x];
+          if (q == 0 || rp != r) ldg2(grid, unsigned(c * cs) + 2 * unsigned((q ? rp : r) * N + x), v.x, v.y);
         }
         return v;
       },
-      [&](int t, const T& v) { buf0[t] = v; });
+      [&](int t, const T& v) {
+        int line, x;
+        dn.divmod(t, line, x);
+        buf0[line * S + x] = v;
+      });
   __syncthreads();
-  T* X = stockham<T, R>(buf0, buf1, tw, N, N, NL, plan, -1);
+  T* X = stockham_lm_any<T, R>(buf0, buf1, tw, N, S, NL, plan, -1);
   T* O = (X == buf0) ? buf1 : buf0;
   const double tp = 2.0 * M_PI / wp.L, gam = (!TABLE && wp.gam) ? *wp.gam : 0.0;
   for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
@@ -1562,8 +1730,8 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     const bool nyq = (N % 2 == 0) && (kx == N / 2 || ky == N / 2 || kz == N / 2);
     if (nyq || (kx == 0 && ky == 0 && kz == 0)) {
       for (int c = 0; c < 3; ++c) {
-        O[(l0 + 2 * c + q) * N + kx].x = 0;
-        O[(l0 + 2 * c + q) * N + kx].y = 0;
+        O[(l0 + 2 * c + q) * S + kx].x = 0;
+        O[(l0 + 2 * c + q) * S + kx].y = 0;
       }
       continue;
     }
@@ -1571,7 +1739,7 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     // in FP64 and rounded once)
     R Fr[3], Fi[3], Tr[3], Ti[3];
     for (int c = 0; c < 3; ++c) {
-      const T z = X[(l0 + 2 * c + q) * N + kx], zm = X[(l0 + 2 * c + qm) * N + kxm];
+      const T z = X[(l0 + 2 * c + q) * S + kx], zm = X[(l0 + 2 * c + qm) * S + kxm];
       Fr[c] = R(0.5) * (z.x + zm.x);
       Fi[c] = R(0.5) * (z.y - zm.y);
       Tr[c] = R(0.5) * (z.y + zm.y);
@@ -1634,13 +1802,13 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
       T y;
       y.x = Ur - Wi;
       y.y = Ui + Wr;
-      O[(l0 + 2 * c + q) * N + kx] = y;
+      O[(l0 + 2 * c + q) * S + kx] = y;
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t].y = -tw[t].y;
   __syncthreads();
-  const T* Y = stockham<T, R>(O, X, tw, N, N, NL, plan, +1);
+  const T* Y = stockham_lm_any<T, R>(O, X, tw, N, S, NL, plan, +1);
   for (int t = threadIdx.x; t < NL * N; t += blockDim.x) {
     int line, x;
     dn.divmod(t, line, x);
@@ -1649,7 +1817,8 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     if (pn >= npair) continue;
     const int r = row_of(pn), rp = partner(r);
     if (q == 1 && rp == r) continue;
-    reinterpret_cast<T*>(grid + c * cs)[size_t(q ? rp : r) * N + x] = Y[line * N + x];
+    const T y = Y[line * S + x];
+    stg2(grid, unsigned(c * cs) + 2 * unsigned((q ? rp : r) * N + x), y.x, y.y);
   }
 }
 
@@ -1669,7 +1838,7 @@ bool tile_b_fits(int N, int B, int rbytes) {
 }
 
 bool tile_g_fits(int N, int G, int rbytes) {
-  return G >= 1 && G <= 16 && size_t(2 * rbytes) * (12 * size_t(G) * N + N) <= (size_t(64) << 10);
+  return G >= 1 && G <= 16 && size_t(2 * rbytes) * (12 * size_t(G) * (N | 1) + N) <= (size_t(64) << 10);
 }
 
 // lines per workgroup of the coalesced y/z passes: largest B in {16, 8, 4, 2, 1} dividing N
@@ -1696,7 +1865,7 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
   const size_t cs = 2 * size_t(N) * N * N;
   if (stage == 2) {
     const int G = green_g_of(wp);
-    const size_t shm = sizeof(T) * (12 * size_t(G) * N + N);
+    const size_t shm = sizeof(T) * (12 * size_t(G) * (N | 1) + N);
     const int nblk = (N * N / 2 + 2 + G - 1) / G;
     if (wp.gtab && !wp.gam)  // the cube: tabulated multipliers
       launch_k(k_fft_xgreen<R, true>, nblk, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
@@ -1860,7 +2029,7 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec) {
     case BK_FFT_MID:
       return tb * (2 * size_t(d.bl) * fft_line_stride(int(N), d.bl, int(tb)) + N);
     case BK_FFT_GREEN:
-      return tb * (12 * size_t(d.bg) * N + N);
+      return tb * (12 * size_t(d.bg) * (N | 1) + N);
     default:
       return 0;
   }
