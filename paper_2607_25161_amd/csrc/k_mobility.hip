@@ -437,6 +437,18 @@ __device__ __forceinline__ void stg2(R* p, unsigned i, R a, R b) {
   *(__attribute__((address_space(1))) V2*)((__attribute__((address_space(1))) char*)p + bytes) = v;
 }
 
+// p[i .. i + 3] (i a multiple of 4) in one aligned load, as ldg.
+template <typename R>
+__device__ __forceinline__ void ldg4(const R* p, unsigned i, R& a, R& b, R& c, R& d) {
+  typedef R V4 __attribute__((ext_vector_type(4)));
+  const unsigned bytes = i * unsigned(sizeof(R));
+  const V4 v = *(__attribute__((address_space(1))) const V4*)((__attribute__((address_space(1))) const char*)p + bytes);
+  a = v.x;
+  b = v.y;
+  c = v.z;
+  d = v.w;
+}
+
 // The pair p[i], p[i + 1] (i even) in one load, as ldg.
 template <typename R>
 __device__ __forceinline__ void ldg2(const R* p, unsigned i, R& a, R& b) {
@@ -488,17 +500,22 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
   const R* wy = wts[wv] + kMaxP;
   const R* wz = wts[wv] + 2 * kMaxP;
   R a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
-  // lane -> (kx, ky) column of the support, each lane walking its column along z
-  // (one integer division per column; indices wrap by a conditional subtraction).  The
-  // grid is read through 32-bit offsets from the three component bases (2 N^3 < 2^31 for
-  // N <= 256), in two runs split where the column wraps in z.
+  // lane -> (x pair, ky) of the support, each lane walking its two columns along z: the
+  // pairs (2m, 2m + 1) that cover the support's P x values (P/2 + 1 of them at most, the
+  // points outside the support weighted 0), so each load brings two grid points in one
+  // aligned 16-byte (FP32) or 32-byte (FP64) read; for even N no pair straddles the
+  // periodic wrap.  The grid is read through 32-bit offsets from the three component bases
+  // (2 N^3 < 2^31 for N <= 256), in two runs split where the columns wrap in z.
   const int sxw = wrapi(sx, N), syw = wrapi(sy, N), szw = wrapi(sz, N);
   const unsigned plane = 2 * N * N;
-  const int n1 = min(P, N - szw);
+  const int n1 = min(P, N - szw), half = N >> 1, m0 = sxw >> 1;
+  const int npx = ((sxw + P - 1) >> 1) - m0 + 1;
   const R* g0 = grid;
   const R* g1 = grid + cs;
   const R* g2 = grid + 2 * cs;
-  for (int pq = lane; pq < P * P; pq += 64) {
+  // an odd grid side (set by the caller) keeps one column per lane: its pairs would
+  // straddle the wrap and lose the alignment
+  for (int pq = lane; (N & 1) && pq < P * P; pq += 64) {
     const int ky = pq / P, kx = pq - ky * P;
     int x = sxw + kx, y = syw + ky;
     x -= x >= N ? N : 0;
@@ -507,18 +524,41 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
     const unsigned col = 2 * (y * N + x);
     unsigned off = col + szw * plane;
     for (int kz = 0; kz < P; ++kz) {
-      if (kz == n1) off = col;  // the column wraps to z = 0
+      if (kz == n1) off = col;
       const R w = wxy * wz[kz];
-      R v0, v1, v2, v3, v4, v5;
-      ldg2(g0, off, v0, v3);
-      ldg2(g1, off, v1, v4);
-      ldg2(g2, off, v2, v5);
-      a0 += w * v0;
-      a3 += w * v3;
-      a1 += w * v1;
-      a4 += w * v4;
-      a2 += w * v2;
-      a5 += w * v5;
+      a0 += w * ldg(g0, off);
+      a3 += w * ldg(g0, off + 1);
+      a1 += w * ldg(g1, off);
+      a4 += w * ldg(g1, off + 1);
+      a2 += w * ldg(g2, off);
+      a5 += w * ldg(g2, off + 1);
+      off += plane;
+    }
+  }
+  for (int pq = lane; !(N & 1) && pq < npx * P; pq += 64) {
+    const int ky = pq / npx, mp = pq - ky * npx;
+    int m = m0 + mp, y = syw + ky;
+    m -= m >= half ? half : 0;
+    y -= y >= N ? N : 0;
+    const int kx0 = 2 * (m0 + mp) - sxw;  // support offset of the pair's first point (>= -1)
+    const R wyk = wy[ky];
+    const R wp0 = kx0 >= 0 ? wx[kx0] * wyk : R(0);
+    const R wp1 = kx0 + 1 < P ? wx[kx0 + 1] * wyk : R(0);
+    const unsigned col = 2 * (y * N + 2 * m);
+    unsigned off = col + szw * plane;
+    for (int kz = 0; kz < P; ++kz) {
+      if (kz == n1) off = col;  // the columns wrap to z = 0
+      const R w = wz[kz], u0 = wp0 * w, u1 = wp1 * w;
+      R b0, b1, b2, b3;
+      ldg4(g0, off, b0, b1, b2, b3);
+      a0 += u0 * b0 + u1 * b2;
+      a3 += u0 * b1 + u1 * b3;
+      ldg4(g1, off, b0, b1, b2, b3);
+      a1 += u0 * b0 + u1 * b2;
+      a4 += u0 * b1 + u1 * b3;
+      ldg4(g2, off, b0, b1, b2, b3);
+      a2 += u0 * b0 + u1 * b2;
+      a5 += u0 * b1 + u1 * b3;
       off += plane;
     }
   }
