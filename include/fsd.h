@@ -412,6 +412,15 @@ size_t fsd_batch_used_bytes(const fsd_batch* b);
 /* Select multi-system launches (enable != 0, the default) or one stream per system. */
 fsd_status fsd_batch_set_fused(fsd_batch* b, int enable);
 
+/* Captured graphs for the multi-system launches (Section 2.5; enable != 0, the default):
+ * each lock-step segment of Arnoldi steps (one launch per kernel over every system) is
+ * captured on first use and replayed while the batch's tables stay the same (the same
+ * systems iterating, the same tiles and LDS caps), so the first GMRES cycle of every time
+ * step replays the same graphs; other systems sets are captured anew.  The timing pass
+ * (fsd_batch_set_timing) launches eagerly.  enable == 0 launches every segment eagerly
+ * and frees the captured graphs.  The results are the same either way. */
+fsd_status fsd_batch_set_graphs(fsd_batch* b, int enable);
+
 /* Event timing of the multi-system launches (fsd_timer classes; the Arnoldi steps of the
  * lock-step solve): while on, each launch is bracketed by HIP events on the batch stream,
  * the host checks the stop flags after every Arnoldi step, and each launch is credited

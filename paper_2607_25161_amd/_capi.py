@@ -119,6 +119,7 @@ _sig("fsd_batch_slot_info", C.c_int, C.c_void_p, C.c_int, C.POINTER(SolveInfo))
 _sig("fsd_batch_used_bytes", C.c_size_t, C.c_void_p)
 _sig("fsd_batch_destroy", None, C.c_void_p)
 _sig("fsd_batch_set_fused", C.c_int, C.c_void_p, C.c_int)
+_sig("fsd_batch_set_graphs", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_set_timing", C.c_int, C.c_void_p, C.c_int)
 _sig("fsd_batch_get_timers", C.c_int, C.c_void_p, _D, C.POINTER(C.c_longlong), _D)
 _sig("fsd_batch_time_kernel", C.c_int, C.c_void_p, C.c_int, C.c_int, _D, _D)
@@ -556,6 +557,12 @@ class Batch:
         if rc:
             raise FsdError(rc, "fsd_batch_autotune_tiles")
         return a.value, g.value
+
+    def set_graphs(self, enable=True):
+        """Captured graphs for the lock-step segments (default on)."""
+        rc = lib.fsd_batch_set_graphs(self._h, 1 if enable else 0)
+        if rc:
+            raise FsdError(rc, "fsd_batch_set_graphs")
 
     def set_lds_caps(self, lines, green):
         """LDS caps (bytes, 0: none) of the multi-system line passes and x+Green pass."""

@@ -2564,6 +2564,19 @@ struct fsd_batch {
   // multi-system launches (fused mode): descriptor and block tables on the device and
   // a stream of their own
   bool fused = true;
+  // captured lock-step segments (j0, cnt) of the current tables; recaptured whenever the
+  // tables are uploaded again (another set of systems, other block counts or LDS)
+  struct SegGraph {
+    int j0, cnt;
+    hipGraphExec_t exec;
+  };
+  bool use_graphs = true;
+  std::vector<SegGraph> seg_graphs;
+  unsigned long long table_version = 0, graphs_version = ~0ull;
+  void drop_graphs() {
+    for (auto& g : seg_graphs) (void)hipGraphExecDestroy(g.exec);
+    seg_graphs.clear();
+  }
   hipStream_t st = nullptr;
   bool own_stream = false;
   BatchDesc* d_desc = nullptr;
@@ -2593,6 +2606,7 @@ struct fsd_batch {
   size_t ev_next = 0;
   std::vector<Pend> pending;
   ~fsd_batch() {
+    drop_graphs();
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     if (d_desc) (void)hipFree(d_desc);
     if (d_off) (void)hipFree(d_off);
@@ -2773,6 +2787,7 @@ void set_tables(fsd_batch* b, const std::vector<fsd_system*>& cyc, int prec) {
   const bool same = ns == b->nsys && prec == b->prec && off == b->h_off &&
                     std::memcmp(desc.data(), b->h_desc.data(), sizeof(BatchDesc) * ns) == 0;
   if (same) return;
+  ++b->table_version;  // captured segments hold the old block counts and LDS sizes
   if (ns > b->cap) {
     if (b->d_desc) HIPCHK(hipFree(b->d_desc));
     if (b->d_off) HIPCHK(hipFree(b->d_off));
@@ -2895,11 +2910,39 @@ void batch_segment_body(fsd_batch* b, int j0, int cnt) {
   }
 }
 
-// The multi-system kernels are large enough that launching them eagerly costs little;
-// graphs would have to be re-captured whenever the set of running systems changes.
+// One lock-step segment.  Without timing it replays a captured graph of the segment's
+// launches, captured on first use for the current tables: the first cycle of every time
+// step runs the same systems with the same tables, so its segments are captured once.
 void batch_segment(fsd_batch* b, int j0, int cnt) {
-  batch_segment_body(b, j0, cnt);
-  HIPCHK(hipGetLastError());
+  if (!b->use_graphs || b->timing) {
+    batch_segment_body(b, j0, cnt);
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (b->graphs_version != b->table_version) {
+    b->drop_graphs();
+    b->graphs_version = b->table_version;
+  }
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : b->seg_graphs)
+    if (g.j0 == j0 && g.cnt == cnt) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+    try {
+      batch_segment_body(b, j0, cnt);
+    } catch (...) {
+      (void)hipStreamEndCapture(b->st, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(b->st, &graph));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    b->seg_graphs.push_back({j0, cnt, exec});
+  }
+  HIPCHK(hipGraphLaunch(exec, b->st));
 }
 
 // Advances every solve in sys to its end, each on its own stream with its captured GMRES
@@ -3182,6 +3225,13 @@ size_t fsd_batch_used_bytes(const fsd_batch* b) { return b ? b->used : 0; }
 fsd_status fsd_batch_set_fused(fsd_batch* b, int enable) {
   if (!b) return FSD_EINVAL;
   b->fused = enable != 0;
+  return FSD_OK;
+}
+
+fsd_status fsd_batch_set_graphs(fsd_batch* b, int enable) {
+  if (!b) return FSD_EINVAL;
+  b->use_graphs = enable != 0;
+  if (!b->use_graphs) b->drop_graphs();
   return FSD_OK;
 }
 

@@ -348,6 +348,31 @@ def test_batch_results_equal_alone(F, precision, fused):
         assert np.abs(X1 - X2).max() < tol and np.abs(q1 - q2).max() < max(tol, 1e-12)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_graphs_replay_eager_steps(F, precision):
+    """Captured lock-step segments (replayed across time steps, recaptured when the set of
+    iterating systems changes) give the same trajectory as eager launches, step by step."""
+    systems = _small_uneven()
+    runs = []
+    for graphs in (True, False):
+        live = [F.System.from_suspension(s0, precision=precision) for s0 in systems]
+        b = F.Batch(1 << 34, 16)
+        b.set_graphs(graphs)
+        slots = [b.admit(s) for s in live]
+        traj = []
+        for _ in range(4):
+            assert b.step(1e-3) == 0
+            traj.append([np.concatenate([x.ravel() for x in s.state()]) for s in live])
+            assert all(b.info(sl).status == 0 for sl in slots)
+        runs.append(traj)
+        b.close()
+        for s in live:
+            s.close()
+    for step, (ga, ea) in enumerate(zip(*runs)):
+        for k, (g, e) in enumerate(zip(ga, ea)):
+            assert np.abs(g - e).max() <= 1e-13 * max(1.0, np.abs(e).max()), (step, k)
+
+
 def test_batch_lds_caps_keep_results(F):
     """Narrowed transform tiles in the multi-system launches (LDS caps) and the measured caps
     leave the FP64 solutions as they are alone (same arithmetic up to summation order)."""
