@@ -385,7 +385,7 @@ def bench_serving(args, F, fsdgen, torch):
         sel = reqs if subset is None else subset
         # Brownian requests: the previous solution, not an extrapolation of noisy ones
         be = LibBackend(F, budget, slots, dict(precision=precision), warm_start=0 if args.cold else 1,
-                        lees_edwards=sheared)
+                        lees_edwards=sheared, drift=args.serve_drift)
         eng = BatchEngine(be, max_slots=slots, dt=1e-3, max_steps_per_tick=multi)
         t_arr = np.zeros(len(sel)) if rate is None else poisson_arrivals(np.random.default_rng(seed), len(sel), rate)
         rs = [Request(k, s, n_steps, arrival=float(t_arr[k])) for k, s in enumerate(sel)]
@@ -427,7 +427,9 @@ def bench_serving(args, F, fsdgen, torch):
         "config": {"workload": f"{len(reqs)} requests of {args.req_steps} steps, 100-{args.max_beads} beads "
                                f"(log-uniform), 4-30 beads per aggregate, phi 0.02-0.25, shear rate {args.shear_rate} "
                                f"({'sheared lattice' if sheared else 'cube'}) + lubrication + "
-                               f"Brownian kT {args.kT} with Fixman's drift off, tol 1e-5, closed loop",
+                               f"Brownian kT {args.kT}, drift "
+                               f"{['off', 'by random finite differences', 'by Fixman midpoints'][args.serve_drift]}, "
+                               f"tol 1e-5, closed loop",
                    "n_bead_total": int(sum(s.n_bead for s in reqs)), "slots": args.slots,
                    "mem_budget_gib": round(budget / 2 ** 30, 1), "precision": args.precision,
                    "warm_start": 0 if args.cold else 1, "parallelism": "single GPU, continuous batching"},
@@ -709,6 +711,9 @@ def main():
     ap.add_argument("--loads", default="0.25,0.5,1.0,2.0,4.0",
                     help="serving: Poisson arrival rates as multiples of the measured capacity")
     ap.add_argument("--kT", type=float, default=1.0, help="thermal energy of the serving requests")
+    ap.add_argument("--serve-drift", type=int, choices=[0, 1, 2], default=0,
+                    help="serving: Brownian drift of the requests (0 off, the default: the timed work is the "
+                         "solves; 1 random finite differences, 2 Fixman: two more solves per step)")
     ap.add_argument("--shear-rate", type=float, default=1.0,
                     help="shear rate of the serving requests (on the sheared lattice; 0.01 or less keeps the cube)")
     ap.add_argument("--cold", action="store_true",

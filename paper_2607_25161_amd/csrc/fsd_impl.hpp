@@ -424,6 +424,7 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec);
 // the preconditioner and CGS kinds (mode 0..2 in cgs_mode)
 void launch_batch_mobility(int kind, int prec, int stage, const BatchDesc* D, const int* off, int nsys, int total,
                            size_t shm, hipStream_t st);
+void launch_batch_gather_stop(const BatchDesc* D, int nsys, int* out, hipStream_t st);
 void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, const int* off, int nsys, int total,
                          hipStream_t st);
 

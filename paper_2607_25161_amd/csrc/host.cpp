@@ -2572,6 +2572,10 @@ struct fsd_batch {
   };
   bool use_graphs = true;
   std::vector<SegGraph> seg_graphs;
+  // the systems' stop flags gathered after each segment and read back in one copy
+  int* d_stop = nullptr;
+  int* h_stop = nullptr;  // pinned
+  int stop_cap = 0;
   unsigned long long table_version = 0, graphs_version = ~0ull;
   void drop_graphs() {
     for (auto& g : seg_graphs) (void)hipGraphExecDestroy(g.exec);
@@ -2607,6 +2611,8 @@ struct fsd_batch {
   std::vector<Pend> pending;
   ~fsd_batch() {
     drop_graphs();
+    if (d_stop) (void)hipFree(d_stop);
+    if (h_stop) (void)hipHostFree(h_stop);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     if (d_desc) (void)hipFree(d_desc);
     if (d_off) (void)hipFree(d_off);
@@ -3068,13 +3074,24 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
       for (int j0 = 0;; j0 += S) {
         const int cnt = std::min(S, cyc[0]->m - j0);
         batch_segment(b, j0, cnt);
-        for (auto* s : cyc)
-          HIPCHK(hipMemcpyAsync(s->h_ctl, s->d_ctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, b->st));
+        const int ns = int(cyc.size());
+        if (ns > b->stop_cap) {
+          if (b->d_stop) HIPCHK(hipFree(b->d_stop));
+          if (b->h_stop) HIPCHK(hipHostFree(b->h_stop));
+          b->d_stop = nullptr;
+          b->h_stop = nullptr;
+          b->stop_cap = 0;
+          HIPCHK(hipMalloc(&b->d_stop, sizeof(int) * ns));
+          HIPCHK(hipHostMalloc(&b->h_stop, sizeof(int) * ns));
+          b->stop_cap = ns;
+        }
+        launch_batch_gather_stop(b->d_desc, ns, b->d_stop, b->st);
+        HIPCHK(hipMemcpyAsync(b->h_stop, b->d_stop, sizeof(int) * ns, hipMemcpyDeviceToHost, b->st));
         HIPCHK(hipStreamSynchronize(b->st));
         bool all = true;
-        for (size_t k = 0; k < cyc.size(); ++k) {
-          b->active[k] = !cyc[k]->h_ctl->stop;
-          all = all && cyc[k]->h_ctl->stop;
+        for (int k = 0; k < ns; ++k) {
+          b->active[k] = !b->h_stop[k];
+          all = all && b->h_stop[k];
         }
         if (all || j0 + cnt >= cyc[0]->m) break;
       }

@@ -1040,6 +1040,16 @@ __global__ __launch_bounds__(kCgsThreads) void kb_arnoldi_reduce(const BatchDesc
   arnoldi_update_staged(a, tot[0], st[0], st[1], st[2]);
 }
 
+// every system's stop flag into one array (one read-back per lock-step segment)
+__global__ void kb_gather_stop(const BatchDesc* __restrict__ D, int nsys, int* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nsys) out[k] = D[k].ctl->stop;
+}
+
+void launch_batch_gather_stop(const BatchDesc* D, int nsys, int* out, hipStream_t st) {
+  if (nsys > 0) kb_gather_stop<<<(nsys + 255) / 256, 256, 0, st>>>(D, nsys, out);
+}
+
 void launch_batch_solver(int kind, int j, int cgs_mode, const BatchDesc* D, const int* off, int nsys, int total,
                          hipStream_t st) {
   if (total <= 0) return;

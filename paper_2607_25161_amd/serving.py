@@ -48,13 +48,17 @@ class LibBackend:
     """The real backend: one System per request, one fsd_batch for all."""
 
     def __init__(self, F, mem_budget: int, max_slots: int, params: dict, warm_start: int = 0,
-                 lees_edwards: bool = False):
+                 lees_edwards: bool = False, drift: int = 0):
         self.F = F
         self.batch = F.Batch(mem_budget, max_slots)
         self.params = params
         self.budget = mem_budget
         self.warm_start = warm_start  # GMRES initial guess of each request's solves (fsd_set_warm_start)
         self.lees_edwards = lees_edwards
+        # Brownian drift of requests with kT > 0 (fsd_set_drift: 1 random finite differences,
+        # 2 Fixman; 0 none): the drift is what makes the served trajectories sample the
+        # equilibrium distribution (Appendix A), at two more solves per step
+        self.drift = drift
 
     def estimate(self, req: Request) -> int:
         """Device bytes the request's system will hold.  On the sheared lattice the library
@@ -84,6 +88,8 @@ class LibBackend:
         sysm = self.F.System.from_suspension(s, lees_edwards=self.lees_edwards, **self.params)
         if self.warm_start:
             sysm.set_warm_start(self.warm_start)
+        if self.drift and getattr(s, "kT", 0.0) > 0:
+            sysm.set_drift(self.drift)
         slot = self.batch.try_admit(sysm)
         if slot is None:
             sysm.close()

@@ -101,3 +101,26 @@ def test_sheared_requests_in_mix_equal_alone(F):
         assert abs(alone.strain() - 3e-3) < 1e-15
         alone.close()
     be.batch.close()
+
+
+@pytest.mark.parametrize("drift", [1, 2])
+def test_brownian_requests_with_drift_in_mix_equal_alone(F, drift):
+    """Brownian requests served with the drift on (random finite differences, Fixman): each
+    result equals the same request stepped alone with that drift."""
+    from paper_2607_25161_amd.serving import BatchEngine, LibBackend, Request
+    reqs = fsdgen.serving_requests(3, seed=93, n_range=(100, 400), n_steps=2, kT=1.0)
+    be = LibBackend(F, 1 << 34, 3, {}, drift=drift)
+    eng = BatchEngine(be, max_slots=3, dt=1e-3)
+    rep = eng.run([Request(k, s, 2) for k, s in enumerate(reqs)])
+    assert rep["completed"] == 3 and rep["failed"] == 0
+    served = {r.rid: r.result for r in eng.done}
+    for k, s in enumerate(reqs):
+        alone = F.System.from_suspension(s)
+        alone.set_drift(drift)
+        for _ in range(2):
+            assert alone.step(1e-3, 1).status == 0
+        X, q = alone.state()
+        Xm, qm = served[k]
+        assert np.abs(X - Xm).max() < 1e-9 and np.abs(q - qm).max() < 1e-9, k
+        alone.close()
+    be.batch.close()
