@@ -514,8 +514,11 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
   const R* g1 = grid + cs;
   const R* g2 = grid + 2 * cs;
   // an odd grid side (set by the caller) keeps one column per lane: its pairs would
-  // straddle the wrap and lose the alignment
-  for (int pq = lane; (N & 1) && pq < P * P; pq += 64) {
+  // straddle the wrap and lose the alignment.  So does FP64, where the pairs' registers
+  // (128 VGPRs against 70) cost more occupancy than the wider loads gain (the 4096x20
+  // system: 267 us against 233 per launch)
+  const bool paired = sizeof(R) == 4 && !(N & 1);
+  for (int pq = lane; !paired && pq < P * P; pq += 64) {
     const int ky = pq / P, kx = pq - ky * P;
     int x = sxw + kx, y = syw + ky;
     x -= x >= N ? N : 0;
@@ -535,7 +538,7 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
       off += plane;
     }
   }
-  for (int pq = lane; !(N & 1) && pq < npx * P; pq += 64) {
+  for (int pq = lane; paired && pq < npx * P; pq += 64) {
     const int ky = pq / npx, mp = pq - ky * npx;
     int m = m0 + mp, y = syw + ky;
     m -= m >= half ? half : 0;
