@@ -418,15 +418,10 @@ void launch_interp_sheared(int nb, const double* pos4, const R* grid, const Wave
            body, (const double4*)r4, V);
 }
 
-// Element i of a device array read as global memory (32-bit index from a base the
-// workgroup shares), so the load takes a 32-bit offset instead of a 64-bit address.
-template <typename R>
-__device__ __forceinline__ R ldg(const R* p, unsigned i) {
-  const unsigned bytes = i * unsigned(sizeof(R));  // the caller keeps this below 2^32
-  return *(__attribute__((address_space(1))) const R*)((__attribute__((address_space(1))) const char*)p + bytes);
-}
-
-// The pair p[i], p[i + 1] (i even) stored in one store, addressed as ldg addresses.
+// Global-memory accesses through a 32-bit element index i from a base the workgroup shares
+// (the caller keeps i sizeof(R) below 2^32), so a load or store takes a 32-bit offset
+// instead of a 64-bit address.  stg2 stores the pair p[i], p[i + 1] (i even); ldg4 loads
+// p[i .. i + 3] (i a multiple of 4, aligned); ldg2 loads the pair p[i], p[i + 1].
 template <typename R>
 __device__ __forceinline__ void stg2(R* p, unsigned i, R a, R b) {
   typedef R V2 __attribute__((ext_vector_type(2)));
@@ -437,7 +432,6 @@ __device__ __forceinline__ void stg2(R* p, unsigned i, R a, R b) {
   *(__attribute__((address_space(1))) V2*)((__attribute__((address_space(1))) char*)p + bytes) = v;
 }
 
-// p[i .. i + 3] (i a multiple of 4) in one aligned load, as ldg.
 template <typename R>
 __device__ __forceinline__ void ldg4(const R* p, unsigned i, R& a, R& b, R& c, R& d) {
   typedef R V4 __attribute__((ext_vector_type(4)));
@@ -449,7 +443,6 @@ __device__ __forceinline__ void ldg4(const R* p, unsigned i, R& a, R& b, R& c, R
   d = v.w;
 }
 
-// The pair p[i], p[i + 1] (i even) in one load, as ldg.
 template <typename R>
 __device__ __forceinline__ void ldg2(const R* p, unsigned i, R& a, R& b) {
   typedef R V2 __attribute__((ext_vector_type(2)));
@@ -529,12 +522,16 @@ __device__ __forceinline__ void interp_body(int nb, const double4* __restrict__ 
     for (int kz = 0; kz < P; ++kz) {
       if (kz == n1) off = col;
       const R w = wxy * wz[kz];
-      a0 += w * ldg(g0, off);
-      a3 += w * ldg(g0, off + 1);
-      a1 += w * ldg(g1, off);
-      a4 += w * ldg(g1, off + 1);
-      a2 += w * ldg(g2, off);
-      a5 += w * ldg(g2, off + 1);
+      R v0, v1, v2, v3, v4, v5;
+      ldg2(g0, off, v0, v3);
+      ldg2(g1, off, v1, v4);
+      ldg2(g2, off, v2, v5);
+      a0 += w * v0;
+      a3 += w * v3;
+      a1 += w * v1;
+      a4 += w * v4;
+      a2 += w * v2;
+      a5 += w * v5;
       off += plane;
     }
   }
