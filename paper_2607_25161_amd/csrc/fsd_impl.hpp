@@ -80,6 +80,9 @@ struct WaveParams {
   // Green's multipliers by |m|^2 = m_x^2 + m_y^2 + m_z^2 on the cube (5 per entry: sinc(ka),
   // jv(ka), the solve's and the Brownian root's scalar factors, 1/|k|), or nullptr
   const double* gtab;
+  // the same multipliers rounded to FP32, 8 per entry: sinc, jv, the solve's and the
+  // Brownian root's factors, 1/|k|, then 3 unused (16-byte aligned rows), or nullptr
+  const float* gtab32;
   // transform tiles (0: the default rules fft_lines_b / fft_green_rows): lines per workgroup
   // of the z and y passes, row pairs per workgroup of the x+Green pass
   int tile_b, tile_g;

@@ -644,6 +644,12 @@ void upload_tables(fsd_system* s) {
   double* d_gt = dalloc<double>(s->owned, gt.size());
   HIPCHK(hipMemcpy(d_gt, gt.data(), gt.size() * sizeof(double), hipMemcpyHostToDevice));
   s->wp.gtab = d_gt;
+  std::vector<float> gf(8 * size_t(Q + 1), 0.0f);
+  for (size_t q = 0; q <= size_t(Q); ++q)
+    for (int c = 0; c < 5; ++c) gf[8 * q + c] = float(gt[5 * q + c]);
+  float* d_gf = dalloc<float>(s->owned, gf.size());
+  HIPCHK(hipMemcpy(d_gf, gf.data(), gf.size() * sizeof(float), hipMemcpyHostToDevice));
+  s->wp.gtab32 = d_gf;
 }
 
 // grow a column buffer (the only allocation after set-up)

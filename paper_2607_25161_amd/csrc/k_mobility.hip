@@ -1699,6 +1699,15 @@ __global__ __launch_bounds__(256) void k_fft_lines(R* __restrict__ grid, size_t 
 // TABLE: the cube, multipliers read from the table by |m|^2; otherwise (the sheared lattice)
 // computed per mode.  Two instantiations keep the per-mode FP64 arithmetic out of the
 // cube's register budget.
+// LDS of the x+Green pass with G row slots and complex values of tb bytes: two buffers of
+// 6 G lines (stride N | 1) and the twiddles, then (16-byte aligned) the 2 G row descriptors
+__host__ __device__ inline size_t xgreen_rows_offset(int N, int G, int tb) {
+  return (size_t(tb) * (12 * size_t(G) * (N | 1) + N) + 15) & ~size_t(15);
+}
+__host__ __device__ inline size_t xgreen_shm(int N, int G, int tb) {
+  return xgreen_rows_offset(N, G, tb) + 2 * size_t(G) * sizeof(int4);
+}
+
 template <typename R, bool TABLE>
 __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs, FftPlan plan,
                                                 const R* __restrict__ twiddle, WaveParams wp, int G,
@@ -1715,6 +1724,7 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   T* buf0 = reinterpret_cast<T*>(smem_raw);
   T* buf1 = buf0 + NL * S;
   T* tw = buf1 + NL * S;
+  int4* rows = reinterpret_cast<int4*>(smem_raw + xgreen_rows_offset(N, G, int(sizeof(T))));
   const int H = N / 2, npair = NN / 2 + 2;
   const FastDiv dn(N);
   auto row_of = [N, H](int p) {  // pair number -> its first row r
@@ -1723,26 +1733,41 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     if (p < (H - 1) * N) return N + p;           // kz = 1 .. N/2 - 1, all ky
     return H * N + (p - (H - 1) * N);            // kz = N/2, ky = 0 .. N/2
   };
-  auto partner = [N, &dn](int r) {  // the row of (-kz, -ky)
-    int kz, ky;
-    dn.divmod(r, kz, ky);
-    return (kz ? N - kz : 0) * N + (ky ? N - ky : 0);
-  };
+  // one descriptor per (slot g, row q), index 2 g + q: x = the row's (kz, ky) packed with
+  // bit 31 set (0: no row), y, z = LDS offsets of its line and of its partner's line
+  // (component 0), w = the row's index in the grid (-1: none)
+  for (int i = threadIdx.x; i < 2 * G; i += blockDim.x) {
+    const int g = i >> 1, q = i & 1, pn = bx_ * G + g;
+    int4 v = make_int4(0, 0, 0, -1);
+    if (pn < npair) {
+      const int r = row_of(pn);
+      int kz, ky;
+      dn.divmod(r, kz, ky);
+      const int rp = (kz ? N - kz : 0) * N + (ky ? N - ky : 0);  // the row of (-kz, -ky)
+      if (q == 0 || rp != r) {
+        if (q) dn.divmod(rp, kz, ky);
+        const int qm = rp == r ? 0 : 1 - q;
+        v.x = int(0x80000000u | (unsigned(kz) << 15) | unsigned(ky));
+        v.y = (6 * g + q) * S;
+        v.z = (6 * g + qm) * S;
+        v.w = q ? rp : r;
+      }
+    }
+    rows[i] = v;
+  }
   load_twiddles(tw, reinterpret_cast<const T*>(twiddle), N, -1);
+  __syncthreads();
   staged_copy<8, T>(
       NL * N,
       [&](int t) {
         int line, x;
         dn.divmod(t, line, x);
         const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
-        const int pn = bx_ * G + g;
+        const int row = rows[2 * g + q].w;
         T v;
         v.x = 0;
         v.y = 0;
-        if (pn < npair) {
-          const int r = row_of(pn), rp = partner(r);
-          if (q == 0 || rp != r) ldg2(grid, unsigned(c * cs) + 2 * unsigned((q ? rp : r) * N + x), v.x, v.y);
-        }
+        if (row >= 0) ldg2(grid, unsigned(c * cs) + 2 * unsigned(row * N + x), v.x, v.y);
         return v;
       },
       [&](int t, const T& v) {
@@ -1754,36 +1779,39 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
   T* X = stockham_lm_any<T, R>(buf0, buf1, tw, N, S, NL, plan, -1);
   T* O = (X == buf0) ? buf1 : buf0;
   const double tp = 2.0 * M_PI / wp.L, gam = (!TABLE && wp.gam) ? *wp.gam : 0.0;
-  for (int t = threadIdx.x; t < 2 * G * N; t += blockDim.x) {
-    int gq, kx;
-    dn.divmod(t, gq, kx);
-    const int g = gq >> 1, q = gq & 1;
-    const int pn = bx_ * G + g;
-    if (pn >= npair) continue;
-    const int r = row_of(pn), rp = partner(r);
-    if (rp == r && q == 1) continue;
-    const int qm = rp == r ? 0 : 1 - q, kxm = kx ? N - kx : 0;
-    const int row = q ? rp : r;
-    int kz, ky;
-    dn.divmod(row, kz, ky);
-    const int l0 = 6 * g;
+  // items (row 2 g + q, x mode kx), kx fastest; each thread steps blockDim.x items at a time
+  int gq, kx;
+  dn.divmod(int(threadIdx.x), gq, kx);
+  const int dq = int(blockDim.x) / N, dr = int(blockDim.x) - dq * N;
+  for (; gq < 2 * G; gq += dq, kx += dr) {
+    if (kx >= N) {
+      kx -= N;
+      if (++gq >= 2 * G) break;
+    }
+    const int4 ri = rows[gq];
+    if (ri.x >= 0) continue;  // no row
+    const int kz = (ri.x >> 15) & 0x7fff, ky = ri.x & 0x7fff;
+    const int kxm = kx ? N - kx : 0;
+    const int o = ri.y + kx, om = ri.z + kxm;  // this mode and its (-k) partner, component 0
     const bool nyq = (N % 2 == 0) && (kx == N / 2 || ky == N / 2 || kz == N / 2);
     if (nyq || (kx == 0 && ky == 0 && kz == 0)) {
       for (int c = 0; c < 3; ++c) {
-        O[(l0 + 2 * c + q) * S + kx].x = 0;
-        O[(l0 + 2 * c + q) * S + kx].y = 0;
+        O[o + 2 * c * S].x = 0;
+        O[o + 2 * c * S].y = 0;
       }
       continue;
     }
     // the per-mode arithmetic runs in the grid's precision R (the multipliers are tabulated
-    // in FP64 and rounded once)
+    // in FP64 and rounded once).  F, T below are twice the split spectra
+    // F^ = (Z(k) + conj Z(-k)) / 2, T^ = (Z(k) - conj Z(-k)) / 2i; the halving moves into the
+    // scalar factor Bk (exact: the products scale by powers of two)
     R Fr[3], Fi[3], Tr[3], Ti[3];
     for (int c = 0; c < 3; ++c) {
-      const T z = X[(l0 + 2 * c + q) * S + kx], zm = X[(l0 + 2 * c + qm) * S + kxm];
-      Fr[c] = R(0.5) * (z.x + zm.x);
-      Fi[c] = R(0.5) * (z.y - zm.y);
-      Tr[c] = R(0.5) * (z.y + zm.y);
-      Ti[c] = R(-0.5) * (z.x - zm.x);
+      const T z = X[o + 2 * c * S], zm = X[om + 2 * c * S];
+      Fr[c] = z.x + zm.x;
+      Fi[c] = z.y - zm.y;
+      Tr[c] = z.y + zm.y;
+      Ti[c] = zm.x - z.x;
     }
     // Cartesian wave vector of grid mode m: (2 pi / L)(m_x, m_y - gam m_x, m_z) (the
     // reciprocal lattice of the sheared lattice; gam = 0 for the cube)
@@ -1793,11 +1821,20 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     const R k[3] = {R(tp * mx), R(tp * (my - gam * mx)), R(tp * mz)};
     R sk, jk, Bk, ikn;
     if (TABLE) {  // the multipliers depend on the integer |m|^2 alone
-      const double* gt = wp.gtab + 5 * (mx * mx + my * my + mz * mz);
-      sk = R(gt[0]);
-      jk = R(gt[1]);
-      Bk = R(wp.brownian ? gt[3] : gt[2]);
-      ikn = R(gt[4]);
+      const int m2 = mx * mx + my * my + mz * mz;
+      if constexpr (sizeof(R) == 4) {  // the FP32 copy of the table (the same roundings)
+        const float4 g4 = *reinterpret_cast<const float4*>(wp.gtab32 + 8 * m2);
+        sk = g4.x;
+        jk = g4.y;
+        Bk = wp.brownian ? g4.w : g4.z;
+        ikn = wp.gtab32[8 * m2 + 4];
+      } else {
+        const double* gt = wp.gtab + 5 * m2;
+        sk = R(gt[0]);
+        jk = R(gt[1]);
+        Bk = R(wp.brownian ? gt[3] : gt[2]);
+        ikn = R(gt[4]);
+      }
     } else {
       const double kd[3] = {tp * mx, tp * (my - gam * mx), tp * mz};
       const double k2 = kd[0] * kd[0] + kd[1] * kd[1] + kd[2] * kd[2];
@@ -1811,6 +1848,8 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
       ikn = R(1.0 / kn);
       Bk = R(wp.brownian ? sqrt(wp.scale / (double(N) * N * N) * damp) / kn : wp.scale * damp / k2);
     }
+    Bk *= R(0.5);
+    const R hjk = R(0.5) * jk;
     const R kh[3] = {k[0] * ikn, k[1] * ikn, k[2] * ikn};
     R gr[3], gi[3];
     if (wp.brownian) {
@@ -1822,8 +1861,8 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
       const R cxr[3] = {k[1] * Tr[2] - k[2] * Tr[1], k[2] * Tr[0] - k[0] * Tr[2], k[0] * Tr[1] - k[1] * Tr[0]};
       const R cxi[3] = {k[1] * Ti[2] - k[2] * Ti[1], k[2] * Ti[0] - k[0] * Ti[2], k[0] * Ti[1] - k[1] * Ti[0]};
       for (int a = 0; a < 3; ++a) {
-        gr[a] = sk * Fr[a] - R(0.5) * jk * cxi[a];
-        gi[a] = sk * Fi[a] + R(0.5) * jk * cxr[a];
+        gr[a] = sk * Fr[a] - hjk * cxi[a];
+        gi[a] = sk * Fi[a] + hjk * cxr[a];
       }
     }
     const R pr = kh[0] * gr[0] + kh[1] * gr[1] + kh[2] * gr[2];
@@ -1838,11 +1877,11 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     const R kui[3] = {k[1] * ui[2] - k[2] * ui[1], k[2] * ui[0] - k[0] * ui[2], k[0] * ui[1] - k[1] * ui[0]};
     for (int c = 0; c < 3; ++c) {
       const R Ur = sk * ur[c], Ui = sk * ui[c];
-      const R Wr = R(-0.5) * jk * kui[c], Wi = R(0.5) * jk * kur[c];
+      const R Wr = -hjk * kui[c], Wi = hjk * kur[c];
       T y;
       y.x = Ur - Wi;
       y.y = Ui + Wr;
-      O[(l0 + 2 * c + q) * S + kx] = y;
+      O[o + 2 * c * S] = y;
     }
   }
   __syncthreads();
@@ -1853,12 +1892,10 @@ __device__ __forceinline__ void fft_xgreen_body(R* __restrict__ grid, size_t cs,
     int line, x;
     dn.divmod(t, line, x);
     const int g = line / 6, c = (line % 6) >> 1, q = line & 1;
-    const int pn = bx_ * G + g;
-    if (pn >= npair) continue;
-    const int r = row_of(pn), rp = partner(r);
-    if (q == 1 && rp == r) continue;
+    const int row = rows[2 * g + q].w;
+    if (row < 0) continue;
     const T y = Y[line * S + x];
-    stg2(grid, unsigned(c * cs) + 2 * unsigned((q ? rp : r) * N + x), y.x, y.y);
+    stg2(grid, unsigned(c * cs) + 2 * unsigned(row * N + x), y.x, y.y);
   }
 }
 
@@ -1878,7 +1915,7 @@ bool tile_b_fits(int N, int B, int rbytes) {
 }
 
 bool tile_g_fits(int N, int G, int rbytes) {
-  return G >= 1 && G <= 16 && size_t(2 * rbytes) * (12 * size_t(G) * (N | 1) + N) <= (size_t(64) << 10);
+  return G >= 1 && G <= 16 && xgreen_shm(N, G, 2 * rbytes) <= (size_t(64) << 10);
 }
 
 // lines per workgroup of the coalesced y/z passes: largest B in {16, 8, 4, 2, 1} dividing N
@@ -1905,7 +1942,7 @@ void launch_wave_fft(R* grid, const FftPlan& plan, const R* twiddle, const WaveP
   const size_t cs = 2 * size_t(N) * N * N;
   if (stage == 2) {
     const int G = green_g_of(wp);
-    const size_t shm = sizeof(T) * (12 * size_t(G) * (N | 1) + N);
+    const size_t shm = xgreen_shm(N, G, int(sizeof(T)));
     const int nblk = (N * N / 2 + 2 + G - 1) / G;
     if (wp.gtab && !wp.gam)  // the cube: tabulated multipliers
       launch_k(k_fft_xgreen<R, true>, nblk, kThreads, shm, st, grid, cs, plan, twiddle, wp, G, skip);
@@ -2069,7 +2106,7 @@ size_t batch_shm(const BatchDesc& d, int kind, int prec) {
     case BK_FFT_MID:
       return tb * (2 * size_t(d.bl) * fft_line_stride(int(N), d.bl, int(tb)) + N);
     case BK_FFT_GREEN:
-      return tb * (12 * size_t(d.bg) * (N | 1) + N);
+      return xgreen_shm(int(N), d.bg, int(tb));
     default:
       return 0;
   }
