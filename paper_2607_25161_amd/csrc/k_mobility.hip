@@ -1014,11 +1014,17 @@ __device__ __forceinline__ void spread_split_body(const int* __restrict__ blk_st
         const R wxy = wq[ix] * wq[P + iy];
         const R* l = sh_l + 6 * q;
         const R l0 = l[0], l1 = l[1], l2 = l[2], l3 = l[3], l4 = l[4], l5 = l[5];
+        // the planes zz of the block inside the support, (oz + zz) mod N < P: before the
+        // wrap zz < P - oz, after it N - oz <= zz < N - oz + P; the same in every lane, so
+        // the mask goes to a scalar register and the plane tests are scalar branches
+        const int hi1 = min(max(P - oz, 0), ZW), lo2 = min(N - oz, ZW), hi2 = min(N - oz + P, ZW);
+        const unsigned zmask = __builtin_amdgcn_readfirstlane(
+            int(((1u << hi1) - 1u) | (((1u << hi2) - 1u) & ~((1u << lo2) - 1u))));
 #pragma unroll
         for (int zz = 0; zz < ZW; ++zz) {
-          int iz = z0 + zz - s.z;
-          iz += iz < 0 ? N : 0;
-          if (iz < P) {
+          if (zmask & (1u << zz)) {
+            int iz = oz + zz;
+            iz -= iz >= N ? N : 0;
             const R w = wxy * wq[2 * P + iz];
             a[zz][0] += w * l0;
             a[zz][1] += w * l1;
