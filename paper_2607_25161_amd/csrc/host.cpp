@@ -13,8 +13,6 @@
 #include <new>
 #include <stdexcept>
 #include <string>
-#include <thread>
-#include <unordered_set>
 #include <vector>
 
 #include "fsd.h"
@@ -2999,48 +2997,6 @@ void advance_solves(const std::vector<fsd_system*>& sys) {
 // at most this many systems still iterating: they leave the lock step and finish alone
 constexpr size_t kSoloTail = 4;
 
-// Host threads that launch the per-system work of a batched step (lists, factors,
-// right-hand sides, cycle starts, the Euler update): some 70 launches per system, which
-// one thread issues more slowly than the GPU runs them.
-constexpr size_t kLaunchThreads = 4;
-
-// body(k) for every k in ks (statuses into st[k]), on up to kLaunchThreads threads when
-// every system has a stream of its own; systems that share a stream stay on one thread,
-// so that their launches and graph captures cannot interleave.  body touches its own
-// system only (graph captures are thread-local, launch-event records are per thread).
-template <typename F>
-void for_each_system(const std::vector<fsd_system*>& act, const std::vector<size_t>& ks,
-                     std::vector<fsd_status>& st, F&& body) {
-  size_t nt = std::min(kLaunchThreads, ks.size() / 8);
-  if (nt > 1) {
-    std::unordered_set<hipStream_t> seen;
-    for (size_t k : ks)
-      if (!seen.insert(act[k]->st).second) {
-        nt = 1;
-        break;
-      }
-  }
-  auto run = [&](size_t t, size_t stride) {
-    for (size_t i = t; i < ks.size(); i += stride) {
-      fsd_system* s = act[ks[i]];
-      st[ks[i]] = guarded(s, [&]() -> fsd_status {
-        HIPCHK(hipSetDevice(s->device));
-        body(s);
-        return FSD_OK;
-      });
-    }
-  };
-  if (nt <= 1) {
-    run(0, 1);
-    return;
-  }
-  std::vector<std::thread> th;
-  th.reserve(nt - 1);
-  for (size_t t = 1; t < nt; ++t) th.emplace_back(run, t, nt);
-  run(0, nt);
-  for (auto& x : th) x.join();
-}
-
 // Lock-step solve of all admitted systems with multi-system launches.  Preparation,
 // right-hand sides and GMRES cycle starts/ends run per system on the systems' own
 // streams (they overlap); the Arnoldi steps of all systems whose cycle is running are
@@ -3061,25 +3017,26 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
     done[k] = 1;
     if (worst == FSD_OK) worst = r;
   };
-  std::vector<fsd_status> rs(na, FSD_OK);
-  std::vector<size_t> ks;
-  for (size_t k = 0; k < na; ++k) ks.push_back(k);
-  for_each_system(act, ks, rs, [&](fsd_system* s) {
+  for (size_t k = 0; k < na; ++k) {
+    fsd_system* s = act[k];
     if (integrate) s->bdt = dt;
-    if (integrate) step_before_solve(s);
-    solve_begin(s);
-  });
-  for (size_t k = 0; k < na; ++k)
-    if (rs[k] != FSD_OK) fail_one(k, rs[k]);
-  ks.clear();
-  for (size_t k = 0; k < na; ++k)
-    if (!done[k]) ks.push_back(k);
-  for_each_system(act, ks, rs, [&](fsd_system* s) {  // PREP: lists, right-hand side, first cycle start
-    HIPCHK(hipStreamSynchronize(s->st));
-    (void)solve_advance(s);
-  });
-  for (size_t k : ks)
-    if (rs[k] != FSD_OK) fail_one(k, rs[k]);
+    fsd_status r = guarded(s, [&]() -> fsd_status {
+      if (integrate) step_before_solve(s);
+      solve_begin(s);
+      return FSD_OK;
+    });
+    if (r != FSD_OK) fail_one(k, r);
+  }
+  for (size_t k = 0; k < na; ++k) {  // PREP: lists, right-hand side, first cycle start
+    if (done[k]) continue;
+    fsd_system* s = act[k];
+    fsd_status r = guarded(s, [&]() -> fsd_status {
+      HIPCHK(hipStreamSynchronize(s->st));
+      (void)solve_advance(s);
+      return FSD_OK;
+    });
+    if (r != FSD_OK) fail_one(k, r);
+  }
   const int S = b->timing ? 1 : std::max(1, std::min(act[0]->batch, act[0]->m));
   const int prec = act[0]->p.precision == FSD_MIXED ? 1 : 0;
   int cycles = 0;  // lock-step cycles run
@@ -3159,17 +3116,20 @@ fsd_status batch_run_fused(fsd_batch* b, const std::vector<fsd_system*>& act, do
       break;
     }
   }
-  ks.clear();
-  for (size_t k = 0; k < na; ++k)
-    if (integrate && act[k]->sv.status == FSD_OK) ks.push_back(k);
-  for_each_system(act, ks, rs, [&](fsd_system* s) { step_after_solve(s, dt); });
-  for (size_t k : ks)
-    if (rs[k] != FSD_OK) {
-      act[k]->sv.status = rs[k];
-      if (worst == FSD_OK) worst = rs[k];
+  for (size_t k = 0; k < na; ++k) {
+    fsd_system* s = act[k];
+    if (integrate && s->sv.status == FSD_OK) {
+      fsd_status r = guarded(s, [&]() -> fsd_status {
+        step_after_solve(s, dt);
+        return FSD_OK;
+      });
+      if (r != FSD_OK) {
+        s->sv.status = r;
+        if (worst == FSD_OK) worst = r;
+      }
     }
-  for (size_t k = 0; k < na; ++k)
-    if (act[k]->sv.status != FSD_OK && worst == FSD_OK) worst = act[k]->sv.status;
+    if (s->sv.status != FSD_OK && worst == FSD_OK) worst = s->sv.status;
+  }
   for (auto* s : act) (void)hipStreamSynchronize(s->st);
   batch_harvest(b);
   return worst;
