@@ -191,12 +191,23 @@ __global__ void k_cell_keys(int nb, const double4* __restrict__ pos, double cs, 
   vals[i] = i;
 }
 
-__global__ void k_cell_bounds(int nb, const int* __restrict__ keys, int* start, int* end) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nb) return;
-  const int c = keys[k];
-  if (k == 0 || keys[k - 1] != c) start[c] = k;
-  if (k == nb - 1 || keys[k + 1] != c) end[c] = k + 1;
+// [start, end) of every cell c in the sorted keys, by binary search (empty cells get
+// start == end), so no clearing of the two arrays is needed
+__global__ void k_cell_bounds(int nb, int ncell, const int* __restrict__ keys, int* start, int* end) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int lo = 0, hi = nb;  // first key >= c
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  int e = lo, h2 = nb;  // first key > c
+  while (e < h2) {
+    const int mid = (e + h2) >> 1;
+    if (keys[mid] <= c) e = mid + 1; else h2 = mid;
+  }
+  start[c] = lo;
+  end[c] = e;
 }
 
 // One wavefront per bead scans the 27 surrounding cells (nc >= 3, so each cell is visited
@@ -214,6 +225,7 @@ __global__ __launch_bounds__(256) void k_cell_pairs(int nb, const double4* __res
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= nb) return;  // whole wavefronts leave together
+  if (!FILL && i == 0 && lane == 0) counts[nb] = 0;  // the scan's last input: rowptr[nb] = total
   const double4 p = pos[i];
   const int bi = body[i];
   const int cx = min(nc - 1, int(p.x / cs)), cy = min(nc - 1, int(p.y / cs)), cz = min(nc - 1, int(p.z / cs));
@@ -264,6 +276,7 @@ __global__ void k_brute_pairs(int nb, const double4* __restrict__ pos, const int
                               const int* __restrict__ rowptr, uint32_t* __restrict__ col) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
+  if (!FILL && i == 0) counts[nb] = 0;  // the scan's last input: rowptr[nb] = total
   const double4 p = pos[i];
   const int bi = body[i];
   int cnt = 0;
@@ -316,9 +329,7 @@ hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const i
     if ((e = hipcub::DeviceRadixSort::SortPairs(w->temp, tb, w->keys_in, w->keys_out, w->vals_in, w->vals_out, nb, 0,
                                                  bits, st)) != hipSuccess)
       return e;
-    if ((e = hipMemsetAsync(w->cell_start, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(w->cell_end, 0, sizeof(int) * ncell, st)) != hipSuccess) return e;
-    k_cell_bounds<<<nblocks(nb), kThreads, 0, st>>>(nb, w->keys_out, w->cell_start, w->cell_end);
+    k_cell_bounds<<<nblocks(ncell), kThreads, 0, st>>>(nb, ncell, w->keys_out, w->cell_start, w->cell_end);
     k_cell_pairs<false><<<nblocks(nb, 4), kThreads, 0, st>>>(nb, pos, body, L, gam, cs, nc, rc2, exclude_same_body,
                                                            w->cell_start, w->cell_end, w->vals_out, w->counts,
                                                            nullptr, nullptr);
@@ -327,7 +338,7 @@ hipError_t neighbors_count(NeighborWork* w, int nb, const double* pos4v, const i
     k_brute_pairs<false><<<nblocks(nb), kThreads, 0, st>>>(nb, pos, body, L, gam, rc2, nmax, exclude_same_body,
                                                             w->counts, nullptr, nullptr);
   }
-  if ((e = hipMemsetAsync(w->counts + nb, 0, sizeof(int), st)) != hipSuccess) return e;
+  if (nb == 0 && (e = hipMemsetAsync(w->counts, 0, sizeof(int), st)) != hipSuccess) return e;
   size_t tb = w->temp_bytes;
   if ((e = hipcub::DeviceScan::ExclusiveSum(w->temp, tb, w->counts, rowptr, nb + 1, st)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(w->total, rowptr + nb, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
