@@ -17,6 +17,7 @@
 
 #include "fsd.h"
 #include "fsd_impl.hpp"
+#include "tridiag.hpp"
 
 using namespace fsd;
 
@@ -966,62 +967,6 @@ double dev_dot(fsd_system* s, size_t n, const double* x, const double* y) {
   HIPCHK(hipMemcpyAsync(s->h_small, s->d_h, sizeof(double), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   return s->h_small[0];
-}
-
-// Eigen-decomposition of a symmetric k x k matrix (row-major, overwritten by its
-// eigenvalues on the diagonal) by cyclic Jacobi rotations; Q receives the eigenvectors.
-void sym_eig(int k, std::vector<double>& A, std::vector<double>& Q) {
-  Q.assign(size_t(k) * k, 0.0);
-  for (int i = 0; i < k; ++i) Q[size_t(i) * k + i] = 1.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0, diag = 0;
-    for (int i = 0; i < k; ++i) {
-      diag += A[size_t(i) * k + i] * A[size_t(i) * k + i];
-      for (int j = i + 1; j < k; ++j) off += A[size_t(i) * k + j] * A[size_t(i) * k + j];
-    }
-    if (off == 0.0 || off <= 1e-32 * diag) break;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[size_t(p) * k + q];
-        if (apq == 0.0) continue;
-        const double th = (A[size_t(q) * k + q] - A[size_t(p) * k + p]) / (2.0 * apq);
-        const double tn = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double c = 1.0 / std::sqrt(tn * tn + 1.0), sn = tn * c;
-        for (int r = 0; r < k; ++r) {  // A J
-          const double ap = A[size_t(r) * k + p], aq = A[size_t(r) * k + q];
-          A[size_t(r) * k + p] = c * ap - sn * aq;
-          A[size_t(r) * k + q] = sn * ap + c * aq;
-        }
-        for (int r = 0; r < k; ++r) {  // J^T A
-          const double ap = A[size_t(p) * k + r], aq = A[size_t(q) * k + r];
-          A[size_t(p) * k + r] = c * ap - sn * aq;
-          A[size_t(q) * k + r] = sn * ap + c * aq;
-        }
-        for (int r = 0; r < k; ++r) {  // Q J
-          const double qp = Q[size_t(r) * k + p], qq = Q[size_t(r) * k + q];
-          Q[size_t(r) * k + p] = c * qp - sn * qq;
-          Q[size_t(r) * k + q] = sn * qp + c * qq;
-        }
-      }
-  }
-}
-
-// T^{1/2} e1 for the Lanczos tridiagonal T (diagonal al, off-diagonal be); negative
-// eigenvalues from rounding are clamped at zero
-std::vector<double> tridiag_sqrt_e1(const std::vector<double>& al, const std::vector<double>& be) {
-  const int k = int(al.size());
-  std::vector<double> A(size_t(k) * k, 0.0), Q;
-  for (int i = 0; i < k; ++i) {
-    A[size_t(i) * k + i] = al[i];
-    if (i + 1 < k) A[size_t(i) * k + i + 1] = A[size_t(i + 1) * k + i] = be[i];
-  }
-  sym_eig(k, A, Q);
-  std::vector<double> out(k, 0.0);
-  for (int e = 0; e < k; ++e) {
-    const double f = std::sqrt(std::max(A[size_t(e) * k + e], 0.0)) * Q[e];  // sqrt(lambda_e) (Q^T e1)_e
-    for (int i = 0; i < k; ++i) out[i] += Q[size_t(i) * k + e] * f;
-  }
-  return out;
 }
 
 // out = A^{1/2} z for a symmetric positive semi-definite operator by the Lanczos
