@@ -123,10 +123,11 @@ def test_mobility_real_and_wave_parts(F, xi, L, n):
     assert np.abs(ut - Mb @ lam).max() < 1e-8 * sc
 
 
-@pytest.mark.parametrize("grid", [27, 36])
+@pytest.mark.parametrize("grid", [27, 36, 96, 128, 256])
 def test_wave_part_on_odd_and_uneven_grids(F, grid):
-    """Explicit grids that are odd (no Nyquist modes, symmetric mode range) or not a multiple
-    of 8 (scatter spreading) give the oracle's wave-space part."""
+    """Explicit grids that are odd (no Nyquist modes, symmetric mode range), not a multiple
+    of 8 (scatter spreading), of the compile-time transform sizes (96, 128) or the largest
+    side the library takes (256, a run-time plan) give the oracle's wave-space part."""
     kw = _single_beads(6, 11.0, 31)
     s = _make(F, kw, xi=0.6, grid=grid)
     assert s.info().grid == grid
